@@ -1,0 +1,167 @@
+/*
+ * mgwr.h -- C ABI of libmgwr: multigrid waveform relaxation (MGWR) with an
+ * H-matrix representation of the L1 time discretisation, for the
+ * time-fractional heat equation on graded time meshes, on AMD gfx950.
+ *
+ * Method (Hu, Rodrigo, Gaspar, arXiv 1706.07632):
+ *   Section 2  -- model problem, Caputo derivative, L1 scheme on the graded
+ *                 mesh t_m = T (m/M)^r, matrix R (lower triangular).
+ *   Section 3  -- H-matrix representation R~ of R: admissibility
+ *                 (Definition 3.1), rank-k Taylor factors A, B, recursive 2x2
+ *                 block construction.
+ *   Section 4  -- Algorithm 2 (discrete WRMG: zebra-in-time red-black line
+ *                 relaxation, coarsening in space only), Algorithm 3 (H-matrix
+ *                 matrix-vector product), Algorithm 4 (H-matrix forward
+ *                 substitution).
+ *
+ * The discrete system solved (interior points q, levels m = 1..M):
+ *   sum_j R~_{m,j} u_{q,j} + (A_h u_{.,m})_q = f_{q,m} + a_{m,1} g_q
+ * with A_h the 3-point (1D) / 5-point (2D) negative Laplacian over h^2 and
+ * homogeneous Dirichlet values.
+ *
+ * Conventions
+ *  - Pointers named *_dev are device pointers of the GPU the plan is bound
+ *    to (e.g. torch.Tensor.data_ptr() of a ROCm tensor); every other pointer
+ *    is host memory.
+ *  - Space-time arrays are [M][N] row-major, float64: row m-1 holds time level
+ *    t_m, N = n^dim interior points, in 2D the flat index is q = iy*n + ix.
+ *  - The library never allocates device memory.  The caller provides one
+ *    workspace (mgwr_plan_workspace_bytes) at bind time and owns all arrays.
+ *  - All entry points return an mgwr status; on failure mgwr_last_error()
+ *    returns a thread-local message.  Nothing throws across the ABI.
+ *  - A plan is bound to one device and one stream; it is not thread-safe.
+ *    Calls are asynchronous on that stream unless stated otherwise.
+ */
+#ifndef MGWR_H
+#define MGWR_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MGWR_OK = 0,
+  MGWR_ERR_INVALID_ARG = 1,   /* parameter validation failed; no device work done */
+  MGWR_ERR_STATE = 2,         /* plan not bound, or workspace too small */
+  MGWR_ERR_HIP = 3,           /* a HIP runtime call failed */
+  MGWR_ERR_NOT_CONVERGED = 4, /* max_cycles reached; u and stats still written */
+  MGWR_ERR_NONFINITE = 5      /* a residual norm was NaN/Inf; u and stats still written */
+};
+
+typedef enum {
+  MGWR_FP64 = 0,        /* every cycle in float64 */
+  MGWR_MIXED_FP32 = 1   /* float64 outer residual and correction, float32 inner V-cycles */
+} mgwr_precision;
+
+/* Flags of mgwr_solve. */
+enum {
+  MGWR_GUESS_IN_U = 1u  /* u_dev holds the initial iterate (otherwise the zero grid function) */
+};
+
+typedef struct {
+  int dim;          /* 1 or 2 */
+  int n;            /* interior points per side; n = 2^L - 1 with L >= 1; N = n^dim */
+  double length;    /* spatial domain (0, length)^dim */
+  int M;            /* number of time steps, >= 1 */
+  double T;         /* final time (used only when no explicit mesh is given) */
+  double alpha;     /* fractional order, 0 < alpha < 1 */
+  double r;         /* grading exponent >= 1 (used only when no explicit mesh is given) */
+  int k;            /* Taylor terms per admissible block (rank), 1 <= k <= 16 */
+  int leaf;         /* cluster leaf size, 1 <= leaf <= 16 (16 by default) */
+  int nu1, nu2;     /* pre/post smoothing steps of one cycle (Algorithm 2) */
+  int gamma;        /* cycles on each coarser level: 1 = V-cycle, 2 = W-cycle */
+  int max_cycles;   /* cap on cycles (plain) or inner cycles in total (mixed) */
+  int precision;    /* mgwr_precision */
+  int inner_cycles; /* mixed precision: inner V-cycles per outer refinement step */
+} mgwr_params;
+
+/* Fill *p with defaults: leaf 16, V(1,1), gamma 1, max_cycles 50, FP64, length 1, T 1. */
+void mgwr_params_default(mgwr_params* p);
+
+typedef struct {
+  int cycles;        /* V-cycles run (all precisions) */
+  int refinements;   /* outer float64 residual evaluations in mixed precision */
+  double res0;       /* ||b - A u_initial||_inf */
+  double bnorm;      /* ||b||_inf, b = f + a_{.,1} g */
+  double res;        /* final ||b - A u||_inf (float64) */
+  double avg_factor; /* (res/res0)^(1/cycles) */
+} mgwr_stats;
+
+typedef struct mgwr_plan mgwr_plan;
+
+/* Host-only setup (no device work).  Builds the time mesh (t_host[0..M] if
+ * given, else t_m = T (m/M)^r), the L1 weights, the cluster tree, the block
+ * tree of Definition 3.1, the Taylor factors of Section 3 and every level's
+ * shifted diagonal blocks, all in float64, and packs them for the device.
+ * t_host must be strictly increasing with t_host[0] = 0.
+ * Errors: MGWR_ERR_INVALID_ARG (n not 2^L-1, alpha outside (0,1), M < 1,
+ * k or leaf out of range, non-monotone mesh). */
+int mgwr_plan_create(const mgwr_params* p, const double* t_host, mgwr_plan** out);
+
+/* Device bytes the caller must provide at bind time. */
+int mgwr_plan_workspace_bytes(const mgwr_plan* plan, size_t* bytes);
+
+/* Bind to the current device: copies the packed H-matrix (one host-to-device
+ * copy on `stream`) into workspace_dev, which must stay valid and unused by
+ * the caller until the plan is destroyed or re-bound.  `stream` is a
+ * hipStream_t (NULL = default stream).  workspace_dev must be 256-byte
+ * aligned.  Synchronises the stream before returning. */
+int mgwr_plan_bind(mgwr_plan* plan, void* workspace_dev, size_t bytes, void* stream);
+
+/* Solve the discrete system (Algorithm 2 cycles until
+ * ||b - A u||_inf <= tol ||b||_inf, b = f + a_{.,1} g).
+ *   f_dev [M][N]  source at t_1..t_M
+ *   g_dev [N]     initial value u(x, 0); NULL means zero
+ *   u_dev [M][N]  output; read as the initial iterate iff flags & MGWR_GUESS_IN_U
+ * Returns MGWR_OK, MGWR_ERR_NOT_CONVERGED or MGWR_ERR_NONFINITE (u and stats
+ * written in all three cases).  Synchronises the stream once per cycle to
+ * read the residual norm. */
+int mgwr_solve(mgwr_plan* plan, const double* f_dev, const double* g_dev, double tol,
+               double* u_dev, unsigned flags, mgwr_stats* stats);
+
+/* out_dev = b - A u with b = f + a_{.,1} g (g_dev may be NULL): the float64
+ * defect of the full system (Algorithm 2 "compute the defect", Algorithm 3
+ * for R~).  If norm_host is not NULL the stream is synchronised and
+ * ||out||_inf is stored there.  out_dev may be NULL when only the norm is
+ * wanted. */
+int mgwr_residual(mgwr_plan* plan, const double* f_dev, const double* g_dev, const double* u_dev,
+                  double* out_dev, double* norm_host);
+
+/* Algorithm 3 on its own: y_dev = R~ x_dev for `ncols` independent columns,
+ * both [M][ncols] row-major. */
+int mgwr_hmatvec(mgwr_plan* plan, const double* x_dev, double* y_dev, int ncols);
+
+/* Algorithm 4 on its own: solve (R~ + c_level I) x = b for `ncols` columns,
+ * [M][ncols] row-major, where c_level = 2 dim / h_level^2 is the diagonal of
+ * the spatial stencil on multigrid level `level` (0 = finest). */
+int mgwr_htrsm(mgwr_plan* plan, int level, const double* b_dev, double* x_dev, int ncols);
+
+/* Plan facts for tests and reports (host, no device work). */
+typedef struct {
+  int M, nleaf, nclusters, ndense, nrk, nzclusters, nslots, window, levels, k;
+  long long stored_entries;  /* dense entries + k (|rows| + |cols|) over low-rank blocks */
+  double shift0;             /* c_0 = 2 dim / h^2 */
+} mgwr_plan_info;
+int mgwr_plan_get_info(const mgwr_plan* plan, mgwr_plan_info* info);
+
+/* Host copy of the mesh t[0..M] and of the initial-value weights a_{m,1}
+ * (m = 1..M) used by the plan. */
+int mgwr_plan_get_mesh(const mgwr_plan* plan, double* t_host, double* a1_host);
+
+/* Expand R~ to a dense M x M row-major host array from the packed blocks the
+ * device receives (tests compare it with an independent construction). */
+int mgwr_plan_export_dense(const mgwr_plan* plan, double* Rt_host);
+
+/* Release host state.  Never frees caller memory.  Safe on NULL. */
+int mgwr_plan_destroy(mgwr_plan* plan);
+
+/* Message of the last non-OK return on this thread ("" if none). */
+const char* mgwr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MGWR_H */

@@ -1,0 +1,253 @@
+"""Python binding of libmgwr (argument marshalling only).
+
+Every step of the solver runs in the HIP kernels of libmgwr.so; this module
+only converts arguments, owns the torch workspace tensor that backs a plan,
+and raises on non-OK status codes.  It fails loudly when the library has not
+been built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libmgwr.so")
+
+MGWR_OK = 0
+MGWR_ERR_INVALID_ARG = 1
+MGWR_ERR_STATE = 2
+MGWR_ERR_HIP = 3
+MGWR_ERR_NOT_CONVERGED = 4
+MGWR_ERR_NONFINITE = 5
+MGWR_FP64 = 0
+MGWR_MIXED_FP32 = 1
+MGWR_GUESS_IN_U = 1
+
+EXPORTED = [
+    "mgwr_params_default", "mgwr_plan_create", "mgwr_plan_workspace_bytes", "mgwr_plan_bind",
+    "mgwr_solve", "mgwr_residual", "mgwr_hmatvec", "mgwr_htrsm", "mgwr_plan_get_info",
+    "mgwr_plan_get_mesh", "mgwr_plan_export_dense", "mgwr_plan_destroy", "mgwr_last_error",
+]
+
+
+class MgwrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mgwr error {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int), ("length", ctypes.c_double),
+                ("M", ctypes.c_int), ("T", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("r", ctypes.c_double), ("k", ctypes.c_int), ("leaf", ctypes.c_int),
+                ("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("gamma", ctypes.c_int),
+                ("max_cycles", ctypes.c_int), ("precision", ctypes.c_int), ("inner_cycles", ctypes.c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int), ("refinements", ctypes.c_int), ("res0", ctypes.c_double),
+                ("bnorm", ctypes.c_double), ("res", ctypes.c_double), ("avg_factor", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int), ("nleaf", ctypes.c_int), ("nclusters", ctypes.c_int),
+                ("ndense", ctypes.c_int), ("nrk", ctypes.c_int), ("nzclusters", ctypes.c_int),
+                ("nslots", ctypes.c_int), ("window", ctypes.c_int), ("levels", ctypes.c_int),
+                ("k", ctypes.c_int), ("stored_entries", ctypes.c_longlong), ("shift0", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libmgwr (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1706_07632_amd.build` "
+                          "or __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int
+    L.mgwr_params_default.argtypes = [ctypes.POINTER(Params)]
+    L.mgwr_params_default.restype = None
+    L.mgwr_plan_create.argtypes = [ctypes.POINTER(Params), dp, ctypes.POINTER(vp)]
+    L.mgwr_plan_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.mgwr_plan_bind.argtypes = [vp, vp, ctypes.c_size_t, vp]
+    L.mgwr_solve.argtypes = [vp, vp, vp, ctypes.c_double, vp, ctypes.c_uint, ctypes.POINTER(Stats)]
+    L.mgwr_residual.argtypes = [vp, vp, vp, vp, vp, dp]
+    L.mgwr_hmatvec.argtypes = [vp, vp, vp, ip]
+    L.mgwr_htrsm.argtypes = [vp, ip, vp, vp, ip]
+    L.mgwr_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+    L.mgwr_plan_get_mesh.argtypes = [vp, dp, dp]
+    L.mgwr_plan_export_dense.argtypes = [vp, dp]
+    L.mgwr_plan_destroy.argtypes = [vp]
+    L.mgwr_last_error.argtypes = []
+    L.mgwr_last_error.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        fn = getattr(L, name)
+        if name not in ("mgwr_params_default", "mgwr_last_error"):
+            fn.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc, ok=(MGWR_OK,)):
+    if rc not in ok:
+        raise MgwrError(rc, lib().mgwr_last_error().decode())
+    return rc
+
+
+def _dptr(x):
+    return None if x is None else ctypes.c_void_p(x.data_ptr())
+
+
+def _require(x, name, shape, dtype=None):
+    import torch
+    dtype = torch.float64 if dtype is None else dtype
+    if not x.is_cuda:
+        raise ValueError(f"{name} must be a ROCm device tensor")
+    if x.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(x.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(x.shape)}, expected {tuple(shape)}")
+
+
+class Plan:
+    """H-matrix MGWR plan for one (mesh, alpha, k, grid).
+
+    dim, n, M, alpha, k: problem and rank; r / T build the graded mesh unless
+    an explicit mesh `t` (length M+1, host array) is given.
+    """
+
+    def __init__(self, dim, n, M, alpha, k=10, r=1.0, T=1.0, length=1.0, t=None, leaf=16,
+                 nu1=1, nu2=1, gamma=1, max_cycles=50, precision="fp64", inner_cycles=1):
+        import numpy as np
+        L = lib()
+        p = Params()
+        L.mgwr_params_default(ctypes.byref(p))
+        p.dim, p.n, p.M, p.alpha, p.k = int(dim), int(n), int(M), float(alpha), int(k)
+        p.r, p.T, p.length, p.leaf = float(r), float(T), float(length), int(leaf)
+        p.nu1, p.nu2, p.gamma, p.max_cycles = int(nu1), int(nu2), int(gamma), int(max_cycles)
+        p.precision = {"fp64": MGWR_FP64, "mixed": MGWR_MIXED_FP32, "fp32": MGWR_MIXED_FP32}[precision]
+        p.inner_cycles = int(inner_cycles)
+        self.params = p
+        self.dim, self.n, self.M = int(dim), int(n), int(M)
+        self.N = self.n ** self.dim
+        handle = ctypes.c_void_p()
+        tp = None
+        if t is not None:
+            self._t_host = np.ascontiguousarray(np.asarray(t, dtype=np.float64))
+            if self._t_host.shape != (self.M + 1,):
+                raise ValueError("t must have M+1 entries")
+            tp = self._t_host.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        _check(L.mgwr_plan_create(ctypes.byref(p), tp, ctypes.byref(handle)))
+        self._h = handle
+        self._ws = None
+        self._stream = None
+
+    # -- host facts ---------------------------------------------------------
+    def info(self):
+        inf = PlanInfo()
+        _check(lib().mgwr_plan_get_info(self._h, ctypes.byref(inf)))
+        return inf.as_dict()
+
+    def mesh(self):
+        import numpy as np
+        t = np.empty(self.M + 1)
+        a1 = np.empty(self.M)
+        _check(lib().mgwr_plan_get_mesh(self._h, t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        a1.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return t, a1
+
+    def export_dense(self):
+        import numpy as np
+        R = np.empty((self.M, self.M))
+        _check(lib().mgwr_plan_export_dense(self._h, R.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return R
+
+    def workspace_bytes(self):
+        b = ctypes.c_size_t()
+        _check(lib().mgwr_plan_workspace_bytes(self._h, ctypes.byref(b)))
+        return b.value
+
+    # -- device ---------------------------------------------------------------
+    def bind(self, device=None, stream=None):
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        with torch.cuda.device(dev):
+            nbytes = self.workspace_bytes()
+            self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+            base = self._ws.data_ptr()
+            aligned = (base + 255) & ~255
+            self._stream = torch.cuda.current_stream(dev) if stream is None else stream
+            _check(lib().mgwr_plan_bind(self._h, ctypes.c_void_p(aligned), nbytes,
+                                        ctypes.c_void_p(self._stream.cuda_stream)))
+        self.device = dev
+        return self
+
+    def solve(self, f, g=None, tol=1e-10, u=None, guess=False, allow_unconverged=False):
+        import torch
+        _require(f, "f", (self.M, self.N))
+        if g is not None:
+            _require(g, "g", (self.N,))
+        if u is None:
+            u = torch.empty((self.M, self.N), dtype=torch.float64, device=f.device)
+        _require(u, "u", (self.M, self.N))
+        st = Stats()
+        rc = lib().mgwr_solve(self._h, _dptr(f), _dptr(g), float(tol), _dptr(u),
+                              MGWR_GUESS_IN_U if guess else 0, ctypes.byref(st))
+        _check(rc, ok=(MGWR_OK, MGWR_ERR_NOT_CONVERGED) if allow_unconverged else (MGWR_OK,))
+        return u, st.as_dict()
+
+    def residual(self, f, u, g=None, out=None, want_norm=True):
+        _require(f, "f", (self.M, self.N))
+        _require(u, "u", (self.M, self.N))
+        if g is not None:
+            _require(g, "g", (self.N,))
+        if out is not None:
+            _require(out, "out", (self.M, self.N))
+        nrm = ctypes.c_double(0.0)
+        _check(lib().mgwr_residual(self._h, _dptr(f), _dptr(g), _dptr(u), _dptr(out),
+                                   ctypes.byref(nrm) if want_norm else None))
+        return out, (nrm.value if want_norm else None)
+
+    def hmatvec(self, x, y=None):
+        import torch
+        ncols = x.shape[1]
+        _require(x, "x", (self.M, ncols))
+        if y is None:
+            y = torch.empty_like(x)
+        _require(y, "y", (self.M, ncols))
+        _check(lib().mgwr_hmatvec(self._h, _dptr(x), _dptr(y), int(ncols)))
+        return y
+
+    def htrsm(self, b, level=0, x=None):
+        import torch
+        ncols = b.shape[1]
+        _require(b, "b", (self.M, ncols))
+        if x is None:
+            x = torch.empty_like(b)
+        _require(x, "x", (self.M, ncols))
+        _check(lib().mgwr_htrsm(self._h, int(level), _dptr(b), _dptr(x), int(ncols)))
+        return x
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mgwr_plan_destroy(self._h)
+            self._h = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

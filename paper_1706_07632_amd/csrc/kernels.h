@@ -1,0 +1,51 @@
+// Launch interface of the gfx950 kernels (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "hplan.h"
+
+namespace mgwr {
+
+enum { MODE_SMOOTH = 0, MODE_RESID = 1, MODE_TRSM = 2, MODE_MATVEC = 3 };
+
+// Arguments of the time-marching kernel.  Column p (0 <= p < ncols) of the
+// launch is the spatial index q = cstride * p + coff of arrays [M][ld].
+template <typename T>
+struct MarchArgs {
+  // packed H-matrix (device)
+  const LeafDesc* leaves;
+  int nleaf;
+  const int* dn_list;
+  const T* dense;
+  const T* dinv;      // this level's shifted diagonal inverses [nleaf][256] (SMOOTH/TRSM)
+  const int* ff_row;
+  const T* ffA;
+  const int* zu_row;
+  const T* zuB;
+  int k, nslots, ring;
+  // data
+  const T* F;         // right-hand side (SMOOTH, RESID, TRSM)
+  T* U;               // iterate: written (SMOOTH, TRSM) or read (RESID, MATVEC)
+  T* Out;             // defect (RESID) or product (MATVEC)
+  long long ld;
+  int ncols, cstride, coff;
+  // stencil: dim 0 (none), 1 or 2; n points per side; 1/h^2
+  int dim, n;
+  T inv_h2;
+};
+
+template <typename T> size_t march_lds_bytes(const MarchArgs<T>& a);
+template <typename T> hipError_t launch_march(int mode, const MarchArgs<T>& a, hipStream_t s);
+template <typename T> hipError_t set_march_lds_limit(size_t bytes);
+template <typename T> hipError_t launch_restrict(const T* rf, T* fc, int dim, int nf, int M, hipStream_t s);
+template <typename T> hipError_t launch_prolong(const T* ec, T* uf, int dim, int nf, int M, hipStream_t s);
+hipError_t launch_rhs0(const double* f, const double* gq, const double* a1, double* b, long long M, long long N,
+                       hipStream_t s);
+template <typename T> hipError_t launch_fill(T* x, long long count, T v, hipStream_t s);
+template <typename S, typename D> hipError_t launch_cast(const S* x, D* y, long long count, hipStream_t s);
+hipError_t launch_add_correction(double* u, const float* e, long long count, hipStream_t s);
+template <typename T>
+hipError_t launch_maxabs(const T* x, long long count, double* part, int nparts, double* out, hipStream_t s);
+
+}  // namespace mgwr

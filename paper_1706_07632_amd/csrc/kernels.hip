@@ -1,0 +1,452 @@
+// gfx950 kernels of the MGWR path.
+//
+// march_kernel: one 64-lane wavefront owns 16 spatial columns and marches
+// through the time leaves of the H-matrix in order (Algorithm 4 for the
+// smoother, Algorithm 3 for the defect).  Per leaf i it
+//   1. forms the right-hand side of the leaf rows (stencil of the other colour
+//      for the zebra line relaxation of Algorithm 2, or the defect's f - A_h u),
+//   2. subtracts the dense near-diagonal blocks D_ij x_j (j < i, x_j kept in an
+//      LDS ring of recent leaves),
+//   3. subtracts the low-rank far field A_theta Z_theta of every row cluster
+//      theta containing leaf i (Z in LDS, stacked along the MFMA K dimension),
+//   4. solves with the pre-inverted shifted diagonal leaf (D_ii + c I)^{-1}
+//      (smoother) or subtracts D_ii x_i (defect / product),
+//   5. accumulates Z_theta += B_{theta sigma}^T x_i for every admissible block
+//      whose column cluster sigma contains leaf i (16-row tiles over (theta, nu)).
+// All contractions are v_mfma_*_16x16x4 with the 16 columns as the N dimension.
+//
+// MFMA 16x16x4 operand layout used throughout (lane l, g = l/16, c = l%16):
+//   A (16 x 4):  lane l holds A[c][g]
+//   B (4 x 16):  lane l holds B[g][c]
+//   C/D (16x16): lane l, element r holds D[4g + r][c]
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "hplan.h"
+#include "kernels.h"
+
+namespace mgwr {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct V4;
+template <> struct V4<double> { typedef d4 type; };
+template <> struct V4<float> { typedef f4 type; };
+
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+constexpr int ZFIRST = 1 << 30;
+constexpr int ZMASK = (1 << 30) - 1;
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(64) void march_kernel(MarchArgs<T> a) {
+  typedef typename V4<T>::type v4;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* ring = reinterpret_cast<T*>(smem_raw);   // [R][16][16]
+  T* tbuf = ring + a.ring * 256;               // [16][16]
+  T* Z = tbuf + 256;                           // [nslots*k][16]
+
+  const int lane = threadIdx.x;
+  const int g = lane >> 4;
+  const int c = lane & 15;
+  const int p = blockIdx.x * 16 + c;
+  const bool colok = p < a.ncols;
+  const long long q = colok ? (long long)a.cstride * p + a.coff : 0;
+
+  // stencil neighbours of column q (a.dim == 0: none)
+  long long nb[4] = {0, 0, 0, 0};
+  bool nbok[4] = {false, false, false, false};
+  if (a.dim == 1) {
+    nb[0] = q - 1; nbok[0] = colok && q >= 1;
+    nb[1] = q + 1; nbok[1] = colok && q + 1 < a.n;
+  } else if (a.dim == 2) {
+    long long ix = q % a.n, iy = q / a.n;
+    nb[0] = q - 1;   nbok[0] = colok && ix >= 1;
+    nb[1] = q + 1;   nbok[1] = colok && ix + 1 < a.n;
+    nb[2] = q - a.n; nbok[2] = colok && iy >= 1;
+    nb[3] = q + a.n; nbok[3] = colok && iy + 1 < a.n;
+  }
+  const T diagc = (T)(2 * a.dim);
+
+  for (int i = 0; i < a.nleaf; ++i) {
+    const LeafDesc d = a.leaves[i];
+    T* cur = ring + (i % a.ring) * 256;
+    v4 acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 4 * g + r;
+      const bool ok = colok && row < d.sz;
+      const long long off = (long long)(d.lo + row) * a.ld;
+      T v = (T)0;
+      if (ok) {
+        if constexpr (MODE == MODE_SMOOTH || MODE == MODE_RESID) {
+          T s = (T)0;
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (nbok[e]) s += a.U[off + nb[e]];
+          if constexpr (MODE == MODE_SMOOTH) {
+            v = a.F[off + q] + a.inv_h2 * s;
+          } else {
+            const T uq = a.U[off + q];
+            v = a.F[off + q] - a.inv_h2 * (diagc * uq - s);
+          }
+        } else if constexpr (MODE == MODE_TRSM) {
+          v = a.F[off + q];
+        }
+      }
+      acc[r] = v;
+    }
+    if constexpr (MODE == MODE_RESID || MODE == MODE_MATVEC) {
+      // the known iterate of this leaf enters the ring (B-operand tile layout)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 4 * g + r;
+        const bool ok = colok && row < d.sz;
+        cur[row * 16 + c] = ok ? a.U[(long long)(d.lo + row) * a.ld + q] : (T)0;
+      }
+      __syncthreads();
+    }
+
+    // 2. dense near-diagonal blocks (stored negated)
+    for (int e = d.dn_begin; e < d.dn_end; ++e) {
+      const int j = a.dn_list[2 * e];
+      const T* D = a.dense + (long long)a.dn_list[2 * e + 1] * 256;
+      const T* xj = ring + (j % a.ring) * 256;
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) acc = mfma(D[kc * 64 + lane], xj[(4 * kc + g) * 16 + c], acc);
+    }
+    if constexpr (MODE == MODE_RESID || MODE == MODE_MATVEC) {
+      const T* D = a.dense + (long long)d.diag_off * 256;
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) acc = mfma(D[kc * 64 + lane], cur[(4 * kc + g) * 16 + c], acc);
+    }
+
+    // 3. far field: stacked (theta, nu) rows, A stored negated
+    for (int ch = 0; ch < d.ff_nchunk; ++ch) {
+      const int zr = a.ff_row[(d.ff_begin + ch) * 4 + g];
+      const T bv = zr >= 0 ? Z[zr * 16 + c] : (T)0;
+      acc = mfma(a.ffA[(long long)(d.ff_begin + ch) * 64 + lane], bv, acc);
+    }
+
+    // 4. diagonal leaf
+    if constexpr (MODE == MODE_SMOOTH || MODE == MODE_TRSM) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) tbuf[(4 * g + r) * 16 + c] = acc[r];
+      __syncthreads();
+      v4 x = {0, 0, 0, 0};
+      const T* Di = a.dinv + (long long)i * 256;
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) x = mfma(Di[kc * 64 + lane], tbuf[(4 * kc + g) * 16 + c], x);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 4 * g + r;
+        const bool ok = colok && row < d.sz;
+        if (ok) a.U[(long long)(d.lo + row) * a.ld + q] = x[r];
+        cur[row * 16 + c] = ok ? x[r] : (T)0;
+      }
+      __syncthreads();
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 4 * g + r;
+        if (colok && row < d.sz) {
+          const T v = (MODE == MODE_MATVEC) ? -acc[r] : acc[r];
+          a.Out[(long long)(d.lo + row) * a.ld + q] = v;
+        }
+      }
+    }
+
+    // 5. column-side low-rank updates Z += B^T x_i
+    for (int tt = 0; tt < d.zu_ntile; ++tt) {
+      const int* zrow = a.zu_row + (long long)(d.zu_begin + tt) * 16 + 4 * g;
+      int zr[4];
+      v4 z;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        zr[r] = zrow[r];
+        z[r] = (zr[r] >= 0 && !(zr[r] & ZFIRST)) ? Z[(zr[r] & ZMASK) * 16 + c] : (T)0;
+      }
+      const T* Bt = a.zuB + (long long)(d.zu_begin + tt) * 256;
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) z = mfma(Bt[kc * 64 + lane], cur[(4 * kc + g) * 16 + c], z);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (zr[r] >= 0) Z[(zr[r] & ZMASK) * 16 + c] = z[r];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Stencil kernels (space only, every time row independently)
+
+// Full weighting (Algorithm 2 "restrict the defect only in space").
+template <typename T>
+__global__ void restrict_kernel(const T* __restrict__ rf, T* __restrict__ fc, int dim, int nf, int nc, long long M) {
+  const long long Nc = dim == 1 ? nc : (long long)nc * nc;
+  const long long Nf = dim == 1 ? nf : (long long)nf * nf;
+  const long long total = M * Nc;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const long long m = idx / Nc, Q = idx % Nc;
+    const T* r = rf + m * Nf;
+    T v;
+    if (dim == 1) {
+      const long long f = 2 * Q + 1;
+      v = (T)0.25 * (r[f - 1] + (T)2 * r[f] + r[f + 1]);
+    } else {
+      const long long I = Q % nc, J = Q / nc;
+      const long long fx = 2 * I + 1, fy = 2 * J + 1;
+      const T* r0 = r + (fy - 1) * nf;
+      const T* r1 = r + fy * nf;
+      const T* r2 = r + (fy + 1) * nf;
+      v = (T)(1.0 / 16.0) * ((r0[fx - 1] + r0[fx + 1] + r2[fx - 1] + r2[fx + 1]) +
+                             (T)2 * (r0[fx] + r2[fx] + r1[fx - 1] + r1[fx + 1]) + (T)4 * r1[fx]);
+    }
+    fc[idx] = v;
+  }
+}
+
+// Linear / bilinear interpolation plus correction (Algorithm 2 "interpolate
+// the correction only in space" and "compute a new approximation").
+template <typename T>
+__global__ void prolong_kernel(const T* __restrict__ ec, T* __restrict__ uf, int dim, int nf, int nc, long long M) {
+  const long long Nc = dim == 1 ? nc : (long long)nc * nc;
+  const long long Nf = dim == 1 ? nf : (long long)nf * nf;
+  const long long total = M * Nf;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const long long m = idx / Nf, q = idx % Nf;
+    const T* e = ec + m * Nc;
+    T v;
+    if (dim == 1) {
+      if (q & 1) {
+        v = e[(q - 1) / 2];
+      } else {
+        const long long I = q / 2;  // between coarse I-1 and I
+        const T lo = I >= 1 ? e[I - 1] : (T)0;
+        const T hi = I < nc ? e[I] : (T)0;
+        v = (T)0.5 * (lo + hi);
+      }
+    } else {
+      const long long ix = q % nf, iy = q / nf;
+      long long cx[2], cy[2];
+      T wx[2], wy[2];
+      int nx, ny;
+      if (ix & 1) { cx[0] = (ix - 1) / 2; wx[0] = (T)1; nx = 1; }
+      else { cx[0] = ix / 2 - 1; cx[1] = ix / 2; wx[0] = wx[1] = (T)0.5; nx = 2; }
+      if (iy & 1) { cy[0] = (iy - 1) / 2; wy[0] = (T)1; ny = 1; }
+      else { cy[0] = iy / 2 - 1; cy[1] = iy / 2; wy[0] = wy[1] = (T)0.5; ny = 2; }
+      v = (T)0;
+      for (int b = 0; b < ny; ++b) {
+        if (cy[b] < 0 || cy[b] >= nc) continue;
+        for (int a2 = 0; a2 < nx; ++a2) {
+          if (cx[a2] < 0 || cx[a2] >= nc) continue;
+          v += wx[a2] * wy[b] * e[cy[b] * nc + cx[a2]];
+        }
+      }
+    }
+    uf[idx] += v;
+  }
+}
+
+// b = f + a_{m,1} g (initial value moved to the right-hand side).
+__global__ void rhs0_kernel(const double* __restrict__ f, const double* __restrict__ gq, const double* __restrict__ a1,
+                            double* __restrict__ b, long long M, long long N) {
+  const long long total = M * N;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x)
+    b[idx] = f[idx] + a1[idx / N] * gq[idx % N];
+}
+
+template <typename T>
+__global__ void fill_kernel(T* __restrict__ x, long long count, T v) {
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < count;
+       idx += (long long)gridDim.x * blockDim.x)
+    x[idx] = v;
+}
+
+template <typename S, typename D>
+__global__ void cast_kernel(const S* __restrict__ x, D* __restrict__ y, long long count) {
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < count;
+       idx += (long long)gridDim.x * blockDim.x)
+    y[idx] = (D)x[idx];
+}
+
+// u += e (float correction into the float64 iterate)
+__global__ void add_correction_kernel(double* __restrict__ u, const float* __restrict__ e, long long count) {
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < count;
+       idx += (long long)gridDim.x * blockDim.x)
+    u[idx] += (double)e[idx];
+}
+
+// max |x| in two passes; non-finite values are counted separately
+template <typename T>
+__global__ __launch_bounds__(256) void maxabs_partial_kernel(const T* __restrict__ x, long long count,
+                                                            double* __restrict__ part) {
+  __shared__ double sm[256];
+  __shared__ int sbad[256];
+  double m = 0.0;
+  int bad = 0;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < count;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const double v = (double)x[idx];
+    if (!isfinite(v)) bad = 1;
+    else m = fmax(m, fabs(v));
+  }
+  sm[threadIdx.x] = m;
+  sbad[threadIdx.x] = bad;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+      sbad[threadIdx.x] |= sbad[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sbad[0] ? __builtin_nan("") : sm[0];
+}
+
+__global__ __launch_bounds__(256) void maxabs_final_kernel(const double* __restrict__ part, int nparts,
+                                                          double* __restrict__ out) {
+  __shared__ double sm[256];
+  __shared__ int sbad[256];
+  double m = 0.0;
+  int bad = 0;
+  for (int idx = threadIdx.x; idx < nparts; idx += blockDim.x) {
+    const double v = part[idx];
+    if (v != v) bad = 1;
+    else m = fmax(m, v);
+  }
+  sm[threadIdx.x] = m;
+  sbad[threadIdx.x] = bad;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+      sbad[threadIdx.x] |= sbad[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sbad[0] ? __builtin_nan("") : sm[0];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+static inline int grid_for(long long total, int block) {
+  long long g = (total + block - 1) / block;
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+template <typename T>
+size_t march_lds_bytes(const MarchArgs<T>& a) {
+  return ((size_t)a.ring * 256 + 256 + (size_t)a.nslots * a.k * 16) * sizeof(T);
+}
+
+template <typename T>
+hipError_t launch_march(int mode, const MarchArgs<T>& a, hipStream_t s) {
+  if (a.ncols <= 0) return hipSuccess;
+  dim3 grid((a.ncols + 15) / 16), block(64);
+  size_t lds = march_lds_bytes(a);
+  switch (mode) {
+    case MODE_SMOOTH: hipLaunchKernelGGL((march_kernel<T, MODE_SMOOTH>), grid, block, lds, s, a); break;
+    case MODE_RESID: hipLaunchKernelGGL((march_kernel<T, MODE_RESID>), grid, block, lds, s, a); break;
+    case MODE_TRSM: hipLaunchKernelGGL((march_kernel<T, MODE_TRSM>), grid, block, lds, s, a); break;
+    case MODE_MATVEC: hipLaunchKernelGGL((march_kernel<T, MODE_MATVEC>), grid, block, lds, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t set_march_lds_limit(size_t bytes) {
+  hipError_t e;
+  e = hipFuncSetAttribute((const void*)march_kernel<T, MODE_SMOOTH>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)march_kernel<T, MODE_RESID>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)march_kernel<T, MODE_TRSM>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)march_kernel<T, MODE_MATVEC>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <typename T>
+hipError_t launch_restrict(const T* rf, T* fc, int dim, int nf, int M, hipStream_t s) {
+  int nc = (nf - 1) / 2;
+  long long total = (long long)M * (dim == 1 ? nc : (long long)nc * nc);
+  hipLaunchKernelGGL(restrict_kernel<T>, dim3(grid_for(total, 256)), dim3(256), 0, s, rf, fc, dim, nf, nc, (long long)M);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prolong(const T* ec, T* uf, int dim, int nf, int M, hipStream_t s) {
+  int nc = (nf - 1) / 2;
+  long long total = (long long)M * (dim == 1 ? nf : (long long)nf * nf);
+  hipLaunchKernelGGL(prolong_kernel<T>, dim3(grid_for(total, 256)), dim3(256), 0, s, ec, uf, dim, nf, nc, (long long)M);
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs0(const double* f, const double* gq, const double* a1, double* b, long long M, long long N,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(rhs0_kernel, dim3(grid_for(M * N, 256)), dim3(256), 0, s, f, gq, a1, b, M, N);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill(T* x, long long count, T v, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel<T>, dim3(grid_for(count, 256)), dim3(256), 0, s, x, count, v);
+  return hipGetLastError();
+}
+
+template <typename S, typename D>
+hipError_t launch_cast(const S* x, D* y, long long count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL((cast_kernel<S, D>), dim3(grid_for(count, 256)), dim3(256), 0, s, x, y, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_correction(double* u, const float* e, long long count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(add_correction_kernel, dim3(grid_for(count, 256)), dim3(256), 0, s, u, e, count);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_maxabs(const T* x, long long count, double* part, int nparts, double* out, hipStream_t s) {
+  int blocks = grid_for(count, 256);
+  if (blocks > nparts) blocks = nparts;
+  hipLaunchKernelGGL(maxabs_partial_kernel<T>, dim3(blocks), dim3(256), 0, s, x, count, part);
+  hipLaunchKernelGGL(maxabs_final_kernel, dim3(1), dim3(256), 0, s, part, blocks, out);
+  return hipGetLastError();
+}
+
+// explicit instantiations
+template size_t march_lds_bytes<double>(const MarchArgs<double>&);
+template size_t march_lds_bytes<float>(const MarchArgs<float>&);
+template hipError_t launch_march<double>(int, const MarchArgs<double>&, hipStream_t);
+template hipError_t launch_march<float>(int, const MarchArgs<float>&, hipStream_t);
+template hipError_t set_march_lds_limit<double>(size_t);
+template hipError_t set_march_lds_limit<float>(size_t);
+template hipError_t launch_restrict<double>(const double*, double*, int, int, int, hipStream_t);
+template hipError_t launch_restrict<float>(const float*, float*, int, int, int, hipStream_t);
+template hipError_t launch_prolong<double>(const double*, double*, int, int, int, hipStream_t);
+template hipError_t launch_prolong<float>(const float*, float*, int, int, int, hipStream_t);
+template hipError_t launch_fill<double>(double*, long long, double, hipStream_t);
+template hipError_t launch_fill<float>(float*, long long, float, hipStream_t);
+template hipError_t launch_cast<double, float>(const double*, float*, long long, hipStream_t);
+template hipError_t launch_cast<float, double>(const float*, double*, long long, hipStream_t);
+template hipError_t launch_maxabs<double>(const double*, long long, double*, int, double*, hipStream_t);
+template hipError_t launch_maxabs<float>(const float*, long long, double*, int, double*, hipStream_t);
+
+}  // namespace mgwr

@@ -1,0 +1,197 @@
+"""GPU parity of the HIP path (through the C ABI) against the float64 oracle."""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1706_07632_amd as mg  # noqa: E402  (fails loudly if the library is missing)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def _plan(p, dev, **kw):
+    return mg.Plan(p.dim, p.n, p.M, p.alpha, k=p.k, t=p.t, length=p.length, leaf=p.leaf, **kw).bind()
+
+
+def _cuda(a, dev):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+
+
+@pytest.mark.parametrize("M,alpha,r,k,ncols", [(128, 0.5, 3.0, 8, 16), (256, 0.3, 17 / 3, 10, 37),
+                                               (1024, 0.5, 3.0, 10, 5), (300, 0.7, 1.857142857142857, 6, 70)])
+def test_hmatvec_matches_oracle(dev, M, alpha, r, k, ncols):
+    t = W.graded_mesh(M, 1.0, r)
+    plan = mg.Plan(1, 15, M, alpha, k=k, t=t).bind()
+    rng = np.random.default_rng(1)
+    X = rng.standard_normal((M, ncols))
+    Y = plan.hmatvec(_cuda(X, dev)).cpu().numpy()
+    ref = oracle.hmatrix_dense(t, alpha, k) @ X
+    assert np.max(np.abs(Y - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("M,alpha,r,k,ncols,level", [(128, 0.5, 3.0, 8, 16, 0), (512, 0.3, 17 / 3, 10, 33, 1),
+                                                     (2048, 0.2, 9.0, 10, 20, 0), (100, 0.5, 1.0, 6, 3, 2)])
+def test_htrsm_matches_oracle(dev, M, alpha, r, k, ncols, level):
+    t = W.graded_mesh(M, 1.0, r)
+    plan = mg.Plan(1, 31, M, alpha, k=k, t=t).bind()
+    rng = np.random.default_rng(2)
+    B = rng.standard_normal((M, ncols))
+    X = plan.htrsm(_cuda(B, dev), level=level).cpu().numpy()
+    n_l = (31 + 1) // (2 ** level) - 1
+    c = 2.0 / (1.0 / (n_l + 1)) ** 2
+    Rt = oracle.hmatrix_dense(t, alpha, k)
+    ref = scipy.linalg.solve_triangular(Rt + c * np.eye(M), B, lower=True)
+    assert np.max(np.abs(X - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def _solve_and_compare(p, dev, tol=1e-12, parity=1e-10, g=None, **kw):
+    plan = _plan(p, dev, **kw)
+    f = _cuda(p.f, dev)
+    gd = None if g is None else _cuda(g, dev)
+    u, st = plan.solve(f, gd, tol=tol)
+    U = u.cpu().numpy()
+    Rt = oracle.hmatrix_dense(p.t, p.alpha, p.k, p.leaf)
+    B = oracle.rhs(p.f, p.t, p.alpha, g)
+    ref = oracle.timestep_solve(Rt, B, p.dim, p.n, p.length)
+    err = np.max(np.abs(U - ref)) / np.max(np.abs(ref))
+    res = np.max(np.abs(oracle.residual(Rt, U, B, p.dim, p.n, p.length))) / np.max(np.abs(B))
+    return err, res, st
+
+
+def test_small1d_manufactured_parity(dev):
+    p = W.config("small1d")
+    err, res, st = _solve_and_compare(p, dev)
+    assert err < 1e-10, (err, st)
+    assert res < 1e-12, (res, st)
+    assert 4 <= st["cycles"] <= 15
+
+
+def test_small1d_mesh_from_formula(dev):
+    p = W.config("small1d")
+    plan = mg.Plan(1, p.n, p.M, p.alpha, k=p.k, r=p.r).bind()
+    u, st = plan.solve(_cuda(p.f, dev), tol=1e-12)
+    Rt = oracle.hmatrix_dense(p.t, p.alpha, p.k)
+    ref = oracle.timestep_solve(Rt, oracle.rhs(p.f, p.t, p.alpha, None), 1, p.n, 1.0)
+    assert np.max(np.abs(u.cpu().numpy() - ref)) / np.max(np.abs(ref)) < 1e-10
+
+
+@pytest.mark.parametrize("dim,n,M,alpha,r,k", [(1, 31, 96, 0.3, 17 / 3, 6), (2, 15, 64, 0.5, 3.0, 8),
+                                               (2, 7, 40, 0.8, 1.25, 10), (1, 1, 32, 0.5, 2.0, 4),
+                                               (2, 3, 17, 0.6, 2.0, 5)])
+def test_random_source_and_initial_value_parity(dev, dim, n, M, alpha, r, k):
+    rng = np.random.default_rng(3)
+    N = n ** dim
+    t = W.graded_mesh(M, 1.0, r)
+    p = W.Problem(dim=dim, n=n, M=M, alpha=alpha, r=r, k=k, t=t, f=rng.standard_normal((M, N)))
+    g = rng.standard_normal(N)
+    err, res, st = _solve_and_compare(p, dev, g=g)
+    assert err < 1e-10, (err, st)
+    assert res < 1e-12
+
+
+def test_paper_1d_problem_small(dev):
+    p = W.paper_1d_mittag_leffler(63, 64, 0.6, k=20)
+    err, res, st = _solve_and_compare(p, dev, g=p.g)
+    assert err < 1e-10
+    ex = oracle.mittag_leffler(0.6, -p.t[1:] ** 0.6)[:, None] * p.g[None, :]
+    plan = _plan(p, dev)
+    u, _ = plan.solve(_cuda(p.f, dev), _cuda(p.g, dev), tol=1e-10)
+    assert np.max(np.abs(u.cpu().numpy() - ex)) < 2e-2   # discretisation error at this size
+
+
+def test_residual_entry_point(dev):
+    rng = np.random.default_rng(4)
+    p = W.manufactured(2, 15, 64, 0.4, r=3.0, k=8)
+    plan = _plan(p, dev)
+    U = rng.standard_normal((p.M, p.N))
+    g = rng.standard_normal(p.N)
+    out = torch.empty((p.M, p.N), dtype=torch.float64, device=dev)
+    _, nrm = plan.residual(_cuda(p.f, dev), _cuda(U, dev), g=_cuda(g, dev), out=out)
+    Rt = oracle.hmatrix_dense(p.t, p.alpha, p.k)
+    ref = oracle.residual(Rt, U, oracle.rhs(p.f, p.t, p.alpha, g), 2, p.n, 1.0)
+    assert np.max(np.abs(out.cpu().numpy() - ref)) <= 1e-13 * np.max(np.abs(ref))
+    assert abs(nrm - np.max(np.abs(ref))) <= 1e-13 * np.max(np.abs(ref))
+
+
+def test_w_cycle_and_v01_converge(dev):
+    p = W.config("small1d")
+    e1, _, st1 = _solve_and_compare(p, dev, gamma=2)
+    e2, _, st2 = _solve_and_compare(p, dev, nu1=0, nu2=1)
+    assert e1 < 1e-10 and e2 < 1e-10
+    assert st1["cycles"] <= st2["cycles"] + 2
+
+
+def _single_mode_reference(p):
+    Rt = oracle.hmatrix_dense(p.t, p.alpha, p.k, p.leaf)
+    (kvec, prof), = p.modes
+    w = oracle.single_mode_profile(Rt, oracle.mode_eigenvalue(kvec, p.n, p.length), prof)
+    s = W.sine_mode(p.n, p.dim, p.length, kvec)
+    return Rt, w, s
+
+
+@pytest.mark.parametrize("alpha", [0.3, 0.5, 0.7])
+def test_large1d_parity_full_size(dev, alpha):
+    """n = 1023, M = 4096: the source is one sine mode, so the exact discrete
+    solution is w(t) s(x) with (R~ + lambda_h I) w = phi (one triangular solve)."""
+    p = W.config("large1d", alpha)
+    plan = _plan(p, dev)
+    u, st = plan.solve(_cuda(p.f, dev), tol=1e-12)
+    Rt, w, s = _single_mode_reference(p)
+    ref = np.outer(w, s)
+    U = u.cpu().numpy()
+    assert np.max(np.abs(U - ref)) / np.max(np.abs(ref)) < 1e-10, st
+    cols = np.array([0, 1, 511, 512, 1000, 1022])
+    r = oracle.residual_columns(Rt, U, p.f, 1, p.n, 1.0, cols)
+    assert np.max(np.abs(r)) <= 1e-12 * st["bnorm"] * 1.01
+
+
+def test_large2d_parity_full_size(dev):
+    p = W.config("large2d")
+    plan = _plan(p, dev)
+    u, st = plan.solve(_cuda(p.f, dev), tol=1e-12)
+    Rt, w, s = _single_mode_reference(p)
+    rng = np.random.default_rng(5)
+    cols = np.unique(np.concatenate([[0, 1, 254, 255, 32512, 65024], rng.integers(0, p.N, 200)]))
+    U = u[:, torch.as_tensor(cols, device=dev)].cpu().numpy()
+    ref = np.outer(w, s[cols])
+    assert np.max(np.abs(U - ref)) / np.max(np.abs(np.outer(w, s))) < 1e-10, st
+
+
+def test_mixed_precision_reaches_tolerance(dev):
+    p = W.manufactured(1, 255, 1024, 0.5, r=3.0, k=10)
+    plan = _plan(p, dev, precision="mixed", inner_cycles=1)
+    u, st = plan.solve(_cuda(p.f, dev), tol=1e-8)
+    Rt, w, s = _single_mode_reference(p)
+    U = u.cpu().numpy()
+    res = np.max(np.abs(oracle.residual(Rt, U, p.f, 1, p.n, 1.0)))
+    assert res <= 1e-8 * st["bnorm"] * 1.01, st
+    assert st["refinements"] >= 1
+    err = np.max(np.abs(U - np.outer(w, s))) / np.max(np.abs(w))
+    assert err < 1e-7, err
+
+
+def test_not_converged_status_and_nonfinite(dev):
+    p = W.config("small1d")
+    plan = _plan(p, dev, max_cycles=1)
+    u, st = plan.solve(_cuda(p.f, dev), tol=1e-14, allow_unconverged=True)
+    assert st["cycles"] == 1 and st["res"] > 1e-14 * st["bnorm"]
+    with pytest.raises(mg.MgwrError) as ei:
+        plan.solve(_cuda(p.f, dev), tol=1e-14)
+    assert ei.value.code == mg.MGWR_ERR_NOT_CONVERGED
+    f = p.f.copy()
+    f[3, 7] = np.nan
+    with pytest.raises(mg.MgwrError) as ei:
+        plan.solve(_cuda(f, dev), tol=1e-10)
+    assert ei.value.code == mg.MGWR_ERR_NONFINITE

@@ -1,0 +1,120 @@
+"""Host-side checks of libmgwr (no GPU): exports, validation, and the packed
+H-matrix against the independent oracle construction."""
+import os
+import re
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+mg = pytest.importorskip("paper_1706_07632_amd")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "mgwr.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mgwr_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = mg.lib()
+    names = _declared_functions()
+    assert "mgwr_solve" in names and "mgwr_htrsm" in names
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(mg.EXPORTED)
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(n=64), "2^L - 1"),
+    (dict(alpha=1.2), "alpha"),
+    (dict(alpha=0.0), "alpha"),
+    (dict(M=0), "M must"),
+    (dict(k=0), "k must"),
+    (dict(k=17), "k must"),
+    (dict(dim=3), "dim"),
+    (dict(leaf=0), "leaf"),
+    (dict(r=0.5), "r >= 1"),
+    (dict(nu1=0, nu2=0), "nu1"),
+    (dict(gamma=3), "gamma"),
+])
+def test_invalid_parameters_are_rejected(kw, msg):
+    args = dict(dim=1, n=31, M=64, alpha=0.5, k=8, r=2.0)
+    args.update(kw)
+    with pytest.raises(mg.MgwrError) as ei:
+        mg.Plan(**args)
+    assert ei.value.code == mg.MGWR_ERR_INVALID_ARG
+    assert msg in str(ei.value)
+
+
+def test_non_monotone_mesh_rejected():
+    t = W.graded_mesh(32, 1.0, 2.0)
+    t[5] = t[4]
+    with pytest.raises(mg.MgwrError):
+        mg.Plan(1, 15, 32, 0.5, k=6, t=t)
+
+
+CONFIGS = [
+    (128, 0.5, 3.0, 8, 16),
+    (1024, 0.5, 3.0, 10, 16),
+    (512, 0.3, 17 / 3, 10, 16),
+    (300, 0.7, 1.857142857142857, 6, 12),
+    (100, 0.2, 9.0, 10, 7),
+    (33, 0.5, 1.0, 4, 16),
+]
+
+
+@pytest.mark.parametrize("M,alpha,r,k,leaf", CONFIGS)
+def test_packed_hmatrix_matches_oracle(M, alpha, r, k, leaf):
+    t = W.graded_mesh(M, 1.0, r)
+    plan = mg.Plan(1, 15, M, alpha, k=k, t=t, leaf=leaf)
+    Rt_lib = plan.export_dense()
+    Rt_or = oracle.hmatrix_dense(t, alpha, k, leaf)
+    scale = np.max(np.abs(np.diag(Rt_or)))
+    assert np.max(np.abs(Rt_lib - Rt_or)) <= 1e-13 * scale
+    info = plan.info()
+    parts = oracle.block_partition(t, leaf)
+    assert info["ndense"] == sum(1 for kind, _, _ in parts if kind == "full")
+    assert info["nrk"] == sum(1 for kind, _, _ in parts if kind == "rk")
+    tt, a1 = plan.mesh()
+    assert np.array_equal(tt, t)
+    assert np.max(np.abs(a1 - oracle.initial_value_weights(t, alpha)) / np.abs(a1)) < 1e-13
+
+
+def test_mesh_formula_when_no_mesh_given():
+    plan = mg.Plan(1, 15, 64, 0.4, k=6, r=4.0, T=2.0)
+    t, _ = plan.mesh()
+    assert np.max(np.abs(t - W.graded_mesh(64, 2.0, 4.0))) <= 4e-16 * 2.0
+
+
+def test_workspace_grows_with_grid():
+    a = mg.Plan(2, 31, 64, 0.5, k=6, r=3.0).workspace_bytes()
+    b = mg.Plan(2, 63, 64, 0.5, k=6, r=3.0).workspace_bytes()
+    assert b > 3 * a
+
+
+@pytest.mark.parametrize("args", ["128 0.5 3 8 16 40", "4096 0.5 3 10 16 20", "2048 0.2 9 10 16 16",
+                                  "300 0.7 1.857 6 12 17", "100 0.5 1 10 7 16"])
+def test_kernel_algorithm_emulated_on_cpu(args):
+    """The kernel's per-leaf program (ring of recent leaves, stacked far field,
+    accumulator slots, MFMA operand layout) emulated lane by lane on the CPU
+    reproduces R~ x and (R~ + c I)^{-1} b of the plan's dense expansion."""
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    with tempfile.TemporaryDirectory() as d:
+        exe = os.path.join(d, "emu")
+        subprocess.run([gxx, "-O2", "-std=c++17", "-I", os.path.join(ROOT, "include"),
+                        "-I", os.path.join(ROOT, "paper_1706_07632_amd", "csrc"),
+                        os.path.join(ROOT, "tests", "native", "march_emu.cpp"),
+                        os.path.join(ROOT, "paper_1706_07632_amd", "csrc", "hplan.cpp"), "-o", exe],
+                       check=True)
+        out = subprocess.run([exe] + args.split(), check=True, capture_output=True, text=True).stdout.split()
+    assert float(out[0]) < 1e-12 and float(out[1]) < 1e-12, out
