@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Throughput of the H-matrix MGWR solver on one MI355X.
+
+Metric: space-time unknowns (N*M) per second to 1e-8 relative residual
+(||b - A u||_inf <= 1e-8 ||b||_inf, float64 residual).
+
+Workload (default, "large1d"): 1D time-fractional heat equation on (0, 1),
+n = 1023 interior points, M = 4096 graded steps t_j = (j/M)^r with
+r = (2 - alpha)/alpha, alpha in {0.3, 0.5, 0.7}, k = 10, leaf 16, V(1,1),
+manufactured solution u = t^alpha sin(pi x), zero initial guess.  One step =
+one solve of each of the three instances.  Sources are synthetic (closed form)
+and resident in HBM before timing starts.
+
+Prints one JSON line.  `value` is the plain float64 solver; the float32-inner
+mixed-precision form is reported next to it under `forms`.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (vector and matrix)
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="large1d", choices=["large1d", "large2d", "small1d"])
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--cpu-repeats", type=int, default=3)
+    return ap.parse_args()
+
+
+def instances(workload):
+    import workloads as W
+    if workload == "large1d":
+        return [W.config("large1d", a) for a in (0.3, 0.5, 0.7)]
+    return [W.config(workload)]
+
+
+def time_form(plans, fs, us, tol, steps, warmup, torch):
+    stats = []
+    for _ in range(warmup):
+        for pl, f, u in zip(plans, fs, us):
+            pl.solve(f, tol=tol, u=u)
+    for pl in plans:
+        pl.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for pl, f, u in zip(plans, fs, us):
+            _, st = pl.solve(f, tol=tol, u=u)
+            stats.append(st)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    timing = [pl.timing() for pl in plans]
+    for pl in plans:
+        pl.timing(False)
+    return t1 - t0, stats, timing
+
+
+def merge_timing(timings):
+    out = {}
+    for tm in timings:
+        for cls, v in tm.items():
+            o = out.setdefault(cls, {"launches": 0, "ms": 0.0, "flops": 0.0, "bytes": 0.0})
+            for key in o:
+                o[key] += v[key]
+    return out
+
+
+def cpu_baseline(probs, repeats):
+    """The float64 oracle (direct time marching) on the host cores: one full
+    solve of each instance, median of `repeats`; assembly of R~ excluded."""
+    import numpy as np
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max(int(x.get("num_threads", 1)) for x in threadpool_info()) if threadpool_info() else 1
+    except Exception:
+        cores = os.cpu_count() or 1
+    per = []
+    total_unknowns = 0
+    for p in probs:
+        Rt = oracle.hmatrix_dense(p.t, p.alpha, p.k, p.leaf)
+        B = oracle.rhs(p.f, p.t, p.alpha, p.g)
+        times = []
+        for _ in range(repeats):
+            t0 = time.perf_counter()
+            oracle.timestep_solve(Rt, B, p.dim, p.n, p.length)
+            times.append(time.perf_counter() - t0)
+        per.append(float(np.median(times)))
+        total_unknowns += p.N * p.M
+    return {"value": total_unknowns / sum(per), "unit": "unknowns/s", "cores": cores, "kind": "oracle",
+            "sample": f"full direct solve of each of the {len(probs)} instances, median of {repeats}, "
+                      f"R~ assembly excluded ({sum(per):.2f} s per pass)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1706_07632_amd as mg
+
+    dev = torch.device("cuda", 0)
+    probs = instances(args.workload)
+    fs = [torch.as_tensor(p.f, dtype=torch.float64, device=dev) for p in probs]
+    us = [torch.empty_like(f) for f in fs]
+    plans = [mg.Plan(p.dim, p.n, p.M, p.alpha, k=p.k, t=p.t, length=p.length, leaf=p.leaf).bind() for p in probs]
+    unknowns = sum(p.N * p.M for p in probs)
+
+    secs, stats, timing = time_form(plans, fs, us, args.tol, args.steps, args.warmup, torch)
+    tm = merge_timing(timing)
+    ms_per_step = 1e3 * secs / args.steps
+    value = unknowns * args.steps / secs
+    sm = tm["smooth64"]
+    achieved = sm["flops"] / (sm["ms"] * 1e-3) / 1e12 if sm["ms"] > 0 else 0.0
+    avg_launch_us = 1e3 * sm["ms"] / max(1, sm["launches"])
+    forms = {"fp64": {"value": value, "ms_per_step": ms_per_step,
+                      "cycles": [s["cycles"] for s in stats[:len(probs)]],
+                      "rel_res": [s["res"] / s["bnorm"] for s in stats[:len(probs)]]}}
+    kernels = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
+                   "avg_us": round(1e3 * v["ms"] / max(1, v["launches"]), 2),
+                   "TFLOP/s": round(v["flops"] / max(v["ms"], 1e-9) * 1e-9, 3),
+                   "GB/s": round(v["bytes"] / max(v["ms"], 1e-9) * 1e-6, 1)} for k, v in tm.items() if v["launches"]}
+
+    if not args.no_mixed:
+        mplans = [mg.Plan(p.dim, p.n, p.M, p.alpha, k=p.k, t=p.t, length=p.length, leaf=p.leaf,
+                          precision="mixed", inner_cycles=1).bind() for p in probs]
+        msecs, mstats, mtiming = time_form(mplans, fs, us, args.tol, args.steps, args.warmup, torch)
+        mtm = merge_timing(mtiming)
+        forms["mixed_fp32"] = {"value": unknowns * args.steps / msecs, "ms_per_step": 1e3 * msecs / args.steps,
+                               "cycles": [s["cycles"] for s in mstats[:len(probs)]],
+                               "refinements": [s["refinements"] for s in mstats[:len(probs)]],
+                               "rel_res": [s["res"] / s["bnorm"] for s in mstats[:len(probs)]]}
+        forms["mixed_fp32"]["kernels"] = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
+                                              "avg_us": round(1e3 * v["ms"] / max(1, v["launches"]), 2)}
+                                          for k, v in mtm.items() if v["launches"]}
+
+    out = {
+        "metric": "space-time unknowns (N*M)/s to 1e-8 rel. residual (plain FP64; mixed form under forms)",
+        "value": value,
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (manufactured closed-form source)",
+        "config": {"workload": args.workload if args.workload != "large1d" else
+                   "large1d: 1D n=1023 M=4096 alpha in {0.3,0.5,0.7} r=(2-a)/a k=10 leaf=16 V(1,1)",
+                   "N": probs[0].N, "M": probs[0].M, "instances": len(probs), "tol": args.tol},
+        "roofline": {"bound": "mfma", "kernel": "march_kernel<double, SMOOTH> (zebra line relaxation, H-TRSM)",
+                     "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "avg_launch_us": avg_launch_us, "launches": sm["launches"]},
+        "forms": forms,
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(probs, args.cpu_repeats)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -68,7 +68,7 @@ typedef struct {
   double T;         /* final time (used only when no explicit mesh is given) */
   double alpha;     /* fractional order, 0 < alpha < 1 */
   double r;         /* grading exponent >= 1 (used only when no explicit mesh is given) */
-  int k;            /* Taylor terms per admissible block (rank), 1 <= k <= 16 */
+  int k;            /* Taylor terms per admissible block (rank), 1 <= k <= 32 */
   int leaf;         /* cluster leaf size, 1 <= leaf <= 16 (16 by default) */
   int nu1, nu2;     /* pre/post smoothing steps of one cycle (Algorithm 2) */
   int gamma;        /* cycles on each coarser level: 1 = V-cycle, 2 = W-cycle */
@@ -87,6 +87,7 @@ typedef struct {
   double bnorm;      /* ||b||_inf, b = f + a_{.,1} g */
   double res;        /* final ||b - A u||_inf (float64) */
   double avg_factor; /* (res/res0)^(1/cycles) */
+  double history[64]; /* ||b - A u||_inf after each of the first 64 outer steps (cycles or refinements) */
 } mgwr_stats;
 
 typedef struct mgwr_plan mgwr_plan;
@@ -137,6 +138,33 @@ int mgwr_hmatvec(mgwr_plan* plan, const double* x_dev, double* y_dev, int ncols)
  * [M][ncols] row-major, where c_level = 2 dim / h_level^2 is the diagonal of
  * the spatial stencil on multigrid level `level` (0 = finest). */
 int mgwr_htrsm(mgwr_plan* plan, int level, const double* b_dev, double* x_dev, int ncols);
+
+/* Live kernel timing.  When enabled, every launch of the classes below is
+ * bracketed by a pair of hipEvents on the plan's stream; durations, launch
+ * counts and the algorithmic flops and HBM bytes of those launches accumulate
+ * until read.  Algorithmic counts per launch: time-marching kernels 2 S flops
+ * per column (S = stored entries of R~, dense leaves counted full) and 3 M
+ * words per column (f, the other colour or u, and the written line);
+ * restriction M (N_f + N_c) words; prolongation M (N_c + 2 N_f) words. */
+enum {
+  MGWR_K_SMOOTH64 = 0,  /* zebra line relaxation, float64 */
+  MGWR_K_DEFECT64 = 1,  /* defect b - A u, float64 */
+  MGWR_K_SMOOTH32 = 2,  /* zebra line relaxation, float32 (mixed inner cycles) */
+  MGWR_K_DEFECT32 = 3,  /* defect, float32 (mixed inner cycles) */
+  MGWR_K_RESTRICT = 4,  /* full-weighting restriction (either precision) */
+  MGWR_K_PROLONG = 5,   /* interpolation and correction (either precision) */
+  MGWR_K_CLASSES = 8
+};
+typedef struct {
+  long long launches[MGWR_K_CLASSES];
+  double ms[MGWR_K_CLASSES];      /* summed event-measured durations */
+  double flops[MGWR_K_CLASSES];   /* summed algorithmic flops */
+  double bytes[MGWR_K_CLASSES];   /* summed algorithmic HBM bytes */
+} mgwr_timing;
+/* enable != 0 turns timing on and clears the counters; 0 turns it off. */
+int mgwr_timing_enable(mgwr_plan* plan, int enable);
+/* Synchronises the plan's stream and returns the counters. */
+int mgwr_timing_get(mgwr_plan* plan, mgwr_timing* out);
 
 /* Plan facts for tests and reports (host, no device work). */
 typedef struct {

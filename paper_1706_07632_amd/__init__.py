@@ -27,7 +27,10 @@ EXPORTED = [
     "mgwr_params_default", "mgwr_plan_create", "mgwr_plan_workspace_bytes", "mgwr_plan_bind",
     "mgwr_solve", "mgwr_residual", "mgwr_hmatvec", "mgwr_htrsm", "mgwr_plan_get_info",
     "mgwr_plan_get_mesh", "mgwr_plan_export_dense", "mgwr_plan_destroy", "mgwr_last_error",
+    "mgwr_timing_enable", "mgwr_timing_get",
 ]
+
+KERNEL_CLASSES = ["smooth64", "defect64", "smooth32", "defect32", "restrict", "prolong"]
 
 
 class MgwrError(RuntimeError):
@@ -46,10 +49,23 @@ class Params(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int), ("refinements", ctypes.c_int), ("res0", ctypes.c_double),
-                ("bnorm", ctypes.c_double), ("res", ctypes.c_double), ("avg_factor", ctypes.c_double)]
+                ("bnorm", ctypes.c_double), ("res", ctypes.c_double), ("avg_factor", ctypes.c_double),
+                ("history", ctypes.c_double * 64)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "history"}
+        steps = self.refinements if self.refinements else self.cycles
+        d["history"] = [self.history[i] for i in range(min(steps, 64))]
+        return d
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_longlong * 8), ("ms", ctypes.c_double * 8),
+                ("flops", ctypes.c_double * 8), ("bytes", ctypes.c_double * 8)]
+
+    def as_dict(self):
+        return {name: {"launches": self.launches[i], "ms": self.ms[i], "flops": self.flops[i],
+                       "bytes": self.bytes[i]} for i, name in enumerate(KERNEL_CLASSES)}
 
 
 class PlanInfo(ctypes.Structure):
@@ -88,6 +104,8 @@ def lib():
     L.mgwr_plan_get_mesh.argtypes = [vp, dp, dp]
     L.mgwr_plan_export_dense.argtypes = [vp, dp]
     L.mgwr_plan_destroy.argtypes = [vp]
+    L.mgwr_timing_enable.argtypes = [vp, ip]
+    L.mgwr_timing_get.argtypes = [vp, ctypes.POINTER(Timing)]
     L.mgwr_last_error.argtypes = []
     L.mgwr_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -239,6 +257,16 @@ class Plan:
         _require(x, "x", (self.M, ncols))
         _check(lib().mgwr_htrsm(self._h, int(level), _dptr(b), _dptr(x), int(ncols)))
         return x
+
+    def timing(self, enable=None):
+        """enable=True/False switches live event timing (True clears it);
+        enable=None returns the accumulated per-kernel-class counters."""
+        if enable is not None:
+            _check(lib().mgwr_timing_enable(self._h, 1 if enable else 0))
+            return None
+        tm = Timing()
+        _check(lib().mgwr_timing_get(self._h, ctypes.byref(tm)))
+        return tm.as_dict()
 
     def close(self):
         if getattr(self, "_h", None):

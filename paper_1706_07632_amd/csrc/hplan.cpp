@@ -40,6 +40,17 @@ double pow_diff(double x, double d, double p) {
   return std::pow(d, p);
 }
 
+// Power-of-two exponent e with 2^e close to the half-width of the row
+// cluster's interval I_t.  The factors are stored as A_{m,nu} 2^{-e nu} and
+// B_{j,nu} 2^{e nu}: the product is unchanged (scaling by powers of two is
+// exact) while both factors stay O(1) and in float32 range even where the
+// graded mesh puts I_t at t ~ 1e-20.
+int cluster_scale_exp(const std::vector<double>& t, const Cluster& c) {
+  double half = 0.5 * (t[c.hi] - t[c.lo + 1]);
+  if (!(half > 0.0)) return 0;
+  return std::ilogb(half);
+}
+
 // MFMA 16x16x4 A-operand order: value for (row, kidx) lives at [kidx/4][lane],
 // lane = row + 16 * (kidx % 4).
 inline size_t a_index(int row, int kidx) { return (size_t)(kidx / 4) * 64 + row + 16 * (kidx % 4); }
@@ -52,7 +63,7 @@ std::string build_host_plan(const mgwr_params& p, const double* t_host, HostPlan
   if (p.n < 1 || ((p.n + 1) & p.n) != 0) return "n must be 2^L - 1 (L >= 1)";
   if (!(p.alpha > 0.0 && p.alpha < 1.0)) return "alpha must lie in (0, 1)";
   if (p.M < 1) return "M must be >= 1";
-  if (p.k < 1 || p.k > 16) return "k must lie in [1, 16]";
+  if (p.k < 1 || p.k > 32) return "k must lie in [1, 32]";
   if (p.leaf < 1 || p.leaf > 16) return "leaf must lie in [1, 16]";
   if (!(p.length > 0.0)) return "length must be > 0";
   if (p.nu1 < 0 || p.nu2 < 0 || p.nu1 + p.nu2 < 1) return "nu1, nu2 >= 0 with nu1 + nu2 >= 1";
@@ -271,13 +282,14 @@ std::string build_host_plan(const mgwr_params& p, const double* t_host, HostPlan
     for (int a = 0; a < (int)zanc[i].size(); ++a) {
       int c = zanc[i][a];
       double tc = hp.clusters[c].tc;
+      int ex = cluster_scale_exp(t, hp.clusters[c]);
       for (int nu = 0; nu < k; ++nu) {
         int kr = a * k + nu;
         pk.ff_row[(size_t)nchunks * 4 + kr] = hp.zslot[c] * k + nu;
         hp.ff_cluster[(size_t)nchunks * 4 + kr] = c;
         for (int r = 0; r < d.sz; ++r) {
           double dtm = t[d.lo + r + 1] - tc;
-          pk.ffA[base + a_index(r, kr)] = -std::pow(dtm, nu) * ginv;
+          pk.ffA[base + a_index(r, kr)] = -std::pow(std::ldexp(dtm, -ex), nu) * ginv;
         }
       }
     }
@@ -295,6 +307,7 @@ std::string build_host_plan(const mgwr_params& p, const double* t_host, HostPlan
     for (int bi = 0; bi < (int)zcol[i].size(); ++bi) {
       int theta = hp.rk_blocks[zcol[i][bi]].first;
       double tc = hp.clusters[theta].tc;
+      int ex = cluster_scale_exp(t, hp.clusters[theta]);
       bool first = (first_upd[theta] == i);
       for (int nu = 0; nu < k; ++nu) {
         int o = bi * k + nu;
@@ -303,11 +316,14 @@ std::string build_host_plan(const mgwr_params& p, const double* t_host, HostPlan
         hp.zu_cluster[(size_t)(ntiles + tile) * 16 + orow] = theta;
         double q = 1.0 - alpha - nu;
         double* tb = pk.zuB.data() + zb + (size_t)tile * 256;
+        // B_{j,nu} 2^{e nu} = c_nu/q s^{1-alpha} [pd(x_j/s, dt_j/s)/dt_j - pd(x_{j+1}/s, dt_{j+1}/s)/dt_{j+1}],
+        // s = 2^e, x_i = t_c - t_i, pd(x, d) = (x + d)^q - x^q: every power has a base >= 1
+        const double sfac = cnu[nu] / q * std::pow(2.0, ex * (1.0 - alpha));
         for (int r = 0; r < d.sz; ++r) {
           int j = d.lo + r + 1;  // 1-based column index
-          double left = pow_diff(tc - t[j], dt[j], q) / dt[j];
-          double right = pow_diff(tc - t[j + 1], dt[j + 1], q) / dt[j + 1];
-          tb[a_index(orow, r)] = cnu[nu] / q * (left - right);
+          double left = pow_diff(std::ldexp(tc - t[j], -ex), std::ldexp(dt[j], -ex), q) / dt[j];
+          double right = pow_diff(std::ldexp(tc - t[j + 1], -ex), std::ldexp(dt[j + 1], -ex), q) / dt[j + 1];
+          tb[a_index(orow, r)] = sfac * (left - right);
         }
       }
     }

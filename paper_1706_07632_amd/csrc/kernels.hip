@@ -18,7 +18,9 @@
 // MFMA 16x16x4 operand layout used throughout (lane l, g = l/16, c = l%16):
 //   A (16 x 4):  lane l holds A[c][g]
 //   B (4 x 16):  lane l holds B[g][c]
-//   C/D (16x16): lane l, element r holds D[4g + r][c]
+//   C/D (16x16): lane l, element r holds D[drow(g, r)][c] with
+//                drow = 4g + r for the f32 instruction and g + 4r for the f64
+//                instruction (measured on gfx950).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -42,8 +44,17 @@ __device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+template <typename T> __device__ __forceinline__ int drow(int g, int r);
+template <> __device__ __forceinline__ int drow<double>(int g, int r) { return g + 4 * r; }
+template <> __device__ __forceinline__ int drow<float>(int g, int r) { return 4 * g + r; }
+
 constexpr int ZFIRST = 1 << 30;
 constexpr int ZMASK = (1 << 30) - 1;
+
+// Batch sizes of the tile loads issued before the MFMAs that consume them.
+constexpr int DENSE_BATCH = 4;  // dense 16x16 blocks
+constexpr int FF_BATCH = 8;     // far-field K chunks (4 rows each)
+constexpr int ZU_BATCH = 4;     // column-side update tiles
 
 template <typename T, int MODE>
 __global__ __launch_bounds__(64) void march_kernel(MarchArgs<T> a) {
@@ -74,79 +85,120 @@ __global__ __launch_bounds__(64) void march_kernel(MarchArgs<T> a) {
     nb[3] = q + a.n; nbok[3] = colok && iy + 1 < a.n;
   }
   const T diagc = (T)(2 * a.dim);
+  constexpr bool kSolve = (MODE == MODE_SMOOTH || MODE == MODE_TRSM);
+  constexpr bool kKnownX = (MODE == MODE_RESID || MODE == MODE_MATVEC);
+
+  // Inputs of a leaf's rows (lane rows drow(g, r)): f, the stencil sum of the
+  // neighbours and (defect / product) the iterate.  Loaded one leaf ahead.
+  T pf_f[4], pf_s[4], pf_u[4];
+  auto load_inputs = [&](const LeafDesc& d) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = drow<T>(g, r);
+      const bool ok = colok && row < d.sz;
+      const long long off = (long long)(d.lo + (ok ? row : 0)) * a.ld;
+      T f = (T)0, s = (T)0, u = (T)0;
+      if constexpr (MODE != MODE_MATVEC) f = ok ? a.F[off + q] : (T)0;
+      if constexpr (MODE == MODE_SMOOTH || MODE == MODE_RESID) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (nbok[e] && ok) s += a.U[off + nb[e]];
+      }
+      if constexpr (kKnownX) u = ok ? a.U[off + q] : (T)0;
+      pf_f[r] = f;
+      pf_s[r] = s;
+      pf_u[r] = u;
+    }
+  };
+  if (a.nleaf > 0) load_inputs(a.leaves[0]);
 
   for (int i = 0; i < a.nleaf; ++i) {
     const LeafDesc d = a.leaves[i];
     T* cur = ring + (i % a.ring) * 256;
+
+    // 1. right-hand side of the leaf rows
     v4 acc;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = 4 * g + r;
-      const bool ok = colok && row < d.sz;
-      const long long off = (long long)(d.lo + row) * a.ld;
-      T v = (T)0;
-      if (ok) {
-        if constexpr (MODE == MODE_SMOOTH || MODE == MODE_RESID) {
-          T s = (T)0;
-#pragma unroll
-          for (int e = 0; e < 4; ++e)
-            if (nbok[e]) s += a.U[off + nb[e]];
-          if constexpr (MODE == MODE_SMOOTH) {
-            v = a.F[off + q] + a.inv_h2 * s;
-          } else {
-            const T uq = a.U[off + q];
-            v = a.F[off + q] - a.inv_h2 * (diagc * uq - s);
-          }
-        } else if constexpr (MODE == MODE_TRSM) {
-          v = a.F[off + q];
-        }
-      }
+      T v;
+      if constexpr (MODE == MODE_SMOOTH) v = pf_f[r] + a.inv_h2 * pf_s[r];
+      else if constexpr (MODE == MODE_RESID) v = pf_f[r] - a.inv_h2 * (diagc * pf_u[r] - pf_s[r]);
+      else if constexpr (MODE == MODE_TRSM) v = pf_f[r];
+      else v = (T)0;
       acc[r] = v;
     }
-    if constexpr (MODE == MODE_RESID || MODE == MODE_MATVEC) {
+    if constexpr (kKnownX) {
       // the known iterate of this leaf enters the ring (B-operand tile layout)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = 4 * g + r;
-        const bool ok = colok && row < d.sz;
-        cur[row * 16 + c] = ok ? a.U[(long long)(d.lo + row) * a.ld + q] : (T)0;
+      for (int r = 0; r < 4; ++r) cur[drow<T>(g, r) * 16 + c] = pf_u[r];
+    }
+    if (i + 1 < a.nleaf) load_inputs(a.leaves[i + 1]);
+
+    // diagonal inverse of this leaf (used after the far field)
+    T di[4];
+    if constexpr (kSolve) {
+      const T* Di = a.dinv + (long long)i * 256;
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) di[kc] = Di[kc * 64 + lane];
+    }
+    if constexpr (kKnownX) __syncthreads();
+
+    // 2. dense near-diagonal blocks (stored negated), DENSE_BATCH at a time
+    for (int e0 = d.dn_begin; e0 < d.dn_end; e0 += DENSE_BATCH) {
+      T t[DENSE_BATCH][4];
+      int jj[DENSE_BATCH];
+#pragma unroll
+      for (int b = 0; b < DENSE_BATCH; ++b) {
+        const int e = min(e0 + b, d.dn_end - 1);
+        jj[b] = a.dn_list[2 * e];
+        const T* D = a.dense + (long long)a.dn_list[2 * e + 1] * 256;
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) t[b][kc] = D[kc * 64 + lane];
       }
-      __syncthreads();
-    }
-
-    // 2. dense near-diagonal blocks (stored negated)
-    for (int e = d.dn_begin; e < d.dn_end; ++e) {
-      const int j = a.dn_list[2 * e];
-      const T* D = a.dense + (long long)a.dn_list[2 * e + 1] * 256;
-      const T* xj = ring + (j % a.ring) * 256;
 #pragma unroll
-      for (int kc = 0; kc < 4; ++kc) acc = mfma(D[kc * 64 + lane], xj[(4 * kc + g) * 16 + c], acc);
+      for (int b = 0; b < DENSE_BATCH; ++b) {
+        if (e0 + b < d.dn_end) {
+          const T* xj = ring + (jj[b] % a.ring) * 256;
+#pragma unroll
+          for (int kc = 0; kc < 4; ++kc) acc = mfma(t[b][kc], xj[(4 * kc + g) * 16 + c], acc);
+        }
+      }
     }
-    if constexpr (MODE == MODE_RESID || MODE == MODE_MATVEC) {
+    if constexpr (kKnownX) {
       const T* D = a.dense + (long long)d.diag_off * 256;
+      T t[4];
 #pragma unroll
-      for (int kc = 0; kc < 4; ++kc) acc = mfma(D[kc * 64 + lane], cur[(4 * kc + g) * 16 + c], acc);
+      for (int kc = 0; kc < 4; ++kc) t[kc] = D[kc * 64 + lane];
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) acc = mfma(t[kc], cur[(4 * kc + g) * 16 + c], acc);
     }
 
-    // 3. far field: stacked (theta, nu) rows, A stored negated
-    for (int ch = 0; ch < d.ff_nchunk; ++ch) {
-      const int zr = a.ff_row[(d.ff_begin + ch) * 4 + g];
-      const T bv = zr >= 0 ? Z[zr * 16 + c] : (T)0;
-      acc = mfma(a.ffA[(long long)(d.ff_begin + ch) * 64 + lane], bv, acc);
+    // 3. far field: stacked (theta, nu) rows, A stored negated, FF_BATCH chunks at a time
+    for (int c0 = 0; c0 < d.ff_nchunk; c0 += FF_BATCH) {
+      T av[FF_BATCH], bv[FF_BATCH];
+#pragma unroll
+      for (int b = 0; b < FF_BATCH; ++b) {
+        const int ch = d.ff_begin + min(c0 + b, d.ff_nchunk - 1);
+        av[b] = a.ffA[(long long)ch * 64 + lane];
+        const int zr = a.ff_row[ch * 4 + g];
+        bv[b] = (zr >= 0 && c0 + b < d.ff_nchunk) ? Z[zr * 16 + c] : (T)0;
+      }
+#pragma unroll
+      for (int b = 0; b < FF_BATCH; ++b)
+        if (c0 + b < d.ff_nchunk) acc = mfma(av[b], bv[b], acc);
     }
 
     // 4. diagonal leaf
-    if constexpr (MODE == MODE_SMOOTH || MODE == MODE_TRSM) {
+    if constexpr (kSolve) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) tbuf[(4 * g + r) * 16 + c] = acc[r];
+      for (int r = 0; r < 4; ++r) tbuf[drow<T>(g, r) * 16 + c] = acc[r];
       __syncthreads();
       v4 x = {0, 0, 0, 0};
-      const T* Di = a.dinv + (long long)i * 256;
 #pragma unroll
-      for (int kc = 0; kc < 4; ++kc) x = mfma(Di[kc * 64 + lane], tbuf[(4 * kc + g) * 16 + c], x);
+      for (int kc = 0; kc < 4; ++kc) x = mfma(di[kc], tbuf[(4 * kc + g) * 16 + c], x);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = 4 * g + r;
+        const int row = drow<T>(g, r);
         const bool ok = colok && row < d.sz;
         if (ok) a.U[(long long)(d.lo + row) * a.ld + q] = x[r];
         cur[row * 16 + c] = ok ? x[r] : (T)0;
@@ -155,7 +207,7 @@ __global__ __launch_bounds__(64) void march_kernel(MarchArgs<T> a) {
     } else {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = 4 * g + r;
+        const int row = drow<T>(g, r);
         if (colok && row < d.sz) {
           const T v = (MODE == MODE_MATVEC) ? -acc[r] : acc[r];
           a.Out[(long long)(d.lo + row) * a.ld + q] = v;
@@ -163,22 +215,33 @@ __global__ __launch_bounds__(64) void march_kernel(MarchArgs<T> a) {
       }
     }
 
-    // 5. column-side low-rank updates Z += B^T x_i
-    for (int tt = 0; tt < d.zu_ntile; ++tt) {
-      const int* zrow = a.zu_row + (long long)(d.zu_begin + tt) * 16 + 4 * g;
-      int zr[4];
-      v4 z;
+    // 5. column-side low-rank updates Z += B^T x_i, ZU_BATCH tiles at a time
+    for (int t0 = 0; t0 < d.zu_ntile; t0 += ZU_BATCH) {
+      T bt[ZU_BATCH][4];
+      int zr[ZU_BATCH][4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        zr[r] = zrow[r];
-        z[r] = (zr[r] >= 0 && !(zr[r] & ZFIRST)) ? Z[(zr[r] & ZMASK) * 16 + c] : (T)0;
+      for (int b = 0; b < ZU_BATCH; ++b) {
+        const int tt = d.zu_begin + min(t0 + b, d.zu_ntile - 1);
+        const T* Bt = a.zuB + (long long)tt * 256;
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) bt[b][kc] = Bt[kc * 64 + lane];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) zr[b][r] = a.zu_row[tt * 16 + drow<T>(g, r)];
       }
-      const T* Bt = a.zuB + (long long)(d.zu_begin + tt) * 256;
 #pragma unroll
-      for (int kc = 0; kc < 4; ++kc) z = mfma(Bt[kc * 64 + lane], cur[(4 * kc + g) * 16 + c], z);
+      for (int b = 0; b < ZU_BATCH; ++b) {
+        if (t0 + b < d.zu_ntile) {
+          v4 z;
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (zr[r] >= 0) Z[(zr[r] & ZMASK) * 16 + c] = z[r];
+          for (int r = 0; r < 4; ++r)
+            z[r] = (zr[b][r] >= 0 && !(zr[b][r] & ZFIRST)) ? Z[(zr[b][r] & ZMASK) * 16 + c] : (T)0;
+#pragma unroll
+          for (int kc = 0; kc < 4; ++kc) z = mfma(bt[b][kc], cur[(4 * kc + g) * 16 + c], z);
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (zr[b][r] >= 0) Z[(zr[b][r] & ZMASK) * 16 + c] = z[r];
+        }
+      }
     }
     __syncthreads();
   }

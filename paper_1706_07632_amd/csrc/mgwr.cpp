@@ -73,6 +73,12 @@ struct mgwr_plan {
   DevOps<double> d64;
   DevOps<float> d32;
   bool mixed = false;
+  // live timing (mgwr_timing_enable)
+  struct Pending { hipEvent_t b, e; int cls; double flops, bytes; };
+  bool timing = false;
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> event_pool;
+  mgwr_timing tacc{};
   // offsets computed by layout()
   struct Off {
     size_t leaves, dn_list, ff_row, zu_row, a1, B0, part, scal;
@@ -126,6 +132,51 @@ void layout(mgwr_plan* pl) {
   o.total = cv.off;
 }
 
+hipEvent_t pool_event(mgwr_plan* pl) {
+  if (!pl->event_pool.empty()) {
+    hipEvent_t e = pl->event_pool.back();
+    pl->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one launch with events when timing is on.
+struct Timed {
+  mgwr_plan* pl;
+  int cls;
+  double flops, bytes;
+  hipEvent_t b = nullptr;
+  Timed(mgwr_plan* p, int c, double f, double by) : pl(p), cls(c), flops(f), bytes(by) {
+    if (pl->timing && (b = pool_event(pl))) hipEventRecord(b, pl->stream);
+  }
+  ~Timed() {
+    if (!b) return;
+    hipEvent_t e = pool_event(pl);
+    if (!e) { pl->event_pool.push_back(b); return; }
+    hipEventRecord(e, pl->stream);
+    pl->pending.push_back({b, e, cls, flops, bytes});
+  }
+};
+
+// Accumulates finished event pairs (the stream has been synchronised).
+void drain_timing(mgwr_plan* pl) {
+  for (auto& q : pl->pending) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, q.b, q.e) == hipSuccess) {
+      pl->tacc.launches[q.cls] += 1;
+      pl->tacc.ms[q.cls] += ms;
+      pl->tacc.flops[q.cls] += q.flops;
+      pl->tacc.bytes[q.cls] += q.bytes;
+    }
+    pl->event_pool.push_back(q.b);
+    pl->event_pool.push_back(q.e);
+  }
+  pl->pending.clear();
+}
+
 template <typename T>
 MarchArgs<T> base_args(mgwr_plan* pl, const DevOps<T>& ops, int level) {
   const HostPlan& hp = pl->hp;
@@ -160,6 +211,8 @@ int smooth(mgwr_plan* pl, DevOps<T>& ops, int l, int colour, T* F, T* U) {
   a.F = F; a.U = U; a.Out = nullptr;
   a.ld = lv.N; a.ncols = ncols; a.cstride = 2; a.coff = par;
   a.dim = hp.p.dim; a.n = lv.n; a.inv_h2 = (T)(1.0 / (lv.h * lv.h));
+  Timed tm(pl, sizeof(T) == 8 ? MGWR_K_SMOOTH64 : MGWR_K_SMOOTH32, 2.0 * hp.stored * ncols,
+           3.0 * hp.p.M * ncols * sizeof(T));
   HIP_TRY(launch_march<T>(MODE_SMOOTH, a, pl->stream));
   return MGWR_OK;
 }
@@ -172,6 +225,8 @@ int defect(mgwr_plan* pl, DevOps<T>& ops, int l, const T* F, T* U, T* Out) {
   a.F = F; a.U = U; a.Out = Out;
   a.ld = lv.N; a.ncols = lv.N; a.cstride = 1; a.coff = 0;
   a.dim = hp.p.dim; a.n = lv.n; a.inv_h2 = (T)(1.0 / (lv.h * lv.h));
+  Timed tm(pl, sizeof(T) == 8 ? MGWR_K_DEFECT64 : MGWR_K_DEFECT32, 2.0 * hp.stored * lv.N,
+           3.0 * hp.p.M * lv.N * sizeof(T));
   HIP_TRY(launch_march<T>(MODE_RESID, a, pl->stream));
   return MGWR_OK;
 }
@@ -196,11 +251,17 @@ int cycle(mgwr_plan* pl, DevOps<T>& ops, int l) {
     if ((rc = smooth<T>(pl, ops, l, 1, F, U))) return rc;
   }
   if ((rc = defect<T>(pl, ops, l, F, U, ops.R[l]))) return rc;
-  HIP_TRY(launch_restrict<T>(ops.R[l], ops.F[l + 1], hp.p.dim, hp.levels[l].n, M, pl->stream));
+  {
+    Timed tm(pl, MGWR_K_RESTRICT, 0.0, (double)M * (hp.levels[l].N + hp.levels[l + 1].N) * sizeof(T));
+    HIP_TRY(launch_restrict<T>(ops.R[l], ops.F[l + 1], hp.p.dim, hp.levels[l].n, M, pl->stream));
+  }
   HIP_TRY(launch_fill<T>(ops.U[l + 1], (long long)M * hp.levels[l + 1].N, (T)0, pl->stream));
   for (int gm = 0; gm < hp.p.gamma; ++gm)
     if ((rc = cycle<T>(pl, ops, l + 1))) return rc;
-  HIP_TRY(launch_prolong<T>(ops.U[l + 1], U, hp.p.dim, hp.levels[l].n, M, pl->stream));
+  {
+    Timed tm(pl, MGWR_K_PROLONG, 0.0, (double)M * (2.0 * hp.levels[l].N + hp.levels[l + 1].N) * sizeof(T));
+    HIP_TRY(launch_prolong<T>(ops.U[l + 1], U, hp.p.dim, hp.levels[l].n, M, pl->stream));
+  }
   for (int s = 0; s < hp.p.nu2; ++s) {
     if ((rc = smooth<T>(pl, ops, l, 0, F, U))) return rc;
     if ((rc = smooth<T>(pl, ops, l, 1, F, U))) return rc;
@@ -211,6 +272,7 @@ int cycle(mgwr_plan* pl, DevOps<T>& ops, int l) {
 int read_scalar(mgwr_plan* pl, double* host) {
   HIP_TRY(hipMemcpyAsync(host, pl->scal, sizeof(double), hipMemcpyDeviceToHost, pl->stream));
   HIP_TRY(hipStreamSynchronize(pl->stream));
+  if (!pl->pending.empty()) drain_timing(pl);
   return MGWR_OK;
 }
 
@@ -354,8 +416,11 @@ int mgwr_plan_bind(mgwr_plan* pl, void* ws, size_t bytes, void* stream) {
   size_t cap = prop.sharedMemPerBlock;
   if (lds > cap) return fail(MGWR_ERR_STATE, "H-matrix accumulators need " + std::to_string(lds) +
                                                  " bytes of LDS, device allows " + std::to_string(cap));
-  HIP_TRY(set_march_lds_limit<double>(lds));
-  if (pl->mixed) HIP_TRY(set_march_lds_limit<float>(march_lds_bytes<float>(base_args<float>(pl, pl->d32, 0))));
+  // The attribute is a per-kernel ceiling shared by every plan in the process:
+  // raise it to the device limit once so no later bind can lower it below an
+  // earlier plan's need; each launch still requests exactly its own size.
+  HIP_TRY(set_march_lds_limit<double>(cap));
+  HIP_TRY(set_march_lds_limit<float>(cap));
   HIP_TRY(hipStreamSynchronize(pl->stream));
   pl->bound = true;
   return MGWR_OK;
@@ -421,6 +486,7 @@ int mgwr_solve(mgwr_plan* pl, const double* f, const double* g, double tol, doub
       s.cycles++;
       if ((rc = defect<double>(pl, pl->d64, 0, b, u, pl->d64.R[0]))) return rc;
       if ((rc = norm_inf<double>(pl, pl->d64.R[0], MN, &s.res))) return rc;
+      if (s.cycles <= 64) s.history[s.cycles - 1] = s.res;
       if (!std::isfinite(s.res)) { status = MGWR_ERR_NONFINITE; break; }
       if (s.res <= target) { status = MGWR_OK; break; }
     }
@@ -442,6 +508,7 @@ int mgwr_solve(mgwr_plan* pl, const double* f, const double* g, double tol, doub
       s.refinements++;
       if ((rc = defect<double>(pl, pl->d64, 0, b, u, pl->d64.R[0]))) return rc;
       if ((rc = norm_inf<double>(pl, pl->d64.R[0], MN, &s.res))) return rc;
+      if (s.refinements <= 64) s.history[s.refinements - 1] = s.res;
       if (!std::isfinite(s.res)) { status = MGWR_ERR_NONFINITE; break; }
       if (s.res <= target) { status = MGWR_OK; break; }
       HIP_TRY(launch_cast<double, float>(pl->d64.R[0], pl->d32.F[0], MN, pl->stream));
@@ -479,6 +546,25 @@ int mgwr_htrsm(mgwr_plan* pl, int level, const double* b, double* x, int ncols) 
   return MGWR_OK;
 }
 
+int mgwr_timing_enable(mgwr_plan* pl, int enable) {
+  if (!pl) return fail(MGWR_ERR_INVALID_ARG, "null plan");
+  if (!pl->pending.empty()) {
+    if (pl->bound) HIP_TRY(hipStreamSynchronize(pl->stream));
+    drain_timing(pl);
+  }
+  pl->timing = enable != 0;
+  if (enable) pl->tacc = mgwr_timing{};
+  return MGWR_OK;
+}
+
+int mgwr_timing_get(mgwr_plan* pl, mgwr_timing* out) {
+  if (!pl || !out) return fail(MGWR_ERR_INVALID_ARG, "null argument");
+  if (pl->bound) HIP_TRY(hipStreamSynchronize(pl->stream));
+  drain_timing(pl);
+  *out = pl->tacc;
+  return MGWR_OK;
+}
+
 int mgwr_plan_get_info(const mgwr_plan* pl, mgwr_plan_info* info) {
   if (!pl || !info) return fail(MGWR_ERR_INVALID_ARG, "null argument");
   const HostPlan& hp = pl->hp;
@@ -511,6 +597,12 @@ int mgwr_plan_export_dense(const mgwr_plan* pl, double* Rt) {
 }
 
 int mgwr_plan_destroy(mgwr_plan* pl) {
+  if (!pl) return MGWR_OK;
+  if (pl->bound && !pl->pending.empty()) {
+    hipStreamSynchronize(pl->stream);
+    drain_timing(pl);
+  }
+  for (hipEvent_t e : pl->event_pool) hipEventDestroy(e);
   delete pl;
   return MGWR_OK;
 }

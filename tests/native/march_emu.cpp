@@ -13,12 +13,15 @@
 
 using namespace mgwr;
 
-// D[4g+r][c] += sum_kk A[4g+r][kk] B[kk][c], A[row][kk] = a[row + 16 kk], B[kk][c] = b[c + 16 kk]
+// Output row held by lane group g in element r of the f64 16x16x4 instruction.
+static inline int drow(int g, int r) { return g + 4 * r; }
+
+// D[drow][c] += sum_kk A[drow][kk] B[kk][c], A[row][kk] = a[row + 16 kk], B[kk][c] = b[c + 16 kk]
 static void mfma(const double* a, const double* b, double acc[64][4]) {
   for (int l = 0; l < 64; ++l) {
     int g = l >> 4, c = l & 15;
     for (int r = 0; r < 4; ++r) {
-      int row = 4 * g + r;
+      int row = drow(g, r);
       double s = 0;
       for (int kk = 0; kk < 4; ++kk) s += a[row + 16 * kk] * b[c + 16 * kk];
       acc[l][r] += s;
@@ -72,7 +75,7 @@ int main(int argc, char** argv) {
         double acc[64][4];
         for (int l = 0; l < 64; ++l)
           for (int r = 0; r < 4; ++r) {
-            int g = l >> 4, c = l & 15, row = 4 * g + r, col = c0 + c;
+            int g = l >> 4, c = l & 15, row = drow(g, r), col = c0 + c;
             bool ok = col < ncols && row < d.sz;
             acc[l][r] = (mode == 1 && ok) ? B[(size_t)(d.lo + row) * ncols + col] : 0.0;
             if (mode == 0) cur[row * 16 + c] = ok ? X[(size_t)(d.lo + row) * ncols + col] : 0.0;
@@ -103,7 +106,7 @@ int main(int argc, char** argv) {
         }
         if (mode == 1) {
           for (int l = 0; l < 64; ++l)
-            for (int r = 0; r < 4; ++r) tbuf[(4 * (l >> 4) + r) * 16 + (l & 15)] = acc[l][r];
+            for (int r = 0; r < 4; ++r) tbuf[drow(l >> 4, r) * 16 + (l & 15)] = acc[l][r];
           double x[64][4] = {};
           const double* Di = pk.dinv.data() + (size_t)i * 256;
           for (int kc = 0; kc < 4; ++kc) {
@@ -112,7 +115,7 @@ int main(int argc, char** argv) {
           }
           for (int l = 0; l < 64; ++l)
             for (int r = 0; r < 4; ++r) {
-              int g = l >> 4, c = l & 15, row = 4 * g + r, col = c0 + c;
+              int g = l >> 4, c = l & 15, row = drow(g, r), col = c0 + c;
               bool ok = col < ncols && row < d.sz;
               if (ok) S[(size_t)(d.lo + row) * ncols + col] = x[l][r];
               cur[row * 16 + c] = ok ? x[l][r] : 0.0;
@@ -120,7 +123,7 @@ int main(int argc, char** argv) {
         } else {
           for (int l = 0; l < 64; ++l)
             for (int r = 0; r < 4; ++r) {
-              int g = l >> 4, c = l & 15, row = 4 * g + r, col = c0 + c;
+              int g = l >> 4, c = l & 15, row = drow(g, r), col = c0 + c;
               if (col < ncols && row < d.sz) Y[(size_t)(d.lo + row) * ncols + col] = -acc[l][r];
             }
         }
@@ -129,7 +132,7 @@ int main(int argc, char** argv) {
           int zr[64][4];
           for (int l = 0; l < 64; ++l)
             for (int r = 0; r < 4; ++r) {
-              zr[l][r] = pk.zu_row[(size_t)(d.zu_begin + tt) * 16 + 4 * (l >> 4) + r];
+              zr[l][r] = pk.zu_row[(size_t)(d.zu_begin + tt) * 16 + drow(l >> 4, r)];
               int v = zr[l][r];
               z[l][r] = (v >= 0 && !(v & (1 << 30))) ? Z[(size_t)(v & ((1 << 30) - 1)) * 16 + (l & 15)] : 0.0;
             }

@@ -147,20 +147,22 @@ def test_large1d_parity_full_size(dev, alpha):
     solution is w(t) s(x) with (R~ + lambda_h I) w = phi (one triangular solve)."""
     p = W.config("large1d", alpha)
     plan = _plan(p, dev)
-    u, st = plan.solve(_cuda(p.f, dev), tol=1e-12)
+    # the float64 relative residual of any iterate stalls near 2e-10 at h = 1/1024
+    # (rounding of A u with ||A|| ~ 4/h^2), so stop at 5e-10
+    u, st = plan.solve(_cuda(p.f, dev), tol=5e-10)
     Rt, w, s = _single_mode_reference(p)
     ref = np.outer(w, s)
     U = u.cpu().numpy()
     assert np.max(np.abs(U - ref)) / np.max(np.abs(ref)) < 1e-10, st
     cols = np.array([0, 1, 511, 512, 1000, 1022])
     r = oracle.residual_columns(Rt, U, p.f, 1, p.n, 1.0, cols)
-    assert np.max(np.abs(r)) <= 1e-12 * st["bnorm"] * 1.01
+    assert np.max(np.abs(r)) <= 5e-10 * st["bnorm"] * 1.01
 
 
 def test_large2d_parity_full_size(dev):
     p = W.config("large2d")
     plan = _plan(p, dev)
-    u, st = plan.solve(_cuda(p.f, dev), tol=1e-12)
+    u, st = plan.solve(_cuda(p.f, dev), tol=1e-10)   # residual floor here is about 1.5e-11
     Rt, w, s = _single_mode_reference(p)
     rng = np.random.default_rng(5)
     cols = np.unique(np.concatenate([[0, 1, 254, 255, 32512, 65024], rng.integers(0, p.N, 200)]))
@@ -195,3 +197,18 @@ def test_not_converged_status_and_nonfinite(dev):
     with pytest.raises(mg.MgwrError) as ei:
         plan.solve(_cuda(f, dev), tol=1e-10)
     assert ei.value.code == mg.MGWR_ERR_NONFINITE
+
+
+def test_mixed_precision_on_strongly_graded_mesh(dev):
+    """alpha = 0.3, r = 17/3, M = 4096 puts t_1 near 3e-21: the float32 copies of
+    the Taylor factors must stay in range (they are stored rescaled)."""
+    p = W.config("large1d", 0.3)
+    plan = _plan(p, dev, precision="mixed", inner_cycles=1)
+    u, st = plan.solve(_cuda(p.f, dev), tol=1e-8)
+    Rt, w, s = _single_mode_reference(p)
+    U = u.cpu().numpy()
+    cols = np.array([0, 3, 511, 512, 1022])
+    r = oracle.residual_columns(Rt, U, p.f, 1, p.n, 1.0, cols)
+    assert np.max(np.abs(r)) <= 1e-8 * st["bnorm"] * 1.01, st
+    err = np.max(np.abs(U - np.outer(w, s))) / np.max(np.abs(w))
+    assert err < 1e-7, err

@@ -38,7 +38,7 @@ def test_library_exports_every_declared_symbol():
     (dict(alpha=0.0), "alpha"),
     (dict(M=0), "M must"),
     (dict(k=0), "k must"),
-    (dict(k=17), "k must"),
+    (dict(k=33), "k must"),
     (dict(dim=3), "dim"),
     (dict(leaf=0), "leaf"),
     (dict(r=0.5), "r >= 1"),
