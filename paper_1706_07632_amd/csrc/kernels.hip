@@ -1,7 +1,7 @@
 // gfx950 kernels of the MGWR path.
 //
-// march_kernel: one 64-lane wavefront owns 16 spatial columns and marches
-// through the time leaves of the H-matrix in order (Algorithm 4 for the
+// march_kernel: a workgroup owns 16 spatial columns and marches through the
+// time leaves of the H-matrix in order (Algorithm 4 for the
 // smoother, Algorithm 3 for the defect).  Per leaf i it
 //   1. forms the right-hand side of the leaf rows (stencil of the other colour
 //      for the zebra line relaxation of Algorithm 2, or the defect's f - A_h u),
@@ -51,27 +51,40 @@ template <> __device__ __forceinline__ int drow<float>(int g, int r) { return 4 
 constexpr int ZFIRST = 1 << 30;
 constexpr int ZMASK = (1 << 30) - 1;
 
-// Batch sizes of the tile loads issued before the MFMAs that consume them.
-constexpr int DENSE_BATCH = 4;  // dense 16x16 blocks
-constexpr int FF_BATCH = 8;     // far-field K chunks (4 rows each)
-constexpr int ZU_BATCH = 4;     // column-side update tiles
+// Work split inside a workgroup: NW waves share one chain of 16 columns.
+// Per time leaf s there are two phases separated by workgroup barriers:
+//   phase 1: wave 0 sums the partial right-hand sides of leaf s and solves
+//            with the pre-inverted shifted diagonal leaf (critical path);
+//            waves 1.. apply the column-side updates Z += B^T x_{s-1}.
+//   phase 2: all waves build partial right-hand sides of leaf s+1 (stencil
+//            right-hand side on wave 0, dense near-diagonal blocks and the far
+//            field split round-robin).
+// The tiles of the next phase are loaded into registers while the current
+// phase runs.  Every admissible column cluster ends at least one leaf before
+// its row cluster starts, so the far field of leaf s+1 never needs the updates
+// of leaf s.
+constexpr int NW = 4;
+constexpr int ZPF = 4;   // column-update tiles prefetched per helper wave
+constexpr int DPF = 2;   // dense blocks prefetched per wave
+constexpr int FPF = 4;   // far-field chunks prefetched per wave
 
 template <typename T, int MODE>
-__global__ __launch_bounds__(64) void march_kernel(MarchArgs<T> a) {
+__global__ __launch_bounds__(256) void march_kernel(MarchArgs<T> a) {
   typedef typename V4<T>::type v4;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* ring = reinterpret_cast<T*>(smem_raw);   // [R][16][16]
-  T* tbuf = ring + a.ring * 256;               // [16][16]
+  T* ring = reinterpret_cast<T*>(smem_raw);   // [R][16][16] x of recent leaves, row-major
+  T* part = ring + a.ring * 256;               // [NW][16][16] partial right-hand sides
+  T* tbuf = part + NW * 256;                   // [16][16] (f32 transposition)
   T* Z = tbuf + 256;                           // [nslots*k][16]
 
-  const int lane = threadIdx.x;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   const int g = lane >> 4;
   const int c = lane & 15;
   const int p = blockIdx.x * 16 + c;
   const bool colok = p < a.ncols;
   const long long q = colok ? (long long)a.cstride * p + a.coff : 0;
 
-  // stencil neighbours of column q (a.dim == 0: none)
   long long nb[4] = {0, 0, 0, 0};
   bool nbok[4] = {false, false, false, false};
   if (a.dim == 1) {
@@ -87,161 +100,249 @@ __global__ __launch_bounds__(64) void march_kernel(MarchArgs<T> a) {
   const T diagc = (T)(2 * a.dim);
   constexpr bool kSolve = (MODE == MODE_SMOOTH || MODE == MODE_TRSM);
   constexpr bool kKnownX = (MODE == MODE_RESID || MODE == MODE_MATVEC);
+  const int nleaf = a.nleaf;
 
-  // Inputs of a leaf's rows (lane rows drow(g, r)): f, the stencil sum of the
-  // neighbours and (defect / product) the iterate.  Loaded one leaf ahead.
-  T pf_f[4], pf_s[4], pf_u[4];
-  auto load_inputs = [&](const LeafDesc& d) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = drow<T>(g, r);
-      const bool ok = colok && row < d.sz;
-      const long long off = (long long)(d.lo + (ok ? row : 0)) * a.ld;
-      T f = (T)0, s = (T)0, u = (T)0;
-      if constexpr (MODE != MODE_MATVEC) f = ok ? a.F[off + q] : (T)0;
-      if constexpr (MODE == MODE_SMOOTH || MODE == MODE_RESID) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (nbok[e] && ok) s += a.U[off + nb[e]];
-      }
-      if constexpr (kKnownX) u = ok ? a.U[off + q] : (T)0;
-      pf_f[r] = f;
-      pf_s[r] = s;
-      pf_u[r] = u;
+  // ---- registers holding prefetched operands -------------------------------
+  T pf_f[4], pf_s[4], pf_u[4];          // wave 0: inputs of the next leaf's rows
+  T dpf[DPF][4];                        // dense tiles of the next phase 2
+  int djj[DPF];
+  T fpf[FPF];                           // far-field chunks of the next phase 2
+  int fzr[FPF];
+  T zpf[ZPF][4];                        // helper: column-update tiles of the next phase 1
+  int zpr[ZPF][4];
+  T di[4];                              // wave 0: diagonal inverse of the next solve
+
+  // dense items of leaf d: the off-diagonal blocks, then (known x) the diagonal
+  auto n_dense = [&](const LeafDesc& d) { return d.dn_end - d.dn_begin + (kKnownX ? 1 : 0); };
+  auto dense_item = [&](const LeafDesc& d, int li, int e, int& j) -> const T* {
+    if (e < d.dn_end - d.dn_begin) {
+      j = a.dn_list[2 * (d.dn_begin + e)];
+      return a.dense + (long long)a.dn_list[2 * (d.dn_begin + e) + 1] * 256;
     }
+    j = li;
+    return a.dense + (long long)d.diag_off * 256;
   };
-  if (a.nleaf > 0) load_inputs(a.leaves[0]);
 
-  for (int i = 0; i < a.nleaf; ++i) {
-    const LeafDesc d = a.leaves[i];
-    T* cur = ring + (i % a.ring) * 256;
-
-    // 1. right-hand side of the leaf rows
-    v4 acc;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      T v;
-      if constexpr (MODE == MODE_SMOOTH) v = pf_f[r] + a.inv_h2 * pf_s[r];
-      else if constexpr (MODE == MODE_RESID) v = pf_f[r] - a.inv_h2 * (diagc * pf_u[r] - pf_s[r]);
-      else if constexpr (MODE == MODE_TRSM) v = pf_f[r];
-      else v = (T)0;
-      acc[r] = v;
-    }
-    if constexpr (kKnownX) {
-      // the known iterate of this leaf enters the ring (B-operand tile layout)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) cur[drow<T>(g, r) * 16 + c] = pf_u[r];
-    }
-    if (i + 1 < a.nleaf) load_inputs(a.leaves[i + 1]);
-
-    // diagonal inverse of this leaf (used after the far field)
-    T di[4];
-    if constexpr (kSolve) {
-      const T* Di = a.dinv + (long long)i * 256;
-#pragma unroll
-      for (int kc = 0; kc < 4; ++kc) di[kc] = Di[kc * 64 + lane];
-    }
-    if constexpr (kKnownX) __syncthreads();
-
-    // 2. dense near-diagonal blocks (stored negated), DENSE_BATCH at a time
-    for (int e0 = d.dn_begin; e0 < d.dn_end; e0 += DENSE_BATCH) {
-      T t[DENSE_BATCH][4];
-      int jj[DENSE_BATCH];
-#pragma unroll
-      for (int b = 0; b < DENSE_BATCH; ++b) {
-        const int e = min(e0 + b, d.dn_end - 1);
-        jj[b] = a.dn_list[2 * e];
-        const T* D = a.dense + (long long)a.dn_list[2 * e + 1] * 256;
-#pragma unroll
-        for (int kc = 0; kc < 4; ++kc) t[b][kc] = D[kc * 64 + lane];
-      }
-#pragma unroll
-      for (int b = 0; b < DENSE_BATCH; ++b) {
-        if (e0 + b < d.dn_end) {
-          const T* xj = ring + (jj[b] % a.ring) * 256;
-#pragma unroll
-          for (int kc = 0; kc < 4; ++kc) acc = mfma(t[b][kc], xj[(4 * kc + g) * 16 + c], acc);
-        }
-      }
-    }
-    if constexpr (kKnownX) {
-      const T* D = a.dense + (long long)d.diag_off * 256;
-      T t[4];
-#pragma unroll
-      for (int kc = 0; kc < 4; ++kc) t[kc] = D[kc * 64 + lane];
-#pragma unroll
-      for (int kc = 0; kc < 4; ++kc) acc = mfma(t[kc], cur[(4 * kc + g) * 16 + c], acc);
-    }
-
-    // 3. far field: stacked (theta, nu) rows, A stored negated, FF_BATCH chunks at a time
-    for (int c0 = 0; c0 < d.ff_nchunk; c0 += FF_BATCH) {
-      T av[FF_BATCH], bv[FF_BATCH];
-#pragma unroll
-      for (int b = 0; b < FF_BATCH; ++b) {
-        const int ch = d.ff_begin + min(c0 + b, d.ff_nchunk - 1);
-        av[b] = a.ffA[(long long)ch * 64 + lane];
-        const int zr = a.ff_row[ch * 4 + g];
-        bv[b] = (zr >= 0 && c0 + b < d.ff_nchunk) ? Z[zr * 16 + c] : (T)0;
-      }
-#pragma unroll
-      for (int b = 0; b < FF_BATCH; ++b)
-        if (c0 + b < d.ff_nchunk) acc = mfma(av[b], bv[b], acc);
-    }
-
-    // 4. diagonal leaf
-    if constexpr (kSolve) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) tbuf[drow<T>(g, r) * 16 + c] = acc[r];
-      __syncthreads();
-      v4 x = {0, 0, 0, 0};
-#pragma unroll
-      for (int kc = 0; kc < 4; ++kc) x = mfma(di[kc], tbuf[(4 * kc + g) * 16 + c], x);
+  auto prefetch_phase2 = [&](int li) {
+    const LeafDesc d = a.leaves[li];
+    if (wave == 0) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = drow<T>(g, r);
         const bool ok = colok && row < d.sz;
-        if (ok) a.U[(long long)(d.lo + row) * a.ld + q] = x[r];
-        cur[row * 16 + c] = ok ? x[r] : (T)0;
-      }
-      __syncthreads();
-    } else {
+        const long long off = (long long)(d.lo + (ok ? row : 0)) * a.ld;
+        T f = (T)0, s = (T)0, u = (T)0;
+        if constexpr (MODE != MODE_MATVEC) f = ok ? a.F[off + q] : (T)0;
+        if constexpr (MODE == MODE_SMOOTH || MODE == MODE_RESID) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = drow<T>(g, r);
-        if (colok && row < d.sz) {
-          const T v = (MODE == MODE_MATVEC) ? -acc[r] : acc[r];
-          a.Out[(long long)(d.lo + row) * a.ld + q] = v;
+          for (int e = 0; e < 4; ++e)
+            if (nbok[e] && ok) s += a.U[off + nb[e]];
         }
+        if constexpr (kKnownX) u = ok ? a.U[off + q] : (T)0;
+        pf_f[r] = f; pf_s[r] = s; pf_u[r] = u;
       }
     }
+    const int nd = n_dense(d);
+#pragma unroll
+    for (int k2 = 0; k2 < DPF; ++k2) {
+      const int e = wave + k2 * NW;
+      if (e < nd) {
+        const T* D = dense_item(d, li, e, djj[k2]);
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) dpf[k2][kc] = D[kc * 64 + lane];
+      }
+    }
+#pragma unroll
+    for (int k2 = 0; k2 < FPF; ++k2) {
+      const int ch = wave + k2 * NW;
+      if (ch < d.ff_nchunk) {
+        fpf[k2] = a.ffA[(long long)(d.ff_begin + ch) * 64 + lane];
+        fzr[k2] = a.ff_row[(d.ff_begin + ch) * 4 + g];
+      }
+    }
+  };
 
-    // 5. column-side low-rank updates Z += B^T x_i, ZU_BATCH tiles at a time
-    for (int t0 = 0; t0 < d.zu_ntile; t0 += ZU_BATCH) {
-      T bt[ZU_BATCH][4];
-      int zr[ZU_BATCH][4];
+  auto prefetch_zu = [&](int li) {  // helpers: update tiles of leaf li
+    const LeafDesc d = a.leaves[li];
 #pragma unroll
-      for (int b = 0; b < ZU_BATCH; ++b) {
-        const int tt = d.zu_begin + min(t0 + b, d.zu_ntile - 1);
-        const T* Bt = a.zuB + (long long)tt * 256;
+    for (int k2 = 0; k2 < ZPF; ++k2) {
+      const int tt = (wave - 1) + k2 * (NW - 1);
+      if (tt < d.zu_ntile) {
+        const T* Bt = a.zuB + (long long)(d.zu_begin + tt) * 256;
 #pragma unroll
-        for (int kc = 0; kc < 4; ++kc) bt[b][kc] = Bt[kc * 64 + lane];
+        for (int kc = 0; kc < 4; ++kc) zpf[k2][kc] = Bt[kc * 64 + lane];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) zr[b][r] = a.zu_row[tt * 16 + drow<T>(g, r)];
+        for (int r = 0; r < 4; ++r) zpr[k2][r] = a.zu_row[(d.zu_begin + tt) * 16 + drow<T>(g, r)];
+      }
+    }
+  };
+
+  auto prefetch_dinv = [&](int li) {
+    if constexpr (kSolve) {
+      const T* Di = a.dinv + (long long)li * 256;
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) di[kc] = Di[kc * 64 + lane];
+    }
+  };
+
+  // phase 2: partial right-hand side of leaf li from this wave's share
+  auto partial = [&](int li) {
+    const LeafDesc d = a.leaves[li];
+    v4 acc = {0, 0, 0, 0};
+    if (wave == 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        T v;
+        if constexpr (MODE == MODE_SMOOTH) v = pf_f[r] + a.inv_h2 * pf_s[r];
+        else if constexpr (MODE == MODE_RESID) v = pf_f[r] - a.inv_h2 * (diagc * pf_u[r] - pf_s[r]);
+        else if constexpr (MODE == MODE_TRSM) v = pf_f[r];
+        else v = (T)0;
+        acc[r] = v;
+      }
+    }
+    const int nd = n_dense(d);
+#pragma unroll
+    for (int k2 = 0; k2 < DPF; ++k2) {
+      if (wave + k2 * NW < nd) {
+        const T* xj = ring + (djj[k2] % a.ring) * 256;
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) acc = mfma(dpf[k2][kc], xj[(4 * kc + g) * 16 + c], acc);
+      }
+    }
+    for (int e = wave + DPF * NW; e < nd; e += NW) {   // beyond the prefetched share
+      int j;
+      const T* D = dense_item(d, li, e, j);
+      T t[4];
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) t[kc] = D[kc * 64 + lane];
+      const T* xj = ring + (j % a.ring) * 256;
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) acc = mfma(t[kc], xj[(4 * kc + g) * 16 + c], acc);
+    }
+#pragma unroll
+    for (int k2 = 0; k2 < FPF; ++k2) {
+      if (wave + k2 * NW < d.ff_nchunk) {
+        const T bv = fzr[k2] >= 0 ? Z[fzr[k2] * 16 + c] : (T)0;
+        acc = mfma(fpf[k2], bv, acc);
+      }
+    }
+    for (int ch0 = wave + FPF * NW; ch0 < d.ff_nchunk; ch0 += FPF * NW) {
+      T av[FPF], bv[FPF];
+#pragma unroll
+      for (int b = 0; b < FPF; ++b) {
+        const int ch = min(ch0 + b * NW, d.ff_nchunk - 1);
+        av[b] = a.ffA[(long long)(d.ff_begin + ch) * 64 + lane];
+        const int zr = a.ff_row[(d.ff_begin + ch) * 4 + g];
+        bv[b] = (zr >= 0 && ch0 + b * NW < d.ff_nchunk) ? Z[zr * 16 + c] : (T)0;
       }
 #pragma unroll
-      for (int b = 0; b < ZU_BATCH; ++b) {
-        if (t0 + b < d.zu_ntile) {
-          v4 z;
+      for (int b = 0; b < FPF; ++b)
+        if (ch0 + b * NW < d.ff_nchunk) acc = mfma(av[b], bv[b], acc);
+    }
+    T* pw = part + wave * 256;
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-            z[r] = (zr[b][r] >= 0 && !(zr[b][r] & ZFIRST)) ? Z[(zr[b][r] & ZMASK) * 16 + c] : (T)0;
+    for (int r = 0; r < 4; ++r) pw[drow<T>(g, r) * 16 + c] = acc[r];
+  };
+
+  // phase 1 (helpers): Z += B^T x for the update tiles of leaf li owned by this wave
+  auto zupdate = [&](int li) {
+    const LeafDesc d = a.leaves[li];
+    const T* xs = ring + (li % a.ring) * 256;
+    auto apply = [&](const T* bt, const int* zr) {
+      v4 z;
 #pragma unroll
-          for (int kc = 0; kc < 4; ++kc) z = mfma(bt[b][kc], cur[(4 * kc + g) * 16 + c], z);
+      for (int r = 0; r < 4; ++r) z[r] = (zr[r] >= 0 && !(zr[r] & ZFIRST)) ? Z[(zr[r] & ZMASK) * 16 + c] : (T)0;
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (zr[b][r] >= 0) Z[(zr[b][r] & ZMASK) * 16 + c] = z[r];
+      for (int kc = 0; kc < 4; ++kc) z = mfma(bt[kc], xs[(4 * kc + g) * 16 + c], z);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (zr[r] >= 0) Z[(zr[r] & ZMASK) * 16 + c] = z[r];
+    };
+#pragma unroll
+    for (int k2 = 0; k2 < ZPF; ++k2)
+      if ((wave - 1) + k2 * (NW - 1) < d.zu_ntile) apply(zpf[k2], zpr[k2]);
+    for (int tt = (wave - 1) + ZPF * (NW - 1); tt < d.zu_ntile; tt += NW - 1) {
+      T bt[4];
+      int zr[4];
+      const T* Bt = a.zuB + (long long)(d.zu_begin + tt) * 256;
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) bt[kc] = Bt[kc * 64 + lane];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) zr[r] = a.zu_row[(d.zu_begin + tt) * 16 + drow<T>(g, r)];
+      apply(bt, zr);
+    }
+  };
+
+  if (nleaf <= 0) return;
+
+  // ---- prologue: partial right-hand side of leaf 0 ---------------------------
+  prefetch_phase2(0);
+  if constexpr (kKnownX) {
+    if (wave == 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) ring[drow<T>(g, r) * 16 + c] = pf_u[r];
+    }
+    __syncthreads();
+  }
+  if (wave == 0) prefetch_dinv(0);
+  partial(0);
+  __syncthreads();
+
+  for (int s = 0; s < nleaf; ++s) {
+    const LeafDesc d = a.leaves[s];
+    // ---- phase 1 --------------------------------------------------------------
+    if (s + 1 < nleaf) prefetch_phase2(s + 1);
+    if (wave == 0) {
+      v4 acc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        T v = (T)0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) v += part[w * 256 + drow<T>(g, r) * 16 + c];
+        acc[r] = v;
+      }
+      T* cur = ring + (s % a.ring) * 256;
+      if constexpr (kSolve) {
+        v4 x = {0, 0, 0, 0};
+        if constexpr (sizeof(T) == 8) {
+          // f64 layout: element kc of lane (g, c) holds row g + 4 kc, the B row of chunk kc
+#pragma unroll
+          for (int kc = 0; kc < 4; ++kc) x = mfma(di[kc], acc[kc], x);
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) tbuf[drow<T>(g, r) * 16 + c] = acc[r];
+          __builtin_amdgcn_wave_barrier();
+#pragma unroll
+          for (int kc = 0; kc < 4; ++kc) x = mfma(di[kc], tbuf[(4 * kc + g) * 16 + c], x);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = drow<T>(g, r);
+          const bool ok = colok && row < d.sz;
+          if (ok) a.U[(long long)(d.lo + row) * a.ld + q] = x[r];
+          cur[row * 16 + c] = ok ? x[r] : (T)0;
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = drow<T>(g, r);
+          if (colok && row < d.sz) a.Out[(long long)(d.lo + row) * a.ld + q] = (MODE == MODE_MATVEC) ? -acc[r] : acc[r];
+        }
+        if (s + 1 < nleaf) {
+          T* nxt = ring + ((s + 1) % a.ring) * 256;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) nxt[drow<T>(g, r) * 16 + c] = pf_u[r];
         }
       }
+    } else if (s >= 1) {
+      zupdate(s - 1);
+    }
+    __syncthreads();
+    // ---- phase 2 --------------------------------------------------------------
+    if (s + 1 < nleaf) {
+      if (wave == 0) prefetch_dinv(s + 1);
+      else prefetch_zu(s);
+      partial(s + 1);
     }
     __syncthreads();
   }
@@ -413,13 +514,13 @@ static inline int grid_for(long long total, int block) {
 
 template <typename T>
 size_t march_lds_bytes(const MarchArgs<T>& a) {
-  return ((size_t)a.ring * 256 + 256 + (size_t)a.nslots * a.k * 16) * sizeof(T);
+  return ((size_t)a.ring * 256 + (size_t)NW * 256 + 256 + (size_t)a.nslots * a.k * 16) * sizeof(T);
 }
 
 template <typename T>
 hipError_t launch_march(int mode, const MarchArgs<T>& a, hipStream_t s) {
   if (a.ncols <= 0) return hipSuccess;
-  dim3 grid((a.ncols + 15) / 16), block(64);
+  dim3 grid((a.ncols + 15) / 16), block(64 * NW);
   size_t lds = march_lds_bytes(a);
   switch (mode) {
     case MODE_SMOOTH: hipLaunchKernelGGL((march_kernel<T, MODE_SMOOTH>), grid, block, lds, s, a); break;

@@ -192,7 +192,7 @@ MarchArgs<T> base_args(mgwr_plan* pl, const DevOps<T>& ops, int level) {
   a.zuB = ops.zuB;
   a.k = hp.p.k;
   a.nslots = hp.nslots;
-  a.ring = hp.window + 1;
+  a.ring = std::max(hp.window + 2, 3);  // leaves written while older ones are still read
   return a;
 }
 
