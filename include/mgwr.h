@@ -75,9 +75,19 @@ typedef struct {
   int max_cycles;   /* cap on cycles (plain) or inner cycles in total (mixed) */
   int precision;    /* mgwr_precision */
   int inner_cycles; /* mixed precision: inner V-cycles per outer refinement step */
+  int schedule;     /* MGWR_SCHED_PIPELINED (default) or MGWR_SCHED_STAGED */
 } mgwr_params;
 
-/* Fill *p with defaults: leaf 16, V(1,1), gamma 1, max_cycles 50, FP64, length 1, T 1. */
+/* Cycle schedules (float64 solver).  Every operator of a cycle is causal in
+ * time, so the pipelined schedule runs several whole cycles in one launch,
+ * each stage (a smoothing half-sweep, a defect, a grid transfer) starting
+ * time leaf i as soon as the stage before it has finished leaf i.  The staged
+ * schedule launches one kernel per stage and checks the residual after every
+ * cycle.  Both compute the same iterates up to the order of float64 rounding. */
+enum { MGWR_SCHED_PIPELINED = 0, MGWR_SCHED_STAGED = 1 };
+
+/* Fill *p with defaults: leaf 16, V(1,1), gamma 1, max_cycles 50, FP64, length 1, T 1,
+ * pipelined schedule. */
 void mgwr_params_default(mgwr_params* p);
 
 typedef struct {
@@ -153,6 +163,7 @@ enum {
   MGWR_K_DEFECT32 = 3,  /* defect, float32 (mixed inner cycles) */
   MGWR_K_RESTRICT = 4,  /* full-weighting restriction (either precision) */
   MGWR_K_PROLONG = 5,   /* interpolation and correction (either precision) */
+  MGWR_K_PIPE64 = 6,    /* one launch of K time-pipelined float64 cycles (all stages) */
   MGWR_K_CLASSES = 8
 };
 typedef struct {

@@ -30,7 +30,7 @@ EXPORTED = [
     "mgwr_timing_enable", "mgwr_timing_get",
 ]
 
-KERNEL_CLASSES = ["smooth64", "defect64", "smooth32", "defect32", "restrict", "prolong"]
+KERNEL_CLASSES = ["smooth64", "defect64", "smooth32", "defect32", "restrict", "prolong", "pipe64"]
 
 
 class MgwrError(RuntimeError):
@@ -44,7 +44,8 @@ class Params(ctypes.Structure):
                 ("M", ctypes.c_int), ("T", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("r", ctypes.c_double), ("k", ctypes.c_int), ("leaf", ctypes.c_int),
                 ("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("gamma", ctypes.c_int),
-                ("max_cycles", ctypes.c_int), ("precision", ctypes.c_int), ("inner_cycles", ctypes.c_int)]
+                ("max_cycles", ctypes.c_int), ("precision", ctypes.c_int), ("inner_cycles", ctypes.c_int),
+                ("schedule", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -147,7 +148,8 @@ class Plan:
     """
 
     def __init__(self, dim, n, M, alpha, k=10, r=1.0, T=1.0, length=1.0, t=None, leaf=16,
-                 nu1=1, nu2=1, gamma=1, max_cycles=50, precision="fp64", inner_cycles=1):
+                 nu1=1, nu2=1, gamma=1, max_cycles=50, precision="fp64", inner_cycles=1,
+                 schedule="pipelined"):
         import numpy as np
         L = lib()
         p = Params()
@@ -157,6 +159,7 @@ class Plan:
         p.nu1, p.nu2, p.gamma, p.max_cycles = int(nu1), int(nu2), int(gamma), int(max_cycles)
         p.precision = {"fp64": MGWR_FP64, "mixed": MGWR_MIXED_FP32, "fp32": MGWR_MIXED_FP32}[precision]
         p.inner_cycles = int(inner_cycles)
+        p.schedule = {"pipelined": 0, "staged": 1}[schedule]
         self.params = p
         self.dim, self.n, self.M = int(dim), int(n), int(M)
         self.N = self.n ** self.dim

@@ -35,7 +35,44 @@ struct MarchArgs {
   T inv_h2;
 };
 
+// One stage of the time-pipelined cycle kernel.  Stage kinds:
+enum { STG_SMOOTH = 0, STG_RESID = 1, STG_RESTRICT = 2, STG_PROLONG = 3 };
+
+template <typename T>
+struct Stage {
+  int kind;
+  int prev;          // producer stage (index into the stage array) or -1
+  int nchunks;       // work items of this stage
+  int task0;         // first work item (tickets are taken in stage order)
+  int cnt_off;       // this stage's per-leaf counters start at counters + cnt_off
+  int nleaf;
+  const LeafDesc* leaves;
+  MarchArgs<T> m;    // STG_SMOOTH / STG_RESID
+  double* norm_out;  // STG_RESID: per-work-item max |r| (or null)
+  // STG_RESTRICT: src = fine defect, dst = coarse right-hand side, zero = coarse iterate
+  // STG_PROLONG:  src = coarse correction, dst = fine iterate (updated)
+  const T* src;
+  T* dst;
+  T* zero;
+  int dim, nf, nc;
+};
+
+template <typename T>
+struct PipeArgs {
+  const Stage<T>* stages;
+  int nstages;
+  int ntasks;
+  int* counters;
+  int* ticket;
+  int* abortf;
+};
+
+constexpr int kStencilCols = 256;  // columns per work item of a stencil stage
+
 template <typename T> size_t march_lds_bytes(const MarchArgs<T>& a);
+template <typename T> hipError_t launch_pipeline(const PipeArgs<T>& pa, size_t lds, hipStream_t s);
+template <typename T> hipError_t set_pipeline_lds_limit(size_t bytes);
+hipError_t launch_fill_int(int* x, long long count, int v, hipStream_t s);
 template <typename T> hipError_t launch_march(int mode, const MarchArgs<T>& a, hipStream_t s);
 template <typename T> hipError_t set_march_lds_limit(size_t bytes);
 template <typename T> hipError_t launch_restrict(const T* rf, T* fc, int dim, int nf, int M, hipStream_t s);

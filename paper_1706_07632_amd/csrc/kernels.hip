@@ -48,6 +48,72 @@ template <typename T> __device__ __forceinline__ int drow(int g, int r);
 template <> __device__ __forceinline__ int drow<double>(int g, int r) { return g + 4 * r; }
 template <> __device__ __forceinline__ int drow<float>(int g, int r) { return 4 * g + r; }
 
+// Loads and stores of the space-time arrays.  Inside the pipelined cycle
+// kernel a stage reads rows another workgroup (possibly on another XCD) has
+// just written, so those accesses are device-coherent (relaxed agent-scope
+// atomics: sc1 loads/stores, no cache flushes); the hand-off order is
+// established by the per-leaf progress counters below.
+template <bool PIPE, typename T>
+__device__ __forceinline__ T gld(const T* p) {
+  if constexpr (!PIPE) {
+    return *p;
+  } else if constexpr (sizeof(T) == 8) {
+    unsigned long long v = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+    return __builtin_bit_cast(T, v);
+  } else {
+    unsigned int v = __hip_atomic_load(reinterpret_cast<const unsigned int*>(p), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+    return __builtin_bit_cast(T, v);
+  }
+}
+template <bool PIPE, typename T>
+__device__ __forceinline__ void gst(T* p, T v) {
+  if constexpr (!PIPE) {
+    *p = v;
+  } else if constexpr (sizeof(T) == 8) {
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), __builtin_bit_cast(unsigned long long, v),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    __hip_atomic_store(reinterpret_cast<unsigned int*>(p), __builtin_bit_cast(unsigned int, v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Progress hand-off between pipeline stages.  done[i] counts the work items of
+// a stage that have finished (and made visible) their rows of leaf i.
+struct PipeCtx {
+  const int* wait;   // producer's per-leaf counters, or null
+  int need;          // producer's number of work items
+  int* done;         // this stage's per-leaf counters
+  int* abortf;       // set when a wait exceeds its bound; every waiter then gives up
+  double* norm_out;  // defect stages: max |r| of this work item, or null
+};
+
+constexpr unsigned kSpinLimit = 1u << 22;
+
+// Called by whole waves (uniform); returns false if the pipeline was aborted.
+__device__ bool wait_leaf(const PipeCtx& pc, int leaf) {
+  if (!pc.wait) return true;
+  const int* cnt = pc.wait + leaf;
+  for (unsigned it = 0;; ++it) {
+    if (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= pc.need) return true;
+    if (__hip_atomic_load(pc.abortf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+    if (it > kSpinLimit) {
+      __hip_atomic_store(pc.abortf, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
+// Called by one wave after its stores of the leaf rows: wait until they are
+// complete, then publish.
+__device__ __forceinline__ void signal_leaf(const PipeCtx& pc, int leaf, int lane) {
+  __builtin_amdgcn_s_waitcnt(0);
+  if (lane == 0) __hip_atomic_fetch_add(pc.done + leaf, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 constexpr int ZFIRST = 1 << 30;
 constexpr int ZMASK = (1 << 30) - 1;
 
@@ -68,10 +134,10 @@ constexpr int ZPF = 4;   // column-update tiles prefetched per helper wave
 constexpr int DPF = 2;   // dense blocks prefetched per wave
 constexpr int FPF = 4;   // far-field chunks prefetched per wave
 
-template <typename T, int MODE>
-__global__ __launch_bounds__(256) void march_kernel(MarchArgs<T> a) {
+template <typename T, int MODE, bool PIPE>
+__device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, const PipeCtx& pc,
+                                           unsigned char* smem_raw, int* sh_abort) {
   typedef typename V4<T>::type v4;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
   T* ring = reinterpret_cast<T*>(smem_raw);   // [R][16][16] x of recent leaves, row-major
   T* part = ring + a.ring * 256;               // [NW][16][16] partial right-hand sides
   T* tbuf = part + NW * 256;                   // [16][16] (f32 transposition)
@@ -81,7 +147,7 @@ __global__ __launch_bounds__(256) void march_kernel(MarchArgs<T> a) {
   const int lane = threadIdx.x & 63;
   const int g = lane >> 4;
   const int c = lane & 15;
-  const int p = blockIdx.x * 16 + c;
+  const int p = chunk * 16 + c;
   const bool colok = p < a.ncols;
   const long long q = colok ? (long long)a.cstride * p + a.coff : 0;
 
@@ -123,25 +189,35 @@ __global__ __launch_bounds__(256) void march_kernel(MarchArgs<T> a) {
     return a.dense + (long long)d.diag_off * 256;
   };
 
-  auto prefetch_phase2 = [&](int li) {
+  // wave 0: inputs of leaf li (in the pipeline, after the producer finished it)
+  auto prefetch_inputs = [&](int li) -> bool {
+    if constexpr (PIPE) {
+      if (!wait_leaf(pc, li)) return false;
+    }
     const LeafDesc d = a.leaves[li];
-    if (wave == 0) {
+    {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = drow<T>(g, r);
         const bool ok = colok && row < d.sz;
         const long long off = (long long)(d.lo + (ok ? row : 0)) * a.ld;
         T f = (T)0, s = (T)0, u = (T)0;
-        if constexpr (MODE != MODE_MATVEC) f = ok ? a.F[off + q] : (T)0;
+        if constexpr (MODE != MODE_MATVEC) f = ok ? gld<PIPE>(a.F + off + q) : (T)0;
         if constexpr (MODE == MODE_SMOOTH || MODE == MODE_RESID) {
 #pragma unroll
           for (int e = 0; e < 4; ++e)
-            if (nbok[e] && ok) s += a.U[off + nb[e]];
+            if (nbok[e] && ok) s += gld<PIPE>(a.U + off + nb[e]);
         }
-        if constexpr (kKnownX) u = ok ? a.U[off + q] : (T)0;
+        if constexpr (kKnownX) u = ok ? gld<PIPE>(a.U + off + q) : (T)0;
         pf_f[r] = f; pf_s[r] = s; pf_u[r] = u;
       }
     }
+    return true;
+  };
+
+  // all waves: H-matrix tiles of their share of leaf li's phase 2
+  auto prefetch_tiles = [&](int li) {
+    const LeafDesc d = a.leaves[li];
     const int nd = n_dense(d);
 #pragma unroll
     for (int k2 = 0; k2 < DPF; ++k2) {
@@ -274,24 +350,29 @@ __global__ __launch_bounds__(256) void march_kernel(MarchArgs<T> a) {
   };
 
   if (nleaf <= 0) return;
+  if (threadIdx.x == 0) *sh_abort = 0;
+  T nmax = (T)0;
+  bool nbad = false;
 
   // ---- prologue: partial right-hand side of leaf 0 ---------------------------
-  prefetch_phase2(0);
-  if constexpr (kKnownX) {
-    if (wave == 0) {
+  prefetch_tiles(0);
+  if (wave == 0) {
+    if (!prefetch_inputs(0)) *sh_abort = 1;
+    if constexpr (kKnownX) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) ring[drow<T>(g, r) * 16 + c] = pf_u[r];
     }
-    __syncthreads();
+    prefetch_dinv(0);
   }
-  if (wave == 0) prefetch_dinv(0);
+  __syncthreads();
+  if (*sh_abort) return;
   partial(0);
   __syncthreads();
 
   for (int s = 0; s < nleaf; ++s) {
     const LeafDesc d = a.leaves[s];
     // ---- phase 1 --------------------------------------------------------------
-    if (s + 1 < nleaf) prefetch_phase2(s + 1);
+    if (s + 1 < nleaf) prefetch_tiles(s + 1);
     if (wave == 0) {
       v4 acc;
 #pragma unroll
@@ -319,16 +400,27 @@ __global__ __launch_bounds__(256) void march_kernel(MarchArgs<T> a) {
         for (int r = 0; r < 4; ++r) {
           const int row = drow<T>(g, r);
           const bool ok = colok && row < d.sz;
-          if (ok) a.U[(long long)(d.lo + row) * a.ld + q] = x[r];
+          if (ok) gst<PIPE>(a.U + (long long)(d.lo + row) * a.ld + q, x[r]);
           cur[row * 16 + c] = ok ? x[r] : (T)0;
         }
       } else {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = drow<T>(g, r);
-          if (colok && row < d.sz) a.Out[(long long)(d.lo + row) * a.ld + q] = (MODE == MODE_MATVEC) ? -acc[r] : acc[r];
+          if (colok && row < d.sz) {
+            const T v = (MODE == MODE_MATVEC) ? -acc[r] : acc[r];
+            gst<PIPE>(a.Out + (long long)(d.lo + row) * a.ld + q, v);
+            if constexpr (PIPE) {
+              if (!(v == v) || __builtin_isinf(v)) nbad = true;
+              else nmax = v > nmax ? v : (-v > nmax ? -v : nmax);
+            }
+          }
         }
-        if (s + 1 < nleaf) {
+      }
+      if constexpr (PIPE) signal_leaf(pc, s, lane);
+      if (s + 1 < nleaf) {
+        if (!prefetch_inputs(s + 1)) *sh_abort = 1;
+        if constexpr (kKnownX) {
           T* nxt = ring + ((s + 1) % a.ring) * 256;
 #pragma unroll
           for (int r = 0; r < 4; ++r) nxt[drow<T>(g, r) * 16 + c] = pf_u[r];
@@ -338,6 +430,9 @@ __global__ __launch_bounds__(256) void march_kernel(MarchArgs<T> a) {
       zupdate(s - 1);
     }
     __syncthreads();
+    if constexpr (PIPE) {
+      if (*sh_abort) return;
+    }
     // ---- phase 2 --------------------------------------------------------------
     if (s + 1 < nleaf) {
       if (wave == 0) prefetch_dinv(s + 1);
@@ -346,6 +441,196 @@ __global__ __launch_bounds__(256) void march_kernel(MarchArgs<T> a) {
     }
     __syncthreads();
   }
+  if constexpr (PIPE && MODE == MODE_RESID) {
+    if (pc.norm_out && wave == 0) {
+      double m = nbad ? __builtin_nan("") : (double)nmax;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(m, off, 64);
+        m = (o != o || m != m) ? __builtin_nan("") : (o > m ? o : m);
+      }
+      if (lane == 0) pc.norm_out[chunk] = m;
+    }
+  }
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void march_kernel(MarchArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int sh_abort;
+  PipeCtx pc{};
+  march_body<T, MODE, false>(a, blockIdx.x, pc, smem_raw, &sh_abort);
+}
+
+
+// ---------------------------------------------------------------------------
+// Time-pipelined cycles.  Every operator of a cycle of Algorithm 2 is causal
+// in time (the line solves and the H-matrix product are lower triangular,
+// the grid transfers act on one time level), so stage k may process leaf i as
+// soon as stage k-1 has finished leaf i.  One launch runs all stages of
+// several cycles; work items take tickets in stage order, so every item a
+// workgroup waits for already holds a running workgroup.
+
+static hipError_t set_dyn_lds(const void* fn, size_t bytes);
+
+// Full-weighting restriction of the rows of one leaf, and the zero start of
+// the coarse iterate on those rows.
+template <typename T>
+__device__ void restrict_stage(const Stage<T>& st, int chunk, const PipeCtx& pc, int* sh_abort) {
+  const int nf = st.nf, nc = st.nc;
+  const long long Nc = st.dim == 1 ? nc : (long long)nc * nc;
+  const long long Nf = st.dim == 1 ? nf : (long long)nf * nf;
+  const long long Q = (long long)chunk * kStencilCols + threadIdx.x;
+  const bool ok = Q < Nc;
+  const int lane = threadIdx.x & 63;
+  for (int i = 0; i < st.nleaf; ++i) {
+    const LeafDesc d = st.leaves[i];
+    if (threadIdx.x < 64) {
+      if (!wait_leaf(pc, i)) *sh_abort = 1;
+    }
+    __syncthreads();
+    if (*sh_abort) return;
+    if (ok) {
+      for (int row = 0; row < d.sz; ++row) {
+        const long long m = d.lo + row;
+        const T* r = st.src + m * Nf;
+        T v;
+        if (st.dim == 1) {
+          const long long f = 2 * Q + 1;
+          v = (T)0.25 * (gld<true>(r + f - 1) + (T)2 * gld<true>(r + f) + gld<true>(r + f + 1));
+        } else {
+          const long long I = Q % nc, J = Q / nc;
+          const long long fx = 2 * I + 1, fy = 2 * J + 1;
+          const T* r0 = r + (fy - 1) * nf;
+          const T* r1 = r + fy * nf;
+          const T* r2 = r + (fy + 1) * nf;
+          v = (T)(1.0 / 16.0) * ((gld<true>(r0 + fx - 1) + gld<true>(r0 + fx + 1) + gld<true>(r2 + fx - 1) +
+                                  gld<true>(r2 + fx + 1)) +
+                                 (T)2 * (gld<true>(r0 + fx) + gld<true>(r2 + fx) + gld<true>(r1 + fx - 1) +
+                                         gld<true>(r1 + fx + 1)) +
+                                 (T)4 * gld<true>(r1 + fx));
+        }
+        gst<true>(st.dst + m * Nc + Q, v);
+        gst<true>(st.zero + m * Nc + Q, (T)0);
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x < 64) signal_leaf(pc, i, lane);
+  }
+}
+
+// Linear / bilinear interpolation of the coarse correction, added to the
+// fine iterate on the rows of one leaf.
+template <typename T>
+__device__ void prolong_stage(const Stage<T>& st, int chunk, const PipeCtx& pc, int* sh_abort) {
+  const int nf = st.nf, nc = st.nc;
+  const long long Nc = st.dim == 1 ? nc : (long long)nc * nc;
+  const long long Nf = st.dim == 1 ? nf : (long long)nf * nf;
+  const long long q = (long long)chunk * kStencilCols + threadIdx.x;
+  const bool ok = q < Nf;
+  const int lane = threadIdx.x & 63;
+  long long cidx[4];
+  T cw[4];
+  int ncoef = 0;
+  if (ok) {
+    if (st.dim == 1) {
+      if (q & 1) { cidx[0] = (q - 1) / 2; cw[0] = (T)1; ncoef = 1; }
+      else {
+        const long long I = q / 2;
+        if (I >= 1) { cidx[ncoef] = I - 1; cw[ncoef++] = (T)0.5; }
+        if (I < nc) { cidx[ncoef] = I; cw[ncoef++] = (T)0.5; }
+      }
+    } else {
+      const long long ix = q % nf, iy = q / nf;
+      long long cx[2], cy[2];
+      T wx[2], wy[2];
+      int nx, ny;
+      if (ix & 1) { cx[0] = (ix - 1) / 2; wx[0] = (T)1; nx = 1; }
+      else { cx[0] = ix / 2 - 1; cx[1] = ix / 2; wx[0] = wx[1] = (T)0.5; nx = 2; }
+      if (iy & 1) { cy[0] = (iy - 1) / 2; wy[0] = (T)1; ny = 1; }
+      else { cy[0] = iy / 2 - 1; cy[1] = iy / 2; wy[0] = wy[1] = (T)0.5; ny = 2; }
+      for (int b = 0; b < ny; ++b) {
+        if (cy[b] < 0 || cy[b] >= nc) continue;
+        for (int a2 = 0; a2 < nx; ++a2) {
+          if (cx[a2] < 0 || cx[a2] >= nc) continue;
+          cidx[ncoef] = cy[b] * nc + cx[a2];
+          cw[ncoef++] = wx[a2] * wy[b];
+        }
+      }
+    }
+  }
+  for (int i = 0; i < st.nleaf; ++i) {
+    const LeafDesc d = st.leaves[i];
+    if (threadIdx.x < 64) {
+      if (!wait_leaf(pc, i)) *sh_abort = 1;
+    }
+    __syncthreads();
+    if (*sh_abort) return;
+    if (ok) {
+      for (int row = 0; row < d.sz; ++row) {
+        const long long m = d.lo + row;
+        const T* e = st.src + m * Nc;
+        T v = (T)0;
+        for (int t = 0; t < ncoef; ++t) v += cw[t] * gld<true>(e + cidx[t]);
+        T* u = st.dst + m * Nf + q;
+        gst<true>(u, gld<true>(u) + v);
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x < 64) signal_leaf(pc, i, lane);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void pipeline_kernel(PipeArgs<T> pa) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int sh_task;
+  __shared__ int sh_abort;
+  if (threadIdx.x == 0) sh_task = atomicAdd(pa.ticket, 1);
+  __syncthreads();
+  const int task = sh_task;
+  if (task >= pa.ntasks) return;
+  int lo = 0, hi = pa.nstages - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pa.stages[mid].task0 <= task) lo = mid;
+    else hi = mid - 1;
+  }
+  const Stage<T>& st = pa.stages[lo];
+  PipeCtx pc;
+  pc.wait = st.prev >= 0 ? pa.counters + pa.stages[st.prev].cnt_off : nullptr;
+  pc.need = st.prev >= 0 ? pa.stages[st.prev].nchunks : 0;
+  pc.done = pa.counters + st.cnt_off;
+  pc.abortf = pa.abortf;
+  pc.norm_out = st.norm_out;
+  const int chunk = task - st.task0;
+  switch (st.kind) {
+    case STG_SMOOTH: march_body<T, MODE_SMOOTH, true>(st.m, chunk, pc, smem_raw, &sh_abort); break;
+    case STG_RESID: march_body<T, MODE_RESID, true>(st.m, chunk, pc, smem_raw, &sh_abort); break;
+    case STG_RESTRICT: if (threadIdx.x == 0) sh_abort = 0; __syncthreads(); restrict_stage<T>(st, chunk, pc, &sh_abort); break;
+    case STG_PROLONG: if (threadIdx.x == 0) sh_abort = 0; __syncthreads(); prolong_stage<T>(st, chunk, pc, &sh_abort); break;
+    default: break;
+  }
+}
+
+template <typename T>
+hipError_t launch_pipeline(const PipeArgs<T>& pa, size_t lds, hipStream_t s) {
+  if (pa.ntasks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(pipeline_kernel<T>, dim3(pa.ntasks), dim3(256), lds, s, pa);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t set_pipeline_lds_limit(size_t bytes) {
+  return set_dyn_lds((const void*)pipeline_kernel<T>, bytes);
+}
+
+__global__ void fill_int_kernel(int* __restrict__ x, long long count, int v) {
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < count;
+       idx += (long long)gridDim.x * blockDim.x)
+    x[idx] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -532,16 +817,23 @@ hipError_t launch_march(int mode, const MarchArgs<T>& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Raises a kernel's dynamic-LDS ceiling to `bytes` minus its static LDS.
+static hipError_t set_dyn_lds(const void* fn, size_t bytes) {
+  hipFuncAttributes attr;
+  hipError_t e = hipFuncGetAttributes(&attr, fn);
+  if (e != hipSuccess) return e;
+  size_t stat = attr.sharedSizeBytes;
+  if (stat >= bytes) return hipErrorInvalidValue;
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(bytes - stat));
+}
+
 template <typename T>
 hipError_t set_march_lds_limit(size_t bytes) {
   hipError_t e;
-  e = hipFuncSetAttribute((const void*)march_kernel<T, MODE_SMOOTH>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)march_kernel<T, MODE_RESID>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)march_kernel<T, MODE_TRSM>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)march_kernel<T, MODE_MATVEC>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if ((e = set_dyn_lds((const void*)march_kernel<T, MODE_SMOOTH>, bytes)) != hipSuccess) return e;
+  if ((e = set_dyn_lds((const void*)march_kernel<T, MODE_RESID>, bytes)) != hipSuccess) return e;
+  if ((e = set_dyn_lds((const void*)march_kernel<T, MODE_TRSM>, bytes)) != hipSuccess) return e;
+  return set_dyn_lds((const void*)march_kernel<T, MODE_MATVEC>, bytes);
 }
 
 template <typename T>
@@ -595,7 +887,17 @@ hipError_t launch_maxabs(const T* x, long long count, double* part, int nparts, 
   return hipGetLastError();
 }
 
+hipError_t launch_fill_int(int* x, long long count, int v, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_int_kernel, dim3(grid_for(count, 256)), dim3(256), 0, s, x, count, v);
+  return hipGetLastError();
+}
+
 // explicit instantiations
+template hipError_t launch_pipeline<double>(const PipeArgs<double>&, size_t, hipStream_t);
+template hipError_t launch_pipeline<float>(const PipeArgs<float>&, size_t, hipStream_t);
+template hipError_t set_pipeline_lds_limit<double>(size_t);
+template hipError_t set_pipeline_lds_limit<float>(size_t);
 template size_t march_lds_bytes<double>(const MarchArgs<double>&);
 template size_t march_lds_bytes<float>(const MarchArgs<float>&);
 template hipError_t launch_march<double>(int, const MarchArgs<double>&, hipStream_t);

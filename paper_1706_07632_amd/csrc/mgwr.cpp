@@ -79,8 +79,21 @@ struct mgwr_plan {
   std::vector<Pending> pending;
   std::vector<hipEvent_t> event_pool;
   mgwr_timing tacc{};
+  // time-pipelined cycles (float64)
+  static constexpr int kMaxPipeCycles = 16;
+  std::vector<Stage<double>> stages;   // host image for kMaxPipeCycles cycles
+  int stages_per_cycle = 0, tasks_per_cycle = 0, norm_chunks = 0;
+  const double* stages_f = nullptr;    // level-0 arrays the uploaded image refers to
+  const double* stages_u = nullptr;
+  Stage<double>* stages_dev = nullptr;
+  int* counters = nullptr;
+  int* flags_dev = nullptr;            // [0] ticket, [1] abort
+  double* norms = nullptr;             // [kMaxPipeCycles][norm_chunks]
+  int khint = 0;                       // cycles the last pipelined solve needed
+  double cycle_flops = 0.0, cycle_bytes = 0.0;  // algorithmic work of one pipelined cycle
   // offsets computed by layout()
   struct Off {
+    size_t stages, counters, flags, norms;
     size_t leaves, dn_list, ff_row, zu_row, a1, B0, part, scal;
     size_t dense64, dinv64, ffA64, zuB64, dense32, dinv32, ffA32, zuB32;
     std::vector<size_t> U64, F64, R64, U32, F32, R32;
@@ -128,6 +141,23 @@ void layout(mgwr_plan* pl) {
       o.F32[l] = cv.take(bytes);
       if (l + 1 < L) o.R32[l] = cv.take(bytes);
     }
+  }
+  // pipelined schedule: stage table, per-(stage, leaf) counters, norms
+  {
+    const int nleaf = (int)pk.leaves.size();
+    // stages per cycle: per non-coarsest level 2(nu1+nu2) half-sweeps + defect +
+    // restriction + prolongation, times gamma^depth visits; coarsest 2; plus the norm defect
+    long long spc = 1, visits = 1;
+    for (int l = 0; l < L; ++l) {
+      if (l == L - 1) spc += 2 * visits;
+      else spc += visits * (2LL * (hp.p.nu1 + hp.p.nu2) + 3);
+      visits *= hp.p.gamma;
+    }
+    const long long S = spc * mgwr_plan::kMaxPipeCycles;
+    o.stages = cv.take((size_t)S * sizeof(Stage<double>));
+    o.counters = cv.take((size_t)S * nleaf * sizeof(int));
+    o.flags = cv.take(2 * sizeof(int));
+    o.norms = cv.take((size_t)mgwr_plan::kMaxPipeCycles * ((hp.levels[0].N + 15) / 16) * sizeof(double));
   }
   o.total = cv.off;
 }
@@ -269,6 +299,178 @@ int cycle(mgwr_plan* pl, DevOps<T>& ops, int l) {
   return MGWR_OK;
 }
 
+
+// ---- time-pipelined cycles ------------------------------------------------
+// Stage list of one cycle of Algorithm 2 on level l (float64), appended to
+// `out`; `prev` is the index of the stage whose output the first new stage
+// consumes.  Returns the index of the last stage appended.
+int append_cycle_stages(mgwr_plan* pl, int l, int prev, std::vector<Stage<double>>& out) {
+  const HostPlan& hp = pl->hp;
+  const int L = (int)hp.levels.size();
+  const Level& lv = hp.levels[l];
+  DevOps<double>& ops = pl->d64;
+  auto base = [&](int kind) {
+    Stage<double> st{};
+    st.kind = kind;
+    st.prev = prev;
+    st.nleaf = (int)hp.pk.leaves.size();
+    st.leaves = pl->leaves;
+    return st;
+  };
+  auto push = [&](Stage<double>& st) {
+    out.push_back(st);
+    prev = (int)out.size() - 1;
+  };
+  auto smooth_stage = [&](int colour) {
+    int par0 = hp.p.dim == 1 ? 1 : 0;
+    int par = colour == 0 ? par0 : 1 - par0;
+    int ncols = (lv.N - par + 1) / 2;
+    if (ncols <= 0) return;
+    Stage<double> st = base(STG_SMOOTH);
+    st.m = base_args<double>(pl, ops, l);
+    st.m.F = ops.F[l]; st.m.U = ops.U[l]; st.m.Out = nullptr;
+    st.m.ld = lv.N; st.m.ncols = ncols; st.m.cstride = 2; st.m.coff = par;
+    st.m.dim = hp.p.dim; st.m.n = lv.n; st.m.inv_h2 = 1.0 / (lv.h * lv.h);
+    st.nchunks = (ncols + 15) / 16;
+    push(st);
+  };
+  if (l == L - 1) {
+    smooth_stage(0);
+    smooth_stage(1);
+    return prev;
+  }
+  for (int s2 = 0; s2 < hp.p.nu1; ++s2) { smooth_stage(0); smooth_stage(1); }
+  {
+    Stage<double> st = base(STG_RESID);
+    st.m = base_args<double>(pl, ops, l);
+    st.m.F = ops.F[l]; st.m.U = ops.U[l]; st.m.Out = ops.R[l];
+    st.m.ld = lv.N; st.m.ncols = lv.N; st.m.cstride = 1; st.m.coff = 0;
+    st.m.dim = hp.p.dim; st.m.n = lv.n; st.m.inv_h2 = 1.0 / (lv.h * lv.h);
+    st.nchunks = (lv.N + 15) / 16;
+    push(st);
+  }
+  const Level& lc = hp.levels[l + 1];
+  {
+    Stage<double> st = base(STG_RESTRICT);
+    st.src = ops.R[l]; st.dst = ops.F[l + 1]; st.zero = ops.U[l + 1];
+    st.dim = hp.p.dim; st.nf = lv.n; st.nc = lc.n;
+    st.nchunks = (lc.N + kStencilCols - 1) / kStencilCols;
+    push(st);
+  }
+  for (int gm = 0; gm < hp.p.gamma; ++gm) prev = append_cycle_stages(pl, l + 1, prev, out);
+  {
+    Stage<double> st = base(STG_PROLONG);
+    st.prev = prev;
+    st.src = ops.U[l + 1]; st.dst = ops.U[l];
+    st.dim = hp.p.dim; st.nf = lv.n; st.nc = lc.n;
+    st.nchunks = (lv.N + kStencilCols - 1) / kStencilCols;
+    push(st);
+  }
+  for (int s2 = 0; s2 < hp.p.nu2; ++s2) { smooth_stage(0); smooth_stage(1); }
+  return prev;
+}
+
+// Builds and uploads the stage table of kMaxPipeCycles cycles for level-0
+// arrays (f, u); task and counter offsets are assigned in stage order.
+int upload_stages(mgwr_plan* pl, const double* b, double* u) {
+  if (pl->stages_f == b && pl->stages_u == u && !pl->stages.empty()) return MGWR_OK;
+  const HostPlan& hp = pl->hp;
+  const int nleaf = (int)hp.pk.leaves.size();
+  pl->d64.F[0] = const_cast<double*>(b);
+  pl->d64.U[0] = u;
+  std::vector<Stage<double>>& st = pl->stages;
+  st.clear();
+  int prev = -1;
+  int per_cycle = -1;
+  for (int c = 0; c < mgwr_plan::kMaxPipeCycles; ++c) {
+    prev = append_cycle_stages(pl, 0, prev, st);
+    // defect of the full system after the cycle: its norm is the stopping test
+    Stage<double> nd{};
+    nd.kind = STG_RESID;
+    nd.prev = prev;
+    nd.nleaf = nleaf;
+    nd.leaves = pl->leaves;
+    nd.m = base_args<double>(pl, pl->d64, 0);
+    const Level& lv = hp.levels[0];
+    nd.m.F = b; nd.m.U = u; nd.m.Out = pl->d64.R[0];
+    nd.m.ld = lv.N; nd.m.ncols = lv.N; nd.m.cstride = 1; nd.m.coff = 0;
+    nd.m.dim = hp.p.dim; nd.m.n = lv.n; nd.m.inv_h2 = 1.0 / (lv.h * lv.h);
+    nd.nchunks = (lv.N + 15) / 16;
+    pl->norm_chunks = nd.nchunks;
+    nd.norm_out = pl->norms + (size_t)c * nd.nchunks;
+    st.push_back(nd);
+    prev = (int)st.size() - 1;
+    if (per_cycle < 0) per_cycle = (int)st.size();
+  }
+  int task = 0;
+  for (size_t i = 0; i < st.size(); ++i) {
+    st[i].task0 = task;
+    task += st[i].nchunks;
+    st[i].cnt_off = (int)i * nleaf;
+  }
+  pl->stages_per_cycle = per_cycle;
+  pl->cycle_flops = pl->cycle_bytes = 0.0;
+  for (int i = 0; i < per_cycle; ++i) {
+    const Stage<double>& x = st[i];
+    if (x.kind == STG_SMOOTH || x.kind == STG_RESID) {
+      pl->cycle_flops += 2.0 * hp.stored * x.m.ncols;
+      pl->cycle_bytes += 3.0 * hp.p.M * x.m.ncols * sizeof(double);
+    } else {
+      const double Nf = hp.p.dim == 1 ? x.nf : (double)x.nf * x.nf;
+      const double Nc = hp.p.dim == 1 ? x.nc : (double)x.nc * x.nc;
+      pl->cycle_bytes += (x.kind == STG_RESTRICT ? (Nf + 2 * Nc) : (Nc + 2 * Nf)) * hp.p.M * sizeof(double);
+    }
+  }
+  pl->tasks_per_cycle = st[per_cycle].task0;
+  if ((size_t)st.size() * sizeof(Stage<double>) > pl->off.counters - pl->off.stages)
+    return fail(MGWR_ERR_STATE, "internal error: stage table larger than its workspace region");
+  HIP_TRY(hipMemcpyAsync(pl->stages_dev, st.data(), st.size() * sizeof(Stage<double>), hipMemcpyHostToDevice,
+                         pl->stream));
+  pl->stages_f = b;
+  pl->stages_u = u;
+  return MGWR_OK;
+}
+
+// Runs `K` cycles in one launch; per-cycle residual norms land in res[0..K).
+int run_pipelined(mgwr_plan* pl, const double* b, double* u, int K, double* res) {
+  int rc;
+  if ((rc = upload_stages(pl, b, u))) return rc;
+  const int nleaf = (int)pl->hp.pk.leaves.size();
+  const int S = pl->stages_per_cycle * K;
+  HIP_TRY(launch_fill_int(pl->counters, (long long)S * nleaf, 0, pl->stream));
+  HIP_TRY(launch_fill_int(pl->flags_dev, 2, 0, pl->stream));
+  PipeArgs<double> pa;
+  pa.stages = pl->stages_dev;
+  pa.nstages = S;
+  pa.ntasks = pl->tasks_per_cycle * K;
+  pa.counters = pl->counters;
+  pa.ticket = pl->flags_dev;
+  pa.abortf = pl->flags_dev + 1;
+  size_t lds = march_lds_bytes<double>(base_args<double>(pl, pl->d64, 0));
+  {
+    Timed tm(pl, MGWR_K_PIPE64, pl->cycle_flops * K, pl->cycle_bytes * K);
+    HIP_TRY(launch_pipeline<double>(pa, lds, pl->stream));
+  }
+  std::vector<double> nh((size_t)K * pl->norm_chunks);
+  int flags[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(nh.data(), pl->norms, nh.size() * sizeof(double), hipMemcpyDeviceToHost, pl->stream));
+  HIP_TRY(hipMemcpyAsync(flags, pl->flags_dev, sizeof(flags), hipMemcpyDeviceToHost, pl->stream));
+  HIP_TRY(hipStreamSynchronize(pl->stream));
+  if (!pl->pending.empty()) drain_timing(pl);
+  if (flags[1]) return fail(MGWR_ERR_HIP, "pipelined cycles stalled (a progress wait exceeded its bound)");
+  for (int c = 0; c < K; ++c) {
+    double m = 0.0;
+    bool bad = false;
+    for (int j = 0; j < pl->norm_chunks; ++j) {
+      double v = nh[(size_t)c * pl->norm_chunks + j];
+      if (v != v) bad = true;
+      else m = std::max(m, v);
+    }
+    res[c] = bad ? std::nan("") : m;
+  }
+  return MGWR_OK;
+}
+
 int read_scalar(mgwr_plan* pl, double* host) {
   HIP_TRY(hipMemcpyAsync(host, pl->scal, sizeof(double), hipMemcpyDeviceToHost, pl->stream));
   HIP_TRY(hipStreamSynchronize(pl->stream));
@@ -366,6 +568,13 @@ int mgwr_plan_bind(mgwr_plan* pl, void* ws, size_t bytes, void* stream) {
   pl->part = (double*)(w + o.part);
   pl->scal = (double*)(w + o.scal);
   pl->B0 = (double*)(w + o.B0);
+  pl->stages_dev = (Stage<double>*)(w + o.stages);
+  pl->counters = (int*)(w + o.counters);
+  pl->flags_dev = (int*)(w + o.flags);
+  pl->norms = (double*)(w + o.norms);
+  pl->stages.clear();
+  pl->stages_f = nullptr;
+  pl->stages_u = nullptr;
   pl->d64.dense = (double*)(w + o.dense64);
   pl->d64.dinv = (double*)(w + o.dinv64);
   pl->d64.ffA = (double*)(w + o.ffA64);
@@ -414,13 +623,15 @@ int mgwr_plan_bind(mgwr_plan* pl, void* ws, size_t bytes, void* stream) {
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, pl->device));
   size_t cap = prop.sharedMemPerBlock;
-  if (lds > cap) return fail(MGWR_ERR_STATE, "H-matrix accumulators need " + std::to_string(lds) +
+  if (lds + 64 > cap) return fail(MGWR_ERR_STATE, "H-matrix accumulators need " + std::to_string(lds) +
                                                  " bytes of LDS, device allows " + std::to_string(cap));
   // The attribute is a per-kernel ceiling shared by every plan in the process:
   // raise it to the device limit once so no later bind can lower it below an
   // earlier plan's need; each launch still requests exactly its own size.
   HIP_TRY(set_march_lds_limit<double>(cap));
   HIP_TRY(set_march_lds_limit<float>(cap));
+  HIP_TRY(set_pipeline_lds_limit<double>(cap));
+  HIP_TRY(set_pipeline_lds_limit<float>(cap));
   HIP_TRY(hipStreamSynchronize(pl->stream));
   pl->bound = true;
   return MGWR_OK;
@@ -478,7 +689,28 @@ int mgwr_solve(mgwr_plan* pl, const double* f, const double* g, double tol, doub
   if (!std::isfinite(s.res0)) status = MGWR_ERR_NONFINITE;
   else if (s.res0 <= target) status = MGWR_OK;
 
-  if (status == MGWR_ERR_NOT_CONVERGED && !pl->mixed) {
+  if (status == MGWR_ERR_NOT_CONVERGED && !pl->mixed && hp.p.schedule == MGWR_SCHED_PIPELINED) {
+    int K = pl->khint > 0 ? pl->khint : 8;
+    int converged_at = -1;
+    while (s.cycles < hp.p.max_cycles) {
+      K = std::max(1, std::min({K, mgwr_plan::kMaxPipeCycles, hp.p.max_cycles - s.cycles}));
+      double res[mgwr_plan::kMaxPipeCycles];
+      if ((rc = run_pipelined(pl, b, u, K, res))) return rc;
+      for (int c = 0; c < K; ++c) {
+        if (s.cycles + c < 64) s.history[s.cycles + c] = res[c];
+        if (converged_at < 0 && res[c] <= target) converged_at = s.cycles + c + 1;
+      }
+      const double first = s.cycles == 0 ? s.res0 : s.res;
+      s.cycles += K;
+      s.res = res[K - 1];
+      if (!std::isfinite(s.res)) { status = MGWR_ERR_NONFINITE; break; }
+      if (s.res <= target) { status = MGWR_OK; break; }
+      // extrapolate the remaining cycles from the observed contraction
+      double rate = std::pow(std::max(s.res / first, 1e-300), 1.0 / K);
+      K = (rate < 0.99 && rate > 0) ? (int)std::ceil(std::log(target / s.res) / std::log(rate)) : K;
+    }
+    if (converged_at > 0) pl->khint = converged_at;
+  } else if (status == MGWR_ERR_NOT_CONVERGED && !pl->mixed) {
     pl->d64.F[0] = const_cast<double*>(b);
     pl->d64.U[0] = u;
     while (s.cycles < hp.p.max_cycles) {

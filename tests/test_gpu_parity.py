@@ -212,3 +212,25 @@ def test_mixed_precision_on_strongly_graded_mesh(dev):
     assert np.max(np.abs(r)) <= 1e-8 * st["bnorm"] * 1.01, st
     err = np.max(np.abs(U - np.outer(w, s))) / np.max(np.abs(w))
     assert err < 1e-7, err
+
+
+@pytest.mark.parametrize("dim,n,M,alpha,r,k,gamma", [(1, 63, 128, 0.5, 3.0, 8, 1), (2, 31, 256, 0.4, 3.0, 10, 1),
+                                                     (1, 127, 512, 0.3, 17 / 3, 10, 2)])
+def test_pipelined_schedule_matches_staged(dev, dim, n, M, alpha, r, k, gamma):
+    """The time-pipelined launch of whole cycles computes the same iterates as one
+    launch per stage (up to float64 rounding order)."""
+    rng = np.random.default_rng(9)
+    N = n ** dim
+    t = W.graded_mesh(M, 1.0, r)
+    f = _cuda(rng.standard_normal((M, N)), dev)
+    g = _cuda(rng.standard_normal(N), dev)
+    out = {}
+    for sched in ("staged", "pipelined"):
+        plan = mg.Plan(dim, n, M, alpha, k=k, t=t, gamma=gamma, schedule=sched, max_cycles=5).bind()
+        u, st = plan.solve(f, g, tol=1e-30, allow_unconverged=True)
+        out[sched] = (u.cpu().numpy(), st)
+    (u1, s1), (u2, s2) = out["staged"], out["pipelined"]
+    assert s1["cycles"] == s2["cycles"] == 5
+    assert np.max(np.abs(u1 - u2)) <= 1e-12 * np.max(np.abs(u1))
+    h1, h2 = np.array(s1["history"]), np.array(s2["history"])
+    assert np.all(np.abs(h1 - h2) <= 1e-6 * h1 + 1e-14 * s1["bnorm"]), (h1, h2)
