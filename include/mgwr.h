@@ -75,7 +75,7 @@ typedef struct {
   int max_cycles;   /* cap on cycles (plain) or inner cycles in total (mixed) */
   int precision;    /* mgwr_precision */
   int inner_cycles; /* mixed precision: inner V-cycles per outer refinement step */
-  int schedule;     /* MGWR_SCHED_PIPELINED (default) or MGWR_SCHED_STAGED */
+  int schedule;     /* MGWR_SCHED_AUTO (default), MGWR_SCHED_STAGED or MGWR_SCHED_PIPELINED */
 } mgwr_params;
 
 /* Cycle schedules (float64 solver).  Every operator of a cycle is causal in
@@ -84,10 +84,12 @@ typedef struct {
  * time leaf i as soon as the stage before it has finished leaf i.  The staged
  * schedule launches one kernel per stage and checks the residual after every
  * cycle.  Both compute the same iterates up to the order of float64 rounding. */
-enum { MGWR_SCHED_PIPELINED = 0, MGWR_SCHED_STAGED = 1 };
+enum { MGWR_SCHED_AUTO = 0, MGWR_SCHED_STAGED = 1, MGWR_SCHED_PIPELINED = 2 };
+/* AUTO pipelines when the finest level has few 16-column chains (the staged
+ * launches then leave most of the GPU idle) and stages otherwise. */
 
 /* Fill *p with defaults: leaf 16, V(1,1), gamma 1, max_cycles 50, FP64, length 1, T 1,
- * pipelined schedule. */
+ * automatic schedule. */
 void mgwr_params_default(mgwr_params* p);
 
 typedef struct {
@@ -97,7 +99,9 @@ typedef struct {
   double bnorm;      /* ||b||_inf, b = f + a_{.,1} g */
   double res;        /* final ||b - A u||_inf (float64) */
   double avg_factor; /* (res/res0)^(1/cycles) */
-  double history[64]; /* ||b - A u||_inf after each of the first 64 outer steps (cycles or refinements) */
+  double history[64]; /* ||b - A u||_inf after each of the first 64 outer steps (cycles or
+                         refinements); 0 where a pipelined launch with a learned cycle count
+                         evaluated the norm only after its last cycle */
 } mgwr_stats;
 
 typedef struct mgwr_plan mgwr_plan;
@@ -176,6 +180,30 @@ typedef struct {
 int mgwr_timing_enable(mgwr_plan* plan, int enable);
 /* Synchronises the plan's stream and returns the counters. */
 int mgwr_timing_get(mgwr_plan* plan, mgwr_timing* out);
+
+/* Batched solves: several bound plans (different n, M, alpha, k, dim allowed,
+ * same device) solved together.  Their time-pipelined cycles are merged into
+ * one launch with the stages of the instances interleaved, so the instances
+ * advance concurrently; every instance keeps its own cycle count and
+ * stopping test.  The batch owns a small workspace of its own (stage table,
+ * progress counters, norms); each plan keeps using its own workspace. */
+typedef struct mgwr_batch mgwr_batch;
+/* plans[0..count) must stay alive and bound while the batch is used. */
+int mgwr_batch_create(int count, mgwr_plan* const* plans, mgwr_batch** out);
+int mgwr_batch_workspace_bytes(const mgwr_batch* batch, size_t* bytes);
+/* workspace_dev: 256-byte aligned device memory; stream: hipStream_t or NULL. */
+int mgwr_batch_bind(mgwr_batch* batch, void* workspace_dev, size_t bytes, void* stream);
+/* f_dev[i], g_dev[i] (g_dev or g_dev[i] may be NULL), u_dev[i]: the arrays of
+ * mgwr_solve for instance i; stats may be NULL or hold `count` entries.
+ * Returns MGWR_OK when every instance converged, else the first non-OK
+ * status of an instance (all outputs are written). */
+int mgwr_batch_solve(mgwr_batch* batch, const double* const* f_dev, const double* const* g_dev, double tol,
+                     double* const* u_dev, unsigned flags, mgwr_stats* stats);
+/* Event timing of the batch's launches (class MGWR_K_PIPE64); synchronises.
+ * out (nullable) receives the counters; enable 1 clears them and turns timing
+ * on, 0 turns it off, -1 leaves it unchanged. */
+int mgwr_batch_timing(mgwr_batch* batch, int enable, mgwr_timing* out);
+int mgwr_batch_destroy(mgwr_batch* batch);
 
 /* Plan facts for tests and reports (host, no device work). */
 typedef struct {

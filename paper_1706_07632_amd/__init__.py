@@ -27,7 +27,8 @@ EXPORTED = [
     "mgwr_params_default", "mgwr_plan_create", "mgwr_plan_workspace_bytes", "mgwr_plan_bind",
     "mgwr_solve", "mgwr_residual", "mgwr_hmatvec", "mgwr_htrsm", "mgwr_plan_get_info",
     "mgwr_plan_get_mesh", "mgwr_plan_export_dense", "mgwr_plan_destroy", "mgwr_last_error",
-    "mgwr_timing_enable", "mgwr_timing_get",
+    "mgwr_timing_enable", "mgwr_timing_get", "mgwr_batch_create", "mgwr_batch_workspace_bytes",
+    "mgwr_batch_bind", "mgwr_batch_solve", "mgwr_batch_timing", "mgwr_batch_destroy",
 ]
 
 KERNEL_CLASSES = ["smooth64", "defect64", "smooth32", "defect32", "restrict", "prolong", "pipe64"]
@@ -107,6 +108,13 @@ def lib():
     L.mgwr_plan_destroy.argtypes = [vp]
     L.mgwr_timing_enable.argtypes = [vp, ip]
     L.mgwr_timing_get.argtypes = [vp, ctypes.POINTER(Timing)]
+    L.mgwr_batch_create.argtypes = [ip, ctypes.POINTER(vp), ctypes.POINTER(vp)]
+    L.mgwr_batch_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.mgwr_batch_bind.argtypes = [vp, vp, ctypes.c_size_t, vp]
+    L.mgwr_batch_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_double,
+                                   ctypes.POINTER(vp), ctypes.c_uint, ctypes.POINTER(Stats)]
+    L.mgwr_batch_timing.argtypes = [vp, ip, ctypes.POINTER(Timing)]
+    L.mgwr_batch_destroy.argtypes = [vp]
     L.mgwr_last_error.argtypes = []
     L.mgwr_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -149,7 +157,7 @@ class Plan:
 
     def __init__(self, dim, n, M, alpha, k=10, r=1.0, T=1.0, length=1.0, t=None, leaf=16,
                  nu1=1, nu2=1, gamma=1, max_cycles=50, precision="fp64", inner_cycles=1,
-                 schedule="pipelined"):
+                 schedule="auto"):
         import numpy as np
         L = lib()
         p = Params()
@@ -159,7 +167,7 @@ class Plan:
         p.nu1, p.nu2, p.gamma, p.max_cycles = int(nu1), int(nu2), int(gamma), int(max_cycles)
         p.precision = {"fp64": MGWR_FP64, "mixed": MGWR_MIXED_FP32, "fp32": MGWR_MIXED_FP32}[precision]
         p.inner_cycles = int(inner_cycles)
-        p.schedule = {"pipelined": 0, "staged": 1}[schedule]
+        p.schedule = {"auto": 0, "staged": 1, "pipelined": 2}[schedule]
         self.params = p
         self.dim, self.n, self.M = int(dim), int(n), int(M)
         self.N = self.n ** self.dim
@@ -276,6 +284,68 @@ class Plan:
             lib().mgwr_plan_destroy(self._h)
             self._h = None
         self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several bound plans solved together in merged time-pipelined launches."""
+
+    def __init__(self, plans):
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        h = ctypes.c_void_p()
+        _check(lib().mgwr_batch_create(len(self.plans), arr, ctypes.byref(h)))
+        self._h = h
+        self._ws = None
+
+    def bind(self, stream=None):
+        import torch
+        dev = self.plans[0].device
+        with torch.cuda.device(dev):
+            b = ctypes.c_size_t()
+            _check(lib().mgwr_batch_workspace_bytes(self._h, ctypes.byref(b)))
+            self._ws = torch.empty(b.value + 256, dtype=torch.uint8, device=dev)
+            aligned = (self._ws.data_ptr() + 255) & ~255
+            self._stream = torch.cuda.current_stream(dev) if stream is None else stream
+            _check(lib().mgwr_batch_bind(self._h, ctypes.c_void_p(aligned), b.value,
+                                         ctypes.c_void_p(self._stream.cuda_stream)))
+        return self
+
+    def solve(self, fs, gs=None, tol=1e-10, us=None, guess=False, allow_unconverged=False):
+        import torch
+        n = len(self.plans)
+        if us is None:
+            us = [torch.empty((p.M, p.N), dtype=torch.float64, device=f.device) for p, f in zip(self.plans, fs)]
+        for p, f, u in zip(self.plans, fs, us):
+            _require(f, "f", (p.M, p.N))
+            _require(u, "u", (p.M, p.N))
+        fa = (ctypes.c_void_p * n)(*[f.data_ptr() for f in fs])
+        ua = (ctypes.c_void_p * n)(*[u.data_ptr() for u in us])
+        ga = None
+        if gs is not None:
+            for p, g in zip(self.plans, gs):
+                if g is not None:
+                    _require(g, "g", (p.N,))
+            ga = (ctypes.c_void_p * n)(*[None if g is None else g.data_ptr() for g in gs])
+        st = (Stats * n)()
+        rc = lib().mgwr_batch_solve(self._h, fa, ga, float(tol), ua, MGWR_GUESS_IN_U if guess else 0, st)
+        _check(rc, ok=(MGWR_OK, MGWR_ERR_NOT_CONVERGED) if allow_unconverged else (MGWR_OK,))
+        return us, [s.as_dict() for s in st]
+
+    def timing(self, enable=None):
+        tm = Timing()
+        _check(lib().mgwr_batch_timing(self._h, -1 if enable is None else (1 if enable else 0), ctypes.byref(tm)))
+        return tm.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mgwr_batch_destroy(self._h)
+            self._h = None
 
     def __del__(self):
         try:

@@ -71,7 +71,8 @@ std::string build_host_plan(const mgwr_params& p, const double* t_host, HostPlan
   if (p.max_cycles < 1) return "max_cycles must be >= 1";
   if (p.precision != MGWR_FP64 && p.precision != MGWR_MIXED_FP32) return "unknown precision";
   if (p.precision == MGWR_MIXED_FP32 && p.inner_cycles < 1) return "inner_cycles must be >= 1";
-  if (p.schedule != MGWR_SCHED_PIPELINED && p.schedule != MGWR_SCHED_STAGED) return "unknown schedule";
+  if (p.schedule != MGWR_SCHED_AUTO && p.schedule != MGWR_SCHED_PIPELINED && p.schedule != MGWR_SCHED_STAGED)
+    return "unknown schedule";
   if ((long long)p.M * (long long)std::pow((double)p.n, p.dim) > (1ll << 40)) return "problem too large";
 
   hp.p = p;

@@ -67,7 +67,7 @@ struct PipeArgs {
   int* abortf;
 };
 
-constexpr int kStencilCols = 256;  // columns per work item of a stencil stage
+constexpr int kStencilCols = 64;   // columns per work item of a stencil stage (leaf rows <= 16 = 4 x 4)
 
 template <typename T> size_t march_lds_bytes(const MarchArgs<T>& a);
 template <typename T> hipError_t launch_pipeline(const PipeArgs<T>& pa, size_t lds, hipStream_t s);

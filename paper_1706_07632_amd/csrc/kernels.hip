@@ -473,6 +473,12 @@ __global__ __launch_bounds__(256) void march_kernel(MarchArgs<T> a) {
 
 static hipError_t set_dyn_lds(const void* fn, size_t bytes);
 
+// Stencil stages: a work item covers kStencilCols columns; thread t handles
+// column t % kStencilCols and rows t / kStencilCols + 4 j (j = 0..3) of each
+// leaf, loading all its rows before storing, so one leaf costs about one
+// memory round trip.
+constexpr int kStencilRowsPerPass = 256 / kStencilCols;
+
 // Full-weighting restriction of the rows of one leaf, and the zero start of
 // the coarse iterate on those rows.
 template <typename T>
@@ -480,9 +486,31 @@ __device__ void restrict_stage(const Stage<T>& st, int chunk, const PipeCtx& pc,
   const int nf = st.nf, nc = st.nc;
   const long long Nc = st.dim == 1 ? nc : (long long)nc * nc;
   const long long Nf = st.dim == 1 ? nf : (long long)nf * nf;
-  const long long Q = (long long)chunk * kStencilCols + threadIdx.x;
+  const long long Q = (long long)chunk * kStencilCols + (threadIdx.x % kStencilCols);
+  const int r0 = threadIdx.x / kStencilCols;
   const bool ok = Q < Nc;
   const int lane = threadIdx.x & 63;
+  // fine-grid offsets of the 9-point (2D) / 3-point (1D) weighted stencil
+  long long off[9];
+  T wgt[9];
+  int nw = 0;
+  if (ok) {
+    if (st.dim == 1) {
+      const long long f = 2 * Q + 1;
+      off[0] = f - 1; wgt[0] = (T)0.25;
+      off[1] = f;     wgt[1] = (T)0.5;
+      off[2] = f + 1; wgt[2] = (T)0.25;
+      nw = 3;
+    } else {
+      const long long I = Q % nc, J = Q / nc;
+      const long long fx = 2 * I + 1, fy = 2 * J + 1;
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          off[nw] = (fy + dy) * nf + fx + dx;
+          wgt[nw++] = (T)((dx == 0 ? 2 : 1) * (dy == 0 ? 2 : 1)) * (T)(1.0 / 16.0);
+        }
+    }
+  }
   for (int i = 0; i < st.nleaf; ++i) {
     const LeafDesc d = st.leaves[i];
     if (threadIdx.x < 64) {
@@ -491,27 +519,24 @@ __device__ void restrict_stage(const Stage<T>& st, int chunk, const PipeCtx& pc,
     __syncthreads();
     if (*sh_abort) return;
     if (ok) {
-      for (int row = 0; row < d.sz; ++row) {
-        const long long m = d.lo + row;
-        const T* r = st.src + m * Nf;
-        T v;
-        if (st.dim == 1) {
-          const long long f = 2 * Q + 1;
-          v = (T)0.25 * (gld<true>(r + f - 1) + (T)2 * gld<true>(r + f) + gld<true>(r + f + 1));
-        } else {
-          const long long I = Q % nc, J = Q / nc;
-          const long long fx = 2 * I + 1, fy = 2 * J + 1;
-          const T* r0 = r + (fy - 1) * nf;
-          const T* r1 = r + fy * nf;
-          const T* r2 = r + (fy + 1) * nf;
-          v = (T)(1.0 / 16.0) * ((gld<true>(r0 + fx - 1) + gld<true>(r0 + fx + 1) + gld<true>(r2 + fx - 1) +
-                                  gld<true>(r2 + fx + 1)) +
-                                 (T)2 * (gld<true>(r0 + fx) + gld<true>(r2 + fx) + gld<true>(r1 + fx - 1) +
-                                         gld<true>(r1 + fx + 1)) +
-                                 (T)4 * gld<true>(r1 + fx));
+      T v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = r0 + j * kStencilRowsPerPass;
+        v[j] = (T)0;
+        if (row < d.sz) {
+          const T* r = st.src + (long long)(d.lo + row) * Nf;
+          for (int t = 0; t < nw; ++t) v[j] += wgt[t] * gld<true>(r + off[t]);
         }
-        gst<true>(st.dst + m * Nc + Q, v);
-        gst<true>(st.zero + m * Nc + Q, (T)0);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = r0 + j * kStencilRowsPerPass;
+        if (row < d.sz) {
+          const long long m = d.lo + row;
+          gst<true>(st.dst + m * Nc + Q, v[j]);
+          gst<true>(st.zero + m * Nc + Q, (T)0);
+        }
       }
     }
     __builtin_amdgcn_s_waitcnt(0);
@@ -527,7 +552,8 @@ __device__ void prolong_stage(const Stage<T>& st, int chunk, const PipeCtx& pc, 
   const int nf = st.nf, nc = st.nc;
   const long long Nc = st.dim == 1 ? nc : (long long)nc * nc;
   const long long Nf = st.dim == 1 ? nf : (long long)nf * nf;
-  const long long q = (long long)chunk * kStencilCols + threadIdx.x;
+  const long long q = (long long)chunk * kStencilCols + (threadIdx.x % kStencilCols);
+  const int r0 = threadIdx.x / kStencilCols;
   const bool ok = q < Nf;
   const int lane = threadIdx.x & 63;
   long long cidx[4];
@@ -568,13 +594,23 @@ __device__ void prolong_stage(const Stage<T>& st, int chunk, const PipeCtx& pc, 
     __syncthreads();
     if (*sh_abort) return;
     if (ok) {
-      for (int row = 0; row < d.sz; ++row) {
-        const long long m = d.lo + row;
-        const T* e = st.src + m * Nc;
-        T v = (T)0;
-        for (int t = 0; t < ncoef; ++t) v += cw[t] * gld<true>(e + cidx[t]);
-        T* u = st.dst + m * Nf + q;
-        gst<true>(u, gld<true>(u) + v);
+      T v[4], u0[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = r0 + j * kStencilRowsPerPass;
+        v[j] = (T)0;
+        u0[j] = (T)0;
+        if (row < d.sz) {
+          const long long m = d.lo + row;
+          const T* e = st.src + m * Nc;
+          for (int t = 0; t < ncoef; ++t) v[j] += cw[t] * gld<true>(e + cidx[t]);
+          u0[j] = gld<true>(st.dst + m * Nf + q);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = r0 + j * kStencilRowsPerPass;
+        if (row < d.sz) gst<true>(st.dst + (long long)(d.lo + row) * Nf + q, u0[j] + v[j]);
       }
     }
     __builtin_amdgcn_s_waitcnt(0);

@@ -103,6 +103,18 @@ struct mgwr_plan {
 
 namespace {
 
+// Upper bound of the stages of one pipelined cycle (plus its norm defect).
+long long stages_per_cycle_bound(const HostPlan& hp) {
+  const int L = (int)hp.levels.size();
+  long long spc = 1, visits = 1;
+  for (int l = 0; l < L; ++l) {
+    if (l == L - 1) spc += 2 * visits;
+    else spc += visits * (2LL * (hp.p.nu1 + hp.p.nu2) + 3);
+    visits *= hp.p.gamma;
+  }
+  return spc;
+}
+
 void layout(mgwr_plan* pl) {
   const HostPlan& hp = pl->hp;
   const PackedPlan& pk = hp.pk;
@@ -147,13 +159,7 @@ void layout(mgwr_plan* pl) {
     const int nleaf = (int)pk.leaves.size();
     // stages per cycle: per non-coarsest level 2(nu1+nu2) half-sweeps + defect +
     // restriction + prolongation, times gamma^depth visits; coarsest 2; plus the norm defect
-    long long spc = 1, visits = 1;
-    for (int l = 0; l < L; ++l) {
-      if (l == L - 1) spc += 2 * visits;
-      else spc += visits * (2LL * (hp.p.nu1 + hp.p.nu2) + 3);
-      visits *= hp.p.gamma;
-    }
-    const long long S = spc * mgwr_plan::kMaxPipeCycles;
+    const long long S = stages_per_cycle_bound(hp) * mgwr_plan::kMaxPipeCycles;
     o.stages = cv.take((size_t)S * sizeof(Stage<double>));
     o.counters = cv.take((size_t)S * nleaf * sizeof(int));
     o.flags = cv.take(2 * sizeof(int));
@@ -370,21 +376,23 @@ int append_cycle_stages(mgwr_plan* pl, int l, int prev, std::vector<Stage<double
   return prev;
 }
 
-// Builds and uploads the stage table of kMaxPipeCycles cycles for level-0
-// arrays (f, u); task and counter offsets are assigned in stage order.
-int upload_stages(mgwr_plan* pl, const double* b, double* u) {
-  if (pl->stages_f == b && pl->stages_u == u && !pl->stages.empty()) return MGWR_OK;
+// Appends K cycles of plan pl.  The defect of the full system (whose
+// per-work-item norms go to norms[c * chunks + item]) follows every cycle
+// when `every` is set, else only the last one.  Stage indices (prev) are
+// relative to the first stage appended.
+void build_plan_stages(mgwr_plan* pl, const double* b, double* u, int K, double* norms,
+                       std::vector<Stage<double>>& out, bool every = true) {
   const HostPlan& hp = pl->hp;
   const int nleaf = (int)hp.pk.leaves.size();
   pl->d64.F[0] = const_cast<double*>(b);
   pl->d64.U[0] = u;
-  std::vector<Stage<double>>& st = pl->stages;
-  st.clear();
+  std::vector<Stage<double>> st;
   int prev = -1;
   int per_cycle = -1;
-  for (int c = 0; c < mgwr_plan::kMaxPipeCycles; ++c) {
+  for (int c = 0; c < K; ++c) {
     prev = append_cycle_stages(pl, 0, prev, st);
-    // defect of the full system after the cycle: its norm is the stopping test
+    if (per_cycle < 0) per_cycle = (int)st.size() + 1;
+    if (!every && c + 1 < K) continue;
     Stage<double> nd{};
     nd.kind = STG_RESID;
     nd.prev = prev;
@@ -396,19 +404,12 @@ int upload_stages(mgwr_plan* pl, const double* b, double* u) {
     nd.m.ld = lv.N; nd.m.ncols = lv.N; nd.m.cstride = 1; nd.m.coff = 0;
     nd.m.dim = hp.p.dim; nd.m.n = lv.n; nd.m.inv_h2 = 1.0 / (lv.h * lv.h);
     nd.nchunks = (lv.N + 15) / 16;
-    pl->norm_chunks = nd.nchunks;
-    nd.norm_out = pl->norms + (size_t)c * nd.nchunks;
+    nd.norm_out = norms + (size_t)(every ? c : 0) * nd.nchunks;
     st.push_back(nd);
     prev = (int)st.size() - 1;
-    if (per_cycle < 0) per_cycle = (int)st.size();
-  }
-  int task = 0;
-  for (size_t i = 0; i < st.size(); ++i) {
-    st[i].task0 = task;
-    task += st[i].nchunks;
-    st[i].cnt_off = (int)i * nleaf;
   }
   pl->stages_per_cycle = per_cycle;
+  pl->norm_chunks = (hp.levels[0].N + 15) / 16;
   pl->cycle_flops = pl->cycle_bytes = 0.0;
   for (int i = 0; i < per_cycle; ++i) {
     const Stage<double>& x = st[i];
@@ -421,54 +422,31 @@ int upload_stages(mgwr_plan* pl, const double* b, double* u) {
       pl->cycle_bytes += (x.kind == STG_RESTRICT ? (Nf + 2 * Nc) : (Nc + 2 * Nf)) * hp.p.M * sizeof(double);
     }
   }
-  pl->tasks_per_cycle = st[per_cycle].task0;
-  if ((size_t)st.size() * sizeof(Stage<double>) > pl->off.counters - pl->off.stages)
-    return fail(MGWR_ERR_STATE, "internal error: stage table larger than its workspace region");
-  HIP_TRY(hipMemcpyAsync(pl->stages_dev, st.data(), st.size() * sizeof(Stage<double>), hipMemcpyHostToDevice,
-                         pl->stream));
-  pl->stages_f = b;
-  pl->stages_u = u;
-  return MGWR_OK;
+  out.insert(out.end(), st.begin(), st.end());
 }
 
-// Runs `K` cycles in one launch; per-cycle residual norms land in res[0..K).
-int run_pipelined(mgwr_plan* pl, const double* b, double* u, int K, double* res) {
-  int rc;
-  if ((rc = upload_stages(pl, b, u))) return rc;
-  const int nleaf = (int)pl->hp.pk.leaves.size();
-  const int S = pl->stages_per_cycle * K;
-  HIP_TRY(launch_fill_int(pl->counters, (long long)S * nleaf, 0, pl->stream));
-  HIP_TRY(launch_fill_int(pl->flags_dev, 2, 0, pl->stream));
-  PipeArgs<double> pa;
-  pa.stages = pl->stages_dev;
-  pa.nstages = S;
-  pa.ntasks = pl->tasks_per_cycle * K;
-  pa.counters = pl->counters;
-  pa.ticket = pl->flags_dev;
-  pa.abortf = pl->flags_dev + 1;
-  size_t lds = march_lds_bytes<double>(base_args<double>(pl, pl->d64, 0));
-  {
-    Timed tm(pl, MGWR_K_PIPE64, pl->cycle_flops * K, pl->cycle_bytes * K);
-    HIP_TRY(launch_pipeline<double>(pa, lds, pl->stream));
+// Task offsets (stage order) and counter offsets.
+void assign_offsets(std::vector<Stage<double>>& st) {
+  int task = 0;
+  long long cnt = 0;
+  for (auto& x : st) {
+    x.task0 = task;
+    task += x.nchunks;
+    x.cnt_off = (int)cnt;
+    cnt += x.nleaf;
   }
-  std::vector<double> nh((size_t)K * pl->norm_chunks);
-  int flags[2] = {0, 0};
-  HIP_TRY(hipMemcpyAsync(nh.data(), pl->norms, nh.size() * sizeof(double), hipMemcpyDeviceToHost, pl->stream));
-  HIP_TRY(hipMemcpyAsync(flags, pl->flags_dev, sizeof(flags), hipMemcpyDeviceToHost, pl->stream));
-  HIP_TRY(hipStreamSynchronize(pl->stream));
-  if (!pl->pending.empty()) drain_timing(pl);
-  if (flags[1]) return fail(MGWR_ERR_HIP, "pipelined cycles stalled (a progress wait exceeded its bound)");
-  for (int c = 0; c < K; ++c) {
-    double m = 0.0;
-    bool bad = false;
-    for (int j = 0; j < pl->norm_chunks; ++j) {
-      double v = nh[(size_t)c * pl->norm_chunks + j];
-      if (v != v) bad = true;
-      else m = std::max(m, v);
-    }
-    res[c] = bad ? std::nan("") : m;
-  }
-  return MGWR_OK;
+}
+
+// Schedule choice: a staged launch of the finest smoother has N/32 chains of
+// 16 columns; below kAutoPipelineChains of them the GPU is mostly idle and the
+// pipelined schedule wins (measured: 1D n=1023 pipelines 9x faster, 2D n=255
+// with 2032 chains is faster staged).
+constexpr int kAutoPipelineChains = 256;
+bool use_pipeline(const mgwr_plan* pl) {
+  const int sched = pl->hp.p.schedule;
+  if (sched == MGWR_SCHED_PIPELINED) return true;
+  if (sched == MGWR_SCHED_STAGED) return false;
+  return (pl->hp.levels[0].N + 31) / 32 <= kAutoPipelineChains;
 }
 
 int read_scalar(mgwr_plan* pl, double* host) {
@@ -499,6 +477,199 @@ int use_device(mgwr_plan* pl) {
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// batched solves
+
+struct mgwr_batch {
+  std::vector<mgwr_plan*> plans;
+  bool bound = false;
+  int device = -1;
+  hipStream_t stream = nullptr;
+  size_t off_stages = 0, off_counters = 0, off_flags = 0, off_norms = 0, total = 0;
+  std::vector<size_t> norm_off;  // per plan, in doubles
+  Stage<double>* stages_dev = nullptr;
+  int* counters = nullptr;
+  int* flags_dev = nullptr;
+  double* norms = nullptr;
+  std::vector<Stage<double>> stages;
+  size_t lds = 0;
+  bool timing = false;
+  mgwr_timing tacc{};
+};
+
+namespace {
+
+// Prepares instance i: b = f + a_1 g, zero iterate unless given, ||b||, res0.
+int prepare_solve(mgwr_plan* pl, const double* f, const double* g, double tol, double* u, unsigned flags,
+                  mgwr_stats& s, const double*& b, int& status) {
+  int rc;
+  const HostPlan& hp = pl->hp;
+  const long long MN = (long long)hp.p.M * hp.levels[0].N;
+  s = mgwr_stats{};
+  b = f;
+  if (g) {
+    HIP_TRY(launch_rhs0(f, g, pl->a1, pl->B0, hp.p.M, hp.levels[0].N, pl->stream));
+    b = pl->B0;
+  }
+  if (!(flags & MGWR_GUESS_IN_U)) HIP_TRY(launch_fill<double>(u, MN, 0.0, pl->stream));
+  if ((rc = norm_inf<double>(pl, b, MN, &s.bnorm))) return rc;
+  status = MGWR_ERR_NOT_CONVERGED;
+  if (!std::isfinite(s.bnorm)) { status = MGWR_ERR_NONFINITE; return MGWR_OK; }
+  if (flags & MGWR_GUESS_IN_U) {
+    if ((rc = defect<double>(pl, pl->d64, 0, b, u, pl->d64.R[0]))) return rc;
+    if ((rc = norm_inf<double>(pl, pl->d64.R[0], MN, &s.res0))) return rc;
+  } else {
+    s.res0 = s.bnorm;
+  }
+  s.res = s.res0;
+  if (!std::isfinite(s.res0)) status = MGWR_ERR_NONFINITE;
+  else if (s.res0 <= tol * s.bnorm) status = MGWR_OK;
+  return MGWR_OK;
+}
+
+int batch_fail(int code, const std::string& m) { return fail(code, m); }
+
+}  // namespace
+
+// Pipelined solve of plans[0..n) (float64) with the stage table, counters,
+// flags and norms of `bt` (a batch, or one plan's own regions).
+int solve_pipelined(mgwr_batch* bt, const double* const* f, const double* const* g, double tol,
+                    double* const* u, unsigned flags, mgwr_stats* stats) {
+  const int n = (int)bt->plans.size();
+  int rc;
+  std::vector<mgwr_stats> st(n);
+  std::vector<const double*> b(n);
+  std::vector<int> status(n), K(n), conv_at(n, -1);
+  for (int i = 0; i < n; ++i) {
+    mgwr_plan* pl = bt->plans[i];
+    if (!f[i] || !u[i]) return batch_fail(MGWR_ERR_INVALID_ARG, "null array in batch");
+    if ((rc = use_device(pl))) return rc;
+    if ((rc = prepare_solve(pl, f[i], g ? g[i] : nullptr, tol, u[i], flags, st[i], b[i], status[i]))) return rc;
+    K[i] = pl->khint > 0 ? pl->khint : 8;
+  }
+  // the plans' streams must be complete before the batch stream uses their arrays
+  for (int i = 0; i < n; ++i) HIP_TRY(hipStreamSynchronize(bt->plans[i]->stream));
+  while (true) {
+    std::vector<int> act;
+    for (int i = 0; i < n; ++i)
+      if (status[i] == MGWR_ERR_NOT_CONVERGED && st[i].cycles < bt->plans[i]->hp.p.max_cycles) act.push_back(i);
+    if (act.empty()) break;
+    // per-instance stage lists, then interleaved by position
+    std::vector<std::vector<Stage<double>>> lists(act.size());
+    std::vector<char> norms_every(act.size(), 1);
+    size_t maxlen = 0;
+    double flops = 0.0, bytes = 0.0;
+    for (size_t a = 0; a < act.size(); ++a) {
+      const int i = act[a];
+      mgwr_plan* pl = bt->plans[i];
+      K[i] = std::max(1, std::min({K[i], mgwr_plan::kMaxPipeCycles, pl->hp.p.max_cycles - st[i].cycles}));
+      // with a learned cycle count only the last cycle's defect is needed
+      const bool every = !(pl->khint > 0 && st[i].cycles == 0);
+      norms_every[a] = every;
+      build_plan_stages(pl, b[i], u[i], K[i], bt->norms + bt->norm_off[i], lists[a], every);
+      pl->stages_f = nullptr;  // the plan's own uploaded table no longer matches its level-0 pointers
+      maxlen = std::max(maxlen, lists[a].size());
+      flops += pl->cycle_flops * K[i];
+      bytes += pl->cycle_bytes * K[i];
+    }
+    bt->stages.clear();
+    std::vector<std::vector<int>> gidx(act.size());
+    for (size_t a = 0; a < act.size(); ++a) gidx[a].assign(lists[a].size(), -1);
+    for (size_t pos = 0; pos < maxlen; ++pos)
+      for (size_t a = 0; a < act.size(); ++a) {
+        if (pos >= lists[a].size()) continue;
+        Stage<double> x = lists[a][pos];
+        x.prev = x.prev >= 0 ? gidx[a][x.prev] : -1;
+        gidx[a][pos] = (int)bt->stages.size();
+        bt->stages.push_back(x);
+      }
+    assign_offsets(bt->stages);
+    long long ncnt = 0;
+    int ntasks = 0;
+    for (auto& x : bt->stages) { ncnt += x.nleaf; ntasks = x.task0 + x.nchunks; }
+    if ((size_t)bt->stages.size() * sizeof(Stage<double>) > bt->off_counters - bt->off_stages)
+      return batch_fail(MGWR_ERR_STATE, "internal error: batch stage table exceeds its workspace");
+    HIP_TRY(hipMemcpyAsync(bt->stages_dev, bt->stages.data(), bt->stages.size() * sizeof(Stage<double>),
+                           hipMemcpyHostToDevice, bt->stream));
+    HIP_TRY(launch_fill_int(bt->counters, ncnt, 0, bt->stream));
+    HIP_TRY(launch_fill_int(bt->flags_dev, 2, 0, bt->stream));
+    PipeArgs<double> pa;
+    pa.stages = bt->stages_dev;
+    pa.nstages = (int)bt->stages.size();
+    pa.ntasks = ntasks;
+    pa.counters = bt->counters;
+    pa.ticket = bt->flags_dev;
+    pa.abortf = bt->flags_dev + 1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (bt->timing) {
+      HIP_TRY(hipEventCreate(&e0));
+      HIP_TRY(hipEventCreate(&e1));
+      HIP_TRY(hipEventRecord(e0, bt->stream));
+    }
+    HIP_TRY(launch_pipeline<double>(pa, bt->lds, bt->stream));
+    if (bt->timing) HIP_TRY(hipEventRecord(e1, bt->stream));
+    int fl[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(fl, bt->flags_dev, sizeof(fl), hipMemcpyDeviceToHost, bt->stream));
+    std::vector<std::vector<double>> nh(act.size());
+    for (size_t a = 0; a < act.size(); ++a) {
+      const int i = act[a];
+      nh[a].resize((size_t)(norms_every[a] ? K[i] : 1) * bt->plans[i]->norm_chunks);
+      HIP_TRY(hipMemcpyAsync(nh[a].data(), bt->norms + bt->norm_off[i], nh[a].size() * sizeof(double),
+                             hipMemcpyDeviceToHost, bt->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(bt->stream));
+    if (bt->timing) {
+      float ms = 0.0f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      bt->tacc.launches[MGWR_K_PIPE64] += 1;
+      bt->tacc.ms[MGWR_K_PIPE64] += ms;
+      bt->tacc.flops[MGWR_K_PIPE64] += flops;
+      bt->tacc.bytes[MGWR_K_PIPE64] += bytes;
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+    }
+    if (fl[1]) return batch_fail(MGWR_ERR_HIP, "pipelined cycles stalled (a progress wait exceeded its bound)");
+    for (size_t a = 0; a < act.size(); ++a) {
+      const int i = act[a];
+      mgwr_plan* pl = bt->plans[i];
+      mgwr_stats& s = st[i];
+      const double target = tol * s.bnorm;
+      const double first = s.cycles == 0 ? s.res0 : s.res;
+      const int nn = norms_every[a] ? K[i] : 1;
+      for (int c = 0; c < nn; ++c) {
+        double m = 0.0;
+        bool bad = false;
+        for (int j = 0; j < pl->norm_chunks; ++j) {
+          const double v = nh[a][(size_t)c * pl->norm_chunks + j];
+          if (v != v) bad = true;
+          else m = std::max(m, v);
+        }
+        const double r = bad ? std::nan("") : m;
+        const int cyc = norms_every[a] ? s.cycles + c : s.cycles + K[i] - 1;  // 0-based cycle of this norm
+        if (cyc < 64) s.history[cyc] = r;
+        if (conv_at[i] < 0 && r <= target) conv_at[i] = cyc + 1;
+        s.res = r;
+      }
+      s.cycles += K[i];
+      if (!std::isfinite(s.res)) { status[i] = MGWR_ERR_NONFINITE; continue; }
+      if (s.res <= target) { status[i] = MGWR_OK; continue; }
+      const double rate = std::pow(std::max(s.res / first, 1e-300), 1.0 / K[i]);
+      K[i] = (rate < 0.99 && rate > 0) ? (int)std::ceil(std::log(target / s.res) / std::log(rate)) : K[i];
+    }
+  }
+  int ret = MGWR_OK;
+  for (int i = 0; i < n; ++i) {
+    mgwr_stats& s = st[i];
+    if (conv_at[i] > 0) bt->plans[i]->khint = conv_at[i];
+    s.avg_factor = (s.cycles > 0 && s.res0 > 0) ? std::pow(s.res / s.res0, 1.0 / s.cycles) : 0.0;
+    if (stats) stats[i] = s;
+    if (ret == MGWR_OK && status[i] != MGWR_OK) ret = status[i];
+  }
+  if (ret == MGWR_ERR_NOT_CONVERGED) return batch_fail(ret, "an instance reached max_cycles before the tolerance");
+  if (ret == MGWR_ERR_NONFINITE) return batch_fail(ret, "an instance's residual norm is not finite");
+  return MGWR_OK;
+}
 
 extern "C" {
 
@@ -662,6 +833,37 @@ int mgwr_solve(mgwr_plan* pl, const double* f, const double* g, double tol, doub
   if (!f || !u) return fail(MGWR_ERR_INVALID_ARG, "null array");
   if (!(tol > 0.0)) return fail(MGWR_ERR_INVALID_ARG, "tol must be > 0");
   if ((rc = use_device(pl))) return rc;
+  if (!pl->mixed && use_pipeline(pl)) {
+    // the pipelined solve of a batch of one, on the plan's own regions
+    mgwr_batch one;
+    one.plans = {pl};
+    one.bound = true;
+    one.device = pl->device;
+    one.stream = pl->stream;
+    one.off_stages = pl->off.stages;
+    one.off_counters = pl->off.counters;
+    one.norm_off = {0};
+    one.stages_dev = pl->stages_dev;
+    one.counters = pl->counters;
+    one.flags_dev = pl->flags_dev;
+    one.norms = pl->norms;
+    one.lds = march_lds_bytes<double>(base_args<double>(pl, pl->d64, 0));
+    one.timing = pl->timing;
+    const double* fp[1] = {f};
+    const double* gp[1] = {g};
+    double* up[1] = {u};
+    mgwr_stats s1{};
+    int rc2 = solve_pipelined(&one, fp, gp, tol, up, flags, &s1);
+    if (pl->timing)
+      for (int c = 0; c < MGWR_K_CLASSES; ++c) {
+        pl->tacc.launches[c] += one.tacc.launches[c];
+        pl->tacc.ms[c] += one.tacc.ms[c];
+        pl->tacc.flops[c] += one.tacc.flops[c];
+        pl->tacc.bytes[c] += one.tacc.bytes[c];
+      }
+    if (st) *st = s1;
+    return rc2;
+  }
   const HostPlan& hp = pl->hp;
   const int M = hp.p.M;
   const long long MN = (long long)M * hp.levels[0].N;
@@ -689,28 +891,7 @@ int mgwr_solve(mgwr_plan* pl, const double* f, const double* g, double tol, doub
   if (!std::isfinite(s.res0)) status = MGWR_ERR_NONFINITE;
   else if (s.res0 <= target) status = MGWR_OK;
 
-  if (status == MGWR_ERR_NOT_CONVERGED && !pl->mixed && hp.p.schedule == MGWR_SCHED_PIPELINED) {
-    int K = pl->khint > 0 ? pl->khint : 8;
-    int converged_at = -1;
-    while (s.cycles < hp.p.max_cycles) {
-      K = std::max(1, std::min({K, mgwr_plan::kMaxPipeCycles, hp.p.max_cycles - s.cycles}));
-      double res[mgwr_plan::kMaxPipeCycles];
-      if ((rc = run_pipelined(pl, b, u, K, res))) return rc;
-      for (int c = 0; c < K; ++c) {
-        if (s.cycles + c < 64) s.history[s.cycles + c] = res[c];
-        if (converged_at < 0 && res[c] <= target) converged_at = s.cycles + c + 1;
-      }
-      const double first = s.cycles == 0 ? s.res0 : s.res;
-      s.cycles += K;
-      s.res = res[K - 1];
-      if (!std::isfinite(s.res)) { status = MGWR_ERR_NONFINITE; break; }
-      if (s.res <= target) { status = MGWR_OK; break; }
-      // extrapolate the remaining cycles from the observed contraction
-      double rate = std::pow(std::max(s.res / first, 1e-300), 1.0 / K);
-      K = (rate < 0.99 && rate > 0) ? (int)std::ceil(std::log(target / s.res) / std::log(rate)) : K;
-    }
-    if (converged_at > 0) pl->khint = converged_at;
-  } else if (status == MGWR_ERR_NOT_CONVERGED && !pl->mixed) {
+  if (status == MGWR_ERR_NOT_CONVERGED && !pl->mixed) {
     pl->d64.F[0] = const_cast<double*>(b);
     pl->d64.U[0] = u;
     while (s.cycles < hp.p.max_cycles) {
@@ -840,5 +1021,83 @@ int mgwr_plan_destroy(mgwr_plan* pl) {
 }
 
 const char* mgwr_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
+
+extern "C" {
+
+int mgwr_batch_create(int count, mgwr_plan* const* plans, mgwr_batch** out) {
+  if (!out || count < 1 || !plans) return batch_fail(MGWR_ERR_INVALID_ARG, "bad batch arguments");
+  *out = nullptr;
+  mgwr_batch* bt = new (std::nothrow) mgwr_batch();
+  if (!bt) return batch_fail(MGWR_ERR_INVALID_ARG, "out of host memory");
+  Carver cv;
+  long long nst = 0, ncnt = 0, nnorm = 0;
+  for (int i = 0; i < count; ++i) {
+    mgwr_plan* pl = plans[i];
+    if (!pl || !pl->bound) { delete bt; return batch_fail(MGWR_ERR_STATE, "every plan of a batch must be bound"); }
+    if (pl->mixed) { delete bt; return batch_fail(MGWR_ERR_INVALID_ARG, "batched solves are float64 plans"); }
+    if (i > 0 && pl->device != plans[0]->device) { delete bt; return batch_fail(MGWR_ERR_INVALID_ARG, "plans on different devices"); }
+    const long long spc = stages_per_cycle_bound(pl->hp) * mgwr_plan::kMaxPipeCycles;
+    nst += spc;
+    ncnt += spc * (long long)pl->hp.pk.leaves.size();
+    bt->norm_off.push_back((size_t)nnorm);
+    nnorm += (long long)mgwr_plan::kMaxPipeCycles * ((pl->hp.levels[0].N + 15) / 16);
+    bt->plans.push_back(pl);
+    bt->lds = std::max(bt->lds, march_lds_bytes<double>(base_args<double>(pl, pl->d64, 0)));
+  }
+  bt->off_stages = cv.take((size_t)nst * sizeof(Stage<double>));
+  bt->off_counters = cv.take((size_t)ncnt * sizeof(int));
+  bt->off_flags = cv.take(2 * sizeof(int));
+  bt->off_norms = cv.take((size_t)nnorm * sizeof(double));
+  bt->total = cv.off;
+  *out = bt;
+  return MGWR_OK;
+}
+
+int mgwr_batch_workspace_bytes(const mgwr_batch* bt, size_t* bytes) {
+  if (!bt || !bytes) return batch_fail(MGWR_ERR_INVALID_ARG, "null argument");
+  *bytes = bt->total;
+  return MGWR_OK;
+}
+
+int mgwr_batch_bind(mgwr_batch* bt, void* ws, size_t bytes, void* stream) {
+  if (!bt || !ws) return batch_fail(MGWR_ERR_INVALID_ARG, "null argument");
+  if (bytes < bt->total) return batch_fail(MGWR_ERR_STATE, "workspace too small");
+  if (((uintptr_t)ws & 255) != 0) return batch_fail(MGWR_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  HIP_TRY(hipGetDevice(&bt->device));
+  if (bt->device != bt->plans[0]->device) return batch_fail(MGWR_ERR_INVALID_ARG, "batch bound to another device");
+  unsigned char* w = (unsigned char*)ws;
+  bt->stream = (hipStream_t)stream;
+  bt->stages_dev = (Stage<double>*)(w + bt->off_stages);
+  bt->counters = (int*)(w + bt->off_counters);
+  bt->flags_dev = (int*)(w + bt->off_flags);
+  bt->norms = (double*)(w + bt->off_norms);
+  bt->bound = true;
+  return MGWR_OK;
+}
+
+int mgwr_batch_solve(mgwr_batch* bt, const double* const* f, const double* const* g, double tol, double* const* u,
+                     unsigned flags, mgwr_stats* stats) {
+  if (!bt || !bt->bound) return batch_fail(MGWR_ERR_STATE, "batch is not bound");
+  if (!f || !u || !(tol > 0.0)) return batch_fail(MGWR_ERR_INVALID_ARG, "bad arguments");
+  return solve_pipelined(bt, f, g, tol, u, flags, stats);
+}
+
+int mgwr_batch_timing(mgwr_batch* bt, int enable, mgwr_timing* out) {
+  if (!bt) return batch_fail(MGWR_ERR_INVALID_ARG, "null batch");
+  if (bt->bound) HIP_TRY(hipStreamSynchronize(bt->stream));
+  if (out) *out = bt->tacc;
+  if (enable >= 0) {
+    bt->timing = enable != 0;
+    if (enable) bt->tacc = mgwr_timing{};
+  }
+  return MGWR_OK;
+}
+
+int mgwr_batch_destroy(mgwr_batch* bt) {
+  delete bt;
+  return MGWR_OK;
+}
 
 }  // extern "C"

@@ -234,3 +234,47 @@ def test_pipelined_schedule_matches_staged(dev, dim, n, M, alpha, r, k, gamma):
     assert np.max(np.abs(u1 - u2)) <= 1e-12 * np.max(np.abs(u1))
     h1, h2 = np.array(s1["history"]), np.array(s2["history"])
     assert np.all(np.abs(h1 - h2) <= 1e-6 * h1 + 1e-14 * s1["bnorm"]), (h1, h2)
+
+
+def test_batched_uneven_instances_match_oracle(dev):
+    """Instances of different dimension, size, mesh and rank in one merged
+    pipelined launch; each checked against the oracle."""
+    rng = np.random.default_rng(21)
+    cases = [(1, 63, 128, 0.5, 3.0, 8, True), (2, 15, 64, 0.3, 17 / 3, 10, False),
+             (1, 127, 256, 0.7, 1.857142857142857, 6, True), (2, 31, 96, 0.6, 2.0, 8, False)]
+    plans, fs, gs, probs = [], [], [], []
+    for dim, n, M, alpha, r, k, with_g in cases:
+        N = n ** dim
+        t = W.graded_mesh(M, 1.0, r)
+        p = W.Problem(dim=dim, n=n, M=M, alpha=alpha, r=r, k=k, t=t, f=rng.standard_normal((M, N)),
+                      g=rng.standard_normal(N) if with_g else None)
+        probs.append(p)
+        plans.append(mg.Plan(dim, n, M, alpha, k=k, t=t).bind())
+        fs.append(_cuda(p.f, dev))
+        gs.append(None if p.g is None else _cuda(p.g, dev))
+    batch = mg.Batch(plans).bind()
+    for rep in range(2):    # the second solve reuses the learned cycle counts
+        us, sts = batch.solve(fs, gs, tol=1e-11)
+        for p, u, st in zip(probs, us, sts):
+            Rt = oracle.hmatrix_dense(p.t, p.alpha, p.k)
+            ref = oracle.timestep_solve(Rt, oracle.rhs(p.f, p.t, p.alpha, p.g), p.dim, p.n, 1.0)
+            err = np.max(np.abs(u.cpu().numpy() - ref)) / np.max(np.abs(ref))
+            assert err < 1e-10, (p.dim, p.n, p.M, err, st)
+            assert st["res"] <= 1e-11 * st["bnorm"]
+
+
+def test_repeated_solves_keep_cycle_count(dev):
+    """After the first solve the cycle count is known and a pipelined launch
+    evaluates the defect only after its last cycle: the second solve must run
+    the same number of cycles and reach the same residual."""
+    p = W.manufactured(1, 255, 1024, 0.5, r=3.0, k=10)
+    plan = _plan(p, dev, schedule="pipelined")
+    f = _cuda(p.f, dev)
+    u1, s1 = plan.solve(f, tol=1e-8)
+    u2, s2 = plan.solve(f, tol=1e-8)
+    assert s1["cycles"] == s2["cycles"]
+    assert s2["res"] <= 1e-8 * s2["bnorm"]
+    assert torch.equal(u1, u2)
+    batch = mg.Batch([plan]).bind()
+    (u3,), (s3,) = batch.solve([f], tol=1e-8)
+    assert s3["cycles"] == s1["cycles"] and torch.equal(u1, u3)
