@@ -35,10 +35,14 @@ struct MarchArgs {
   T inv_h2;
 };
 
-// One stage of the time-pipelined cycle kernel.  Stage kinds:
-enum { STG_SMOOTH = 0, STG_RESID = 1, STG_RESTRICT = 2, STG_PROLONG = 3 };
+// One stage of the time-pipelined kernel.  Stage kinds:
+enum {
+  STG_SMOOTH = 0, STG_RESID = 1, STG_RESTRICT = 2, STG_PROLONG = 3,          // float64
+  STG_SMOOTH32 = 4, STG_RESID32 = 5, STG_RESTRICT32 = 6, STG_PROLONG32 = 7,  // float32 (inner cycles)
+  STG_CAST = 8,     // float32 right-hand side := float64 defect, float32 iterate := 0 (leaf rows)
+  STG_CORRECT = 9   // float64 iterate += float32 correction (leaf rows)
+};
 
-template <typename T>
 struct Stage {
   int kind;
   int prev;          // producer stage (index into the stage array) or -1
@@ -47,19 +51,22 @@ struct Stage {
   int cnt_off;       // this stage's per-leaf counters start at counters + cnt_off
   int nleaf;
   const LeafDesc* leaves;
-  MarchArgs<T> m;    // STG_SMOOTH / STG_RESID
-  double* norm_out;  // STG_RESID: per-work-item max |r| (or null)
-  // STG_RESTRICT: src = fine defect, dst = coarse right-hand side, zero = coarse iterate
-  // STG_PROLONG:  src = coarse correction, dst = fine iterate (updated)
-  const T* src;
-  T* dst;
-  T* zero;
+  MarchArgs<double> m;   // STG_SMOOTH / STG_RESID
+  MarchArgs<float> mf;   // STG_SMOOTH32 / STG_RESID32
+  double* norm_out;      // STG_RESID: per-work-item max |r| (or null)
+  // STG_RESTRICT*: src = fine defect, dst = coarse right-hand side, zero = coarse iterate
+  // STG_PROLONG*:  src = coarse correction, dst = fine iterate (updated)
+  // STG_CAST: src = float64 defect, dst = float32 right-hand side, zero = float32 iterate
+  // STG_CORRECT: src = float32 correction, dst = float64 iterate (updated)
+  const void* src;
+  void* dst;
+  void* zero;
   int dim, nf, nc;
+  long long npoints;     // STG_CAST / STG_CORRECT: points per time row
 };
 
-template <typename T>
 struct PipeArgs {
-  const Stage<T>* stages;
+  const Stage* stages;
   int nstages;
   int ntasks;
   int* counters;
@@ -70,8 +77,8 @@ struct PipeArgs {
 constexpr int kStencilCols = 64;   // columns per work item of a stencil stage (leaf rows <= 16 = 4 x 4)
 
 template <typename T> size_t march_lds_bytes(const MarchArgs<T>& a);
-template <typename T> hipError_t launch_pipeline(const PipeArgs<T>& pa, size_t lds, hipStream_t s);
-template <typename T> hipError_t set_pipeline_lds_limit(size_t bytes);
+hipError_t launch_pipeline(const PipeArgs& pa, size_t lds, hipStream_t s);
+hipError_t set_pipeline_lds_limit(size_t bytes);
 hipError_t launch_fill_int(int* x, long long count, int v, hipStream_t s);
 template <typename T> hipError_t launch_march(int mode, const MarchArgs<T>& a, hipStream_t s);
 template <typename T> hipError_t set_march_lds_limit(size_t bytes);

@@ -482,7 +482,10 @@ constexpr int kStencilRowsPerPass = 256 / kStencilCols;
 // Full-weighting restriction of the rows of one leaf, and the zero start of
 // the coarse iterate on those rows.
 template <typename T>
-__device__ void restrict_stage(const Stage<T>& st, int chunk, const PipeCtx& pc, int* sh_abort) {
+__device__ void restrict_stage(const Stage& st, int chunk, const PipeCtx& pc, int* sh_abort) {
+  const T* src = static_cast<const T*>(st.src);
+  T* dst = static_cast<T*>(st.dst);
+  T* zero = static_cast<T*>(st.zero);
   const int nf = st.nf, nc = st.nc;
   const long long Nc = st.dim == 1 ? nc : (long long)nc * nc;
   const long long Nf = st.dim == 1 ? nf : (long long)nf * nf;
@@ -525,7 +528,7 @@ __device__ void restrict_stage(const Stage<T>& st, int chunk, const PipeCtx& pc,
         const int row = r0 + j * kStencilRowsPerPass;
         v[j] = (T)0;
         if (row < d.sz) {
-          const T* r = st.src + (long long)(d.lo + row) * Nf;
+          const T* r = src + (long long)(d.lo + row) * Nf;
           for (int t = 0; t < nw; ++t) v[j] += wgt[t] * gld<true>(r + off[t]);
         }
       }
@@ -534,8 +537,8 @@ __device__ void restrict_stage(const Stage<T>& st, int chunk, const PipeCtx& pc,
         const int row = r0 + j * kStencilRowsPerPass;
         if (row < d.sz) {
           const long long m = d.lo + row;
-          gst<true>(st.dst + m * Nc + Q, v[j]);
-          gst<true>(st.zero + m * Nc + Q, (T)0);
+          gst<true>(dst + m * Nc + Q, v[j]);
+          gst<true>(zero + m * Nc + Q, (T)0);
         }
       }
     }
@@ -548,7 +551,9 @@ __device__ void restrict_stage(const Stage<T>& st, int chunk, const PipeCtx& pc,
 // Linear / bilinear interpolation of the coarse correction, added to the
 // fine iterate on the rows of one leaf.
 template <typename T>
-__device__ void prolong_stage(const Stage<T>& st, int chunk, const PipeCtx& pc, int* sh_abort) {
+__device__ void prolong_stage(const Stage& st, int chunk, const PipeCtx& pc, int* sh_abort) {
+  const T* src = static_cast<const T*>(st.src);
+  T* dst = static_cast<T*>(st.dst);
   const int nf = st.nf, nc = st.nc;
   const long long Nc = st.dim == 1 ? nc : (long long)nc * nc;
   const long long Nf = st.dim == 1 ? nf : (long long)nf * nf;
@@ -602,15 +607,15 @@ __device__ void prolong_stage(const Stage<T>& st, int chunk, const PipeCtx& pc, 
         u0[j] = (T)0;
         if (row < d.sz) {
           const long long m = d.lo + row;
-          const T* e = st.src + m * Nc;
+          const T* e = src + m * Nc;
           for (int t = 0; t < ncoef; ++t) v[j] += cw[t] * gld<true>(e + cidx[t]);
-          u0[j] = gld<true>(st.dst + m * Nf + q);
+          u0[j] = gld<true>(dst + m * Nf + q);
         }
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int row = r0 + j * kStencilRowsPerPass;
-        if (row < d.sz) gst<true>(st.dst + (long long)(d.lo + row) * Nf + q, u0[j] + v[j]);
+        if (row < d.sz) gst<true>(dst + (long long)(d.lo + row) * Nf + q, u0[j] + v[j]);
       }
     }
     __builtin_amdgcn_s_waitcnt(0);
@@ -619,8 +624,67 @@ __device__ void prolong_stage(const Stage<T>& st, int chunk, const PipeCtx& pc, 
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void pipeline_kernel(PipeArgs<T> pa) {
+// Precision hand-over of mixed-precision refinement on the rows of one leaf:
+// STG_CAST: float32 right-hand side = float64 defect, float32 iterate = 0;
+// STG_CORRECT: float64 iterate += float32 correction.
+__device__ void pointwise_stage(const Stage& st, int chunk, const PipeCtx& pc, int* sh_abort) {
+  const long long N = st.npoints;
+  const long long q = (long long)chunk * kStencilCols + (threadIdx.x % kStencilCols);
+  const int r0 = threadIdx.x / kStencilCols;
+  const bool ok = q < N;
+  const int lane = threadIdx.x & 63;
+  for (int i = 0; i < st.nleaf; ++i) {
+    const LeafDesc d = st.leaves[i];
+    if (threadIdx.x < 64) {
+      if (!wait_leaf(pc, i)) *sh_abort = 1;
+    }
+    __syncthreads();
+    if (*sh_abort) return;
+    if (ok) {
+      if (st.kind == STG_CAST) {
+        const double* src = static_cast<const double*>(st.src);
+        float* dst = static_cast<float*>(st.dst);
+        float* zero = static_cast<float*>(st.zero);
+        double v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int row = r0 + j * kStencilRowsPerPass;
+          v[j] = row < d.sz ? gld<true>(src + (long long)(d.lo + row) * N + q) : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int row = r0 + j * kStencilRowsPerPass;
+          if (row < d.sz) {
+            gst<true>(dst + (long long)(d.lo + row) * N + q, (float)v[j]);
+            gst<true>(zero + (long long)(d.lo + row) * N + q, 0.0f);
+          }
+        }
+      } else {
+        const float* src = static_cast<const float*>(st.src);
+        double* dst = static_cast<double*>(st.dst);
+        double v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int row = r0 + j * kStencilRowsPerPass;
+          v[j] = 0.0;
+          if (row < d.sz)
+            v[j] = gld<true>(dst + (long long)(d.lo + row) * N + q) +
+                   (double)gld<true>(src + (long long)(d.lo + row) * N + q);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int row = r0 + j * kStencilRowsPerPass;
+          if (row < d.sz) gst<true>(dst + (long long)(d.lo + row) * N + q, v[j]);
+        }
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x < 64) signal_leaf(pc, i, lane);
+  }
+}
+
+__global__ __launch_bounds__(256) void pipeline_kernel(PipeArgs pa) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int sh_task;
   __shared__ int sh_abort;
@@ -634,7 +698,7 @@ __global__ __launch_bounds__(256) void pipeline_kernel(PipeArgs<T> pa) {
     if (pa.stages[mid].task0 <= task) lo = mid;
     else hi = mid - 1;
   }
-  const Stage<T>& st = pa.stages[lo];
+  const Stage& st = pa.stages[lo];
   PipeCtx pc;
   pc.wait = st.prev >= 0 ? pa.counters + pa.stages[st.prev].cnt_off : nullptr;
   pc.need = st.prev >= 0 ? pa.stages[st.prev].nchunks : 0;
@@ -642,26 +706,31 @@ __global__ __launch_bounds__(256) void pipeline_kernel(PipeArgs<T> pa) {
   pc.abortf = pa.abortf;
   pc.norm_out = st.norm_out;
   const int chunk = task - st.task0;
-  switch (st.kind) {
-    case STG_SMOOTH: march_body<T, MODE_SMOOTH, true>(st.m, chunk, pc, smem_raw, &sh_abort); break;
-    case STG_RESID: march_body<T, MODE_RESID, true>(st.m, chunk, pc, smem_raw, &sh_abort); break;
-    case STG_RESTRICT: if (threadIdx.x == 0) sh_abort = 0; __syncthreads(); restrict_stage<T>(st, chunk, pc, &sh_abort); break;
-    case STG_PROLONG: if (threadIdx.x == 0) sh_abort = 0; __syncthreads(); prolong_stage<T>(st, chunk, pc, &sh_abort); break;
+  const int kind = st.kind;
+  if (kind == STG_SMOOTH) { march_body<double, MODE_SMOOTH, true>(st.m, chunk, pc, smem_raw, &sh_abort); return; }
+  if (kind == STG_RESID) { march_body<double, MODE_RESID, true>(st.m, chunk, pc, smem_raw, &sh_abort); return; }
+  if (kind == STG_SMOOTH32) { march_body<float, MODE_SMOOTH, true>(st.mf, chunk, pc, smem_raw, &sh_abort); return; }
+  if (kind == STG_RESID32) { march_body<float, MODE_RESID, true>(st.mf, chunk, pc, smem_raw, &sh_abort); return; }
+  if (threadIdx.x == 0) sh_abort = 0;
+  __syncthreads();
+  switch (kind) {
+    case STG_RESTRICT: restrict_stage<double>(st, chunk, pc, &sh_abort); break;
+    case STG_PROLONG: prolong_stage<double>(st, chunk, pc, &sh_abort); break;
+    case STG_RESTRICT32: restrict_stage<float>(st, chunk, pc, &sh_abort); break;
+    case STG_PROLONG32: prolong_stage<float>(st, chunk, pc, &sh_abort); break;
+    case STG_CAST:
+    case STG_CORRECT: pointwise_stage(st, chunk, pc, &sh_abort); break;
     default: break;
   }
 }
 
-template <typename T>
-hipError_t launch_pipeline(const PipeArgs<T>& pa, size_t lds, hipStream_t s) {
+hipError_t launch_pipeline(const PipeArgs& pa, size_t lds, hipStream_t s) {
   if (pa.ntasks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(pipeline_kernel<T>, dim3(pa.ntasks), dim3(256), lds, s, pa);
+  hipLaunchKernelGGL(pipeline_kernel, dim3(pa.ntasks), dim3(256), lds, s, pa);
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t set_pipeline_lds_limit(size_t bytes) {
-  return set_dyn_lds((const void*)pipeline_kernel<T>, bytes);
-}
+hipError_t set_pipeline_lds_limit(size_t bytes) { return set_dyn_lds((const void*)pipeline_kernel, bytes); }
 
 __global__ void fill_int_kernel(int* __restrict__ x, long long count, int v) {
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < count;
@@ -930,10 +999,7 @@ hipError_t launch_fill_int(int* x, long long count, int v, hipStream_t s) {
 }
 
 // explicit instantiations
-template hipError_t launch_pipeline<double>(const PipeArgs<double>&, size_t, hipStream_t);
-template hipError_t launch_pipeline<float>(const PipeArgs<float>&, size_t, hipStream_t);
-template hipError_t set_pipeline_lds_limit<double>(size_t);
-template hipError_t set_pipeline_lds_limit<float>(size_t);
+
 template size_t march_lds_bytes<double>(const MarchArgs<double>&);
 template size_t march_lds_bytes<float>(const MarchArgs<float>&);
 template hipError_t launch_march<double>(int, const MarchArgs<double>&, hipStream_t);

@@ -81,11 +81,11 @@ struct mgwr_plan {
   mgwr_timing tacc{};
   // time-pipelined cycles (float64)
   static constexpr int kMaxPipeCycles = 16;
-  std::vector<Stage<double>> stages;   // host image for kMaxPipeCycles cycles
+  std::vector<Stage> stages;   // host image for kMaxPipeCycles cycles
   int stages_per_cycle = 0, tasks_per_cycle = 0, norm_chunks = 0;
   const double* stages_f = nullptr;    // level-0 arrays the uploaded image refers to
   const double* stages_u = nullptr;
-  Stage<double>* stages_dev = nullptr;
+  Stage* stages_dev = nullptr;
   int* counters = nullptr;
   int* flags_dev = nullptr;            // [0] ticket, [1] abort
   double* norms = nullptr;             // [kMaxPipeCycles][norm_chunks]
@@ -160,7 +160,7 @@ void layout(mgwr_plan* pl) {
     // stages per cycle: per non-coarsest level 2(nu1+nu2) half-sweeps + defect +
     // restriction + prolongation, times gamma^depth visits; coarsest 2; plus the norm defect
     const long long S = stages_per_cycle_bound(hp) * mgwr_plan::kMaxPipeCycles;
-    o.stages = cv.take((size_t)S * sizeof(Stage<double>));
+    o.stages = cv.take((size_t)S * sizeof(Stage));
     o.counters = cv.take((size_t)S * nleaf * sizeof(int));
     o.flags = cv.take(2 * sizeof(int));
     o.norms = cv.take((size_t)mgwr_plan::kMaxPipeCycles * ((hp.levels[0].N + 15) / 16) * sizeof(double));
@@ -310,20 +310,22 @@ int cycle(mgwr_plan* pl, DevOps<T>& ops, int l) {
 // Stage list of one cycle of Algorithm 2 on level l (float64), appended to
 // `out`; `prev` is the index of the stage whose output the first new stage
 // consumes.  Returns the index of the last stage appended.
-int append_cycle_stages(mgwr_plan* pl, int l, int prev, std::vector<Stage<double>>& out) {
+int append_cycle_stages(mgwr_plan* pl, int l, int prev, std::vector<Stage>& out, bool f32 = false) {
   const HostPlan& hp = pl->hp;
   const int L = (int)hp.levels.size();
   const Level& lv = hp.levels[l];
   DevOps<double>& ops = pl->d64;
+  DevOps<float>& o32 = pl->d32;
+  const int kofs = f32 ? STG_SMOOTH32 : 0;  // float32 kinds follow the float64 ones
   auto base = [&](int kind) {
-    Stage<double> st{};
+    Stage st{};
     st.kind = kind;
     st.prev = prev;
     st.nleaf = (int)hp.pk.leaves.size();
     st.leaves = pl->leaves;
     return st;
   };
-  auto push = [&](Stage<double>& st) {
+  auto push = [&](Stage& st) {
     out.push_back(st);
     prev = (int)out.size() - 1;
   };
@@ -332,11 +334,18 @@ int append_cycle_stages(mgwr_plan* pl, int l, int prev, std::vector<Stage<double
     int par = colour == 0 ? par0 : 1 - par0;
     int ncols = (lv.N - par + 1) / 2;
     if (ncols <= 0) return;
-    Stage<double> st = base(STG_SMOOTH);
-    st.m = base_args<double>(pl, ops, l);
-    st.m.F = ops.F[l]; st.m.U = ops.U[l]; st.m.Out = nullptr;
-    st.m.ld = lv.N; st.m.ncols = ncols; st.m.cstride = 2; st.m.coff = par;
-    st.m.dim = hp.p.dim; st.m.n = lv.n; st.m.inv_h2 = 1.0 / (lv.h * lv.h);
+    Stage st = base(STG_SMOOTH + kofs);
+    if (!f32) {
+      st.m = base_args<double>(pl, ops, l);
+      st.m.F = ops.F[l]; st.m.U = ops.U[l]; st.m.Out = nullptr;
+      st.m.ld = lv.N; st.m.ncols = ncols; st.m.cstride = 2; st.m.coff = par;
+      st.m.dim = hp.p.dim; st.m.n = lv.n; st.m.inv_h2 = 1.0 / (lv.h * lv.h);
+    } else {
+      st.mf = base_args<float>(pl, o32, l);
+      st.mf.F = o32.F[l]; st.mf.U = o32.U[l]; st.mf.Out = nullptr;
+      st.mf.ld = lv.N; st.mf.ncols = ncols; st.mf.cstride = 2; st.mf.coff = par;
+      st.mf.dim = hp.p.dim; st.mf.n = lv.n; st.mf.inv_h2 = (float)(1.0 / (lv.h * lv.h));
+    }
     st.nchunks = (ncols + 15) / 16;
     push(st);
   };
@@ -347,27 +356,36 @@ int append_cycle_stages(mgwr_plan* pl, int l, int prev, std::vector<Stage<double
   }
   for (int s2 = 0; s2 < hp.p.nu1; ++s2) { smooth_stage(0); smooth_stage(1); }
   {
-    Stage<double> st = base(STG_RESID);
-    st.m = base_args<double>(pl, ops, l);
-    st.m.F = ops.F[l]; st.m.U = ops.U[l]; st.m.Out = ops.R[l];
-    st.m.ld = lv.N; st.m.ncols = lv.N; st.m.cstride = 1; st.m.coff = 0;
-    st.m.dim = hp.p.dim; st.m.n = lv.n; st.m.inv_h2 = 1.0 / (lv.h * lv.h);
+    Stage st = base(STG_RESID + kofs);
+    if (!f32) {
+      st.m = base_args<double>(pl, ops, l);
+      st.m.F = ops.F[l]; st.m.U = ops.U[l]; st.m.Out = ops.R[l];
+      st.m.ld = lv.N; st.m.ncols = lv.N; st.m.cstride = 1; st.m.coff = 0;
+      st.m.dim = hp.p.dim; st.m.n = lv.n; st.m.inv_h2 = 1.0 / (lv.h * lv.h);
+    } else {
+      st.mf = base_args<float>(pl, o32, l);
+      st.mf.F = o32.F[l]; st.mf.U = o32.U[l]; st.mf.Out = o32.R[l];
+      st.mf.ld = lv.N; st.mf.ncols = lv.N; st.mf.cstride = 1; st.mf.coff = 0;
+      st.mf.dim = hp.p.dim; st.mf.n = lv.n; st.mf.inv_h2 = (float)(1.0 / (lv.h * lv.h));
+    }
     st.nchunks = (lv.N + 15) / 16;
     push(st);
   }
   const Level& lc = hp.levels[l + 1];
   {
-    Stage<double> st = base(STG_RESTRICT);
-    st.src = ops.R[l]; st.dst = ops.F[l + 1]; st.zero = ops.U[l + 1];
+    Stage st = base(STG_RESTRICT + kofs);
+    if (!f32) { st.src = ops.R[l]; st.dst = ops.F[l + 1]; st.zero = ops.U[l + 1]; }
+    else { st.src = o32.R[l]; st.dst = o32.F[l + 1]; st.zero = o32.U[l + 1]; }
     st.dim = hp.p.dim; st.nf = lv.n; st.nc = lc.n;
     st.nchunks = (lc.N + kStencilCols - 1) / kStencilCols;
     push(st);
   }
-  for (int gm = 0; gm < hp.p.gamma; ++gm) prev = append_cycle_stages(pl, l + 1, prev, out);
+  for (int gm = 0; gm < hp.p.gamma; ++gm) prev = append_cycle_stages(pl, l + 1, prev, out, f32);
   {
-    Stage<double> st = base(STG_PROLONG);
+    Stage st = base(STG_PROLONG + kofs);
     st.prev = prev;
-    st.src = ops.U[l + 1]; st.dst = ops.U[l];
+    if (!f32) { st.src = ops.U[l + 1]; st.dst = ops.U[l]; }
+    else { st.src = o32.U[l + 1]; st.dst = o32.U[l]; }
     st.dim = hp.p.dim; st.nf = lv.n; st.nc = lc.n;
     st.nchunks = (lv.N + kStencilCols - 1) / kStencilCols;
     push(st);
@@ -381,19 +399,51 @@ int append_cycle_stages(mgwr_plan* pl, int l, int prev, std::vector<Stage<double
 // when `every` is set, else only the last one.  Stage indices (prev) are
 // relative to the first stage appended.
 void build_plan_stages(mgwr_plan* pl, const double* b, double* u, int K, double* norms,
-                       std::vector<Stage<double>>& out, bool every = true) {
+                       std::vector<Stage>& out, bool every = true, bool first_src_is_b = true) {
   const HostPlan& hp = pl->hp;
   const int nleaf = (int)hp.pk.leaves.size();
   pl->d64.F[0] = const_cast<double*>(b);
   pl->d64.U[0] = u;
-  std::vector<Stage<double>> st;
+  std::vector<Stage> st;
   int prev = -1;
   int per_cycle = -1;
+  const long long N0 = hp.levels[0].N;
   for (int c = 0; c < K; ++c) {
-    prev = append_cycle_stages(pl, 0, prev, st);
+    if (!pl->mixed) {
+      prev = append_cycle_stages(pl, 0, prev, st);
+    } else {
+      // one refinement step: float32 right-hand side from the float64 defect
+      // (b itself before the first correction of a zero iterate), inner
+      // float32 cycles on A e = r from e = 0, u += e, float64 defect
+      Stage cs{};
+      cs.kind = STG_CAST;
+      cs.prev = prev;
+      cs.nleaf = nleaf;
+      cs.leaves = pl->leaves;
+      cs.src = (c == 0 && first_src_is_b) ? (const void*)b : (const void*)pl->d64.R[0];
+      cs.dst = pl->d32.F[0];
+      cs.zero = pl->d32.U[0];
+      cs.npoints = N0;
+      cs.nchunks = (int)((N0 + kStencilCols - 1) / kStencilCols);
+      st.push_back(cs);
+      prev = (int)st.size() - 1;
+      for (int ic = 0; ic < hp.p.inner_cycles; ++ic) prev = append_cycle_stages(pl, 0, prev, st, true);
+      Stage co{};
+      co.kind = STG_CORRECT;
+      co.prev = prev;
+      co.nleaf = nleaf;
+      co.leaves = pl->leaves;
+      co.src = pl->d32.U[0];
+      co.dst = u;
+      co.npoints = N0;
+      co.nchunks = cs.nchunks;
+      st.push_back(co);
+      prev = (int)st.size() - 1;
+      every = true;  // the next step's right-hand side is this defect
+    }
     if (per_cycle < 0) per_cycle = (int)st.size() + 1;
     if (!every && c + 1 < K) continue;
-    Stage<double> nd{};
+    Stage nd{};
     nd.kind = STG_RESID;
     nd.prev = prev;
     nd.nleaf = nleaf;
@@ -412,21 +462,27 @@ void build_plan_stages(mgwr_plan* pl, const double* b, double* u, int K, double*
   pl->norm_chunks = (hp.levels[0].N + 15) / 16;
   pl->cycle_flops = pl->cycle_bytes = 0.0;
   for (int i = 0; i < per_cycle; ++i) {
-    const Stage<double>& x = st[i];
+    const Stage& x = st[i];
     if (x.kind == STG_SMOOTH || x.kind == STG_RESID) {
       pl->cycle_flops += 2.0 * hp.stored * x.m.ncols;
       pl->cycle_bytes += 3.0 * hp.p.M * x.m.ncols * sizeof(double);
+    } else if (x.kind == STG_SMOOTH32 || x.kind == STG_RESID32) {
+      pl->cycle_flops += 2.0 * hp.stored * x.mf.ncols;
+      pl->cycle_bytes += 3.0 * hp.p.M * x.mf.ncols * sizeof(float);
+    } else if (x.kind == STG_CAST || x.kind == STG_CORRECT) {
+      pl->cycle_bytes += (x.kind == STG_CAST ? 16.0 : 20.0) * hp.p.M * x.npoints;
     } else {
       const double Nf = hp.p.dim == 1 ? x.nf : (double)x.nf * x.nf;
       const double Nc = hp.p.dim == 1 ? x.nc : (double)x.nc * x.nc;
-      pl->cycle_bytes += (x.kind == STG_RESTRICT ? (Nf + 2 * Nc) : (Nc + 2 * Nf)) * hp.p.M * sizeof(double);
+      const double w = (x.kind == STG_RESTRICT || x.kind == STG_PROLONG) ? 8.0 : 4.0;
+      pl->cycle_bytes += ((x.kind == STG_RESTRICT || x.kind == STG_RESTRICT32) ? (Nf + 2 * Nc) : (Nc + 2 * Nf)) * hp.p.M * w;
     }
   }
   out.insert(out.end(), st.begin(), st.end());
 }
 
 // Task offsets (stage order) and counter offsets.
-void assign_offsets(std::vector<Stage<double>>& st) {
+void assign_offsets(std::vector<Stage>& st) {
   int task = 0;
   long long cnt = 0;
   for (auto& x : st) {
@@ -488,11 +544,11 @@ struct mgwr_batch {
   hipStream_t stream = nullptr;
   size_t off_stages = 0, off_counters = 0, off_flags = 0, off_norms = 0, total = 0;
   std::vector<size_t> norm_off;  // per plan, in doubles
-  Stage<double>* stages_dev = nullptr;
+  Stage* stages_dev = nullptr;
   int* counters = nullptr;
   int* flags_dev = nullptr;
   double* norms = nullptr;
-  std::vector<Stage<double>> stages;
+  std::vector<Stage> stages;
   size_t lds = 0;
   bool timing = false;
   mgwr_timing tacc{};
@@ -553,21 +609,26 @@ int solve_pipelined(mgwr_batch* bt, const double* const* f, const double* const*
   while (true) {
     std::vector<int> act;
     for (int i = 0; i < n; ++i)
-      if (status[i] == MGWR_ERR_NOT_CONVERGED && st[i].cycles < bt->plans[i]->hp.p.max_cycles) act.push_back(i);
+      if (status[i] == MGWR_ERR_NOT_CONVERGED &&
+          st[i].cycles + (bt->plans[i]->mixed ? bt->plans[i]->hp.p.inner_cycles : 1) <= bt->plans[i]->hp.p.max_cycles)
+        act.push_back(i);
     if (act.empty()) break;
     // per-instance stage lists, then interleaved by position
-    std::vector<std::vector<Stage<double>>> lists(act.size());
+    std::vector<std::vector<Stage>> lists(act.size());
     std::vector<char> norms_every(act.size(), 1);
     size_t maxlen = 0;
     double flops = 0.0, bytes = 0.0;
     for (size_t a = 0; a < act.size(); ++a) {
       const int i = act[a];
       mgwr_plan* pl = bt->plans[i];
-      K[i] = std::max(1, std::min({K[i], mgwr_plan::kMaxPipeCycles, pl->hp.p.max_cycles - st[i].cycles}));
-      // with a learned cycle count only the last cycle's defect is needed
-      const bool every = !(pl->khint > 0 && st[i].cycles == 0);
+      const int per = pl->mixed ? pl->hp.p.inner_cycles : 1;  // cycles per outer step
+      K[i] = std::max(1, std::min({K[i], mgwr_plan::kMaxPipeCycles, (pl->hp.p.max_cycles - st[i].cycles) / per}));
+      // with a learned step count only the last step's defect is needed (float64
+      // cycles); refinement steps need every defect as the next right-hand side
+      const bool every = pl->mixed || !(pl->khint > 0 && st[i].cycles == 0);
       norms_every[a] = every;
-      build_plan_stages(pl, b[i], u[i], K[i], bt->norms + bt->norm_off[i], lists[a], every);
+      build_plan_stages(pl, b[i], u[i], K[i], bt->norms + bt->norm_off[i], lists[a], every,
+                        st[i].cycles == 0 && !(flags & MGWR_GUESS_IN_U));
       pl->stages_f = nullptr;  // the plan's own uploaded table no longer matches its level-0 pointers
       maxlen = std::max(maxlen, lists[a].size());
       flops += pl->cycle_flops * K[i];
@@ -579,7 +640,7 @@ int solve_pipelined(mgwr_batch* bt, const double* const* f, const double* const*
     for (size_t pos = 0; pos < maxlen; ++pos)
       for (size_t a = 0; a < act.size(); ++a) {
         if (pos >= lists[a].size()) continue;
-        Stage<double> x = lists[a][pos];
+        Stage x = lists[a][pos];
         x.prev = x.prev >= 0 ? gidx[a][x.prev] : -1;
         gidx[a][pos] = (int)bt->stages.size();
         bt->stages.push_back(x);
@@ -588,13 +649,13 @@ int solve_pipelined(mgwr_batch* bt, const double* const* f, const double* const*
     long long ncnt = 0;
     int ntasks = 0;
     for (auto& x : bt->stages) { ncnt += x.nleaf; ntasks = x.task0 + x.nchunks; }
-    if ((size_t)bt->stages.size() * sizeof(Stage<double>) > bt->off_counters - bt->off_stages)
+    if ((size_t)bt->stages.size() * sizeof(Stage) > bt->off_counters - bt->off_stages)
       return batch_fail(MGWR_ERR_STATE, "internal error: batch stage table exceeds its workspace");
-    HIP_TRY(hipMemcpyAsync(bt->stages_dev, bt->stages.data(), bt->stages.size() * sizeof(Stage<double>),
+    HIP_TRY(hipMemcpyAsync(bt->stages_dev, bt->stages.data(), bt->stages.size() * sizeof(Stage),
                            hipMemcpyHostToDevice, bt->stream));
     HIP_TRY(launch_fill_int(bt->counters, ncnt, 0, bt->stream));
     HIP_TRY(launch_fill_int(bt->flags_dev, 2, 0, bt->stream));
-    PipeArgs<double> pa;
+    PipeArgs pa;
     pa.stages = bt->stages_dev;
     pa.nstages = (int)bt->stages.size();
     pa.ntasks = ntasks;
@@ -607,7 +668,7 @@ int solve_pipelined(mgwr_batch* bt, const double* const* f, const double* const*
       HIP_TRY(hipEventCreate(&e1));
       HIP_TRY(hipEventRecord(e0, bt->stream));
     }
-    HIP_TRY(launch_pipeline<double>(pa, bt->lds, bt->stream));
+    HIP_TRY(launch_pipeline(pa, bt->lds, bt->stream));
     if (bt->timing) HIP_TRY(hipEventRecord(e1, bt->stream));
     int fl[2] = {0, 0};
     HIP_TRY(hipMemcpyAsync(fl, bt->flags_dev, sizeof(fl), hipMemcpyDeviceToHost, bt->stream));
@@ -646,12 +707,18 @@ int solve_pipelined(mgwr_batch* bt, const double* const* f, const double* const*
           else m = std::max(m, v);
         }
         const double r = bad ? std::nan("") : m;
-        const int cyc = norms_every[a] ? s.cycles + c : s.cycles + K[i] - 1;  // 0-based cycle of this norm
+        const int done_steps = pl->mixed ? s.refinements : s.cycles;
+        const int cyc = norms_every[a] ? done_steps + c : done_steps + K[i] - 1;  // 0-based step of this norm
         if (cyc < 64) s.history[cyc] = r;
         if (conv_at[i] < 0 && r <= target) conv_at[i] = cyc + 1;
         s.res = r;
       }
-      s.cycles += K[i];
+      if (pl->mixed) {
+        s.refinements += K[i];
+        s.cycles += K[i] * pl->hp.p.inner_cycles;
+      } else {
+        s.cycles += K[i];
+      }
       if (!std::isfinite(s.res)) { status[i] = MGWR_ERR_NONFINITE; continue; }
       if (s.res <= target) { status[i] = MGWR_OK; continue; }
       const double rate = std::pow(std::max(s.res / first, 1e-300), 1.0 / K[i]);
@@ -739,7 +806,7 @@ int mgwr_plan_bind(mgwr_plan* pl, void* ws, size_t bytes, void* stream) {
   pl->part = (double*)(w + o.part);
   pl->scal = (double*)(w + o.scal);
   pl->B0 = (double*)(w + o.B0);
-  pl->stages_dev = (Stage<double>*)(w + o.stages);
+  pl->stages_dev = (Stage*)(w + o.stages);
   pl->counters = (int*)(w + o.counters);
   pl->flags_dev = (int*)(w + o.flags);
   pl->norms = (double*)(w + o.norms);
@@ -801,8 +868,7 @@ int mgwr_plan_bind(mgwr_plan* pl, void* ws, size_t bytes, void* stream) {
   // earlier plan's need; each launch still requests exactly its own size.
   HIP_TRY(set_march_lds_limit<double>(cap));
   HIP_TRY(set_march_lds_limit<float>(cap));
-  HIP_TRY(set_pipeline_lds_limit<double>(cap));
-  HIP_TRY(set_pipeline_lds_limit<float>(cap));
+  HIP_TRY(set_pipeline_lds_limit(cap));
   HIP_TRY(hipStreamSynchronize(pl->stream));
   pl->bound = true;
   return MGWR_OK;
@@ -833,7 +899,7 @@ int mgwr_solve(mgwr_plan* pl, const double* f, const double* g, double tol, doub
   if (!f || !u) return fail(MGWR_ERR_INVALID_ARG, "null array");
   if (!(tol > 0.0)) return fail(MGWR_ERR_INVALID_ARG, "tol must be > 0");
   if ((rc = use_device(pl))) return rc;
-  if (!pl->mixed && use_pipeline(pl)) {
+  if (use_pipeline(pl)) {
     // the pipelined solve of a batch of one, on the plan's own regions
     mgwr_batch one;
     one.plans = {pl};
@@ -848,6 +914,7 @@ int mgwr_solve(mgwr_plan* pl, const double* f, const double* g, double tol, doub
     one.flags_dev = pl->flags_dev;
     one.norms = pl->norms;
     one.lds = march_lds_bytes<double>(base_args<double>(pl, pl->d64, 0));
+    if (pl->mixed) one.lds = std::max(one.lds, march_lds_bytes<float>(base_args<float>(pl, pl->d32, 0)));
     one.timing = pl->timing;
     const double* fp[1] = {f};
     const double* gp[1] = {g};
@@ -1036,7 +1103,6 @@ int mgwr_batch_create(int count, mgwr_plan* const* plans, mgwr_batch** out) {
   for (int i = 0; i < count; ++i) {
     mgwr_plan* pl = plans[i];
     if (!pl || !pl->bound) { delete bt; return batch_fail(MGWR_ERR_STATE, "every plan of a batch must be bound"); }
-    if (pl->mixed) { delete bt; return batch_fail(MGWR_ERR_INVALID_ARG, "batched solves are float64 plans"); }
     if (i > 0 && pl->device != plans[0]->device) { delete bt; return batch_fail(MGWR_ERR_INVALID_ARG, "plans on different devices"); }
     const long long spc = stages_per_cycle_bound(pl->hp) * mgwr_plan::kMaxPipeCycles;
     nst += spc;
@@ -1045,8 +1111,9 @@ int mgwr_batch_create(int count, mgwr_plan* const* plans, mgwr_batch** out) {
     nnorm += (long long)mgwr_plan::kMaxPipeCycles * ((pl->hp.levels[0].N + 15) / 16);
     bt->plans.push_back(pl);
     bt->lds = std::max(bt->lds, march_lds_bytes<double>(base_args<double>(pl, pl->d64, 0)));
+    if (pl->mixed) bt->lds = std::max(bt->lds, march_lds_bytes<float>(base_args<float>(pl, pl->d32, 0)));
   }
-  bt->off_stages = cv.take((size_t)nst * sizeof(Stage<double>));
+  bt->off_stages = cv.take((size_t)nst * sizeof(Stage));
   bt->off_counters = cv.take((size_t)ncnt * sizeof(int));
   bt->off_flags = cv.take(2 * sizeof(int));
   bt->off_norms = cv.take((size_t)nnorm * sizeof(double));
@@ -1069,7 +1136,7 @@ int mgwr_batch_bind(mgwr_batch* bt, void* ws, size_t bytes, void* stream) {
   if (bt->device != bt->plans[0]->device) return batch_fail(MGWR_ERR_INVALID_ARG, "batch bound to another device");
   unsigned char* w = (unsigned char*)ws;
   bt->stream = (hipStream_t)stream;
-  bt->stages_dev = (Stage<double>*)(w + bt->off_stages);
+  bt->stages_dev = (Stage*)(w + bt->off_stages);
   bt->counters = (int*)(w + bt->off_counters);
   bt->flags_dev = (int*)(w + bt->off_flags);
   bt->norms = (double*)(w + bt->off_norms);

@@ -171,9 +171,10 @@ def test_large2d_parity_full_size(dev):
     assert np.max(np.abs(U - ref)) / np.max(np.abs(np.outer(w, s))) < 1e-10, st
 
 
-def test_mixed_precision_reaches_tolerance(dev):
+@pytest.mark.parametrize("schedule,inner", [("staged", 1), ("pipelined", 1), ("pipelined", 2)])
+def test_mixed_precision_reaches_tolerance(dev, schedule, inner):
     p = W.manufactured(1, 255, 1024, 0.5, r=3.0, k=10)
-    plan = _plan(p, dev, precision="mixed", inner_cycles=1)
+    plan = _plan(p, dev, precision="mixed", inner_cycles=inner, schedule=schedule)
     u, st = plan.solve(_cuda(p.f, dev), tol=1e-8)
     Rt, w, s = _single_mode_reference(p)
     U = u.cpu().numpy()
@@ -278,3 +279,19 @@ def test_repeated_solves_keep_cycle_count(dev):
     batch = mg.Batch([plan]).bind()
     (u3,), (s3,) = batch.solve([f], tol=1e-8)
     assert s3["cycles"] == s1["cycles"] and torch.equal(u1, u3)
+
+
+def test_batched_mixed_and_plain_instances(dev):
+    """A batch holding float64 and mixed-precision plans (1D and 2D)."""
+    probs = [W.manufactured(1, 127, 512, 0.4, k=10), W.manufactured(2, 31, 256, 0.6, r=3.0, k=8)]
+    plans = [_plan(probs[0], dev, precision="mixed"), _plan(probs[1], dev),
+             _plan(probs[1], dev, precision="mixed", inner_cycles=2)]
+    probs = [probs[0], probs[1], probs[1]]
+    batch = mg.Batch(plans).bind()
+    us, sts = batch.solve([_cuda(p.f, dev) for p in probs], tol=1e-8)
+    for p, u, st in zip(probs, us, sts):
+        Rt, w, s = _single_mode_reference(p)
+        U = u.cpu().numpy()
+        res = np.max(np.abs(oracle.residual(Rt, U, p.f, p.dim, p.n, 1.0)))
+        assert res <= 1e-8 * st["bnorm"] * 1.01, st
+        assert np.max(np.abs(U - np.outer(w, s))) / np.max(np.abs(w)) < 1e-7
