@@ -57,7 +57,10 @@ typedef enum {
 
 /* Flags of mgwr_solve. */
 enum {
-  MGWR_GUESS_IN_U = 1u  /* u_dev holds the initial iterate (otherwise the zero grid function) */
+  MGWR_GUESS_IN_U = 1u,  /* u_dev holds the initial iterate (otherwise the zero grid function) */
+  MGWR_WARM_START = 2u   /* initial iterate predicted by the plan's network (mgwr_plan_set_warm_start);
+                            falls back to the zero iterate when the prediction's float64 defect is not
+                            smaller than ||b||_inf or not finite */
 };
 
 typedef struct {
@@ -102,6 +105,8 @@ typedef struct {
   double history[64]; /* ||b - A u||_inf after each of the first 64 outer steps (cycles or
                          refinements); 0 where a pipelined launch with a learned cycle count
                          evaluated the norm only after its last cycle */
+  int used_warm_start; /* 1 if the network's prediction was the initial iterate */
+  double warm_res0;    /* ||b - A u_predicted||_inf (when a warm start was requested) */
 } mgwr_stats;
 
 typedef struct mgwr_plan mgwr_plan;
@@ -204,6 +209,43 @@ int mgwr_batch_solve(mgwr_batch* batch, const double* const* f_dev, const double
  * on, 0 turns it off, -1 leaves it unchanged. */
 int mgwr_batch_timing(mgwr_batch* batch, int enable, mgwr_timing* out);
 int mgwr_batch_destroy(mgwr_batch* batch);
+
+/* Learned initial guess (a small convolution network).  Layers l = 0..L-1
+ * are 3x3 convolutions with zero padding from channels[l] to channels[l+1],
+ * tanh after all but the last; tensors are [batch][channel][H][W] float32 (a
+ * 1D grid is an image of height 1).  The forward pass and the data gradient
+ * use bfloat16 copies of the weights with float32 accumulation; master
+ * weights, gradients and Adam moments are float32.  Parameter layout: for
+ * each layer, weights [c_out][c_in][3][3] then biases [c_out]. */
+typedef struct mgwr_net mgwr_net;
+int mgwr_net_create(int layers, const int* channels, mgwr_net** out);
+int mgwr_net_param_count(const mgwr_net* net, size_t* count);
+/* Device bytes for activations and optimiser state when batch*H*W <= max_bhw. */
+int mgwr_net_workspace_bytes(const mgwr_net* net, long long max_bhw, size_t* bytes);
+/* params_dev: caller-owned float32 master weights (mgwr_net_param_count
+ * entries); resets the Adam moments and rounds the bfloat16 copies. */
+int mgwr_net_bind(mgwr_net* net, float* params_dev, long long max_bhw, void* workspace_dev, size_t bytes,
+                  void* stream);
+/* Re-round the bfloat16 copies after the caller changed params_dev. */
+int mgwr_net_sync_weights(mgwr_net* net);
+int mgwr_net_forward(mgwr_net* net, const float* x_dev, int batch, int H, int W, float* y_dev);
+/* Loss L = (1/B) sum_b ||y_b - t_b||^2 / ||t_b||^2 and its gradient with
+ * respect to every parameter (kept in the net; copied to grad_dev if not
+ * NULL); loss_host (nullable) synchronises. */
+int mgwr_net_gradient(mgwr_net* net, const float* x_dev, const float* target_dev, int batch, int H, int W,
+                      float* grad_dev, double* loss_host);
+/* Adam update of params_dev with the last gradient (step counts from 1). */
+int mgwr_net_adam_step(mgwr_net* net, float lr, float beta1, float beta2, float eps, int step);
+int mgwr_net_destroy(mgwr_net* net);
+
+/* Attach a bound network to a plan for MGWR_WARM_START solves: its input is
+ * f (or b = f + a_1 g) at `nslices` time rows rows_host[0..nslices) divided by
+ * ||b||_inf, then the constant channels alpha and r/10 (channels[0] must be
+ * nslices + 2); its output (channels[L] = nslices) is the solution at those
+ * rows, times ||b||_inf, interpolated linearly in the row index (zero before
+ * the first row).  The network must be bound with max_bhw >= N and on the
+ * plan's device; net NULL detaches. */
+int mgwr_plan_set_warm_start(mgwr_plan* plan, mgwr_net* net, int nslices, const int* rows_host);
 
 /* Plan facts for tests and reports (host, no device work). */
 typedef struct {

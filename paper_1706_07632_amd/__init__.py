@@ -22,6 +22,7 @@ MGWR_ERR_NONFINITE = 5
 MGWR_FP64 = 0
 MGWR_MIXED_FP32 = 1
 MGWR_GUESS_IN_U = 1
+MGWR_WARM_START = 2
 
 EXPORTED = [
     "mgwr_params_default", "mgwr_plan_create", "mgwr_plan_workspace_bytes", "mgwr_plan_bind",
@@ -29,6 +30,9 @@ EXPORTED = [
     "mgwr_plan_get_mesh", "mgwr_plan_export_dense", "mgwr_plan_destroy", "mgwr_last_error",
     "mgwr_timing_enable", "mgwr_timing_get", "mgwr_batch_create", "mgwr_batch_workspace_bytes",
     "mgwr_batch_bind", "mgwr_batch_solve", "mgwr_batch_timing", "mgwr_batch_destroy",
+    "mgwr_net_create", "mgwr_net_param_count", "mgwr_net_workspace_bytes", "mgwr_net_bind",
+    "mgwr_net_sync_weights", "mgwr_net_forward", "mgwr_net_gradient", "mgwr_net_adam_step", "mgwr_net_destroy",
+    "mgwr_plan_set_warm_start",
 ]
 
 KERNEL_CLASSES = ["smooth64", "defect64", "smooth32", "defect32", "restrict", "prolong", "pipe64"]
@@ -52,7 +56,7 @@ class Params(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int), ("refinements", ctypes.c_int), ("res0", ctypes.c_double),
                 ("bnorm", ctypes.c_double), ("res", ctypes.c_double), ("avg_factor", ctypes.c_double),
-                ("history", ctypes.c_double * 64)]
+                ("history", ctypes.c_double * 64), ("used_warm_start", ctypes.c_int), ("warm_res0", ctypes.c_double)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "history"}
@@ -115,6 +119,16 @@ def lib():
                                    ctypes.POINTER(vp), ctypes.c_uint, ctypes.POINTER(Stats)]
     L.mgwr_batch_timing.argtypes = [vp, ip, ctypes.POINTER(Timing)]
     L.mgwr_batch_destroy.argtypes = [vp]
+    L.mgwr_net_create.argtypes = [ip, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(vp)]
+    L.mgwr_net_param_count.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.mgwr_net_workspace_bytes.argtypes = [vp, ctypes.c_longlong, ctypes.POINTER(ctypes.c_size_t)]
+    L.mgwr_net_bind.argtypes = [vp, vp, ctypes.c_longlong, vp, ctypes.c_size_t, vp]
+    L.mgwr_net_sync_weights.argtypes = [vp]
+    L.mgwr_net_forward.argtypes = [vp, vp, ip, ip, ip, vp]
+    L.mgwr_net_gradient.argtypes = [vp, vp, vp, ip, ip, ip, vp, ctypes.POINTER(ctypes.c_double)]
+    L.mgwr_net_adam_step.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, ip]
+    L.mgwr_net_destroy.argtypes = [vp]
+    L.mgwr_plan_set_warm_start.argtypes = [vp, vp, ip, ctypes.POINTER(ctypes.c_int)]
     L.mgwr_last_error.argtypes = []
     L.mgwr_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -223,7 +237,15 @@ class Plan:
         self.device = dev
         return self
 
-    def solve(self, f, g=None, tol=1e-10, u=None, guess=False, allow_unconverged=False):
+    def set_warm_start(self, net, rows):
+        """Attach a bound Net as the initial-guess predictor (rows: the time
+        rows of its input/output slices)."""
+        rows = [int(r) for r in rows]
+        arr = (ctypes.c_int * len(rows))(*rows)
+        _check(lib().mgwr_plan_set_warm_start(self._h, None if net is None else net._h, len(rows), arr))
+        self._net = net
+
+    def solve(self, f, g=None, tol=1e-10, u=None, guess=False, allow_unconverged=False, warm_start=False):
         import torch
         _require(f, "f", (self.M, self.N))
         if g is not None:
@@ -232,8 +254,8 @@ class Plan:
             u = torch.empty((self.M, self.N), dtype=torch.float64, device=f.device)
         _require(u, "u", (self.M, self.N))
         st = Stats()
-        rc = lib().mgwr_solve(self._h, _dptr(f), _dptr(g), float(tol), _dptr(u),
-                              MGWR_GUESS_IN_U if guess else 0, ctypes.byref(st))
+        fl = (MGWR_GUESS_IN_U if guess else 0) | (MGWR_WARM_START if warm_start else 0)
+        rc = lib().mgwr_solve(self._h, _dptr(f), _dptr(g), float(tol), _dptr(u), fl, ctypes.byref(st))
         _check(rc, ok=(MGWR_OK, MGWR_ERR_NOT_CONVERGED) if allow_unconverged else (MGWR_OK,))
         return u, st.as_dict()
 
@@ -316,7 +338,7 @@ class Batch:
                                          ctypes.c_void_p(self._stream.cuda_stream)))
         return self
 
-    def solve(self, fs, gs=None, tol=1e-10, us=None, guess=False, allow_unconverged=False):
+    def solve(self, fs, gs=None, tol=1e-10, us=None, guess=False, allow_unconverged=False, warm_start=False):
         import torch
         n = len(self.plans)
         if us is None:
@@ -333,7 +355,8 @@ class Batch:
                     _require(g, "g", (p.N,))
             ga = (ctypes.c_void_p * n)(*[None if g is None else g.data_ptr() for g in gs])
         st = (Stats * n)()
-        rc = lib().mgwr_batch_solve(self._h, fa, ga, float(tol), ua, MGWR_GUESS_IN_U if guess else 0, st)
+        fl = (MGWR_GUESS_IN_U if guess else 0) | (MGWR_WARM_START if warm_start else 0)
+        rc = lib().mgwr_batch_solve(self._h, fa, ga, float(tol), ua, fl, st)
         _check(rc, ok=(MGWR_OK, MGWR_ERR_NOT_CONVERGED) if allow_unconverged else (MGWR_OK,))
         return us, [s.as_dict() for s in st]
 
@@ -345,6 +368,97 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None):
             lib().mgwr_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Net:
+    """Convolution network of the learned initial guess (3x3 layers, tanh
+    between them); `channels` = [c_0, ..., c_L].  Weights live in a torch
+    float32 tensor `params` (master copy); the library keeps bfloat16 copies."""
+
+    def __init__(self, channels, max_bhw, device=None, seed=0):
+        import torch
+        self.channels = [int(c) for c in channels]
+        arr = (ctypes.c_int * len(self.channels))(*self.channels)
+        h = ctypes.c_void_p()
+        _check(lib().mgwr_net_create(len(self.channels) - 1, arr, ctypes.byref(h)))
+        self._h = h
+        n = ctypes.c_size_t()
+        _check(lib().mgwr_net_param_count(self._h, ctypes.byref(n)))
+        self.nparam = n.value
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.params = torch.empty(self.nparam, dtype=torch.float32, device=dev)
+        self.init_params(seed)
+        b = ctypes.c_size_t()
+        _check(lib().mgwr_net_workspace_bytes(self._h, int(max_bhw), ctypes.byref(b)))
+        self._ws = torch.empty(b.value + 256, dtype=torch.uint8, device=dev)
+        aligned = (self._ws.data_ptr() + 255) & ~255
+        self._stream = torch.cuda.current_stream(dev)
+        _check(lib().mgwr_net_bind(self._h, ctypes.c_void_p(self.params.data_ptr()), int(max_bhw),
+                                   ctypes.c_void_p(aligned), b.value, ctypes.c_void_p(self._stream.cuda_stream)))
+        self.step = 0
+
+    def layout(self):
+        """[(weight offset, weight shape, bias offset, bias size)] per layer."""
+        out, off = [], 0
+        for cin, cout in zip(self.channels[:-1], self.channels[1:]):
+            out.append((off, (cout, cin, 3, 3), off + cout * cin * 9, cout))
+            off += cout * cin * 9 + cout
+        return out
+
+    def init_params(self, seed=0):
+        import numpy as np
+        import torch
+        rng = np.random.default_rng(seed)
+        host = np.zeros(self.nparam, dtype=np.float32)
+        for woff, shape, boff, nb in self.layout():
+            fan_in = shape[1] * 9
+            host[woff:woff + int(np.prod(shape))] = rng.uniform(-1, 1, int(np.prod(shape))) * np.sqrt(3.0 / fan_in)
+        self.params.copy_(torch.from_numpy(host))
+        if getattr(self, "_ws", None) is not None:
+            _check(lib().mgwr_net_sync_weights(self._h))
+
+    def set_params(self, values):
+        import torch
+        self.params.copy_(torch.as_tensor(values, dtype=torch.float32))
+        _check(lib().mgwr_net_sync_weights(self._h))
+
+    def forward(self, x):
+        import torch
+        B, C, H, W = x.shape
+        _require(x, "x", (B, self.channels[0], H, W), torch.float32)
+        y = torch.empty((B, self.channels[-1], H, W), dtype=torch.float32, device=x.device)
+        _check(lib().mgwr_net_forward(self._h, _dptr(x), B, H, W, _dptr(y)))
+        return y
+
+    def gradient(self, x, target):
+        import torch
+        B, C, H, W = x.shape
+        _require(x, "x", (B, self.channels[0], H, W), torch.float32)
+        _require(target, "target", (B, self.channels[-1], H, W), torch.float32)
+        g = torch.empty(self.nparam, dtype=torch.float32, device=x.device)
+        loss = ctypes.c_double()
+        _check(lib().mgwr_net_gradient(self._h, _dptr(x), _dptr(target), B, H, W, _dptr(g), ctypes.byref(loss)))
+        return loss.value, g
+
+    def train_step(self, x, target, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        import torch
+        B, C, H, W = x.shape
+        loss = ctypes.c_double()
+        _check(lib().mgwr_net_gradient(self._h, _dptr(x), _dptr(target), B, H, W, None, ctypes.byref(loss)))
+        self.step += 1
+        _check(lib().mgwr_net_adam_step(self._h, float(lr), float(beta1), float(beta2), float(eps), self.step))
+        return loss.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mgwr_net_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -13,6 +13,7 @@
 #include "hplan.h"
 #include "kernels.h"
 #include "mgwr.h"
+#include "net.h"
 
 using namespace mgwr;
 
@@ -24,6 +25,14 @@ int fail(int code, const std::string& msg) {
   g_last_error = msg;
   return code;
 }
+
+}  // namespace
+
+namespace mgwr {
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace mgwr
+
+namespace {
 
 #define HIP_TRY(...)                                                                          \
   do {                                                                                        \
@@ -91,9 +100,15 @@ struct mgwr_plan {
   double* norms = nullptr;             // [kMaxPipeCycles][norm_chunks]
   int khint = 0;                       // cycles the last pipelined solve needed
   double cycle_flops = 0.0, cycle_bytes = 0.0;  // algorithmic work of one pipelined cycle
+  // learned initial guess
+  static constexpr int kMaxSlices = 64;
+  mgwr_net* net = nullptr;
+  int nslices = 0;
+  int* rows_dev = nullptr;
+  float* netx = nullptr;   // network input [nslices + 2][N]
   // offsets computed by layout()
   struct Off {
-    size_t stages, counters, flags, norms;
+    size_t stages, counters, flags, norms, wrows, wx;
     size_t leaves, dn_list, ff_row, zu_row, a1, B0, part, scal;
     size_t dense64, dinv64, ffA64, zuB64, dense32, dinv32, ffA32, zuB32;
     std::vector<size_t> U64, F64, R64, U32, F32, R32;
@@ -165,6 +180,8 @@ void layout(mgwr_plan* pl) {
     o.flags = cv.take(2 * sizeof(int));
     o.norms = cv.take((size_t)mgwr_plan::kMaxPipeCycles * ((hp.levels[0].N + 15) / 16) * sizeof(double));
   }
+  o.wrows = cv.take(mgwr_plan::kMaxSlices * sizeof(int));
+  o.wx = cv.take((size_t)(mgwr_plan::kMaxSlices + 2) * hp.levels[0].N * sizeof(float));
   o.total = cv.off;
 }
 
@@ -556,25 +573,55 @@ struct mgwr_batch {
 
 namespace {
 
-// Prepares instance i: b = f + a_1 g, zero iterate unless given, ||b||, res0.
-int prepare_solve(mgwr_plan* pl, const double* f, const double* g, double tol, double* u, unsigned flags,
+// Prepares an instance: b = f + a_1 g, the initial iterate (zero, given, or
+// predicted by the warm-start network with a fall back to zero), ||b||,
+// res0.  `flags` returns with MGWR_GUESS_IN_U set iff u holds a non-zero
+// iterate whose defect is in R64_0.
+int prepare_solve(mgwr_plan* pl, const double* f, const double* g, double tol, double* u, unsigned& flags,
                   mgwr_stats& s, const double*& b, int& status) {
   int rc;
   const HostPlan& hp = pl->hp;
-  const long long MN = (long long)hp.p.M * hp.levels[0].N;
+  const long long N = hp.levels[0].N;
+  const long long MN = (long long)hp.p.M * N;
   s = mgwr_stats{};
   b = f;
   if (g) {
-    HIP_TRY(launch_rhs0(f, g, pl->a1, pl->B0, hp.p.M, hp.levels[0].N, pl->stream));
+    HIP_TRY(launch_rhs0(f, g, pl->a1, pl->B0, hp.p.M, N, pl->stream));
     b = pl->B0;
   }
-  if (!(flags & MGWR_GUESS_IN_U)) HIP_TRY(launch_fill<double>(u, MN, 0.0, pl->stream));
+  if (!(flags & (MGWR_GUESS_IN_U | MGWR_WARM_START))) HIP_TRY(launch_fill<double>(u, MN, 0.0, pl->stream));
   if ((rc = norm_inf<double>(pl, b, MN, &s.bnorm))) return rc;
   status = MGWR_ERR_NOT_CONVERGED;
   if (!std::isfinite(s.bnorm)) { status = MGWR_ERR_NONFINITE; return MGWR_OK; }
+  if (flags & MGWR_WARM_START) {
+    if (!pl->net) return fail(MGWR_ERR_STATE, "MGWR_WARM_START needs a network (mgwr_plan_set_warm_start)");
+    flags &= ~(unsigned)MGWR_GUESS_IN_U;
+    if (s.bnorm > 0.0) {
+      const int ns = pl->nslices;
+      const int H = hp.p.dim == 1 ? 1 : hp.levels[0].n, W = hp.levels[0].n;
+      HIP_TRY(launch_gather_slices(b, pl->rows_dev, ns, N, s.bnorm, (float)hp.p.alpha, (float)(hp.p.r / 10.0),
+                                   pl->netx, pl->stream));
+      HIP_TRY(hipStreamSynchronize(pl->stream));
+      const float* y = nullptr;
+      if ((rc = net_infer(pl->net, pl->netx, H, W, &y))) return rc;
+      HIP_TRY(hipStreamSynchronize(net_stream(pl->net)));
+      HIP_TRY(launch_time_interp(y, pl->rows_dev, ns, hp.p.M, N, s.bnorm, u, pl->stream));
+      if ((rc = defect<double>(pl, pl->d64, 0, b, u, pl->d64.R[0]))) return rc;
+      if ((rc = norm_inf<double>(pl, pl->d64.R[0], MN, &s.warm_res0))) return rc;
+      if (std::isfinite(s.warm_res0) && s.warm_res0 < s.bnorm) {
+        s.used_warm_start = 1;
+        flags |= MGWR_GUESS_IN_U;
+      }
+    }
+    if (!(flags & MGWR_GUESS_IN_U)) HIP_TRY(launch_fill<double>(u, MN, 0.0, pl->stream));
+  }
   if (flags & MGWR_GUESS_IN_U) {
-    if ((rc = defect<double>(pl, pl->d64, 0, b, u, pl->d64.R[0]))) return rc;
-    if ((rc = norm_inf<double>(pl, pl->d64.R[0], MN, &s.res0))) return rc;
+    if (!s.used_warm_start) {
+      if ((rc = defect<double>(pl, pl->d64, 0, b, u, pl->d64.R[0]))) return rc;
+      if ((rc = norm_inf<double>(pl, pl->d64.R[0], MN, &s.res0))) return rc;
+    } else {
+      s.res0 = s.warm_res0;
+    }
   } else {
     s.res0 = s.bnorm;
   }
@@ -597,11 +644,12 @@ int solve_pipelined(mgwr_batch* bt, const double* const* f, const double* const*
   std::vector<mgwr_stats> st(n);
   std::vector<const double*> b(n);
   std::vector<int> status(n), K(n), conv_at(n, -1);
+  std::vector<unsigned> fl_i(n, flags);
   for (int i = 0; i < n; ++i) {
     mgwr_plan* pl = bt->plans[i];
     if (!f[i] || !u[i]) return batch_fail(MGWR_ERR_INVALID_ARG, "null array in batch");
     if ((rc = use_device(pl))) return rc;
-    if ((rc = prepare_solve(pl, f[i], g ? g[i] : nullptr, tol, u[i], flags, st[i], b[i], status[i]))) return rc;
+    if ((rc = prepare_solve(pl, f[i], g ? g[i] : nullptr, tol, u[i], fl_i[i], st[i], b[i], status[i]))) return rc;
     K[i] = pl->khint > 0 ? pl->khint : 8;
   }
   // the plans' streams must be complete before the batch stream uses their arrays
@@ -628,7 +676,7 @@ int solve_pipelined(mgwr_batch* bt, const double* const* f, const double* const*
       const bool every = pl->mixed || !(pl->khint > 0 && st[i].cycles == 0);
       norms_every[a] = every;
       build_plan_stages(pl, b[i], u[i], K[i], bt->norms + bt->norm_off[i], lists[a], every,
-                        st[i].cycles == 0 && !(flags & MGWR_GUESS_IN_U));
+                        st[i].cycles == 0 && !(fl_i[i] & MGWR_GUESS_IN_U));
       pl->stages_f = nullptr;  // the plan's own uploaded table no longer matches its level-0 pointers
       maxlen = std::max(maxlen, lists[a].size());
       flops += pl->cycle_flops * K[i];
@@ -806,6 +854,8 @@ int mgwr_plan_bind(mgwr_plan* pl, void* ws, size_t bytes, void* stream) {
   pl->part = (double*)(w + o.part);
   pl->scal = (double*)(w + o.scal);
   pl->B0 = (double*)(w + o.B0);
+  pl->rows_dev = (int*)(w + o.wrows);
+  pl->netx = (float*)(w + o.wx);
   pl->stages_dev = (Stage*)(w + o.stages);
   pl->counters = (int*)(w + o.counters);
   pl->flags_dev = (int*)(w + o.flags);
@@ -936,27 +986,13 @@ int mgwr_solve(mgwr_plan* pl, const double* f, const double* g, double tol, doub
   const long long MN = (long long)M * hp.levels[0].N;
   mgwr_stats s{};
   const double* b = f;
-  if (g) {
-    HIP_TRY(launch_rhs0(f, g, pl->a1, pl->B0, M, hp.levels[0].N, pl->stream));
-    b = pl->B0;
-  }
-  if (!(flags & MGWR_GUESS_IN_U)) HIP_TRY(launch_fill<double>(u, MN, 0.0, pl->stream));
-  if ((rc = norm_inf<double>(pl, b, MN, &s.bnorm))) return rc;
+  int status = MGWR_ERR_NOT_CONVERGED;
+  if ((rc = prepare_solve(pl, f, g, tol, u, flags, s, b, status))) return rc;
   if (!std::isfinite(s.bnorm)) {
     if (st) *st = s;
     return fail(MGWR_ERR_NONFINITE, "right-hand side is not finite");
   }
-  if (flags & MGWR_GUESS_IN_U) {
-    if ((rc = defect<double>(pl, pl->d64, 0, b, u, pl->d64.R[0]))) return rc;
-    if ((rc = norm_inf<double>(pl, pl->d64.R[0], MN, &s.res0))) return rc;
-  } else {
-    s.res0 = s.bnorm;
-  }
-  s.res = s.res0;
   const double target = tol * s.bnorm;
-  int status = MGWR_ERR_NOT_CONVERGED;
-  if (!std::isfinite(s.res0)) status = MGWR_ERR_NONFINITE;
-  else if (s.res0 <= target) status = MGWR_OK;
 
   if (status == MGWR_ERR_NOT_CONVERGED && !pl->mixed) {
     pl->d64.F[0] = const_cast<double*>(b);
@@ -1042,6 +1078,30 @@ int mgwr_timing_get(mgwr_plan* pl, mgwr_timing* out) {
   if (pl->bound) HIP_TRY(hipStreamSynchronize(pl->stream));
   drain_timing(pl);
   *out = pl->tacc;
+  return MGWR_OK;
+}
+
+int mgwr_plan_set_warm_start(mgwr_plan* pl, mgwr_net* net, int nslices, const int* rows) {
+  int rc = check_bound(pl);
+  if (rc) return rc;
+  if (!net) {
+    pl->net = nullptr;
+    pl->nslices = 0;
+    return MGWR_OK;
+  }
+  const HostPlan& hp = pl->hp;
+  if (nslices < 1 || nslices > mgwr_plan::kMaxSlices || !rows)
+    return fail(MGWR_ERR_INVALID_ARG, "nslices must lie in [1, 64] with a row list");
+  if (net_in_channels(net) != nslices + 2 || net_out_channels(net) != nslices)
+    return fail(MGWR_ERR_INVALID_ARG, "network channels must be nslices + 2 in and nslices out");
+  for (int i = 0; i < nslices; ++i)
+    if (rows[i] < 0 || rows[i] >= hp.p.M || (i > 0 && rows[i] <= rows[i - 1]))
+      return fail(MGWR_ERR_INVALID_ARG, "slice rows must increase within [0, M)");
+  std::vector<int> rv(rows, rows + nslices);
+  HIP_TRY(hipMemcpyAsync(pl->rows_dev, rv.data(), nslices * sizeof(int), hipMemcpyHostToDevice, pl->stream));
+  HIP_TRY(hipStreamSynchronize(pl->stream));
+  pl->net = net;
+  pl->nslices = nslices;
   return MGWR_OK;
 }
 

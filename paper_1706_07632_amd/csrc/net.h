@@ -1,0 +1,22 @@
+// Internal interface between the solver and the warm-start network.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "mgwr.h"
+
+namespace mgwr {
+// Forward pass of one instance (batch 1) on the network's buffers; *y points
+// at the output activations [c_L][H][W].
+int net_infer(mgwr_net* net, const float* x, int H, int W, const float** y);
+int net_in_channels(const mgwr_net* net);
+int net_out_channels(const mgwr_net* net);
+hipStream_t net_stream(const mgwr_net* net);
+hipError_t launch_gather_slices(const double* b, const int* rows, int nslices, long long N, double scale,
+                                float alpha, float rdiv, float* x, hipStream_t s);
+hipError_t launch_time_interp(const float* y, const int* rows, int nslices, long long M, long long N, double scale,
+                              double* u, hipStream_t s);
+void set_last_error(const std::string& msg);
+}  // namespace mgwr
