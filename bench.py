@@ -30,6 +30,13 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (vector and matrix)
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
+# HBM bytes per batched launch of pipeline_kernel<double> on the large1d
+# workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by what the same
+# counters read for a 1 GiB device copy (--copy-probe): fetch x 2.000, write x
+# 1.000.  Valid only for the kernel source they were taken on.
+TRAFFIC_KERNEL_SHA256 = "15d56455dd0b82e97872cacb416226569d35d8dc61d7502bef619f90e279fd93"
+TRAFFIC_BYTES = {"large1d": (2.000 * 23504558.6 + 1.000 * 12931669.8) * 1024}
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -40,8 +47,36 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--cpu-repeats", type=int, default=3)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 1 GiB three times on the device (counter calibration) and exit")
     return ap.parse_args()
+
+
+def copy_probe():
+    import torch
+    x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": x.numel() * 8, "copies": 3}), flush=True)
+
+
+def traffic_for(workload):
+    """Counter-measured HBM bytes per launch, or None when the kernel source
+    differs from the one the counters were taken on."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_1706_07632_amd", "csrc", "kernels.hip")
+    try:
+        with open(src, "rb") as fh:
+            digest = hashlib.sha256(fh.read()).hexdigest()
+    except OSError:
+        return None
+    if digest != TRAFFIC_KERNEL_SHA256:
+        return None
+    return TRAFFIC_BYTES.get(workload)
 
 
 def instances(workload):
@@ -51,18 +86,18 @@ def instances(workload):
     return [W.config(workload)]
 
 
-def time_form(plans, fs, us, tol, steps, warmup, torch):
+def time_form(plans, fs, us, tol, steps, warmup, torch, warm_start=False):
     stats = []
     for _ in range(warmup):
         for pl, f, u in zip(plans, fs, us):
-            pl.solve(f, tol=tol, u=u)
+            pl.solve(f, tol=tol, u=u, warm_start=warm_start)
     for pl in plans:
         pl.timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         for pl, f, u in zip(plans, fs, us):
-            _, st = pl.solve(f, tol=tol, u=u)
+            _, st = pl.solve(f, tol=tol, u=u, warm_start=warm_start)
             stats.append(st)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -72,15 +107,15 @@ def time_form(plans, fs, us, tol, steps, warmup, torch):
     return t1 - t0, stats, timing
 
 
-def time_batch(batch, fs, us, tol, steps, warmup, torch):
+def time_batch(batch, fs, us, tol, steps, warmup, torch, warm_start=False):
     stats = []
     for _ in range(warmup):
-        batch.solve(fs, tol=tol, us=us)
+        batch.solve(fs, tol=tol, us=us, warm_start=warm_start)
     batch.timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        _, st = batch.solve(fs, tol=tol, us=us)
+        _, st = batch.solve(fs, tol=tol, us=us, warm_start=warm_start)
         stats.extend(st)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -125,8 +160,41 @@ def cpu_baseline(probs, repeats):
                       f"R~ assembly excluded ({sum(per):.2f} s per pass)"}
 
 
+def learned_forms(args, probs, fs, us, unknowns, mg, torch):
+    """Warm-started solves (the trained network's prediction, judged by the
+    float64 residual), float64 and mixed, the instances batched as for `value`."""
+    from paper_1706_07632_amd import learn
+    dim = probs[0].dim
+    path = os.path.join(ROOT, "paper_1706_07632_amd", "weights", f"warm{dim}d.npz")
+    if not os.path.exists(path):
+        return {}
+    net, meta = learn.load(path, max(p.N for p in probs))
+    out = {}
+    for name, precision in (("fp64_learned", "fp64"), ("mixed_learned", "mixed")):
+        plans = [mg.Plan(p.dim, p.n, p.M, p.alpha, k=p.k, r=p.r, t=p.t, length=p.length, leaf=p.leaf,
+                         precision=precision, inner_cycles=1).bind() for p in probs]
+        for pl in plans:
+            learn.attach(pl, net)
+        if len(plans) > 1:
+            batch = mg.Batch(plans).bind()
+            secs, st, _ = time_batch(batch, fs, us, args.tol, args.steps, args.warmup, torch, warm_start=True)
+        else:
+            secs, st, _ = time_form(plans, fs, us, args.tol, args.steps, args.warmup, torch, warm_start=True)
+        last = st[-len(probs):]
+        out[name] = {"value": unknowns * args.steps / secs, "ms_per_step": 1e3 * secs / args.steps,
+                     "cycles": [s["cycles"] for s in last],
+                     "used_warm_start": [s["used_warm_start"] for s in last],
+                     "warm_res0_rel": [s["warm_res0"] / s["bnorm"] for s in last],
+                     "rel_res": [s["res"] / s["bnorm"] for s in last],
+                     "network": {k: meta[k] for k in ("dim", "n", "M", "count", "steps", "val_loss")}}
+    return out
+
+
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
@@ -139,7 +207,8 @@ def main():
     probs = instances(args.workload)
     fs = [torch.as_tensor(p.f, dtype=torch.float64, device=dev) for p in probs]
     us = [torch.empty_like(f) for f in fs]
-    plans = [mg.Plan(p.dim, p.n, p.M, p.alpha, k=p.k, t=p.t, length=p.length, leaf=p.leaf).bind() for p in probs]
+    plans = [mg.Plan(p.dim, p.n, p.M, p.alpha, k=p.k, r=p.r, t=p.t, length=p.length, leaf=p.leaf).bind()
+             for p in probs]
     unknowns = sum(p.N * p.M for p in probs)
 
     # one step = the instances solved together: their pipelined cycles are
@@ -174,9 +243,13 @@ def main():
                    "GB/s": round(v["bytes"] / max(v["ms"], 1e-9) * 1e-6, 1)} for k, v in tm.items() if v["launches"]}
 
     if not args.no_mixed:
-        mplans = [mg.Plan(p.dim, p.n, p.M, p.alpha, k=p.k, t=p.t, length=p.length, leaf=p.leaf,
+        mplans = [mg.Plan(p.dim, p.n, p.M, p.alpha, k=p.k, r=p.r, t=p.t, length=p.length, leaf=p.leaf,
                           precision="mixed", inner_cycles=1).bind() for p in probs]
-        msecs, mstats, mtiming = time_form(mplans, fs, us, args.tol, args.steps, args.warmup, torch)
+        if len(mplans) > 1:
+            mbatch = mg.Batch(mplans).bind()
+            msecs, mstats, mtiming = time_batch(mbatch, fs, us, args.tol, args.steps, args.warmup, torch)
+        else:
+            msecs, mstats, mtiming = time_form(mplans, fs, us, args.tol, args.steps, args.warmup, torch)
         mtm = merge_timing(mtiming)
         forms["mixed_fp32"] = {"value": unknowns * args.steps / msecs, "ms_per_step": 1e3 * msecs / args.steps,
                                "cycles": [s["cycles"] for s in mstats[:len(probs)]],
@@ -186,8 +259,11 @@ def main():
                                               "avg_us": round(1e3 * v["ms"] / max(1, v["launches"]), 2)}
                                           for k, v in mtm.items() if v["launches"]}
 
+    if not args.no_learned:
+        forms.update(learned_forms(args, probs, fs, us, unknowns, mg, torch))
+
     out = {
-        "metric": "space-time unknowns (N*M)/s to 1e-8 rel. residual (plain FP64; mixed form under forms)",
+        "metric": "space-time unknowns (N*M)/s to 1e-8 rel. residual (plain FP64; mixed and learned forms under forms)",
         "value": value,
         "unit": "unknowns/s",
         "n_gpus": 1,
@@ -204,7 +280,9 @@ def main():
                    "N": probs[0].N, "M": probs[0].M, "instances": len(probs), "tol": args.tol},
         "roofline": {"bound": "mfma", "kernel": dom_name,
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": traffic_for(args.workload) if dom == "pipe64" else None,
+                     "algorithmic_bytes": sm["bytes"] / max(1, sm["launches"]),
                      "avg_launch_us": avg_launch_us, "launches": sm["launches"]},
         "forms": forms,
         "kernels": kernels,

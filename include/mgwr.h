@@ -58,9 +58,12 @@ typedef enum {
 /* Flags of mgwr_solve. */
 enum {
   MGWR_GUESS_IN_U = 1u,  /* u_dev holds the initial iterate (otherwise the zero grid function) */
-  MGWR_WARM_START = 2u   /* initial iterate predicted by the plan's network (mgwr_plan_set_warm_start);
-                            falls back to the zero iterate when the prediction's float64 defect is not
-                            smaller than ||b||_inf or not finite */
+  MGWR_WARM_START = 2u   /* initial iterate predicted by the plan's network (mgwr_plan_set_warm_start).
+                            Judged by the true float64 residual: a prediction whose defect is not
+                            finite is dropped at once, and one whose residual after the first cycles
+                            (the first pipelined launch, or the first cycle / refinement of a staged
+                            solve) is not below ||b||_inf is dropped then; the solve restarts from the
+                            zero iterate and the cycles already spent stay counted */
 };
 
 typedef struct {
@@ -105,7 +108,7 @@ typedef struct {
   double history[64]; /* ||b - A u||_inf after each of the first 64 outer steps (cycles or
                          refinements); 0 where a pipelined launch with a learned cycle count
                          evaluated the norm only after its last cycle */
-  int used_warm_start; /* 1 if the network's prediction was the initial iterate */
+  int used_warm_start; /* 1 if the network's prediction was the initial iterate of the returned solution */
   double warm_res0;    /* ||b - A u_predicted||_inf (when a warm start was requested) */
 } mgwr_stats;
 
@@ -210,41 +213,68 @@ int mgwr_batch_solve(mgwr_batch* batch, const double* const* f_dev, const double
 int mgwr_batch_timing(mgwr_batch* batch, int enable, mgwr_timing* out);
 int mgwr_batch_destroy(mgwr_batch* batch);
 
-/* Learned initial guess (a small convolution network).  Layers l = 0..L-1
- * are 3x3 convolutions with zero padding from channels[l] to channels[l+1],
- * tanh after all but the last; tensors are [batch][channel][H][W] float32 (a
- * 1D grid is an image of height 1).  The forward pass and the data gradient
- * use bfloat16 copies of the weights with float32 accumulation; master
- * weights, gradients and Adam moments are float32.  Parameter layout: for
- * each layer, weights [c_out][c_in][3][3] then biases [c_out]. */
+/* Learned initial guess.  Not part of the paper's method, which starts its
+ * iteration from a given iterate: this network only proposes that iterate,
+ * and the multigrid iteration's own float64 residual judges the proposal.
+ *
+ * A stack of 3x3 convolutions (zero padding, tanh after all layers but the
+ * last) applied band by band to a spatial pyramid.  Input x [B][S+E][H][W]
+ * float32 with S = nsignal signal channels and E = channels[0] - 1 - S extra
+ * channels; a 1D grid is an image of height 1, a 2D grid has H = W; W must be
+ * 2^p - 1 >= 3.  Levels n_0 = W, n_{l+1} = (n_l - 1)/2 down to 3 points; the
+ * signal is split into bands band_l = c_l - P c_{l+1} (c_0 = signal,
+ * c_{l+1} = full-weighting restriction of c_l, P 4-point (cubic) interpolation
+ * with odd reflection at the zero boundary,
+ * band_last = c_last); the convolution stack maps [band_l, the extra channels
+ * sampled at the level's points, log2(1/h_l)/10] (channels[0] channels) to
+ * out_l (channels[L] channels), and the output is
+ * y = sum_l P^l (4 h_l^2 out_l), h_l = 2^l h with h the fine-grid spacing.
+ * The forward pass and the data gradient use bfloat16 copies of the
+ * convolution weights (biases stay float32) with float32 accumulation; master
+ * weights, gradients and Adam moments are float32.  Parameter layout: for each layer, weights [c_out][c_in][3][3]
+ * then biases [c_out].  All arrays are device pointers on the stream given to
+ * mgwr_net_bind; calls are asynchronous unless stated. */
 typedef struct mgwr_net mgwr_net;
-int mgwr_net_create(int layers, const int* channels, mgwr_net** out);
+/* layers in [1, 16]; channels[0..layers] in [1, 1024]; nsignal in [1, channels[0] - 1]. */
+int mgwr_net_create(int layers, const int* channels, int nsignal, mgwr_net** out);
 int mgwr_net_param_count(const mgwr_net* net, size_t* count);
 /* Device bytes for activations and optimiser state when batch*H*W <= max_bhw. */
 int mgwr_net_workspace_bytes(const mgwr_net* net, long long max_bhw, size_t* bytes);
 /* params_dev: caller-owned float32 master weights (mgwr_net_param_count
- * entries); resets the Adam moments and rounds the bfloat16 copies. */
+ * entries); workspace 256-byte aligned; resets the Adam moments and rounds
+ * the bfloat16 copies (synchronises). */
 int mgwr_net_bind(mgwr_net* net, float* params_dev, long long max_bhw, void* workspace_dev, size_t bytes,
                   void* stream);
 /* Re-round the bfloat16 copies after the caller changed params_dev. */
 int mgwr_net_sync_weights(mgwr_net* net);
-int mgwr_net_forward(mgwr_net* net, const float* x_dev, int batch, int H, int W, float* y_dev);
+/* y [B][channels[L]][H][W] = network(x); h > 0 the fine-grid spacing.  The
+ * grid shape is checked (MGWR_ERR_INVALID_ARG). */
+int mgwr_net_forward(mgwr_net* net, const float* x_dev, int batch, int H, int W, double h, float* y_dev);
 /* Loss L = (1/B) sum_b ||y_b - t_b||^2 / ||t_b||^2 and its gradient with
  * respect to every parameter (kept in the net; copied to grad_dev if not
  * NULL); loss_host (nullable) synchronises. */
 int mgwr_net_gradient(mgwr_net* net, const float* x_dev, const float* target_dev, int batch, int H, int W,
-                      float* grad_dev, double* loss_host);
-/* Adam update of params_dev with the last gradient (step counts from 1). */
+                      double h, float* grad_dev, double* loss_host);
+/* Leave out every level with spacing h_l < h_min (its convolution stack is not
+ * run and out_l counts as zero): bands finer than the grids a network was
+ * trained on.  0 (the default) keeps all levels.  Gradients follow the same
+ * rule. */
+int mgwr_net_set_finest(mgwr_net* net, double h_min);
+/* Adam update of params_dev with the last gradient (step counts from 1);
+ * refreshes the bfloat16 copies. */
 int mgwr_net_adam_step(mgwr_net* net, float lr, float beta1, float beta2, float eps, int step);
 int mgwr_net_destroy(mgwr_net* net);
 
-/* Attach a bound network to a plan for MGWR_WARM_START solves: its input is
- * f (or b = f + a_1 g) at `nslices` time rows rows_host[0..nslices) divided by
- * ||b||_inf, then the constant channels alpha and r/10 (channels[0] must be
- * nslices + 2); its output (channels[L] = nslices) is the solution at those
- * rows, times ||b||_inf, interpolated linearly in the row index (zero before
- * the first row).  The network must be bound with max_bhw >= N and on the
- * plan's device; net NULL detaches. */
+/* Attach a bound network to a plan for MGWR_WARM_START solves.  Its input is
+ * b = f + a_{.,1} g at the `nslices` time rows rows_host[0..nslices)
+ * (increasing, in [0, M)) divided by ||b||_inf, then the constant channels
+ * alpha and r/10 (nsignal = nslices, channels[0] = nslices + 3); its output
+ * (channels[L] = nslices) times ||b||_inf is the solution at those rows,
+ * placed at t_{rows[s]+1} and interpolated piecewise linearly in the variable
+ * t^alpha (the solution's behaviour near t = 0, Section 2) from the initial
+ * value g (zero if NULL) at t_0, constant after the last row.  Needs
+ * n = 2^p - 1 and a network bound with max_bhw >= N on the plan's device;
+ * the network must outlive the attachment.  net NULL detaches. */
 int mgwr_plan_set_warm_start(mgwr_plan* plan, mgwr_net* net, int nslices, const int* rows_host);
 
 /* Plan facts for tests and reports (host, no device work). */

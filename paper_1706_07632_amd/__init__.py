@@ -31,7 +31,8 @@ EXPORTED = [
     "mgwr_timing_enable", "mgwr_timing_get", "mgwr_batch_create", "mgwr_batch_workspace_bytes",
     "mgwr_batch_bind", "mgwr_batch_solve", "mgwr_batch_timing", "mgwr_batch_destroy",
     "mgwr_net_create", "mgwr_net_param_count", "mgwr_net_workspace_bytes", "mgwr_net_bind",
-    "mgwr_net_sync_weights", "mgwr_net_forward", "mgwr_net_gradient", "mgwr_net_adam_step", "mgwr_net_destroy",
+    "mgwr_net_sync_weights", "mgwr_net_forward", "mgwr_net_gradient", "mgwr_net_set_finest",
+    "mgwr_net_adam_step", "mgwr_net_destroy",
     "mgwr_plan_set_warm_start",
 ]
 
@@ -119,13 +120,14 @@ def lib():
                                    ctypes.POINTER(vp), ctypes.c_uint, ctypes.POINTER(Stats)]
     L.mgwr_batch_timing.argtypes = [vp, ip, ctypes.POINTER(Timing)]
     L.mgwr_batch_destroy.argtypes = [vp]
-    L.mgwr_net_create.argtypes = [ip, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(vp)]
+    L.mgwr_net_create.argtypes = [ip, ctypes.POINTER(ctypes.c_int), ip, ctypes.POINTER(vp)]
     L.mgwr_net_param_count.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
     L.mgwr_net_workspace_bytes.argtypes = [vp, ctypes.c_longlong, ctypes.POINTER(ctypes.c_size_t)]
     L.mgwr_net_bind.argtypes = [vp, vp, ctypes.c_longlong, vp, ctypes.c_size_t, vp]
     L.mgwr_net_sync_weights.argtypes = [vp]
-    L.mgwr_net_forward.argtypes = [vp, vp, ip, ip, ip, vp]
-    L.mgwr_net_gradient.argtypes = [vp, vp, vp, ip, ip, ip, vp, ctypes.POINTER(ctypes.c_double)]
+    L.mgwr_net_forward.argtypes = [vp, vp, ip, ip, ip, ctypes.c_double, vp]
+    L.mgwr_net_gradient.argtypes = [vp, vp, vp, ip, ip, ip, ctypes.c_double, vp, ctypes.POINTER(ctypes.c_double)]
+    L.mgwr_net_set_finest.argtypes = [vp, ctypes.c_double]
     L.mgwr_net_adam_step.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, ip]
     L.mgwr_net_destroy.argtypes = [vp]
     L.mgwr_plan_set_warm_start.argtypes = [vp, vp, ip, ctypes.POINTER(ctypes.c_int)]
@@ -378,23 +380,27 @@ class Batch:
 
 
 class Net:
-    """Convolution network of the learned initial guess (3x3 layers, tanh
-    between them); `channels` = [c_0, ..., c_L].  Weights live in a torch
-    float32 tensor `params` (master copy); the library keeps bfloat16 copies."""
+    """Band-pyramid convolution network of the learned initial guess.
 
-    def __init__(self, channels, max_bhw, device=None, seed=0):
+    `channels` = [c_0, ..., c_L] of the 3x3 convolution stack; the input
+    tensor has c_0 - 1 channels, the first `nsignal` of which are split into
+    spatial bands (the last one of c_0 is the level value the library adds).
+    Weights live in the float32 tensor `params` (master copy); the library
+    keeps bfloat16 copies for the forward and data-gradient passes."""
+
+    def __init__(self, channels, nsignal, max_bhw, device=None, seed=0):
         import torch
         self.channels = [int(c) for c in channels]
+        self.nsignal = int(nsignal)
         arr = (ctypes.c_int * len(self.channels))(*self.channels)
         h = ctypes.c_void_p()
-        _check(lib().mgwr_net_create(len(self.channels) - 1, arr, ctypes.byref(h)))
+        _check(lib().mgwr_net_create(len(self.channels) - 1, arr, self.nsignal, ctypes.byref(h)))
         self._h = h
         n = ctypes.c_size_t()
         _check(lib().mgwr_net_param_count(self._h, ctypes.byref(n)))
         self.nparam = n.value
         dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
-        self.params = torch.empty(self.nparam, dtype=torch.float32, device=dev)
-        self.init_params(seed)
+        self.params = torch.zeros(self.nparam, dtype=torch.float32, device=dev)
         b = ctypes.c_size_t()
         _check(lib().mgwr_net_workspace_bytes(self._h, int(max_bhw), ctypes.byref(b)))
         self._ws = torch.empty(b.value + 256, dtype=torch.uint8, device=dev)
@@ -402,7 +408,13 @@ class Net:
         self._stream = torch.cuda.current_stream(dev)
         _check(lib().mgwr_net_bind(self._h, ctypes.c_void_p(self.params.data_ptr()), int(max_bhw),
                                    ctypes.c_void_p(aligned), b.value, ctypes.c_void_p(self._stream.cuda_stream)))
+        self.max_bhw = int(max_bhw)
         self.step = 0
+        self.init_params(seed)
+
+    @property
+    def in_channels(self):
+        return self.channels[0] - 1
 
     def layout(self):
         """[(weight offset, weight shape, bias offset, bias size)] per layer."""
@@ -413,48 +425,56 @@ class Net:
         return out
 
     def init_params(self, seed=0):
+        """Uniform weights with variance 1/fan_in, zero biases (host RNG)."""
         import numpy as np
-        import torch
-        rng = np.random.default_rng(seed)
         host = np.zeros(self.nparam, dtype=np.float32)
+        rng = np.random.default_rng(seed)
         for woff, shape, boff, nb in self.layout():
-            fan_in = shape[1] * 9
-            host[woff:woff + int(np.prod(shape))] = rng.uniform(-1, 1, int(np.prod(shape))) * np.sqrt(3.0 / fan_in)
-        self.params.copy_(torch.from_numpy(host))
-        if getattr(self, "_ws", None) is not None:
-            _check(lib().mgwr_net_sync_weights(self._h))
+            cnt = int(np.prod(shape))
+            host[woff:woff + cnt] = rng.uniform(-1, 1, cnt) * np.sqrt(3.0 / (shape[1] * 9))
+        self.set_params(host)
 
     def set_params(self, values):
         import torch
         self.params.copy_(torch.as_tensor(values, dtype=torch.float32))
         _check(lib().mgwr_net_sync_weights(self._h))
+        self.step = 0
 
-    def forward(self, x):
+    def set_finest(self, h_min):
+        """Leave out the bands finer than spacing h_min (0 keeps all)."""
+        _check(lib().mgwr_net_set_finest(self._h, float(h_min)))
+        self.h_min = float(h_min)
+
+    def forward(self, x, h):
         import torch
         B, C, H, W = x.shape
-        _require(x, "x", (B, self.channels[0], H, W), torch.float32)
+        _require(x, "x", (B, self.in_channels, H, W), torch.float32)
         y = torch.empty((B, self.channels[-1], H, W), dtype=torch.float32, device=x.device)
-        _check(lib().mgwr_net_forward(self._h, _dptr(x), B, H, W, _dptr(y)))
+        _check(lib().mgwr_net_forward(self._h, _dptr(x), B, H, W, float(h), _dptr(y)))
         return y
 
-    def gradient(self, x, target):
+    def gradient(self, x, target, h):
         import torch
         B, C, H, W = x.shape
-        _require(x, "x", (B, self.channels[0], H, W), torch.float32)
+        _require(x, "x", (B, self.in_channels, H, W), torch.float32)
         _require(target, "target", (B, self.channels[-1], H, W), torch.float32)
         g = torch.empty(self.nparam, dtype=torch.float32, device=x.device)
         loss = ctypes.c_double()
-        _check(lib().mgwr_net_gradient(self._h, _dptr(x), _dptr(target), B, H, W, _dptr(g), ctypes.byref(loss)))
+        _check(lib().mgwr_net_gradient(self._h, _dptr(x), _dptr(target), B, H, W, float(h), _dptr(g),
+                                       ctypes.byref(loss)))
         return loss.value, g
 
-    def train_step(self, x, target, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    def train_step(self, x, target, h, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, want_loss=False):
         import torch
         B, C, H, W = x.shape
+        _require(x, "x", (B, self.in_channels, H, W), torch.float32)
+        _require(target, "target", (B, self.channels[-1], H, W), torch.float32)
         loss = ctypes.c_double()
-        _check(lib().mgwr_net_gradient(self._h, _dptr(x), _dptr(target), B, H, W, None, ctypes.byref(loss)))
+        _check(lib().mgwr_net_gradient(self._h, _dptr(x), _dptr(target), B, H, W, float(h), None,
+                                       ctypes.byref(loss) if want_loss else None))
         self.step += 1
         _check(lib().mgwr_net_adam_step(self._h, float(lr), float(beta1), float(beta2), float(eps), self.step))
-        return loss.value
+        return loss.value if want_loss else None
 
     def close(self):
         if getattr(self, "_h", None):

@@ -76,6 +76,7 @@ struct mgwr_plan {
   int* ff_row = nullptr;
   int* zu_row = nullptr;
   double* a1 = nullptr;
+  double* tpow = nullptr;             // t_m^alpha, m = 0..M (time variable of the warm-start interpolation)
   double* B0 = nullptr;      // f + a_{.,1} g
   double* part = nullptr;    // norm partials
   double* scal = nullptr;    // device scalar(s)
@@ -98,7 +99,8 @@ struct mgwr_plan {
   int* counters = nullptr;
   int* flags_dev = nullptr;            // [0] ticket, [1] abort
   double* norms = nullptr;             // [kMaxPipeCycles][norm_chunks]
-  int khint = 0;                       // cycles the last pipelined solve needed
+  int khint = 0;                       // cycles the last pipelined solve from a zero or given iterate needed
+  int khint_warm = 0;                  // the same from a predicted iterate
   double cycle_flops = 0.0, cycle_bytes = 0.0;  // algorithmic work of one pipelined cycle
   // learned initial guess
   static constexpr int kMaxSlices = 64;
@@ -109,7 +111,7 @@ struct mgwr_plan {
   // offsets computed by layout()
   struct Off {
     size_t stages, counters, flags, norms, wrows, wx;
-    size_t leaves, dn_list, ff_row, zu_row, a1, B0, part, scal;
+    size_t leaves, dn_list, ff_row, zu_row, a1, tm, B0, part, scal;
     size_t dense64, dinv64, ffA64, zuB64, dense32, dinv32, ffA32, zuB32;
     std::vector<size_t> U64, F64, R64, U32, F32, R32;
     size_t total;
@@ -142,6 +144,7 @@ void layout(mgwr_plan* pl) {
   o.ff_row = cv.take(std::max<size_t>(1, pk.ff_row.size()) * sizeof(int));
   o.zu_row = cv.take(std::max<size_t>(1, pk.zu_row.size()) * sizeof(int));
   o.a1 = cv.take((size_t)M * sizeof(double));
+  o.tm = cv.take((size_t)(M + 1) * sizeof(double));
   o.part = cv.take(kNormParts * sizeof(double));
   o.scal = cv.take(16 * sizeof(double));
   o.dense64 = cv.take(pk.dense.size() * sizeof(double));
@@ -203,13 +206,13 @@ struct Timed {
   double flops, bytes;
   hipEvent_t b = nullptr;
   Timed(mgwr_plan* p, int c, double f, double by) : pl(p), cls(c), flops(f), bytes(by) {
-    if (pl->timing && (b = pool_event(pl))) hipEventRecord(b, pl->stream);
+    if (pl->timing && (b = pool_event(pl))) (void)hipEventRecord(b, pl->stream);
   }
   ~Timed() {
     if (!b) return;
     hipEvent_t e = pool_event(pl);
     if (!e) { pl->event_pool.push_back(b); return; }
-    hipEventRecord(e, pl->stream);
+    (void)hipEventRecord(e, pl->stream);
     pl->pending.push_back({b, e, cls, flops, bytes});
   }
 };
@@ -574,9 +577,11 @@ struct mgwr_batch {
 namespace {
 
 // Prepares an instance: b = f + a_1 g, the initial iterate (zero, given, or
-// predicted by the warm-start network with a fall back to zero), ||b||,
-// res0.  `flags` returns with MGWR_GUESS_IN_U set iff u holds a non-zero
-// iterate whose defect is in R64_0.
+// predicted by the warm-start network), ||b||, res0.  `flags` returns with
+// MGWR_GUESS_IN_U set iff u holds a non-zero iterate whose defect is in R64_0.
+// A prediction whose defect is not finite is dropped for the zero iterate
+// here; the solve loops judge a finite one by the true residual after its
+// first cycles (see fall_back_to_zero).
 int prepare_solve(mgwr_plan* pl, const double* f, const double* g, double tol, double* u, unsigned& flags,
                   mgwr_stats& s, const double*& b, int& status) {
   int rc;
@@ -603,12 +608,12 @@ int prepare_solve(mgwr_plan* pl, const double* f, const double* g, double tol, d
                                    pl->netx, pl->stream));
       HIP_TRY(hipStreamSynchronize(pl->stream));
       const float* y = nullptr;
-      if ((rc = net_infer(pl->net, pl->netx, H, W, &y))) return rc;
+      if ((rc = net_infer(pl->net, pl->netx, H, W, hp.levels[0].h, &y))) return rc;
       HIP_TRY(hipStreamSynchronize(net_stream(pl->net)));
-      HIP_TRY(launch_time_interp(y, pl->rows_dev, ns, hp.p.M, N, s.bnorm, u, pl->stream));
+      HIP_TRY(launch_time_interp(y, pl->rows_dev, ns, pl->tpow, g, hp.p.M, N, s.bnorm, u, pl->stream));
       if ((rc = defect<double>(pl, pl->d64, 0, b, u, pl->d64.R[0]))) return rc;
       if ((rc = norm_inf<double>(pl, pl->d64.R[0], MN, &s.warm_res0))) return rc;
-      if (std::isfinite(s.warm_res0) && s.warm_res0 < s.bnorm) {
+      if (std::isfinite(s.warm_res0)) {
         s.used_warm_start = 1;
         flags |= MGWR_GUESS_IN_U;
       }
@@ -633,6 +638,22 @@ int prepare_solve(mgwr_plan* pl, const double* f, const double* g, double tol, d
 
 int batch_fail(int code, const std::string& m) { return fail(code, m); }
 
+// The true-residual judge of a predicted iterate: after the first cycles from
+// it, a residual that is not below ||b|| (the zero iterate's) means the
+// prediction did no better than no prediction at all; the solve then restarts
+// from zero (the cycles spent stay counted).  Returns 1 when it restarted.
+int fall_back_to_zero(mgwr_plan* pl, const double* b, double* u, mgwr_stats& s, int* rc) {
+  *rc = MGWR_OK;
+  if (!s.used_warm_start || s.res < s.bnorm) return 0;
+  const long long MN = (long long)pl->hp.p.M * pl->hp.levels[0].N;
+  s.used_warm_start = 0;
+  s.res = s.res0 = s.bnorm;
+  hipError_t e = launch_fill<double>(u, MN, 0.0, pl->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(pl->d64.R[0], b, MN * sizeof(double), hipMemcpyDeviceToDevice, pl->stream);
+  if (e != hipSuccess) *rc = fail(MGWR_ERR_HIP, std::string("warm-start fall back: ") + hipGetErrorString(e));
+  return 1;
+}
+
 }  // namespace
 
 // Pipelined solve of plans[0..n) (float64) with the stage table, counters,
@@ -643,14 +664,16 @@ int solve_pipelined(mgwr_batch* bt, const double* const* f, const double* const*
   int rc;
   std::vector<mgwr_stats> st(n);
   std::vector<const double*> b(n);
-  std::vector<int> status(n), K(n), conv_at(n, -1);
+  std::vector<int> status(n), K(n), conv_at(n, -1), base(n, 0), judged(n, 0), zero_start(n, 0);
   std::vector<unsigned> fl_i(n, flags);
   for (int i = 0; i < n; ++i) {
     mgwr_plan* pl = bt->plans[i];
     if (!f[i] || !u[i]) return batch_fail(MGWR_ERR_INVALID_ARG, "null array in batch");
     if ((rc = use_device(pl))) return rc;
     if ((rc = prepare_solve(pl, f[i], g ? g[i] : nullptr, tol, u[i], fl_i[i], st[i], b[i], status[i]))) return rc;
-    K[i] = pl->khint > 0 ? pl->khint : 8;
+    const int hint = st[i].used_warm_start ? (pl->khint_warm > 0 ? pl->khint_warm : pl->khint) : pl->khint;
+    K[i] = hint > 0 ? hint : 8;
+    zero_start[i] = !(fl_i[i] & MGWR_GUESS_IN_U);
   }
   // the plans' streams must be complete before the batch stream uses their arrays
   for (int i = 0; i < n; ++i) HIP_TRY(hipStreamSynchronize(bt->plans[i]->stream));
@@ -673,10 +696,11 @@ int solve_pipelined(mgwr_batch* bt, const double* const* f, const double* const*
       K[i] = std::max(1, std::min({K[i], mgwr_plan::kMaxPipeCycles, (pl->hp.p.max_cycles - st[i].cycles) / per}));
       // with a learned step count only the last step's defect is needed (float64
       // cycles); refinement steps need every defect as the next right-hand side
-      const bool every = pl->mixed || !(pl->khint > 0 && st[i].cycles == 0);
+      const int hint = st[i].used_warm_start ? pl->khint_warm : pl->khint;
+      const bool every = pl->mixed || !(hint > 0 && st[i].cycles == 0);
       norms_every[a] = every;
-      build_plan_stages(pl, b[i], u[i], K[i], bt->norms + bt->norm_off[i], lists[a], every,
-                        st[i].cycles == 0 && !(fl_i[i] & MGWR_GUESS_IN_U));
+      build_plan_stages(pl, b[i], u[i], K[i], bt->norms + bt->norm_off[i], lists[a], every, zero_start[i] != 0);
+      zero_start[i] = 0;
       pl->stages_f = nullptr;  // the plan's own uploaded table no longer matches its level-0 pointers
       maxlen = std::max(maxlen, lists[a].size());
       flops += pl->cycle_flops * K[i];
@@ -735,8 +759,8 @@ int solve_pipelined(mgwr_batch* bt, const double* const* f, const double* const*
       bt->tacc.ms[MGWR_K_PIPE64] += ms;
       bt->tacc.flops[MGWR_K_PIPE64] += flops;
       bt->tacc.bytes[MGWR_K_PIPE64] += bytes;
-      hipEventDestroy(e0);
-      hipEventDestroy(e1);
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
     }
     if (fl[1]) return batch_fail(MGWR_ERR_HIP, "pipelined cycles stalled (a progress wait exceeded its bound)");
     for (size_t a = 0; a < act.size(); ++a) {
@@ -758,7 +782,7 @@ int solve_pipelined(mgwr_batch* bt, const double* const* f, const double* const*
         const int done_steps = pl->mixed ? s.refinements : s.cycles;
         const int cyc = norms_every[a] ? done_steps + c : done_steps + K[i] - 1;  // 0-based step of this norm
         if (cyc < 64) s.history[cyc] = r;
-        if (conv_at[i] < 0 && r <= target) conv_at[i] = cyc + 1;
+        if (conv_at[i] < 0 && r <= target) conv_at[i] = cyc + 1 - base[i];
         s.res = r;
       }
       if (pl->mixed) {
@@ -766,6 +790,19 @@ int solve_pipelined(mgwr_batch* bt, const double* const* f, const double* const*
         s.cycles += K[i] * pl->hp.p.inner_cycles;
       } else {
         s.cycles += K[i];
+      }
+      if (!judged[i]) {
+        judged[i] = 1;
+        int frc;
+        if (fall_back_to_zero(pl, b[i], u[i], s, &frc)) {
+          if (frc) return frc;
+          HIP_TRY(hipStreamSynchronize(pl->stream));
+          base[i] = pl->mixed ? s.refinements : s.cycles;
+          conv_at[i] = -1;
+          zero_start[i] = 1;
+          K[i] = pl->khint > 0 ? pl->khint : 8;
+          continue;
+        }
       }
       if (!std::isfinite(s.res)) { status[i] = MGWR_ERR_NONFINITE; continue; }
       if (s.res <= target) { status[i] = MGWR_OK; continue; }
@@ -776,7 +813,7 @@ int solve_pipelined(mgwr_batch* bt, const double* const* f, const double* const*
   int ret = MGWR_OK;
   for (int i = 0; i < n; ++i) {
     mgwr_stats& s = st[i];
-    if (conv_at[i] > 0) bt->plans[i]->khint = conv_at[i];
+    if (conv_at[i] > 0) (s.used_warm_start ? bt->plans[i]->khint_warm : bt->plans[i]->khint) = conv_at[i];
     s.avg_factor = (s.cycles > 0 && s.res0 > 0) ? std::pow(s.res / s.res0, 1.0 / s.cycles) : 0.0;
     if (stats) stats[i] = s;
     if (ret == MGWR_OK && status[i] != MGWR_OK) ret = status[i];
@@ -851,6 +888,7 @@ int mgwr_plan_bind(mgwr_plan* pl, void* ws, size_t bytes, void* stream) {
   pl->ff_row = (int*)(w + o.ff_row);
   pl->zu_row = (int*)(w + o.zu_row);
   pl->a1 = (double*)(w + o.a1);
+  pl->tpow = (double*)(w + o.tm);
   pl->part = (double*)(w + o.part);
   pl->scal = (double*)(w + o.scal);
   pl->B0 = (double*)(w + o.B0);
@@ -883,6 +921,11 @@ int mgwr_plan_bind(mgwr_plan* pl, void* ws, size_t bytes, void* stream) {
   put(o.ff_row, pk.ff_row.data(), pk.ff_row.size() * sizeof(int));
   put(o.zu_row, pk.zu_row.data(), pk.zu_row.size() * sizeof(int));
   put(o.a1, pk.a1.data(), pk.a1.size() * sizeof(double));
+  {
+    std::vector<double> tp(hp.t.size());
+    for (size_t m = 0; m < tp.size(); ++m) tp[m] = std::pow(hp.t[m], hp.p.alpha);
+    put(o.tm, tp.data(), tp.size() * sizeof(double));
+  }
   put(o.dense64, pk.dense.data(), pk.dense.size() * sizeof(double));
   put(o.dinv64, pk.dinv.data(), pk.dinv.size() * sizeof(double));
   put(o.ffA64, pk.ffA.data(), pk.ffA.size() * sizeof(double));
@@ -1003,6 +1046,10 @@ int mgwr_solve(mgwr_plan* pl, const double* f, const double* g, double tol, doub
       if ((rc = defect<double>(pl, pl->d64, 0, b, u, pl->d64.R[0]))) return rc;
       if ((rc = norm_inf<double>(pl, pl->d64.R[0], MN, &s.res))) return rc;
       if (s.cycles <= 64) s.history[s.cycles - 1] = s.res;
+      if (s.cycles == 1 && fall_back_to_zero(pl, b, u, s, &rc)) {
+        if (rc) return rc;
+        continue;
+      }
       if (!std::isfinite(s.res)) { status = MGWR_ERR_NONFINITE; break; }
       if (s.res <= target) { status = MGWR_OK; break; }
     }
@@ -1025,6 +1072,11 @@ int mgwr_solve(mgwr_plan* pl, const double* f, const double* g, double tol, doub
       if ((rc = defect<double>(pl, pl->d64, 0, b, u, pl->d64.R[0]))) return rc;
       if ((rc = norm_inf<double>(pl, pl->d64.R[0], MN, &s.res))) return rc;
       if (s.refinements <= 64) s.history[s.refinements - 1] = s.res;
+      if (s.refinements == 1 && fall_back_to_zero(pl, b, u, s, &rc)) {
+        if (rc) return rc;
+        HIP_TRY(launch_cast<double, float>(b, pl->d32.F[0], MN, pl->stream));
+        continue;
+      }
       if (!std::isfinite(s.res)) { status = MGWR_ERR_NONFINITE; break; }
       if (s.res <= target) { status = MGWR_OK; break; }
       HIP_TRY(launch_cast<double, float>(pl->d64.R[0], pl->d32.F[0], MN, pl->stream));
@@ -1092,8 +1144,12 @@ int mgwr_plan_set_warm_start(mgwr_plan* pl, mgwr_net* net, int nslices, const in
   const HostPlan& hp = pl->hp;
   if (nslices < 1 || nslices > mgwr_plan::kMaxSlices || !rows)
     return fail(MGWR_ERR_INVALID_ARG, "nslices must lie in [1, 64] with a row list");
-  if (net_in_channels(net) != nslices + 2 || net_out_channels(net) != nslices)
-    return fail(MGWR_ERR_INVALID_ARG, "network channels must be nslices + 2 in and nslices out");
+  if (net_signal_channels(net) != nslices || net_input_channels(net) != nslices + 2 || net_out_channels(net) != nslices)
+    return fail(MGWR_ERR_INVALID_ARG, "the network must take nslices signal + 2 extra channels and give nslices");
+  const int n0 = hp.levels[0].n;
+  if (((n0 + 1) & n0) != 0 || n0 < 3)
+    return fail(MGWR_ERR_INVALID_ARG, "a warm start needs n = 2^p - 1 points per side");
+  if (net_capacity(net) < hp.levels[0].N) return fail(MGWR_ERR_STATE, "the network must be bound for >= N points");
   for (int i = 0; i < nslices; ++i)
     if (rows[i] < 0 || rows[i] >= hp.p.M || (i > 0 && rows[i] <= rows[i - 1]))
       return fail(MGWR_ERR_INVALID_ARG, "slice rows must increase within [0, M)");
@@ -1139,10 +1195,10 @@ int mgwr_plan_export_dense(const mgwr_plan* pl, double* Rt) {
 int mgwr_plan_destroy(mgwr_plan* pl) {
   if (!pl) return MGWR_OK;
   if (pl->bound && !pl->pending.empty()) {
-    hipStreamSynchronize(pl->stream);
+    (void)hipStreamSynchronize(pl->stream);
     drain_timing(pl);
   }
-  for (hipEvent_t e : pl->event_pool) hipEventDestroy(e);
+  for (hipEvent_t e : pl->event_pool) (void)hipEventDestroy(e);
   delete pl;
   return MGWR_OK;
 }

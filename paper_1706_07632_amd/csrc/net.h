@@ -8,15 +8,17 @@
 #include "mgwr.h"
 
 namespace mgwr {
-// Forward pass of one instance (batch 1) on the network's buffers; *y points
-// at the output activations [c_L][H][W].
-int net_infer(mgwr_net* net, const float* x, int H, int W, const float** y);
-int net_in_channels(const mgwr_net* net);
+// Forward pass of one instance (batch 1, fine-grid spacing h) on the
+// network's buffers; *y points at the output [c_L][H][W].
+int net_infer(mgwr_net* net, const float* x, int H, int W, double h, const float** y);
+int net_signal_channels(const mgwr_net* net);
+int net_input_channels(const mgwr_net* net);
 int net_out_channels(const mgwr_net* net);
+long long net_capacity(const mgwr_net* net);
 hipStream_t net_stream(const mgwr_net* net);
 hipError_t launch_gather_slices(const double* b, const int* rows, int nslices, long long N, double scale,
                                 float alpha, float rdiv, float* x, hipStream_t s);
-hipError_t launch_time_interp(const float* y, const int* rows, int nslices, long long M, long long N, double scale,
-                              double* u, hipStream_t s);
+hipError_t launch_time_interp(const float* y, const int* rows, int nslices, const double* t, const double* g,
+                              long long M, long long N, double scale, double* u, hipStream_t s);
 void set_last_error(const std::string& msg);
 }  // namespace mgwr

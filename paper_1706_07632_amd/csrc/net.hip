@@ -1,14 +1,25 @@
-// Learned initial guess: a small convolution network on the gfx950, with
-// hand-written forward, backward and Adam kernels.
+// Learned initial guess: a convolution network applied band by band to a
+// spatial pyramid, with hand-written forward, backward and Adam kernels for
+// the gfx950.
 //
-// Layers l = 0..L-1: 3x3 convolution (zero padding, stride 1) from c_l to
-// c_{l+1} channels, tanh after every layer but the last.  Tensors are
-// [batch][channel][H][W] float32; a 1D grid is an image of height 1.  The
-// forward pass and the data gradient use bfloat16 copies of the weights
-// (refreshed after every update) with float32 accumulation; the master
-// weights, their gradients and the Adam moments are float32.
+// Input x [B][S + E][H][W]: S signal channels and E extra channels (H = 1 for
+// a 1D grid, else H = W; W = 2^p - 1).  The signal is split into bands over
+// the grid hierarchy n_0 = W, n_{l+1} = (n_l - 1) / 2 (down to 3 points):
+//   c_0 = signal,  c_{l+1} = R c_l (full weighting),
+//   band_l = c_l - P c_{l+1} (P 4-point interpolation),  band_last = c_last,
+// so that sum_l P^l band_l = signal.  At every level the same stack of 3x3
+// convolutions (zero padding, tanh between layers, none after the last) maps
+// [band_l, extra channels sampled at the level's points, log2(1/h_l)/10] to
+// out_l, and the output is
+//   y = sum_l P^l (4 h_l^2 out_l),   h_l = 2^l h_0,
+// the factor h_l^2 carrying the scale of the inverse of a second-order
+// operator on the band's grid.  The forward pass and the data gradient use
+// bfloat16 copies of the convolution weights (biases stay float32) with
+// float32 accumulation; master weights, gradients and Adam moments are
+// float32.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -30,116 +41,333 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
   return (uint16_t)(u >> 16);
 }
 
-// y[b][co][p] = bias[co] + sum_ci sum_k w[co][ci][k] x[b][ci][p + off(k)], optional tanh
-__global__ void conv_fwd_kernel(const float* __restrict__ x, const uint16_t* __restrict__ w,
-                                const float* __restrict__ bias, float* __restrict__ y, int B, int cin, int cout,
-                                int H, int W, int act) {
-  const long long HW = (long long)H * W;
-  const long long total = (long long)B * cout * HW;
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
-       idx += (long long)gridDim.x * blockDim.x) {
-    const long long p = idx % HW;
-    const int co = (int)((idx / HW) % cout);
-    const int b = (int)(idx / (HW * cout));
-    const int py = (int)(p / W), px = (int)(p % W);
-    float acc = bias[co];
-    const float* xb = x + (long long)b * cin * HW;
-    const uint16_t* wc = w + (long long)co * cin * 9;
-    for (int ci = 0; ci < cin; ++ci) {
-      const float* xc = xb + ci * HW;
-      const uint16_t* wk = wc + ci * 9;
+constexpr int kCoTile = 8;  // output (forward) or input (data gradient) channels per thread
+
+// Forward convolution.  Grid: x = pixel blocks of 256 over B*H*W, y = groups
+// of kCoTile output channels (uniform per block, so weight reads are uniform).
+// y[b][co][p] = bias[co] + sum_ci sum_k w[co][ci][k] x[b][ci][p + off(k)]
+__global__ __launch_bounds__(256) void conv_fwd_kernel(const float* __restrict__ x, const uint16_t* __restrict__ w,
+                                                       const float* __restrict__ bias, float* __restrict__ y, int B,
+                                                       int cin, int cout, int H, int W, int act) {
+  const int HW = H * W;
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  const int co0 = blockIdx.y * kCoTile;
+  if (t >= (long long)B * HW) return;
+  const int b = (int)(t / HW), p = (int)(t % HW);
+  const int py = p / W, px = p % W;
+  int off[9];
+  bool ok[9];
 #pragma unroll
-      for (int ky = 0; ky < 3; ++ky) {
-        const int yy = py + ky - 1;
-        if (yy < 0 || yy >= H) continue;
+  for (int k = 0; k < 9; ++k) {
+    const int yy = py + k / 3 - 1, xx = px + k % 3 - 1;
+    ok[k] = yy >= 0 && yy < H && xx >= 0 && xx < W;
+    off[k] = ok[k] ? yy * W + xx : 0;
+  }
+  float acc[kCoTile];
 #pragma unroll
-        for (int kx = 0; kx < 3; ++kx) {
-          const int xx = px + kx - 1;
-          if (xx < 0 || xx >= W) continue;
-          acc += bf16_to_f32(wk[ky * 3 + kx]) * xc[(long long)yy * W + xx];
-        }
+  for (int j = 0; j < kCoTile; ++j) acc[j] = co0 + j < cout ? bias[co0 + j] : 0.0f;
+  const float* xb = x + (long long)b * cin * HW;
+  for (int ci = 0; ci < cin; ++ci) {
+    float xv[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) xv[k] = ok[k] ? xb[(long long)ci * HW + off[k]] : 0.0f;
+#pragma unroll
+    for (int j = 0; j < kCoTile; ++j) {
+      if (co0 + j < cout) {
+        const uint16_t* wk = w + ((long long)(co0 + j) * cin + ci) * 9;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc[j] += bf16_to_f32(wk[k]) * xv[k];
       }
     }
-    y[idx] = act ? tanhf(acc) : acc;
+  }
+  float* yb = y + (long long)b * cout * HW + p;
+#pragma unroll
+  for (int j = 0; j < kCoTile; ++j)
+    if (co0 + j < cout) yb[(long long)(co0 + j) * HW] = act ? tanhf(acc[j]) : acc[j];
+}
+
+// Data gradient.  Grid: x = pixel blocks, y = groups of kCoTile input channels.
+// dx[b][ci][p] = sum_co sum_k w[co][ci][k] dy[b][co][p - off(k)], times
+// (1 - a^2) when the layer's input is the tanh output a of the previous layer.
+__global__ __launch_bounds__(256) void conv_bwd_data_kernel(const float* __restrict__ dy,
+                                                            const uint16_t* __restrict__ w,
+                                                            const float* __restrict__ a_prev, float* __restrict__ dx,
+                                                            int B, int cin, int cout, int H, int W, int act_prev) {
+  const int HW = H * W;
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  const int ci0 = blockIdx.y * kCoTile;
+  if (t >= (long long)B * HW) return;
+  const int b = (int)(t / HW), p = (int)(t % HW);
+  const int py = p / W, px = p % W;
+  int off[9];
+  bool ok[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const int yy = py - (k / 3 - 1), xx = px - (k % 3 - 1);
+    ok[k] = yy >= 0 && yy < H && xx >= 0 && xx < W;
+    off[k] = ok[k] ? yy * W + xx : 0;
+  }
+  float acc[kCoTile];
+#pragma unroll
+  for (int j = 0; j < kCoTile; ++j) acc[j] = 0.0f;
+  const float* db = dy + (long long)b * cout * HW;
+  for (int co = 0; co < cout; ++co) {
+    float dv[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) dv[k] = ok[k] ? db[(long long)co * HW + off[k]] : 0.0f;
+#pragma unroll
+    for (int j = 0; j < kCoTile; ++j) {
+      if (ci0 + j < cin) {
+        const uint16_t* wk = w + ((long long)co * cin + ci0 + j) * 9;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc[j] += bf16_to_f32(wk[k]) * dv[k];
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kCoTile; ++j) {
+    if (ci0 + j < cin) {
+      const long long idx = ((long long)b * cin + ci0 + j) * HW + p;
+      float v = acc[j];
+      if (act_prev) {
+        const float a = a_prev[idx];
+        v *= 1.0f - a * a;
+      }
+      dx[idx] = v;
+    }
   }
 }
 
-// dx[b][ci][p] = sum_co sum_k w[co][ci][k] dy[b][co][p - off(k)]; times (1 - a^2)
-// when the input of this layer is the tanh output a of the previous layer
-__global__ void conv_bwd_data_kernel(const float* __restrict__ dy, const uint16_t* __restrict__ w,
-                                     const float* __restrict__ a_prev, float* __restrict__ dx, int B, int cin,
-                                     int cout, int H, int W, int act_prev) {
-  const long long HW = (long long)H * W;
-  const long long total = (long long)B * cin * HW;
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
-       idx += (long long)gridDim.x * blockDim.x) {
-    const long long p = idx % HW;
-    const int ci = (int)((idx / HW) % cin);
-    const int b = (int)(idx / (HW * cin));
-    const int py = (int)(p / W), px = (int)(p % W);
-    float acc = 0.0f;
-    const float* db = dy + (long long)b * cout * HW;
-    for (int co = 0; co < cout; ++co) {
-      const float* dc = db + co * HW;
-      const uint16_t* wk = w + ((long long)co * cin + ci) * 9;
+constexpr int kWgCo = 4;  // output channels per block of the weight gradient
+
+__device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
-      for (int ky = 0; ky < 3; ++ky) {
-        const int yy = py - (ky - 1);
-        if (yy < 0 || yy >= H) continue;
-#pragma unroll
-        for (int kx = 0; kx < 3; ++kx) {
-          const int xx = px - (kx - 1);
-          if (xx < 0 || xx >= W) continue;
-          acc += bf16_to_f32(wk[ky * 3 + kx]) * dc[(long long)yy * W + xx];
-        }
-      }
-    }
-    if (act_prev) {
-      const float a = a_prev[idx];
-      acc *= 1.0f - a * a;
-    }
-    dx[idx] = acc;
-  }
+  for (int s = 32; s > 0; s >>= 1) v += __shfl_xor(v, s, 64);
+  return v;
 }
 
-// dw[co][ci][k] = sum_{b,p} dy[b][co][p] x[b][ci][p + off(k)]  (one block per weight),
-// db[co] = sum_{b,p} dy[b][co][p]  (blocks with ci == cin)
+// Weight gradient, accumulated (+=) into dw and dbias.  One block per
+// (group of kWgCo output channels, input channel):
+//   dw[co][ci][k] += sum_{b,p} dy[b][co][p] x[b][ci][p + off(k)],
+//   dbias[co]     += sum_{b,p} dy[b][co][p]   (blocks with ci == 0).
 __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(const float* __restrict__ dy,
                                                               const float* __restrict__ x, float* __restrict__ dw,
                                                               float* __restrict__ dbias, int B, int cin, int cout,
                                                               int H, int W) {
-  __shared__ float red[256];
-  const int blk = blockIdx.x;  // co * (cin*9 + 1) + j
-  const int per = cin * 9 + 1;
-  const int co = blk / per, j = blk % per;
-  const long long HW = (long long)H * W;
+  constexpr int NV = kWgCo * 10;
+  __shared__ float red[4][NV];
+  const int ci = blockIdx.x % cin;
+  const int co0 = (blockIdx.x / cin) * kWgCo;
+  const int HW = H * W;
   const long long total = (long long)B * HW;
-  float acc = 0.0f;
-  if (j == cin * 9) {
-    for (long long t = threadIdx.x; t < total; t += blockDim.x) {
-      const long long b = t / HW, p = t % HW;
-      acc += dy[(b * cout + co) * HW + p];
+  float acc[NV];
+#pragma unroll
+  for (int j = 0; j < NV; ++j) acc[j] = 0.0f;
+  for (long long t = threadIdx.x; t < total; t += 256) {
+    const int b = (int)(t / HW), p = (int)(t % HW);
+    const int py = p / W, px = p % W;
+    const float* xc = x + ((long long)b * cin + ci) * HW;
+    float xv[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const int yy = py + k / 3 - 1, xx = px + k % 3 - 1;
+      xv[k] = (yy >= 0 && yy < H && xx >= 0 && xx < W) ? xc[yy * W + xx] : 0.0f;
     }
-  } else {
-    const int ci = j / 9, k = j % 9, ky = k / 3, kx = k % 3;
-    for (long long t = threadIdx.x; t < total; t += blockDim.x) {
-      const long long b = t / HW, p = t % HW;
-      const int py = (int)(p / W), px = (int)(p % W);
-      const int yy = py + ky - 1, xx = px + kx - 1;
-      if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
-      acc += dy[(b * cout + co) * HW + p] * x[(b * cin + ci) * HW + (long long)yy * W + xx];
+#pragma unroll
+    for (int j = 0; j < kWgCo; ++j) {
+      const float d = co0 + j < cout ? dy[((long long)b * cout + co0 + j) * HW + p] : 0.0f;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) acc[j * 10 + k] += d * xv[k];
+      acc[j * 10 + 9] += d;
     }
   }
-  red[threadIdx.x] = acc;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    const float s = wave_sum(acc[j]);
+    if (lane == 0) red[wv][j] = s;
+  }
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
+  if (threadIdx.x < NV) {
+    const int j = threadIdx.x / 10, k = threadIdx.x % 10;
+    const int co = co0 + j;
+    if (co < cout) {
+      const float s = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+      if (k < 9) dw[((long long)co * cin + ci) * 9 + k] += s;
+      else if (ci == 0) dbias[co] += s;
+    }
   }
-  if (threadIdx.x == 0) {
-    if (j == cin * 9) dbias[co] = red[0];
-    else dw[(long long)co * cin * 9 + j] = red[0];
+}
+
+// Grid of n points per side onto the next coarser one: coarse point i sits on
+// fine point 2i + 1.  Full weighting, (1/4)[1 2 1] per dimension.
+// dst [B][C][HWc] from src[b * sbs + c * HWf + ...]
+__global__ void pyr_restrict_kernel(const float* __restrict__ src, long long sbs, float* __restrict__ dst, int B,
+                                    int C, int nf, int two_d) {
+  const int nc = (nf - 1) / 2;
+  const int HWc = (two_d ? nc : 1) * nc;
+  const int HWf = (two_d ? nf : 1) * nf;
+  const long long total = (long long)B * C * HWc;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int q = (int)(idx % HWc);
+    const long long bc = idx / HWc;
+    const int c = (int)(bc % C), b = (int)(bc / C);
+    const int i = q / nc, j = q % nc;
+    const float* s = src + b * sbs + (long long)c * HWf;
+    const int fj = 2 * j + 1;
+    float v;
+    if (two_d) {
+      const int fi = 2 * i + 1;
+      const float* r0 = s + (long long)(fi - 1) * nf;
+      const float* r1 = r0 + nf;
+      const float* r2 = r1 + nf;
+      v = 0.0625f * (r0[fj - 1] + 2.0f * r0[fj] + r0[fj + 1]) + 0.125f * (r1[fj - 1] + 2.0f * r1[fj] + r1[fj + 1]) +
+          0.0625f * (r2[fj - 1] + 2.0f * r2[fj] + r2[fj + 1]);
+    } else {
+      v = 0.25f * (s[fj - 1] + 2.0f * s[fj] + s[fj + 1]);
+    }
+    dst[idx] = v;
   }
+}
+
+// Interpolation P from a coarse grid (nc points per side) to the next finer
+// one, per dimension: a fine point on coarse point i takes its value; a fine
+// point halfway between coarse i-1 and i takes the 4-point (cubic) value
+// (-c_{i-2} + 9 c_{i-1} + 9 c_i - c_{i+1}) / 16, where the coarse values are
+// extended by the zero boundary values (c_{-1} = c_{nc} = 0) and their odd
+// reflections (c_{-2} = -c_0, c_{nc+1} = -c_{nc-1}), as grid functions with
+// homogeneous Dirichlet data are.  Sine modes are reproduced up to the factor
+// (9 cos(theta/2) - cos(3 theta/2)) / 8.
+__device__ __forceinline__ float p4_ext(const float* __restrict__ r, int nc, int j) {
+  if (j >= 0 && j < nc) return r[j];
+  if (j == -1 || j == nc) return 0.0f;
+  return j < 0 ? -r[0] : -r[nc - 1];
+}
+__device__ __forceinline__ float p4_row(const float* __restrict__ r, int nc, int fj) {
+  if (fj & 1) return r[(fj - 1) >> 1];
+  const int i = fj >> 1;
+  return (9.0f * (p4_ext(r, nc, i - 1) + p4_ext(r, nc, i)) - (p4_ext(r, nc, i - 2) + p4_ext(r, nc, i + 1))) *
+         0.0625f;
+}
+// row ri of the coarse grid (extended like the values of one row) at fine column fj
+__device__ __forceinline__ float p4_rowsel(const float* __restrict__ c, int nc, int ri, int fj) {
+  if (ri >= 0 && ri < nc) return p4_row(c + (long long)ri * nc, nc, fj);
+  if (ri == -1 || ri == nc) return 0.0f;
+  return -p4_row(c + (long long)(ri < 0 ? 0 : nc - 1) * nc, nc, fj);
+}
+__device__ __forceinline__ float prolong_at(const float* __restrict__ c, int nc, int fi, int fj, int two_d) {
+  if (!two_d) return p4_row(c, nc, fj);
+  if (fi & 1) return p4_row(c + (long long)((fi - 1) >> 1) * nc, nc, fj);
+  const int i = fi >> 1;
+  return (9.0f * (p4_rowsel(c, nc, i - 1, fj) + p4_rowsel(c, nc, i, fj)) -
+          (p4_rowsel(c, nc, i - 2, fj) + p4_rowsel(c, nc, i + 1, fj))) *
+         0.0625f;
+}
+
+// Weights of coarse point i in the fine points (1D): P^T collects
+// fine 2i+1 (1), 2i and 2i+2 (9/16), 2i-2 and 2i+4 (-1/16), and through the
+// odd reflections fine 0 (+1/16 more, i = 0) and fine 2nc (+1/16 more, i = nc-1).
+__device__ __forceinline__ int p4_adj_taps(int i, int nc, int* f, float* w) {
+  int k = 0;
+  const int nf = 2 * nc + 1;
+  auto add = [&](int fi, float wi) {
+    if (fi >= 0 && fi < nf) { f[k] = fi; w[k] = wi; ++k; }
+  };
+  add(2 * i - 2, -0.0625f);
+  add(2 * i, i == 0 ? 0.625f : 0.5625f);
+  add(2 * i + 1, 1.0f);
+  add(2 * i + 2, i == nc - 1 ? 0.625f : 0.5625f);
+  add(2 * i + 4, -0.0625f);
+  return k;
+}
+
+// Level input [B][S + E + 1][HW_l]: the band (S channels), the extra channels
+// of x sampled at the level's points, the level value.  sig[b * sbs + c * HW_l]
+// is this level's signal, sig_next [B][S][HW_{l+1}] the next one (null at the
+// coarsest level); x the fine input [B][S + E][HW_0].
+__global__ void pyr_input_kernel(const float* __restrict__ sig, long long sbs, const float* __restrict__ sig_next,
+                                 const float* __restrict__ x, float* __restrict__ xin, int B, int S, int E, int n,
+                                 int n0, int stride, int two_d, float lval) {
+  const int HW = (two_d ? n : 1) * n;
+  const int HW0 = (two_d ? n0 : 1) * n0;
+  const int C0 = S + E + 1;
+  const int nc = (n - 1) / 2;
+  const int HWc = (two_d ? nc : 1) * nc;
+  const long long total = (long long)B * C0 * HW;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int q = (int)(idx % HW);
+    const long long bc = idx / HW;
+    const int c = (int)(bc % C0), b = (int)(bc / C0);
+    const int i = q / n, j = q % n;
+    float v;
+    if (c < S) {
+      v = sig[b * sbs + (long long)c * HW + q];
+      if (sig_next) v -= prolong_at(sig_next + ((long long)b * S + c) * HWc, nc, i, j, two_d);
+    } else if (c < S + E) {
+      const int fi = two_d ? stride * (i + 1) - 1 : 0, fj = stride * (j + 1) - 1;
+      v = x[((long long)b * (S + E) + c) * HW0 + (long long)fi * n0 + fj];
+    } else {
+      v = lval;
+    }
+    xin[idx] = v;
+  }
+}
+
+// Y_l = s * out_l + P Y_{l+1}  (Y_next null at the coarsest level, out null
+// for a level the network leaves out)
+__global__ void pyr_combine_kernel(const float* __restrict__ out, const float* __restrict__ ynext,
+                                   float* __restrict__ y, int BC, int n, int two_d, float s) {
+  const int HW = (two_d ? n : 1) * n;
+  const int nc = (n - 1) / 2;
+  const int HWc = (two_d ? nc : 1) * nc;
+  const long long total = (long long)BC * HW;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int q = (int)(idx % HW);
+    const long long bc = idx / HW;
+    float v = out ? s * out[idx] : 0.0f;
+    if (ynext) v += prolong_at(ynext + bc * HWc, nc, q / n, q % n, two_d);
+    y[idx] = v;
+  }
+}
+
+// Adjoint of the interpolation, g_c = P^T g_f (taps of p4_adj_taps per dimension).
+__global__ void pyr_prolong_adj_kernel(const float* __restrict__ gf, float* __restrict__ gc, int BC, int nf,
+                                       int two_d) {
+  const int nc = (nf - 1) / 2;
+  const int HWc = (two_d ? nc : 1) * nc;
+  const int HWf = (two_d ? nf : 1) * nf;
+  const long long total = (long long)BC * HWc;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int q = (int)(idx % HWc);
+    const long long bc = idx / HWc;
+    const int i = q / nc, j = q % nc;
+    const float* g = gf + bc * HWf;
+    int fj[5], fi[5];
+    float wj[5], wi[5];
+    const int kj = p4_adj_taps(j, nc, fj, wj);
+    float v = 0.0f;
+    if (two_d) {
+      const int ki = p4_adj_taps(i, nc, fi, wi);
+      for (int a = 0; a < ki; ++a) {
+        const float* r = g + (long long)fi[a] * nf;
+        float rs = 0.0f;
+        for (int b = 0; b < kj; ++b) rs += wj[b] * r[fj[b]];
+        v += wi[a] * rs;
+      }
+    } else {
+      for (int b = 0; b < kj; ++b) v += wj[b] * g[fj[b]];
+    }
+    gc[idx] = v;
+  }
+}
+
+__global__ void scale_kernel(const float* __restrict__ x, float* __restrict__ y, long long n, float s) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    y[i] = s * x[i];
 }
 
 // per-sample ||t_b||^2 and ||y_b - t_b||^2 (one block per sample)
@@ -201,7 +429,7 @@ __global__ void round_bf16_kernel(const float* __restrict__ p, uint16_t* __restr
     wbf[i] = f32_to_bf16(p[i]);
 }
 
-// Input channels of the warm start for one instance: f at the slice rows
+// Input channels of the warm start for one instance: b at the slice rows
 // divided by `scale`, then constant channels alpha and r / 10.
 __global__ void gather_slices_kernel(const double* __restrict__ b, const int* __restrict__ rows, int nslices,
                                      long long N, double scale, float alpha, float rdiv, float* __restrict__ x) {
@@ -217,11 +445,13 @@ __global__ void gather_slices_kernel(const double* __restrict__ b, const int* __
   }
 }
 
-// u[m][q] = scale * linear interpolation in the row index of the predicted
-// slices (value 0 at row -1, i.e. at t = 0 for a zero initial value; constant
-// after the last slice row)
+// u[m][q] = interpolation of the predicted slices (times scale), piecewise
+// linear in the variable s = t^alpha (tp[m] = t_m^alpha): slice k sits at
+// tp[rows[k] + 1].  Before the first slice it runs from the initial value g
+// (zero if null) at tp[0]; after the last slice it stays constant.
 __global__ void time_interp_kernel(const float* __restrict__ y, const int* __restrict__ rows, int nslices,
-                                   long long M, long long N, double scale, double* __restrict__ u) {
+                                   const double* __restrict__ t, const double* __restrict__ g, long long M,
+                                   long long N, double scale, double* __restrict__ u) {
   const long long total = M * N;
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
        idx += (long long)gridDim.x * blockDim.x) {
@@ -229,15 +459,15 @@ __global__ void time_interp_kernel(const float* __restrict__ y, const int* __res
     int s = 0;
     while (s < nslices && rows[s] < m) ++s;
     double v;
-    if (s == nslices) v = y[(long long)(nslices - 1) * N + q];
-    else if (rows[s] == m) v = y[(long long)s * N + q];
+    if (s == nslices) v = scale * y[(long long)(nslices - 1) * N + q];
+    else if (rows[s] == m) v = scale * y[(long long)s * N + q];
     else {
-      const double r0 = s == 0 ? -1.0 : (double)rows[s - 1];
-      const double y0 = s == 0 ? 0.0 : (double)y[(long long)(s - 1) * N + q];
-      const double r1 = rows[s], y1 = y[(long long)s * N + q];
-      v = y0 + (y1 - y0) * ((double)m - r0) / (r1 - r0);
+      const double ta = s == 0 ? t[0] : t[rows[s - 1] + 1];
+      const double ya = s == 0 ? (g ? g[q] : 0.0) : scale * y[(long long)(s - 1) * N + q];
+      const double tb = t[rows[s] + 1], yb = scale * y[(long long)s * N + q];
+      v = ya + (yb - ya) * (t[m + 1] - ta) / (tb - ta);
     }
-    u[idx] = scale * v;
+    u[idx] = v;
   }
 }
 
@@ -253,9 +483,10 @@ hipError_t launch_gather_slices(const double* b, const int* rows, int nslices, l
   return hipGetLastError();
 }
 
-hipError_t launch_time_interp(const float* y, const int* rows, int nslices, long long M, long long N, double scale,
-                              double* u, hipStream_t s) {
-  hipLaunchKernelGGL(time_interp_kernel, dim3(grid_of(M * N)), dim3(256), 0, s, y, rows, nslices, M, N, scale, u);
+hipError_t launch_time_interp(const float* y, const int* rows, int nslices, const double* t, const double* g,
+                              long long M, long long N, double scale, double* u, hipStream_t s) {
+  hipLaunchKernelGGL(time_interp_kernel, dim3(grid_of(M * N)), dim3(256), 0, s, y, rows, nslices, t, g, M, N, scale,
+                     u);
   return hipGetLastError();
 }
 
@@ -273,39 +504,83 @@ int nfail(int code, const std::string& m) {
     hipError_t e_ = (__VA_ARGS__);                                                                \
     if (e_ != hipSuccess) return nfail(MGWR_ERR_HIP, std::string(#__VA_ARGS__) + ": " + hipGetErrorString(e_)); \
   } while (0)
+
+// Pyramid geometry of one call.
+struct Geo {
+  int B, H, W, two_d, nlev;
+  std::vector<int> n;         // points per side at each level
+  std::vector<long long> hw;  // points per level
+  std::vector<long long> cum; // sum of hw over the finer levels
+};
+
+bool geometry(int B, int H, int W, Geo* g) {
+  if (B < 1 || W < 3 || ((W + 1) & W) != 0 || !(H == 1 || H == W)) return false;
+  g->B = B;
+  g->H = H;
+  g->W = W;
+  g->two_d = H == W ? 1 : 0;
+  g->n.clear();
+  g->hw.clear();
+  g->cum.clear();
+  long long acc = 0;
+  for (int n = W; n >= 3; n = (n - 1) / 2) {
+    g->n.push_back(n);
+    const long long hw = (long long)(g->two_d ? n : 1) * n;
+    g->cum.push_back(acc);
+    g->hw.push_back(hw);
+    acc += hw;
+  }
+  g->nlev = (int)g->n.size();
+  return true;
+}
 }  // namespace
 
 struct mgwr_net {
-  std::vector<int> ch;              // channels c_0..c_L
+  std::vector<int> ch;              // convolution channels c_0..c_L (c_0 = S + E + 1)
+  int nsig = 0, nextra = 0;
   std::vector<size_t> woff, boff;   // parameter offsets (floats)
   size_t nparam = 0;
-  long long cap_bhw = 0;            // capacity of the bound activation buffers (batch*H*W)
+  long long cap = 0;                // bound capacity: batch * H * W of the finest level
   int maxc = 0;
   bool bound = false;
   hipStream_t stream = nullptr;
   float* params = nullptr;          // caller-owned master weights
   uint16_t* wbf = nullptr;
   float *grad = nullptr, *m = nullptr, *v = nullptr;
-  std::vector<float*> act;          // act[l]: output of layer l (l = 0..L-1), [cap_bhw * c_{l+1}]
-  float *gbuf0 = nullptr, *gbuf1 = nullptr;
-  double* norms = nullptr;          // per-sample loss norms (cap 4096 samples)
-  size_t total = 0;
-  long long layout(long long bhw, std::vector<size_t>* offs) const {
+  float *sig = nullptr, *xin = nullptr, *ybuf = nullptr, *gy = nullptr;  // per-level arenas
+  std::vector<float*> act;          // act[j]: output of layer j at every level
+  float *g0 = nullptr, *g1 = nullptr;  // backprop scratch of one level [cap * maxc]
+  double* norms = nullptr;          // per-sample loss norms
+  double h_min = 0.0;               // levels with h_l < h_min contribute nothing
+  static constexpr int kMaxBatch = 4096;
+
+  // a level takes part when its spacing is not finer than h_min
+  bool active(double hl) const { return hl >= h_min * (1.0 - 1e-9); }
+
+  int L() const { return (int)ch.size() - 1; }
+  int in_channels() const { return nsig + nextra; }
+
+  long long layout(long long cap_, std::vector<size_t>* offs) const {
     size_t off = 0;
     auto take = [&](size_t bytes) {
       size_t o = off;
       off += (bytes + 255) & ~size_t(255);
       return o;
     };
+    const size_t P = (size_t)2 * cap_;  // all levels of a pyramid fit in twice the finest
     std::vector<size_t> o;
-    o.push_back(take(nparam * 2));        // wbf
-    o.push_back(take(nparam * 4));        // grad
-    o.push_back(take(nparam * 4));        // m
-    o.push_back(take(nparam * 4));        // v
-    for (size_t l = 0; l + 1 < ch.size(); ++l) o.push_back(take((size_t)bhw * ch[l + 1] * 4));
-    o.push_back(take((size_t)bhw * maxc * 4));
-    o.push_back(take((size_t)bhw * maxc * 4));
-    o.push_back(take(4096 * 2 * sizeof(double)));
+    o.push_back(take(nparam * 2));                      // 0 wbf
+    o.push_back(take(nparam * 4));                      // 1 grad
+    o.push_back(take(nparam * 4));                      // 2 m
+    o.push_back(take(nparam * 4));                      // 3 v
+    o.push_back(take(P * nsig * 4));                    // 4 sig
+    o.push_back(take(P * ch[0] * 4));                   // 5 xin
+    o.push_back(take(P * ch.back() * 4));               // 6 ybuf
+    o.push_back(take(P * ch.back() * 4));               // 7 gy
+    o.push_back(take((size_t)cap_ * maxc * 4));         // 8 g0
+    o.push_back(take((size_t)cap_ * maxc * 4));         // 9 g1
+    o.push_back(take(kMaxBatch * 2 * sizeof(double)));  // 10 norms
+    for (int j = 0; j < L(); ++j) o.push_back(take(P * ch[j + 1] * 4));  // 11 + j act
     if (offs) *offs = o;
     return (long long)off;
   }
@@ -313,45 +588,91 @@ struct mgwr_net {
 
 namespace {
 
-// Forward pass; activations of every layer stay in net->act.
-int net_forward(mgwr_net* net, const float* x, int B, int H, int W) {
-  const int L = (int)net->ch.size() - 1;
-  const float* in = x;
-  for (int l = 0; l < L; ++l) {
-    const long long total = (long long)B * net->ch[l + 1] * H * W;
-    hipLaunchKernelGGL(conv_fwd_kernel, dim3(grid_of(total)), dim3(256), 0, net->stream, in,
-                       net->wbf + net->woff[l], net->params + net->boff[l], net->act[l], B, net->ch[l], net->ch[l + 1],
-                       H, W, l + 1 < L ? 1 : 0);
+int check_net(mgwr_net* net, int B, int H, int W, Geo* g) {
+  if (!net || !net->bound) return nfail(MGWR_ERR_STATE, "network is not bound");
+  if (B > mgwr_net::kMaxBatch) return nfail(MGWR_ERR_INVALID_ARG, "batch exceeds 4096");
+  if (!geometry(B, H, W, g))
+    return nfail(MGWR_ERR_INVALID_ARG, "grid must have W = 2^p - 1 >= 3 points with H = 1 or H = W");
+  if ((long long)B * H * W > net->cap) return nfail(MGWR_ERR_INVALID_ARG, "batch*H*W exceeds the bound capacity");
+  return MGWR_OK;
+}
+
+int launch_conv_fwd(mgwr_net* net, int j, const float* in, float* out, int B, int H, int W) {
+  const int cin = net->ch[j], cout = net->ch[j + 1];
+  const long long px = (long long)B * H * W;
+  dim3 grid((unsigned)((px + 255) / 256), (unsigned)((cout + kCoTile - 1) / kCoTile));
+  hipLaunchKernelGGL(conv_fwd_kernel, grid, dim3(256), 0, net->stream, in, net->wbf + net->woff[j],
+                     net->params + net->boff[j], out, B, cin, cout, H, W, j + 1 < net->L() ? 1 : 0);
+  NET_TRY(hipGetLastError());
+  return MGWR_OK;
+}
+
+// Forward pass of the whole pyramid; leaves the activations of every level in
+// the arenas and the output in level 0 of ybuf.
+int net_forward(mgwr_net* net, const float* x, const Geo& g, double h0) {
+  const int B = g.B, S = net->nsig, E = net->nextra, C0 = net->ch[0], CL = net->ch.back();
+  const long long HW0 = g.hw[0];
+  int rc;
+  // the signal of level l: x itself at level 0, the sig arena below
+  auto sig_at = [&](int l) -> const float* { return l == 0 ? x : net->sig + (size_t)B * S * g.cum[l]; };
+  auto sig_bs = [&](int l) -> long long { return l == 0 ? (long long)(S + E) * HW0 : (long long)S * g.hw[l]; };
+  for (int l = 0; l + 1 < g.nlev; ++l) {
+    float* dst = net->sig + (size_t)B * S * g.cum[l + 1];
+    hipLaunchKernelGGL(pyr_restrict_kernel, dim3(grid_of((long long)B * S * g.hw[l + 1])), dim3(256), 0,
+                       net->stream, sig_at(l), sig_bs(l), dst, B, S, g.n[l], g.two_d);
     NET_TRY(hipGetLastError());
-    in = net->act[l];
+  }
+  for (int l = 0; l < g.nlev; ++l) {
+    const int Hl = g.two_d ? g.n[l] : 1, Wl = g.n[l];
+    const float* sn = l + 1 < g.nlev ? net->sig + (size_t)B * S * g.cum[l + 1] : nullptr;
+    float* xin = net->xin + (size_t)B * C0 * g.cum[l];
+    const double hl = std::ldexp(h0, l);
+    if (!net->active(hl)) continue;
+    hipLaunchKernelGGL(pyr_input_kernel, dim3(grid_of((long long)B * C0 * g.hw[l])), dim3(256), 0, net->stream,
+                       sig_at(l), sig_bs(l), sn, x, xin, B, S, E, g.n[l], g.W, 1 << l, g.two_d,
+                       (float)(std::log2(1.0 / hl) / 10.0));
+    NET_TRY(hipGetLastError());
+    const float* in = xin;
+    for (int j = 0; j < net->L(); ++j) {
+      float* out = net->act[j] + (size_t)B * net->ch[j + 1] * g.cum[l];
+      if ((rc = launch_conv_fwd(net, j, in, out, B, Hl, Wl))) return rc;
+      in = out;
+    }
+  }
+  for (int l = g.nlev - 1; l >= 0; --l) {
+    const double hl = std::ldexp(h0, l);
+    const float* out = net->active(hl) ? net->act[net->L() - 1] + (size_t)B * CL * g.cum[l] : nullptr;
+    const float* yn = l + 1 < g.nlev ? net->ybuf + (size_t)B * CL * g.cum[l + 1] : nullptr;
+    float* y = net->ybuf + (size_t)B * CL * g.cum[l];
+    hipLaunchKernelGGL(pyr_combine_kernel, dim3(grid_of((long long)B * CL * g.hw[l])), dim3(256), 0, net->stream,
+                       out, yn, y, B * CL, g.n[l], g.two_d, (float)(4.0 * hl * hl));
+    NET_TRY(hipGetLastError());
   }
   return MGWR_OK;
 }
 
-int check_net(mgwr_net* net, int B, int H, int W) {
-  if (!net || !net->bound) return nfail(MGWR_ERR_STATE, "network is not bound");
-  if (B < 1 || H < 1 || W < 1 || (long long)B * H * W > net->cap_bhw || B > 4096)
-    return nfail(MGWR_ERR_INVALID_ARG, "batch*H*W exceeds the bound capacity");
-  return MGWR_OK;
-}
+bool valid_h(double h) { return std::isfinite(h) && h > 0.0; }
 
 }  // namespace
 
 extern "C" {
 
-int mgwr_net_create(int layers, const int* channels, mgwr_net** out) {
+int mgwr_net_create(int layers, const int* channels, int nsignal, mgwr_net** out) {
   if (!out || !channels || layers < 1 || layers > 16) return nfail(MGWR_ERR_INVALID_ARG, "bad network shape");
   *out = nullptr;
+  for (int l = 0; l <= layers; ++l)
+    if (channels[l] < 1 || channels[l] > 1024)
+      return nfail(MGWR_ERR_INVALID_ARG, "channel counts must lie in [1, 1024]");
+  if (nsignal < 1 || nsignal > channels[0] - 1)
+    return nfail(MGWR_ERR_INVALID_ARG, "nsignal must lie in [1, channels[0] - 1]");
   mgwr_net* net = new (std::nothrow) mgwr_net();
   if (!net) return nfail(MGWR_ERR_INVALID_ARG, "out of host memory");
   for (int l = 0; l <= layers; ++l) {
-    if (channels[l] < 1 || channels[l] > 1024) {
-      delete net;
-      return nfail(MGWR_ERR_INVALID_ARG, "channel counts must lie in [1, 1024]");
-    }
     net->ch.push_back(channels[l]);
     net->maxc = std::max(net->maxc, channels[l]);
   }
+  net->nsig = nsignal;
+  net->nextra = channels[0] - 1 - nsignal;
   size_t off = 0;
   for (int l = 0; l < layers; ++l) {
     net->woff.push_back(off);
@@ -378,6 +699,7 @@ int mgwr_net_workspace_bytes(const mgwr_net* net, long long max_bhw, size_t* byt
 
 int mgwr_net_bind(mgwr_net* net, float* params_dev, long long max_bhw, void* ws, size_t bytes, void* stream) {
   if (!net || !params_dev || !ws || max_bhw < 1) return nfail(MGWR_ERR_INVALID_ARG, "bad argument");
+  if (((uintptr_t)ws & 255) != 0) return nfail(MGWR_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
   std::vector<size_t> o;
   const long long need = net->layout(max_bhw, &o);
   if ((long long)bytes < need) return nfail(MGWR_ERR_STATE, "workspace too small");
@@ -388,14 +710,16 @@ int mgwr_net_bind(mgwr_net* net, float* params_dev, long long max_bhw, void* ws,
   net->grad = (float*)(w + o[1]);
   net->m = (float*)(w + o[2]);
   net->v = (float*)(w + o[3]);
-  const int L = (int)net->ch.size() - 1;
-  net->act.assign(L, nullptr);
-  for (int l = 0; l < L; ++l) net->act[l] = (float*)(w + o[4 + l]);
-  net->gbuf0 = (float*)(w + o[4 + L]);
-  net->gbuf1 = (float*)(w + o[5 + L]);
-  net->norms = (double*)(w + o[6 + L]);
-  net->cap_bhw = max_bhw;
-  net->total = (size_t)need;
+  net->sig = (float*)(w + o[4]);
+  net->xin = (float*)(w + o[5]);
+  net->ybuf = (float*)(w + o[6]);
+  net->gy = (float*)(w + o[7]);
+  net->g0 = (float*)(w + o[8]);
+  net->g1 = (float*)(w + o[9]);
+  net->norms = (double*)(w + o[10]);
+  net->act.assign(net->L(), nullptr);
+  for (int j = 0; j < net->L(); ++j) net->act[j] = (float*)(w + o[11 + j]);
+  net->cap = max_bhw;
   NET_TRY(hipMemsetAsync(net->m, 0, net->nparam * 4, net->stream));
   NET_TRY(hipMemsetAsync(net->v, 0, net->nparam * 4, net->stream));
   hipLaunchKernelGGL(round_bf16_kernel, dim3(grid_of((long long)net->nparam)), dim3(256), 0, net->stream,
@@ -414,44 +738,66 @@ int mgwr_net_sync_weights(mgwr_net* net) {
   return MGWR_OK;
 }
 
-int mgwr_net_forward(mgwr_net* net, const float* x, int B, int H, int W, float* y) {
-  int rc = check_net(net, B, H, W);
+int mgwr_net_forward(mgwr_net* net, const float* x, int B, int H, int W, double h, float* y) {
+  Geo g;
+  int rc = check_net(net, B, H, W, &g);
   if (rc) return rc;
   if (!x || !y) return nfail(MGWR_ERR_INVALID_ARG, "null array");
-  if ((rc = net_forward(net, x, B, H, W))) return rc;
-  const int L = (int)net->ch.size() - 1;
-  NET_TRY(hipMemcpyAsync(y, net->act[L - 1], (size_t)B * net->ch[L] * H * W * 4, hipMemcpyDeviceToDevice,
+  if (!valid_h(h)) return nfail(MGWR_ERR_INVALID_ARG, "h must be positive");
+  if ((rc = net_forward(net, x, g, h))) return rc;
+  NET_TRY(hipMemcpyAsync(y, net->ybuf, (size_t)B * net->ch.back() * g.hw[0] * 4, hipMemcpyDeviceToDevice,
                          net->stream));
   return MGWR_OK;
 }
 
-int mgwr_net_gradient(mgwr_net* net, const float* x, const float* target, int B, int H, int W, float* grad_out,
-                      double* loss_host) {
-  int rc = check_net(net, B, H, W);
+int mgwr_net_gradient(mgwr_net* net, const float* x, const float* target, int B, int H, int W, double h,
+                      float* grad_out, double* loss_host) {
+  Geo g;
+  int rc = check_net(net, B, H, W, &g);
   if (rc) return rc;
   if (!x || !target) return nfail(MGWR_ERR_INVALID_ARG, "null array");
-  if ((rc = net_forward(net, x, B, H, W))) return rc;
-  const int L = (int)net->ch.size() - 1;
-  const long long HW = (long long)H * W;
-  const long long per = (long long)net->ch[L] * HW;
-  hipLaunchKernelGGL(loss_norms_kernel, dim3(B), dim3(256), 0, net->stream, net->act[L - 1], target, per, net->norms);
+  if (!valid_h(h)) return nfail(MGWR_ERR_INVALID_ARG, "h must be positive");
+  if ((rc = net_forward(net, x, g, h))) return rc;
+  const int L = net->L(), CL = net->ch.back(), C0 = net->ch[0];
+  const long long per = (long long)CL * g.hw[0];
+  hipLaunchKernelGGL(loss_norms_kernel, dim3(B), dim3(256), 0, net->stream, net->ybuf, target, per, net->norms);
   NET_TRY(hipGetLastError());
-  hipLaunchKernelGGL(loss_grad_kernel, dim3(grid_of(B * per)), dim3(256), 0, net->stream, net->act[L - 1], target,
-                     net->norms, net->gbuf0, B, per, 1e-30);
+  hipLaunchKernelGGL(loss_grad_kernel, dim3(grid_of(B * per)), dim3(256), 0, net->stream, net->ybuf, target,
+                     net->norms, net->gy, B, per, 1e-30);
   NET_TRY(hipGetLastError());
-  float* dcur = net->gbuf0;
-  float* dnext = net->gbuf1;
-  for (int l = L - 1; l >= 0; --l) {
-    const float* in = l == 0 ? x : net->act[l - 1];
-    const int cin = net->ch[l], cout = net->ch[l + 1];
-    hipLaunchKernelGGL(conv_bwd_weight_kernel, dim3(cout * (cin * 9 + 1)), dim3(256), 0, net->stream, dcur, in,
-                       net->grad + net->woff[l], net->grad + net->boff[l], B, cin, cout, H, W);
-    NET_TRY(hipGetLastError());
+  NET_TRY(hipMemsetAsync(net->grad, 0, net->nparam * 4, net->stream));
+  for (int l = 0; l < g.nlev; ++l) {
+    const int Hl = g.two_d ? g.n[l] : 1, Wl = g.n[l];
+    float* gyl = net->gy + (size_t)B * CL * g.cum[l];
     if (l > 0) {
-      hipLaunchKernelGGL(conv_bwd_data_kernel, dim3(grid_of((long long)B * cin * HW)), dim3(256), 0, net->stream,
-                         dcur, net->wbf + net->woff[l], net->act[l - 1], dnext, B, cin, cout, H, W, 1);
+      const float* gyp = net->gy + (size_t)B * CL * g.cum[l - 1];
+      hipLaunchKernelGGL(pyr_prolong_adj_kernel, dim3(grid_of((long long)B * CL * g.hw[l])), dim3(256), 0,
+                         net->stream, gyp, gyl, B * CL, g.n[l - 1], g.two_d);
       NET_TRY(hipGetLastError());
-      std::swap(dcur, dnext);
+    }
+    const double hl = std::ldexp(h, l);
+    if (!net->active(hl)) continue;
+    const long long cnt = (long long)B * CL * g.hw[l];
+    hipLaunchKernelGGL(scale_kernel, dim3(grid_of(cnt)), dim3(256), 0, net->stream, gyl, net->g0, cnt,
+                       (float)(4.0 * hl * hl));
+    NET_TRY(hipGetLastError());
+    float* dcur = net->g0;
+    float* dnext = net->g1;
+    for (int j = L - 1; j >= 0; --j) {
+      const int cin = net->ch[j], cout = net->ch[j + 1];
+      const float* in = j == 0 ? net->xin + (size_t)B * C0 * g.cum[l] : net->act[j - 1] + (size_t)B * cin * g.cum[l];
+      const int nblk = ((cout + kWgCo - 1) / kWgCo) * cin;
+      hipLaunchKernelGGL(conv_bwd_weight_kernel, dim3(nblk), dim3(256), 0, net->stream, dcur, in,
+                         net->grad + net->woff[j], net->grad + net->boff[j], B, cin, cout, Hl, Wl);
+      NET_TRY(hipGetLastError());
+      if (j > 0) {
+        const long long px = (long long)B * Hl * Wl;
+        dim3 grid((unsigned)((px + 255) / 256), (unsigned)((cin + kCoTile - 1) / kCoTile));
+        hipLaunchKernelGGL(conv_bwd_data_kernel, grid, dim3(256), 0, net->stream, dcur, net->wbf + net->woff[j], in,
+                           dnext, B, cin, cout, Hl, Wl, 1);
+        NET_TRY(hipGetLastError());
+        std::swap(dcur, dnext);
+      }
     }
   }
   if (grad_out)
@@ -464,6 +810,13 @@ int mgwr_net_gradient(mgwr_net* net, const float* x, const float* target, int B,
     for (int b = 0; b < B; ++b) lsum += nh[2 * b + 1] / (nh[2 * b] + 1e-30);
     *loss_host = lsum / B;
   }
+  return MGWR_OK;
+}
+
+int mgwr_net_set_finest(mgwr_net* net, double h_min) {
+  if (!net) return nfail(MGWR_ERR_INVALID_ARG, "null network");
+  if (!(h_min >= 0.0) || !std::isfinite(h_min)) return nfail(MGWR_ERR_INVALID_ARG, "h_min must be >= 0");
+  net->h_min = h_min;
   return MGWR_OK;
 }
 
@@ -484,16 +837,20 @@ int mgwr_net_destroy(mgwr_net* net) {
 
 }  // extern "C"
 
-// internal: forward pass for the solver's warm start (x, y are net buffers)
+// internal: forward pass for the solver's warm start
 namespace mgwr {
-int net_infer(mgwr_net* net, const float* x, int H, int W, const float** y) {
-  int rc = check_net(net, 1, H, W);
+int net_infer(mgwr_net* net, const float* x, int H, int W, double h, const float** y) {
+  Geo g;
+  int rc = check_net(net, 1, H, W, &g);
   if (rc) return rc;
-  if ((rc = net_forward(net, x, 1, H, W))) return rc;
-  *y = net->act[net->ch.size() - 2];
+  if (!valid_h(h)) return nfail(MGWR_ERR_INVALID_ARG, "h must be positive");
+  if ((rc = net_forward(net, x, g, h))) return rc;
+  *y = net->ybuf;
   return MGWR_OK;
 }
-int net_in_channels(const mgwr_net* net) { return net->ch.front(); }
+int net_signal_channels(const mgwr_net* net) { return net->nsig; }
+int net_input_channels(const mgwr_net* net) { return net->in_channels(); }
 int net_out_channels(const mgwr_net* net) { return net->ch.back(); }
+long long net_capacity(const mgwr_net* net) { return net->bound ? net->cap : 0; }
 hipStream_t net_stream(const mgwr_net* net) { return net->stream; }
 }  // namespace mgwr

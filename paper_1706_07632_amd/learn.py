@@ -1,0 +1,231 @@
+"""Training and use of the learned initial guess.
+
+The network (Net, a band-pyramid stack of 3x3 convolutions run by the
+library's own kernels) maps the right-hand side at `nslices` time rows, plus
+the constant channels alpha and r/10, to the solution at those rows.  Its
+training data are solutions that the solver itself computes (plain float64
+MGWR to a tight tolerance) on seeded instances of
+`workloads.warm_start_family`; training runs the library's forward, backward
+and Adam kernels.  In a solve the prediction is interpolated in time and
+judged by the method's own float64 residual (MGWR_WARM_START).
+
+Command line (on a GPU):
+    python -m paper_1706_07632_amd.learn --dim 1 --n 255 --M 1024 --count 512 \
+        --steps 3000 --out weights.npz
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import Net, Plan
+
+NSLICES = 32
+HIDDEN = 64
+LAYERS = 4
+
+
+def slice_rows(M: int, nslices: int = NSLICES) -> list[int]:
+    """Time rows of the network's slices: rows s*M/nslices - 1, s = 1..nslices
+    (the last one is the final time level)."""
+    if M < nslices:
+        raise ValueError("M must be at least the number of slices")
+    return [s * M // nslices - 1 for s in range(1, nslices + 1)]
+
+
+def channels(nslices: int = NSLICES, hidden: int = HIDDEN, layers: int = LAYERS) -> list[int]:
+    """[slices + alpha + r/10 + level value, hidden..., slices]."""
+    return [nslices + 3] + [hidden] * (layers - 1) + [nslices]
+
+
+def make_net(max_bhw: int, nslices: int = NSLICES, hidden: int = HIDDEN, layers: int = LAYERS, seed: int = 0):
+    return Net(channels(nslices, hidden, layers), nslices, max_bhw, seed=seed)
+
+
+def grid_shape(dim: int, n: int):
+    return (1, n) if dim == 1 else (n, n)
+
+
+def generate(dim: int, n: int, M: int, count: int, seed: int, tol: float = 1e-10, k: int = 10,
+             nslices: int = NSLICES, log=None):
+    """Solver-generated samples: X [count][nslices+2][H][W] (f at the slice
+    rows over ||f||_inf, alpha, r/10) and Y [count][nslices][H][W] (the
+    float64 MGWR solution at those rows over ||f||_inf), float32 on the GPU."""
+    import torch
+    import workloads as W
+    H, Wd = grid_shape(dim, n)
+    rows = slice_rows(M, nslices)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    X = torch.empty((count, nslices + 2, H, Wd), dtype=torch.float32, device=dev)
+    Y = torch.empty((count, nslices, H, Wd), dtype=torch.float32, device=dev)
+    ridx = torch.tensor(rows, device=dev)
+    cycles = []
+    t0 = time.time()
+    for i in range(count):
+        p = W.warm_start_family(dim, n, M, np.random.default_rng([seed, i]), k=k)
+        plan = Plan(dim, n, M, p.alpha, k=p.k, r=p.r, t=p.t).bind()
+        f = torch.as_tensor(p.f, dtype=torch.float64, device=dev)
+        u, st = plan.solve(f, tol=tol)
+        scale = f.abs().max()
+        X[i, :nslices] = (f.index_select(0, ridx) / scale).reshape(nslices, H, Wd).float()
+        X[i, nslices] = p.alpha
+        X[i, nslices + 1] = p.r / 10.0
+        Y[i] = (u.index_select(0, ridx) / scale).reshape(nslices, H, Wd).float()
+        cycles.append(st["cycles"])
+        plan.close()
+        if log and (i + 1) % max(1, count // 8) == 0:
+            log(f"generated {i + 1}/{count} samples ({time.time() - t0:.1f} s)")
+    return X, Y, cycles
+
+
+def train(net, X, Y, h: float, steps: int, batch: int = 16, lr: float = 1e-3, lr_end: float = 1e-5,
+          seed: int = 0, log=None, log_every: int = 250):
+    """Adam with a cosine learning-rate decay on random minibatches."""
+    import torch
+    g = torch.Generator(device=X.device)
+    g.manual_seed(seed)
+    losses = []
+    t0 = time.time()
+    for it in range(steps):
+        idx = torch.randint(0, X.shape[0], (batch,), device=X.device, generator=g)
+        xb = X.index_select(0, idx).contiguous()
+        yb = Y.index_select(0, idx).contiguous()
+        cur = lr_end + 0.5 * (lr - lr_end) * (1 + math.cos(math.pi * it / max(1, steps)))
+        want = (it % log_every == 0) or it == steps - 1
+        loss = net.train_step(xb, yb, h, lr=cur, want_loss=want)
+        if want:
+            losses.append((it, loss))
+            if log:
+                log(f"step {it} loss {loss:.4e} lr {cur:.2e} ({time.time() - t0:.1f} s)")
+    return losses
+
+
+def evaluate_loss(net, X, Y, h: float, batch: int = 16) -> float:
+    tot, cnt = 0.0, 0
+    for s in range(0, X.shape[0], batch):
+        xb, yb = X[s:s + batch].contiguous(), Y[s:s + batch].contiguous()
+        loss, _ = net.gradient(xb, yb, h)
+        tot += loss * xb.shape[0]
+        cnt += xb.shape[0]
+    return tot / max(1, cnt)
+
+
+def gain(net, problems, tol: float = 1e-8, precision: str = "fp64", repeats: int = 2, log=None):
+    """Cycles and solve times with the zero iterate and with the warm start on
+    `problems` (workloads.Problem); each form is solved `repeats` times on the
+    same plan and the last solve counts (it runs with the cycle count the
+    earlier ones learned)."""
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device())
+    rows = []
+    for p in problems:
+        plan = Plan(p.dim, p.n, p.M, p.alpha, k=p.k, r=p.r, t=p.t, precision=precision).bind()
+        attach(plan, net)
+        f = torch.as_tensor(p.f, dtype=torch.float64, device=dev)
+        out = {}
+        for form, ws in (("zero", False), ("warm", True)):
+            for _ in range(repeats):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, st = plan.solve(f, tol=tol, warm_start=ws)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+            out[form] = {"cycles": st["cycles"], "seconds": dt, "rel_res": st["res"] / st["bnorm"],
+                         "used_warm_start": st["used_warm_start"], "warm_res0": st["warm_res0"] / st["bnorm"]}
+        rows.append(out)
+        plan.close()
+        if log:
+            log(f"alpha={p.alpha:.3f}: zero {out['zero']['cycles']} cycles {out['zero']['seconds'] * 1e3:.1f} ms, "
+                f"warm {out['warm']['cycles']} cycles {out['warm']['seconds'] * 1e3:.1f} ms "
+                f"(accepted {out['warm']['used_warm_start']}, res0/||b|| {out['warm']['warm_res0']:.2e})")
+    return rows
+
+
+def save(net, path: str, meta: dict):
+    params = net.params.detach().float().cpu().numpy()
+    np.savez(path, params=params, channels=np.array(net.channels, dtype=np.int32),
+             nsignal=np.array(net.nsignal, dtype=np.int32), meta=np.array(json.dumps(meta)))
+
+
+def load(path: str, max_bhw: int):
+    """(Net with the stored weights, metadata dict); bands finer than the
+    training grid are left out."""
+    with np.load(path, allow_pickle=False) as z:
+        params = z["params"]
+        ch = [int(c) for c in z["channels"]]
+        nsig = int(z["nsignal"])
+        meta = json.loads(str(z["meta"]))
+    net = Net(ch, nsig, max_bhw)
+    net.set_params(params)
+    net.set_finest(meta.get("h_min", 0.0))
+    return net, meta
+
+
+def attach(plan, net, nslices: int = NSLICES):
+    """Attach `net` to `plan` for warm-started solves at the plan's slice rows."""
+    plan.set_warm_start(net, slice_rows(plan.M, nslices))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--dim", type=int, default=1)
+    ap.add_argument("--n", type=int, default=255)
+    ap.add_argument("--M", type=int, default=1024)
+    ap.add_argument("--count", type=int, default=512)
+    ap.add_argument("--val", type=int, default=32)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--eval-n", type=int, default=0, help="held-out evaluation grid (0: skip)")
+    ap.add_argument("--eval-M", type=int, default=0)
+    ap.add_argument("--eval-count", type=int, default=4)
+    a = ap.parse_args(argv)
+    import torch
+
+    def log(msg):
+        print(msg, flush=True)
+
+    H, Wd = grid_shape(a.dim, a.n)
+    h = 1.0 / (a.n + 1)
+    log(f"generating {a.count} + {a.val} samples: dim={a.dim} n={a.n} M={a.M}")
+    X, Y, cyc = generate(a.dim, a.n, a.M, a.count, a.seed, log=log)
+    Xv, Yv, _ = generate(a.dim, a.n, a.M, a.val, a.seed + 1000)
+    log(f"solver cycles per sample: mean {np.mean(cyc):.2f}")
+    net = make_net(max(a.batch, 16) * H * Wd, seed=a.seed)
+    losses = train(net, X, Y, h, a.steps, a.batch, a.lr, log=log)
+    vloss = evaluate_loss(net, Xv, Yv, h)
+    log(f"validation loss {vloss:.4e}")
+    meta = {"dim": a.dim, "n": a.n, "M": a.M, "count": a.count, "seed": a.seed, "steps": a.steps,
+            "batch": a.batch, "lr": a.lr, "final_train_loss": losses[-1][1], "val_loss": vloss,
+            "family": "workloads.warm_start_family", "nslices": NSLICES, "h_min": h}
+    os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
+    save(net, a.out, meta)
+    log(json.dumps(meta))
+    if a.eval_n:
+        import workloads as W
+        probs = [W.warm_start_family(a.dim, a.eval_n, a.eval_M, np.random.default_rng([100001, i]))
+                 for i in range(a.eval_count)]
+        big = make_net(a.eval_n ** a.dim, seed=0)
+        big.set_params(net.params.detach().cpu().numpy())
+        big.set_finest(h)
+        for precision in ("fp64", "mixed"):
+            log(f"held-out gain at n={a.eval_n} M={a.eval_M} ({precision})")
+            rows = gain(big, probs, precision=precision, log=log)
+            z = sum(r["zero"]["seconds"] for r in rows)
+            w = sum(r["warm"]["seconds"] for r in rows)
+            log(f"total: zero {sum(r['zero']['cycles'] for r in rows)} cycles {z:.3f} s, warm "
+                f"{sum(r['warm']['cycles'] for r in rows)} cycles {w:.3f} s, speed-up {z / w:.3f}")
+    torch.cuda.synchronize()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -31,6 +31,7 @@ __all__ = [
     "paper_2d_polynomial",
     "random_fourier_2d",
     "batched_instances",
+    "warm_start_family",
     "config",
 ]
 
@@ -195,6 +196,35 @@ def batched_instances(count: int = 64, seed: int = 20261203, sides=(63, 127, 255
         else:
             out.append((n, M, alpha))
     return out
+
+
+def warm_start_family(dim: int, n: int, M: int, rng: np.random.Generator, alpha_range=(0.2, 0.9),
+                      nmodes: int = 6, kmax: int = 16, k: int = 10) -> Problem:
+    """Training and evaluation family of the learned initial guess: alpha ~
+    U(alpha_range), r = (2 - alpha)/alpha, zero initial data on (0, 1)^dim,
+    T = 1, and a source made of `nmodes` distinct sine modes (wave numbers in
+    {1..kmax}^dim, mode 1 always present) with time profiles
+    a * Gamma(1 + alpha) + c * t^alpha, a ~ U(0, 1), c ~ N(0, 1), both divided by
+    1 + |kvec|^2.  The manufactured sources of the benchmark workloads (one mode,
+    a = 1, c = pi^2 dim) lie in its span."""
+    alpha = float(rng.uniform(*alpha_range))
+    r = default_grading(alpha)
+    t = graded_mesh(M, 1.0, r)
+    total = kmax ** dim
+    flat = np.concatenate([[0], 1 + rng.choice(total - 1, size=nmodes - 1, replace=False)])
+    a = rng.uniform(0.0, 1.0, nmodes)
+    c = rng.standard_normal(nmodes)
+    tt = t[1:] ** alpha
+    f = np.zeros((M, n ** dim))
+    modes = []
+    for idx, ai, ci in zip(flat, a, c):
+        kvec = tuple(int(idx // kmax ** d % kmax) + 1 for d in range(dim))
+        w = 1.0 + sum(kk * kk for kk in kvec)
+        prof = (ai * math.gamma(1 + alpha) + ci * tt) / w
+        f += np.outer(prof, sine_mode(n, dim, 1.0, kvec))
+        modes.append((kvec, prof))
+    return Problem(dim=dim, n=n, M=M, alpha=alpha, r=r, k=k, t=t, f=f, modes=modes,
+                   name=f"warm{dim}d_n{n}_M{M}_a{alpha:.3f}")
 
 
 def config(name: str, alpha: float | None = None) -> Problem:
