@@ -212,6 +212,25 @@ int mgwr_batch_solve(mgwr_batch* batch, const double* const* f_dev, const double
  * on, 0 turns it off, -1 leaves it unchanged. */
 int mgwr_batch_timing(mgwr_batch* batch, int enable, mgwr_timing* out);
 int mgwr_batch_destroy(mgwr_batch* batch);
+/* Graph replay of the batched launch (off by default).  When on, a launch
+ * whose stage table, counters and grid equal the previous one's (the same
+ * plans and arrays solved again with the learned cycle counts) is replayed
+ * from a captured HIP graph (fill kernels + pipeline kernel, no memset
+ * nodes) instead of being re-uploaded and re-launched; any change recaptures. */
+int mgwr_batch_set_graph(mgwr_batch* batch, int enable);
+/* Number of graph replays so far (host). */
+int mgwr_batch_graph_replays(const mgwr_batch* batch, long long* replays);
+
+/* Autotuner of the schedule (staged launches per operator, or whole cycles
+ * time-pipelined in one launch): solves f twice with each schedule (the
+ * second solve of each runs with the cycle count the first one learned),
+ * keeps the faster for this plan and for every MGWR_SCHED_AUTO plan of the
+ * same (dim, n, M, precision, inner cycles, k) created in this process, and
+ * returns it in *chosen (nullable).  u receives the solution.  A batch runs
+ * its pipelined instances in one merged launch and its staged ones one
+ * after another. */
+int mgwr_plan_autotune(mgwr_plan* plan, const double* f_dev, const double* g_dev, double tol, double* u_dev,
+                       int* chosen);
 
 /* Learned initial guess.  Not part of the paper's method, which starts its
  * iteration from a given iterate: this network only proposes that iterate,

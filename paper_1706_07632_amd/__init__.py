@@ -33,7 +33,7 @@ EXPORTED = [
     "mgwr_net_create", "mgwr_net_param_count", "mgwr_net_workspace_bytes", "mgwr_net_bind",
     "mgwr_net_sync_weights", "mgwr_net_forward", "mgwr_net_gradient", "mgwr_net_set_finest",
     "mgwr_net_adam_step", "mgwr_net_destroy",
-    "mgwr_plan_set_warm_start",
+    "mgwr_plan_set_warm_start", "mgwr_batch_set_graph", "mgwr_batch_graph_replays", "mgwr_plan_autotune",
 ]
 
 KERNEL_CLASSES = ["smooth64", "defect64", "smooth32", "defect32", "restrict", "prolong", "pipe64"]
@@ -120,6 +120,9 @@ def lib():
                                    ctypes.POINTER(vp), ctypes.c_uint, ctypes.POINTER(Stats)]
     L.mgwr_batch_timing.argtypes = [vp, ip, ctypes.POINTER(Timing)]
     L.mgwr_batch_destroy.argtypes = [vp]
+    L.mgwr_batch_set_graph.argtypes = [vp, ip]
+    L.mgwr_batch_graph_replays.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong)]
+    L.mgwr_plan_autotune.argtypes = [vp, vp, vp, ctypes.c_double, vp, ctypes.POINTER(ctypes.c_int)]
     L.mgwr_net_create.argtypes = [ip, ctypes.POINTER(ctypes.c_int), ip, ctypes.POINTER(vp)]
     L.mgwr_net_param_count.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
     L.mgwr_net_workspace_bytes.argtypes = [vp, ctypes.c_longlong, ctypes.POINTER(ctypes.c_size_t)]
@@ -239,6 +242,19 @@ class Plan:
         self.device = dev
         return self
 
+    def autotune(self, f, g=None, tol=1e-8, u=None):
+        """Measure both schedules on f and keep the faster (also for later
+        plans of the same shape); returns "staged" or "pipelined"."""
+        import torch
+        _require(f, "f", (self.M, self.N))
+        if g is not None:
+            _require(g, "g", (self.N,))
+        if u is None:
+            u = torch.empty_like(f)
+        chosen = ctypes.c_int()
+        _check(lib().mgwr_plan_autotune(self._h, _dptr(f), _dptr(g), float(tol), _dptr(u), ctypes.byref(chosen)))
+        return {1: "staged", 2: "pipelined"}[chosen.value]
+
     def set_warm_start(self, net, rows):
         """Attach a bound Net as the initial-guess predictor (rows: the time
         rows of its input/output slices)."""
@@ -317,15 +333,26 @@ class Plan:
 
 
 class Batch:
-    """Several bound plans solved together in merged time-pipelined launches."""
+    """Several bound plans solved together: the instances with a pipelined
+    schedule in one merged launch (replayed from a HIP graph when `graph`
+    is on and nothing changed), the others one after another."""
 
-    def __init__(self, plans):
+    def __init__(self, plans, graph=False):
         self.plans = list(plans)
         arr = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
         h = ctypes.c_void_p()
         _check(lib().mgwr_batch_create(len(self.plans), arr, ctypes.byref(h)))
         self._h = h
         self._ws = None
+        self.set_graph(graph)
+
+    def set_graph(self, enable):
+        _check(lib().mgwr_batch_set_graph(self._h, 1 if enable else 0))
+
+    def graph_replays(self):
+        n = ctypes.c_longlong()
+        _check(lib().mgwr_batch_graph_replays(self._h, ctypes.byref(n)))
+        return n.value
 
     def bind(self, stream=None):
         import torch

@@ -4,10 +4,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "hplan.h"
@@ -101,6 +105,7 @@ struct mgwr_plan {
   double* norms = nullptr;             // [kMaxPipeCycles][norm_chunks]
   int khint = 0;                       // cycles the last pipelined solve from a zero or given iterate needed
   int khint_warm = 0;                  // the same from a predicted iterate
+  int tuned = 0;                       // schedule measured best by mgwr_plan_autotune (0: none)
   double cycle_flops = 0.0, cycle_bytes = 0.0;  // algorithmic work of one pipelined cycle
   // learned initial guess
   static constexpr int kMaxSlices = 64;
@@ -518,10 +523,27 @@ void assign_offsets(std::vector<Stage>& st) {
 // pipelined schedule wins (measured: 1D n=1023 pipelines 9x faster, 2D n=255
 // with 2032 chains is faster staged).
 constexpr int kAutoPipelineChains = 256;
+// Schedules measured by mgwr_plan_autotune, shared by every plan of the same
+// shape in the process: (dim, n, M, precision, inner cycles, k) -> schedule.
+using TuneKey = std::tuple<int, int, int, int, int, int>;
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tuned;
+
+TuneKey tune_key(const mgwr_plan* pl) {
+  const mgwr_params& p = pl->hp.p;
+  return TuneKey(p.dim, p.n, p.M, p.precision, p.inner_cycles, p.k);
+}
+
 bool use_pipeline(const mgwr_plan* pl) {
   const int sched = pl->hp.p.schedule;
   if (sched == MGWR_SCHED_PIPELINED) return true;
   if (sched == MGWR_SCHED_STAGED) return false;
+  if (pl->tuned) return pl->tuned == MGWR_SCHED_PIPELINED;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(tune_key(pl));
+    if (it != g_tuned.end()) return it->second == MGWR_SCHED_PIPELINED;
+  }
   return (pl->hp.levels[0].N + 31) / 32 <= kAutoPipelineChains;
 }
 
@@ -572,6 +594,26 @@ struct mgwr_batch {
   size_t lds = 0;
   bool timing = false;
   mgwr_timing tacc{};
+  // replay of an unchanged launch (stage table, counters, grid) as a HIP graph
+  bool use_graph = false;
+  std::vector<Stage> graph_stages;     // the table the captured graph runs
+  long long graph_ncnt = 0;
+  int graph_ntasks = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  hipStream_t capture_stream = nullptr;  // private (the caller's may be the legacy stream, which cannot capture)
+  long long graph_replays = 0;
+  void drop_graph() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    graph_exec = nullptr;
+    graph = nullptr;
+    graph_stages.clear();
+  }
+  ~mgwr_batch() {
+    drop_graph();
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
+  }
 };
 
 namespace {
@@ -658,15 +700,66 @@ int fall_back_to_zero(mgwr_plan* pl, const double* b, double* u, mgwr_stats& s, 
 
 // Pipelined solve of plans[0..n) (float64) with the stage table, counters,
 // flags and norms of `bt` (a batch, or one plan's own regions).
+// Launch of the merged stage table: counters and flags cleared, then the
+// pipeline kernel; replayed from a captured graph when the table, counter
+// count and grid equal those of the graph (batches with graphs enabled).
+int launch_batch_table(mgwr_batch* bt, long long ncnt, int ntasks) {
+  PipeArgs pa;
+  pa.stages = bt->stages_dev;
+  pa.nstages = (int)bt->stages.size();
+  pa.ntasks = ntasks;
+  pa.counters = bt->counters;
+  pa.ticket = bt->flags_dev;
+  pa.abortf = bt->flags_dev + 1;
+  const bool same = bt->graph_exec && bt->graph_ncnt == ncnt && bt->graph_ntasks == ntasks &&
+                    bt->graph_stages.size() == bt->stages.size() &&
+                    std::memcmp(bt->graph_stages.data(), bt->stages.data(), bt->stages.size() * sizeof(Stage)) == 0;
+  if (same) {
+    HIP_TRY(hipGraphLaunch(bt->graph_exec, bt->stream));
+    bt->graph_replays++;
+    return MGWR_OK;
+  }
+  HIP_TRY(hipMemcpyAsync(bt->stages_dev, bt->stages.data(), bt->stages.size() * sizeof(Stage),
+                         hipMemcpyHostToDevice, bt->stream));
+  if (!bt->use_graph) {
+    HIP_TRY(launch_fill_int(bt->counters, ncnt, 0, bt->stream));
+    HIP_TRY(launch_fill_int(bt->flags_dev, 2, 0, bt->stream));
+    HIP_TRY(launch_pipeline(pa, bt->lds, bt->stream));
+    return MGWR_OK;
+  }
+  // capture on the private stream (nothing runs while capturing): fill
+  // kernels (no memset nodes) and the pipeline kernel; the graph is then
+  // launched on the batch's stream after the table upload above
+  bt->drop_graph();
+  if (!bt->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&bt->capture_stream, hipStreamNonBlocking));
+  HIP_TRY(hipStreamBeginCapture(bt->capture_stream, hipStreamCaptureModeRelaxed));
+  hipError_t e1 = launch_fill_int(bt->counters, ncnt, 0, bt->capture_stream);
+  hipError_t e2 = launch_fill_int(bt->flags_dev, 2, 0, bt->capture_stream);
+  hipError_t e3 = launch_pipeline(pa, bt->lds, bt->capture_stream);
+  hipGraph_t gr = nullptr;
+  hipError_t e4 = hipStreamEndCapture(bt->capture_stream, &gr);
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) {
+    if (gr) (void)hipGraphDestroy(gr);
+    return fail(MGWR_ERR_HIP, "capturing the batched launch failed");
+  }
+  bt->graph = gr;
+  HIP_TRY(hipGraphInstantiate(&bt->graph_exec, bt->graph, nullptr, nullptr, 0));
+  bt->graph_stages = bt->stages;
+  bt->graph_ncnt = ncnt;
+  bt->graph_ntasks = ntasks;
+  HIP_TRY(hipGraphLaunch(bt->graph_exec, bt->stream));
+  return MGWR_OK;
+}
+
 int solve_pipelined(mgwr_batch* bt, const double* const* f, const double* const* g, double tol,
-                    double* const* u, unsigned flags, mgwr_stats* stats) {
+                    double* const* u, unsigned flags, mgwr_stats* stats, const std::vector<int>& sel) {
   const int n = (int)bt->plans.size();
   int rc;
   std::vector<mgwr_stats> st(n);
   std::vector<const double*> b(n);
   std::vector<int> status(n), K(n), conv_at(n, -1), base(n, 0), judged(n, 0), zero_start(n, 0);
   std::vector<unsigned> fl_i(n, flags);
-  for (int i = 0; i < n; ++i) {
+  for (int i : sel) {
     mgwr_plan* pl = bt->plans[i];
     if (!f[i] || !u[i]) return batch_fail(MGWR_ERR_INVALID_ARG, "null array in batch");
     if ((rc = use_device(pl))) return rc;
@@ -676,10 +769,10 @@ int solve_pipelined(mgwr_batch* bt, const double* const* f, const double* const*
     zero_start[i] = !(fl_i[i] & MGWR_GUESS_IN_U);
   }
   // the plans' streams must be complete before the batch stream uses their arrays
-  for (int i = 0; i < n; ++i) HIP_TRY(hipStreamSynchronize(bt->plans[i]->stream));
+  for (int i : sel) HIP_TRY(hipStreamSynchronize(bt->plans[i]->stream));
   while (true) {
     std::vector<int> act;
-    for (int i = 0; i < n; ++i)
+    for (int i : sel)
       if (status[i] == MGWR_ERR_NOT_CONVERGED &&
           st[i].cycles + (bt->plans[i]->mixed ? bt->plans[i]->hp.p.inner_cycles : 1) <= bt->plans[i]->hp.p.max_cycles)
         act.push_back(i);
@@ -723,24 +816,13 @@ int solve_pipelined(mgwr_batch* bt, const double* const* f, const double* const*
     for (auto& x : bt->stages) { ncnt += x.nleaf; ntasks = x.task0 + x.nchunks; }
     if ((size_t)bt->stages.size() * sizeof(Stage) > bt->off_counters - bt->off_stages)
       return batch_fail(MGWR_ERR_STATE, "internal error: batch stage table exceeds its workspace");
-    HIP_TRY(hipMemcpyAsync(bt->stages_dev, bt->stages.data(), bt->stages.size() * sizeof(Stage),
-                           hipMemcpyHostToDevice, bt->stream));
-    HIP_TRY(launch_fill_int(bt->counters, ncnt, 0, bt->stream));
-    HIP_TRY(launch_fill_int(bt->flags_dev, 2, 0, bt->stream));
-    PipeArgs pa;
-    pa.stages = bt->stages_dev;
-    pa.nstages = (int)bt->stages.size();
-    pa.ntasks = ntasks;
-    pa.counters = bt->counters;
-    pa.ticket = bt->flags_dev;
-    pa.abortf = bt->flags_dev + 1;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (bt->timing) {
       HIP_TRY(hipEventCreate(&e0));
       HIP_TRY(hipEventCreate(&e1));
       HIP_TRY(hipEventRecord(e0, bt->stream));
     }
-    HIP_TRY(launch_pipeline(pa, bt->lds, bt->stream));
+    if ((rc = launch_batch_table(bt, ncnt, ntasks))) return rc;
     if (bt->timing) HIP_TRY(hipEventRecord(e1, bt->stream));
     int fl[2] = {0, 0};
     HIP_TRY(hipMemcpyAsync(fl, bt->flags_dev, sizeof(fl), hipMemcpyDeviceToHost, bt->stream));
@@ -811,7 +893,7 @@ int solve_pipelined(mgwr_batch* bt, const double* const* f, const double* const*
     }
   }
   int ret = MGWR_OK;
-  for (int i = 0; i < n; ++i) {
+  for (int i : sel) {
     mgwr_stats& s = st[i];
     if (conv_at[i] > 0) (s.used_warm_start ? bt->plans[i]->khint_warm : bt->plans[i]->khint) = conv_at[i];
     s.avg_factor = (s.cycles > 0 && s.res0 > 0) ? std::pow(s.res / s.res0, 1.0 / s.cycles) : 0.0;
@@ -1013,7 +1095,7 @@ int mgwr_solve(mgwr_plan* pl, const double* f, const double* g, double tol, doub
     const double* gp[1] = {g};
     double* up[1] = {u};
     mgwr_stats s1{};
-    int rc2 = solve_pipelined(&one, fp, gp, tol, up, flags, &s1);
+    int rc2 = solve_pipelined(&one, fp, gp, tol, up, flags, &s1, std::vector<int>{0});
     if (pl->timing)
       for (int c = 0; c < MGWR_K_CLASSES; ++c) {
         pl->tacc.launches[c] += one.tacc.launches[c];
@@ -1264,7 +1346,82 @@ int mgwr_batch_solve(mgwr_batch* bt, const double* const* f, const double* const
                      unsigned flags, mgwr_stats* stats) {
   if (!bt || !bt->bound) return batch_fail(MGWR_ERR_STATE, "batch is not bound");
   if (!f || !u || !(tol > 0.0)) return batch_fail(MGWR_ERR_INVALID_ARG, "bad arguments");
-  return solve_pipelined(bt, f, g, tol, u, flags, stats);
+  // instances whose schedule is pipelined share one launch; the others are
+  // solved one after another with their staged schedule
+  std::vector<int> pipe, staged;
+  for (int i = 0; i < (int)bt->plans.size(); ++i) (use_pipeline(bt->plans[i]) ? pipe : staged).push_back(i);
+  int ret = MGWR_OK;
+  std::string msg;
+  if (!pipe.empty()) {
+    ret = solve_pipelined(bt, f, g, tol, u, flags, stats, pipe);
+    if (ret) msg = mgwr_last_error();
+    if (ret != MGWR_OK && ret != MGWR_ERR_NOT_CONVERGED && ret != MGWR_ERR_NONFINITE) return ret;
+  }
+  for (int i : staged) {
+    mgwr_stats si{};
+    const int rc = mgwr_solve(bt->plans[i], f[i], g ? g[i] : nullptr, tol, u[i], flags, &si);
+    if (stats) stats[i] = si;
+    if (rc != MGWR_OK && rc != MGWR_ERR_NOT_CONVERGED && rc != MGWR_ERR_NONFINITE) return rc;
+    if (rc != MGWR_OK && ret == MGWR_OK) {
+      ret = rc;
+      msg = mgwr_last_error();
+    }
+  }
+  if (ret != MGWR_OK) return batch_fail(ret, msg);
+  return MGWR_OK;
+}
+
+int mgwr_batch_set_graph(mgwr_batch* bt, int enable) {
+  if (!bt) return batch_fail(MGWR_ERR_INVALID_ARG, "null batch");
+  bt->use_graph = enable != 0;
+  if (!bt->use_graph) bt->drop_graph();
+  return MGWR_OK;
+}
+
+int mgwr_batch_graph_replays(const mgwr_batch* bt, long long* replays) {
+  if (!bt || !replays) return batch_fail(MGWR_ERR_INVALID_ARG, "null argument");
+  *replays = bt->graph_replays;
+  return MGWR_OK;
+}
+
+int mgwr_plan_autotune(mgwr_plan* pl, const double* f, const double* g, double tol, double* u, int* chosen) {
+  int rc = check_bound(pl);
+  if (rc) return rc;
+  if (!f || !u || !(tol > 0.0)) return fail(MGWR_ERR_INVALID_ARG, "bad arguments");
+  const int saved = pl->tuned;
+  double best = 1e300;
+  int pick = MGWR_SCHED_STAGED;
+  for (int sched : {MGWR_SCHED_STAGED, MGWR_SCHED_PIPELINED}) {
+    pl->tuned = sched;
+    const int keep = pl->hp.p.schedule;
+    pl->hp.p.schedule = MGWR_SCHED_AUTO;
+    double secs = 0.0;
+    // the second solve runs with what the first one learned (cycle count)
+    for (int rep = 0; rep < 2 && !rc; ++rep) {
+      auto t0 = std::chrono::steady_clock::now();
+      rc = mgwr_solve(pl, f, g, tol, u, 0u, nullptr);
+      if (rc == MGWR_OK) {
+        if (hipStreamSynchronize(pl->stream) != hipSuccess) rc = fail(MGWR_ERR_HIP, "synchronise failed");
+        secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      }
+    }
+    pl->hp.p.schedule = keep;
+    if (rc) {
+      pl->tuned = saved;
+      return rc;
+    }
+    if (secs < best) {
+      best = secs;
+      pick = sched;
+    }
+  }
+  pl->tuned = pick;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[tune_key(pl)] = pick;
+  }
+  if (chosen) *chosen = pick;
+  return MGWR_OK;
 }
 
 int mgwr_batch_timing(mgwr_batch* bt, int enable, mgwr_timing* out) {
