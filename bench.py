@@ -43,7 +43,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="large1d", choices=["large1d", "large2d", "small1d"])
+    ap.add_argument("--workload", default="large1d", choices=["large1d", "large2d", "small1d", "batched"])
+    ap.add_argument("--batch-count", type=int, default=64, help="instances of the batched workload")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
@@ -190,6 +191,76 @@ def learned_forms(args, probs, fs, us, unknowns, mg, torch):
     return out
 
 
+def batched_main(args):
+    """The batched workload: `batch_count` uneven 2D instances of the
+    random-Fourier family (sides {63, 127, 255}, M in {256..2048}, alpha ~
+    U[0.2, 0.9]) solved together: the schedule of each (n, M) bucket chosen
+    by the autotuner on its first instance, the pipelined instances in one
+    merged launch (graph-replayed), the staged ones after it."""
+    import torch
+
+    import paper_1706_07632_amd as mg
+    import workloads as W
+    dev = torch.device("cuda", 0)
+    probs = W.batched_instances(count=args.batch_count, build_f="modes")
+    fs = []
+    for p in probs:
+        f = torch.zeros((p.M, p.N), dtype=torch.float64, device=dev)
+        for kvec, prof in p.modes:
+            f.add_(torch.outer(torch.as_tensor(prof, dtype=torch.float64, device=dev),
+                               torch.as_tensor(W.sine_mode(p.n, 2, 1.0, kvec), dtype=torch.float64, device=dev)))
+        fs.append(f)
+    us = [torch.empty_like(f) for f in fs]
+    unknowns = sum(p.N * p.M for p in probs)
+    forms, out_timing, tuned = {}, None, {}
+    for name, precision in (("fp64", "fp64"), ("mixed_fp32", "mixed")):
+        if name == "mixed_fp32" and args.no_mixed:
+            continue
+        plans = [mg.Plan(2, p.n, p.M, p.alpha, k=p.k, r=p.r, t=p.t, precision=precision, inner_cycles=1).bind()
+                 for p in probs]
+        t0 = time.perf_counter()
+        for p, pl, f, u in zip(probs, plans, fs, us):
+            key = (p.n, p.M, precision)
+            if key not in tuned:
+                tuned[key] = pl.autotune(f, tol=args.tol, u=u)
+        tune_s = time.perf_counter() - t0
+        batch = mg.Batch(plans, graph=True).bind()
+        for pl in plans:
+            pl.timing(True)     # the staged instances are timed by their plans
+        secs, stats, timing = time_batch(batch, fs, us, args.tol, args.steps, args.warmup, torch)
+        last = stats[-len(probs):]
+        forms[name] = {"value": unknowns * args.steps / secs, "ms_per_step": 1e3 * secs / args.steps,
+                       "cycles_total": sum(s["cycles"] for s in last),
+                       "max_rel_res": max(s["res"] / s["bnorm"] for s in last),
+                       "autotune_s": round(tune_s, 2), "graph_replays": batch.graph_replays()}
+        if out_timing is None:
+            out_timing = merge_timing(timing + [pl.timing() for pl in plans])
+        batch.close()
+        for pl in plans:
+            pl.close()
+    tm = out_timing
+    dom = max(tm, key=lambda k: tm[k]["ms"])
+    sm = tm[dom]
+    achieved = sm["flops"] / (sm["ms"] * 1e-3) / 1e12 if sm["ms"] > 0 else 0.0
+    out = {
+        "metric": "space-time unknowns (N*M)/s to 1e-8 rel. residual, batched uneven 2D instances",
+        "value": forms["fp64"]["value"], "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": forms["fp64"]["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded random-Fourier sources)",
+        "config": {"workload": f"batched: {len(probs)} 2D instances, sides {{63,127,255}}, M {{256..2048}}, "
+                               "alpha~U[0.2,0.9], r=(2-a)/a, k=10, leaf 16, V(1,1)",
+                   "instances": len(probs), "unknowns": unknowns, "tol": args.tol,
+                   "schedules": {f"n{k[0]}_M{k[1]}_{k[2]}": v for k, v in sorted(tuned.items())}},
+        "roofline": {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "avg_launch_us": 1e3 * sm["ms"] / max(1, sm["launches"]), "launches": sm["launches"]},
+        "forms": forms,
+        "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3)} for k, v in tm.items() if v["launches"]},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_probe:
@@ -198,6 +269,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "batched":
+        batched_main(args)
+        return
     import numpy as np
     import torch
 

@@ -158,23 +158,24 @@ def paper_2d_polynomial(n: int, M: int, alpha: float, k: int = 20,
 
 
 def random_fourier_2d(n: int, M: int, alpha: float, rng: np.random.Generator, k: int = 10,
-                      r: float | None = None, nmodes: int = 8, kmax: int = 16) -> Problem:
+                      r: float | None = None, nmodes: int = 8, kmax: int = 16, build_f: bool = True) -> Problem:
     """Source made of `nmodes` distinct sine modes (kx, ky) in {1..kmax}^2 with
     amplitudes z/(1 + kx^2 + ky^2), z ~ N(0, 1), times t^alpha; zero initial data,
-    unit square, T = 1."""
+    unit square, T = 1.  With build_f False only the modes are kept (f None):
+    f = sum over modes of outer(profile, sine_mode(n, 2, 1, kvec))."""
     if r is None:
         r = default_grading(alpha)
     t = graded_mesh(M, 1.0, r)
     flat = rng.choice(kmax * kmax, size=nmodes, replace=False)
     z = rng.standard_normal(nmodes)
     tt = t[1:] ** alpha
-    f = np.zeros((M, n * n))
+    f = np.zeros((M, n * n)) if build_f else None
     modes = []
     for idx, zi in zip(flat, z):
         kx, ky = int(idx % kmax) + 1, int(idx // kmax) + 1
         amp = zi / (1.0 + kx * kx + ky * ky)
-        s = sine_mode(n, 2, 1.0, (kx, ky))
-        f += np.outer(amp * tt, s)
+        if build_f:
+            f += np.outer(amp * tt, sine_mode(n, 2, 1.0, (kx, ky)))
         modes.append(((kx, ky), amp * tt))
     return Problem(dim=2, n=n, M=M, alpha=alpha, r=r, k=k, t=t, f=f, modes=modes,
                    name=f"fourier2d_n{n}_M{M}_a{alpha:.3f}")
@@ -191,7 +192,9 @@ def batched_instances(count: int = 64, seed: int = 20261203, sides=(63, 127, 255
         n = int(rng.choice(sides))
         M = int(rng.choice(Ms))
         alpha = float(rng.uniform(*alpha_range))
-        if build_f:
+        if build_f == "modes":
+            out.append(random_fourier_2d(n, M, alpha, rng, k=k, build_f=False))
+        elif build_f:
             out.append(random_fourier_2d(n, M, alpha, rng, k=k))
         else:
             out.append((n, M, alpha))
