@@ -48,6 +48,28 @@ template <typename T> __device__ __forceinline__ int drow(int g, int r);
 template <> __device__ __forceinline__ int drow<double>(int g, int r) { return g + 4 * r; }
 template <> __device__ __forceinline__ int drow<float>(int g, int r) { return 4 * g + r; }
 
+// Every pointer the kernels receive inside a struct is a global-memory
+// pointer; saying so turns flat accesses (which also count against the LDS
+// wait counter, so that an LDS barrier would drain them) into global ones.
+#define GLOBAL_AS __attribute__((address_space(1)))
+template <typename T> __device__ __forceinline__ const GLOBAL_AS T* gp(const T* p) { return (const GLOBAL_AS T*)p; }
+template <typename T> __device__ __forceinline__ GLOBAL_AS T* gp(T* p) { return (GLOBAL_AS T*)p; }
+template <typename T> __device__ __forceinline__ T ld(const T* p) { return *gp(p); }
+// a struct, word by word (its copy constructor cannot read another address
+// space); with `uniform` the words go to scalar registers
+template <typename T, bool uniform = false> __device__ __forceinline__ T ld_struct(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "word-sized struct");
+  T out;
+  const GLOBAL_AS unsigned int* src = (const GLOBAL_AS unsigned int*)p;
+  unsigned int* dst = reinterpret_cast<unsigned int*>(&out);
+#pragma unroll
+  for (unsigned i = 0; i < sizeof(T) / 4; ++i) {
+    if constexpr (uniform) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    else dst[i] = src[i];
+  }
+  return out;
+}
+
 // Loads and stores of the space-time arrays.  Inside the pipelined cycle
 // kernel a stage reads rows another workgroup (possibly on another XCD) has
 // just written, so those accesses are device-coherent (relaxed agent-scope
@@ -56,13 +78,13 @@ template <> __device__ __forceinline__ int drow<float>(int g, int r) { return 4 
 template <bool PIPE, typename T>
 __device__ __forceinline__ T gld(const T* p) {
   if constexpr (!PIPE) {
-    return *p;
+    return *gp(p);
   } else if constexpr (sizeof(T) == 8) {
-    unsigned long long v = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED,
+    unsigned long long v = __hip_atomic_load((const GLOBAL_AS unsigned long long*)p, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT);
     return __builtin_bit_cast(T, v);
   } else {
-    unsigned int v = __hip_atomic_load(reinterpret_cast<const unsigned int*>(p), __ATOMIC_RELAXED,
+    unsigned int v = __hip_atomic_load((const GLOBAL_AS unsigned int*)p, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
     return __builtin_bit_cast(T, v);
   }
@@ -70,12 +92,12 @@ __device__ __forceinline__ T gld(const T* p) {
 template <bool PIPE, typename T>
 __device__ __forceinline__ void gst(T* p, T v) {
   if constexpr (!PIPE) {
-    *p = v;
+    *gp(p) = v;
   } else if constexpr (sizeof(T) == 8) {
-    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), __builtin_bit_cast(unsigned long long, v),
+    __hip_atomic_store((GLOBAL_AS unsigned long long*)p, __builtin_bit_cast(unsigned long long, v),
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   } else {
-    __hip_atomic_store(reinterpret_cast<unsigned int*>(p), __builtin_bit_cast(unsigned int, v), __ATOMIC_RELAXED,
+    __hip_atomic_store((GLOBAL_AS unsigned int*)p, __builtin_bit_cast(unsigned int, v), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
   }
 }
@@ -114,6 +136,12 @@ __device__ __forceinline__ void signal_leaf(const PipeCtx& pc, int leaf, int lan
   if (lane == 0) __hip_atomic_fetch_add(pc.done + leaf, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Workgroup barrier for data exchanged through LDS only: waits for this
+// wave's LDS operations, not for its global loads, which stay in flight
+// across the barrier (a full __syncthreads drains them, putting their latency
+// on the critical path of every leaf).
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 constexpr int ZFIRST = 1 << 30;
 constexpr int ZMASK = (1 << 30) - 1;
 
@@ -143,7 +171,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
   T* tbuf = part + NW * 256;                   // [16][16] (f32 transposition)
   T* Z = tbuf + 256;                           // [nslots*k][16]
 
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int g = lane >> 4;
   const int c = lane & 15;
@@ -169,7 +197,8 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
   const int nleaf = a.nleaf;
 
   // ---- registers holding prefetched operands -------------------------------
-  T pf_f[4], pf_s[4], pf_u[4];          // wave 0: inputs of the next leaf's rows
+  constexpr int NB = 4;                 // stencil neighbours loaded per row (2 used in 1D)
+  T pf_f[4], pf_n[4][NB], pf_u[4];      // wave 0: raw inputs of the next leaf's rows
   T dpf[DPF][4];                        // dense tiles of the next phase 2
   int djj[DPF];
   T fpf[FPF];                           // far-field chunks of the next phase 2
@@ -182,8 +211,8 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
   auto n_dense = [&](const LeafDesc& d) { return d.dn_end - d.dn_begin + (kKnownX ? 1 : 0); };
   auto dense_item = [&](const LeafDesc& d, int li, int e, int& j) -> const T* {
     if (e < d.dn_end - d.dn_begin) {
-      j = a.dn_list[2 * (d.dn_begin + e)];
-      return a.dense + (long long)a.dn_list[2 * (d.dn_begin + e) + 1] * 256;
+      j = ld(a.dn_list + 2 * (d.dn_begin + e));
+      return a.dense + (long long)ld(a.dn_list + 2 * (d.dn_begin + e) + 1) * 256;
     }
     j = li;
     return a.dense + (long long)d.diag_off * 256;
@@ -194,30 +223,27 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
     if constexpr (PIPE) {
       if (!wait_leaf(pc, li)) return false;
     }
-    const LeafDesc d = a.leaves[li];
-    {
+    const LeafDesc d = ld_struct<LeafDesc, true>(a.leaves + li);
+    // every load is issued before any of them is used, so that they are in
+    // flight together; they are consumed at the end of the next phase 2
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = drow<T>(g, r);
-        const bool ok = colok && row < d.sz;
-        const long long off = (long long)(d.lo + (ok ? row : 0)) * a.ld;
-        T f = (T)0, s = (T)0, u = (T)0;
-        if constexpr (MODE != MODE_MATVEC) f = ok ? gld<PIPE>(a.F + off + q) : (T)0;
-        if constexpr (MODE == MODE_SMOOTH || MODE == MODE_RESID) {
+    for (int r = 0; r < 4; ++r) {
+      const int row = drow<T>(g, r);
+      const bool ok = colok && row < d.sz;
+      const long long off = (long long)(d.lo + (ok ? row : 0)) * a.ld;
+      pf_f[r] = (MODE != MODE_MATVEC && ok) ? gld<PIPE>(a.F + off + q) : (T)0;
 #pragma unroll
-          for (int e = 0; e < 4; ++e)
-            if (nbok[e] && ok) s += gld<PIPE>(a.U + off + nb[e]);
-        }
-        if constexpr (kKnownX) u = ok ? gld<PIPE>(a.U + off + q) : (T)0;
-        pf_f[r] = f; pf_s[r] = s; pf_u[r] = u;
-      }
+      for (int e = 0; e < NB; ++e)
+        pf_n[r][e] = ((MODE == MODE_SMOOTH || MODE == MODE_RESID) && nbok[e] && ok) ? gld<PIPE>(a.U + off + nb[e])
+                                                                                     : (T)0;
+      pf_u[r] = (kKnownX && ok) ? gld<PIPE>(a.U + off + q) : (T)0;
     }
     return true;
   };
 
   // all waves: H-matrix tiles of their share of leaf li's phase 2
   auto prefetch_tiles = [&](int li) {
-    const LeafDesc d = a.leaves[li];
+    const LeafDesc d = ld_struct<LeafDesc, true>(a.leaves + li);
     const int nd = n_dense(d);
 #pragma unroll
     for (int k2 = 0; k2 < DPF; ++k2) {
@@ -225,30 +251,30 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
       if (e < nd) {
         const T* D = dense_item(d, li, e, djj[k2]);
 #pragma unroll
-        for (int kc = 0; kc < 4; ++kc) dpf[k2][kc] = D[kc * 64 + lane];
+        for (int kc = 0; kc < 4; ++kc) dpf[k2][kc] = ld(D + kc * 64 + lane);
       }
     }
 #pragma unroll
     for (int k2 = 0; k2 < FPF; ++k2) {
       const int ch = wave + k2 * NW;
       if (ch < d.ff_nchunk) {
-        fpf[k2] = a.ffA[(long long)(d.ff_begin + ch) * 64 + lane];
-        fzr[k2] = a.ff_row[(d.ff_begin + ch) * 4 + g];
+        fpf[k2] = ld(a.ffA + (long long)(d.ff_begin + ch) * 64 + lane);
+        fzr[k2] = ld(a.ff_row + (d.ff_begin + ch) * 4 + g);
       }
     }
   };
 
   auto prefetch_zu = [&](int li) {  // helpers: update tiles of leaf li
-    const LeafDesc d = a.leaves[li];
+    const LeafDesc d = ld_struct<LeafDesc, true>(a.leaves + li);
 #pragma unroll
     for (int k2 = 0; k2 < ZPF; ++k2) {
       const int tt = (wave - 1) + k2 * (NW - 1);
       if (tt < d.zu_ntile) {
         const T* Bt = a.zuB + (long long)(d.zu_begin + tt) * 256;
 #pragma unroll
-        for (int kc = 0; kc < 4; ++kc) zpf[k2][kc] = Bt[kc * 64 + lane];
+        for (int kc = 0; kc < 4; ++kc) zpf[k2][kc] = ld(Bt + kc * 64 + lane);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) zpr[k2][r] = a.zu_row[(d.zu_begin + tt) * 16 + drow<T>(g, r)];
+        for (int r = 0; r < 4; ++r) zpr[k2][r] = ld(a.zu_row + (d.zu_begin + tt) * 16 + drow<T>(g, r));
       }
     }
   };
@@ -257,25 +283,14 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
     if constexpr (kSolve) {
       const T* Di = a.dinv + (long long)li * 256;
 #pragma unroll
-      for (int kc = 0; kc < 4; ++kc) di[kc] = Di[kc * 64 + lane];
+      for (int kc = 0; kc < 4; ++kc) di[kc] = ld(Di + kc * 64 + lane);
     }
   };
 
   // phase 2: partial right-hand side of leaf li from this wave's share
   auto partial = [&](int li) {
-    const LeafDesc d = a.leaves[li];
+    const LeafDesc d = ld_struct<LeafDesc, true>(a.leaves + li);
     v4 acc = {0, 0, 0, 0};
-    if (wave == 0) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        T v;
-        if constexpr (MODE == MODE_SMOOTH) v = pf_f[r] + a.inv_h2 * pf_s[r];
-        else if constexpr (MODE == MODE_RESID) v = pf_f[r] - a.inv_h2 * (diagc * pf_u[r] - pf_s[r]);
-        else if constexpr (MODE == MODE_TRSM) v = pf_f[r];
-        else v = (T)0;
-        acc[r] = v;
-      }
-    }
     const int nd = n_dense(d);
 #pragma unroll
     for (int k2 = 0; k2 < DPF; ++k2) {
@@ -290,7 +305,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
       const T* D = dense_item(d, li, e, j);
       T t[4];
 #pragma unroll
-      for (int kc = 0; kc < 4; ++kc) t[kc] = D[kc * 64 + lane];
+      for (int kc = 0; kc < 4; ++kc) t[kc] = ld(D + kc * 64 + lane);
       const T* xj = ring + (j % a.ring) * 256;
 #pragma unroll
       for (int kc = 0; kc < 4; ++kc) acc = mfma(t[kc], xj[(4 * kc + g) * 16 + c], acc);
@@ -307,13 +322,27 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
 #pragma unroll
       for (int b = 0; b < FPF; ++b) {
         const int ch = min(ch0 + b * NW, d.ff_nchunk - 1);
-        av[b] = a.ffA[(long long)(d.ff_begin + ch) * 64 + lane];
-        const int zr = a.ff_row[(d.ff_begin + ch) * 4 + g];
+        av[b] = ld(a.ffA + (long long)(d.ff_begin + ch) * 64 + lane);
+        const int zr = ld(a.ff_row + (d.ff_begin + ch) * 4 + g);
         bv[b] = (zr >= 0 && ch0 + b * NW < d.ff_nchunk) ? Z[zr * 16 + c] : (T)0;
       }
 #pragma unroll
       for (int b = 0; b < FPF; ++b)
         if (ch0 + b * NW < d.ff_nchunk) acc = mfma(av[b], bv[b], acc);
+    }
+    if (wave == 0) {   // stencil right-hand side last: its loads had the most time
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        T sn = (T)0;
+#pragma unroll
+        for (int e = 0; e < NB; ++e) sn += pf_n[r][e];
+        T v;
+        if constexpr (MODE == MODE_SMOOTH) v = pf_f[r] + a.inv_h2 * sn;
+        else if constexpr (MODE == MODE_RESID) v = pf_f[r] - a.inv_h2 * (diagc * pf_u[r] - sn);
+        else if constexpr (MODE == MODE_TRSM) v = pf_f[r];
+        else v = (T)0;
+        acc[r] += v;
+      }
     }
     T* pw = part + wave * 256;
 #pragma unroll
@@ -322,7 +351,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
 
   // phase 1 (helpers): Z += B^T x for the update tiles of leaf li owned by this wave
   auto zupdate = [&](int li) {
-    const LeafDesc d = a.leaves[li];
+    const LeafDesc d = ld_struct<LeafDesc, true>(a.leaves + li);
     const T* xs = ring + (li % a.ring) * 256;
     auto apply = [&](const T* bt, const int* zr) {
       v4 z;
@@ -342,9 +371,9 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
       int zr[4];
       const T* Bt = a.zuB + (long long)(d.zu_begin + tt) * 256;
 #pragma unroll
-      for (int kc = 0; kc < 4; ++kc) bt[kc] = Bt[kc * 64 + lane];
+      for (int kc = 0; kc < 4; ++kc) bt[kc] = ld(Bt + kc * 64 + lane);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) zr[r] = a.zu_row[(d.zu_begin + tt) * 16 + drow<T>(g, r)];
+      for (int r = 0; r < 4; ++r) zr[r] = ld(a.zu_row + (d.zu_begin + tt) * 16 + drow<T>(g, r));
       apply(bt, zr);
     }
   };
@@ -370,9 +399,11 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
   __syncthreads();
 
   for (int s = 0; s < nleaf; ++s) {
-    const LeafDesc d = a.leaves[s];
+    const LeafDesc d = ld_struct<LeafDesc, true>(a.leaves + s);
     // ---- phase 1 --------------------------------------------------------------
-    if (s + 1 < nleaf) prefetch_tiles(s + 1);
+    // (wave 0 loads its tiles after the solve: the wait before the progress
+    // signal then covers its row stores only)
+    if (s + 1 < nleaf && wave != 0) prefetch_tiles(s + 1);
     if (wave == 0) {
       v4 acc;
 #pragma unroll
@@ -419,6 +450,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
       }
       if constexpr (PIPE) signal_leaf(pc, s, lane);
       if (s + 1 < nleaf) {
+        prefetch_tiles(s + 1);
         if (!prefetch_inputs(s + 1)) *sh_abort = 1;
         if constexpr (kKnownX) {
           T* nxt = ring + ((s + 1) % a.ring) * 256;
@@ -429,7 +461,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
     } else if (s >= 1) {
       zupdate(s - 1);
     }
-    __syncthreads();
+    lds_barrier();
     if constexpr (PIPE) {
       if (*sh_abort) return;
     }
@@ -439,7 +471,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
       else prefetch_zu(s);
       partial(s + 1);
     }
-    __syncthreads();
+    lds_barrier();
   }
   if constexpr (PIPE && MODE == MODE_RESID) {
     if (pc.norm_out && wave == 0) {
@@ -515,21 +547,36 @@ __device__ void restrict_stage(const Stage& st, int chunk, const PipeCtx& pc, in
     }
   }
   for (int i = 0; i < st.nleaf; ++i) {
-    const LeafDesc d = st.leaves[i];
+    const LeafDesc d = ld_struct<LeafDesc, true>(st.leaves + i);
     if (threadIdx.x < 64) {
       if (!wait_leaf(pc, i)) *sh_abort = 1;
     }
     __syncthreads();
     if (*sh_abort) return;
     if (ok) {
+      // all loads of a group of rows are issued before any is used (4 rows
+      // of 3 taps in 1D, 2 rows of 9 taps in 2D)
       T v[4];
+      const int rows_per_group = st.dim == 1 ? 4 : 2;
+      for (int j0 = 0; j0 < 4; j0 += rows_per_group) {
+        T raw[4][9];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int row = r0 + j * kStencilRowsPerPass;
-        v[j] = (T)0;
-        if (row < d.sz) {
-          const T* r = src + (long long)(d.lo + row) * Nf;
-          for (int t = 0; t < nw; ++t) v[j] += wgt[t] * gld<true>(r + off[t]);
+        for (int jj = 0; jj < 4; ++jj) {
+          const int row = r0 + (j0 + jj) * kStencilRowsPerPass;
+          const bool rok = jj < rows_per_group && row < d.sz;
+          const T* r = src + (long long)(d.lo + (rok ? row : 0)) * Nf;
+#pragma unroll
+          for (int t = 0; t < 9; ++t) raw[jj][t] = (rok && t < nw) ? gld<true>(r + off[t]) : (T)0;
+        }
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          if (jj < rows_per_group) {
+            T acc = (T)0;
+#pragma unroll
+            for (int t = 0; t < 9; ++t)
+              if (t < nw) acc += wgt[t] * raw[jj][t];
+            v[j0 + jj] = acc;
+          }
         }
       }
 #pragma unroll
@@ -592,25 +639,32 @@ __device__ void prolong_stage(const Stage& st, int chunk, const PipeCtx& pc, int
     }
   }
   for (int i = 0; i < st.nleaf; ++i) {
-    const LeafDesc d = st.leaves[i];
+    const LeafDesc d = ld_struct<LeafDesc, true>(st.leaves + i);
     if (threadIdx.x < 64) {
       if (!wait_leaf(pc, i)) *sh_abort = 1;
     }
     __syncthreads();
     if (*sh_abort) return;
     if (ok) {
-      T v[4], u0[4];
+      // every load of the leaf's rows is issued before any is used
+      T v[4], u0[4], raw[4][4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int row = r0 + j * kStencilRowsPerPass;
-        v[j] = (T)0;
-        u0[j] = (T)0;
-        if (row < d.sz) {
-          const long long m = d.lo + row;
-          const T* e = src + m * Nc;
-          for (int t = 0; t < ncoef; ++t) v[j] += cw[t] * gld<true>(e + cidx[t]);
-          u0[j] = gld<true>(dst + m * Nf + q);
-        }
+        const bool rok = row < d.sz;
+        const long long m = d.lo + (rok ? row : 0);
+        const T* e = src + m * Nc;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) raw[j][t] = (rok && t < ncoef) ? gld<true>(e + cidx[t]) : (T)0;
+        u0[j] = rok ? gld<true>(dst + m * Nf + q) : (T)0;
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        T acc = (T)0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (t < ncoef) acc += cw[t] * raw[j][t];
+        v[j] = acc;
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -634,7 +688,7 @@ __device__ void pointwise_stage(const Stage& st, int chunk, const PipeCtx& pc, i
   const bool ok = q < N;
   const int lane = threadIdx.x & 63;
   for (int i = 0; i < st.nleaf; ++i) {
-    const LeafDesc d = st.leaves[i];
+    const LeafDesc d = ld_struct<LeafDesc, true>(st.leaves + i);
     if (threadIdx.x < 64) {
       if (!wait_leaf(pc, i)) *sh_abort = 1;
     }
@@ -698,21 +752,32 @@ __global__ __launch_bounds__(256) void pipeline_kernel(PipeArgs pa) {
     if (pa.stages[mid].task0 <= task) lo = mid;
     else hi = mid - 1;
   }
-  const Stage& st = pa.stages[lo];
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  const Stage* stp = pa.stages + lo;   // global memory; the fields a march stage needs go to registers
+  const int kind = ld(&stp->kind);
+  const int prev = ld(&stp->prev);
   PipeCtx pc;
-  pc.wait = st.prev >= 0 ? pa.counters + pa.stages[st.prev].cnt_off : nullptr;
-  pc.need = st.prev >= 0 ? pa.stages[st.prev].nchunks : 0;
-  pc.done = pa.counters + st.cnt_off;
+  pc.wait = prev >= 0 ? pa.counters + ld(&pa.stages[prev].cnt_off) : nullptr;
+  pc.need = prev >= 0 ? ld(&pa.stages[prev].nchunks) : 0;
+  pc.done = pa.counters + ld(&stp->cnt_off);
   pc.abortf = pa.abortf;
-  pc.norm_out = st.norm_out;
-  const int chunk = task - st.task0;
-  const int kind = st.kind;
-  if (kind == STG_SMOOTH) { march_body<double, MODE_SMOOTH, true>(st.m, chunk, pc, smem_raw, &sh_abort); return; }
-  if (kind == STG_RESID) { march_body<double, MODE_RESID, true>(st.m, chunk, pc, smem_raw, &sh_abort); return; }
-  if (kind == STG_SMOOTH32) { march_body<float, MODE_SMOOTH, true>(st.mf, chunk, pc, smem_raw, &sh_abort); return; }
-  if (kind == STG_RESID32) { march_body<float, MODE_RESID, true>(st.mf, chunk, pc, smem_raw, &sh_abort); return; }
+  pc.norm_out = ld(&stp->norm_out);
+  const int chunk = task - ld(&stp->task0);
+  if (kind == STG_SMOOTH || kind == STG_RESID) {
+    const MarchArgs<double> m = ld_struct<MarchArgs<double>, true>(&stp->m);
+    if (kind == STG_SMOOTH) march_body<double, MODE_SMOOTH, true>(m, chunk, pc, smem_raw, &sh_abort);
+    else march_body<double, MODE_RESID, true>(m, chunk, pc, smem_raw, &sh_abort);
+    return;
+  }
+  if (kind == STG_SMOOTH32 || kind == STG_RESID32) {
+    const MarchArgs<float> m = ld_struct<MarchArgs<float>, true>(&stp->mf);
+    if (kind == STG_SMOOTH32) march_body<float, MODE_SMOOTH, true>(m, chunk, pc, smem_raw, &sh_abort);
+    else march_body<float, MODE_RESID, true>(m, chunk, pc, smem_raw, &sh_abort);
+    return;
+  }
   if (threadIdx.x == 0) sh_abort = 0;
   __syncthreads();
+  const Stage& st = *stp;
   switch (kind) {
     case STG_RESTRICT: restrict_stage<double>(st, chunk, pc, &sh_abort); break;
     case STG_PROLONG: prolong_stage<double>(st, chunk, pc, &sh_abort); break;
