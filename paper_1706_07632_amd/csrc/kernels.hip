@@ -55,17 +55,25 @@ template <> __device__ __forceinline__ int drow<float>(int g, int r) { return 4 
 template <typename T> __device__ __forceinline__ const GLOBAL_AS T* gp(const T* p) { return (const GLOBAL_AS T*)p; }
 template <typename T> __device__ __forceinline__ GLOBAL_AS T* gp(T* p) { return (GLOBAL_AS T*)p; }
 template <typename T> __device__ __forceinline__ T ld(const T* p) { return *gp(p); }
+// Read-only tables indexed uniformly across a wave (leaf descriptors, the
+// dense-block list, stage arguments) are read through the constant address
+// space, i.e. scalar loads with their own cache and shorter latency.
+#define CONST_AS __attribute__((address_space(4)))
+template <typename T> __device__ __forceinline__ T ldc(const T* p) { return *(const CONST_AS T*)p; }
 // a struct, word by word (its copy constructor cannot read another address
-// space); with `uniform` the words go to scalar registers
+// space); `uniform`: the address is the same in every lane (scalar loads)
 template <typename T, bool uniform = false> __device__ __forceinline__ T ld_struct(const T* p) {
   static_assert(sizeof(T) % 4 == 0, "word-sized struct");
   T out;
-  const GLOBAL_AS unsigned int* src = (const GLOBAL_AS unsigned int*)p;
   unsigned int* dst = reinterpret_cast<unsigned int*>(&out);
+  if constexpr (uniform) {
+    const CONST_AS unsigned int* src = (const CONST_AS unsigned int*)p;
 #pragma unroll
-  for (unsigned i = 0; i < sizeof(T) / 4; ++i) {
-    if constexpr (uniform) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
-    else dst[i] = src[i];
+    for (unsigned i = 0; i < sizeof(T) / 4; ++i) dst[i] = src[i];
+  } else {
+    const GLOBAL_AS unsigned int* src = (const GLOBAL_AS unsigned int*)p;
+#pragma unroll
+    for (unsigned i = 0; i < sizeof(T) / 4; ++i) dst[i] = src[i];
   }
   return out;
 }
@@ -211,8 +219,8 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
   auto n_dense = [&](const LeafDesc& d) { return d.dn_end - d.dn_begin + (kKnownX ? 1 : 0); };
   auto dense_item = [&](const LeafDesc& d, int li, int e, int& j) -> const T* {
     if (e < d.dn_end - d.dn_begin) {
-      j = ld(a.dn_list + 2 * (d.dn_begin + e));
-      return a.dense + (long long)ld(a.dn_list + 2 * (d.dn_begin + e) + 1) * 256;
+      j = ldc(a.dn_list + 2 * (d.dn_begin + e));
+      return a.dense + (long long)ldc(a.dn_list + 2 * (d.dn_begin + e) + 1) * 256;
     }
     j = li;
     return a.dense + (long long)d.diag_off * 256;
@@ -754,15 +762,15 @@ __global__ __launch_bounds__(256) void pipeline_kernel(PipeArgs pa) {
   }
   lo = __builtin_amdgcn_readfirstlane(lo);
   const Stage* stp = pa.stages + lo;   // global memory; the fields a march stage needs go to registers
-  const int kind = ld(&stp->kind);
-  const int prev = ld(&stp->prev);
+  const int kind = ldc(&stp->kind);
+  const int prev = ldc(&stp->prev);
   PipeCtx pc;
-  pc.wait = prev >= 0 ? pa.counters + ld(&pa.stages[prev].cnt_off) : nullptr;
-  pc.need = prev >= 0 ? ld(&pa.stages[prev].nchunks) : 0;
-  pc.done = pa.counters + ld(&stp->cnt_off);
+  pc.wait = prev >= 0 ? pa.counters + ldc(&pa.stages[prev].cnt_off) : nullptr;
+  pc.need = prev >= 0 ? ldc(&pa.stages[prev].nchunks) : 0;
+  pc.done = pa.counters + ldc(&stp->cnt_off);
   pc.abortf = pa.abortf;
-  pc.norm_out = ld(&stp->norm_out);
-  const int chunk = task - ld(&stp->task0);
+  pc.norm_out = ldc(&stp->norm_out);
+  const int chunk = task - ldc(&stp->task0);
   if (kind == STG_SMOOTH || kind == STG_RESID) {
     const MarchArgs<double> m = ld_struct<MarchArgs<double>, true>(&stp->m);
     if (kind == STG_SMOOTH) march_body<double, MODE_SMOOTH, true>(m, chunk, pc, smem_raw, &sh_abort);
