@@ -202,6 +202,16 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
   const T diagc = (T)(2 * a.dim);
   constexpr bool kSolve = (MODE == MODE_SMOOTH || MODE == MODE_TRSM);
   constexpr bool kKnownX = (MODE == MODE_RESID || MODE == MODE_MATVEC);
+  // Solves: the last wave moves the solved rows to global memory, signals
+  // progress and loads the next leaf's inputs, all during phase 2, so that
+  // wave 0's critical path (sum, solve) carries no global-memory round trip
+  // and the wait for the producer overlaps the other waves' products.
+  constexpr bool kSplitIO = kSolve;
+  constexpr int kIO = kSplitIO ? NW - 1 : 0;   // the wave that loads the stencil inputs
+  // waves sharing the products of phase 2 (the split-IO wave has none: its
+  // phase 2 holds the stores, the wait for the producer and the input loads)
+  constexpr int NPW = kSplitIO ? NW - 1 : NW;
+  const bool pworker = wave < NPW;
   const int nleaf = a.nleaf;
 
   // ---- registers holding prefetched operands -------------------------------
@@ -251,11 +261,12 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
 
   // all waves: H-matrix tiles of their share of leaf li's phase 2
   auto prefetch_tiles = [&](int li) {
+    if (!pworker) return;
     const LeafDesc d = ld_struct<LeafDesc, true>(a.leaves + li);
     const int nd = n_dense(d);
 #pragma unroll
     for (int k2 = 0; k2 < DPF; ++k2) {
-      const int e = wave + k2 * NW;
+      const int e = wave + k2 * NPW;
       if (e < nd) {
         const T* D = dense_item(d, li, e, djj[k2]);
 #pragma unroll
@@ -264,7 +275,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
     }
 #pragma unroll
     for (int k2 = 0; k2 < FPF; ++k2) {
-      const int ch = wave + k2 * NW;
+      const int ch = wave + k2 * NPW;
       if (ch < d.ff_nchunk) {
         fpf[k2] = ld(a.ffA + (long long)(d.ff_begin + ch) * 64 + lane);
         fzr[k2] = ld(a.ff_row + (d.ff_begin + ch) * 4 + g);
@@ -299,16 +310,17 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
   auto partial = [&](int li) {
     const LeafDesc d = ld_struct<LeafDesc, true>(a.leaves + li);
     v4 acc = {0, 0, 0, 0};
-    const int nd = n_dense(d);
+    const int nd = pworker ? n_dense(d) : 0;
+    const int nff = pworker ? d.ff_nchunk : 0;
 #pragma unroll
     for (int k2 = 0; k2 < DPF; ++k2) {
-      if (wave + k2 * NW < nd) {
+      if (wave + k2 * NPW < nd) {
         const T* xj = ring + (djj[k2] % a.ring) * 256;
 #pragma unroll
         for (int kc = 0; kc < 4; ++kc) acc = mfma(dpf[k2][kc], xj[(4 * kc + g) * 16 + c], acc);
       }
     }
-    for (int e = wave + DPF * NW; e < nd; e += NW) {   // beyond the prefetched share
+    for (int e = wave + DPF * NPW; e < nd; e += NPW) {   // beyond the prefetched share
       int j;
       const T* D = dense_item(d, li, e, j);
       T t[4];
@@ -320,25 +332,25 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
     }
 #pragma unroll
     for (int k2 = 0; k2 < FPF; ++k2) {
-      if (wave + k2 * NW < d.ff_nchunk) {
+      if (wave + k2 * NPW < nff) {
         const T bv = fzr[k2] >= 0 ? Z[fzr[k2] * 16 + c] : (T)0;
         acc = mfma(fpf[k2], bv, acc);
       }
     }
-    for (int ch0 = wave + FPF * NW; ch0 < d.ff_nchunk; ch0 += FPF * NW) {
+    for (int ch0 = wave + FPF * NPW; ch0 < nff; ch0 += FPF * NPW) {
       T av[FPF], bv[FPF];
 #pragma unroll
       for (int b = 0; b < FPF; ++b) {
-        const int ch = min(ch0 + b * NW, d.ff_nchunk - 1);
+        const int ch = min(ch0 + b * NPW, nff - 1);
         av[b] = ld(a.ffA + (long long)(d.ff_begin + ch) * 64 + lane);
         const int zr = ld(a.ff_row + (d.ff_begin + ch) * 4 + g);
-        bv[b] = (zr >= 0 && ch0 + b * NW < d.ff_nchunk) ? Z[zr * 16 + c] : (T)0;
+        bv[b] = (zr >= 0 && ch0 + b * NPW < nff) ? Z[zr * 16 + c] : (T)0;
       }
 #pragma unroll
       for (int b = 0; b < FPF; ++b)
-        if (ch0 + b * NW < d.ff_nchunk) acc = mfma(av[b], bv[b], acc);
+        if (ch0 + b * NPW < nff) acc = mfma(av[b], bv[b], acc);
     }
-    if (wave == 0) {   // stencil right-hand side last: its loads had the most time
+    if (wave == kIO) {   // stencil right-hand side last: its loads had the most time
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         T sn = (T)0;
@@ -391,16 +403,27 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
   T nmax = (T)0;
   bool nbad = false;
 
+  // rows of leaf li from its ring slot to global memory (split-IO wave)
+  auto store_rows = [&](int li) {
+    const LeafDesc d = ld_struct<LeafDesc, true>(a.leaves + li);
+    const T* xs = ring + (li % a.ring) * 256;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = drow<T>(g, r);
+      if (colok && row < d.sz) gst<PIPE>(a.U + (long long)(d.lo + row) * a.ld + q, xs[row * 16 + c]);
+    }
+  };
+
   // ---- prologue: partial right-hand side of leaf 0 ---------------------------
   prefetch_tiles(0);
-  if (wave == 0) {
+  if (wave == kIO) {
     if (!prefetch_inputs(0)) *sh_abort = 1;
     if constexpr (kKnownX) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) ring[drow<T>(g, r) * 16 + c] = pf_u[r];
     }
-    prefetch_dinv(0);
   }
+  if (wave == 0) prefetch_dinv(0);
   __syncthreads();
   if (*sh_abort) return;
   partial(0);
@@ -409,9 +432,8 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
   for (int s = 0; s < nleaf; ++s) {
     const LeafDesc d = ld_struct<LeafDesc, true>(a.leaves + s);
     // ---- phase 1 --------------------------------------------------------------
-    // (wave 0 loads its tiles after the solve: the wait before the progress
-    // signal then covers its row stores only)
-    if (s + 1 < nleaf && wave != 0) prefetch_tiles(s + 1);
+    // (tile loads are issued after any progress signal of the same wave: the
+    // wait before a signal then covers row stores only)
     if (wave == 0) {
       v4 acc;
 #pragma unroll
@@ -438,9 +460,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = drow<T>(g, r);
-          const bool ok = colok && row < d.sz;
-          if (ok) gst<PIPE>(a.U + (long long)(d.lo + row) * a.ld + q, x[r]);
-          cur[row * 16 + c] = ok ? x[r] : (T)0;
+          cur[row * 16 + c] = (colok && row < d.sz) ? x[r] : (T)0;   // to global memory by the split-IO wave
         }
       } else {
 #pragma unroll
@@ -456,18 +476,26 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
           }
         }
       }
-      if constexpr (PIPE) signal_leaf(pc, s, lane);
+      if constexpr (!kSplitIO) {
+        if constexpr (PIPE) signal_leaf(pc, s, lane);
+      }
       if (s + 1 < nleaf) {
         prefetch_tiles(s + 1);
-        if (!prefetch_inputs(s + 1)) *sh_abort = 1;
-        if constexpr (kKnownX) {
-          T* nxt = ring + ((s + 1) % a.ring) * 256;
+        if constexpr (!kSplitIO) {
+          if (!prefetch_inputs(s + 1)) *sh_abort = 1;
+          if constexpr (kKnownX) {
+            T* nxt = ring + ((s + 1) % a.ring) * 256;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) nxt[drow<T>(g, r) * 16 + c] = pf_u[r];
+            for (int r = 0; r < 4; ++r) nxt[drow<T>(g, r) * 16 + c] = pf_u[r];
+          }
         }
       }
-    } else if (s >= 1) {
-      zupdate(s - 1);
+    } else {
+      if constexpr (kSplitIO && PIPE) {
+        if (wave == kIO && s >= 1) signal_leaf(pc, s - 1, lane);   // its row stores went out in the last phase 2
+      }
+      if (s + 1 < nleaf) prefetch_tiles(s + 1);
+      if (s >= 1) zupdate(s - 1);
     }
     lds_barrier();
     if constexpr (PIPE) {
@@ -477,9 +505,23 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
     if (s + 1 < nleaf) {
       if (wave == 0) prefetch_dinv(s + 1);
       else prefetch_zu(s);
+      if constexpr (kSplitIO) {
+        if (wave == kIO) {
+          store_rows(s);
+          if (!prefetch_inputs(s + 1)) *sh_abort = 1;
+        }
+      }
       partial(s + 1);
+    } else if constexpr (kSplitIO) {
+      if (wave == kIO) store_rows(s);
     }
     lds_barrier();
+    if constexpr (PIPE) {
+      if (*sh_abort) return;
+    }
+  }
+  if constexpr (kSplitIO && PIPE) {
+    if (wave == kIO) signal_leaf(pc, nleaf - 1, lane);
   }
   if constexpr (PIPE && MODE == MODE_RESID) {
     if (pc.norm_out && wave == 0) {
