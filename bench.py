@@ -34,8 +34,8 @@ PEAK_HBM_GBS = 8000.0
 # workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by what the same
 # counters read for a 1 GiB device copy (--copy-probe): fetch x 2.000, write x
 # 1.000.  Valid only for the kernel source they were taken on.
-TRAFFIC_KERNEL_SHA256 = "15d56455dd0b82e97872cacb416226569d35d8dc61d7502bef619f90e279fd93"
-TRAFFIC_BYTES = {"large1d": (2.000 * 23504558.6 + 1.000 * 12931669.8) * 1024}
+TRAFFIC_KERNEL_SHA256 = "427611a2fcd8fa3feeb47f10c72f1c022fde3dddb7c2d3dda383fff448608db8"
+TRAFFIC_BYTES = {"large1d": (2.000 * 24034798.3 + 1.000 * 12088462.4) * 1024}
 
 
 def parse():
@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--value-only", action="store_true",
+                    help="time only the batched float64 step behind `value` (no other forms, no CPU baseline): "
+                         "the command the kernel profiles are taken on")
     ap.add_argument("--cpu-repeats", type=int, default=3)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB three times on the device (counter calibration) and exit")
@@ -263,6 +266,8 @@ def batched_main(args):
 
 def main():
     args = parse()
+    if args.value_only:
+        args.no_mixed = args.no_learned = args.no_cpu_baseline = True
     if args.copy_probe:
         copy_probe()
         return
@@ -290,7 +295,9 @@ def main():
     if len(plans) > 1:
         batch = mg.Batch(plans).bind()
         secs, stats, timing = time_batch(batch, fs, us, args.tol, args.steps, args.warmup, torch)
-        seq_secs, seq_stats, _ = time_form(plans, fs, us, args.tol, args.steps, args.warmup, torch)
+        seq_secs = None
+        if not args.value_only:
+            seq_secs, seq_stats, _ = time_form(plans, fs, us, args.tol, args.steps, args.warmup, torch)
     else:
         secs, stats, timing = time_form(plans, fs, us, args.tol, args.steps, args.warmup, torch)
         seq_secs = None
