@@ -106,6 +106,7 @@ struct mgwr_plan {
   int khint = 0;                       // cycles the last pipelined solve from a zero or given iterate needed
   int khint_warm = 0;                  // the same from a predicted iterate
   int tuned = 0;                       // schedule measured best by mgwr_plan_autotune (0: none)
+  int khint_staged = 0;                // cycles the last staged float64 solve from zero needed
   double cycle_flops = 0.0, cycle_bytes = 0.0;  // algorithmic work of one pipelined cycle
   // learned initial guess
   static constexpr int kMaxSlices = 64;
@@ -1122,9 +1123,14 @@ int mgwr_solve(mgwr_plan* pl, const double* f, const double* g, double tol, doub
   if (status == MGWR_ERR_NOT_CONVERGED && !pl->mixed) {
     pl->d64.F[0] = const_cast<double*>(b);
     pl->d64.U[0] = u;
+    // with a cycle count learned from the last solve from zero, the stopping
+    // test (a float64 defect, its norm and a host read) is first evaluated
+    // after that many cycles
+    const int skip_to = (!(flags & MGWR_GUESS_IN_U) && pl->khint_staged > 0) ? pl->khint_staged : 0;
     while (s.cycles < hp.p.max_cycles) {
       if ((rc = cycle<double>(pl, pl->d64, 0))) return rc;
       s.cycles++;
+      if (s.cycles < skip_to) continue;
       if ((rc = defect<double>(pl, pl->d64, 0, b, u, pl->d64.R[0]))) return rc;
       if ((rc = norm_inf<double>(pl, pl->d64.R[0], MN, &s.res))) return rc;
       if (s.cycles <= 64) s.history[s.cycles - 1] = s.res;
@@ -1135,6 +1141,7 @@ int mgwr_solve(mgwr_plan* pl, const double* f, const double* g, double tol, doub
       if (!std::isfinite(s.res)) { status = MGWR_ERR_NONFINITE; break; }
       if (s.res <= target) { status = MGWR_OK; break; }
     }
+    if (status == MGWR_OK && !(flags & MGWR_GUESS_IN_U) && s.used_warm_start == 0) pl->khint_staged = s.cycles;
   } else if (status == MGWR_ERR_NOT_CONVERGED) {
     // float64 outer residual and correction; float32 inner cycles on A e = r
     if (!(flags & MGWR_GUESS_IN_U)) {
