@@ -188,7 +188,8 @@ def learned_forms(args, probs, fs, us, unknowns, mg, torch):
         out[name] = {"value": unknowns * args.steps / secs, "ms_per_step": 1e3 * secs / args.steps,
                      "cycles": [s["cycles"] for s in last],
                      "used_warm_start": [s["used_warm_start"] for s in last],
-                     "warm_res0_rel": [s["warm_res0"] / s["bnorm"] for s in last],
+                     "warm_res0_rel": [None if s["warm_res0"] != s["warm_res0"] else s["warm_res0"] / s["bnorm"]
+                                       for s in last],
                      "rel_res": [s["res"] / s["bnorm"] for s in last],
                      "network": {k: meta[k] for k in ("dim", "n", "M", "count", "steps", "val_loss")}}
     return out

@@ -58,12 +58,16 @@ typedef enum {
 /* Flags of mgwr_solve. */
 enum {
   MGWR_GUESS_IN_U = 1u,  /* u_dev holds the initial iterate (otherwise the zero grid function) */
-  MGWR_WARM_START = 2u   /* initial iterate predicted by the plan's network (mgwr_plan_set_warm_start).
+  MGWR_WARM_START = 2u,  /* initial iterate predicted by the plan's network (mgwr_plan_set_warm_start).
                             Judged by the true float64 residual: a prediction whose defect is not
                             finite is dropped at once, and one whose residual after the first cycles
                             (the first pipelined launch, or the first cycle / refinement of a staged
                             solve) is not below ||b||_inf is dropped then; the solve restarts from the
                             zero iterate and the cycles already spent stay counted */
+  MGWR_WARM_RES0 = 4u    /* with MGWR_WARM_START: also evaluate the prediction's float64 residual
+                            (stats.warm_res0; always done for mixed precision, whose first step needs
+                            that defect).  Without it a float64 solve skips that defect (NaN in
+                            warm_res0) and a non-finite prediction is caught by the first cycles */
 };
 
 typedef struct {
@@ -109,7 +113,7 @@ typedef struct {
                          refinements); 0 where a pipelined launch with a learned cycle count
                          evaluated the norm only after its last cycle */
   int used_warm_start; /* 1 if the network's prediction was the initial iterate of the returned solution */
-  double warm_res0;    /* ||b - A u_predicted||_inf (when a warm start was requested) */
+  double warm_res0;    /* ||b - A u_predicted||_inf (warm start with MGWR_WARM_RES0 or mixed precision; else NaN) */
 } mgwr_stats;
 
 typedef struct mgwr_plan mgwr_plan;

@@ -23,6 +23,7 @@ MGWR_FP64 = 0
 MGWR_MIXED_FP32 = 1
 MGWR_GUESS_IN_U = 1
 MGWR_WARM_START = 2
+MGWR_WARM_RES0 = 4
 
 EXPORTED = [
     "mgwr_params_default", "mgwr_plan_create", "mgwr_plan_workspace_bytes", "mgwr_plan_bind",
@@ -263,7 +264,10 @@ class Plan:
         _check(lib().mgwr_plan_set_warm_start(self._h, None if net is None else net._h, len(rows), arr))
         self._net = net
 
-    def solve(self, f, g=None, tol=1e-10, u=None, guess=False, allow_unconverged=False, warm_start=False):
+    def solve(self, f, g=None, tol=1e-10, u=None, guess=False, allow_unconverged=False, warm_start=False,
+              warm_res0=False):
+        """warm_start: start from the attached network's prediction;
+        warm_res0: also evaluate that prediction's float64 residual."""
         import torch
         _require(f, "f", (self.M, self.N))
         if g is not None:
@@ -272,7 +276,8 @@ class Plan:
             u = torch.empty((self.M, self.N), dtype=torch.float64, device=f.device)
         _require(u, "u", (self.M, self.N))
         st = Stats()
-        fl = (MGWR_GUESS_IN_U if guess else 0) | (MGWR_WARM_START if warm_start else 0)
+        fl = ((MGWR_GUESS_IN_U if guess else 0) | (MGWR_WARM_START if warm_start else 0) |
+              (MGWR_WARM_RES0 if warm_res0 else 0))
         rc = lib().mgwr_solve(self._h, _dptr(f), _dptr(g), float(tol), _dptr(u), fl, ctypes.byref(st))
         _check(rc, ok=(MGWR_OK, MGWR_ERR_NOT_CONVERGED) if allow_unconverged else (MGWR_OK,))
         return u, st.as_dict()
@@ -367,7 +372,8 @@ class Batch:
                                          ctypes.c_void_p(self._stream.cuda_stream)))
         return self
 
-    def solve(self, fs, gs=None, tol=1e-10, us=None, guess=False, allow_unconverged=False, warm_start=False):
+    def solve(self, fs, gs=None, tol=1e-10, us=None, guess=False, allow_unconverged=False, warm_start=False,
+              warm_res0=False):
         import torch
         n = len(self.plans)
         if us is None:
@@ -384,7 +390,8 @@ class Batch:
                     _require(g, "g", (p.N,))
             ga = (ctypes.c_void_p * n)(*[None if g is None else g.data_ptr() for g in gs])
         st = (Stats * n)()
-        fl = (MGWR_GUESS_IN_U if guess else 0) | (MGWR_WARM_START if warm_start else 0)
+        fl = ((MGWR_GUESS_IN_U if guess else 0) | (MGWR_WARM_START if warm_start else 0) |
+              (MGWR_WARM_RES0 if warm_res0 else 0))
         rc = lib().mgwr_batch_solve(self._h, fa, ga, float(tol), ua, fl, st)
         _check(rc, ok=(MGWR_OK, MGWR_ERR_NOT_CONVERGED) if allow_unconverged else (MGWR_OK,))
         return us, [s.as_dict() for s in st]

@@ -641,6 +641,7 @@ int prepare_solve(mgwr_plan* pl, const double* f, const double* g, double tol, d
   if ((rc = norm_inf<double>(pl, b, MN, &s.bnorm))) return rc;
   status = MGWR_ERR_NOT_CONVERGED;
   if (!std::isfinite(s.bnorm)) { status = MGWR_ERR_NONFINITE; return MGWR_OK; }
+  bool warm_unchecked = false;
   if (flags & MGWR_WARM_START) {
     if (!pl->net) return fail(MGWR_ERR_STATE, "MGWR_WARM_START needs a network (mgwr_plan_set_warm_start)");
     flags &= ~(unsigned)MGWR_GUESS_IN_U;
@@ -654,9 +655,16 @@ int prepare_solve(mgwr_plan* pl, const double* f, const double* g, double tol, d
       if ((rc = net_infer(pl->net, pl->netx, H, W, hp.levels[0].h, &y))) return rc;
       HIP_TRY(hipStreamSynchronize(net_stream(pl->net)));
       HIP_TRY(launch_time_interp(y, pl->rows_dev, ns, pl->tpow, g, hp.p.M, N, s.bnorm, u, pl->stream));
-      if ((rc = defect<double>(pl, pl->d64, 0, b, u, pl->d64.R[0]))) return rc;
-      if ((rc = norm_inf<double>(pl, pl->d64.R[0], MN, &s.warm_res0))) return rc;
-      if (std::isfinite(s.warm_res0)) {
+      // float64 cycles do not need the prediction's defect (the judge is the
+      // residual after the first cycles); refinement steps start from it
+      if (pl->mixed || (flags & MGWR_WARM_RES0)) {
+        if ((rc = defect<double>(pl, pl->d64, 0, b, u, pl->d64.R[0]))) return rc;
+        if ((rc = norm_inf<double>(pl, pl->d64.R[0], MN, &s.warm_res0))) return rc;
+      } else {
+        s.warm_res0 = std::nan("");
+        warm_unchecked = true;
+      }
+      if (warm_unchecked || std::isfinite(s.warm_res0)) {
         s.used_warm_start = 1;
         flags |= MGWR_GUESS_IN_U;
       }
@@ -674,8 +682,13 @@ int prepare_solve(mgwr_plan* pl, const double* f, const double* g, double tol, d
     s.res0 = s.bnorm;
   }
   s.res = s.res0;
-  if (!std::isfinite(s.res0)) status = MGWR_ERR_NONFINITE;
-  else if (s.res0 <= tol * s.bnorm) status = MGWR_OK;
+  if (warm_unchecked) {
+    s.res = s.bnorm;   // not evaluated: the first cycles' residual decides
+  } else if (!std::isfinite(s.res0)) {
+    status = MGWR_ERR_NONFINITE;
+  } else if (s.res0 <= tol * s.bnorm) {
+    status = MGWR_OK;
+  }
   return MGWR_OK;
 }
 

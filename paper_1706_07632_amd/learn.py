@@ -133,7 +133,7 @@ def gain(net, problems, tol: float = 1e-8, precision: str = "fp64", repeats: int
             for _ in range(repeats):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                _, st = plan.solve(f, tol=tol, warm_start=ws)
+                _, st = plan.solve(f, tol=tol, warm_start=ws, warm_res0=ws)
                 torch.cuda.synchronize()
                 dt = time.perf_counter() - t0
             out[form] = {"cycles": st["cycles"], "seconds": dt, "rel_res": st["res"] / st["bnorm"],

@@ -180,7 +180,7 @@ def test_warm_start_guess_and_solution_match_oracle(dev, dim, n, M, schedule):
     plan = _plan(p, schedule=schedule)
     learn.attach(plan, net)
     f = torch.as_tensor(p.f, dtype=torch.float64, device=dev)
-    u, st = plan.solve(f, tol=1e-10, warm_start=True)
+    u, st = plan.solve(f, tol=1e-10, warm_start=True, warm_res0=True)
     U0, res0, Rt, b = _oracle_guess(p, params, ch, plan)
     assert abs(st["warm_res0"] - res0) <= 1e-3 * res0, (st["warm_res0"], res0)
     U = oracle.timestep_solve(Rt, b, p.dim, p.n, p.length)
@@ -200,7 +200,7 @@ def test_warm_start_falls_back_on_nan_weights(dev, schedule):
     plan.solve(f, tol=1e-10)
     _, st0 = plan.solve(f, tol=1e-10)   # with the learned cycle count
     learn.attach(plan, net)
-    u, st = plan.solve(f, tol=1e-10, warm_start=True)
+    u, st = plan.solve(f, tol=1e-10, warm_start=True, warm_res0=True)
     assert st["used_warm_start"] == 0 and not np.isfinite(st["warm_res0"])
     assert st["cycles"] == st0["cycles"]
     assert st["res"] <= 1e-10 * st["bnorm"]
@@ -218,13 +218,26 @@ def test_warm_start_falls_back_on_a_bad_prediction(dev, schedule):
     plan = _plan(p, schedule=schedule)
     learn.attach(plan, net)
     f = torch.as_tensor(p.f, dtype=torch.float64, device=dev)
-    u, st = plan.solve(f, tol=1e-10, warm_start=True)
+    u, st = plan.solve(f, tol=1e-10, warm_start=True, warm_res0=True)
     assert np.isfinite(st["warm_res0"]) and st["warm_res0"] > st["bnorm"]
     assert st["used_warm_start"] == 0
     assert st["res"] <= 1e-10 * st["bnorm"]
     b = oracle.rhs(p.f, p.t, p.alpha, None)
     r = oracle.residual(plan.export_dense(), u.cpu().numpy(), b, p.dim, p.n, p.length)
     assert np.abs(r).max() <= 1.5e-10 * np.abs(b).max()
+
+
+@pytest.mark.parametrize("schedule", ["auto", "staged"])
+def test_unchecked_nan_prediction_is_caught_by_the_first_cycles(dev, schedule):
+    p = _problem(1, 63, 128, 52)
+    ch = learn.channels()
+    net = make(ch, 32, np.full(N.param_count(ch), np.nan, dtype=np.float32), p.N)
+    plan = _plan(p, schedule=schedule)
+    learn.attach(plan, net)
+    f = torch.as_tensor(p.f, dtype=torch.float64, device=dev)
+    u, st = plan.solve(f, tol=1e-10, warm_start=True)    # the prediction's defect is not evaluated
+    assert st["used_warm_start"] == 0 and np.isnan(st["warm_res0"])
+    assert st["res"] <= 1e-10 * st["bnorm"] and np.isfinite(u.cpu().numpy()).all()
 
 
 def test_warm_start_with_zero_network_is_the_zero_iterate(dev):
@@ -236,7 +249,7 @@ def test_warm_start_with_zero_network_is_the_zero_iterate(dev):
     plan.solve(f, tol=1e-10)
     u0, st0 = plan.solve(f, tol=1e-10)   # with the learned cycle count
     learn.attach(plan, net)
-    u1, st1 = plan.solve(f, tol=1e-10, warm_start=True)
+    u1, st1 = plan.solve(f, tol=1e-10, warm_start=True, warm_res0=True)
     assert st1["used_warm_start"] == 1 and st1["warm_res0"] == st1["bnorm"]
     assert st1["cycles"] == st0["cycles"]
     assert torch.allclose(u0, u1, rtol=0, atol=1e-13 * float(u0.abs().max()))
@@ -280,7 +293,7 @@ def test_learned_gain_small(dev):
             for _ in range(2):
                 _, s0 = plan.solve(f, tol=1e-8)
             for _ in range(2):
-                _, s1 = plan.solve(f, tol=1e-8, warm_start=True)
+                _, s1 = plan.solve(f, tol=1e-8, warm_start=True, warm_res0=True)
             assert s0["res"] <= 1e-8 * s0["bnorm"] and s1["res"] <= 1e-8 * s1["bnorm"]
             out.append((s0["cycles"], s1["cycles"], s1["used_warm_start"], s1["warm_res0"] / s1["bnorm"]))
             plan.close()
