@@ -107,6 +107,7 @@ struct mgwr_plan {
   int khint_warm = 0;                  // the same from a predicted iterate
   int tuned = 0;                       // schedule measured best by mgwr_plan_autotune (0: none)
   int khint_staged = 0;                // cycles the last staged float64 solve from zero needed
+  int khint_staged_warm = 0;           // the same from a predicted iterate
   double cycle_flops = 0.0, cycle_bytes = 0.0;  // algorithmic work of one pipelined cycle
   // learned initial guess
   static constexpr int kMaxSlices = 64;
@@ -1139,22 +1140,28 @@ int mgwr_solve(mgwr_plan* pl, const double* f, const double* g, double tol, doub
     // with a cycle count learned from the last solve from zero, the stopping
     // test (a float64 defect, its norm and a host read) is first evaluated
     // after that many cycles
-    const int skip_to = (!(flags & MGWR_GUESS_IN_U) && pl->khint_staged > 0) ? pl->khint_staged : 0;
+    // (a predicted iterate is still judged after its first cycle)
+    int skip_to = 0;
+    if (!(flags & MGWR_GUESS_IN_U)) skip_to = pl->khint_staged;
+    else if (s.used_warm_start) skip_to = pl->khint_staged_warm;
     while (s.cycles < hp.p.max_cycles) {
       if ((rc = cycle<double>(pl, pl->d64, 0))) return rc;
       s.cycles++;
-      if (s.cycles < skip_to) continue;
+      const bool judge = s.used_warm_start && s.cycles == 1;
+      if (!judge && s.cycles < skip_to) continue;
       if ((rc = defect<double>(pl, pl->d64, 0, b, u, pl->d64.R[0]))) return rc;
       if ((rc = norm_inf<double>(pl, pl->d64.R[0], MN, &s.res))) return rc;
       if (s.cycles <= 64) s.history[s.cycles - 1] = s.res;
       if (s.cycles == 1 && fall_back_to_zero(pl, b, u, s, &rc)) {
         if (rc) return rc;
+        skip_to = 0;
         continue;
       }
       if (!std::isfinite(s.res)) { status = MGWR_ERR_NONFINITE; break; }
       if (s.res <= target) { status = MGWR_OK; break; }
     }
-    if (status == MGWR_OK && !(flags & MGWR_GUESS_IN_U) && s.used_warm_start == 0) pl->khint_staged = s.cycles;
+    if (status == MGWR_OK && !(flags & MGWR_GUESS_IN_U)) pl->khint_staged = s.cycles;
+    if (status == MGWR_OK && s.used_warm_start) pl->khint_staged_warm = s.cycles;
   } else if (status == MGWR_ERR_NOT_CONVERGED) {
     // float64 outer residual and correction; float32 inner cycles on A e = r
     if (!(flags & MGWR_GUESS_IN_U)) {

@@ -41,99 +41,163 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
   return (uint16_t)(u >> 16);
 }
 
-constexpr int kCoTile = 8;  // output (forward) or input (data gradient) channels per thread
+constexpr int kCoTile = 8;   // output (forward) or input (data gradient) channels per thread
+constexpr int kPx = 2;       // pixels per thread (weights read once from LDS serve both)
+constexpr int kCiChunk = 64; // input channels whose weights a block stages in LDS at a time
 
-// Forward convolution.  Grid: x = pixel blocks of 256 over B*H*W, y = groups
-// of kCoTile output channels (uniform per block, so weight reads are uniform).
+// Forward convolution.  Grid: x = blocks of 256 x kPx pixels over B*H*W, y =
+// groups of kCoTile output channels.  The block's weights (bfloat16 ->
+// float32) are staged in LDS per chunk of input channels; every thread
+// computes kCoTile channels of kPx pixels (p and p + 256).
 // y[b][co][p] = bias[co] + sum_ci sum_k w[co][ci][k] x[b][ci][p + off(k)]
 __global__ __launch_bounds__(256) void conv_fwd_kernel(const float* __restrict__ x, const uint16_t* __restrict__ w,
                                                        const float* __restrict__ bias, float* __restrict__ y, int B,
                                                        int cin, int cout, int H, int W, int act) {
+  __shared__ float wsh[kCoTile][kCiChunk * 9];
   const int HW = H * W;
-  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long total = (long long)B * HW;
   const int co0 = blockIdx.y * kCoTile;
-  if (t >= (long long)B * HW) return;
-  const int b = (int)(t / HW), p = (int)(t % HW);
-  const int py = p / W, px = p % W;
-  int off[9];
-  bool ok[9];
+  long long t[kPx];
+  bool tok[kPx];
+  int off[kPx][9];
+  bool ok[kPx][9];
+  const float* xb[kPx];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    const int yy = py + k / 3 - 1, xx = px + k % 3 - 1;
-    ok[k] = yy >= 0 && yy < H && xx >= 0 && xx < W;
-    off[k] = ok[k] ? yy * W + xx : 0;
+  for (int u = 0; u < kPx; ++u) {
+    t[u] = (long long)blockIdx.x * (256 * kPx) + u * 256 + threadIdx.x;
+    tok[u] = t[u] < total;
+    const long long tt = tok[u] ? t[u] : 0;
+    const int b = (int)(tt / HW), p = (int)(tt % HW);
+    const int py = p / W, px = p % W;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const int yy = py + k / 3 - 1, xx = px + k % 3 - 1;
+      ok[u][k] = tok[u] && yy >= 0 && yy < H && xx >= 0 && xx < W;
+      off[u][k] = ok[u][k] ? yy * W + xx : 0;
+    }
+    xb[u] = x + (long long)b * cin * HW;
   }
-  float acc[kCoTile];
+  float acc[kPx][kCoTile];
 #pragma unroll
-  for (int j = 0; j < kCoTile; ++j) acc[j] = co0 + j < cout ? bias[co0 + j] : 0.0f;
-  const float* xb = x + (long long)b * cin * HW;
-  for (int ci = 0; ci < cin; ++ci) {
-    float xv[9];
+  for (int j = 0; j < kCoTile; ++j) {
+    const float bj = co0 + j < cout ? bias[co0 + j] : 0.0f;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) xv[k] = ok[k] ? xb[(long long)ci * HW + off[k]] : 0.0f;
+    for (int u = 0; u < kPx; ++u) acc[u][j] = bj;
+  }
+  for (int c0 = 0; c0 < cin; c0 += kCiChunk) {
+    const int nc = min(kCiChunk, cin - c0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < kCoTile * nc * 9; e += 256) {
+      const int j = e / (nc * 9), r = e % (nc * 9);
+      wsh[j][r] = co0 + j < cout ? bf16_to_f32(w[((long long)(co0 + j) * cin + c0) * 9 + r]) : 0.0f;
+    }
+    __syncthreads();
+    for (int ci = 0; ci < nc; ++ci) {
+      float xv[kPx][9];
 #pragma unroll
-    for (int j = 0; j < kCoTile; ++j) {
-      if (co0 + j < cout) {
-        const uint16_t* wk = w + ((long long)(co0 + j) * cin + ci) * 9;
+      for (int u = 0; u < kPx; ++u)
 #pragma unroll
-        for (int k = 0; k < 9; ++k) acc[j] += bf16_to_f32(wk[k]) * xv[k];
+        for (int k = 0; k < 9; ++k) xv[u][k] = ok[u][k] ? xb[u][(long long)(c0 + ci) * HW + off[u][k]] : 0.0f;
+#pragma unroll
+      for (int j = 0; j < kCoTile; ++j) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+          const float wv = wsh[j][ci * 9 + k];
+#pragma unroll
+          for (int u = 0; u < kPx; ++u) acc[u][j] += wv * xv[u][k];
+        }
       }
     }
   }
-  float* yb = y + (long long)b * cout * HW + p;
 #pragma unroll
-  for (int j = 0; j < kCoTile; ++j)
-    if (co0 + j < cout) yb[(long long)(co0 + j) * HW] = act ? tanhf(acc[j]) : acc[j];
+  for (int u = 0; u < kPx; ++u) {
+    if (!tok[u]) continue;
+    const int b = (int)(t[u] / HW), p = (int)(t[u] % HW);
+    float* yb = y + (long long)b * cout * HW + p;
+#pragma unroll
+    for (int j = 0; j < kCoTile; ++j)
+      if (co0 + j < cout) yb[(long long)(co0 + j) * HW] = act ? tanhf(acc[u][j]) : acc[u][j];
+  }
 }
 
-// Data gradient.  Grid: x = pixel blocks, y = groups of kCoTile input channels.
+// Data gradient.  Grid: x = blocks of 256 x kPx pixels, y = groups of kCoTile
+// input channels; the weights w[co][ci0..ci0+7][.] of a chunk of output
+// channels are staged in LDS.
 // dx[b][ci][p] = sum_co sum_k w[co][ci][k] dy[b][co][p - off(k)], times
 // (1 - a^2) when the layer's input is the tanh output a of the previous layer.
 __global__ __launch_bounds__(256) void conv_bwd_data_kernel(const float* __restrict__ dy,
                                                             const uint16_t* __restrict__ w,
                                                             const float* __restrict__ a_prev, float* __restrict__ dx,
                                                             int B, int cin, int cout, int H, int W, int act_prev) {
+  __shared__ float wsh[kCiChunk][kCoTile * 9];   // [co - c0][j * 9 + k]
   const int HW = H * W;
-  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long total = (long long)B * HW;
   const int ci0 = blockIdx.y * kCoTile;
-  if (t >= (long long)B * HW) return;
-  const int b = (int)(t / HW), p = (int)(t % HW);
-  const int py = p / W, px = p % W;
-  int off[9];
-  bool ok[9];
+  long long t[kPx];
+  bool tok[kPx];
+  int off[kPx][9];
+  bool ok[kPx][9];
+  const float* db[kPx];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    const int yy = py - (k / 3 - 1), xx = px - (k % 3 - 1);
-    ok[k] = yy >= 0 && yy < H && xx >= 0 && xx < W;
-    off[k] = ok[k] ? yy * W + xx : 0;
+  for (int u = 0; u < kPx; ++u) {
+    t[u] = (long long)blockIdx.x * (256 * kPx) + u * 256 + threadIdx.x;
+    tok[u] = t[u] < total;
+    const long long tt = tok[u] ? t[u] : 0;
+    const int b = (int)(tt / HW), p = (int)(tt % HW);
+    const int py = p / W, px = p % W;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const int yy = py - (k / 3 - 1), xx = px - (k % 3 - 1);
+      ok[u][k] = tok[u] && yy >= 0 && yy < H && xx >= 0 && xx < W;
+      off[u][k] = ok[u][k] ? yy * W + xx : 0;
+    }
+    db[u] = dy + (long long)b * cout * HW;
   }
-  float acc[kCoTile];
+  float acc[kPx][kCoTile];
 #pragma unroll
-  for (int j = 0; j < kCoTile; ++j) acc[j] = 0.0f;
-  const float* db = dy + (long long)b * cout * HW;
-  for (int co = 0; co < cout; ++co) {
-    float dv[9];
+  for (int u = 0; u < kPx; ++u)
 #pragma unroll
-    for (int k = 0; k < 9; ++k) dv[k] = ok[k] ? db[(long long)co * HW + off[k]] : 0.0f;
+    for (int j = 0; j < kCoTile; ++j) acc[u][j] = 0.0f;
+  for (int c0 = 0; c0 < cout; c0 += kCiChunk) {
+    const int nc = min(kCiChunk, cout - c0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < nc * kCoTile * 9; e += 256) {
+      const int co = e / (kCoTile * 9), r = e % (kCoTile * 9), j = r / 9, k = r % 9;
+      wsh[co][r] = ci0 + j < cin ? bf16_to_f32(w[((long long)(c0 + co) * cin + ci0 + j) * 9 + k]) : 0.0f;
+    }
+    __syncthreads();
+    for (int co = 0; co < nc; ++co) {
+      float dv[kPx][9];
 #pragma unroll
-    for (int j = 0; j < kCoTile; ++j) {
-      if (ci0 + j < cin) {
-        const uint16_t* wk = w + ((long long)co * cin + ci0 + j) * 9;
+      for (int u = 0; u < kPx; ++u)
 #pragma unroll
-        for (int k = 0; k < 9; ++k) acc[j] += bf16_to_f32(wk[k]) * dv[k];
+        for (int k = 0; k < 9; ++k) dv[u][k] = ok[u][k] ? db[u][(long long)(c0 + co) * HW + off[u][k]] : 0.0f;
+#pragma unroll
+      for (int j = 0; j < kCoTile; ++j) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+          const float wv = wsh[co][j * 9 + k];
+#pragma unroll
+          for (int u = 0; u < kPx; ++u) acc[u][j] += wv * dv[u][k];
+        }
       }
     }
   }
 #pragma unroll
-  for (int j = 0; j < kCoTile; ++j) {
-    if (ci0 + j < cin) {
-      const long long idx = ((long long)b * cin + ci0 + j) * HW + p;
-      float v = acc[j];
-      if (act_prev) {
-        const float a = a_prev[idx];
-        v *= 1.0f - a * a;
+  for (int u = 0; u < kPx; ++u) {
+    if (!tok[u]) continue;
+    const int b = (int)(t[u] / HW), p = (int)(t[u] % HW);
+#pragma unroll
+    for (int j = 0; j < kCoTile; ++j) {
+      if (ci0 + j < cin) {
+        const long long idx = ((long long)b * cin + ci0 + j) * HW + p;
+        float v = acc[u][j];
+        if (act_prev) {
+          const float a = a_prev[idx];
+          v *= 1.0f - a * a;
+        }
+        dx[idx] = v;
       }
-      dx[idx] = v;
     }
   }
 }
@@ -600,7 +664,7 @@ int check_net(mgwr_net* net, int B, int H, int W, Geo* g) {
 int launch_conv_fwd(mgwr_net* net, int j, const float* in, float* out, int B, int H, int W) {
   const int cin = net->ch[j], cout = net->ch[j + 1];
   const long long px = (long long)B * H * W;
-  dim3 grid((unsigned)((px + 255) / 256), (unsigned)((cout + kCoTile - 1) / kCoTile));
+  dim3 grid((unsigned)((px + 256 * kPx - 1) / (256 * kPx)), (unsigned)((cout + kCoTile - 1) / kCoTile));
   hipLaunchKernelGGL(conv_fwd_kernel, grid, dim3(256), 0, net->stream, in, net->wbf + net->woff[j],
                      net->params + net->boff[j], out, B, cin, cout, H, W, j + 1 < net->L() ? 1 : 0);
   NET_TRY(hipGetLastError());
@@ -792,7 +856,7 @@ int mgwr_net_gradient(mgwr_net* net, const float* x, const float* target, int B,
       NET_TRY(hipGetLastError());
       if (j > 0) {
         const long long px = (long long)B * Hl * Wl;
-        dim3 grid((unsigned)((px + 255) / 256), (unsigned)((cin + kCoTile - 1) / kCoTile));
+        dim3 grid((unsigned)((px + 256 * kPx - 1) / (256 * kPx)), (unsigned)((cin + kCoTile - 1) / kCoTile));
         hipLaunchKernelGGL(conv_bwd_data_kernel, grid, dim3(256), 0, net->stream, dcur, net->wbf + net->woff[j], in,
                            dnext, B, cin, cout, Hl, Wl, 1);
         NET_TRY(hipGetLastError());
