@@ -92,7 +92,8 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const float* __restrict__
       wsh[j][r] = co0 + j < cout ? bf16_to_f32(w[((long long)(co0 + j) * cin + c0) * 9 + r]) : 0.0f;
     }
     __syncthreads();
-    for (int ci = 0; ci < nc; ++ci) {
+#pragma unroll 4
+    for (int ci = 0; ci < nc; ++ci) {   // unrolled: several channels' loads in flight (small images are latency-bound)
       float xv[kPx][9];
 #pragma unroll
       for (int u = 0; u < kPx; ++u)
@@ -166,6 +167,7 @@ __global__ __launch_bounds__(256) void conv_bwd_data_kernel(const float* __restr
       wsh[co][r] = ci0 + j < cin ? bf16_to_f32(w[((long long)(c0 + co) * cin + ci0 + j) * 9 + k]) : 0.0f;
     }
     __syncthreads();
+#pragma unroll 4
     for (int co = 0; co < nc; ++co) {
       float dv[kPx][9];
 #pragma unroll
@@ -616,6 +618,24 @@ struct mgwr_net {
   float *g0 = nullptr, *g1 = nullptr;  // backprop scratch of one level [cap * maxc]
   double* norms = nullptr;          // per-sample loss norms
   double h_min = 0.0;               // levels with h_l < h_min contribute nothing
+  // the solver's inference replayed from a captured graph while its input
+  // array, grid and spacing stay the same (the weights are read at replay)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  hipStream_t capture_stream = nullptr;
+  const float* graph_x = nullptr;
+  int graph_H = 0, graph_W = 0;
+  double graph_h = 0.0;
+  void drop_graph() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    graph_exec = nullptr;
+    graph = nullptr;
+  }
+  ~mgwr_net() {
+    drop_graph();
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
+  }
   static constexpr int kMaxBatch = 4096;
 
   // a level takes part when its spacing is not finer than h_min
@@ -790,6 +810,7 @@ int mgwr_net_bind(mgwr_net* net, float* params_dev, long long max_bhw, void* ws,
                      net->params, net->wbf, (long long)net->nparam);
   NET_TRY(hipGetLastError());
   NET_TRY(hipStreamSynchronize(net->stream));
+  net->drop_graph();
   net->bound = true;
   return MGWR_OK;
 }
@@ -881,6 +902,7 @@ int mgwr_net_set_finest(mgwr_net* net, double h_min) {
   if (!net) return nfail(MGWR_ERR_INVALID_ARG, "null network");
   if (!(h_min >= 0.0) || !std::isfinite(h_min)) return nfail(MGWR_ERR_INVALID_ARG, "h_min must be >= 0");
   net->h_min = h_min;
+  net->drop_graph();
   return MGWR_OK;
 }
 
@@ -908,8 +930,33 @@ int net_infer(mgwr_net* net, const float* x, int H, int W, double h, const float
   int rc = check_net(net, 1, H, W, &g);
   if (rc) return rc;
   if (!valid_h(h)) return nfail(MGWR_ERR_INVALID_ARG, "h must be positive");
-  if ((rc = net_forward(net, x, g, h))) return rc;
   *y = net->ybuf;
+  if (net->graph_exec && net->graph_x == x && net->graph_H == H && net->graph_W == W && net->graph_h == h) {
+    NET_TRY(hipGraphLaunch(net->graph_exec, net->stream));
+    return MGWR_OK;
+  }
+  // capture the ~60 small launches of one inference once (on a private
+  // stream: the caller's may be the legacy stream), then replay
+  net->drop_graph();
+  if (!net->capture_stream) NET_TRY(hipStreamCreateWithFlags(&net->capture_stream, hipStreamNonBlocking));
+  hipStream_t keep = net->stream;
+  net->stream = net->capture_stream;
+  NET_TRY(hipStreamBeginCapture(net->capture_stream, hipStreamCaptureModeRelaxed));
+  rc = net_forward(net, x, g, h);
+  hipGraph_t gr = nullptr;
+  const hipError_t e = hipStreamEndCapture(net->capture_stream, &gr);
+  net->stream = keep;
+  if (rc || e != hipSuccess) {
+    if (gr) (void)hipGraphDestroy(gr);
+    return rc ? rc : nfail(MGWR_ERR_HIP, "capturing the inference failed");
+  }
+  net->graph = gr;
+  NET_TRY(hipGraphInstantiate(&net->graph_exec, gr, nullptr, nullptr, 0));
+  net->graph_x = x;
+  net->graph_H = H;
+  net->graph_W = W;
+  net->graph_h = h;
+  NET_TRY(hipGraphLaunch(net->graph_exec, net->stream));
   return MGWR_OK;
 }
 int net_signal_channels(const mgwr_net* net) { return net->nsig; }

@@ -189,6 +189,32 @@ def test_warm_start_guess_and_solution_match_oracle(dev, dim, n, M, schedule):
     assert np.abs(u.cpu().numpy() - U).max() <= 1e-8 * np.abs(U).max()
 
 
+def test_inference_graph_replays_match_eager_inference(dev):
+    """The solver replays its inference from a captured graph: three
+    warm-started solves with other work in between (eager inference on
+    another input, another plan's solve, a weight update) each give the
+    prediction the oracle computes for the weights of that moment."""
+    p = _problem(1, 63, 128, 91)
+    ch = learn.channels()
+    params = bf16_params(ch, 92, scale=0.5)
+    net = make(ch, 32, params, 4 * p.N)
+    plan = _plan(p)
+    learn.attach(plan, net)
+    other_p = _problem(1, 31, 64, 93)
+    other = _plan(other_p)
+    f = torch.as_tensor(p.f, dtype=torch.float64, device=dev)
+    for rep in range(3):
+        if rep == 2:   # new weights: the replay must read them
+            params = bf16_params(ch, 94, scale=0.5)
+            net.set_params(params)
+        _, st = plan.solve(f, tol=1e-10, warm_start=True, warm_res0=True)
+        res0 = _oracle_guess(p, params, ch, plan)[1]
+        assert abs(st["warm_res0"] - res0) <= 1e-3 * res0, (rep, st["warm_res0"], res0)
+        net.forward(torch.randn((2, 34, 1, 63), dtype=torch.float32, device=dev), 1.0 / 64)   # eager use
+        other.solve(torch.as_tensor(other_p.f, dtype=torch.float64, device=dev), tol=1e-10)
+        torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("schedule", ["auto", "staged"])
 def test_warm_start_falls_back_on_nan_weights(dev, schedule):
     p = _problem(1, 63, 128, 51)
