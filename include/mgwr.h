@@ -305,6 +305,8 @@ typedef struct {
   int M, nleaf, nclusters, ndense, nrk, nzclusters, nslots, window, levels, k;
   long long stored_entries;  /* dense entries + k (|rows| + |cols|) over low-rank blocks */
   double shift0;             /* c_0 = 2 dim / h^2 */
+  int nf64leaves;            /* leaves solved in float64 inside float32 cycles (steps within the leaf
+                                differ by more than 8x: the near-origin leaves of graded meshes) */
 } mgwr_plan_info;
 int mgwr_plan_get_info(const mgwr_plan* plan, mgwr_plan_info* info);
 

@@ -80,7 +80,8 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int), ("nleaf", ctypes.c_int), ("nclusters", ctypes.c_int),
                 ("ndense", ctypes.c_int), ("nrk", ctypes.c_int), ("nzclusters", ctypes.c_int),
                 ("nslots", ctypes.c_int), ("window", ctypes.c_int), ("levels", ctypes.c_int),
-                ("k", ctypes.c_int), ("stored_entries", ctypes.c_longlong), ("shift0", ctypes.c_double)]
+                ("k", ctypes.c_int), ("stored_entries", ctypes.c_longlong), ("shift0", ctypes.c_double),
+                ("nf64leaves", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -259,6 +259,16 @@ std::string build_host_plan(const mgwr_params& p, const double* t_host, HostPlan
     LeafDesc& d = pk.leaves[i];
     d.lo = L.lo;
     d.sz = L.hi - L.lo;
+    {
+      // near the origin of a graded mesh the steps inside one leaf span
+      // orders of magnitude; float32 inner cycles solve such leaves in float64
+      double dmin = 1e300, dmax = 0.0;
+      for (int r = 0; r < d.sz; ++r) {
+        dmin = std::min(dmin, dt[d.lo + r + 1]);
+        dmax = std::max(dmax, dt[d.lo + r + 1]);
+      }
+      d.f64solve = dmax > kF64LeafStepRatio * dmin ? 1 : 0;
+    }
     // dense off-diagonal blocks, then the unshifted diagonal
     d.dn_begin = (int)pk.dn_list.size() / 2;
     std::sort(dense_by_row[i].begin(), dense_by_row[i].end());

@@ -12,12 +12,17 @@ namespace mgwr {
 
 // Per-leaf program of the time-marching kernels.  All offsets index the
 // packed arrays of PackedPlan.  Mirrored bit-for-bit on the device.
+// A leaf whose time steps differ by more than this factor is solved in
+// float64 inside float32 cycles (the near-origin leaves of graded meshes).
+constexpr double kF64LeafStepRatio = 8.0;
+
 struct LeafDesc {
   int lo, sz;            // first time row (0-based) and number of rows (<= 16)
   int dn_begin, dn_end;  // dense off-diagonal blocks (j < i): pairs in dn_list
   int diag_off;          // unshifted diagonal block (negated) in `dense`, in units of 256 values
   int ff_begin, ff_nchunk;  // far-field: ff_row[4*ff_begin ...], ffA chunk index ff_begin ...
   int zu_begin, zu_ntile;   // column-side updates: zu_row[16*zu_begin ...], zuB tile zu_begin ...
+  int f64solve;          // float32 cycles solve this leaf in float64 (steps within it differ by more than 8x)
 };
 
 // One multigrid level (space only; the time operator is shared).

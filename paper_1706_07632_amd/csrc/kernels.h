@@ -19,6 +19,7 @@ struct MarchArgs {
   const int* dn_list;
   const T* dense;
   const T* dinv;      // this level's shifted diagonal inverses [nleaf][256] (SMOOTH/TRSM)
+  const double* dinv_hi;  // float64 copies of them, for leaves flagged f64solve in float32 cycles (or null)
   const int* ff_row;
   const T* ffA;
   const int* zu_row;

@@ -454,12 +454,30 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
 #pragma unroll
           for (int r = 0; r < 4; ++r) tbuf[drow<T>(g, r) * 16 + c] = acc[r];
           __builtin_amdgcn_wave_barrier();
+          if (!(d.f64solve && a.dinv_hi)) {
 #pragma unroll
-          for (int kc = 0; kc < 4; ++kc) x = mfma(di[kc], tbuf[(4 * kc + g) * 16 + c], x);
+            for (int kc = 0; kc < 4; ++kc) x = mfma(di[kc], tbuf[(4 * kc + g) * 16 + c], x);
+          }
+        }
+        if constexpr (sizeof(T) == 4) {
+          if (d.f64solve && a.dinv_hi) {
+            // near-origin leaf of a graded mesh: float64 inverse and product,
+            // rounded to float32 once (f64 result rows are g + 4r)
+            d4 xh = {0, 0, 0, 0};
+            const double* Dh = a.dinv_hi + (long long)s * 256;
+#pragma unroll
+            for (int kc = 0; kc < 4; ++kc) xh = mfma(ld(Dh + kc * 64 + lane), (double)tbuf[(4 * kc + g) * 16 + c], xh);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) x[r] = (T)xh[r];
+          }
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int row = drow<T>(g, r);
+          // float32 rows follow drow<float> except after a float64 leaf solve (drow<double>)
+          int row = drow<T>(g, r);
+          if constexpr (sizeof(T) == 4) {
+            if (d.f64solve && a.dinv_hi) row = drow<double>(g, r);
+          }
           cur[row * 16 + c] = (colok && row < d.sz) ? x[r] : (T)0;   // to global memory by the split-IO wave
         }
       } else {

@@ -249,6 +249,7 @@ MarchArgs<T> base_args(mgwr_plan* pl, const DevOps<T>& ops, int level) {
   a.dn_list = pl->dn_list;
   a.dense = ops.dense;
   a.dinv = ops.dinv + (size_t)level * a.nleaf * 256;
+  a.dinv_hi = sizeof(T) == 4 ? pl->d64.dinv + (size_t)level * a.nleaf * 256 : nullptr;
   a.ff_row = pl->ff_row;
   a.ffA = ops.ffA;
   a.zu_row = pl->zu_row;
@@ -1285,6 +1286,8 @@ int mgwr_plan_get_info(const mgwr_plan* pl, mgwr_plan_info* info) {
   info->k = hp.p.k;
   info->stored_entries = hp.stored;
   info->shift0 = hp.levels[0].shift;
+  info->nf64leaves = 0;
+  for (const LeafDesc& d : hp.pk.leaves) info->nf64leaves += d.f64solve;
   return MGWR_OK;
 }
 

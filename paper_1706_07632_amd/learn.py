@@ -184,6 +184,9 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--out", required=True)
+    ap.add_argument("--gen-tol", type=float, default=1e-10,
+                    help="relative residual of the solver runs that produce the targets (the float64 floor is "
+                         "about 2e-10 at h = 1/1024)")
     ap.add_argument("--eval-n", type=int, default=0, help="held-out evaluation grid (0: skip)")
     ap.add_argument("--eval-M", type=int, default=0)
     ap.add_argument("--eval-count", type=int, default=4)
@@ -196,8 +199,8 @@ def main(argv=None):
     H, Wd = grid_shape(a.dim, a.n)
     h = 1.0 / (a.n + 1)
     log(f"generating {a.count} + {a.val} samples: dim={a.dim} n={a.n} M={a.M}")
-    X, Y, cyc = generate(a.dim, a.n, a.M, a.count, a.seed, log=log)
-    Xv, Yv, _ = generate(a.dim, a.n, a.M, a.val, a.seed + 1000)
+    X, Y, cyc = generate(a.dim, a.n, a.M, a.count, a.seed, tol=a.gen_tol, log=log)
+    Xv, Yv, _ = generate(a.dim, a.n, a.M, a.val, a.seed + 1000, tol=a.gen_tol)
     log(f"solver cycles per sample: mean {np.mean(cyc):.2f}")
     net = make_net(max(a.batch, 16) * H * Wd, seed=a.seed)
     losses = train(net, X, Y, h, a.steps, a.batch, a.lr, log=log)

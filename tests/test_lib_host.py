@@ -118,3 +118,16 @@ def test_kernel_algorithm_emulated_on_cpu(args):
                        check=True)
         out = subprocess.run([exe] + args.split(), check=True, capture_output=True, text=True).stdout.split()
     assert float(out[0]) < 1e-12 and float(out[1]) < 1e-12, out
+
+
+@pytest.mark.parametrize("M,alpha,r,leaf", [(4096, 0.3, 17 / 3, 16), (1024, 0.5, 3.0, 16), (256, 0.5, 1.0, 16),
+                                            (300, 0.7, 1 / 0.7, 12)])
+def test_near_origin_leaves_flagged_for_float64(M, alpha, r, leaf):
+    """Leaves whose steps span more than a factor 8 are the ones float32 cycles
+    solve in float64 (graded meshes only; a uniform mesh has none)."""
+    plan = mg.Plan(1, 15, M, alpha, k=8, r=r, leaf=leaf)
+    t, _ = plan.mesh()
+    dt = np.diff(t)
+    want = sum(1 for lo in range(0, M, leaf) if dt[lo:lo + leaf].max() > 8.0 * dt[lo:lo + leaf].min())
+    assert plan.info()["nf64leaves"] == want
+    assert (want > 0) == (r > 1.5)
