@@ -582,7 +582,7 @@ constexpr int kStencilRowsPerPass = 256 / kStencilCols;
 // Full-weighting restriction of the rows of one leaf, and the zero start of
 // the coarse iterate on those rows.
 template <typename T>
-__device__ void restrict_stage(const Stage& st, int chunk, const PipeCtx& pc, int* sh_abort) {
+__device__ __forceinline__ void restrict_stage(const Stage& st, int chunk, const PipeCtx& pc, int* sh_abort) {
   const T* src = static_cast<const T*>(st.src);
   T* dst = static_cast<T*>(st.dst);
   T* zero = static_cast<T*>(st.zero);
@@ -593,25 +593,24 @@ __device__ void restrict_stage(const Stage& st, int chunk, const PipeCtx& pc, in
   const int r0 = threadIdx.x / kStencilCols;
   const bool ok = Q < Nc;
   const int lane = threadIdx.x & 63;
-  // fine-grid offsets of the 9-point (2D) / 3-point (1D) weighted stencil
+  // fine-grid offsets of the 9-point (2D) / 3-point (1D) weighted stencil;
+  // tap t sits at a fixed index (registers, not private memory)
+  const int nw = st.dim == 1 ? 3 : 9;
   long long off[9];
   T wgt[9];
-  int nw = 0;
-  if (ok) {
-    if (st.dim == 1) {
-      const long long f = 2 * Q + 1;
-      off[0] = f - 1; wgt[0] = (T)0.25;
-      off[1] = f;     wgt[1] = (T)0.5;
-      off[2] = f + 1; wgt[2] = (T)0.25;
-      nw = 3;
-    } else {
-      const long long I = Q % nc, J = Q / nc;
-      const long long fx = 2 * I + 1, fy = 2 * J + 1;
-      for (int dy = -1; dy <= 1; ++dy)
-        for (int dx = -1; dx <= 1; ++dx) {
-          off[nw] = (fy + dy) * nf + fx + dx;
-          wgt[nw++] = (T)((dx == 0 ? 2 : 1) * (dy == 0 ? 2 : 1)) * (T)(1.0 / 16.0);
-        }
+  {
+    const long long I = st.dim == 1 ? Q : Q % nc, J = st.dim == 1 ? 0 : Q / nc;
+    const long long fx = 2 * I + 1, fy = 2 * J + 1;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      if (st.dim == 1) {
+        off[t] = fx - 1 + (t < 3 ? t : 0);
+        wgt[t] = t == 1 ? (T)0.5 : (T)0.25;
+      } else {
+        const int dy = t / 3 - 1, dx = t % 3 - 1;
+        off[t] = (fy + dy) * nf + fx + dx;
+        wgt[t] = (T)((dx == 0 ? 2 : 1) * (dy == 0 ? 2 : 1)) * (T)(1.0 / 16.0);
+      }
     }
   }
   for (int i = 0; i < st.nleaf; ++i) {
@@ -666,7 +665,7 @@ __device__ void restrict_stage(const Stage& st, int chunk, const PipeCtx& pc, in
 // Linear / bilinear interpolation of the coarse correction, added to the
 // fine iterate on the rows of one leaf.
 template <typename T>
-__device__ void prolong_stage(const Stage& st, int chunk, const PipeCtx& pc, int* sh_abort) {
+__device__ __forceinline__ void prolong_stage(const Stage& st, int chunk, const PipeCtx& pc, int* sh_abort) {
   const T* src = static_cast<const T*>(st.src);
   T* dst = static_cast<T*>(st.dst);
   const int nf = st.nf, nc = st.nc;
@@ -676,34 +675,35 @@ __device__ void prolong_stage(const Stage& st, int chunk, const PipeCtx& pc, int
   const int r0 = threadIdx.x / kStencilCols;
   const bool ok = q < Nf;
   const int lane = threadIdx.x & 63;
+  // coarse neighbours: slot t = 2 b + a of (y neighbour b, x neighbour a);
+  // an odd fine index has one neighbour (slot 0 of its axis), an even one two,
+  // the outer of which may lie on the boundary (cvalid false).  Fixed slots
+  // keep the tables in registers.
   long long cidx[4];
   T cw[4];
-  int ncoef = 0;
-  if (ok) {
-    if (st.dim == 1) {
-      if (q & 1) { cidx[0] = (q - 1) / 2; cw[0] = (T)1; ncoef = 1; }
-      else {
-        const long long I = q / 2;
-        if (I >= 1) { cidx[ncoef] = I - 1; cw[ncoef++] = (T)0.5; }
-        if (I < nc) { cidx[ncoef] = I; cw[ncoef++] = (T)0.5; }
-      }
-    } else {
-      const long long ix = q % nf, iy = q / nf;
-      long long cx[2], cy[2];
-      T wx[2], wy[2];
-      int nx, ny;
-      if (ix & 1) { cx[0] = (ix - 1) / 2; wx[0] = (T)1; nx = 1; }
-      else { cx[0] = ix / 2 - 1; cx[1] = ix / 2; wx[0] = wx[1] = (T)0.5; nx = 2; }
-      if (iy & 1) { cy[0] = (iy - 1) / 2; wy[0] = (T)1; ny = 1; }
-      else { cy[0] = iy / 2 - 1; cy[1] = iy / 2; wy[0] = wy[1] = (T)0.5; ny = 2; }
-      for (int b = 0; b < ny; ++b) {
-        if (cy[b] < 0 || cy[b] >= nc) continue;
-        for (int a2 = 0; a2 < nx; ++a2) {
-          if (cx[a2] < 0 || cx[a2] >= nc) continue;
-          cidx[ncoef] = cy[b] * nc + cx[a2];
-          cw[ncoef++] = wx[a2] * wy[b];
-        }
-      }
+  bool cvalid[4];
+  {
+    const long long ix = st.dim == 1 ? q : q % nf, iy = st.dim == 1 ? 1 : q / nf;
+    long long cx[2], cy[2];
+    T wx[2], wy[2];
+    bool vx[2], vy[2];
+    const bool oddx = ix & 1, oddy = iy & 1;
+    cx[0] = oddx ? (ix - 1) / 2 : ix / 2 - 1;
+    cx[1] = ix / 2;
+    wx[0] = wx[1] = oddx ? (T)1 : (T)0.5;
+    vx[0] = cx[0] >= 0 && cx[0] < nc;
+    vx[1] = !oddx && cx[1] < nc;
+    cy[0] = oddy ? (iy - 1) / 2 : iy / 2 - 1;
+    cy[1] = iy / 2;
+    wy[0] = wy[1] = oddy ? (T)1 : (T)0.5;
+    vy[0] = cy[0] >= 0 && cy[0] < nc;
+    vy[1] = !oddy && cy[1] < nc;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int b = t >> 1, a2 = t & 1;
+      cvalid[t] = ok && vx[a2] && vy[b];
+      cidx[t] = cvalid[t] ? (st.dim == 1 ? cx[a2] : cy[b] * nc + cx[a2]) : 0;
+      cw[t] = wx[a2] * wy[b];
     }
   }
   for (int i = 0; i < st.nleaf; ++i) {
@@ -723,7 +723,7 @@ __device__ void prolong_stage(const Stage& st, int chunk, const PipeCtx& pc, int
         const long long m = d.lo + (rok ? row : 0);
         const T* e = src + m * Nc;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) raw[j][t] = (rok && t < ncoef) ? gld<true>(e + cidx[t]) : (T)0;
+        for (int t = 0; t < 4; ++t) raw[j][t] = (rok && cvalid[t]) ? gld<true>(e + cidx[t]) : (T)0;
         u0[j] = rok ? gld<true>(dst + m * Nf + q) : (T)0;
       }
 #pragma unroll
@@ -731,7 +731,7 @@ __device__ void prolong_stage(const Stage& st, int chunk, const PipeCtx& pc, int
         T acc = (T)0;
 #pragma unroll
         for (int t = 0; t < 4; ++t)
-          if (t < ncoef) acc += cw[t] * raw[j][t];
+          if (cvalid[t]) acc += cw[t] * raw[j][t];
         v[j] = acc;
       }
 #pragma unroll
@@ -749,7 +749,7 @@ __device__ void prolong_stage(const Stage& st, int chunk, const PipeCtx& pc, int
 // Precision hand-over of mixed-precision refinement on the rows of one leaf:
 // STG_CAST: float32 right-hand side = float64 defect, float32 iterate = 0;
 // STG_CORRECT: float64 iterate += float32 correction.
-__device__ void pointwise_stage(const Stage& st, int chunk, const PipeCtx& pc, int* sh_abort) {
+__device__ __forceinline__ void pointwise_stage(const Stage& st, int chunk, const PipeCtx& pc, int* sh_abort) {
   const long long N = st.npoints;
   const long long q = (long long)chunk * kStencilCols + (threadIdx.x % kStencilCols);
   const int r0 = threadIdx.x / kStencilCols;
