@@ -63,6 +63,7 @@ struct Stage {
   void* dst;
   void* zero;
   int dim, nf, nc;
+  int red_only;          // STG_RESTRICT*: the defect is held on the first colour only (see launch_restrict)
   long long npoints;     // STG_CAST / STG_CORRECT: points per time row
 };
 
@@ -83,7 +84,11 @@ hipError_t set_pipeline_lds_limit(size_t bytes);
 hipError_t launch_fill_int(int* x, long long count, int v, hipStream_t s);
 template <typename T> hipError_t launch_march(int mode, const MarchArgs<T>& a, hipStream_t s);
 template <typename T> hipError_t set_march_lds_limit(size_t bytes);
-template <typename T> hipError_t launch_restrict(const T* rf, T* fc, int dim, int nf, int M, hipStream_t s);
+// red_only: the fine defect is read at first-colour points only (the coarse
+// points and, in 2D, the diagonal neighbours); the other colour's defect is
+// zero after its line solves and its entries are not read.
+template <typename T> hipError_t launch_restrict(const T* rf, T* fc, int dim, int nf, int M, bool red_only,
+                                                 hipStream_t s);
 template <typename T> hipError_t launch_prolong(const T* ec, T* uf, int dim, int nf, int M, hipStream_t s);
 hipError_t launch_rhs0(const double* f, const double* gq, const double* a1, double* b, long long M, long long N,
                        hipStream_t s);

@@ -594,10 +594,13 @@ __device__ __forceinline__ void restrict_stage(const Stage& st, int chunk, const
   const bool ok = Q < Nc;
   const int lane = threadIdx.x & 63;
   // fine-grid offsets of the 9-point (2D) / 3-point (1D) weighted stencil;
-  // tap t sits at a fixed index (registers, not private memory)
+  // tap t sits at a fixed index (registers, not private memory).  With a
+  // first-colour defect only the first-colour taps are read.
   const int nw = st.dim == 1 ? 3 : 9;
+  const bool red_only = st.red_only;
   long long off[9];
   T wgt[9];
+  bool tap[9];
   {
     const long long I = st.dim == 1 ? Q : Q % nc, J = st.dim == 1 ? 0 : Q / nc;
     const long long fx = 2 * I + 1, fy = 2 * J + 1;
@@ -606,10 +609,12 @@ __device__ __forceinline__ void restrict_stage(const Stage& st, int chunk, const
       if (st.dim == 1) {
         off[t] = fx - 1 + (t < 3 ? t : 0);
         wgt[t] = t == 1 ? (T)0.5 : (T)0.25;
+        tap[t] = t < 3 && (!red_only || t == 1);
       } else {
         const int dy = t / 3 - 1, dx = t % 3 - 1;
         off[t] = (fy + dy) * nf + fx + dx;
         wgt[t] = (T)((dx == 0 ? 2 : 1) * (dy == 0 ? 2 : 1)) * (T)(1.0 / 16.0);
+        tap[t] = !red_only || (dx == 0) == (dy == 0);   // first colour: centre and corners
       }
     }
   }
@@ -633,7 +638,7 @@ __device__ __forceinline__ void restrict_stage(const Stage& st, int chunk, const
           const bool rok = jj < rows_per_group && row < d.sz;
           const T* r = src + (long long)(d.lo + (rok ? row : 0)) * Nf;
 #pragma unroll
-          for (int t = 0; t < 9; ++t) raw[jj][t] = (rok && t < nw) ? gld<true>(r + off[t]) : (T)0;
+          for (int t = 0; t < 9; ++t) raw[jj][t] = (rok && t < nw && tap[t]) ? gld<true>(r + off[t]) : (T)0;
         }
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
@@ -641,7 +646,7 @@ __device__ __forceinline__ void restrict_stage(const Stage& st, int chunk, const
             T acc = (T)0;
 #pragma unroll
             for (int t = 0; t < 9; ++t)
-              if (t < nw) acc += wgt[t] * raw[jj][t];
+              if (t < nw && tap[t]) acc += wgt[t] * raw[jj][t];
             v[j0 + jj] = acc;
           }
         }
@@ -876,7 +881,8 @@ __global__ void fill_int_kernel(int* __restrict__ x, long long count, int v) {
 
 // Full weighting (Algorithm 2 "restrict the defect only in space").
 template <typename T>
-__global__ void restrict_kernel(const T* __restrict__ rf, T* __restrict__ fc, int dim, int nf, int nc, long long M) {
+__global__ void restrict_kernel(const T* __restrict__ rf, T* __restrict__ fc, int dim, int nf, int nc, long long M,
+                                int red_only) {
   const long long Nc = dim == 1 ? nc : (long long)nc * nc;
   const long long Nf = dim == 1 ? nf : (long long)nf * nf;
   const long long total = M * Nc;
@@ -887,15 +893,15 @@ __global__ void restrict_kernel(const T* __restrict__ rf, T* __restrict__ fc, in
     T v;
     if (dim == 1) {
       const long long f = 2 * Q + 1;
-      v = (T)0.25 * (r[f - 1] + (T)2 * r[f] + r[f + 1]);
+      v = red_only ? (T)0.5 * r[f] : (T)0.25 * (r[f - 1] + (T)2 * r[f] + r[f + 1]);
     } else {
       const long long I = Q % nc, J = Q / nc;
       const long long fx = 2 * I + 1, fy = 2 * J + 1;
       const T* r0 = r + (fy - 1) * nf;
       const T* r1 = r + fy * nf;
       const T* r2 = r + (fy + 1) * nf;
-      v = (T)(1.0 / 16.0) * ((r0[fx - 1] + r0[fx + 1] + r2[fx - 1] + r2[fx + 1]) +
-                             (T)2 * (r0[fx] + r2[fx] + r1[fx - 1] + r1[fx + 1]) + (T)4 * r1[fx]);
+      const T edges = red_only ? (T)0 : (T)2 * (r0[fx] + r2[fx] + r1[fx - 1] + r1[fx + 1]);
+      v = (T)(1.0 / 16.0) * ((r0[fx - 1] + r0[fx + 1] + r2[fx - 1] + r2[fx + 1]) + edges + (T)4 * r1[fx]);
     }
     fc[idx] = v;
   }
@@ -1075,10 +1081,11 @@ hipError_t set_march_lds_limit(size_t bytes) {
 }
 
 template <typename T>
-hipError_t launch_restrict(const T* rf, T* fc, int dim, int nf, int M, hipStream_t s) {
+hipError_t launch_restrict(const T* rf, T* fc, int dim, int nf, int M, bool red_only, hipStream_t s) {
   int nc = (nf - 1) / 2;
   long long total = (long long)M * (dim == 1 ? nc : (long long)nc * nc);
-  hipLaunchKernelGGL(restrict_kernel<T>, dim3(grid_for(total, 256)), dim3(256), 0, s, rf, fc, dim, nf, nc, (long long)M);
+  hipLaunchKernelGGL(restrict_kernel<T>, dim3(grid_for(total, 256)), dim3(256), 0, s, rf, fc, dim, nf, nc, (long long)M,
+                     red_only ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -1139,8 +1146,8 @@ template hipError_t launch_march<double>(int, const MarchArgs<double>&, hipStrea
 template hipError_t launch_march<float>(int, const MarchArgs<float>&, hipStream_t);
 template hipError_t set_march_lds_limit<double>(size_t);
 template hipError_t set_march_lds_limit<float>(size_t);
-template hipError_t launch_restrict<double>(const double*, double*, int, int, int, hipStream_t);
-template hipError_t launch_restrict<float>(const float*, float*, int, int, int, hipStream_t);
+template hipError_t launch_restrict<double>(const double*, double*, int, int, int, bool, hipStream_t);
+template hipError_t launch_restrict<float>(const float*, float*, int, int, int, bool, hipStream_t);
 template hipError_t launch_prolong<double>(const double*, double*, int, int, int, hipStream_t);
 template hipError_t launch_prolong<float>(const float*, float*, int, int, int, hipStream_t);
 template hipError_t launch_fill<double>(double*, long long, double, hipStream_t);

@@ -281,16 +281,24 @@ int smooth(mgwr_plan* pl, DevOps<T>& ops, int l, int colour, T* F, T* U) {
   return MGWR_OK;
 }
 
+// Defect b - A u on level l.  red_only: on the first colour only.  Right
+// after a half-sweep of the second colour the defect there is zero (each of
+// its lines was just solved exactly with the same operator), so a defect
+// that only feeds the restriction needs the first colour alone.
 template <typename T>
-int defect(mgwr_plan* pl, DevOps<T>& ops, int l, const T* F, T* U, T* Out) {
+int defect(mgwr_plan* pl, DevOps<T>& ops, int l, const T* F, T* U, T* Out, bool red_only = false) {
   const HostPlan& hp = pl->hp;
   const Level& lv = hp.levels[l];
   MarchArgs<T> a = base_args<T>(pl, ops, l);
   a.F = F; a.U = U; a.Out = Out;
   a.ld = lv.N; a.ncols = lv.N; a.cstride = 1; a.coff = 0;
+  if (red_only) {
+    const int par0 = hp.p.dim == 1 ? 1 : 0;
+    a.ncols = (lv.N - par0 + 1) / 2; a.cstride = 2; a.coff = par0;
+  }
   a.dim = hp.p.dim; a.n = lv.n; a.inv_h2 = (T)(1.0 / (lv.h * lv.h));
-  Timed tm(pl, sizeof(T) == 8 ? MGWR_K_DEFECT64 : MGWR_K_DEFECT32, 2.0 * hp.stored * lv.N,
-           3.0 * hp.p.M * lv.N * sizeof(T));
+  Timed tm(pl, sizeof(T) == 8 ? MGWR_K_DEFECT64 : MGWR_K_DEFECT32, 2.0 * hp.stored * a.ncols,
+           3.0 * hp.p.M * a.ncols * sizeof(T));
   HIP_TRY(launch_march<T>(MODE_RESID, a, pl->stream));
   return MGWR_OK;
 }
@@ -314,10 +322,11 @@ int cycle(mgwr_plan* pl, DevOps<T>& ops, int l) {
     if ((rc = smooth<T>(pl, ops, l, 0, F, U))) return rc;
     if ((rc = smooth<T>(pl, ops, l, 1, F, U))) return rc;
   }
-  if ((rc = defect<T>(pl, ops, l, F, U, ops.R[l]))) return rc;
+  const bool red_only = hp.p.nu1 >= 1;   // the pre-smoothing ended with a second-colour half-sweep
+  if ((rc = defect<T>(pl, ops, l, F, U, ops.R[l], red_only))) return rc;
   {
     Timed tm(pl, MGWR_K_RESTRICT, 0.0, (double)M * (hp.levels[l].N + hp.levels[l + 1].N) * sizeof(T));
-    HIP_TRY(launch_restrict<T>(ops.R[l], ops.F[l + 1], hp.p.dim, hp.levels[l].n, M, pl->stream));
+    HIP_TRY(launch_restrict<T>(ops.R[l], ops.F[l + 1], hp.p.dim, hp.levels[l].n, M, red_only, pl->stream));
   }
   HIP_TRY(launch_fill<T>(ops.U[l + 1], (long long)M * hp.levels[l + 1].N, (T)0, pl->stream));
   for (int gm = 0; gm < hp.p.gamma; ++gm)
@@ -383,20 +392,26 @@ int append_cycle_stages(mgwr_plan* pl, int l, int prev, std::vector<Stage>& out,
     return prev;
   }
   for (int s2 = 0; s2 < hp.p.nu1; ++s2) { smooth_stage(0); smooth_stage(1); }
+  // after a second-colour half-sweep the defect vanishes on that colour: the
+  // defect stage covers the first colour and the restriction reads only it
+  const bool red_only = hp.p.nu1 >= 1;
   {
+    const int par0 = hp.p.dim == 1 ? 1 : 0;
+    const int ncols = red_only ? (lv.N - par0 + 1) / 2 : lv.N;
+    const int cstride = red_only ? 2 : 1, coff = red_only ? par0 : 0;
     Stage st = base(STG_RESID + kofs);
     if (!f32) {
       st.m = base_args<double>(pl, ops, l);
       st.m.F = ops.F[l]; st.m.U = ops.U[l]; st.m.Out = ops.R[l];
-      st.m.ld = lv.N; st.m.ncols = lv.N; st.m.cstride = 1; st.m.coff = 0;
+      st.m.ld = lv.N; st.m.ncols = ncols; st.m.cstride = cstride; st.m.coff = coff;
       st.m.dim = hp.p.dim; st.m.n = lv.n; st.m.inv_h2 = 1.0 / (lv.h * lv.h);
     } else {
       st.mf = base_args<float>(pl, o32, l);
       st.mf.F = o32.F[l]; st.mf.U = o32.U[l]; st.mf.Out = o32.R[l];
-      st.mf.ld = lv.N; st.mf.ncols = lv.N; st.mf.cstride = 1; st.mf.coff = 0;
+      st.mf.ld = lv.N; st.mf.ncols = ncols; st.mf.cstride = cstride; st.mf.coff = coff;
       st.mf.dim = hp.p.dim; st.mf.n = lv.n; st.mf.inv_h2 = (float)(1.0 / (lv.h * lv.h));
     }
-    st.nchunks = (lv.N + 15) / 16;
+    st.nchunks = (ncols + 15) / 16;
     push(st);
   }
   const Level& lc = hp.levels[l + 1];
@@ -405,6 +420,7 @@ int append_cycle_stages(mgwr_plan* pl, int l, int prev, std::vector<Stage>& out,
     if (!f32) { st.src = ops.R[l]; st.dst = ops.F[l + 1]; st.zero = ops.U[l + 1]; }
     else { st.src = o32.R[l]; st.dst = o32.F[l + 1]; st.zero = o32.U[l + 1]; }
     st.dim = hp.p.dim; st.nf = lv.n; st.nc = lc.n;
+    st.red_only = red_only ? 1 : 0;
     st.nchunks = (lc.N + kStencilCols - 1) / kStencilCols;
     push(st);
   }
