@@ -34,6 +34,17 @@ struct MarchArgs {
   // stencil: dim 0 (none), 1 or 2; n points per side; 1/h^2
   int dim, n;
   T inv_h2;
+  // Grid transfers fused into the march in 1D (null pointers: not fused).
+  // Columns are q = 2p + 1, the coarse points p < nc.
+  //  RESID: the first-colour full weighting of the defect is the injection
+  //         Inj[m][p] = r[m][q] / 2, and the coarse iterate starts at Inj0[m][p] = 0.
+  //  SMOOTH: the neighbours q -/+ 1 are read with the coarse correction Ec
+  //         interpolated onto them (linear interpolation), which adds
+  //         (Ec[m][p-1] + 2 Ec[m][p] + Ec[m][p+1]) / 2 to their sum.
+  T* Inj;
+  T* Inj0;
+  const T* Ec;
+  int nc;
 };
 
 // One stage of the time-pipelined kernel.  Stage kinds:

@@ -189,9 +189,16 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
 
   long long nb[4] = {0, 0, 0, 0};
   bool nbok[4] = {false, false, false, false};
+  // 1D smoothing with the coarse correction fused: slots 2 and 3 hold the
+  // coarse values p - 1 and p + 1 (weight 1/2), pf_c the value p (weight 1)
+  const bool fuse_ec = MODE == MODE_SMOOTH && a.Ec != nullptr;
   if (a.dim == 1) {
     nb[0] = q - 1; nbok[0] = colok && q >= 1;
     nb[1] = q + 1; nbok[1] = colok && q + 1 < a.n;
+    if (fuse_ec) {
+      nb[2] = p - 1; nbok[2] = colok && p >= 1 && p - 1 < a.nc;
+      nb[3] = p + 1; nbok[3] = colok && p + 1 < a.nc;
+    }
   } else if (a.dim == 2) {
     long long ix = q % a.n, iy = q / a.n;
     nb[0] = q - 1;   nbok[0] = colok && ix >= 1;
@@ -217,6 +224,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
   // ---- registers holding prefetched operands -------------------------------
   constexpr int NB = 4;                 // stencil neighbours loaded per row (2 used in 1D)
   T pf_f[4], pf_n[4][NB], pf_u[4];      // wave 0: raw inputs of the next leaf's rows
+  T pf_c[4];                            // fused coarse correction at the column's own coarse point
   T dpf[DPF][4];                        // dense tiles of the next phase 2
   int djj[DPF];
   T fpf[FPF];                           // far-field chunks of the next phase 2
@@ -250,10 +258,13 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
       const bool ok = colok && row < d.sz;
       const long long off = (long long)(d.lo + (ok ? row : 0)) * a.ld;
       pf_f[r] = (MODE != MODE_MATVEC && ok) ? gld<PIPE>(a.F + off + q) : (T)0;
+      const T* ecrow = fuse_ec ? a.Ec + (long long)(d.lo + (ok ? row : 0)) * a.nc : nullptr;
 #pragma unroll
-      for (int e = 0; e < NB; ++e)
-        pf_n[r][e] = ((MODE == MODE_SMOOTH || MODE == MODE_RESID) && nbok[e] && ok) ? gld<PIPE>(a.U + off + nb[e])
-                                                                                     : (T)0;
+      for (int e = 0; e < NB; ++e) {
+        const T* src = (fuse_ec && e >= 2) ? ecrow + nb[e] : a.U + off + nb[e];
+        pf_n[r][e] = ((MODE == MODE_SMOOTH || MODE == MODE_RESID) && nbok[e] && ok) ? gld<PIPE>(src) : (T)0;
+      }
+      pf_c[r] = (fuse_ec && ok && p < a.nc) ? gld<PIPE>(ecrow + p) : (T)0;
       pf_u[r] = (kKnownX && ok) ? gld<PIPE>(a.U + off + q) : (T)0;
     }
     return true;
@@ -353,9 +364,12 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
     if (wave == kIO) {   // stencil right-hand side last: its loads had the most time
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        T sn = (T)0;
-#pragma unroll
-        for (int e = 0; e < NB; ++e) sn += pf_n[r][e];
+        T sn = pf_n[r][0] + pf_n[r][1];
+        if constexpr (MODE == MODE_SMOOTH) {
+          sn += (fuse_ec ? (T)0.5 : (T)1) * (pf_n[r][2] + pf_n[r][3]) + pf_c[r];
+        } else {
+          sn += pf_n[r][2] + pf_n[r][3];
+        }
         T v;
         if constexpr (MODE == MODE_SMOOTH) v = pf_f[r] + a.inv_h2 * sn;
         else if constexpr (MODE == MODE_RESID) v = pf_f[r] - a.inv_h2 * (diagc * pf_u[r] - sn);
@@ -486,7 +500,14 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
           const int row = drow<T>(g, r);
           if (colok && row < d.sz) {
             const T v = (MODE == MODE_MATVEC) ? -acc[r] : acc[r];
-            gst<PIPE>(a.Out + (long long)(d.lo + row) * a.ld + q, v);
+            if (MODE == MODE_RESID && a.Inj) {   // fused 1D restriction (first-colour defect)
+              if (p < a.nc) {
+                gst<PIPE>(a.Inj + (long long)(d.lo + row) * a.nc + p, (T)0.5 * v);
+                gst<PIPE>(a.Inj0 + (long long)(d.lo + row) * a.nc + p, (T)0);
+              }
+            } else {
+              gst<PIPE>(a.Out + (long long)(d.lo + row) * a.ld + q, v);
+            }
             if constexpr (PIPE) {
               if (!(v == v) || __builtin_isinf(v)) nbad = true;
               else nmax = v > nmax ? v : (-v > nmax ? -v : nmax);
@@ -555,7 +576,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
 }
 
 template <typename T, int MODE>
-__global__ __launch_bounds__(256) void march_kernel(MarchArgs<T> a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void march_kernel(MarchArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int sh_abort;
   PipeCtx pc{};
@@ -811,7 +832,7 @@ __device__ __forceinline__ void pointwise_stage(const Stage& st, int chunk, cons
   }
 }
 
-__global__ __launch_bounds__(256) void pipeline_kernel(PipeArgs pa) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void pipeline_kernel(PipeArgs pa) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int sh_task;
   __shared__ int sh_abort;

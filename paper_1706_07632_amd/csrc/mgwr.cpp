@@ -260,12 +260,34 @@ MarchArgs<T> base_args(mgwr_plan* pl, const DevOps<T>& ops, int level) {
   return a;
 }
 
+// Grid transfers fused into the marches (1D only; the cycle is the same in
+// exact arithmetic).  Restriction: after a second-colour half-sweep the
+// defect lives on the first colour, the coarse points q = 2p + 1, where full
+// weighting reduces to r[q] / 2: the defect march writes it straight into
+// the coarse right-hand side.  Prolongation: the first-colour half-sweep that
+// follows the coarse-grid correction reads the iterate only at its
+// second-colour neighbours (its own lines are solved afresh), and the second-
+// colour half-sweep after it reads only first-colour values, so the corrected
+// iterate is needed nowhere else; the half-sweep adds the interpolated
+// correction to the neighbours it reads.
+struct TransferFusion {
+  bool restrict_in_defect, prolong_in_smooth;
+};
+TransferFusion transfer_fusion(const HostPlan& hp) {
+  TransferFusion f;
+  f.restrict_in_defect = hp.p.dim == 1 && hp.p.nu1 >= 1;
+  f.prolong_in_smooth = hp.p.dim == 1 && hp.p.nu2 >= 1;
+  return f;
+}
+
 // Zebra-in-time line relaxation of one colour on one level: every line of
 // the colour is solved with (R~ + c_l I) by the H-forward substitution.
 // Colour 0 is updated first: the coarse-grid points (1-based even in 1D,
 // i + j even in 2D), which are the flat indices q with q % 2 == par0.
+// Ec (1D, colour 0 only): coarse correction whose interpolation the
+// half-sweep applies to the neighbours it reads (see MarchArgs).
 template <typename T>
-int smooth(mgwr_plan* pl, DevOps<T>& ops, int l, int colour, T* F, T* U) {
+int smooth(mgwr_plan* pl, DevOps<T>& ops, int l, int colour, T* F, T* U, const T* Ec = nullptr) {
   const HostPlan& hp = pl->hp;
   const Level& lv = hp.levels[l];
   int par0 = hp.p.dim == 1 ? 1 : 0;
@@ -275,6 +297,7 @@ int smooth(mgwr_plan* pl, DevOps<T>& ops, int l, int colour, T* F, T* U) {
   a.F = F; a.U = U; a.Out = nullptr;
   a.ld = lv.N; a.ncols = ncols; a.cstride = 2; a.coff = par;
   a.dim = hp.p.dim; a.n = lv.n; a.inv_h2 = (T)(1.0 / (lv.h * lv.h));
+  if (Ec) { a.Ec = Ec; a.nc = hp.levels[l + 1].n; }
   Timed tm(pl, sizeof(T) == 8 ? MGWR_K_SMOOTH64 : MGWR_K_SMOOTH32, 2.0 * hp.stored * ncols,
            3.0 * hp.p.M * ncols * sizeof(T));
   HIP_TRY(launch_march<T>(MODE_SMOOTH, a, pl->stream));
@@ -286,7 +309,9 @@ int smooth(mgwr_plan* pl, DevOps<T>& ops, int l, int colour, T* F, T* U) {
 // its lines was just solved exactly with the same operator), so a defect
 // that only feeds the restriction needs the first colour alone.
 template <typename T>
-int defect(mgwr_plan* pl, DevOps<T>& ops, int l, const T* F, T* U, T* Out, bool red_only = false) {
+// Inj / Inj0 (1D, red_only): the restriction is fused, see MarchArgs.
+int defect(mgwr_plan* pl, DevOps<T>& ops, int l, const T* F, T* U, T* Out, bool red_only = false,
+           T* Inj = nullptr, T* Inj0 = nullptr) {
   const HostPlan& hp = pl->hp;
   const Level& lv = hp.levels[l];
   MarchArgs<T> a = base_args<T>(pl, ops, l);
@@ -297,6 +322,7 @@ int defect(mgwr_plan* pl, DevOps<T>& ops, int l, const T* F, T* U, T* Out, bool 
     a.ncols = (lv.N - par0 + 1) / 2; a.cstride = 2; a.coff = par0;
   }
   a.dim = hp.p.dim; a.n = lv.n; a.inv_h2 = (T)(1.0 / (lv.h * lv.h));
+  if (Inj) { a.Inj = Inj; a.Inj0 = Inj0; a.nc = hp.levels[l + 1].n; }
   Timed tm(pl, sizeof(T) == 8 ? MGWR_K_DEFECT64 : MGWR_K_DEFECT32, 2.0 * hp.stored * a.ncols,
            3.0 * hp.p.M * a.ncols * sizeof(T));
   HIP_TRY(launch_march<T>(MODE_RESID, a, pl->stream));
@@ -323,20 +349,26 @@ int cycle(mgwr_plan* pl, DevOps<T>& ops, int l) {
     if ((rc = smooth<T>(pl, ops, l, 1, F, U))) return rc;
   }
   const bool red_only = hp.p.nu1 >= 1;   // the pre-smoothing ended with a second-colour half-sweep
-  if ((rc = defect<T>(pl, ops, l, F, U, ops.R[l], red_only))) return rc;
-  {
-    Timed tm(pl, MGWR_K_RESTRICT, 0.0, (double)M * (hp.levels[l].N + hp.levels[l + 1].N) * sizeof(T));
-    HIP_TRY(launch_restrict<T>(ops.R[l], ops.F[l + 1], hp.p.dim, hp.levels[l].n, M, red_only, pl->stream));
+  const TransferFusion fz = transfer_fusion(hp);
+  if (fz.restrict_in_defect) {
+    if ((rc = defect<T>(pl, ops, l, F, U, nullptr, true, ops.F[l + 1], ops.U[l + 1]))) return rc;
+  } else {
+    if ((rc = defect<T>(pl, ops, l, F, U, ops.R[l], red_only))) return rc;
+    {
+      Timed tm(pl, MGWR_K_RESTRICT, 0.0, (double)M * (hp.levels[l].N + hp.levels[l + 1].N) * sizeof(T));
+      HIP_TRY(launch_restrict<T>(ops.R[l], ops.F[l + 1], hp.p.dim, hp.levels[l].n, M, red_only, pl->stream));
+    }
+    HIP_TRY(launch_fill<T>(ops.U[l + 1], (long long)M * hp.levels[l + 1].N, (T)0, pl->stream));
   }
-  HIP_TRY(launch_fill<T>(ops.U[l + 1], (long long)M * hp.levels[l + 1].N, (T)0, pl->stream));
   for (int gm = 0; gm < hp.p.gamma; ++gm)
     if ((rc = cycle<T>(pl, ops, l + 1))) return rc;
-  {
+  if (!fz.prolong_in_smooth) {
     Timed tm(pl, MGWR_K_PROLONG, 0.0, (double)M * (2.0 * hp.levels[l].N + hp.levels[l + 1].N) * sizeof(T));
     HIP_TRY(launch_prolong<T>(ops.U[l + 1], U, hp.p.dim, hp.levels[l].n, M, pl->stream));
   }
   for (int s = 0; s < hp.p.nu2; ++s) {
-    if ((rc = smooth<T>(pl, ops, l, 0, F, U))) return rc;
+    const T* Ec = (fz.prolong_in_smooth && s == 0) ? ops.U[l + 1] : nullptr;
+    if ((rc = smooth<T>(pl, ops, l, 0, F, U, Ec))) return rc;
     if ((rc = smooth<T>(pl, ops, l, 1, F, U))) return rc;
   }
   return MGWR_OK;
@@ -366,7 +398,7 @@ int append_cycle_stages(mgwr_plan* pl, int l, int prev, std::vector<Stage>& out,
     out.push_back(st);
     prev = (int)out.size() - 1;
   };
-  auto smooth_stage = [&](int colour) {
+  auto smooth_stage = [&](int colour, bool with_ec = false) {
     int par0 = hp.p.dim == 1 ? 1 : 0;
     int par = colour == 0 ? par0 : 1 - par0;
     int ncols = (lv.N - par + 1) / 2;
@@ -377,15 +409,18 @@ int append_cycle_stages(mgwr_plan* pl, int l, int prev, std::vector<Stage>& out,
       st.m.F = ops.F[l]; st.m.U = ops.U[l]; st.m.Out = nullptr;
       st.m.ld = lv.N; st.m.ncols = ncols; st.m.cstride = 2; st.m.coff = par;
       st.m.dim = hp.p.dim; st.m.n = lv.n; st.m.inv_h2 = 1.0 / (lv.h * lv.h);
+      if (with_ec) { st.m.Ec = ops.U[l + 1]; st.m.nc = hp.levels[l + 1].n; }
     } else {
       st.mf = base_args<float>(pl, o32, l);
       st.mf.F = o32.F[l]; st.mf.U = o32.U[l]; st.mf.Out = nullptr;
       st.mf.ld = lv.N; st.mf.ncols = ncols; st.mf.cstride = 2; st.mf.coff = par;
       st.mf.dim = hp.p.dim; st.mf.n = lv.n; st.mf.inv_h2 = (float)(1.0 / (lv.h * lv.h));
+      if (with_ec) { st.mf.Ec = o32.U[l + 1]; st.mf.nc = hp.levels[l + 1].n; }
     }
     st.nchunks = (ncols + 15) / 16;
     push(st);
   };
+  const TransferFusion fz = transfer_fusion(hp);
   if (l == L - 1) {
     smooth_stage(0);
     smooth_stage(1);
@@ -405,17 +440,23 @@ int append_cycle_stages(mgwr_plan* pl, int l, int prev, std::vector<Stage>& out,
       st.m.F = ops.F[l]; st.m.U = ops.U[l]; st.m.Out = ops.R[l];
       st.m.ld = lv.N; st.m.ncols = ncols; st.m.cstride = cstride; st.m.coff = coff;
       st.m.dim = hp.p.dim; st.m.n = lv.n; st.m.inv_h2 = 1.0 / (lv.h * lv.h);
+      if (fz.restrict_in_defect) {
+        st.m.Out = nullptr; st.m.Inj = ops.F[l + 1]; st.m.Inj0 = ops.U[l + 1]; st.m.nc = hp.levels[l + 1].n;
+      }
     } else {
       st.mf = base_args<float>(pl, o32, l);
       st.mf.F = o32.F[l]; st.mf.U = o32.U[l]; st.mf.Out = o32.R[l];
       st.mf.ld = lv.N; st.mf.ncols = ncols; st.mf.cstride = cstride; st.mf.coff = coff;
       st.mf.dim = hp.p.dim; st.mf.n = lv.n; st.mf.inv_h2 = (float)(1.0 / (lv.h * lv.h));
+      if (fz.restrict_in_defect) {
+        st.mf.Out = nullptr; st.mf.Inj = o32.F[l + 1]; st.mf.Inj0 = o32.U[l + 1]; st.mf.nc = hp.levels[l + 1].n;
+      }
     }
     st.nchunks = (ncols + 15) / 16;
     push(st);
   }
   const Level& lc = hp.levels[l + 1];
-  {
+  if (!fz.restrict_in_defect) {
     Stage st = base(STG_RESTRICT + kofs);
     if (!f32) { st.src = ops.R[l]; st.dst = ops.F[l + 1]; st.zero = ops.U[l + 1]; }
     else { st.src = o32.R[l]; st.dst = o32.F[l + 1]; st.zero = o32.U[l + 1]; }
@@ -425,7 +466,7 @@ int append_cycle_stages(mgwr_plan* pl, int l, int prev, std::vector<Stage>& out,
     push(st);
   }
   for (int gm = 0; gm < hp.p.gamma; ++gm) prev = append_cycle_stages(pl, l + 1, prev, out, f32);
-  {
+  if (!fz.prolong_in_smooth) {
     Stage st = base(STG_PROLONG + kofs);
     st.prev = prev;
     if (!f32) { st.src = ops.U[l + 1]; st.dst = ops.U[l]; }
@@ -434,7 +475,7 @@ int append_cycle_stages(mgwr_plan* pl, int l, int prev, std::vector<Stage>& out,
     st.nchunks = (lv.N + kStencilCols - 1) / kStencilCols;
     push(st);
   }
-  for (int s2 = 0; s2 < hp.p.nu2; ++s2) { smooth_stage(0); smooth_stage(1); }
+  for (int s2 = 0; s2 < hp.p.nu2; ++s2) { smooth_stage(0, fz.prolong_in_smooth && s2 == 0); smooth_stage(1); }
   return prev;
 }
 
