@@ -171,7 +171,11 @@ int mgwr_htrsm(mgwr_plan* plan, int level, const double* b_dev, double* x_dev, i
  * until read.  Algorithmic counts per launch: time-marching kernels 2 S flops
  * per column (S = stored entries of R~, dense leaves counted full) and 3 M
  * words per column (f, the other colour or u, and the written line);
- * restriction M (N_f + N_c) words; prolongation M (N_c + 2 N_f) words. */
+ * restriction M (N_f + 2 N_c) words, N_f / 2 when it reads the first-colour
+ * defect only; prolongation M (N_c + 2 N_f) words, N_c + N_f when it corrects
+ * the second colour only (a first-colour half-sweep follows).  In 1D with
+ * nu1, nu2 >= 1 both transfers are fused into the marches and have no
+ * launches of their own. */
 enum {
   MGWR_K_SMOOTH64 = 0,  /* zebra line relaxation, float64 */
   MGWR_K_DEFECT64 = 1,  /* defect b - A u, float64 */

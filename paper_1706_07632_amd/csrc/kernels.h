@@ -75,6 +75,7 @@ struct Stage {
   void* zero;
   int dim, nf, nc;
   int red_only;          // STG_RESTRICT*: the defect is held on the first colour only (see launch_restrict)
+  int black_only;        // STG_PROLONG*: correct the second-colour points only (see launch_prolong)
   long long npoints;     // STG_CAST / STG_CORRECT: points per time row
 };
 
@@ -100,7 +101,12 @@ template <typename T> hipError_t set_march_lds_limit(size_t bytes);
 // zero after its line solves and its entries are not read.
 template <typename T> hipError_t launch_restrict(const T* rf, T* fc, int dim, int nf, int M, bool red_only,
                                                  hipStream_t s);
-template <typename T> hipError_t launch_prolong(const T* ec, T* uf, int dim, int nf, int M, hipStream_t s);
+// black_only: only the second-colour fine points are corrected.  A
+// first-colour half-sweep that follows reads the iterate only there (its own
+// lines are solved afresh), so the other corrections would be overwritten
+// unread.
+template <typename T> hipError_t launch_prolong(const T* ec, T* uf, int dim, int nf, int M, bool black_only,
+                                                hipStream_t s);
 hipError_t launch_rhs0(const double* f, const double* gq, const double* a1, double* b, long long M, long long N,
                        hipStream_t s);
 template <typename T> hipError_t launch_fill(T* x, long long count, T v, hipStream_t s);

@@ -155,18 +155,21 @@ constexpr int ZMASK = (1 << 30) - 1;
 
 // Work split inside a workgroup: NW waves share one chain of 16 columns.
 // Per time leaf s there are two phases separated by workgroup barriers:
-//   phase 1: wave 0 sums the partial right-hand sides of leaf s and solves
-//            with the pre-inverted shifted diagonal leaf (critical path);
-//            waves 1.. apply the column-side updates Z += B^T x_{s-1}.
-//   phase 2: all waves build partial right-hand sides of leaf s+1 (stencil
-//            right-hand side on wave 0, dense near-diagonal blocks and the far
-//            field split round-robin).
+//   phase 1: wave 0 sums the partial right-hand sides of leaf s, solves with
+//            the pre-inverted shifted diagonal leaf (or forms the defect) and
+//            stores the rows (critical path); all waves then apply their
+//            share of the column-side updates Z += B^T x_{s-1}, wave 0 the
+//            smallest.
+//   phase 2: the waves build partial right-hand sides of leaf s+1: dense
+//            near-diagonal blocks and the far field split round-robin, the
+//            stencil part on the last wave, which also loads the stencil
+//            inputs of leaf s+2.
 // The tiles of the next phase are loaded into registers while the current
 // phase runs.  Every admissible column cluster ends at least one leaf before
 // its row cluster starts, so the far field of leaf s+1 never needs the updates
 // of leaf s.
 constexpr int NW = 4;
-constexpr int ZPF = 4;   // column-update tiles prefetched per helper wave
+constexpr int ZPF = 4;   // column-update tiles prefetched per wave
 constexpr int DPF = 2;   // dense blocks prefetched per wave
 constexpr int FPF = 4;   // far-field chunks prefetched per wave
 
@@ -209,16 +212,26 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
   const T diagc = (T)(2 * a.dim);
   constexpr bool kSolve = (MODE == MODE_SMOOTH || MODE == MODE_TRSM);
   constexpr bool kKnownX = (MODE == MODE_RESID || MODE == MODE_MATVEC);
-  // Solves: the last wave moves the solved rows to global memory, signals
-  // progress and loads the next leaf's inputs, all during phase 2, so that
-  // wave 0's critical path (sum, solve) carries no global-memory round trip
-  // and the wait for the producer overlaps the other waves' products.
-  constexpr bool kSplitIO = kSolve;
-  constexpr int kIO = kSplitIO ? NW - 1 : 0;   // the wave that loads the stencil inputs
-  // waves sharing the products of phase 2 (the split-IO wave has none: its
-  // phase 2 holds the stores, the wait for the producer and the input loads)
-  constexpr int NPW = kSplitIO ? NW - 1 : NW;
+  // Work split: wave 0 sums, solves (or forms the defect) and stores the
+  // leaf's rows straight from its registers, signalling them one leaf later
+  // (by then they are complete without a wait of their own).  The last wave
+  // (kIO) loads the stencil inputs one leaf ahead: the inputs of leaf s + 2
+  // are in flight while leaf s + 1 is solved, so no global-memory round trip
+  // lies on the path from one solve to the next.
+  constexpr int kIO = NW - 1;
+  // waves sharing the products of phase 2 (the IO wave has none: its phase 2
+  // holds the stencil part, the wait for the producer and the input loads)
+  constexpr int NPW = NW - 1;
   const bool pworker = wave < NPW;
+  // Prefetch slots.  Far-field chunk of slot k2: workers take chunks
+  // wave + k2 NPW (the first FPF NPW), the IO wave the next FPF; chunks
+  // beyond FPF NW go round-robin to the workers, loaded when used.  Update
+  // tile of slot k2: waves 1.. take tiles (wave - 1) + k2 (NW - 1), wave 0
+  // (which solves first) the next ZPF; tiles beyond ZPF NW go to waves 1..
+  const int ffbase = pworker ? wave : FPF * NPW;
+  const int ffstride = pworker ? NPW : 1;
+  const int zbase = wave == 0 ? ZPF * (NW - 1) : wave - 1;
+  const int zstride = wave == 0 ? 1 : NW - 1;
   const int nleaf = a.nleaf;
 
   // ---- registers holding prefetched operands -------------------------------
@@ -272,9 +285,8 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
 
   // all waves: H-matrix tiles of their share of leaf li's phase 2
   auto prefetch_tiles = [&](int li) {
-    if (!pworker) return;
     const LeafDesc d = ld_struct<LeafDesc, true>(a.leaves + li);
-    const int nd = n_dense(d);
+    const int nd = pworker ? n_dense(d) : 0;
 #pragma unroll
     for (int k2 = 0; k2 < DPF; ++k2) {
       const int e = wave + k2 * NPW;
@@ -286,7 +298,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
     }
 #pragma unroll
     for (int k2 = 0; k2 < FPF; ++k2) {
-      const int ch = wave + k2 * NPW;
+      const int ch = ffbase + k2 * ffstride;
       if (ch < d.ff_nchunk) {
         fpf[k2] = ld(a.ffA + (long long)(d.ff_begin + ch) * 64 + lane);
         fzr[k2] = ld(a.ff_row + (d.ff_begin + ch) * 4 + g);
@@ -294,11 +306,11 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
     }
   };
 
-  auto prefetch_zu = [&](int li) {  // helpers: update tiles of leaf li
+  auto prefetch_zu = [&](int li) {  // update tiles of leaf li in this wave's slots
     const LeafDesc d = ld_struct<LeafDesc, true>(a.leaves + li);
 #pragma unroll
     for (int k2 = 0; k2 < ZPF; ++k2) {
-      const int tt = (wave - 1) + k2 * (NW - 1);
+      const int tt = zbase + k2 * zstride;
       if (tt < d.zu_ntile) {
         const T* Bt = a.zuB + (long long)(d.zu_begin + tt) * 256;
 #pragma unroll
@@ -322,7 +334,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
     const LeafDesc d = ld_struct<LeafDesc, true>(a.leaves + li);
     v4 acc = {0, 0, 0, 0};
     const int nd = pworker ? n_dense(d) : 0;
-    const int nff = pworker ? d.ff_nchunk : 0;
+    const int nff = d.ff_nchunk;
 #pragma unroll
     for (int k2 = 0; k2 < DPF; ++k2) {
       if (wave + k2 * NPW < nd) {
@@ -343,12 +355,12 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
     }
 #pragma unroll
     for (int k2 = 0; k2 < FPF; ++k2) {
-      if (wave + k2 * NPW < nff) {
+      if (ffbase + k2 * ffstride < nff) {
         const T bv = fzr[k2] >= 0 ? Z[fzr[k2] * 16 + c] : (T)0;
         acc = mfma(fpf[k2], bv, acc);
       }
     }
-    for (int ch0 = wave + FPF * NPW; ch0 < nff; ch0 += FPF * NPW) {
+    for (int ch0 = FPF * NW + wave; pworker && ch0 < nff; ch0 += FPF * NPW) {
       T av[FPF], bv[FPF];
 #pragma unroll
       for (int b = 0; b < FPF; ++b) {
@@ -383,24 +395,28 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
     for (int r = 0; r < 4; ++r) pw[drow<T>(g, r) * 16 + c] = acc[r];
   };
 
-  // phase 1 (helpers): Z += B^T x for the update tiles of leaf li owned by this wave
+  // phase 1: Z += B^T x for the update tiles of leaf li owned by this wave
   auto zupdate = [&](int li) {
     const LeafDesc d = ld_struct<LeafDesc, true>(a.leaves + li);
+    if (zbase >= d.zu_ntile) return;
     const T* xs = ring + (li % a.ring) * 256;
+    T xb[4];   // the x operand, read once (the Z stores below may not move it)
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) xb[kc] = xs[(4 * kc + g) * 16 + c];
     auto apply = [&](const T* bt, const int* zr) {
       v4 z;
 #pragma unroll
       for (int r = 0; r < 4; ++r) z[r] = (zr[r] >= 0 && !(zr[r] & ZFIRST)) ? Z[(zr[r] & ZMASK) * 16 + c] : (T)0;
 #pragma unroll
-      for (int kc = 0; kc < 4; ++kc) z = mfma(bt[kc], xs[(4 * kc + g) * 16 + c], z);
+      for (int kc = 0; kc < 4; ++kc) z = mfma(bt[kc], xb[kc], z);
 #pragma unroll
       for (int r = 0; r < 4; ++r)
         if (zr[r] >= 0) Z[(zr[r] & ZMASK) * 16 + c] = z[r];
     };
 #pragma unroll
     for (int k2 = 0; k2 < ZPF; ++k2)
-      if ((wave - 1) + k2 * (NW - 1) < d.zu_ntile) apply(zpf[k2], zpr[k2]);
-    for (int tt = (wave - 1) + ZPF * (NW - 1); tt < d.zu_ntile; tt += NW - 1) {
+      if (zbase + k2 * zstride < d.zu_ntile) apply(zpf[k2], zpr[k2]);
+    for (int tt = ZPF * NW + (wave - 1); wave != 0 && tt < d.zu_ntile; tt += NW - 1) {
       T bt[4];
       int zr[4];
       const T* Bt = a.zuB + (long long)(d.zu_begin + tt) * 256;
@@ -417,17 +433,6 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
   T nmax = (T)0;
   bool nbad = false;
 
-  // rows of leaf li from its ring slot to global memory (split-IO wave)
-  auto store_rows = [&](int li) {
-    const LeafDesc d = ld_struct<LeafDesc, true>(a.leaves + li);
-    const T* xs = ring + (li % a.ring) * 256;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = drow<T>(g, r);
-      if (colok && row < d.sz) gst<PIPE>(a.U + (long long)(d.lo + row) * a.ld + q, xs[row * 16 + c]);
-    }
-  };
-
   // ---- prologue: partial right-hand side of leaf 0 ---------------------------
   prefetch_tiles(0);
   if (wave == kIO) {
@@ -441,7 +446,11 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
   __syncthreads();
   if (*sh_abort) return;
   partial(0);
+  if (wave == kIO && nleaf > 1) {
+    if (!prefetch_inputs(1)) *sh_abort = 1;
+  }
   __syncthreads();
+  if (*sh_abort) return;
 
   for (int s = 0; s < nleaf; ++s) {
     const LeafDesc d = ld_struct<LeafDesc, true>(a.leaves + s);
@@ -449,6 +458,9 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
     // (tile loads are issued after any progress signal of the same wave: the
     // wait before a signal then covers row stores only)
     if (wave == 0) {
+      if constexpr (PIPE) {
+        if (s >= 1) signal_leaf(pc, s - 1, lane);   // its rows went out in the last phase 1
+      }
       v4 acc;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -492,7 +504,9 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
           if constexpr (sizeof(T) == 4) {
             if (d.f64solve && a.dinv_hi) row = drow<double>(g, r);
           }
-          cur[row * 16 + c] = (colok && row < d.sz) ? x[r] : (T)0;   // to global memory by the split-IO wave
+          const bool ok = colok && row < d.sz;
+          cur[row * 16 + c] = ok ? x[r] : (T)0;
+          if (ok) gst<PIPE>(a.U + (long long)(d.lo + row) * a.ld + q, x[r]);
         }
       } else {
 #pragma unroll
@@ -515,25 +529,17 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
           }
         }
       }
-      if constexpr (!kSplitIO) {
-        if constexpr (PIPE) signal_leaf(pc, s, lane);
-      }
-      if (s + 1 < nleaf) {
-        prefetch_tiles(s + 1);
-        if constexpr (!kSplitIO) {
-          if (!prefetch_inputs(s + 1)) *sh_abort = 1;
-          if constexpr (kKnownX) {
-            T* nxt = ring + ((s + 1) % a.ring) * 256;
+      if (s + 1 < nleaf) prefetch_tiles(s + 1);
+      if (s >= 1) zupdate(s - 1);
+    } else {
+      if (s + 1 < nleaf) prefetch_tiles(s + 1);
+      if constexpr (kKnownX) {
+        if (wave == kIO && s + 1 < nleaf) {   // known x of leaf s + 1 (loaded one leaf ago)
+          T* nxt = ring + ((s + 1) % a.ring) * 256;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) nxt[drow<T>(g, r) * 16 + c] = pf_u[r];
-          }
+          for (int r = 0; r < 4; ++r) nxt[drow<T>(g, r) * 16 + c] = pf_u[r];
         }
       }
-    } else {
-      if constexpr (kSplitIO && PIPE) {
-        if (wave == kIO && s >= 1) signal_leaf(pc, s - 1, lane);   // its row stores went out in the last phase 2
-      }
-      if (s + 1 < nleaf) prefetch_tiles(s + 1);
       if (s >= 1) zupdate(s - 1);
     }
     lds_barrier();
@@ -543,24 +549,20 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
     // ---- phase 2 --------------------------------------------------------------
     if (s + 1 < nleaf) {
       if (wave == 0) prefetch_dinv(s + 1);
-      else prefetch_zu(s);
-      if constexpr (kSplitIO) {
-        if (wave == kIO) {
-          store_rows(s);
-          if (!prefetch_inputs(s + 1)) *sh_abort = 1;
-        }
+      if (wave != kIO) prefetch_zu(s);
+      partial(s + 1);   // IO wave: stencil part of leaf s + 1 from inputs loaded one leaf ago
+      if (wave == kIO) {
+        if (s + 2 < nleaf && !prefetch_inputs(s + 2)) *sh_abort = 1;
+        prefetch_zu(s);
       }
-      partial(s + 1);
-    } else if constexpr (kSplitIO) {
-      if (wave == kIO) store_rows(s);
     }
     lds_barrier();
     if constexpr (PIPE) {
       if (*sh_abort) return;
     }
   }
-  if constexpr (kSplitIO && PIPE) {
-    if (wave == kIO) signal_leaf(pc, nleaf - 1, lane);
+  if constexpr (PIPE) {
+    if (wave == 0) signal_leaf(pc, nleaf - 1, lane);
   }
   if constexpr (PIPE && MODE == MODE_RESID) {
     if (pc.norm_out && wave == 0) {
@@ -697,9 +699,13 @@ __device__ __forceinline__ void prolong_stage(const Stage& st, int chunk, const 
   const int nf = st.nf, nc = st.nc;
   const long long Nc = st.dim == 1 ? nc : (long long)nc * nc;
   const long long Nf = st.dim == 1 ? nf : (long long)nf * nf;
-  const long long q = (long long)chunk * kStencilCols + (threadIdx.x % kStencilCols);
+  // second colour only: flat indices of parity par1 (even in 1D, odd in 2D)
+  const int par1 = st.dim == 1 ? 0 : 1;
+  const long long Nq = st.black_only ? (Nf - par1 + 1) / 2 : Nf;
+  const long long qi = (long long)chunk * kStencilCols + (threadIdx.x % kStencilCols);
+  const long long q = st.black_only ? 2 * qi + par1 : qi;
   const int r0 = threadIdx.x / kStencilCols;
-  const bool ok = q < Nf;
+  const bool ok = qi < Nq;
   const int lane = threadIdx.x & 63;
   // coarse neighbours: slot t = 2 b + a of (y neighbour b, x neighbour a);
   // an odd fine index has one neighbour (slot 0 of its axis), an even one two,
@@ -931,13 +937,18 @@ __global__ void restrict_kernel(const T* __restrict__ rf, T* __restrict__ fc, in
 // Linear / bilinear interpolation plus correction (Algorithm 2 "interpolate
 // the correction only in space" and "compute a new approximation").
 template <typename T>
-__global__ void prolong_kernel(const T* __restrict__ ec, T* __restrict__ uf, int dim, int nf, int nc, long long M) {
+__global__ void prolong_kernel(const T* __restrict__ ec, T* __restrict__ uf, int dim, int nf, int nc, long long M,
+                               int black_only) {
   const long long Nc = dim == 1 ? nc : (long long)nc * nc;
   const long long Nf = dim == 1 ? nf : (long long)nf * nf;
-  const long long total = M * Nf;
+  // second colour: flat indices of parity par1 (even in 1D, odd in 2D)
+  const int par1 = dim == 1 ? 0 : 1;
+  const long long Nq = black_only ? (Nf - par1 + 1) / 2 : Nf;
+  const long long total = M * Nq;
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
        idx += (long long)gridDim.x * blockDim.x) {
-    const long long m = idx / Nf, q = idx % Nf;
+    const long long m = idx / Nq, qi = idx % Nq;
+    const long long q = black_only ? 2 * qi + par1 : qi;
     const T* e = ec + m * Nc;
     T v;
     if (dim == 1) {
@@ -967,7 +978,7 @@ __global__ void prolong_kernel(const T* __restrict__ ec, T* __restrict__ uf, int
         }
       }
     }
-    uf[idx] += v;
+    uf[m * Nf + q] += v;
   }
 }
 
@@ -1111,10 +1122,12 @@ hipError_t launch_restrict(const T* rf, T* fc, int dim, int nf, int M, bool red_
 }
 
 template <typename T>
-hipError_t launch_prolong(const T* ec, T* uf, int dim, int nf, int M, hipStream_t s) {
+hipError_t launch_prolong(const T* ec, T* uf, int dim, int nf, int M, bool black_only, hipStream_t s) {
   int nc = (nf - 1) / 2;
-  long long total = (long long)M * (dim == 1 ? nf : (long long)nf * nf);
-  hipLaunchKernelGGL(prolong_kernel<T>, dim3(grid_for(total, 256)), dim3(256), 0, s, ec, uf, dim, nf, nc, (long long)M);
+  const long long Nf = dim == 1 ? nf : (long long)nf * nf;
+  const long long total = (long long)M * (black_only ? (Nf - (dim == 1 ? 0 : 1) + 1) / 2 : Nf);
+  hipLaunchKernelGGL(prolong_kernel<T>, dim3(grid_for(total, 256)), dim3(256), 0, s, ec, uf, dim, nf, nc, (long long)M,
+                     black_only ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -1169,8 +1182,8 @@ template hipError_t set_march_lds_limit<double>(size_t);
 template hipError_t set_march_lds_limit<float>(size_t);
 template hipError_t launch_restrict<double>(const double*, double*, int, int, int, bool, hipStream_t);
 template hipError_t launch_restrict<float>(const float*, float*, int, int, int, bool, hipStream_t);
-template hipError_t launch_prolong<double>(const double*, double*, int, int, int, hipStream_t);
-template hipError_t launch_prolong<float>(const float*, float*, int, int, int, hipStream_t);
+template hipError_t launch_prolong<double>(const double*, double*, int, int, int, bool, hipStream_t);
+template hipError_t launch_prolong<float>(const float*, float*, int, int, int, bool, hipStream_t);
 template hipError_t launch_fill<double>(double*, long long, double, hipStream_t);
 template hipError_t launch_fill<float>(float*, long long, float, hipStream_t);
 template hipError_t launch_cast<double, float>(const double*, float*, long long, hipStream_t);

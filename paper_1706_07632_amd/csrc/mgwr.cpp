@@ -355,7 +355,8 @@ int cycle(mgwr_plan* pl, DevOps<T>& ops, int l) {
   } else {
     if ((rc = defect<T>(pl, ops, l, F, U, ops.R[l], red_only))) return rc;
     {
-      Timed tm(pl, MGWR_K_RESTRICT, 0.0, (double)M * (hp.levels[l].N + hp.levels[l + 1].N) * sizeof(T));
+      Timed tm(pl, MGWR_K_RESTRICT, 0.0,
+               (double)M * ((red_only ? 0.5 : 1.0) * hp.levels[l].N + 2.0 * hp.levels[l + 1].N) * sizeof(T));
       HIP_TRY(launch_restrict<T>(ops.R[l], ops.F[l + 1], hp.p.dim, hp.levels[l].n, M, red_only, pl->stream));
     }
     HIP_TRY(launch_fill<T>(ops.U[l + 1], (long long)M * hp.levels[l + 1].N, (T)0, pl->stream));
@@ -363,8 +364,9 @@ int cycle(mgwr_plan* pl, DevOps<T>& ops, int l) {
   for (int gm = 0; gm < hp.p.gamma; ++gm)
     if ((rc = cycle<T>(pl, ops, l + 1))) return rc;
   if (!fz.prolong_in_smooth) {
-    Timed tm(pl, MGWR_K_PROLONG, 0.0, (double)M * (2.0 * hp.levels[l].N + hp.levels[l + 1].N) * sizeof(T));
-    HIP_TRY(launch_prolong<T>(ops.U[l + 1], U, hp.p.dim, hp.levels[l].n, M, pl->stream));
+    Timed tm(pl, MGWR_K_PROLONG, 0.0,
+             (double)M * ((hp.p.nu2 >= 1 ? 1.0 : 2.0) * hp.levels[l].N + hp.levels[l + 1].N) * sizeof(T));
+    HIP_TRY(launch_prolong<T>(ops.U[l + 1], U, hp.p.dim, hp.levels[l].n, M, hp.p.nu2 >= 1, pl->stream));
   }
   for (int s = 0; s < hp.p.nu2; ++s) {
     const T* Ec = (fz.prolong_in_smooth && s == 0) ? ops.U[l + 1] : nullptr;
@@ -472,7 +474,9 @@ int append_cycle_stages(mgwr_plan* pl, int l, int prev, std::vector<Stage>& out,
     if (!f32) { st.src = ops.U[l + 1]; st.dst = ops.U[l]; }
     else { st.src = o32.U[l + 1]; st.dst = o32.U[l]; }
     st.dim = hp.p.dim; st.nf = lv.n; st.nc = lc.n;
-    st.nchunks = (lv.N + kStencilCols - 1) / kStencilCols;
+    st.black_only = hp.p.nu2 >= 1 ? 1 : 0;   // a first-colour half-sweep follows
+    const long long nq = st.black_only ? (lv.N - (hp.p.dim == 1 ? 0 : 1) + 1) / 2 : lv.N;
+    st.nchunks = (int)((nq + kStencilCols - 1) / kStencilCols);
     push(st);
   }
   for (int s2 = 0; s2 < hp.p.nu2; ++s2) { smooth_stage(0, fz.prolong_in_smooth && s2 == 0); smooth_stage(1); }
@@ -560,7 +564,12 @@ void build_plan_stages(mgwr_plan* pl, const double* b, double* u, int K, double*
       const double Nf = hp.p.dim == 1 ? x.nf : (double)x.nf * x.nf;
       const double Nc = hp.p.dim == 1 ? x.nc : (double)x.nc * x.nc;
       const double w = (x.kind == STG_RESTRICT || x.kind == STG_PROLONG) ? 8.0 : 4.0;
-      pl->cycle_bytes += ((x.kind == STG_RESTRICT || x.kind == STG_RESTRICT32) ? (Nf + 2 * Nc) : (Nc + 2 * Nf)) * hp.p.M * w;
+      // restriction: fine defect read (first colour only: half) + coarse rhs and iterate written;
+      // prolongation: coarse correction read + fine iterate read and written (second colour only: half)
+      const double words = (x.kind == STG_RESTRICT || x.kind == STG_RESTRICT32)
+                               ? (x.red_only ? 0.5 : 1.0) * Nf + 2 * Nc
+                               : Nc + 2 * (x.black_only ? 0.5 : 1.0) * Nf;
+      pl->cycle_bytes += words * hp.p.M * w;
     }
   }
   out.insert(out.end(), st.begin(), st.end());

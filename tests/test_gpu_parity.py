@@ -133,6 +133,18 @@ def test_w_cycle_and_v01_converge(dev):
     assert st1["cycles"] <= st2["cycles"] + 2
 
 
+@pytest.mark.parametrize("schedule", ["staged", "pipelined"])
+@pytest.mark.parametrize("dim,nu1,nu2", [(1, 1, 0), (1, 0, 1), (1, 2, 2), (2, 0, 1), (2, 1, 0)])
+def test_smoothing_counts_with_and_without_fused_transfers(dev, schedule, dim, nu1, nu2):
+    """Cycles whose grid transfers are fused into the marches (1D, nu1 >= 1
+    restriction, nu2 >= 1 prolongation) and those that keep separate stencil
+    stages (the others, and 2D) reach the oracle's solution."""
+    p = W.manufactured(dim, 31 if dim == 1 else 15, 128, 0.5, r=3.0, k=8)
+    print("case", schedule, dim, nu1, nu2, flush=True)
+    err, res, st = _solve_and_compare(p, dev, nu1=nu1, nu2=nu2, schedule=schedule, tol=1e-11, parity=1e-9)
+    assert err < 1e-9 and res < 1e-10, (err, res, st)
+
+
 def _single_mode_reference(p):
     Rt = oracle.hmatrix_dense(p.t, p.alpha, p.k, p.leaf)
     (kvec, prof), = p.modes
