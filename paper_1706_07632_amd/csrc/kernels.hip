@@ -122,12 +122,30 @@ struct PipeCtx {
 
 constexpr unsigned kSpinLimit = 1u << 22;
 
-// Called by whole waves (uniform); returns false if the pipeline was aborted.
-__device__ bool wait_leaf(const PipeCtx& pc, int leaf) {
-  if (!pc.wait) return true;
-  const int* cnt = pc.wait + leaf;
+// Waits until the producer has finished leaf `leaf` (of nleaf).  `ready` is
+// held by the calling wave: the last leaf known finished.  A wait that must
+// read reads the counters of up to kReadAhead consecutive leaves at once (one
+// round trip through the device-coherent level), so a producer running ahead
+// is checked once per kReadAhead leaves.  Called by whole waves (uniform);
+// returns false if the pipeline was aborted.
+constexpr int kReadAhead = 4;
+__device__ bool wait_leaf(const PipeCtx& pc, int leaf, int nleaf, int& ready) {
+  if (!pc.wait || leaf <= ready) return true;
+  const int n = min(kReadAhead, nleaf - leaf);
   for (unsigned it = 0;; ++it) {
-    if (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= pc.need) return true;
+    int cnt[kReadAhead];
+#pragma unroll
+    for (int i = 0; i < kReadAhead; ++i)
+      cnt[i] = i < n ? __hip_atomic_load(pc.wait + leaf + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+    int k = 0;
+#pragma unroll
+    for (int i = 0; i < kReadAhead; ++i)
+      if (k == i && i < n && cnt[i] >= pc.need) k = i + 1;
+    k = __builtin_amdgcn_readfirstlane(k);
+    if (k > 0) {
+      ready = leaf + k - 1;
+      return true;
+    }
     if (__hip_atomic_load(pc.abortf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
     if (it > kSpinLimit) {
       __hip_atomic_store(pc.abortf, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -233,6 +251,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
   const int zbase = wave == 0 ? ZPF * (NW - 1) : wave - 1;
   const int zstride = wave == 0 ? 1 : NW - 1;
   const int nleaf = a.nleaf;
+  int ready = -1;   // IO wave: last producer leaf known finished
 
   // ---- registers holding prefetched operands -------------------------------
   constexpr int NB = 4;                 // stencil neighbours loaded per row (2 used in 1D)
@@ -260,7 +279,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
   // wave 0: inputs of leaf li (in the pipeline, after the producer finished it)
   auto prefetch_inputs = [&](int li) -> bool {
     if constexpr (PIPE) {
-      if (!wait_leaf(pc, li)) return false;
+      if (!wait_leaf(pc, li, nleaf, ready)) return false;
     }
     const LeafDesc d = ld_struct<LeafDesc, true>(a.leaves + li);
     // every load is issued before any of them is used, so that they are in
@@ -641,10 +660,11 @@ __device__ __forceinline__ void restrict_stage(const Stage& st, int chunk, const
       }
     }
   }
+  int ready = -1;   // wave 0: last producer leaf known finished
   for (int i = 0; i < st.nleaf; ++i) {
     const LeafDesc d = ld_struct<LeafDesc, true>(st.leaves + i);
     if (threadIdx.x < 64) {
-      if (!wait_leaf(pc, i)) *sh_abort = 1;
+      if (!wait_leaf(pc, i, st.nleaf, ready)) *sh_abort = 1;
     }
     __syncthreads();
     if (*sh_abort) return;
@@ -738,10 +758,11 @@ __device__ __forceinline__ void prolong_stage(const Stage& st, int chunk, const 
       cw[t] = wx[a2] * wy[b];
     }
   }
+  int ready = -1;   // wave 0: last producer leaf known finished
   for (int i = 0; i < st.nleaf; ++i) {
     const LeafDesc d = ld_struct<LeafDesc, true>(st.leaves + i);
     if (threadIdx.x < 64) {
-      if (!wait_leaf(pc, i)) *sh_abort = 1;
+      if (!wait_leaf(pc, i, st.nleaf, ready)) *sh_abort = 1;
     }
     __syncthreads();
     if (*sh_abort) return;
@@ -787,10 +808,11 @@ __device__ __forceinline__ void pointwise_stage(const Stage& st, int chunk, cons
   const int r0 = threadIdx.x / kStencilCols;
   const bool ok = q < N;
   const int lane = threadIdx.x & 63;
+  int ready = -1;   // wave 0: last producer leaf known finished
   for (int i = 0; i < st.nleaf; ++i) {
     const LeafDesc d = ld_struct<LeafDesc, true>(st.leaves + i);
     if (threadIdx.x < 64) {
-      if (!wait_leaf(pc, i)) *sh_abort = 1;
+      if (!wait_leaf(pc, i, st.nleaf, ready)) *sh_abort = 1;
     }
     __syncthreads();
     if (*sh_abort) return;
