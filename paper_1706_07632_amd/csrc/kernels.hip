@@ -175,30 +175,34 @@ constexpr int ZMASK = (1 << 30) - 1;
 // Per time leaf s there are two phases separated by workgroup barriers:
 //   phase 1: wave 0 sums the partial right-hand sides of leaf s, solves with
 //            the pre-inverted shifted diagonal leaf (or forms the defect) and
-//            stores the rows (critical path); all waves then apply their
-//            share of the column-side updates Z += B^T x_{s-1}, wave 0 the
-//            smallest.
-//   phase 2: the waves build partial right-hand sides of leaf s+1: dense
-//            near-diagonal blocks and the far field split round-robin, the
-//            stencil part on the last wave, which also loads the stencil
-//            inputs of leaf s+2.
+//            stores the rows (critical path), then applies its (small) share
+//            of the column-side updates Z += B^T x_{s-1}; waves 1 .. NW-2
+//            apply theirs; the last wave (IO) forms the stencil part of leaf
+//            s+1 from inputs loaded one leaf earlier, waits for the producer
+//            and issues the loads of leaf s+2.
+//   phase 2: waves 0 .. NW-2 build their partial right-hand sides of leaf s+1
+//            (dense near-diagonal blocks and the far field, round-robin); the
+//            IO wave applies its share of the updates of leaf s and adds its
+//            far-field share of leaf s+1.
 // The tiles of the next phase are loaded into registers while the current
 // phase runs.  Every admissible column cluster ends at least one leaf before
 // its row cluster starts, so the far field of leaf s+1 never needs the updates
-// of leaf s.
+// of leaf s, and the accumulators updated with leaf s are not those read for
+// leaf s+1 (their live intervals overlap, so they hold different slots).
 constexpr int NW = 4;
-constexpr int ZPF = 4;   // column-update tiles prefetched per wave
+constexpr int ZPF = 6;   // column-update tiles prefetched per wave (even: applied in pairs)
 constexpr int DPF = 2;   // dense blocks prefetched per wave
-constexpr int FPF = 4;   // far-field chunks prefetched per wave
+constexpr int FPF = 5;   // far-field chunks prefetched per wave
 
 template <typename T, int MODE, bool PIPE>
 __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, const PipeCtx& pc,
                                            unsigned char* smem_raw, int* sh_abort) {
   typedef typename V4<T>::type v4;
   T* ring = reinterpret_cast<T*>(smem_raw);   // [R][16][16] x of recent leaves, row-major
-  T* part = ring + a.ring * 256;               // [NW][16][16] partial right-hand sides
-  T* tbuf = part + NW * 256;                   // [16][16] (f32 transposition)
-  T* Z = tbuf + 256;                           // [nslots*k][16]
+  T* part = ring + a.ring * 256;               // [NW + 1][16][16] partial right-hand sides (slot NW:
+                                               // the IO wave's, odd leaves)
+  T* tbuf = part + (NW + 1) * 256;             // [16][16] float32 transposition (none in float64)
+  T* Z = tbuf + (sizeof(T) == 4 ? 256 : 0);    // [nslots*k][16]
 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -348,12 +352,19 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
     }
   };
 
-  // phase 2: partial right-hand side of leaf li from this wave's share
-  auto partial = [&](int li) {
+  // Partial right-hand side of leaf li from this wave's share, to pw.  The
+  // IO wave writes its stencil part in phase 1 (stencil) and adds its
+  // far-field share in phase 2 (products, accumulating into pw).
+  auto partial = [&](int li, T* pw, bool products, bool stencil) {
     const LeafDesc d = ld_struct<LeafDesc, true>(a.leaves + li);
     v4 acc = {0, 0, 0, 0};
-    const int nd = pworker ? n_dense(d) : 0;
-    const int nff = d.ff_nchunk;
+    const int nd = (pworker && products) ? n_dense(d) : 0;
+    const int nff = products ? d.ff_nchunk : 0;
+    if (!stencil && !pworker) {   // IO wave, products: nothing unless it holds far-field chunks
+      if (ffbase >= nff) return;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] = pw[drow<T>(g, r) * 16 + c];
+    }
 #pragma unroll
     for (int k2 = 0; k2 < DPF; ++k2) {
       if (wave + k2 * NPW < nd) {
@@ -392,7 +403,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
       for (int b = 0; b < FPF; ++b)
         if (ch0 + b * NPW < nff) acc = mfma(av[b], bv[b], acc);
     }
-    if (wave == kIO) {   // stencil right-hand side last: its loads had the most time
+    if (stencil) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         T sn = pf_n[r][0] + pf_n[r][1];
@@ -409,10 +420,10 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
         acc[r] += v;
       }
     }
-    T* pw = part + wave * 256;
 #pragma unroll
     for (int r = 0; r < 4; ++r) pw[drow<T>(g, r) * 16 + c] = acc[r];
   };
+  auto ioslot = [&](int li) { return part + ((li & 1) ? NW : kIO) * 256; };
 
   // phase 1: Z += B^T x for the update tiles of leaf li owned by this wave
   auto zupdate = [&](int li) {
@@ -432,9 +443,31 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
       for (int r = 0; r < 4; ++r)
         if (zr[r] >= 0) Z[(zr[r] & ZMASK) * 16 + c] = z[r];
     };
+    // two tiles at a time: independent accumulation chains on the MFMA pipe
+    auto apply2 = [&](const T* b0, const int* r0, const T* b1, const int* r1) {
+      v4 z0, z1;
 #pragma unroll
-    for (int k2 = 0; k2 < ZPF; ++k2)
-      if (zbase + k2 * zstride < d.zu_ntile) apply(zpf[k2], zpr[k2]);
+      for (int r = 0; r < 4; ++r) {
+        z0[r] = (r0[r] >= 0 && !(r0[r] & ZFIRST)) ? Z[(r0[r] & ZMASK) * 16 + c] : (T)0;
+        z1[r] = (r1[r] >= 0 && !(r1[r] & ZFIRST)) ? Z[(r1[r] & ZMASK) * 16 + c] : (T)0;
+      }
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) {
+        z0 = mfma(b0[kc], xb[kc], z0);
+        z1 = mfma(b1[kc], xb[kc], z1);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (r0[r] >= 0) Z[(r0[r] & ZMASK) * 16 + c] = z0[r];
+        if (r1[r] >= 0) Z[(r1[r] & ZMASK) * 16 + c] = z1[r];
+      }
+    };
+    static_assert(ZPF % 2 == 0, "tiles go in pairs");
+#pragma unroll
+    for (int k2 = 0; k2 < ZPF; k2 += 2) {
+      if (zbase + (k2 + 1) * zstride < d.zu_ntile) apply2(zpf[k2], zpr[k2], zpf[k2 + 1], zpr[k2 + 1]);
+      else if (zbase + k2 * zstride < d.zu_ntile) apply(zpf[k2], zpr[k2]);
+    }
     for (int tt = ZPF * NW + (wave - 1); wave != 0 && tt < d.zu_ntile; tt += NW - 1) {
       T bt[4];
       int zr[4];
@@ -448,44 +481,83 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
   };
 
   if (nleaf <= 0) return;
-  if (threadIdx.x == 0) *sh_abort = 0;
   T nmax = (T)0;
   bool nbad = false;
 
-  // ---- prologue: partial right-hand side of leaf 0 ---------------------------
-  prefetch_tiles(0);
+  // The IO wave and the other waves run separate loops with the same
+  // sequence of barriers, so that the registers each role carries from one
+  // leaf to the next are allocated side by side rather than added up.
   if (wave == kIO) {
+    // ---- IO wave ---------------------------------------------------------------
+    // phase 1 of leaf s: stencil part of leaf s + 1 from the inputs loaded one
+    // leaf ago, the wait for the producer and the loads of leaf s + 2;
+    // phase 2: its share of the updates of leaf s (no partial sum of leaf
+    // s + 1 reads those accumulators) and of the far field of leaf s + 1.
+    prefetch_tiles(0);
     if (!prefetch_inputs(0)) *sh_abort = 1;
     if constexpr (kKnownX) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) ring[drow<T>(g, r) * 16 + c] = pf_u[r];
     }
+    prefetch_zu(0);
+    __syncthreads();
+    if (*sh_abort) return;
+    partial(0, ioslot(0), false, true);
+    partial(0, ioslot(0), true, false);
+    if (nleaf > 1 && !prefetch_inputs(1)) *sh_abort = 1;
+    __syncthreads();
+    if (*sh_abort) return;
+    for (int s = 0; s < nleaf; ++s) {
+      if (s + 1 < nleaf) {
+        if constexpr (kKnownX) {
+          T* nxt = ring + ((s + 1) % a.ring) * 256;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) nxt[drow<T>(g, r) * 16 + c] = pf_u[r];
+        }
+        partial(s + 1, ioslot(s + 1), false, true);
+        if (s + 2 < nleaf && !prefetch_inputs(s + 2)) *sh_abort = 1;
+        prefetch_tiles(s + 1);
+      }
+      lds_barrier();
+      if constexpr (PIPE) {
+        if (*sh_abort) return;
+      }
+      if (s + 1 < nleaf) {
+        if (s + 2 < nleaf) zupdate(s);
+        prefetch_zu(s + 1);
+        partial(s + 1, ioslot(s + 1), true, false);
+      }
+      lds_barrier();
+      if constexpr (PIPE) {
+        if (*sh_abort) return;
+      }
+    }
+    return;
   }
+
+  // ---- wave 0 and the workers ---------------------------------------------------
+  prefetch_tiles(0);
   if (wave == 0) prefetch_dinv(0);
   __syncthreads();
   if (*sh_abort) return;
-  partial(0);
-  if (wave == kIO && nleaf > 1) {
-    if (!prefetch_inputs(1)) *sh_abort = 1;
-  }
+  partial(0, part + wave * 256, true, false);
   __syncthreads();
   if (*sh_abort) return;
 
   for (int s = 0; s < nleaf; ++s) {
     const LeafDesc d = ld_struct<LeafDesc, true>(a.leaves + s);
     // ---- phase 1 --------------------------------------------------------------
-    // (tile loads are issued after any progress signal of the same wave: the
-    // wait before a signal then covers row stores only)
     if (wave == 0) {
       if constexpr (PIPE) {
         if (s >= 1) signal_leaf(pc, s - 1, lane);   // its rows went out in the last phase 1
       }
       v4 acc;
+      const T* io = ioslot(s);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        T v = (T)0;
+        T v = io[drow<T>(g, r) * 16 + c];
 #pragma unroll
-        for (int w = 0; w < NW; ++w) v += part[w * 256 + drow<T>(g, r) * 16 + c];
+        for (int w = 0; w < NPW; ++w) v += part[w * 256 + drow<T>(g, r) * 16 + c];
         acc[r] = v;
       }
       T* cur = ring + (s % a.ring) * 256;
@@ -548,19 +620,9 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
           }
         }
       }
-      if (s + 1 < nleaf) prefetch_tiles(s + 1);
-      if (s >= 1) zupdate(s - 1);
-    } else {
-      if (s + 1 < nleaf) prefetch_tiles(s + 1);
-      if constexpr (kKnownX) {
-        if (wave == kIO && s + 1 < nleaf) {   // known x of leaf s + 1 (loaded one leaf ago)
-          T* nxt = ring + ((s + 1) % a.ring) * 256;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) nxt[drow<T>(g, r) * 16 + c] = pf_u[r];
-        }
-      }
-      if (s >= 1) zupdate(s - 1);
     }
+    if (s + 1 < nleaf) prefetch_tiles(s + 1);
+    if (s >= 1 && s + 1 < nleaf) zupdate(s - 1);
     lds_barrier();
     if constexpr (PIPE) {
       if (*sh_abort) return;
@@ -568,12 +630,8 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
     // ---- phase 2 --------------------------------------------------------------
     if (s + 1 < nleaf) {
       if (wave == 0) prefetch_dinv(s + 1);
-      if (wave != kIO) prefetch_zu(s);
-      partial(s + 1);   // IO wave: stencil part of leaf s + 1 from inputs loaded one leaf ago
-      if (wave == kIO) {
-        if (s + 2 < nleaf && !prefetch_inputs(s + 2)) *sh_abort = 1;
-        prefetch_zu(s);
-      }
+      prefetch_zu(s);
+      partial(s + 1, part + wave * 256, true, false);
     }
     lds_barrier();
     if constexpr (PIPE) {
@@ -600,6 +658,8 @@ template <typename T, int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void march_kernel(MarchArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int sh_abort;
+  if (threadIdx.x == 0) sh_abort = 0;
+  __syncthreads();
   PipeCtx pc{};
   march_body<T, MODE, false>(a, blockIdx.x, pc, smem_raw, &sh_abort);
 }
@@ -864,7 +924,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void p
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int sh_task;
   __shared__ int sh_abort;
-  if (threadIdx.x == 0) sh_task = atomicAdd(pa.ticket, 1);
+  if (threadIdx.x == 0) {
+    sh_task = atomicAdd(pa.ticket, 1);
+    sh_abort = 0;
+  }
   __syncthreads();
   const int task = sh_task;
   if (task >= pa.ntasks) return;
@@ -1097,7 +1160,8 @@ static inline int grid_for(long long total, int block) {
 
 template <typename T>
 size_t march_lds_bytes(const MarchArgs<T>& a) {
-  return ((size_t)a.ring * 256 + (size_t)NW * 256 + 256 + (size_t)a.nslots * a.k * 16) * sizeof(T);
+  return ((size_t)a.ring * 256 + (size_t)(NW + 1) * 256 + (sizeof(T) == 4 ? 256 : 0) + (size_t)a.nslots * a.k * 16) *
+         sizeof(T);
 }
 
 template <typename T>
