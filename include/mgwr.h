@@ -84,7 +84,7 @@ typedef struct {
   int gamma;        /* cycles on each coarser level: 1 = V-cycle, 2 = W-cycle */
   int max_cycles;   /* cap on cycles (plain) or inner cycles in total (mixed) */
   int precision;    /* mgwr_precision */
-  int inner_cycles; /* mixed precision: inner V-cycles per outer refinement step */
+  int inner_cycles; /* mixed precision: inner V-cycles per outer refinement step (1..16) */
   int schedule;     /* MGWR_SCHED_AUTO (default), MGWR_SCHED_STAGED or MGWR_SCHED_PIPELINED */
 } mgwr_params;
 

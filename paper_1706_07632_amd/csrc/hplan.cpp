@@ -70,7 +70,8 @@ std::string build_host_plan(const mgwr_params& p, const double* t_host, HostPlan
   if (p.gamma < 1 || p.gamma > 2) return "gamma must be 1 (V) or 2 (W)";
   if (p.max_cycles < 1) return "max_cycles must be >= 1";
   if (p.precision != MGWR_FP64 && p.precision != MGWR_MIXED_FP32) return "unknown precision";
-  if (p.precision == MGWR_MIXED_FP32 && p.inner_cycles < 1) return "inner_cycles must be >= 1";
+  if (p.precision == MGWR_MIXED_FP32 && (p.inner_cycles < 1 || p.inner_cycles > kMaxInnerCycles))
+    return "inner_cycles must be between 1 and " + std::to_string(kMaxInnerCycles);
   if (p.schedule != MGWR_SCHED_AUTO && p.schedule != MGWR_SCHED_PIPELINED && p.schedule != MGWR_SCHED_STAGED)
     return "unknown schedule";
   if ((long long)p.M * (long long)std::pow((double)p.n, p.dim) > (1ll << 40)) return "problem too large";

@@ -16,6 +16,10 @@ namespace mgwr {
 // float64 inside float32 cycles (the near-origin leaves of graded meshes).
 constexpr double kF64LeafStepRatio = 8.0;
 
+// Mixed precision: at most this many float32 cycles per refinement step (one
+// pipelined launch holds at least one whole step).
+constexpr int kMaxInnerCycles = 16;
+
 struct LeafDesc {
   int lo, sz;            // first time row (0-based) and number of rows (<= 16)
   int dn_begin, dn_end;  // dense off-diagonal blocks (j < i): pairs in dn_list

@@ -95,6 +95,7 @@ struct mgwr_plan {
   mgwr_timing tacc{};
   // time-pipelined cycles (float64)
   static constexpr int kMaxPipeCycles = 16;
+  static_assert(kMaxPipeCycles >= kMaxInnerCycles, "a launch holds one refinement step");
   std::vector<Stage> stages;   // host image for kMaxPipeCycles cycles
   int stages_per_cycle = 0, tasks_per_cycle = 0, norm_chunks = 0;
   const double* stages_f = nullptr;    // level-0 arrays the uploaded image refers to
@@ -127,10 +128,12 @@ struct mgwr_plan {
 
 namespace {
 
-// Upper bound of the stages of one pipelined cycle (plus its norm defect).
+// Upper bound of the stages of one pipelined cycle plus what one outer step
+// adds to it (its norm defect; in mixed precision also the cast and the
+// correction).  A launch holds at most kMaxPipeCycles cycles in all.
 long long stages_per_cycle_bound(const HostPlan& hp) {
   const int L = (int)hp.levels.size();
-  long long spc = 1, visits = 1;
+  long long spc = 3, visits = 1;
   for (int l = 0; l < L; ++l) {
     if (l == L - 1) spc += 2 * visits;
     else spc += visits * (2LL * (hp.p.nu1 + hp.p.nu2) + 3);
@@ -868,7 +871,7 @@ int solve_pipelined(mgwr_batch* bt, const double* const* f, const double* const*
       const int i = act[a];
       mgwr_plan* pl = bt->plans[i];
       const int per = pl->mixed ? pl->hp.p.inner_cycles : 1;  // cycles per outer step
-      K[i] = std::max(1, std::min({K[i], mgwr_plan::kMaxPipeCycles, (pl->hp.p.max_cycles - st[i].cycles) / per}));
+      K[i] = std::max(1, std::min({K[i], mgwr_plan::kMaxPipeCycles / per, (pl->hp.p.max_cycles - st[i].cycles) / per}));
       // with a learned step count only the last step's defect is needed (float64
       // cycles); refinement steps need every defect as the next right-hand side
       const int hint = st[i].used_warm_start ? pl->khint_warm : pl->khint;

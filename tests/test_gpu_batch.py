@@ -120,3 +120,17 @@ def test_batch_runs_staged_and_pipelined_instances(dev):
         ref = _modewise_reference(p)
         assert np.abs(u.cpu().numpy() - ref).max() <= 1e-8 * np.abs(ref).max(), st
         assert st["res"] <= 1e-10 * st["bnorm"]
+
+
+def test_batch_of_mixed_plans_with_several_inner_cycles(dev):
+    """A pipelined batch whose refinement steps hold 3 float32 cycles each
+    (the launch's stage table grows with the inner cycles)."""
+    probs = [W.manufactured(1, 127, 512, a, k=10) for a in (0.4, 0.6)]
+    plans = [_plan(p, precision="mixed", inner_cycles=3, schedule="pipelined") for p in probs]
+    batch = mg.Batch(plans).bind()
+    for rep in range(2):
+        us, sts = batch.solve([_cuda(p.f, dev) for p in probs], tol=1e-9)
+        for p, u, st in zip(probs, us, sts):
+            ref = _modewise_reference(p)
+            assert np.abs(u.cpu().numpy() - ref).max() <= 1e-7 * np.abs(ref).max(), st
+            assert st["res"] <= 1e-9 * st["bnorm"] and st["cycles"] % 3 == 0

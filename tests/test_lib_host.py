@@ -44,6 +44,8 @@ def test_library_exports_every_declared_symbol():
     (dict(r=0.5), "r >= 1"),
     (dict(nu1=0, nu2=0), "nu1"),
     (dict(gamma=3), "gamma"),
+    (dict(precision="mixed", inner_cycles=0), "inner_cycles"),
+    (dict(precision="mixed", inner_cycles=17), "inner_cycles"),
 ])
 def test_invalid_parameters_are_rejected(kw, msg):
     args = dict(dim=1, n=31, M=64, alpha=0.5, k=8, r=2.0)
