@@ -168,6 +168,13 @@ __device__ __forceinline__ void signal_leaf(const PipeCtx& pc, int leaf, int lan
 // on the critical path of every leaf).
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
+// Waits for all of this wave's vector-memory operations (vmcnt 0; expcnt and
+// lgkmcnt left at their maxima).  Placed where everything outstanding was
+// issued at least one phase earlier: the compiler then knows those registers
+// are ready and does not wait again (waits count in issue order, so a later
+// wait for them would also wait for the prefetches issued after them).
+__device__ __forceinline__ void vm_drain() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 constexpr int ZFIRST = 1 << 30;
 constexpr int ZMASK = (1 << 30) - 1;
 
@@ -508,6 +515,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
     __syncthreads();
     if (*sh_abort) return;
     for (int s = 0; s < nleaf; ++s) {
+      vm_drain();
       if (s + 1 < nleaf) {
         if constexpr (kKnownX) {
           T* nxt = ring + ((s + 1) % a.ring) * 256;
@@ -524,8 +532,8 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
       }
       if (s + 1 < nleaf) {
         if (s + 2 < nleaf) zupdate(s);
-        prefetch_zu(s + 1);
         partial(s + 1, ioslot(s + 1), true, false);
+        prefetch_zu(s + 1);
       }
       lds_barrier();
       if constexpr (PIPE) {
@@ -547,6 +555,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
   for (int s = 0; s < nleaf; ++s) {
     const LeafDesc d = ld_struct<LeafDesc, true>(a.leaves + s);
     // ---- phase 1 --------------------------------------------------------------
+    vm_drain();
     if (wave == 0) {
       if constexpr (PIPE) {
         if (s >= 1) signal_leaf(pc, s - 1, lane);   // its rows went out in the last phase 1
@@ -628,6 +637,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
       if (*sh_abort) return;
     }
     // ---- phase 2 --------------------------------------------------------------
+    vm_drain();
     if (s + 1 < nleaf) {
       if (wave == 0) prefetch_dinv(s + 1);
       prefetch_zu(s);
