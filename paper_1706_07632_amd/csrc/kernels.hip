@@ -313,9 +313,13 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
     return true;
   };
 
+  // Leaf descriptors read by the prefetches, kept (uniform, in scalar
+  // registers) for the phase that uses the tiles: no second scalar load there.
+  LeafDesc dt{}, dz{};
   // all waves: H-matrix tiles of their share of leaf li's phase 2
   auto prefetch_tiles = [&](int li) {
     const LeafDesc d = ld_struct<LeafDesc, true>(a.leaves + li);
+    dt = d;
     const int nd = pworker ? n_dense(d) : 0;
 #pragma unroll
     for (int k2 = 0; k2 < DPF; ++k2) {
@@ -338,6 +342,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
 
   auto prefetch_zu = [&](int li) {  // update tiles of leaf li in this wave's slots
     const LeafDesc d = ld_struct<LeafDesc, true>(a.leaves + li);
+    dz = d;
 #pragma unroll
     for (int k2 = 0; k2 < ZPF; ++k2) {
       const int tt = zbase + k2 * zstride;
@@ -362,8 +367,9 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
   // Partial right-hand side of leaf li from this wave's share, to pw.  The
   // IO wave writes its stencil part in phase 1 (stencil) and adds its
   // far-field share in phase 2 (products, accumulating into pw).
+  // (products: after prefetch_tiles(li), whose descriptor it uses)
   auto partial = [&](int li, T* pw, bool products, bool stencil) {
-    const LeafDesc d = ld_struct<LeafDesc, true>(a.leaves + li);
+    const LeafDesc& d = dt;
     v4 acc = {0, 0, 0, 0};
     const int nd = (pworker && products) ? n_dense(d) : 0;
     const int nff = products ? d.ff_nchunk : 0;
@@ -433,8 +439,9 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
   auto ioslot = [&](int li) { return part + ((li & 1) ? NW : kIO) * 256; };
 
   // phase 1: Z += B^T x for the update tiles of leaf li owned by this wave
+  // (after prefetch_zu(li), whose descriptor it uses)
   auto zupdate = [&](int li) {
-    const LeafDesc d = ld_struct<LeafDesc, true>(a.leaves + li);
+    const LeafDesc& d = dz;
     if (zbase >= d.zu_ntile) return;
     const T* xs = ring + (li % a.ring) * 256;
     T xb[4];   // the x operand, read once (the Z stores below may not move it)
