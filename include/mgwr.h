@@ -184,6 +184,7 @@ enum {
   MGWR_K_RESTRICT = 4,  /* full-weighting restriction (either precision) */
   MGWR_K_PROLONG = 5,   /* interpolation and correction (either precision) */
   MGWR_K_PIPE64 = 6,    /* one launch of K time-pipelined float64 cycles (all stages) */
+  MGWR_K_COARSE = 7,    /* staged schedule: one pipelined launch of a cycle's coarse levels (either precision) */
   MGWR_K_CLASSES = 8
 };
 typedef struct {

@@ -37,7 +37,7 @@ EXPORTED = [
     "mgwr_plan_set_warm_start", "mgwr_batch_set_graph", "mgwr_batch_graph_replays", "mgwr_plan_autotune",
 ]
 
-KERNEL_CLASSES = ["smooth64", "defect64", "smooth32", "defect32", "restrict", "prolong", "pipe64"]
+KERNEL_CLASSES = ["smooth64", "defect64", "smooth32", "defect32", "restrict", "prolong", "pipe64", "coarse"]
 
 
 class MgwrError(RuntimeError):

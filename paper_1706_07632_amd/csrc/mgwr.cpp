@@ -110,6 +110,17 @@ struct mgwr_plan {
   int khint_staged = 0;                // cycles the last staged float64 solve from zero needed
   int khint_staged_warm = 0;           // the same from a predicted iterate
   double cycle_flops = 0.0, cycle_bytes = 0.0;  // algorithmic work of one pipelined cycle
+  // staged schedule: from level coarse_l on (0: never) a cycle's levels run as
+  // one pipelined launch ([0] float64, [1] float32 stage images)
+  int coarse_l = 0;
+  std::vector<Stage> coarse_stages[2];
+  int coarse_tasks[2] = {0, 0};
+  long long coarse_cnt[2] = {0, 0};
+  double coarse_flops[2] = {0.0, 0.0}, coarse_bytes[2] = {0.0, 0.0};
+  bool coarse_up[2] = {false, false};
+  Stage* cstages_dev[2] = {nullptr, nullptr};
+  int* ccounters = nullptr;
+  int* cflags = nullptr;   // [0] ticket, [1] abort
   // learned initial guess
   static constexpr int kMaxSlices = 64;
   mgwr_net* net = nullptr;
@@ -118,7 +129,7 @@ struct mgwr_plan {
   float* netx = nullptr;   // network input [nslices + 2][N]
   // offsets computed by layout()
   struct Off {
-    size_t stages, counters, flags, norms, wrows, wx;
+    size_t stages, counters, flags, norms, wrows, wx, cstages, ccounters, cflags;
     size_t leaves, dn_list, ff_row, zu_row, a1, tm, B0, part, scal;
     size_t dense64, dinv64, ffA64, zuB64, dense32, dinv32, ffA32, zuB32;
     std::vector<size_t> U64, F64, R64, U32, F32, R32;
@@ -192,6 +203,11 @@ void layout(mgwr_plan* pl) {
     o.counters = cv.take((size_t)S * nleaf * sizeof(int));
     o.flags = cv.take(2 * sizeof(int));
     o.norms = cv.take((size_t)mgwr_plan::kMaxPipeCycles * ((hp.levels[0].N + 15) / 16) * sizeof(double));
+    // the coarse part of a staged cycle (one cycle from level >= 1)
+    const long long C = stages_per_cycle_bound(hp);
+    o.cstages = cv.take((size_t)2 * C * sizeof(Stage));
+    o.ccounters = cv.take((size_t)C * nleaf * sizeof(int));
+    o.cflags = cv.take(2 * sizeof(int));
   }
   o.wrows = cv.take(mgwr_plan::kMaxSlices * sizeof(int));
   o.wx = cv.take((size_t)(mgwr_plan::kMaxSlices + 2) * hp.levels[0].N * sizeof(float));
@@ -332,8 +348,13 @@ int defect(mgwr_plan* pl, DevOps<T>& ops, int l, const T* F, T* U, T* Out, bool 
   return MGWR_OK;
 }
 
+template <typename T>
+int coarse_cycle(mgwr_plan* pl, int l);
+
 // One cycle of Algorithm 2 on level l: ops.F[l] is the right-hand side,
-// ops.U[l] the iterate (level 0 arrays are supplied through F0/U0).
+// ops.U[l] the iterate (level 0 arrays are supplied through F0/U0).  From
+// level coarse_l on, where a half-sweep has too few chains to fill the GPU,
+// the whole remaining cycle is one pipelined launch.
 template <typename T>
 int cycle(mgwr_plan* pl, DevOps<T>& ops, int l) {
   const HostPlan& hp = pl->hp;
@@ -342,6 +363,7 @@ int cycle(mgwr_plan* pl, DevOps<T>& ops, int l) {
   T* F = ops.F[l];
   T* U = ops.U[l];
   int rc;
+  if (l >= 1 && l == pl->coarse_l) return coarse_cycle<T>(pl, l);
   if (l == L - 1) {  // coarsest grid (one point): the line solve is the direct solve
     if ((rc = smooth<T>(pl, ops, l, 0, F, U))) return rc;
     if ((rc = smooth<T>(pl, ops, l, 1, F, U))) return rc;
@@ -595,6 +617,69 @@ void assign_offsets(std::vector<Stage>& st) {
 // pipelined schedule wins (measured: 1D n=1023 pipelines 9x faster, 2D n=255
 // with 2032 chains is faster staged).
 constexpr int kAutoPipelineChains = 256;
+
+// First level below the finest whose half-sweeps have at most
+// kAutoPipelineChains chains (0: none).
+int coarse_switch_level(const HostPlan& hp) {
+  const int L = (int)hp.levels.size();
+  for (int l = 1; l < L; ++l)
+    if ((hp.levels[l].N + 31) / 32 <= kAutoPipelineChains) return l;
+  return 0;
+}
+
+// The coarse part of a staged cycle as one pipelined launch on the plan's
+// own table, counters and flags.  The stage image depends only on the plan's
+// internal arrays, so it is built and uploaded once per binding.  The abort
+// flag is cleared when a staged solve starts and read when it ends.
+template <typename T>
+int coarse_cycle(mgwr_plan* pl, int l) {
+  const int w = sizeof(T) == 4 ? 1 : 0;
+  std::vector<Stage>& st = pl->coarse_stages[w];
+  if (st.empty()) {
+    append_cycle_stages(pl, l, -1, st, w == 1);
+    assign_offsets(st);
+    if ((long long)st.size() > stages_per_cycle_bound(pl->hp)) {
+      st.clear();
+      return fail(MGWR_ERR_STATE, "internal error: coarse stage table exceeds its workspace");
+    }
+    long long cnt = 0;
+    int tasks = 0;
+    double flops = 0.0, bytes = 0.0;
+    for (const Stage& x : st) {
+      cnt += x.nleaf;
+      tasks = x.task0 + x.nchunks;
+      const int nc = w ? x.mf.ncols : x.m.ncols;
+      if (x.kind == STG_SMOOTH + (w ? STG_SMOOTH32 : 0) || x.kind == STG_RESID + (w ? STG_SMOOTH32 : 0)) {
+        flops += 2.0 * pl->hp.stored * nc;
+        bytes += 3.0 * pl->hp.p.M * nc * sizeof(T);
+      }
+    }
+    pl->coarse_cnt[w] = cnt;
+    pl->coarse_tasks[w] = tasks;
+    pl->coarse_flops[w] = flops;
+    pl->coarse_bytes[w] = bytes;
+    pl->coarse_up[w] = false;
+  }
+  if (!pl->coarse_up[w]) {
+    HIP_TRY(hipMemcpyAsync(pl->cstages_dev[w], st.data(), st.size() * sizeof(Stage), hipMemcpyHostToDevice,
+                           pl->stream));
+    pl->coarse_up[w] = true;
+  }
+  PipeArgs pa;
+  pa.stages = pl->cstages_dev[w];
+  pa.nstages = (int)st.size();
+  pa.ntasks = pl->coarse_tasks[w];
+  pa.counters = pl->ccounters;
+  pa.ticket = pl->cflags;
+  pa.abortf = pl->cflags + 1;
+  size_t lds = march_lds_bytes<double>(base_args<double>(pl, pl->d64, 0));
+  if (pl->mixed) lds = std::max(lds, march_lds_bytes<float>(base_args<float>(pl, pl->d32, 0)));
+  Timed tm(pl, MGWR_K_COARSE, pl->coarse_flops[w], pl->coarse_bytes[w]);
+  HIP_TRY(launch_fill_int(pl->ccounters, pl->coarse_cnt[w], 0, pl->stream));
+  HIP_TRY(launch_fill_int(pl->cflags, 1, 0, pl->stream));
+  HIP_TRY(launch_pipeline(pa, lds, pl->stream));
+  return MGWR_OK;
+}
 // Schedules measured by mgwr_plan_autotune, shared by every plan of the same
 // shape in the process: (dim, n, M, precision, inner cycles, k) -> schedule.
 using TuneKey = std::tuple<int, int, int, int, int, int>;
@@ -1065,6 +1150,18 @@ int mgwr_plan_bind(mgwr_plan* pl, void* ws, size_t bytes, void* stream) {
   pl->counters = (int*)(w + o.counters);
   pl->flags_dev = (int*)(w + o.flags);
   pl->norms = (double*)(w + o.norms);
+  {
+    const long long C = stages_per_cycle_bound(hp);
+    pl->cstages_dev[0] = (Stage*)(w + o.cstages);
+    pl->cstages_dev[1] = pl->cstages_dev[0] + C;
+    pl->ccounters = (int*)(w + o.ccounters);
+    pl->cflags = (int*)(w + o.cflags);
+    for (int i = 0; i < 2; ++i) {
+      pl->coarse_stages[i].clear();
+      pl->coarse_up[i] = false;
+    }
+    pl->coarse_l = coarse_switch_level(hp);
+  }
   pl->stages.clear();
   pl->stages_f = nullptr;
   pl->stages_u = nullptr;
@@ -1203,6 +1300,7 @@ int mgwr_solve(mgwr_plan* pl, const double* f, const double* g, double tol, doub
     return fail(MGWR_ERR_NONFINITE, "right-hand side is not finite");
   }
   const double target = tol * s.bnorm;
+  if (pl->coarse_l > 0) HIP_TRY(launch_fill_int(pl->cflags + 1, 1, 0, pl->stream));
 
   if (status == MGWR_ERR_NOT_CONVERGED && !pl->mixed) {
     pl->d64.F[0] = const_cast<double*>(b);
@@ -1260,6 +1358,12 @@ int mgwr_solve(mgwr_plan* pl, const double* f, const double* g, double tol, doub
       if (s.res <= target) { status = MGWR_OK; break; }
       HIP_TRY(launch_cast<double, float>(pl->d64.R[0], pl->d32.F[0], MN, pl->stream));
     }
+  }
+  if (pl->coarse_l > 0 && s.cycles > 0) {
+    int stalled = 0;
+    HIP_TRY(hipMemcpyAsync(&stalled, pl->cflags + 1, sizeof(int), hipMemcpyDeviceToHost, pl->stream));
+    HIP_TRY(hipStreamSynchronize(pl->stream));
+    if (stalled) return fail(MGWR_ERR_HIP, "pipelined coarse cycles stalled (a progress wait exceeded its bound)");
   }
   s.avg_factor = (s.cycles > 0 && s.res0 > 0) ? std::pow(s.res / s.res0, 1.0 / s.cycles) : 0.0;
   if (st) *st = s;
