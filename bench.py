@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large1d", choices=["large1d", "large2d", "small1d", "batched"])
     ap.add_argument("--batch-count", type=int, default=64, help="instances of the batched workload")
+    ap.add_argument("--batch-schedule", default="auto", choices=["auto", "autotune"],
+                    help="batched workload: the plans' AUTO rule, or the autotuner per (n, M) bucket")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
@@ -198,8 +200,9 @@ def learned_forms(args, probs, fs, us, unknowns, mg, torch):
 def batched_main(args):
     """The batched workload: `batch_count` uneven 2D instances of the
     random-Fourier family (sides {63, 127, 255}, M in {256..2048}, alpha ~
-    U[0.2, 0.9]) solved together: the schedule of each (n, M) bucket chosen
-    by the autotuner on its first instance, the pipelined instances in one
+    U[0.2, 0.9]) solved together: the schedule of each instance by the AUTO
+    rule (or, with --batch-schedule autotune, by the autotuner on the first
+    instance of its (n, M) bucket), the pipelined instances in one
     merged launch (graph-replayed), the staged ones after it."""
     import torch
 
@@ -225,7 +228,7 @@ def batched_main(args):
         t0 = time.perf_counter()
         for p, pl, f, u in zip(probs, plans, fs, us):
             key = (p.n, p.M, precision)
-            if key not in tuned:
+            if key not in tuned and args.batch_schedule == "autotune":
                 tuned[key] = pl.autotune(f, tol=args.tol, u=u)
         tune_s = time.perf_counter() - t0
         batch = mg.Batch(plans, graph=True).bind()
@@ -255,7 +258,10 @@ def batched_main(args):
         "config": {"workload": f"batched: {len(probs)} 2D instances, sides {{63,127,255}}, M {{256..2048}}, "
                                "alpha~U[0.2,0.9], r=(2-a)/a, k=10, leaf 16, V(1,1)",
                    "instances": len(probs), "unknowns": unknowns, "tol": args.tol,
-                   "schedules": {f"n{k[0]}_M{k[1]}_{k[2]}": v for k, v in sorted(tuned.items())}},
+                   "schedules": ({f"n{k[0]}_M{k[1]}_{k[2]}": v for k, v in sorted(tuned.items())}
+                                 if args.batch_schedule == "autotune" else
+                                 "auto: pipelined when the finest half-sweep has at most 256 chains of 16 columns, "
+                                 "else staged with the coarse levels pipelined")},
         "roofline": {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
                      "avg_launch_us": 1e3 * sm["ms"] / max(1, sm["launches"]), "launches": sm["launches"]},
