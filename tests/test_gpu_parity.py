@@ -101,6 +101,24 @@ def test_random_source_and_initial_value_parity(dev, dim, n, M, alpha, r, k):
     assert res < 1e-12
 
 
+@pytest.mark.parametrize("schedule", ["staged", "pipelined"])
+@pytest.mark.parametrize("dim,n,M,precision", [(1, 15, 16, "fp64"), (1, 31, 17, "fp64"), (2, 7, 33, "fp64"),
+                                               (2, 15, 16, "mixed"), (1, 63, 33, "mixed")])
+def test_one_to_three_leaves(dev, schedule, dim, n, M, precision):
+    """Time meshes of one leaf (M = 16) and of two or three ragged leaves
+    (M = 17: 8 + 9; M = 33: 16 + 8 + 9): the first and last leaf steps of the
+    marches, the input loads one leaf ahead and the progress reads near the
+    end all meet their edge cases."""
+    rng = np.random.default_rng(M + n)
+    N = n ** dim
+    t = W.graded_mesh(M, 1.0, 2.5)
+    p = W.Problem(dim=dim, n=n, M=M, alpha=0.45, r=2.5, k=6, t=t, f=rng.standard_normal((M, N)))
+    print("case", schedule, dim, n, M, precision, flush=True)
+    err, res, st = _solve_and_compare(p, dev, g=rng.standard_normal(N), schedule=schedule, precision=precision,
+                                      tol=1e-11)
+    assert err < 1e-9 and res < 1e-10, (err, res, st)
+
+
 def test_paper_1d_problem_small(dev):
     p = W.paper_1d_mittag_leffler(63, 64, 0.6, k=20)
     err, res, st = _solve_and_compare(p, dev, g=p.g)
