@@ -248,15 +248,17 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
   // are in flight while leaf s + 1 is solved, so no global-memory round trip
   // lies on the path from one solve to the next.
   constexpr int kIO = NW - 1;
-  // waves sharing the products of phase 2 (the IO wave has none: its phase 2
-  // holds the stencil part, the wait for the producer and the input loads)
+  // waves sharing the dense blocks and the far-field products of phase 2 (the
+  // IO wave only takes far-field chunks left over by them)
   constexpr int NPW = NW - 1;
   const bool pworker = wave < NPW;
   // Prefetch slots.  Far-field chunk of slot k2: workers take chunks
   // wave + k2 NPW (the first FPF NPW), the IO wave the next FPF; chunks
   // beyond FPF NW go round-robin to the workers, loaded when used.  Update
-  // tile of slot k2: waves 1.. take tiles (wave - 1) + k2 (NW - 1), wave 0
-  // (which solves first) the next ZPF; tiles beyond ZPF NW go to waves 1..
+  // tile of slot k2: waves 1 .. NW-1 take tiles (wave - 1) + k2 (NW - 1)
+  // (waves 1 .. NW-2 in phase 1 of the next leaf, the IO wave in phase 2 of
+  // the leaf itself), wave 0 (which solves first) the next ZPF; tiles beyond
+  // ZPF NW go round-robin to waves 1 .. NW-1, loaded when used.
   const int ffbase = pworker ? wave : FPF * NPW;
   const int ffstride = pworker ? NPW : 1;
   const int zbase = wave == 0 ? ZPF * (NW - 1) : wave - 1;
@@ -266,13 +268,13 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
 
   // ---- registers holding prefetched operands -------------------------------
   constexpr int NB = 4;                 // stencil neighbours loaded per row (2 used in 1D)
-  T pf_f[4], pf_n[4][NB], pf_u[4];      // wave 0: raw inputs of the next leaf's rows
+  T pf_f[4], pf_n[4][NB], pf_u[4];      // IO wave: raw stencil inputs of a later leaf's rows
   T pf_c[4];                            // fused coarse correction at the column's own coarse point
   T dpf[DPF][4];                        // dense tiles of the next phase 2
   int djj[DPF];
   T fpf[FPF];                           // far-field chunks of the next phase 2
   int fzr[FPF];
-  T zpf[ZPF][4];                        // helper: column-update tiles of the next phase 1
+  T zpf[ZPF][4];                        // column-update tiles of this wave's next Z update
   int zpr[ZPF][4];
   T di[4];                              // wave 0: diagonal inverse of the next solve
 
@@ -287,7 +289,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
     return a.dense + (long long)d.diag_off * 256;
   };
 
-  // wave 0: inputs of leaf li (in the pipeline, after the producer finished it)
+  // IO wave: stencil inputs of leaf li (in the pipeline, after the producer finished it)
   auto prefetch_inputs = [&](int li) -> bool {
     if constexpr (PIPE) {
       if (!wait_leaf(pc, li, nleaf, ready)) return false;
