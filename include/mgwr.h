@@ -323,6 +323,17 @@ int mgwr_plan_get_mesh(const mgwr_plan* plan, double* t_host, double* a1_host);
  * device receives (tests compare it with an independent construction). */
 int mgwr_plan_export_dense(const mgwr_plan* plan, double* Rt_host);
 
+/* Bound on the polls one work item of a pipelined launch (the pipelined
+ * schedule, a batch holding the plan, the coarse levels of staged cycles)
+ * makes while waiting for the progress of the stage it consumes.  When a wait
+ * exceeds it, the launch sets an abort flag, every waiting work item gives up,
+ * and the solve returns MGWR_ERR_HIP ("... stalled"); the arrays then hold no
+ * meaningful result.  The default, 4194304 polls, is seconds (a failed poll
+ * sleeps about 128 cycles); smaller values make a stalled launch fail sooner.
+ * 0: give up at the first wait whose producer has not finished already (used
+ * to exercise this path).  A batch uses the smallest bound of its plans. */
+int mgwr_plan_set_progress_limit(mgwr_plan* plan, unsigned polls);
+
 /* Release host state.  Never frees caller memory.  Safe on NULL. */
 int mgwr_plan_destroy(mgwr_plan* plan);
 

@@ -28,7 +28,8 @@ MGWR_WARM_RES0 = 4
 EXPORTED = [
     "mgwr_params_default", "mgwr_plan_create", "mgwr_plan_workspace_bytes", "mgwr_plan_bind",
     "mgwr_solve", "mgwr_residual", "mgwr_hmatvec", "mgwr_htrsm", "mgwr_plan_get_info",
-    "mgwr_plan_get_mesh", "mgwr_plan_export_dense", "mgwr_plan_destroy", "mgwr_last_error",
+    "mgwr_plan_get_mesh", "mgwr_plan_export_dense", "mgwr_plan_set_progress_limit", "mgwr_plan_destroy",
+    "mgwr_last_error",
     "mgwr_timing_enable", "mgwr_timing_get", "mgwr_batch_create", "mgwr_batch_workspace_bytes",
     "mgwr_batch_bind", "mgwr_batch_solve", "mgwr_batch_timing", "mgwr_batch_destroy",
     "mgwr_net_create", "mgwr_net_param_count", "mgwr_net_workspace_bytes", "mgwr_net_bind",
@@ -113,6 +114,7 @@ def lib():
     L.mgwr_plan_get_mesh.argtypes = [vp, dp, dp]
     L.mgwr_plan_export_dense.argtypes = [vp, dp]
     L.mgwr_plan_destroy.argtypes = [vp]
+    L.mgwr_plan_set_progress_limit.argtypes = [vp, ctypes.c_uint]
     L.mgwr_timing_enable.argtypes = [vp, ip]
     L.mgwr_timing_get.argtypes = [vp, ctypes.POINTER(Timing)]
     L.mgwr_batch_create.argtypes = [ip, ctypes.POINTER(vp), ctypes.POINTER(vp)]
@@ -324,6 +326,12 @@ class Plan:
         tm = Timing()
         _check(lib().mgwr_timing_get(self._h, ctypes.byref(tm)))
         return tm.as_dict()
+
+    def set_progress_limit(self, polls: int):
+        """Bound on the polls of one progress wait of a pipelined launch
+        (default 4194304); beyond it the solve fails with MGWR_ERR_HIP."""
+        _check(lib().mgwr_plan_set_progress_limit(self._h, int(polls)))
+        return self
 
     def close(self):
         if getattr(self, "_h", None):

@@ -86,7 +86,12 @@ struct PipeArgs {
   int* counters;
   int* ticket;
   int* abortf;
+  unsigned spin_limit;   // polls of a progress wait before the launch gives up
 };
+
+// Default bound on the polls of one progress wait (each poll sleeps about
+// 128 cycles when it fails): seconds, far beyond any producer's lag.
+constexpr unsigned kDefaultSpinLimit = 1u << 22;
 
 constexpr int kStencilCols = 64;   // columns per work item of a stencil stage (leaf rows <= 16 = 4 x 4)
 

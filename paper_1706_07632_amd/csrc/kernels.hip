@@ -118,9 +118,8 @@ struct PipeCtx {
   int* done;         // this stage's per-leaf counters
   int* abortf;       // set when a wait exceeds its bound; every waiter then gives up
   double* norm_out;  // defect stages: max |r| of this work item, or null
+  unsigned spin_limit = kDefaultSpinLimit;   // polls before a wait gives up
 };
-
-constexpr unsigned kSpinLimit = 1u << 22;
 
 // Waits until the producer has finished leaf `leaf` (of nleaf).  `ready` is
 // held by the calling wave: the last leaf known finished.  A wait that must
@@ -147,7 +146,7 @@ __device__ bool wait_leaf(const PipeCtx& pc, int leaf, int nleaf, int& ready) {
       return true;
     }
     if (__hip_atomic_load(pc.abortf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
-    if (it > kSpinLimit) {
+    if (it >= pc.spin_limit) {
       __hip_atomic_store(pc.abortf, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return false;
     }
@@ -965,6 +964,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void p
   pc.need = prev >= 0 ? ldc(&pa.stages[prev].nchunks) : 0;
   pc.done = pa.counters + ldc(&stp->cnt_off);
   pc.abortf = pa.abortf;
+  pc.spin_limit = pa.spin_limit;
   pc.norm_out = ldc(&stp->norm_out);
   const int chunk = task - ldc(&stp->task0);
   if (kind == STG_SMOOTH || kind == STG_RESID) {

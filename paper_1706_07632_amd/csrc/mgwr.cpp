@@ -113,6 +113,7 @@ struct mgwr_plan {
   // staged schedule: from level coarse_l on (0: never) a cycle's levels run as
   // one pipelined launch ([0] float64, [1] float32 stage images)
   int coarse_l = 0;
+  unsigned spin_limit = kDefaultSpinLimit;   // polls of a progress wait (mgwr_plan_set_progress_limit)
   std::vector<Stage> coarse_stages[2];
   int coarse_tasks[2] = {0, 0};
   long long coarse_cnt[2] = {0, 0};
@@ -672,6 +673,7 @@ int coarse_cycle(mgwr_plan* pl, int l) {
   pa.counters = pl->ccounters;
   pa.ticket = pl->cflags;
   pa.abortf = pl->cflags + 1;
+  pa.spin_limit = pl->spin_limit;
   size_t lds = march_lds_bytes<double>(base_args<double>(pl, pl->d64, 0));
   if (pl->mixed) lds = std::max(lds, march_lds_bytes<float>(base_args<float>(pl, pl->d32, 0)));
   Timed tm(pl, MGWR_K_COARSE, pl->coarse_flops[w], pl->coarse_bytes[w]);
@@ -751,11 +753,13 @@ struct mgwr_batch {
   size_t lds = 0;
   bool timing = false;
   mgwr_timing tacc{};
+  unsigned spin_limit = kDefaultSpinLimit;   // the smallest bound of its plans
   // replay of an unchanged launch (stage table, counters, grid) as a HIP graph
   bool use_graph = false;
   std::vector<Stage> graph_stages;     // the table the captured graph runs
   long long graph_ncnt = 0;
   int graph_ntasks = 0;
+  unsigned graph_spin = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   hipStream_t capture_stream = nullptr;  // private (the caller's may be the legacy stream, which cannot capture)
@@ -874,6 +878,8 @@ int fall_back_to_zero(mgwr_plan* pl, const double* b, double* u, mgwr_stats& s, 
 // pipeline kernel; replayed from a captured graph when the table, counter
 // count and grid equal those of the graph (batches with graphs enabled).
 int launch_batch_table(mgwr_batch* bt, long long ncnt, int ntasks) {
+  bt->spin_limit = kDefaultSpinLimit;
+  for (const mgwr_plan* p : bt->plans) bt->spin_limit = std::min(bt->spin_limit, p->spin_limit);
   PipeArgs pa;
   pa.stages = bt->stages_dev;
   pa.nstages = (int)bt->stages.size();
@@ -881,7 +887,9 @@ int launch_batch_table(mgwr_batch* bt, long long ncnt, int ntasks) {
   pa.counters = bt->counters;
   pa.ticket = bt->flags_dev;
   pa.abortf = bt->flags_dev + 1;
+  pa.spin_limit = bt->spin_limit;
   const bool same = bt->graph_exec && bt->graph_ncnt == ncnt && bt->graph_ntasks == ntasks &&
+                    bt->graph_spin == bt->spin_limit &&
                     bt->graph_stages.size() == bt->stages.size() &&
                     std::memcmp(bt->graph_stages.data(), bt->stages.data(), bt->stages.size() * sizeof(Stage)) == 0;
   if (same) {
@@ -917,6 +925,7 @@ int launch_batch_table(mgwr_batch* bt, long long ncnt, int ntasks) {
   bt->graph_stages = bt->stages;
   bt->graph_ncnt = ncnt;
   bt->graph_ntasks = ntasks;
+  bt->graph_spin = bt->spin_limit;
   HIP_TRY(hipGraphLaunch(bt->graph_exec, bt->stream));
   return MGWR_OK;
 }
@@ -1474,6 +1483,12 @@ int mgwr_plan_get_mesh(const mgwr_plan* pl, double* t, double* a1) {
 int mgwr_plan_export_dense(const mgwr_plan* pl, double* Rt) {
   if (!pl || !Rt) return fail(MGWR_ERR_INVALID_ARG, "null argument");
   export_dense(pl->hp, Rt);
+  return MGWR_OK;
+}
+
+int mgwr_plan_set_progress_limit(mgwr_plan* pl, unsigned polls) {
+  if (!pl) return fail(MGWR_ERR_INVALID_ARG, "null plan");
+  pl->spin_limit = polls;
   return MGWR_OK;
 }
 

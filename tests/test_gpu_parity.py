@@ -325,3 +325,24 @@ def test_batched_mixed_and_plain_instances(dev):
         res = np.max(np.abs(oracle.residual(Rt, U, p.f, p.dim, p.n, 1.0)))
         assert res <= 1e-8 * st["bnorm"] * 1.01, st
         assert np.max(np.abs(U - np.outer(w, s))) / np.max(np.abs(w)) < 1e-7
+
+
+@pytest.mark.parametrize("schedule", ["pipelined", "staged"])
+def test_stalled_progress_wait_fails_and_the_plan_recovers(dev, schedule):
+    """A progress bound of 0 polls makes the first wait that finds its
+    producer behind give up: the pipelined launch (or, staged, the launch of
+    the coarse levels) stops every work item, the solve reports the stall, and
+    with the default bound restored the same plan solves correctly."""
+    p = W.manufactured(1, 127, 512, 0.5, r=3.0, k=8)
+    plan = _plan(p, dev, schedule=schedule)
+    f = _cuda(p.f, dev)
+    Rt, w, s = _single_mode_reference(p)
+    plan.set_progress_limit(0)
+    with pytest.raises(mg.MgwrError) as ei:
+        plan.solve(f, tol=1e-10)
+    assert ei.value.code == mg.MGWR_ERR_HIP and "stalled" in str(ei.value)
+    plan.set_progress_limit(1 << 22)
+    for rep in range(2):
+        u, st = plan.solve(f, tol=1e-10)
+        err = np.max(np.abs(u.cpu().numpy() - np.outer(w, s))) / np.max(np.abs(w))
+        assert err < 1e-9, (rep, err, st)
