@@ -34,8 +34,8 @@ PEAK_HBM_GBS = 8000.0
 # workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by what the same
 # counters read for a 1 GiB device copy (--copy-probe): fetch x 2.000, write x
 # 1.000.  Valid only for the kernel source they were taken on.
-TRAFFIC_KERNEL_SHA256 = "3eb882cfa5fd1571214ddadcd50524789ac2fd8e8a00a8b145c16e76d7e51516"
-TRAFFIC_BYTES = {"large1d": (2.000 * 24233395.4 + 1.000 * 8656865.9) * 1024}
+TRAFFIC_KERNEL_SHA256 = "740372dd1b6359e73e0d4558498519457b04c4a0e521749f43157f545eef8b7e"
+TRAFFIC_BYTES = {"large1d": (2.000 * 24585088.7 + 1.000 * 8656866.5) * 1024}
 
 
 def parse():
