@@ -11,8 +11,9 @@ manufactured solution u = t^alpha sin(pi x), zero initial guess.  One step =
 one solve of each of the three instances.  Sources are synthetic (closed form)
 and resident in HBM before timing starts.
 
-Prints one JSON line.  `value` is the plain float64 solver; the float32-inner
-mixed-precision form is reported next to it under `forms`.
+Prints one JSON line.  `value` is the plain float64 solver; the mixed-precision
+forms (float32 inner cycles, with float32 or bfloat16 low-rank factors) and the
+learned warm start are reported next to it under `forms`.
 """
 from __future__ import annotations
 
@@ -220,8 +221,8 @@ def batched_main(args):
     us = [torch.empty_like(f) for f in fs]
     unknowns = sum(p.N * p.M for p in probs)
     forms, out_timing, tuned = {}, None, {}
-    for name, precision in (("fp64", "fp64"), ("mixed_fp32", "mixed")):
-        if name == "mixed_fp32" and args.no_mixed:
+    for name, precision in (("fp64", "fp64"), ("mixed_fp32", "mixed"), ("mixed_bf16", "mixed_bf16")):
+        if name != "fp64" and args.no_mixed:
             continue
         plans = [mg.Plan(2, p.n, p.M, p.alpha, k=p.k, r=p.r, t=p.t, precision=precision, inner_cycles=1).bind()
                  for p in probs]
@@ -330,22 +331,24 @@ def main():
                    "TFLOP/s": round(v["flops"] / max(v["ms"], 1e-9) * 1e-9, 3),
                    "GB/s": round(v["bytes"] / max(v["ms"], 1e-9) * 1e-6, 1)} for k, v in tm.items() if v["launches"]}
 
-    if not args.no_mixed:
+    for name, precision in (("mixed_fp32", "mixed"), ("mixed_bf16", "mixed_bf16")):
+        if args.no_mixed:
+            break
         mplans = [mg.Plan(p.dim, p.n, p.M, p.alpha, k=p.k, r=p.r, t=p.t, length=p.length, leaf=p.leaf,
-                          precision="mixed", inner_cycles=1).bind() for p in probs]
+                          precision=precision, inner_cycles=1).bind() for p in probs]
         if len(mplans) > 1:
             mbatch = mg.Batch(mplans).bind()
             msecs, mstats, mtiming = time_batch(mbatch, fs, us, args.tol, args.steps, args.warmup, torch)
         else:
             msecs, mstats, mtiming = time_form(mplans, fs, us, args.tol, args.steps, args.warmup, torch)
         mtm = merge_timing(mtiming)
-        forms["mixed_fp32"] = {"value": unknowns * args.steps / msecs, "ms_per_step": 1e3 * msecs / args.steps,
-                               "cycles": [s["cycles"] for s in mstats[:len(probs)]],
-                               "refinements": [s["refinements"] for s in mstats[:len(probs)]],
-                               "rel_res": [s["res"] / s["bnorm"] for s in mstats[:len(probs)]]}
-        forms["mixed_fp32"]["kernels"] = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
-                                              "avg_us": round(1e3 * v["ms"] / max(1, v["launches"]), 2)}
-                                          for k, v in mtm.items() if v["launches"]}
+        forms[name] = {"value": unknowns * args.steps / msecs, "ms_per_step": 1e3 * msecs / args.steps,
+                       "cycles": [s["cycles"] for s in mstats[:len(probs)]],
+                       "refinements": [s["refinements"] for s in mstats[:len(probs)]],
+                       "rel_res": [s["res"] / s["bnorm"] for s in mstats[:len(probs)]]}
+        forms[name]["kernels"] = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
+                                      "avg_us": round(1e3 * v["ms"] / max(1, v["launches"]), 2)}
+                                  for k, v in mtm.items() if v["launches"]}
 
     if not args.no_learned:
         forms.update(learned_forms(args, probs, fs, us, unknowns, mg, torch))

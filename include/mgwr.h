@@ -52,7 +52,11 @@ enum {
 
 typedef enum {
   MGWR_FP64 = 0,        /* every cycle in float64 */
-  MGWR_MIXED_FP32 = 1   /* float64 outer residual and correction, float32 inner V-cycles */
+  MGWR_MIXED_FP32 = 1,  /* float64 outer residual and correction, float32 inner V-cycles */
+  MGWR_MIXED_BF16 = 2   /* as MGWR_MIXED_FP32, with the low-rank (Taylor) factors of the inner cycles
+                           stored in bfloat16 (round to nearest even from their float32 values) and
+                           widened to float32 for the products; dense leaves, shifted inverses, the
+                           iterates and every accumulation stay float32, the outer steps float64 */
 } mgwr_precision;
 
 /* Flags of mgwr_solve. */

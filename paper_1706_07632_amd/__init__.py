@@ -21,6 +21,7 @@ MGWR_ERR_NOT_CONVERGED = 4
 MGWR_ERR_NONFINITE = 5
 MGWR_FP64 = 0
 MGWR_MIXED_FP32 = 1
+MGWR_MIXED_BF16 = 2
 MGWR_GUESS_IN_U = 1
 MGWR_WARM_START = 2
 MGWR_WARM_RES0 = 4
@@ -188,7 +189,8 @@ class Plan:
         p.dim, p.n, p.M, p.alpha, p.k = int(dim), int(n), int(M), float(alpha), int(k)
         p.r, p.T, p.length, p.leaf = float(r), float(T), float(length), int(leaf)
         p.nu1, p.nu2, p.gamma, p.max_cycles = int(nu1), int(nu2), int(gamma), int(max_cycles)
-        p.precision = {"fp64": MGWR_FP64, "mixed": MGWR_MIXED_FP32, "fp32": MGWR_MIXED_FP32}[precision]
+        p.precision = {"fp64": MGWR_FP64, "mixed": MGWR_MIXED_FP32, "fp32": MGWR_MIXED_FP32,
+                       "mixed_bf16": MGWR_MIXED_BF16, "bf16": MGWR_MIXED_BF16}[precision]
         p.inner_cycles = int(inner_cycles)
         p.schedule = {"auto": 0, "staged": 1, "pipelined": 2}[schedule]
         self.params = p

@@ -69,8 +69,9 @@ std::string build_host_plan(const mgwr_params& p, const double* t_host, HostPlan
   if (p.nu1 < 0 || p.nu2 < 0 || p.nu1 + p.nu2 < 1) return "nu1, nu2 >= 0 with nu1 + nu2 >= 1";
   if (p.gamma < 1 || p.gamma > 2) return "gamma must be 1 (V) or 2 (W)";
   if (p.max_cycles < 1) return "max_cycles must be >= 1";
-  if (p.precision != MGWR_FP64 && p.precision != MGWR_MIXED_FP32) return "unknown precision";
-  if (p.precision == MGWR_MIXED_FP32 && (p.inner_cycles < 1 || p.inner_cycles > kMaxInnerCycles))
+  if (p.precision != MGWR_FP64 && p.precision != MGWR_MIXED_FP32 && p.precision != MGWR_MIXED_BF16)
+    return "unknown precision";
+  if (p.precision != MGWR_FP64 && (p.inner_cycles < 1 || p.inner_cycles > kMaxInnerCycles))
     return "inner_cycles must be between 1 and " + std::to_string(kMaxInnerCycles);
   if (p.schedule != MGWR_SCHED_AUTO && p.schedule != MGWR_SCHED_PIPELINED && p.schedule != MGWR_SCHED_STAGED)
     return "unknown schedule";

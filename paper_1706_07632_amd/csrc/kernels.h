@@ -24,6 +24,9 @@ struct MarchArgs {
   const T* ffA;
   const int* zu_row;
   const T* zuB;
+  // float32 marches only: when set, ffA and zuB point at bfloat16 copies of
+  // the far-field chunks and update tiles (2-byte entries, same indexing)
+  int lr_bf16;
   int k, nslots, ring;
   // data
   const T* F;         // right-hand side (SMOOTH, RESID, TRSM)
@@ -116,6 +119,8 @@ hipError_t launch_rhs0(const double* f, const double* gq, const double* a1, doub
                        hipStream_t s);
 template <typename T> hipError_t launch_fill(T* x, long long count, T v, hipStream_t s);
 template <typename S, typename D> hipError_t launch_cast(const S* x, D* y, long long count, hipStream_t s);
+// y[i] = bfloat16 bits of (float)x[i], rounded to nearest even (finite x)
+hipError_t launch_cast_bf16(const double* x, unsigned short* y, long long count, hipStream_t s);
 hipError_t launch_add_correction(double* u, const float* e, long long count, hipStream_t s);
 template <typename T>
 hipError_t launch_maxabs(const T* x, long long count, double* part, int nparts, double* out, hipStream_t s);

@@ -55,6 +55,16 @@ template <> __device__ __forceinline__ int drow<float>(int g, int r) { return 4 
 template <typename T> __device__ __forceinline__ const GLOBAL_AS T* gp(const T* p) { return (const GLOBAL_AS T*)p; }
 template <typename T> __device__ __forceinline__ GLOBAL_AS T* gp(T* p) { return (GLOBAL_AS T*)p; }
 template <typename T> __device__ __forceinline__ T ld(const T* p) { return *gp(p); }
+// Word holding entry i of a low-rank factor array.  In float32 marches of a
+// plan that keeps those factors in bfloat16 (`bf16` = 1) the array holds
+// 2-byte entries, two to a word, and the word holding entry i is read (two
+// lanes share it); the lane's half is picked and widened where the value is
+// used, so that nothing waits for the load here.  Otherwise the entry itself.
+template <typename T>
+__device__ __forceinline__ T ld_lr(const T* p, int bf16, long long i) {
+  if constexpr (sizeof(T) == 4) return ld(p + (i >> bf16));
+  else return ld(p + i);
+}
 // Read-only tables indexed uniformly across a wave (leaf descriptors, the
 // dense-block list, stage arguments) are read through the constant address
 // space, i.e. scalar loads with their own cache and shorter latency.
@@ -238,6 +248,17 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
     nb[3] = q + a.n; nbok[3] = colok && iy + 1 < a.n;
   }
   const T diagc = (T)(2 * a.dim);
+  // Low-rank factor operands as ld_lr() loaded them, made values of T.  Every
+  // factor entry a lane reads has the lane's parity (offsets are whole chunks
+  // of 64 plus the lane), so with bfloat16 factors an even lane's entry is the
+  // low half of its word and an odd lane's the high half; a bfloat16 value
+  // widens to float32 as the upper half of the word, the lower half zero.
+  const unsigned lr_shr = (sizeof(T) == 4 && a.lr_bf16) ? (unsigned)(lane & 1) * 16u : 0u;
+  const unsigned lr_shl = (sizeof(T) == 4 && a.lr_bf16) ? 16u : 0u;
+  auto lr = [&](T v) -> T {
+    if constexpr (sizeof(T) == 4) return __uint_as_float((__float_as_uint(v) >> lr_shr) << lr_shl);
+    else return v;
+  };
   constexpr bool kSolve = (MODE == MODE_SMOOTH || MODE == MODE_TRSM);
   constexpr bool kKnownX = (MODE == MODE_RESID || MODE == MODE_MATVEC);
   // Work split: wave 0 sums, solves (or forms the defect) and stores the
@@ -335,7 +356,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
     for (int k2 = 0; k2 < FPF; ++k2) {
       const int ch = ffbase + k2 * ffstride;
       if (ch < d.ff_nchunk) {
-        fpf[k2] = ld(a.ffA + (long long)(d.ff_begin + ch) * 64 + lane);
+        fpf[k2] = ld_lr(a.ffA, a.lr_bf16, (long long)(d.ff_begin + ch) * 64 + lane);
         fzr[k2] = ld(a.ff_row + (d.ff_begin + ch) * 4 + g);
       }
     }
@@ -348,9 +369,9 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
     for (int k2 = 0; k2 < ZPF; ++k2) {
       const int tt = zbase + k2 * zstride;
       if (tt < d.zu_ntile) {
-        const T* Bt = a.zuB + (long long)(d.zu_begin + tt) * 256;
+        const long long bt0 = (long long)(d.zu_begin + tt) * 256;
 #pragma unroll
-        for (int kc = 0; kc < 4; ++kc) zpf[k2][kc] = ld(Bt + kc * 64 + lane);
+        for (int kc = 0; kc < 4; ++kc) zpf[k2][kc] = ld_lr(a.zuB, a.lr_bf16, bt0 + kc * 64 + lane);
 #pragma unroll
         for (int r = 0; r < 4; ++r) zpr[k2][r] = ld(a.zu_row + (d.zu_begin + tt) * 16 + drow<T>(g, r));
       }
@@ -401,7 +422,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
     for (int k2 = 0; k2 < FPF; ++k2) {
       if (ffbase + k2 * ffstride < nff) {
         const T bv = fzr[k2] >= 0 ? Z[fzr[k2] * 16 + c] : (T)0;
-        acc = mfma(fpf[k2], bv, acc);
+        acc = mfma(lr(fpf[k2]), bv, acc);
       }
     }
     for (int ch0 = FPF * NW + wave; pworker && ch0 < nff; ch0 += FPF * NPW) {
@@ -409,13 +430,13 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
 #pragma unroll
       for (int b = 0; b < FPF; ++b) {
         const int ch = min(ch0 + b * NPW, nff - 1);
-        av[b] = ld(a.ffA + (long long)(d.ff_begin + ch) * 64 + lane);
+        av[b] = ld_lr(a.ffA, a.lr_bf16, (long long)(d.ff_begin + ch) * 64 + lane);
         const int zr = ld(a.ff_row + (d.ff_begin + ch) * 4 + g);
         bv[b] = (zr >= 0 && ch0 + b * NPW < nff) ? Z[zr * 16 + c] : (T)0;
       }
 #pragma unroll
       for (int b = 0; b < FPF; ++b)
-        if (ch0 + b * NPW < nff) acc = mfma(av[b], bv[b], acc);
+        if (ch0 + b * NPW < nff) acc = mfma(lr(av[b]), bv[b], acc);
     }
     if (stencil) {
 #pragma unroll
@@ -453,7 +474,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
 #pragma unroll
       for (int r = 0; r < 4; ++r) z[r] = (zr[r] >= 0 && !(zr[r] & ZFIRST)) ? Z[(zr[r] & ZMASK) * 16 + c] : (T)0;
 #pragma unroll
-      for (int kc = 0; kc < 4; ++kc) z = mfma(bt[kc], xb[kc], z);
+      for (int kc = 0; kc < 4; ++kc) z = mfma(lr(bt[kc]), xb[kc], z);
 #pragma unroll
       for (int r = 0; r < 4; ++r)
         if (zr[r] >= 0) Z[(zr[r] & ZMASK) * 16 + c] = z[r];
@@ -468,8 +489,8 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
       }
 #pragma unroll
       for (int kc = 0; kc < 4; ++kc) {
-        z0 = mfma(b0[kc], xb[kc], z0);
-        z1 = mfma(b1[kc], xb[kc], z1);
+        z0 = mfma(lr(b0[kc]), xb[kc], z0);
+        z1 = mfma(lr(b1[kc]), xb[kc], z1);
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -486,9 +507,9 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
     for (int tt = ZPF * NW + (wave - 1); wave != 0 && tt < d.zu_ntile; tt += NW - 1) {
       T bt[4];
       int zr[4];
-      const T* Bt = a.zuB + (long long)(d.zu_begin + tt) * 256;
+      const long long bt0 = (long long)(d.zu_begin + tt) * 256;
 #pragma unroll
-      for (int kc = 0; kc < 4; ++kc) bt[kc] = ld(Bt + kc * 64 + lane);
+      for (int kc = 0; kc < 4; ++kc) bt[kc] = ld_lr(a.zuB, a.lr_bf16, bt0 + kc * 64 + lane);
 #pragma unroll
       for (int r = 0; r < 4; ++r) zr[r] = ld(a.zu_row + (d.zu_begin + tt) * 16 + drow<T>(g, r));
       apply(bt, zr);
@@ -1109,6 +1130,17 @@ __global__ void cast_kernel(const S* __restrict__ x, D* __restrict__ y, long lon
     y[idx] = (D)x[idx];
 }
 
+// y = bfloat16 bits of (float)x, rounded to nearest with ties to even (the
+// values converted here, low-rank factors, are finite)
+__global__ void cast_bf16_kernel(const double* __restrict__ x, unsigned short* __restrict__ y, long long count) {
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < count;
+       idx += (long long)gridDim.x * blockDim.x) {
+    unsigned u = __float_as_uint((float)x[idx]);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    y[idx] = (unsigned short)(u >> 16);
+  }
+}
+
 // u += e (float correction into the float64 iterate)
 __global__ void add_correction_kernel(double* __restrict__ u, const float* __restrict__ e, long long count) {
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < count;
@@ -1253,6 +1285,12 @@ template <typename S, typename D>
 hipError_t launch_cast(const S* x, D* y, long long count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL((cast_kernel<S, D>), dim3(grid_for(count, 256)), dim3(256), 0, s, x, y, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast_bf16(const double* x, unsigned short* y, long long count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(cast_bf16_kernel, dim3(grid_for(count, 256)), dim3(256), 0, s, x, y, count);
   return hipGetLastError();
 }
 

@@ -62,6 +62,9 @@ struct DevOps {  // precision-specific device arrays
   T* dinv = nullptr;
   T* ffA = nullptr;
   T* zuB = nullptr;
+  // float32 operations of a MGWR_MIXED_BF16 plan: ffA and zuB hold bfloat16
+  // entries (2 bytes each)
+  int lr_bf16 = 0;
   std::vector<T*> U, F, R;  // per level
 };
 
@@ -86,7 +89,8 @@ struct mgwr_plan {
   double* scal = nullptr;    // device scalar(s)
   DevOps<double> d64;
   DevOps<float> d32;
-  bool mixed = false;
+  bool mixed = false;   // float32 inner cycles (MGWR_MIXED_FP32 or MGWR_MIXED_BF16)
+  bool bf16 = false;    // their low-rank factors in bfloat16
   // live timing (mgwr_timing_enable)
   struct Pending { hipEvent_t b, e; int cls; double flops, bytes; };
   bool timing = false;
@@ -180,13 +184,16 @@ void layout(mgwr_plan* pl) {
     if (l > 0) { o.U64[l] = cv.take(bytes); o.F64[l] = cv.take(bytes); }
     if (l + 1 < L || l == 0) o.R64[l] = cv.take(bytes);
   }
-  pl->mixed = hp.p.precision == MGWR_MIXED_FP32;
+  pl->mixed = hp.p.precision == MGWR_MIXED_FP32 || hp.p.precision == MGWR_MIXED_BF16;
+  pl->bf16 = hp.p.precision == MGWR_MIXED_BF16;
   o.U32.assign(L, 0); o.F32.assign(L, 0); o.R32.assign(L, 0);
   if (pl->mixed) {
     o.dense32 = cv.take(pk.dense.size() * sizeof(float));
     o.dinv32 = cv.take(pk.dinv.size() * sizeof(float));
-    o.ffA32 = cv.take(std::max<size_t>(1, pk.ffA.size()) * sizeof(float));
-    o.zuB32 = cv.take(std::max<size_t>(1, pk.zuB.size()) * sizeof(float));
+    // the inner cycles' low-rank factors: float32, or bfloat16 (2 bytes)
+    const size_t lr_bytes = pl->bf16 ? 2 : sizeof(float);
+    o.ffA32 = cv.take(std::max<size_t>(1, pk.ffA.size()) * lr_bytes);
+    o.zuB32 = cv.take(std::max<size_t>(1, pk.zuB.size()) * lr_bytes);
     for (int l = 0; l < L; ++l) {
       size_t bytes = (size_t)M * hp.levels[l].N * sizeof(float);
       o.U32[l] = cv.take(bytes);
@@ -274,6 +281,7 @@ MarchArgs<T> base_args(mgwr_plan* pl, const DevOps<T>& ops, int level) {
   a.ffA = ops.ffA;
   a.zu_row = pl->zu_row;
   a.zuB = ops.zuB;
+  a.lr_bf16 = ops.lr_bf16;
   a.k = hp.p.k;
   a.nslots = hp.nslots;
   a.ring = std::max(hp.window + 2, 3);  // leaves written while older ones are still read
@@ -1209,6 +1217,7 @@ int mgwr_plan_bind(mgwr_plan* pl, void* ws, size_t bytes, void* stream) {
     pl->d32.dinv = (float*)(w + o.dinv32);
     pl->d32.ffA = (float*)(w + o.ffA32);
     pl->d32.zuB = (float*)(w + o.zuB32);
+    pl->d32.lr_bf16 = pl->bf16 ? 1 : 0;
     pl->d32.U.assign(L, nullptr); pl->d32.F.assign(L, nullptr); pl->d32.R.assign(L, nullptr);
     for (int l = 0; l < L; ++l) {
       pl->d32.U[l] = (float*)(w + o.U32[l]);
@@ -1218,8 +1227,13 @@ int mgwr_plan_bind(mgwr_plan* pl, void* ws, size_t bytes, void* stream) {
     // float copies are rounded on the device from the float64 image
     HIP_TRY(launch_cast<double, float>(pl->d64.dense, pl->d32.dense, (long long)pk.dense.size(), pl->stream));
     HIP_TRY(launch_cast<double, float>(pl->d64.dinv, pl->d32.dinv, (long long)pk.dinv.size(), pl->stream));
-    HIP_TRY(launch_cast<double, float>(pl->d64.ffA, pl->d32.ffA, (long long)pk.ffA.size(), pl->stream));
-    HIP_TRY(launch_cast<double, float>(pl->d64.zuB, pl->d32.zuB, (long long)pk.zuB.size(), pl->stream));
+    if (pl->bf16) {
+      HIP_TRY(launch_cast_bf16(pl->d64.ffA, (unsigned short*)pl->d32.ffA, (long long)pk.ffA.size(), pl->stream));
+      HIP_TRY(launch_cast_bf16(pl->d64.zuB, (unsigned short*)pl->d32.zuB, (long long)pk.zuB.size(), pl->stream));
+    } else {
+      HIP_TRY(launch_cast<double, float>(pl->d64.ffA, pl->d32.ffA, (long long)pk.ffA.size(), pl->stream));
+      HIP_TRY(launch_cast<double, float>(pl->d64.zuB, pl->d32.zuB, (long long)pk.zuB.size(), pl->stream));
+    }
   }
   // LDS of the marching kernel
   MarchArgs<double> a64 = base_args<double>(pl, pl->d64, 0);

@@ -103,7 +103,8 @@ def test_random_source_and_initial_value_parity(dev, dim, n, M, alpha, r, k):
 
 @pytest.mark.parametrize("schedule", ["staged", "pipelined"])
 @pytest.mark.parametrize("dim,n,M,precision", [(1, 15, 16, "fp64"), (1, 31, 17, "fp64"), (2, 7, 33, "fp64"),
-                                               (2, 15, 16, "mixed"), (1, 63, 33, "mixed")])
+                                               (2, 15, 16, "mixed"), (1, 63, 33, "mixed"),
+                                               (2, 15, 16, "mixed_bf16"), (1, 63, 33, "mixed_bf16")])
 def test_one_to_three_leaves(dev, schedule, dim, n, M, precision):
     """Time meshes of one leaf (M = 16) and of two or three ragged leaves
     (M = 17: 8 + 9; M = 33: 16 + 8 + 9): the first and last leaf steps of the
@@ -201,10 +202,11 @@ def test_large2d_parity_full_size(dev):
     assert np.max(np.abs(U - ref)) / np.max(np.abs(np.outer(w, s))) < 1e-10, st
 
 
+@pytest.mark.parametrize("precision", ["mixed", "mixed_bf16"])
 @pytest.mark.parametrize("schedule,inner", [("staged", 1), ("pipelined", 1), ("pipelined", 2)])
-def test_mixed_precision_reaches_tolerance(dev, schedule, inner):
+def test_mixed_precision_reaches_tolerance(dev, schedule, inner, precision):
     p = W.manufactured(1, 255, 1024, 0.5, r=3.0, k=10)
-    plan = _plan(p, dev, precision="mixed", inner_cycles=inner, schedule=schedule)
+    plan = _plan(p, dev, precision=precision, inner_cycles=inner, schedule=schedule)
     u, st = plan.solve(_cuda(p.f, dev), tol=1e-8)
     Rt, w, s = _single_mode_reference(p)
     U = u.cpu().numpy()
@@ -230,11 +232,13 @@ def test_not_converged_status_and_nonfinite(dev):
     assert ei.value.code == mg.MGWR_ERR_NONFINITE
 
 
-def test_mixed_precision_on_strongly_graded_mesh(dev):
-    """alpha = 0.3, r = 17/3, M = 4096 puts t_1 near 3e-21: the float32 copies of
-    the Taylor factors must stay in range (they are stored rescaled)."""
+@pytest.mark.parametrize("precision", ["mixed", "mixed_bf16"])
+def test_mixed_precision_on_strongly_graded_mesh(dev, precision):
+    """alpha = 0.3, r = 17/3, M = 4096 puts t_1 near 3e-21: the float32 (and
+    bfloat16) copies of the Taylor factors must stay in range (they are stored
+    rescaled)."""
     p = W.config("large1d", 0.3)
-    plan = _plan(p, dev, precision="mixed", inner_cycles=1)
+    plan = _plan(p, dev, precision=precision, inner_cycles=1)
     u, st = plan.solve(_cuda(p.f, dev), tol=1e-8)
     Rt, w, s = _single_mode_reference(p)
     U = u.cpu().numpy()
@@ -312,11 +316,13 @@ def test_repeated_solves_keep_cycle_count(dev):
 
 
 def test_batched_mixed_and_plain_instances(dev):
-    """A batch holding float64 and mixed-precision plans (1D and 2D)."""
+    """A batch holding float64, mixed-precision and bfloat16-factor plans (1D
+    and 2D) in one launch."""
     probs = [W.manufactured(1, 127, 512, 0.4, k=10), W.manufactured(2, 31, 256, 0.6, r=3.0, k=8)]
     plans = [_plan(probs[0], dev, precision="mixed"), _plan(probs[1], dev),
-             _plan(probs[1], dev, precision="mixed", inner_cycles=2)]
-    probs = [probs[0], probs[1], probs[1]]
+             _plan(probs[1], dev, precision="mixed", inner_cycles=2),
+             _plan(probs[0], dev, precision="mixed_bf16"), _plan(probs[1], dev, precision="mixed_bf16")]
+    probs = [probs[0], probs[1], probs[1], probs[0], probs[1]]
     batch = mg.Batch(plans).bind()
     us, sts = batch.solve([_cuda(p.f, dev) for p in probs], tol=1e-8)
     for p, u, st in zip(probs, us, sts):
@@ -346,3 +352,29 @@ def test_stalled_progress_wait_fails_and_the_plan_recovers(dev, schedule):
         u, st = plan.solve(f, tol=1e-10)
         err = np.max(np.abs(u.cpu().numpy() - np.outer(w, s))) / np.max(np.abs(w))
         assert err < 1e-9, (rep, err, st)
+
+
+@pytest.mark.parametrize("schedule", ["staged", "pipelined"])
+def test_bfloat16_factors_change_the_inner_cycles_not_the_answer(dev, schedule):
+    """The bfloat16 form runs different inner cycles from the float32 form (its
+    low-rank factors carry about 3 significant digits), so after one
+    refinement step the two iterates differ by more than float32 rounding
+    explains; both converge to the float64 tolerance and to the oracle's
+    solution."""
+    p = W.manufactured(1, 255, 1024, 0.5, r=3.0, k=10)
+    f = _cuda(p.f, dev)
+    Rt, w, s = _single_mode_reference(p)
+    ref = np.outer(w, s)
+    one = {}
+    for precision in ("mixed", "mixed_bf16"):
+        plan = _plan(p, dev, precision=precision, schedule=schedule, max_cycles=1)
+        u1, _ = plan.solve(f, tol=1e-14, allow_unconverged=True)
+        one[precision] = u1.cpu().numpy()
+        plan = _plan(p, dev, precision=precision, schedule=schedule)
+        u, st = plan.solve(f, tol=1e-9)
+        U = u.cpu().numpy()
+        res = np.max(np.abs(oracle.residual(Rt, U, p.f, 1, p.n, 1.0)))
+        assert res <= 1e-9 * st["bnorm"] * 1.01, (precision, st)
+        assert np.max(np.abs(U - ref)) / np.max(np.abs(w)) < 1e-8, precision
+    d = np.max(np.abs(one["mixed"] - one["mixed_bf16"])) / np.max(np.abs(ref))
+    assert 1e-6 < d < 1e-1, d

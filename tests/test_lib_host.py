@@ -46,6 +46,7 @@ def test_library_exports_every_declared_symbol():
     (dict(gamma=3), "gamma"),
     (dict(precision="mixed", inner_cycles=0), "inner_cycles"),
     (dict(precision="mixed", inner_cycles=17), "inner_cycles"),
+    (dict(precision="mixed_bf16", inner_cycles=0), "inner_cycles"),
 ])
 def test_invalid_parameters_are_rejected(kw, msg):
     args = dict(dim=1, n=31, M=64, alpha=0.5, k=8, r=2.0)
@@ -94,6 +95,14 @@ def test_mesh_formula_when_no_mesh_given():
     plan = mg.Plan(1, 15, 64, 0.4, k=6, r=4.0, T=2.0)
     t, _ = plan.mesh()
     assert np.max(np.abs(t - W.graded_mesh(64, 2.0, 4.0))) <= 4e-16 * 2.0
+
+
+def test_bfloat16_factors_take_less_workspace():
+    args = (1, 255, 1024, 0.5)
+    b64 = mg.Plan(*args, k=10, r=3.0).workspace_bytes()
+    b32 = mg.Plan(*args, k=10, r=3.0, precision="mixed").workspace_bytes()
+    b16 = mg.Plan(*args, k=10, r=3.0, precision="mixed_bf16").workspace_bytes()
+    assert b64 < b16 < b32
 
 
 def test_workspace_grows_with_grid():
