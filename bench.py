@@ -35,8 +35,8 @@ PEAK_HBM_GBS = 8000.0
 # workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by what the same
 # counters read for a 1 GiB device copy (--copy-probe): fetch x 2.000, write x
 # 1.000.  Valid only for the kernel source they were taken on.
-TRAFFIC_KERNEL_SHA256 = "740372dd1b6359e73e0d4558498519457b04c4a0e521749f43157f545eef8b7e"
-TRAFFIC_BYTES = {"large1d": (2.000 * 24585088.7 + 1.000 * 8656866.5) * 1024}
+TRAFFIC_KERNEL_SHA256 = "ee3fed797520ecf38af310f1ae6b8ede7eb77ab6802d1eb044b3b0c30c713b18"
+TRAFFIC_BYTES = {"large1d": (2.000 * 24425730.4 + 1.000 * 8656867.3) * 1024}
 
 
 def parse():
