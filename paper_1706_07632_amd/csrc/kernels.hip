@@ -207,17 +207,19 @@ constexpr int ZMASK = (1 << 30) - 1;
 // leaf s+1 (their live intervals overlap, so they hold different slots).
 constexpr int NW = 4;
 
-template <typename T, int MODE, bool PIPE>
+template <typename T, int MODE, bool PIPE, bool DEEP = PIPE>
 __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, const PipeCtx& pc,
                                            unsigned char* smem_raw, int* sh_abort) {
   typedef typename V4<T>::type v4;
-  // Operands prefetched per wave.  Measured: the pipelined kernel (time-
-  // staggered stages, one leaf of lag) gains from deep prefetch; a march
-  // launched on its own (2D fine grids: thousands of workgroups in rounds)
-  // runs 9 % faster with the shallow set, which also frees 50 registers.
-  constexpr int ZPF = PIPE ? 6 : 2;   // column-update tiles (even: applied in pairs)
+  // Operands prefetched per wave, deep or shallow.  Measured: the pipelined
+  // kernel (time-staggered stages, one leaf of lag) gains from the deep set;
+  // a march launched on its own runs faster with the shallow set (frees 50
+  // registers) up to 64 time leaves (2D n = 255: 7 % at M = 512 and 1024)
+  // and slower from 128 leaves on (4 % at M = 2048), where a leaf row holds
+  // more low-rank blocks whose loads the deep set hides.
+  constexpr int ZPF = DEEP ? 6 : 2;   // column-update tiles (even: applied in pairs)
   constexpr int DPF = 2;              // dense blocks
-  constexpr int FPF = PIPE ? 5 : 3;   // far-field chunks
+  constexpr int FPF = DEEP ? 5 : 3;   // far-field chunks
   T* ring = reinterpret_cast<T*>(smem_raw);   // [R][16][16] x of recent leaves, row-major
   T* part = ring + a.ring * 256;               // [NW + 1][16][16] partial right-hand sides (slot NW:
                                                // the IO wave's, odd leaves)
@@ -697,15 +699,18 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
   }
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, bool DEEP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void march_kernel(MarchArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int sh_abort;
   if (threadIdx.x == 0) sh_abort = 0;
   __syncthreads();
   PipeCtx pc{};
-  march_body<T, MODE, false>(a, blockIdx.x, pc, smem_raw, &sh_abort);
+  march_body<T, MODE, false, DEEP>(a, blockIdx.x, pc, smem_raw, &sh_abort);
 }
+
+// Time leaves from which a march launched on its own takes the deep prefetch.
+constexpr int kDeepPrefetchLeaves = 128;
 
 
 // ---------------------------------------------------------------------------
@@ -1224,11 +1229,16 @@ hipError_t launch_march(int mode, const MarchArgs<T>& a, hipStream_t s) {
   if (a.ncols <= 0) return hipSuccess;
   dim3 grid((a.ncols + 15) / 16), block(64 * NW);
   size_t lds = march_lds_bytes(a);
-  switch (mode) {
-    case MODE_SMOOTH: hipLaunchKernelGGL((march_kernel<T, MODE_SMOOTH>), grid, block, lds, s, a); break;
-    case MODE_RESID: hipLaunchKernelGGL((march_kernel<T, MODE_RESID>), grid, block, lds, s, a); break;
-    case MODE_TRSM: hipLaunchKernelGGL((march_kernel<T, MODE_TRSM>), grid, block, lds, s, a); break;
-    case MODE_MATVEC: hipLaunchKernelGGL((march_kernel<T, MODE_MATVEC>), grid, block, lds, s, a); break;
+  const bool deep = a.nleaf >= kDeepPrefetchLeaves;
+  switch (mode * 2 + (deep ? 1 : 0)) {
+    case 2 * MODE_SMOOTH: hipLaunchKernelGGL((march_kernel<T, MODE_SMOOTH, false>), grid, block, lds, s, a); break;
+    case 2 * MODE_SMOOTH + 1: hipLaunchKernelGGL((march_kernel<T, MODE_SMOOTH, true>), grid, block, lds, s, a); break;
+    case 2 * MODE_RESID: hipLaunchKernelGGL((march_kernel<T, MODE_RESID, false>), grid, block, lds, s, a); break;
+    case 2 * MODE_RESID + 1: hipLaunchKernelGGL((march_kernel<T, MODE_RESID, true>), grid, block, lds, s, a); break;
+    case 2 * MODE_TRSM: hipLaunchKernelGGL((march_kernel<T, MODE_TRSM, false>), grid, block, lds, s, a); break;
+    case 2 * MODE_TRSM + 1: hipLaunchKernelGGL((march_kernel<T, MODE_TRSM, true>), grid, block, lds, s, a); break;
+    case 2 * MODE_MATVEC: hipLaunchKernelGGL((march_kernel<T, MODE_MATVEC, false>), grid, block, lds, s, a); break;
+    case 2 * MODE_MATVEC + 1: hipLaunchKernelGGL((march_kernel<T, MODE_MATVEC, true>), grid, block, lds, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1244,13 +1254,19 @@ static hipError_t set_dyn_lds(const void* fn, size_t bytes) {
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(bytes - stat));
 }
 
+template <typename T, bool DEEP>
+static hipError_t set_march_lds_limit_depth(size_t bytes) {
+  hipError_t e;
+  if ((e = set_dyn_lds((const void*)march_kernel<T, MODE_SMOOTH, DEEP>, bytes)) != hipSuccess) return e;
+  if ((e = set_dyn_lds((const void*)march_kernel<T, MODE_RESID, DEEP>, bytes)) != hipSuccess) return e;
+  if ((e = set_dyn_lds((const void*)march_kernel<T, MODE_TRSM, DEEP>, bytes)) != hipSuccess) return e;
+  return set_dyn_lds((const void*)march_kernel<T, MODE_MATVEC, DEEP>, bytes);
+}
+
 template <typename T>
 hipError_t set_march_lds_limit(size_t bytes) {
-  hipError_t e;
-  if ((e = set_dyn_lds((const void*)march_kernel<T, MODE_SMOOTH>, bytes)) != hipSuccess) return e;
-  if ((e = set_dyn_lds((const void*)march_kernel<T, MODE_RESID>, bytes)) != hipSuccess) return e;
-  if ((e = set_dyn_lds((const void*)march_kernel<T, MODE_TRSM>, bytes)) != hipSuccess) return e;
-  return set_dyn_lds((const void*)march_kernel<T, MODE_MATVEC>, bytes);
+  hipError_t e = set_march_lds_limit_depth<T, false>(bytes);
+  return e != hipSuccess ? e : set_march_lds_limit_depth<T, true>(bytes);
 }
 
 template <typename T>

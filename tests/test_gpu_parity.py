@@ -30,7 +30,8 @@ def _cuda(a, dev):
 
 
 @pytest.mark.parametrize("M,alpha,r,k,ncols", [(128, 0.5, 3.0, 8, 16), (256, 0.3, 17 / 3, 10, 37),
-                                               (1024, 0.5, 3.0, 10, 5), (300, 0.7, 1.857142857142857, 6, 70)])
+                                               (1024, 0.5, 3.0, 10, 5), (300, 0.7, 1.857142857142857, 6, 70),
+                                               (2048, 0.4, 4.0, 10, 24)])
 def test_hmatvec_matches_oracle(dev, M, alpha, r, k, ncols):
     t = W.graded_mesh(M, 1.0, r)
     plan = mg.Plan(1, 15, M, alpha, k=k, t=t).bind()
@@ -170,6 +171,22 @@ def _single_mode_reference(p):
     w = oracle.single_mode_profile(Rt, oracle.mode_eigenvalue(kvec, p.n, p.length), prof)
     s = W.sine_mode(p.n, p.dim, p.length, kvec)
     return Rt, w, s
+
+
+@pytest.mark.parametrize("dim,n,M,precision", [(1, 63, 2048, "fp64"), (2, 31, 2048, "fp64"),
+                                               (2, 31, 2048, "mixed"), (1, 127, 4096, "mixed_bf16"),
+                                               (2, 15, 1024, "fp64")])
+def test_staged_solves_on_long_meshes(dev, dim, n, M, precision):
+    """Marches launched one by one on meshes of 128 and 256 time leaves
+    (which take the deeper operand prefetch) and of 64 leaves (the shallower
+    one), against the single-mode oracle."""
+    p = W.manufactured(dim, n, M, 0.4, r=4.0, k=10)
+    print("case", dim, n, M, precision, flush=True)
+    plan = _plan(p, dev, schedule="staged", precision=precision)
+    u, st = plan.solve(_cuda(p.f, dev), tol=1e-10)
+    Rt, w, s = _single_mode_reference(p)
+    ref = np.outer(w, s)
+    assert np.max(np.abs(u.cpu().numpy() - ref)) / np.max(np.abs(ref)) < 1e-9, st
 
 
 @pytest.mark.parametrize("alpha", [0.3, 0.5, 0.7])
