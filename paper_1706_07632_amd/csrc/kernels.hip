@@ -187,7 +187,8 @@ __device__ __forceinline__ void vm_drain() { __builtin_amdgcn_s_waitcnt(0x0F70);
 constexpr int ZFIRST = 1 << 30;
 constexpr int ZMASK = (1 << 30) - 1;
 
-// Work split inside a workgroup: NW waves share one chain of 16 columns.
+// Work split inside a workgroup: NW waves share one chain of 16 columns
+// ("wave k" below is the wave holding role k, see kRoleShift).
 // Per time leaf s there are two phases separated by workgroup barriers:
 //   phase 1: wave 0 sums the partial right-hand sides of leaf s, solves with
 //            the pre-inverted shifted diagonal leaf (or forms the defect) and
@@ -206,6 +207,15 @@ constexpr int ZMASK = (1 << 30) - 1;
 // of leaf s, and the accumulators updated with leaf s are not those read for
 // leaf s+1 (their live intervals overlap, so they hold different slots).
 constexpr int NW = 4;
+// Wave w of a workgroup holds role (w + kRoleShift) mod NW.  Measured on
+// gfx950: with roles by wave index the pipelined launch is 2.5 % slower
+// (large1d 16.4 against 16.0 ms; large2d 1.5 %); shifts 1, 2 and 3 measure
+// alike, as does swapping only roles 1 and 2, while swaps that keep roles 1
+// and 2 in place gain less.  (Placing roles by the HW_ID SIMD of each wave
+// so that the update-heavy roles of the two workgroups on a CU never share a
+// SIMD gained less than any constant shift.)
+constexpr int kRoleShift = 2;
+static_assert((NW & (NW - 1)) == 0, "roles rotate with a mask");
 
 template <typename T, int MODE, bool PIPE, bool DEEP = PIPE>
 __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, const PipeCtx& pc,
@@ -226,7 +236,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
   T* tbuf = part + (NW + 1) * 256;             // [16][16] float32 transposition (none in float64)
   T* Z = tbuf + (sizeof(T) == 4 ? 256 : 0);    // [nslots*k][16]
 
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wave = __builtin_amdgcn_readfirstlane(((threadIdx.x >> 6) + kRoleShift) & (NW - 1));   // role
   const int lane = threadIdx.x & 63;
   const int g = lane >> 4;
   const int c = lane & 15;
