@@ -627,12 +627,20 @@ void assign_offsets(std::vector<Stage>& st) {
 // with 2032 chains is faster staged).
 constexpr int kAutoPipelineChains = 256;
 
+// In a staged cycle, the levels from the first one whose half-sweeps have at
+// most kCoarsePipelineChains chains run as one pipelined launch.  Measured on
+// 2D n = 255, M = 1024: from level 3 (n = 31, 31 chains) 60.4 ms per solve,
+// from level 2 (125 chains) 62.9 ms, from level 1 (505 chains) 66.6 ms, from
+// level 4 (8 chains) 67.0 ms; batches of uneven 2D instances 3 % faster than
+// from level 2.
+constexpr int kCoarsePipelineChains = 64;
+
 // First level below the finest whose half-sweeps have at most
-// kAutoPipelineChains chains (0: none).
+// kCoarsePipelineChains chains (0: none).
 int coarse_switch_level(const HostPlan& hp) {
   const int L = (int)hp.levels.size();
   for (int l = 1; l < L; ++l)
-    if ((hp.levels[l].N + 31) / 32 <= kAutoPipelineChains) return l;
+    if ((hp.levels[l].N + 31) / 32 <= kCoarsePipelineChains) return l;
   return 0;
 }
 
