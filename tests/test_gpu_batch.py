@@ -134,3 +134,55 @@ def test_batch_of_mixed_plans_with_several_inner_cycles(dev):
             ref = _modewise_reference(p)
             assert np.abs(u.cpu().numpy() - ref).max() <= 1e-7 * np.abs(ref).max(), st
             assert st["res"] <= 1e-9 * st["bnorm"] and st["cycles"] % 3 == 0
+
+
+def test_staged_instances_solved_side_by_side(dev):
+    """Five staged instances (1D and 2D, float64 and mixed precision, uneven
+    sizes) and one pipelined one in a batch: the staged ones are solved by
+    several host threads, each on a stream of its own; every solution against
+    the oracle, twice in a row."""
+    cases = [(2, 63, 128, 0.5, "fp64"), (1, 255, 256, 0.4, "fp64"), (2, 31, 64, 0.6, "mixed"),
+             (1, 127, 512, 0.7, "fp64"), (2, 63, 256, 0.3, "mixed")]
+    probs = [W.manufactured(d, n, M, a, r=3.0, k=8) for d, n, M, a, _ in cases]
+    plans = [_plan(p, schedule="staged", precision=c[4]) for p, c in zip(probs, cases)]
+    pp = W.manufactured(1, 63, 128, 0.5, k=8)
+    probs.append(pp)
+    plans.append(_plan(pp, schedule="pipelined"))
+    batch = mg.Batch(plans).bind()
+    fs = [_cuda(p.f, dev) for p in probs]
+    refs = [_modewise_reference(p) for p in probs]
+    for rep in range(2):
+        us, sts = batch.solve(fs, tol=1e-9)
+        for p, u, st, ref in zip(probs, us, sts, refs):
+            assert np.abs(u.cpu().numpy() - ref).max() <= 1e-7 * np.abs(ref).max(), (rep, p.dim, p.n, p.M, st)
+            assert st["res"] <= 1e-9 * st["bnorm"], (rep, st)
+
+
+def test_batch_holding_one_plan_twice(dev):
+    """Two entries on one plan (one workspace) are solved one after the other."""
+    p = W.manufactured(2, 63, 128, 0.5, k=8)
+    plan = _plan(p, schedule="staged")
+    batch = mg.Batch([plan, plan]).bind()
+    us, sts = batch.solve([_cuda(p.f, dev), _cuda(2.0 * p.f, dev)], tol=1e-10)
+    ref = _modewise_reference(p)
+    for u, scale in zip(us, (1.0, 2.0)):
+        assert np.abs(u.cpu().numpy() - scale * ref).max() <= 1e-8 * scale * np.abs(ref).max()
+
+
+def test_stall_in_one_side_by_side_instance_is_reported(dev):
+    """A zero progress bound on one of three staged plans: its coarse launch
+    stops and the batch reports the stall; the others are unaffected, and with
+    the bound restored the whole batch solves correctly."""
+    probs = [W.manufactured(2, 63, 128, a, r=3.0, k=8) for a in (0.3, 0.5, 0.7)]
+    plans = [_plan(p, schedule="staged") for p in probs]
+    batch = mg.Batch(plans).bind()
+    fs = [_cuda(p.f, dev) for p in probs]
+    plans[1].set_progress_limit(0)
+    with pytest.raises(mg.MgwrError) as ei:
+        batch.solve(fs, tol=1e-10)
+    assert ei.value.code == mg.MGWR_ERR_HIP and "stalled" in str(ei.value)
+    plans[1].set_progress_limit(1 << 22)
+    us, sts = batch.solve(fs, tol=1e-10)
+    for p, u in zip(probs, us):
+        ref = _modewise_reference(p)
+        assert np.abs(u.cpu().numpy() - ref).max() <= 1e-8 * np.abs(ref).max()
