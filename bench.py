@@ -114,11 +114,16 @@ def time_form(plans, fs, us, tol, steps, warmup, torch, warm_start=False):
     return t1 - t0, stats, timing
 
 
-def time_batch(batch, fs, us, tol, steps, warmup, torch, warm_start=False):
+def time_batch(batch, fs, us, tol, steps, warmup, torch, warm_start=False, plans=()):
+    """Wall time of `steps` batch solves after `warmup` untimed ones; kernel
+    timing (the batch's and that of `plans`, which time their own staged
+    launches) covers the timed solves only."""
     stats = []
     for _ in range(warmup):
         batch.solve(fs, tol=tol, us=us, warm_start=warm_start)
     batch.timing(True)
+    for pl in plans:
+        pl.timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -221,6 +226,7 @@ def batched_main(args):
     us = [torch.empty_like(f) for f in fs]
     unknowns = sum(p.N * p.M for p in probs)
     forms, out_timing, tuned = {}, None, {}
+    timed_s = 0.0
     for name, precision in (("fp64", "fp64"), ("mixed_fp32", "mixed"), ("mixed_bf16", "mixed_bf16")):
         if name != "fp64" and args.no_mixed:
             continue
@@ -233,9 +239,9 @@ def batched_main(args):
                 tuned[key] = pl.autotune(f, tol=args.tol, u=u)
         tune_s = time.perf_counter() - t0
         batch = mg.Batch(plans, graph=True).bind()
-        for pl in plans:
-            pl.timing(True)     # the staged instances are timed by their plans
-        secs, stats, timing = time_batch(batch, fs, us, args.tol, args.steps, args.warmup, torch)
+        secs, stats, timing = time_batch(batch, fs, us, args.tol, args.steps, args.warmup, torch, plans=plans)
+        if out_timing is None:
+            timed_s = secs
         last = stats[-len(probs):]
         forms[name] = {"value": unknowns * args.steps / secs, "ms_per_step": 1e3 * secs / args.steps,
                        "cycles_total": sum(s["cycles"] for s in last),
@@ -249,7 +255,11 @@ def batched_main(args):
     tm = out_timing
     dom = max(tm, key=lambda k: tm[k]["ms"])
     sm = tm[dom]
-    achieved = sm["flops"] / (sm["ms"] * 1e-3) / 1e12 if sm["ms"] > 0 else 0.0
+    # Staged instances run side by side on several streams, so launches of the
+    # dominant class overlap and their summed durations exceed the wall time:
+    # the rate is taken over the timed wall time instead (a lower bound).
+    achieved = sm["flops"] / timed_s / 1e12 if timed_s > 0 else 0.0
+    per_launch = sm["flops"] / (sm["ms"] * 1e-3) / 1e12 if sm["ms"] > 0 else 0.0
     out = {
         "metric": "space-time unknowns (N*M)/s to 1e-8 rel. residual, batched uneven 2D instances",
         "value": forms["fp64"]["value"], "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps,
@@ -265,6 +275,9 @@ def batched_main(args):
                                  "else staged with the coarse levels pipelined")},
         "roofline": {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "basis": "algorithmic flops of the class over the timed wall time (launches of several "
+                              "streams overlap)",
+                     "per_launch_achieved": per_launch,
                      "avg_launch_us": 1e3 * sm["ms"] / max(1, sm["launches"]), "launches": sm["launches"]},
         "forms": forms,
         "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3)} for k, v in tm.items() if v["launches"]},
