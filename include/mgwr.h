@@ -234,16 +234,36 @@ int mgwr_batch_set_graph(mgwr_batch* batch, int enable);
 /* Number of graph replays so far (host). */
 int mgwr_batch_graph_replays(const mgwr_batch* batch, long long* replays);
 
-/* Autotuner of the schedule (staged launches per operator, or whole cycles
- * time-pipelined in one launch): solves f twice with each schedule (the
- * second solve of each runs with the cycle count the first one learned),
- * keeps the faster for this plan and for every MGWR_SCHED_AUTO plan of the
- * same (dim, n, M, precision, inner cycles, k) created in this process, and
- * returns it in *chosen (nullable).  u receives the solution.  A batch runs
- * its pipelined instances in one merged launch and its staged ones one
- * after another. */
+/* Autotuner of the schedule and of the staged schedule's knobs: solves f
+ * twice with each candidate (the second solve of each runs with the cycle
+ * count the first one learned) and keeps the fastest.  Candidates: whole
+ * cycles time-pipelined in one launch; staged launches per operator with the
+ * shallow or the deep operand prefetch in the marches (see
+ * mgwr_plan_set_staging) and the coarse pipelined launch starting at the
+ * level the rule picks or one level either side.  The choice holds for this
+ * plan and for every MGWR_SCHED_AUTO plan of the same (dim, n, M, precision,
+ * inner cycles, k) in this process; the schedule is returned in *chosen
+ * (MGWR_SCHED_STAGED or MGWR_SCHED_PIPELINED, nullable).  u receives the
+ * solution.  A batch runs its pipelined instances in one merged launch and
+ * its staged ones side by side on worker streams. */
 int mgwr_plan_autotune(mgwr_plan* plan, const double* f_dev, const double* g_dev, double tol, double* u_dev,
                        int* chosen);
+
+/* Knobs of the staged schedule (host only; Section 4's cycle is unchanged,
+ * only how its operators are launched).  prefetch: operand prefetch of the
+ * marches launched on their own, 0 = by mesh length (deep from 128 time
+ * leaves), 1 = shallow (2 update tiles, 3 far-field chunks per wave), 2 =
+ * deep (6 and 5).  coarse_level: the level from which each cycle's remaining
+ * levels run as one pipelined launch, -1 = by rule (first level with at most
+ * 64 chains of 16 columns), 0 = none, 1 .. levels-1.  (0, -1) restores the
+ * rules.  MGWR_ERR_INVALID_ARG for values out of range. */
+int mgwr_plan_set_staging(mgwr_plan* plan, int prefetch, int coarse_level);
+
+/* What a solve of this plan uses now: schedule (MGWR_SCHED_STAGED or
+ * MGWR_SCHED_PIPELINED), march prefetch (0 by mesh length, 1 shallow, 2
+ * deep) and coarse level (0 none) of the staged schedule.  Host only;
+ * every pointer nullable. */
+int mgwr_plan_tuned(const mgwr_plan* plan, int* schedule, int* prefetch, int* coarse_level);
 
 /* Learned initial guess.  Not part of the paper's method, which starts its
  * iteration from a given iterate: this network only proposes that iterate,

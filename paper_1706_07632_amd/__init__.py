@@ -37,6 +37,7 @@ EXPORTED = [
     "mgwr_net_sync_weights", "mgwr_net_forward", "mgwr_net_gradient", "mgwr_net_set_finest",
     "mgwr_net_adam_step", "mgwr_net_destroy",
     "mgwr_plan_set_warm_start", "mgwr_batch_set_graph", "mgwr_batch_graph_replays", "mgwr_plan_autotune",
+    "mgwr_plan_set_staging", "mgwr_plan_tuned",
 ]
 
 KERNEL_CLASSES = ["smooth64", "defect64", "smooth32", "defect32", "restrict", "prolong", "pipe64", "coarse"]
@@ -128,6 +129,9 @@ def lib():
     L.mgwr_batch_set_graph.argtypes = [vp, ip]
     L.mgwr_batch_graph_replays.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong)]
     L.mgwr_plan_autotune.argtypes = [vp, vp, vp, ctypes.c_double, vp, ctypes.POINTER(ctypes.c_int)]
+    L.mgwr_plan_set_staging.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    ipp = ctypes.POINTER(ctypes.c_int)
+    L.mgwr_plan_tuned.argtypes = [vp, ipp, ipp, ipp]
     L.mgwr_net_create.argtypes = [ip, ctypes.POINTER(ctypes.c_int), ip, ctypes.POINTER(vp)]
     L.mgwr_net_param_count.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
     L.mgwr_net_workspace_bytes.argtypes = [vp, ctypes.c_longlong, ctypes.POINTER(ctypes.c_size_t)]
@@ -249,8 +253,9 @@ class Plan:
         return self
 
     def autotune(self, f, g=None, tol=1e-8, u=None):
-        """Measure both schedules on f and keep the faster (also for later
-        plans of the same shape); returns "staged" or "pipelined"."""
+        """Measure the schedules (and the staged schedule's prefetch and
+        coarse level, see tuned()) on f and keep the fastest, also for later
+        plans of the same shape; returns "staged" or "pipelined"."""
         import torch
         _require(f, "f", (self.M, self.N))
         if g is not None:
@@ -328,6 +333,20 @@ class Plan:
         tm = Timing()
         _check(lib().mgwr_timing_get(self._h, ctypes.byref(tm)))
         return tm.as_dict()
+
+    def set_staging(self, prefetch: int = 0, coarse_level: int = -1):
+        """Staged-schedule knobs: march prefetch (0 by mesh length, 1 shallow,
+        2 deep) and the level the coarse pipelined launch starts at (-1 by
+        rule, 0 none)."""
+        _check(lib().mgwr_plan_set_staging(self._h, int(prefetch), int(coarse_level)))
+        return self
+
+    def tuned(self):
+        """{"schedule", "prefetch", "coarse_level"} a solve uses now."""
+        s, p, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().mgwr_plan_tuned(self._h, ctypes.byref(s), ctypes.byref(p), ctypes.byref(c)))
+        return {"schedule": {1: "staged", 2: "pipelined"}[s.value],
+                "prefetch": {0: "by_length", 1: "shallow", 2: "deep"}[p.value], "coarse_level": c.value}
 
     def set_progress_limit(self, polls: int):
         """Bound on the polls of one progress wait of a pipelined launch

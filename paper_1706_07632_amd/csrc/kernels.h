@@ -27,6 +27,9 @@ struct MarchArgs {
   // float32 marches only: when set, ffA and zuB point at bfloat16 copies of
   // the far-field chunks and update tiles (2-byte entries, same indexing)
   int lr_bf16;
+  // operand prefetch of a march launched on its own: 0 by mesh length, 1
+  // shallow, 2 deep (the pipelined kernel always prefetches deep)
+  int prefetch;
   int k, nslots, ring;
   // data
   const T* F;         // right-hand side (SMOOTH, RESID, TRSM)

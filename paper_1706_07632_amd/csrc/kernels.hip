@@ -1243,7 +1243,7 @@ hipError_t launch_march(int mode, const MarchArgs<T>& a, hipStream_t s) {
   if (a.ncols <= 0) return hipSuccess;
   dim3 grid((a.ncols + 15) / 16), block(64 * NW);
   size_t lds = march_lds_bytes(a);
-  const bool deep = a.nleaf >= kDeepPrefetchLeaves;
+  const bool deep = a.prefetch == 2 || (a.prefetch == 0 && a.nleaf >= kDeepPrefetchLeaves);
   switch (mode * 2 + (deep ? 1 : 0)) {
     case 2 * MODE_SMOOTH: hipLaunchKernelGGL((march_kernel<T, MODE_SMOOTH, false>), grid, block, lds, s, a); break;
     case 2 * MODE_SMOOTH + 1: hipLaunchKernelGGL((march_kernel<T, MODE_SMOOTH, true>), grid, block, lds, s, a); break;

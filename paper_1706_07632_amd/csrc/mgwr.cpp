@@ -114,6 +114,14 @@ struct mgwr_plan {
   int khint = 0;                       // cycles the last pipelined solve from a zero or given iterate needed
   int khint_warm = 0;                  // the same from a predicted iterate
   int tuned = 0;                       // schedule measured best by mgwr_plan_autotune (0: none)
+  // staged schedule knobs: operand prefetch of the marches (0 by mesh length,
+  // 1 shallow, 2 deep) and the level the coarse pipelined launch starts at
+  // (-1 by rule); set by mgwr_plan_set_staging or mgwr_plan_autotune (else
+  // the autotuner's choice for the shape, if any)
+  int set_prefetch = 0;
+  int set_coarse = -1;
+  bool staging_set = false;
+  int prefetch = 0;                    // in use
   int khint_staged = 0;                // cycles the last staged float64 solve from zero needed
   int khint_staged_warm = 0;           // the same from a predicted iterate
   double cycle_flops = 0.0, cycle_bytes = 0.0;  // algorithmic work of one pipelined cycle
@@ -285,6 +293,7 @@ MarchArgs<T> base_args(mgwr_plan* pl, const DevOps<T>& ops, int level) {
   a.zu_row = pl->zu_row;
   a.zuB = ops.zuB;
   a.lr_bf16 = ops.lr_bf16;
+  a.prefetch = pl->prefetch;
   a.k = hp.p.k;
   a.nslots = hp.nslots;
   a.ring = std::max(hp.window + 2, 3);  // leaves written while older ones are still read
@@ -701,11 +710,15 @@ int coarse_cycle(mgwr_plan* pl, int l) {
   HIP_TRY(launch_pipeline(pa, lds, pl->stream));
   return MGWR_OK;
 }
-// Schedules measured by mgwr_plan_autotune, shared by every plan of the same
-// shape in the process: (dim, n, M, precision, inner cycles, k) -> schedule.
+// Choices measured by mgwr_plan_autotune, shared by every plan of the same
+// shape in the process: (dim, n, M, precision, inner cycles, k) -> schedule,
+// and for the staged schedule the march prefetch and the coarse level.
 using TuneKey = std::tuple<int, int, int, int, int, int>;
+struct TuneChoice {
+  int sched = 0, prefetch = 0, coarse = -1;
+};
 std::mutex g_tune_mu;
-std::map<TuneKey, int> g_tuned;
+std::map<TuneKey, TuneChoice> g_tuned;
 
 TuneKey tune_key(const mgwr_plan* pl) {
   const mgwr_params& p = pl->hp.p;
@@ -720,9 +733,43 @@ bool use_pipeline(const mgwr_plan* pl) {
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find(tune_key(pl));
-    if (it != g_tuned.end()) return it->second == MGWR_SCHED_PIPELINED;
+    if (it != g_tuned.end()) return it->second.sched == MGWR_SCHED_PIPELINED;
   }
   return (pl->hp.levels[0].N + 31) / 32 <= kAutoPipelineChains;
+}
+
+// Prefetch and coarse level a staged solve of `pl` uses: set on the plan,
+// else measured for its shape (AUTO schedule), else the rules.
+void staging_choice(const mgwr_plan* pl, int* prefetch, int* coarse) {
+  *prefetch = 0;
+  *coarse = -1;
+  if (pl->staging_set) {
+    *prefetch = pl->set_prefetch;
+    *coarse = pl->set_coarse;
+  } else if (pl->hp.p.schedule == MGWR_SCHED_AUTO) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(tune_key(pl));
+    if (it != g_tuned.end() && it->second.sched == MGWR_SCHED_STAGED) {
+      *prefetch = it->second.prefetch;
+      *coarse = it->second.coarse;
+    }
+  }
+  if (*coarse < 0) *coarse = coarse_switch_level(pl->hp);
+}
+
+// Puts the staged knobs in force; a new coarse level rebuilds the coarse
+// stage images (their workspace holds a whole cycle's stages).
+void apply_staging(mgwr_plan* pl) {
+  int prefetch, coarse;
+  staging_choice(pl, &prefetch, &coarse);
+  pl->prefetch = prefetch;
+  if (coarse != pl->coarse_l) {
+    pl->coarse_l = coarse;
+    for (int w = 0; w < 2; ++w) {
+      pl->coarse_stages[w].clear();
+      pl->coarse_up[w] = false;
+    }
+  }
 }
 
 int read_scalar(mgwr_plan* pl, double* host) {
@@ -1324,6 +1371,7 @@ int mgwr_solve(mgwr_plan* pl, const double* f, const double* g, double tol, doub
     if (st) *st = s1;
     return rc2;
   }
+  apply_staging(pl);
   const HostPlan& hp = pl->hp;
   const int M = hp.p.M;
   const long long MN = (long long)M * hp.levels[0].N;
@@ -1727,12 +1775,30 @@ int mgwr_plan_autotune(mgwr_plan* pl, const double* f, const double* g, double t
   int rc = check_bound(pl);
   if (rc) return rc;
   if (!f || !u || !(tol > 0.0)) return fail(MGWR_ERR_INVALID_ARG, "bad arguments");
+  // candidates: the pipelined schedule, and the staged one with either march
+  // prefetch and the coarse launch from the rule's level or one level either
+  // side of it
+  struct Cand { int sched, prefetch, coarse; };
+  std::vector<Cand> cands = {{MGWR_SCHED_PIPELINED, 0, -1}};
+  const int L = (int)pl->hp.levels.size();
+  const int c0 = coarse_switch_level(pl->hp);
+  std::vector<int> levels;
+  if (c0 == 0) levels = {0};
+  for (int c = c0 - 1; c0 > 0 && c <= c0 + 1; ++c)
+    if (c >= 1 && c < L) levels.push_back(c);
+  for (int pf : {1, 2})
+    for (int c : levels) cands.push_back({MGWR_SCHED_STAGED, pf, c});
   const int saved = pl->tuned;
+  const bool saved_set = pl->staging_set;
+  const int saved_pf = pl->set_prefetch, saved_c = pl->set_coarse;
+  const int keep = pl->hp.p.schedule;
   double best = 1e300;
-  int pick = MGWR_SCHED_STAGED;
-  for (int sched : {MGWR_SCHED_STAGED, MGWR_SCHED_PIPELINED}) {
-    pl->tuned = sched;
-    const int keep = pl->hp.p.schedule;
+  Cand pick = cands[0];
+  for (const Cand& cd : cands) {
+    pl->tuned = cd.sched;
+    pl->staging_set = true;
+    pl->set_prefetch = cd.prefetch;
+    pl->set_coarse = cd.coarse;
     pl->hp.p.schedule = MGWR_SCHED_AUTO;
     double secs = 0.0;
     // the second solve runs with what the first one learned (cycle count)
@@ -1747,19 +1813,51 @@ int mgwr_plan_autotune(mgwr_plan* pl, const double* f, const double* g, double t
     pl->hp.p.schedule = keep;
     if (rc) {
       pl->tuned = saved;
+      pl->staging_set = saved_set;
+      pl->set_prefetch = saved_pf;
+      pl->set_coarse = saved_c;
       return rc;
     }
     if (secs < best) {
       best = secs;
-      pick = sched;
+      pick = cd;
     }
   }
-  pl->tuned = pick;
+  // the plan keeps the choice as set knobs; later AUTO plans of the shape find it in the table
+  pl->tuned = pick.sched;
+  pl->staging_set = pick.sched == MGWR_SCHED_STAGED;
+  pl->set_prefetch = pick.sched == MGWR_SCHED_STAGED ? pick.prefetch : 0;
+  pl->set_coarse = pick.sched == MGWR_SCHED_STAGED ? pick.coarse : -1;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tuned[tune_key(pl)] = pick;
+    TuneChoice& tc = g_tuned[tune_key(pl)];
+    tc.sched = pick.sched;
+    tc.prefetch = pick.prefetch;
+    tc.coarse = pick.coarse;
   }
-  if (chosen) *chosen = pick;
+  if (chosen) *chosen = pick.sched;
+  return MGWR_OK;
+}
+
+int mgwr_plan_set_staging(mgwr_plan* pl, int prefetch, int coarse_level) {
+  if (!pl) return fail(MGWR_ERR_INVALID_ARG, "null plan");
+  const int L = (int)pl->hp.levels.size();
+  if (prefetch < 0 || prefetch > 2) return fail(MGWR_ERR_INVALID_ARG, "prefetch must be 0, 1 or 2");
+  if (coarse_level < -1 || coarse_level >= L)
+    return fail(MGWR_ERR_INVALID_ARG, "coarse_level must be -1 (rule), 0 (none) or 1 .. " + std::to_string(L - 1));
+  pl->staging_set = !(prefetch == 0 && coarse_level == -1);
+  pl->set_prefetch = prefetch;
+  pl->set_coarse = coarse_level;
+  return MGWR_OK;
+}
+
+int mgwr_plan_tuned(const mgwr_plan* pl, int* schedule, int* prefetch, int* coarse_level) {
+  if (!pl) return fail(MGWR_ERR_INVALID_ARG, "null plan");
+  int pf, c;
+  staging_choice(pl, &pf, &c);
+  if (schedule) *schedule = use_pipeline(pl) ? MGWR_SCHED_PIPELINED : MGWR_SCHED_STAGED;
+  if (prefetch) *prefetch = pf;
+  if (coarse_level) *coarse_level = c;
   return MGWR_OK;
 }
 

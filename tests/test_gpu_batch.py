@@ -108,6 +108,28 @@ def test_autotune_picks_a_schedule_and_later_plans_follow(dev):
     plan2.solve(f, tol=1e-10)
     tm = plan2.timing()
     assert (tm["pipe64"]["launches"] > 0) == (chosen == "pipelined"), (chosen, tm)
+    assert plan.tuned()["schedule"] == chosen and plan2.tuned() == plan.tuned()
+
+
+def test_autotune_of_a_staged_shape_keeps_its_knobs(dev):
+    """A 2D shape where the staged schedule wins: the tuned prefetch and
+    coarse level are among the candidates, later AUTO plans of the shape take
+    them, and their solutions match the oracle."""
+    p = W.manufactured(2, 127, 256, 0.5, r=3.0, k=8)
+    f = _cuda(p.f, dev)
+    plan = _plan(p)
+    chosen = plan.autotune(f, tol=1e-10)
+    t = plan.tuned()
+    print("tuned", chosen, t, flush=True)
+    assert t["schedule"] == chosen
+    if chosen == "staged":
+        assert t["prefetch"] in ("shallow", "deep") and t["coarse_level"] in (1, 2, 3)
+    plan2 = _plan(p)
+    assert plan2.tuned() == t
+    ref = _modewise_reference(p)
+    for pl in (plan, plan2):
+        u, st = pl.solve(f, tol=1e-10)
+        assert np.abs(u.cpu().numpy() - ref).max() <= 1e-8 * np.abs(ref).max(), st
 
 
 def test_batch_runs_staged_and_pipelined_instances(dev):

@@ -395,3 +395,19 @@ def test_bfloat16_factors_change_the_inner_cycles_not_the_answer(dev, schedule):
         assert np.max(np.abs(U - ref)) / np.max(np.abs(w)) < 1e-8, precision
     d = np.max(np.abs(one["mixed"] - one["mixed_bf16"])) / np.max(np.abs(ref))
     assert 1e-6 < d < 1e-1, d
+
+
+@pytest.mark.parametrize("prefetch,coarse,precision", [(1, 1, "fp64"), (2, 1, "fp64"), (1, 2, "fp64"),
+                                                       (2, 3, "fp64"), (1, 0, "fp64"), (2, 0, "mixed"),
+                                                       (0, -1, "mixed")])
+def test_staged_knobs_give_the_same_solution(dev, prefetch, coarse, precision):
+    """Every march prefetch and coarse-launch level of the staged schedule
+    (host-side choices of how the cycle's operators are launched) solves to
+    the oracle's solution."""
+    p = W.manufactured(2, 63, 256, 0.4, r=3.0, k=10)
+    plan = _plan(p, dev, schedule="staged", precision=precision).set_staging(prefetch, coarse)
+    print("case", prefetch, coarse, precision, plan.tuned(), flush=True)
+    u, st = plan.solve(_cuda(p.f, dev), tol=1e-10)
+    Rt, w, s = _single_mode_reference(p)
+    ref = np.outer(w, s)
+    assert np.max(np.abs(u.cpu().numpy() - ref)) / np.max(np.abs(ref)) < 1e-9, st

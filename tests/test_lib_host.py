@@ -97,6 +97,22 @@ def test_mesh_formula_when_no_mesh_given():
     assert np.max(np.abs(t - W.graded_mesh(64, 2.0, 4.0))) <= 4e-16 * 2.0
 
 
+def test_staging_knobs_and_their_validation():
+    plan = mg.Plan(2, 255, 1024, 0.5, k=10, r=3.0)        # levels n = 255 .. 1 (8)
+    assert plan.tuned() == {"schedule": "staged", "prefetch": "by_length", "coarse_level": 3}
+    plan.set_staging(2, 2)
+    assert plan.tuned() == {"schedule": "staged", "prefetch": "deep", "coarse_level": 2}
+    plan.set_staging(1, 0)
+    assert plan.tuned() == {"schedule": "staged", "prefetch": "shallow", "coarse_level": 0}
+    plan.set_staging(0, -1)
+    assert plan.tuned()["coarse_level"] == 3 and plan.tuned()["prefetch"] == "by_length"
+    for bad in ((3, -1), (-1, -1), (0, 8), (0, -2)):
+        with pytest.raises(mg.MgwrError) as ei:
+            plan.set_staging(*bad)
+        assert ei.value.code == mg.MGWR_ERR_INVALID_ARG
+    assert mg.Plan(1, 1023, 512, 0.5, k=8, r=3.0).tuned()["schedule"] == "pipelined"
+
+
 def test_bfloat16_factors_take_less_workspace():
     args = (1, 255, 1024, 0.5)
     b64 = mg.Plan(*args, k=10, r=3.0).workspace_bytes()
