@@ -35,8 +35,8 @@ PEAK_HBM_GBS = 8000.0
 # workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by what the same
 # counters read for a 1 GiB device copy (--copy-probe): fetch x 2.000, write x
 # 1.000.  Valid only for the kernel source they were taken on.
-TRAFFIC_KERNEL_SHA256 = "2c69007a94536bbee3821d37e12c3a2f2dd7dc3a91af85bb67c9b9ed54629a43"
-TRAFFIC_BYTES = {"large1d": (2.000 * 24908386.6 + 1.000 * 8656866.2) * 1024}
+TRAFFIC_KERNEL_SHA256 = "c290e754da27f1f2ca00d0b50fbb644f5f44fbbd2a34b4820e83b14a4ed56226"
+TRAFFIC_BYTES = {"large1d": (2.000 * 24190838.8 + 1.000 * 8656866.5) * 1024}
 
 
 def parse():
