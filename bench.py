@@ -209,7 +209,7 @@ def batched_main(args):
     U[0.2, 0.9]) solved together: the schedule of each instance by the AUTO
     rule (or, with --batch-schedule autotune, by the autotuner on the first
     instance of its (n, M) bucket), the pipelined instances in one
-    merged launch (graph-replayed), the staged ones after it."""
+    merged launch (graph-replayed), the staged ones side by side after it."""
     import torch
 
     import paper_1706_07632_amd as mg
