@@ -411,3 +411,21 @@ def test_staged_knobs_give_the_same_solution(dev, prefetch, coarse, precision):
     Rt, w, s = _single_mode_reference(p)
     ref = np.outer(w, s)
     assert np.max(np.abs(u.cpu().numpy() - ref)) / np.max(np.abs(ref)) < 1e-9, st
+
+
+@pytest.mark.parametrize("schedule", ["staged", "pipelined"])
+@pytest.mark.parametrize("dim,n,M,precision", [(1, 1, 1, "fp64"), (1, 7, 1, "fp64"), (2, 1, 3, "fp64"),
+                                               (2, 3, 2, "fp64"), (1, 15, 5, "fp64"), (2, 7, 9, "mixed"),
+                                               (1, 31, 1, "mixed")])
+def test_degenerate_sizes(dev, schedule, dim, n, M, precision):
+    """One time step, meshes shorter than one leaf, a one-point grid (the
+    coarsest level is the finest): random source and initial value against
+    the oracle's direct time stepping."""
+    rng = np.random.default_rng([dim, n, M])
+    N = n ** dim
+    t = W.graded_mesh(M, 1.0, 2.0)
+    p = W.Problem(dim=dim, n=n, M=M, alpha=0.55, r=2.0, k=6, t=t, f=rng.standard_normal((M, N)))
+    print("case", schedule, dim, n, M, precision, flush=True)
+    err, res, st = _solve_and_compare(p, dev, g=rng.standard_normal(N), schedule=schedule, precision=precision,
+                                      tol=1e-11)
+    assert err < 1e-9 and res < 1e-10, (err, res, st)
