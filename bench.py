@@ -35,8 +35,8 @@ PEAK_HBM_GBS = 8000.0
 # workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by what the same
 # counters read for a 1 GiB device copy (--copy-probe): fetch x 2.000, write x
 # 1.000.  Valid only for the kernel source they were taken on.
-TRAFFIC_KERNEL_SHA256 = "c290e754da27f1f2ca00d0b50fbb644f5f44fbbd2a34b4820e83b14a4ed56226"
-TRAFFIC_BYTES = {"large1d": (2.000 * 24190838.8 + 1.000 * 8656866.5) * 1024}
+TRAFFIC_KERNEL_SHA256 = "b7ae4a201aef9f5b3cc2bb90cb065cadb4a1424ed31840ca864a7264db117436"
+TRAFFIC_BYTES = {"large1d": (2.000 * 23847061.4 + 1.000 * 8656866.5) * 1024}
 
 
 def parse():
