@@ -293,7 +293,7 @@ def main():
         copy_probe()
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the solver runs on one GPU (multi-GPU sharding is not implemented); --gpus must be 1"}))
         sys.exit(2)
     if args.workload == "batched":
         batched_main(args)
