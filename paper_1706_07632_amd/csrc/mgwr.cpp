@@ -883,7 +883,7 @@ int prepare_solve(mgwr_plan* pl, const double* f, const double* g, double tol, d
       if ((rc = net_infer(pl->net, pl->netx, H, W, hp.levels[0].h, &y))) return rc;
       HIP_TRY(hipStreamSynchronize(net_stream(pl->net)));
       HIP_TRY(launch_time_interp(y, pl->rows_dev, ns, pl->tpow, g, hp.p.M, N, s.bnorm, u, pl->stream));
-      // float64 cycles do not need the prediction's defect (the judge is the
+      // float64 cycles do not need the prediction's defect (what decides is the
       // residual after the first cycles); refinement steps start from it
       if (pl->mixed || (flags & MGWR_WARM_RES0)) {
         if ((rc = defect<double>(pl, pl->d64, 0, b, u, pl->d64.R[0]))) return rc;
