@@ -216,8 +216,15 @@ int mgwr_batch_workspace_bytes(const mgwr_batch* batch, size_t* bytes);
 int mgwr_batch_bind(mgwr_batch* batch, void* workspace_dev, size_t bytes, void* stream);
 /* f_dev[i], g_dev[i] (g_dev or g_dev[i] may be NULL), u_dev[i]: the arrays of
  * mgwr_solve for instance i; stats may be NULL or hold `count` entries.
- * Returns MGWR_OK when every instance converged, else the first non-OK
- * status of an instance (all outputs are written). */
+ * Instances with the pipelined schedule run first, in one merged launch on
+ * the batch's stream.  Instances with the staged schedule are then solved
+ * side by side by up to 8 host threads, each on a HIP stream the batch owns
+ * (default priority).  Each plan's own stream is synchronised before its
+ * arrays are touched, and all work is complete when the call returns.  They
+ * run one by one instead when two entries share a plan or with
+ * MGWR_WARM_START (the plans share one network workspace).  Returns MGWR_OK
+ * when every instance converged, else the first non-OK status in entry
+ * order. */
 int mgwr_batch_solve(mgwr_batch* batch, const double* const* f_dev, const double* const* g_dev, double tol,
                      double* const* u_dev, unsigned flags, mgwr_stats* stats);
 /* Event timing of the batch's launches (class MGWR_K_PIPE64); synchronises.

@@ -370,7 +370,8 @@ class Plan:
 class Batch:
     """Several bound plans solved together: the instances with a pipelined
     schedule in one merged launch (replayed from a HIP graph when `graph`
-    is on and nothing changed), the others one after another."""
+    is on and nothing changed), the others side by side on worker streams
+    (one by one when two entries share a plan, or for warm-started solves)."""
 
     def __init__(self, plans, graph=False):
         self.plans = list(plans)

@@ -1719,7 +1719,7 @@ int mgwr_batch_solve(mgwr_batch* bt, const double* const* f, const double* const
   if (!bt || !bt->bound) return batch_fail(MGWR_ERR_STATE, "batch is not bound");
   if (!f || !u || !(tol > 0.0)) return batch_fail(MGWR_ERR_INVALID_ARG, "bad arguments");
   // instances whose schedule is pipelined share one launch; the others are
-  // solved one after another with their staged schedule
+  // solved with their staged schedule, side by side where that is safe
   std::vector<int> pipe, staged;
   for (int i = 0; i < (int)bt->plans.size(); ++i) (use_pipeline(bt->plans[i]) ? pipe : staged).push_back(i);
   int ret = MGWR_OK;
