@@ -47,7 +47,8 @@ enum {
   MGWR_ERR_STATE = 2,         /* plan not bound, or workspace too small */
   MGWR_ERR_HIP = 3,           /* a HIP runtime call failed */
   MGWR_ERR_NOT_CONVERGED = 4, /* max_cycles reached; u and stats still written */
-  MGWR_ERR_NONFINITE = 5      /* a residual norm was NaN/Inf; u and stats still written */
+  MGWR_ERR_NONFINITE = 5,     /* a residual norm was NaN/Inf; u and stats still written */
+  MGWR_ERR_MODEL = 6          /* learned weights missing or corrupt (mgwr_model_load) */
 };
 
 typedef enum {
@@ -62,16 +63,17 @@ typedef enum {
 /* Flags of mgwr_solve. */
 enum {
   MGWR_GUESS_IN_U = 1u,  /* u_dev holds the initial iterate (otherwise the zero grid function) */
-  MGWR_WARM_START = 2u,  /* initial iterate predicted by the plan's network (mgwr_plan_set_warm_start).
-                            Judged by the true float64 residual: a prediction whose defect is not
-                            finite is dropped at once, and one whose residual after the first cycles
-                            (the first pipelined launch, or the first cycle / refinement of a staged
-                            solve) is not below ||b||_inf is dropped then; the solve restarts from the
-                            zero iterate and the cycles already spent stay counted */
-  MGWR_WARM_RES0 = 4u    /* with MGWR_WARM_START: also evaluate the prediction's float64 residual
-                            (stats.warm_res0; always done for mixed precision, whose first step needs
-                            that defect).  Without it a float64 solve skips that defect (NaN in
-                            warm_res0) and a non-finite prediction is caught by the first cycles */
+  MGWR_WARM_START = 2u,  /* initial iterate predicted by the plan's network (mgwr_plan_set_warm_start
+                            or mgwr_model_load).  Judged by the true float64 residual: the prediction's
+                            defect is always evaluated (stats.warm_res0) and a prediction whose defect
+                            is not finite is dropped at once; after the first outer step from it (the
+                            first pipelined launch, or the first cycle / refinement of a staged solve)
+                            its residual is compared with the residual the zero iterate reaches in the
+                            same number of cycles, ||b||_inf rho0^c with rho0 the plan's average
+                            factor of its last solve from zero (rho0 = 1 before there is one).  Above
+                            twice that (and above the tolerance): the prediction is dropped, the solve
+                            restarts from the zero iterate and the cycles already spent stay counted */
+  MGWR_WARM_RES0 = 4u    /* kept for compatibility: the prediction's residual is always evaluated */
 };
 
 typedef struct {
@@ -90,7 +92,22 @@ typedef struct {
   int precision;    /* mgwr_precision */
   int inner_cycles; /* mixed precision: inner V-cycles per outer refinement step (1..16) */
   int schedule;     /* MGWR_SCHED_AUTO (default), MGWR_SCHED_STAGED or MGWR_SCHED_PIPELINED */
+  double eta;       /* admissibility parameter, > 0 (default 1): a block whose row and column
+                       supports I_t, I_s satisfy d < a and diam(I_t) <= eta dist(I_s, I_t) is kept
+                       in low-rank form.  eta = 1 is Definition 3.1; other values are the more
+                       general conditions the remark after it allows.  The Taylor error of a block
+                       decays like (eta / (eta + 2))^k (proof of Theorem 3.1 with the contraction
+                       ratio of the condition), so larger eta compresses more at a given k */
+  int cluster;      /* cluster tree: MGWR_CLUSTER_INDEX (default) or MGWR_CLUSTER_GEOMETRIC */
 } mgwr_params;
+
+/* Cluster trees of the time indices 1..M (Section 3 leaves the split rule open).
+ * INDEX: a cluster of s > leaf indices splits into s/2 (rounded down) and the rest.
+ * GEOMETRIC: a cluster splits where its time interval [t_lo+1, t_hi] is halved
+ * (the first index past the midpoint starts the second child, each child keeping
+ * at least one index): on a graded mesh the early clusters then hold many short
+ * steps and the late ones few long steps, so blocks of similar time extent meet. */
+enum { MGWR_CLUSTER_INDEX = 0, MGWR_CLUSTER_GEOMETRIC = 1 };
 
 /* Cycle schedules (float64 solver).  Every operator of a cycle is causal in
  * time, so the pipelined schedule runs several whole cycles in one launch,
@@ -103,7 +120,7 @@ enum { MGWR_SCHED_AUTO = 0, MGWR_SCHED_STAGED = 1, MGWR_SCHED_PIPELINED = 2 };
  * launches then leave most of the GPU idle) and stages otherwise. */
 
 /* Fill *p with defaults: leaf 16, V(1,1), gamma 1, max_cycles 50, FP64, length 1, T 1,
- * automatic schedule. */
+ * automatic schedule, eta 1, index-bisection clusters. */
 void mgwr_params_default(mgwr_params* p);
 
 typedef struct {
@@ -117,7 +134,9 @@ typedef struct {
                          refinements); 0 where a pipelined launch with a learned cycle count
                          evaluated the norm only after its last cycle */
   int used_warm_start; /* 1 if the network's prediction was the initial iterate of the returned solution */
-  double warm_res0;    /* ||b - A u_predicted||_inf (warm start with MGWR_WARM_RES0 or mixed precision; else NaN) */
+  double warm_res0;    /* ||b - A u_predicted||_inf (every warm start; NaN without one) */
+  double setup_ms;     /* host set-up of the plan: mgwr_plan_create plus the last mgwr_plan_bind */
+  double solve_ms;     /* wall time of this solve (it returns with all its device work finished) */
 } mgwr_stats;
 
 typedef struct mgwr_plan mgwr_plan;
@@ -153,12 +172,20 @@ int mgwr_solve(mgwr_plan* plan, const double* f_dev, const double* g_dev, double
                double* u_dev, unsigned flags, mgwr_stats* stats);
 
 /* out_dev = b - A u with b = f + a_{.,1} g (g_dev may be NULL): the float64
- * defect of the full system (Algorithm 2 "compute the defect", Algorithm 3
+ * defect of the full system (the defect step of Algorithm 2, with Algorithm 3
  * for R~).  If norm_host is not NULL the stream is synchronised and
  * ||out||_inf is stored there.  out_dev may be NULL when only the norm is
  * wanted. */
 int mgwr_residual(mgwr_plan* plan, const double* f_dev, const double* g_dev, const double* u_dev,
                   double* out_dev, double* norm_host);
+
+/* out_dev = A_{h,tau} u_dev in float64: the space-time operator of the
+ * discrete system (Section 2 for R, Section 3 for its representation R~,
+ * Algorithm 3 for the product), (A u)_{q,m} = sum_j R~_{m,j} u_{q,j} +
+ * (A_h u_{.,m})_q, both arrays [M][N] row-major on the plan's device.
+ * u_dev and out_dev must not overlap.  Asynchronous on the plan's stream.
+ * Errors: MGWR_ERR_INVALID_ARG (null array), MGWR_ERR_STATE (plan not bound). */
+int mgwr_apply_A(mgwr_plan* plan, const double* u_dev, double* out_dev);
 
 /* Algorithm 3 on its own: y_dev = R~ x_dev for `ncols` independent columns,
  * both [M][ncols] row-major. */
@@ -189,7 +216,9 @@ enum {
   MGWR_K_PROLONG = 5,   /* interpolation and correction (either precision) */
   MGWR_K_PIPE64 = 6,    /* one launch of K time-pipelined float64 cycles (all stages) */
   MGWR_K_COARSE = 7,    /* staged schedule: one pipelined launch of a cycle's coarse levels (either precision) */
-  MGWR_K_CLASSES = 8
+  MGWR_K_SIDE = 8,      /* a batch's staged instances solved side by side: one entry per batch solve, the
+                           wall time of that whole phase and the algorithmic work of all its cycles */
+  MGWR_K_CLASSES = 9
 };
 typedef struct {
   long long launches[MGWR_K_CLASSES];
@@ -227,7 +256,11 @@ int mgwr_batch_bind(mgwr_batch* batch, void* workspace_dev, size_t bytes, void* 
  * order. */
 int mgwr_batch_solve(mgwr_batch* batch, const double* const* f_dev, const double* const* g_dev, double tol,
                      double* const* u_dev, unsigned flags, mgwr_stats* stats);
-/* Event timing of the batch's launches (class MGWR_K_PIPE64); synchronises.
+/* Timing of the batch's work: event-timed merged launches (class
+ * MGWR_K_PIPE64) and the side-by-side phase of its staged instances (class
+ * MGWR_K_SIDE, host wall clock; per-launch timing of the plans involved is
+ * suspended while worker threads solve them, so that no plan's events are
+ * recorded from another thread); synchronises.
  * out (nullable) receives the counters; enable 1 clears them and turns timing
  * on, 0 turns it off, -1 leaves it unchanged. */
 int mgwr_batch_timing(mgwr_batch* batch, int enable, mgwr_timing* out);
@@ -335,6 +368,33 @@ int mgwr_net_destroy(mgwr_net* net);
  * n = 2^p - 1 and a network bound with max_bhw >= N on the plan's device;
  * the network must outlive the attachment.  net NULL detaches. */
 int mgwr_plan_set_warm_start(mgwr_plan* plan, mgwr_net* net, int nslices, const int* rows_host);
+
+/* Learned weights as one self-describing host blob (little endian):
+ *   char magic[8] = "MGWRNET1"; int32 version = 1; int32 layers L;
+ *   int32 channels[L + 1]; int32 nsignal; int32 nslices; int32 rows[nslices];
+ *   double h_min; int64 nparam; float32 params[nparam] (the layout of
+ *   mgwr_net_param_count); uint64 checksum = 64-bit FNV-1a of every byte before it.
+ * mgwr_model_describe checks a blob and reports its shape; mgwr_model_load
+ * checks it against `net` (same layers, channels and nsignal), copies the
+ * weights into the net's master array (synchronises the net's stream),
+ * refreshes the bfloat16 copies, applies h_min (mgwr_net_set_finest) and
+ * attaches the net to the plan with the blob's slice rows
+ * (mgwr_plan_set_warm_start).  A missing blob (NULL or 0 bytes), a wrong
+ * magic, version or size, a checksum mismatch, non-finite weights, shape
+ * fields out of range, or a shape that differs from net's return
+ * MGWR_ERR_MODEL and change nothing; the plan then keeps its previous
+ * network, if any (solves with MGWR_WARM_START and no network fail with
+ * MGWR_ERR_STATE). */
+typedef struct {
+  int layers;
+  int channels[17];
+  int nsignal, nslices;
+  int rows[64];
+  double h_min;
+  long long nparam;
+} mgwr_model_info;
+int mgwr_model_describe(const void* blob_host, size_t bytes, mgwr_model_info* info);
+int mgwr_model_load(mgwr_plan* plan, mgwr_net* net, const void* blob_host, size_t bytes);
 
 /* Plan facts for tests and reports (host, no device work). */
 typedef struct {

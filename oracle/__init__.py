@@ -26,7 +26,7 @@ from .l1 import steps, pow_diff, l1_weights, l1_matrix, initial_value_weights  #
 from .hmatrix import (cluster_tree, admissible, block_partition, taylor_coeffs, rk_factors,  # noqa: F401
                       hmatrix_dense, theorem_bound)
 from .direct import (laplacian_apply, laplacian_dense, laplacian_eigs, rhs, timestep_solve,  # noqa: F401
-                     residual, residual_columns, single_mode_profile, mode_eigenvalue, kron_solve,
+                     residual, residual_columns, residual_sampled, single_mode_profile, mode_eigenvalue, kron_solve,
                      solve_shifted_spatial)
 from .special import mittag_leffler  # noqa: F401
 

@@ -118,6 +118,18 @@ def residual_columns(Rt: np.ndarray, U: np.ndarray, B: np.ndarray, dim: int, n: 
     return out - lap / (h * h)
 
 
+def residual_sampled(Rt: np.ndarray, b_cols: np.ndarray, u_cols: np.ndarray, u_nbrs, h: float) -> np.ndarray:
+    """Residual at a few spatial points from their time lines alone:
+    r = b - Rt u - (2 dim u - sum of the 2 dim neighbour lines) / h^2, with
+    u_nbrs the neighbour lines [M][len(cols)] (zero where a neighbour is a
+    Dirichlet boundary point); for arrays too large to hold on the host."""
+    dim = len(u_nbrs) // 2
+    lap = 2.0 * dim * u_cols
+    for v in u_nbrs:
+        lap = lap - v
+    return b_cols - Rt @ u_cols - lap / (h * h)
+
+
 def single_mode_profile(Rt: np.ndarray, lam: float, phi: np.ndarray) -> np.ndarray:
     """If b = phi(t) s with A_h s = lam s, then u = w(t) s with (Rt + lam I) w = phi."""
     M = Rt.shape[0]

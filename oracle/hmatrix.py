@@ -26,6 +26,14 @@ Readings where the paper leaves a choice:
   sizes s//2 and s - s//2; leaves have size <= leaf (16 by default);
 * the block recursion pairs clusters of the same depth; if exactly one of the
   two clusters is a leaf, only the other one is split.
+
+Variants the remark after Definition 3.1 leaves open (off by default, so the
+plain construction above is unchanged):
+* admissibility with a parameter eta > 0: diam(I_t) <= eta dist(I_s, I_t)
+  (still with d < a); eta = 1 is Definition 3.1;
+* geometric cluster tree: a cluster of the levels t_{lo+1}..t_hi splits
+  after the last level that does not exceed the midpoint of its time
+  interval, each child keeping at least one level.
 """
 from __future__ import annotations
 
@@ -50,35 +58,44 @@ class Cluster:
         return not self.children
 
 
-def cluster_tree(lo: int, hi: int, leaf: int) -> Cluster:
-    """0-based index range [lo, hi) of the time levels t_{lo+1}..t_{hi}."""
+def cluster_tree(lo: int, hi: int, leaf: int, rule: str = "index", t: np.ndarray | None = None) -> Cluster:
+    """0-based index range [lo, hi) of the time levels t_{lo+1}..t_{hi}.
+    rule "index": halve the index range; "geometric": halve the time
+    interval [t_{lo+1}, t_hi] (needs the mesh t)."""
     c = Cluster(lo, hi)
     if hi - lo > leaf:
-        mid = lo + (hi - lo) // 2
-        c.children = [cluster_tree(lo, mid, leaf), cluster_tree(mid, hi, leaf)]
+        if rule == "index":
+            mid = lo + (hi - lo) // 2
+        elif rule == "geometric":
+            tm = 0.5 * (t[lo + 1] + t[hi])
+            count = int(np.sum(t[lo + 1:hi + 1] <= tm))      # levels at or before the midpoint
+            mid = min(max(lo + count, lo + 1), hi - 1)
+        else:
+            raise ValueError(rule)
+        c.children = [cluster_tree(lo, mid, leaf, rule, t), cluster_tree(mid, hi, leaf, rule, t)]
     return c
 
 
-def admissible(t: np.ndarray, rows: Cluster, cols: Cluster) -> bool:
+def admissible(t: np.ndarray, rows: Cluster, cols: Cluster, eta: float = 1.0) -> bool:
     M = len(t) - 1
     m1, m2 = rows.lo + 1, rows.hi          # 1-based rows
     j2 = cols.hi                            # 1-based last column
     if j2 + 1 > M:
         return False
     a, d = t[m1], t[j2 + 1]
-    return d < a and (t[m2] - t[m1]) <= (a - d)
+    return d < a and (t[m2] - t[m1]) <= eta * (a - d)
 
 
-def block_partition(t: np.ndarray, leaf: int = 16):
+def block_partition(t: np.ndarray, leaf: int = 16, eta: float = 1.0, cluster: str = "index"):
     """List of (kind, rows, cols) with kind in {'rk', 'full'}; zero blocks are omitted."""
     M = len(t) - 1
-    root = cluster_tree(0, M, leaf)
+    root = cluster_tree(0, M, leaf, cluster, t)
     out = []
 
     def rec(r: Cluster, c: Cluster):
         if c.lo >= r.hi:                   # columns entirely after the rows: zero block
             return
-        if admissible(t, r, c):
+        if admissible(t, r, c, eta):
             out.append(("rk", r, c))
             return
         if r.is_leaf() and c.is_leaf():
@@ -124,12 +141,13 @@ def rk_factors(t: np.ndarray, alpha: float, k: int, rows: Cluster, cols: Cluster
     return A, B
 
 
-def hmatrix_dense(t: np.ndarray, alpha: float, k: int, leaf: int = 16, R: np.ndarray | None = None):
+def hmatrix_dense(t: np.ndarray, alpha: float, k: int, leaf: int = 16, R: np.ndarray | None = None,
+                  eta: float = 1.0, cluster: str = "index"):
     """R~ expanded to a dense M x M array: full blocks copy R, admissible blocks are A B^T."""
     if R is None:
         R = l1_matrix(t, alpha)
     Rt = np.zeros_like(R)
-    for kind, r, c in block_partition(t, leaf):
+    for kind, r, c in block_partition(t, leaf, eta, cluster):
         if kind == "full":
             Rt[r.lo:r.hi, c.lo:c.hi] = R[r.lo:r.hi, c.lo:c.hi]
         else:

@@ -19,6 +19,7 @@ MGWR_ERR_STATE = 2
 MGWR_ERR_HIP = 3
 MGWR_ERR_NOT_CONVERGED = 4
 MGWR_ERR_NONFINITE = 5
+MGWR_ERR_MODEL = 6
 MGWR_FP64 = 0
 MGWR_MIXED_FP32 = 1
 MGWR_MIXED_BF16 = 2
@@ -37,10 +38,11 @@ EXPORTED = [
     "mgwr_net_sync_weights", "mgwr_net_forward", "mgwr_net_gradient", "mgwr_net_set_finest",
     "mgwr_net_adam_step", "mgwr_net_destroy",
     "mgwr_plan_set_warm_start", "mgwr_batch_set_graph", "mgwr_batch_graph_replays", "mgwr_plan_autotune",
-    "mgwr_plan_set_staging", "mgwr_plan_tuned",
+    "mgwr_plan_set_staging", "mgwr_plan_tuned", "mgwr_apply_A", "mgwr_model_describe", "mgwr_model_load",
 ]
 
-KERNEL_CLASSES = ["smooth64", "defect64", "smooth32", "defect32", "restrict", "prolong", "pipe64", "coarse"]
+KERNEL_CLASSES = ["smooth64", "defect64", "smooth32", "defect32", "restrict", "prolong", "pipe64", "coarse", "side"]
+NCLASSES = len(KERNEL_CLASSES)
 
 
 class MgwrError(RuntimeError):
@@ -55,13 +57,14 @@ class Params(ctypes.Structure):
                 ("r", ctypes.c_double), ("k", ctypes.c_int), ("leaf", ctypes.c_int),
                 ("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("gamma", ctypes.c_int),
                 ("max_cycles", ctypes.c_int), ("precision", ctypes.c_int), ("inner_cycles", ctypes.c_int),
-                ("schedule", ctypes.c_int)]
+                ("schedule", ctypes.c_int), ("eta", ctypes.c_double), ("cluster", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int), ("refinements", ctypes.c_int), ("res0", ctypes.c_double),
                 ("bnorm", ctypes.c_double), ("res", ctypes.c_double), ("avg_factor", ctypes.c_double),
-                ("history", ctypes.c_double * 64), ("used_warm_start", ctypes.c_int), ("warm_res0", ctypes.c_double)]
+                ("history", ctypes.c_double * 64), ("used_warm_start", ctypes.c_int), ("warm_res0", ctypes.c_double),
+                ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "history"}
@@ -71,12 +74,23 @@ class Stats(ctypes.Structure):
 
 
 class Timing(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_longlong * 8), ("ms", ctypes.c_double * 8),
-                ("flops", ctypes.c_double * 8), ("bytes", ctypes.c_double * 8)]
+    _fields_ = [("launches", ctypes.c_longlong * NCLASSES), ("ms", ctypes.c_double * NCLASSES),
+                ("flops", ctypes.c_double * NCLASSES), ("bytes", ctypes.c_double * NCLASSES)]
 
     def as_dict(self):
         return {name: {"launches": self.launches[i], "ms": self.ms[i], "flops": self.flops[i],
                        "bytes": self.bytes[i]} for i, name in enumerate(KERNEL_CLASSES)}
+
+
+class ModelInfo(ctypes.Structure):
+    _fields_ = [("layers", ctypes.c_int), ("channels", ctypes.c_int * 17), ("nsignal", ctypes.c_int),
+                ("nslices", ctypes.c_int), ("rows", ctypes.c_int * 64), ("h_min", ctypes.c_double),
+                ("nparam", ctypes.c_longlong)]
+
+    def as_dict(self):
+        return {"layers": self.layers, "channels": [self.channels[i] for i in range(self.layers + 1)],
+                "nsignal": self.nsignal, "nslices": self.nslices,
+                "rows": [self.rows[i] for i in range(self.nslices)], "h_min": self.h_min, "nparam": self.nparam}
 
 
 class PlanInfo(ctypes.Structure):
@@ -143,6 +157,9 @@ def lib():
     L.mgwr_net_adam_step.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, ip]
     L.mgwr_net_destroy.argtypes = [vp]
     L.mgwr_plan_set_warm_start.argtypes = [vp, vp, ip, ctypes.POINTER(ctypes.c_int)]
+    L.mgwr_apply_A.argtypes = [vp, vp, vp]
+    L.mgwr_model_describe.argtypes = [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ModelInfo)]
+    L.mgwr_model_load.argtypes = [vp, vp, ctypes.c_char_p, ctypes.c_size_t]
     L.mgwr_last_error.argtypes = []
     L.mgwr_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -185,7 +202,7 @@ class Plan:
 
     def __init__(self, dim, n, M, alpha, k=10, r=1.0, T=1.0, length=1.0, t=None, leaf=16,
                  nu1=1, nu2=1, gamma=1, max_cycles=50, precision="fp64", inner_cycles=1,
-                 schedule="auto"):
+                 schedule="auto", eta=1.0, cluster="index"):
         import numpy as np
         L = lib()
         p = Params()
@@ -197,6 +214,8 @@ class Plan:
                        "mixed_bf16": MGWR_MIXED_BF16, "bf16": MGWR_MIXED_BF16}[precision]
         p.inner_cycles = int(inner_cycles)
         p.schedule = {"auto": 0, "staged": 1, "pipelined": 2}[schedule]
+        p.eta = float(eta)
+        p.cluster = {"index": 0, "geometric": 1}[cluster]
         self.params = p
         self.dim, self.n, self.M = int(dim), int(n), int(M)
         self.N = self.n ** self.dim
@@ -313,6 +332,24 @@ class Plan:
         _require(y, "y", (self.M, ncols))
         _check(lib().mgwr_hmatvec(self._h, _dptr(x), _dptr(y), int(ncols)))
         return y
+
+    def apply_A(self, u, out=None):
+        """out = A u (the float64 space-time operator: R~ in time plus the
+        spatial stencil)."""
+        import torch
+        _require(u, "u", (self.M, self.N))
+        if out is None:
+            out = torch.empty_like(u)
+        _require(out, "out", (self.M, self.N))
+        _check(lib().mgwr_apply_A(self._h, _dptr(u), _dptr(out)))
+        return out
+
+    def load_model(self, net, blob):
+        """Load a weight blob (model_blob) into the bound Net and attach it for
+        warm-started solves (mgwr_model_load)."""
+        blob = bytes(blob)
+        _check(lib().mgwr_model_load(self._h, None if net is None else net._h, blob, len(blob)))
+        self._net = net
 
     def htrsm(self, b, level=0, x=None):
         import torch
@@ -551,3 +588,35 @@ class Net:
             self.close()
         except Exception:
             pass
+
+
+def _fnv1a64(data: bytes) -> int:
+    """64-bit FNV-1a (the weight blob's checksum)."""
+    h = 0xcbf29ce484222325
+    for byte in memoryview(data).cast("B"):
+        h = ((h ^ byte) * 0x100000001b3) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def model_blob(channels, nsignal, rows, h_min, params) -> bytes:
+    """Serialise network weights into the self-describing blob that
+    mgwr_model_load reads (layout in include/mgwr.h)."""
+    import struct
+
+    import numpy as np
+    ch = [int(c) for c in channels]
+    rows = [int(r) for r in rows]
+    w = np.ascontiguousarray(np.asarray(params, dtype="<f4"))
+    body = b"MGWRNET1" + struct.pack("<ii", 1, len(ch) - 1) + struct.pack(f"<{len(ch)}i", *ch)
+    body += struct.pack("<ii", int(nsignal), len(rows)) + struct.pack(f"<{len(rows)}i", *rows)
+    body += struct.pack("<dq", float(h_min), int(w.size)) + w.tobytes()
+    return body + struct.pack("<Q", _fnv1a64(body))
+
+
+def describe_model(blob):
+    """Shape of a weight blob as the library reads it (raises MgwrError with
+    code MGWR_ERR_MODEL if it is missing or corrupt)."""
+    blob = bytes(blob) if blob is not None else b""
+    info = ModelInfo()
+    _check(lib().mgwr_model_describe(blob if blob else None, len(blob), ctypes.byref(info)))
+    return info.as_dict()

@@ -6,10 +6,12 @@
 //    R_{m,m} = a_{m,m}, R_{m,j} = a_{m,j} - a_{m,j+1} (Section 2, entries of R);
 //    differences of powers use x^p expm1(p log1p(d/x)) to avoid cancellation
 //    near the origin of a graded mesh;
-//  * cluster tree by index bisection down to `leaf` indices; block tree by the
+//  * cluster tree by index bisection (or, on request, by halving the time
+//    interval of a cluster) down to `leaf` indices; block tree by the
 //    recursive 2x2 split of Section 3 with Definition 3.1 on the supports
 //    I_t = [t_{m1}, t_{m2}] of the Dirac tests and I_s = [t_{j1-1}, t_{j2+1}] of
-//    the hats;
+//    the hats, diam(I_t) <= eta dist(I_s, I_t) (eta = 1: Definition 3.1; the
+//    remark after it allows other conditions);
 //  * Taylor factors about the midpoint t_c of I_t (Section 3):
 //    A_{m,nu} = (t_m - t_c)^nu / G(1-a),
 //    B_{j,nu} = c_nu/(1-a-nu) [(mu_{j-1}-mu_j)/dt_j - (mu_j-mu_{j+1})/dt_{j+1}],
@@ -76,6 +78,8 @@ std::string build_host_plan(const mgwr_params& p, const double* t_host, HostPlan
   if (p.schedule != MGWR_SCHED_AUTO && p.schedule != MGWR_SCHED_PIPELINED && p.schedule != MGWR_SCHED_STAGED)
     return "unknown schedule";
   if ((long long)p.M * (long long)std::pow((double)p.n, p.dim) > (1ll << 40)) return "problem too large";
+  if (!(p.eta > 0.0) || !std::isfinite(p.eta)) return "eta must be a finite number > 0";
+  if (p.cluster != MGWR_CLUSTER_INDEX && p.cluster != MGWR_CLUSTER_GEOMETRIC) return "unknown cluster rule";
 
   hp.p = p;
   const int M = p.M;
@@ -119,6 +123,14 @@ std::string build_host_plan(const mgwr_params& p, const double* t_host, HostPlan
     hp.clusters.push_back(Cluster{lo, hi, {-1, -1}, -1, 0, 0, 0.5 * (t[lo + 1] + t[hi])});
     if (hi - lo > p.leaf) {
       int mid = lo + (hi - lo) / 2;
+      if (p.cluster == MGWR_CLUSTER_GEOMETRIC) {
+        // the levels t_{lo+1} .. t_hi at or before the midpoint of their time
+        // interval form the first child (at least one level in each child)
+        const double tm = 0.5 * (t[lo + 1] + t[hi]);
+        int c = 0;
+        while (lo + 1 + c <= hi && t[lo + 1 + c] <= tm) ++c;
+        mid = std::min(std::max(lo + c, lo + 1), hi - 1);
+      }
       int a = make(lo, mid);
       int b = make(mid, hi);
       hp.clusters[id].child[0] = a;
@@ -144,7 +156,7 @@ std::string build_host_plan(const mgwr_params& p, const double* t_host, HostPlan
     int m1 = R.lo + 1, m2 = R.hi, j2 = C.hi;
     if (j2 + 1 > M) return false;
     double a = t[m1], d = t[j2 + 1];
-    return d < a && (t[m2] - t[m1]) <= (a - d);
+    return d < a && (t[m2] - t[m1]) <= p.eta * (a - d);
   };
   hp.dense_blocks.clear();
   hp.rk_blocks.clear();

@@ -352,7 +352,8 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
 #pragma unroll
       for (int e = 0; e < NB; ++e) {
         const T* src = (fuse_ec && e >= 2) ? ecrow + nb[e] : a.U + off + nb[e];
-        pf_n[r][e] = ((MODE == MODE_SMOOTH || MODE == MODE_RESID) && nbok[e] && ok) ? gld<PIPE>(src) : (T)0;
+        pf_n[r][e] = ((MODE == MODE_SMOOTH || MODE == MODE_RESID || MODE == MODE_MATVEC) && nbok[e] && ok)
+                         ? gld<PIPE>(src) : (T)0;
       }
       pf_c[r] = (fuse_ec && ok && p < a.nc) ? gld<PIPE>(ecrow + p) : (T)0;
       pf_u[r] = (kKnownX && ok) ? gld<PIPE>(a.U + off + q) : (T)0;
@@ -476,7 +477,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
         if constexpr (MODE == MODE_SMOOTH) v = pf_f[r] + a.inv_h2 * sn;
         else if constexpr (MODE == MODE_RESID) v = pf_f[r] - a.inv_h2 * (diagc * pf_u[r] - sn);
         else if constexpr (MODE == MODE_TRSM) v = pf_f[r];
-        else v = (T)0;
+        else v = a.dim > 0 ? -a.inv_h2 * (diagc * pf_u[r] - sn) : (T)0;   // MATVEC: the stencil part of A u
         acc[r] += v;
       }
     }
@@ -1059,7 +1060,7 @@ __global__ void fill_int_kernel(int* __restrict__ x, long long count, int v) {
 // ---------------------------------------------------------------------------
 // Stencil kernels (space only, every time row independently)
 
-// Full weighting (Algorithm 2 "restrict the defect only in space").
+// Full-weighting restriction of the defect in space only (Algorithm 2).
 template <typename T>
 __global__ void restrict_kernel(const T* __restrict__ rf, T* __restrict__ fc, int dim, int nf, int nc, long long M,
                                 int red_only) {
@@ -1087,8 +1088,8 @@ __global__ void restrict_kernel(const T* __restrict__ rf, T* __restrict__ fc, in
   }
 }
 
-// Linear / bilinear interpolation plus correction (Algorithm 2 "interpolate
-// the correction only in space" and "compute a new approximation").
+// Linear / bilinear interpolation of the coarse correction in space, added to
+// the fine iterate (the correction step of Algorithm 2).
 template <typename T>
 __global__ void prolong_kernel(const T* __restrict__ ec, T* __restrict__ uf, int dim, int nf, int nc, long long M,
                                int black_only) {

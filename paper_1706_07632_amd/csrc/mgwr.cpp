@@ -33,6 +33,10 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
 }  // namespace
 
 namespace mgwr {
@@ -124,6 +128,11 @@ struct mgwr_plan {
   int prefetch = 0;                    // in use
   int khint_staged = 0;                // cycles the last staged float64 solve from zero needed
   int khint_staged_warm = 0;           // the same from a predicted iterate
+  // average residual factor per cycle of the last converged solve from the
+  // zero iterate (0: none yet); the warm-start judge compares a prediction
+  // with what the zero iterate reaches in as many cycles
+  double rate_zero = 0.0;
+  double create_ms = 0.0, bind_ms = 0.0;   // host set-up times (mgwr_stats.setup_ms)
   double cycle_flops = 0.0, cycle_bytes = 0.0;  // algorithmic work of one pipelined cycle
   // staged schedule: from level coarse_l on (0: never) a cycle's levels run as
   // one pipelined launch ([0] float64, [1] float32 stage images)
@@ -529,6 +538,33 @@ int append_cycle_stages(mgwr_plan* pl, int l, int prev, std::vector<Stage>& out,
   return prev;
 }
 
+// Algorithmic work of one stage, added to flops / bytes: a march 2 S flops
+// and 3 M words per column; a restriction reads the fine defect (first colour
+// only: half) and writes the coarse right-hand side and iterate; a
+// prolongation reads the coarse correction and reads and writes the fine
+// iterate (second colour only: half); the precision hand-overs read and
+// write one row each.
+void stage_work(const mgwr_plan* pl, const Stage& x, double& flops, double& bytes) {
+  const HostPlan& hp = pl->hp;
+  if (x.kind == STG_SMOOTH || x.kind == STG_RESID) {
+    flops += 2.0 * hp.stored * x.m.ncols;
+    bytes += 3.0 * hp.p.M * x.m.ncols * sizeof(double);
+  } else if (x.kind == STG_SMOOTH32 || x.kind == STG_RESID32) {
+    flops += 2.0 * hp.stored * x.mf.ncols;
+    bytes += 3.0 * hp.p.M * x.mf.ncols * sizeof(float);
+  } else if (x.kind == STG_CAST || x.kind == STG_CORRECT) {
+    bytes += (x.kind == STG_CAST ? 16.0 : 20.0) * hp.p.M * x.npoints;
+  } else {
+    const double Nf = hp.p.dim == 1 ? x.nf : (double)x.nf * x.nf;
+    const double Nc = hp.p.dim == 1 ? x.nc : (double)x.nc * x.nc;
+    const double w = (x.kind == STG_RESTRICT || x.kind == STG_PROLONG) ? 8.0 : 4.0;
+    const double words = (x.kind == STG_RESTRICT || x.kind == STG_RESTRICT32)
+                             ? (x.red_only ? 0.5 : 1.0) * Nf + 2 * Nc
+                             : Nc + 2 * (x.black_only ? 0.5 : 1.0) * Nf;
+    bytes += words * hp.p.M * w;
+  }
+}
+
 // Appends K cycles of plan pl.  The defect of the full system (whose
 // per-work-item norms go to norms[c * chunks + item]) follows every cycle
 // when `every` is set, else only the last one.  Stage indices (prev) are
@@ -596,28 +632,7 @@ void build_plan_stages(mgwr_plan* pl, const double* b, double* u, int K, double*
   pl->stages_per_cycle = per_cycle;
   pl->norm_chunks = (hp.levels[0].N + 15) / 16;
   pl->cycle_flops = pl->cycle_bytes = 0.0;
-  for (int i = 0; i < per_cycle; ++i) {
-    const Stage& x = st[i];
-    if (x.kind == STG_SMOOTH || x.kind == STG_RESID) {
-      pl->cycle_flops += 2.0 * hp.stored * x.m.ncols;
-      pl->cycle_bytes += 3.0 * hp.p.M * x.m.ncols * sizeof(double);
-    } else if (x.kind == STG_SMOOTH32 || x.kind == STG_RESID32) {
-      pl->cycle_flops += 2.0 * hp.stored * x.mf.ncols;
-      pl->cycle_bytes += 3.0 * hp.p.M * x.mf.ncols * sizeof(float);
-    } else if (x.kind == STG_CAST || x.kind == STG_CORRECT) {
-      pl->cycle_bytes += (x.kind == STG_CAST ? 16.0 : 20.0) * hp.p.M * x.npoints;
-    } else {
-      const double Nf = hp.p.dim == 1 ? x.nf : (double)x.nf * x.nf;
-      const double Nc = hp.p.dim == 1 ? x.nc : (double)x.nc * x.nc;
-      const double w = (x.kind == STG_RESTRICT || x.kind == STG_PROLONG) ? 8.0 : 4.0;
-      // restriction: fine defect read (first colour only: half) + coarse rhs and iterate written;
-      // prolongation: coarse correction read + fine iterate read and written (second colour only: half)
-      const double words = (x.kind == STG_RESTRICT || x.kind == STG_RESTRICT32)
-                               ? (x.red_only ? 0.5 : 1.0) * Nf + 2 * Nc
-                               : Nc + 2 * (x.black_only ? 0.5 : 1.0) * Nf;
-      pl->cycle_bytes += words * hp.p.M * w;
-    }
-  }
+  for (int i = 0; i < per_cycle; ++i) stage_work(pl, st[i], pl->cycle_flops, pl->cycle_bytes);
   out.insert(out.end(), st.begin(), st.end());
 }
 
@@ -850,9 +865,9 @@ namespace {
 // Prepares an instance: b = f + a_1 g, the initial iterate (zero, given, or
 // predicted by the warm-start network), ||b||, res0.  `flags` returns with
 // MGWR_GUESS_IN_U set iff u holds a non-zero iterate whose defect is in R64_0.
-// A prediction whose defect is not finite is dropped for the zero iterate
-// here; the solve loops judge a finite one by the true residual after its
-// first cycles (see fall_back_to_zero).
+// A prediction's float64 defect is always evaluated (stats.warm_res0); one
+// whose defect is not finite is dropped for the zero iterate here, a finite
+// one is judged after its first cycles (see fall_back_to_zero).
 int prepare_solve(mgwr_plan* pl, const double* f, const double* g, double tol, double* u, unsigned& flags,
                   mgwr_stats& s, const double*& b, int& status) {
   int rc;
@@ -860,6 +875,8 @@ int prepare_solve(mgwr_plan* pl, const double* f, const double* g, double tol, d
   const long long N = hp.levels[0].N;
   const long long MN = (long long)hp.p.M * N;
   s = mgwr_stats{};
+  s.warm_res0 = std::nan("");
+  s.setup_ms = pl->create_ms + pl->bind_ms;
   b = f;
   if (g) {
     HIP_TRY(launch_rhs0(f, g, pl->a1, pl->B0, hp.p.M, N, pl->stream));
@@ -869,7 +886,6 @@ int prepare_solve(mgwr_plan* pl, const double* f, const double* g, double tol, d
   if ((rc = norm_inf<double>(pl, b, MN, &s.bnorm))) return rc;
   status = MGWR_ERR_NOT_CONVERGED;
   if (!std::isfinite(s.bnorm)) { status = MGWR_ERR_NONFINITE; return MGWR_OK; }
-  bool warm_unchecked = false;
   if (flags & MGWR_WARM_START) {
     if (!pl->net) return fail(MGWR_ERR_STATE, "MGWR_WARM_START needs a network (mgwr_plan_set_warm_start)");
     flags &= ~(unsigned)MGWR_GUESS_IN_U;
@@ -883,16 +899,11 @@ int prepare_solve(mgwr_plan* pl, const double* f, const double* g, double tol, d
       if ((rc = net_infer(pl->net, pl->netx, H, W, hp.levels[0].h, &y))) return rc;
       HIP_TRY(hipStreamSynchronize(net_stream(pl->net)));
       HIP_TRY(launch_time_interp(y, pl->rows_dev, ns, pl->tpow, g, hp.p.M, N, s.bnorm, u, pl->stream));
-      // float64 cycles do not need the prediction's defect (what decides is the
-      // residual after the first cycles); refinement steps start from it
-      if (pl->mixed || (flags & MGWR_WARM_RES0)) {
-        if ((rc = defect<double>(pl, pl->d64, 0, b, u, pl->d64.R[0]))) return rc;
-        if ((rc = norm_inf<double>(pl, pl->d64.R[0], MN, &s.warm_res0))) return rc;
-      } else {
-        s.warm_res0 = std::nan("");
-        warm_unchecked = true;
-      }
-      if (warm_unchecked || std::isfinite(s.warm_res0)) {
+      // the prediction's true residual (reported, and the right-hand side of
+      // a first refinement step)
+      if ((rc = defect<double>(pl, pl->d64, 0, b, u, pl->d64.R[0]))) return rc;
+      if ((rc = norm_inf<double>(pl, pl->d64.R[0], MN, &s.warm_res0))) return rc;
+      if (std::isfinite(s.warm_res0)) {
         s.used_warm_start = 1;
         flags |= MGWR_GUESS_IN_U;
       }
@@ -910,9 +921,7 @@ int prepare_solve(mgwr_plan* pl, const double* f, const double* g, double tol, d
     s.res0 = s.bnorm;
   }
   s.res = s.res0;
-  if (warm_unchecked) {
-    s.res = s.bnorm;   // not evaluated: the first cycles' residual decides
-  } else if (!std::isfinite(s.res0)) {
+  if (!std::isfinite(s.res0)) {
     status = MGWR_ERR_NONFINITE;
   } else if (s.res0 <= tol * s.bnorm) {
     status = MGWR_OK;
@@ -922,13 +931,22 @@ int prepare_solve(mgwr_plan* pl, const double* f, const double* g, double tol, d
 
 int batch_fail(int code, const std::string& m) { return fail(code, m); }
 
-// The true-residual judge of a predicted iterate: after the first cycles from
-// it, a residual that is not below ||b|| (the zero iterate's) means the
-// prediction did no better than no prediction at all; the solve then restarts
-// from zero (the cycles spent stay counted).  Returns 1 when it restarted.
-int fall_back_to_zero(mgwr_plan* pl, const double* b, double* u, mgwr_stats& s, int* rc) {
+// The true-residual judge of a predicted iterate: after the first outer step
+// from it (`cycles` cycles), its residual is compared with the one the zero
+// iterate reaches in as many cycles, ||b|| rho0^cycles, rho0 the plan's
+// average factor of its last converged solve from zero (||b|| itself before
+// there is one).  More than kJudgeMargin times that means the prediction did
+// worse than no prediction at all; the solve then restarts from zero (the
+// cycles spent stay counted).  The margin absorbs the spread of single-cycle
+// factors around their mean (a prediction no better than zero, e.g. the zero
+// network, is kept: restarting would only repeat its cycles).  A prediction
+// that has already met the tolerance is kept.  Returns 1 when it restarted.
+constexpr double kJudgeMargin = 2.0;
+int fall_back_to_zero(mgwr_plan* pl, const double* b, double* u, mgwr_stats& s, int cycles, double tol, int* rc) {
   *rc = MGWR_OK;
-  if (!s.used_warm_start || s.res < s.bnorm) return 0;
+  if (!s.used_warm_start) return 0;
+  const double expect = s.bnorm * (pl->rate_zero > 0.0 ? std::pow(pl->rate_zero, (double)cycles) : 1.0);
+  if (s.res <= kJudgeMargin * expect || s.res <= tol * s.bnorm) return 0;
   const long long MN = (long long)pl->hp.p.M * pl->hp.levels[0].N;
   s.used_warm_start = 0;
   s.res = s.res0 = s.bnorm;
@@ -1000,8 +1018,10 @@ int launch_batch_table(mgwr_batch* bt, long long ncnt, int ntasks) {
 
 int solve_pipelined(mgwr_batch* bt, const double* const* f, const double* const* g, double tol,
                     double* const* u, unsigned flags, mgwr_stats* stats, const std::vector<int>& sel) {
+  const auto t_start = std::chrono::steady_clock::now();
   const int n = (int)bt->plans.size();
   int rc;
+  const bool from_zero = !(flags & (MGWR_GUESS_IN_U | MGWR_WARM_START));
   std::vector<mgwr_stats> st(n);
   std::vector<const double*> b(n);
   std::vector<int> status(n), K(n), conv_at(n, -1), base(n, 0), judged(n, 0), zero_start(n, 0);
@@ -1123,7 +1143,7 @@ int solve_pipelined(mgwr_batch* bt, const double* const* f, const double* const*
       if (!judged[i]) {
         judged[i] = 1;
         int frc;
-        if (fall_back_to_zero(pl, b[i], u[i], s, &frc)) {
+        if (fall_back_to_zero(pl, b[i], u[i], s, s.cycles, tol, &frc)) {
           if (frc) return frc;
           HIP_TRY(hipStreamSynchronize(pl->stream));
           base[i] = pl->mixed ? s.refinements : s.cycles;
@@ -1140,10 +1160,13 @@ int solve_pipelined(mgwr_batch* bt, const double* const* f, const double* const*
     }
   }
   int ret = MGWR_OK;
+  const double solve_ms = ms_since(t_start);
   for (int i : sel) {
     mgwr_stats& s = st[i];
     if (conv_at[i] > 0) (s.used_warm_start ? bt->plans[i]->khint_warm : bt->plans[i]->khint) = conv_at[i];
     s.avg_factor = (s.cycles > 0 && s.res0 > 0) ? std::pow(s.res / s.res0, 1.0 / s.cycles) : 0.0;
+    s.solve_ms = solve_ms;
+    if (from_zero && status[i] == MGWR_OK && s.cycles > 0) bt->plans[i]->rate_zero = s.avg_factor;
     if (stats) stats[i] = s;
     if (ret == MGWR_OK && status[i] != MGWR_OK) ret = status[i];
   }
@@ -1172,11 +1195,14 @@ void mgwr_params_default(mgwr_params* p) {
   p->max_cycles = 50;
   p->precision = MGWR_FP64;
   p->inner_cycles = 1;
+  p->eta = 1.0;
+  p->cluster = MGWR_CLUSTER_INDEX;
 }
 
 int mgwr_plan_create(const mgwr_params* p, const double* t_host, mgwr_plan** out) {
   if (!p || !out) return fail(MGWR_ERR_INVALID_ARG, "null argument");
   *out = nullptr;
+  const auto t_start = std::chrono::steady_clock::now();
   mgwr_plan* pl = new (std::nothrow) mgwr_plan();
   if (!pl) return fail(MGWR_ERR_INVALID_ARG, "out of host memory");
   std::string e;
@@ -1190,6 +1216,7 @@ int mgwr_plan_create(const mgwr_params* p, const double* t_host, mgwr_plan** out
     return fail(MGWR_ERR_INVALID_ARG, e);
   }
   layout(pl);
+  pl->create_ms = ms_since(t_start);
   *out = pl;
   return MGWR_OK;
 }
@@ -1204,6 +1231,7 @@ int mgwr_plan_bind(mgwr_plan* pl, void* ws, size_t bytes, void* stream) {
   if (!pl || !ws) return fail(MGWR_ERR_INVALID_ARG, "null argument");
   if (bytes < pl->off.total) return fail(MGWR_ERR_STATE, "workspace too small");
   if (((uintptr_t)ws & 255) != 0) return fail(MGWR_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  const auto t_start = std::chrono::steady_clock::now();
   HIP_TRY(hipGetDevice(&pl->device));
   pl->stream = (hipStream_t)stream;
   pl->ws = (unsigned char*)ws;
@@ -1311,6 +1339,7 @@ int mgwr_plan_bind(mgwr_plan* pl, void* ws, size_t bytes, void* stream) {
   HIP_TRY(set_pipeline_lds_limit(cap));
   HIP_TRY(hipStreamSynchronize(pl->stream));
   pl->bound = true;
+  pl->bind_ms = ms_since(t_start);
   return MGWR_OK;
 }
 
@@ -1339,6 +1368,7 @@ int mgwr_solve(mgwr_plan* pl, const double* f, const double* g, double tol, doub
   if (!f || !u) return fail(MGWR_ERR_INVALID_ARG, "null array");
   if (!(tol > 0.0)) return fail(MGWR_ERR_INVALID_ARG, "tol must be > 0");
   if ((rc = use_device(pl))) return rc;
+  const auto t_start = std::chrono::steady_clock::now();
   if (use_pipeline(pl)) {
     // the pipelined solve of a batch of one, on the plan's own regions
     mgwr_batch one;
@@ -1361,6 +1391,7 @@ int mgwr_solve(mgwr_plan* pl, const double* f, const double* g, double tol, doub
     double* up[1] = {u};
     mgwr_stats s1{};
     int rc2 = solve_pipelined(&one, fp, gp, tol, up, flags, &s1, std::vector<int>{0});
+    s1.solve_ms = ms_since(t_start);
     if (pl->timing)
       for (int c = 0; c < MGWR_K_CLASSES; ++c) {
         pl->tacc.launches[c] += one.tacc.launches[c];
@@ -1375,6 +1406,7 @@ int mgwr_solve(mgwr_plan* pl, const double* f, const double* g, double tol, doub
   const HostPlan& hp = pl->hp;
   const int M = hp.p.M;
   const long long MN = (long long)M * hp.levels[0].N;
+  const unsigned flags0 = flags;
   mgwr_stats s{};
   const double* b = f;
   int status = MGWR_ERR_NOT_CONVERGED;
@@ -1404,7 +1436,7 @@ int mgwr_solve(mgwr_plan* pl, const double* f, const double* g, double tol, doub
       if ((rc = defect<double>(pl, pl->d64, 0, b, u, pl->d64.R[0]))) return rc;
       if ((rc = norm_inf<double>(pl, pl->d64.R[0], MN, &s.res))) return rc;
       if (s.cycles <= 64) s.history[s.cycles - 1] = s.res;
-      if (s.cycles == 1 && fall_back_to_zero(pl, b, u, s, &rc)) {
+      if (s.cycles == 1 && fall_back_to_zero(pl, b, u, s, 1, tol, &rc)) {
         if (rc) return rc;
         skip_to = 0;
         continue;
@@ -1433,7 +1465,7 @@ int mgwr_solve(mgwr_plan* pl, const double* f, const double* g, double tol, doub
       if ((rc = defect<double>(pl, pl->d64, 0, b, u, pl->d64.R[0]))) return rc;
       if ((rc = norm_inf<double>(pl, pl->d64.R[0], MN, &s.res))) return rc;
       if (s.refinements <= 64) s.history[s.refinements - 1] = s.res;
-      if (s.refinements == 1 && fall_back_to_zero(pl, b, u, s, &rc)) {
+      if (s.refinements == 1 && fall_back_to_zero(pl, b, u, s, s.cycles, tol, &rc)) {
         if (rc) return rc;
         HIP_TRY(launch_cast<double, float>(b, pl->d32.F[0], MN, pl->stream));
         continue;
@@ -1450,6 +1482,9 @@ int mgwr_solve(mgwr_plan* pl, const double* f, const double* g, double tol, doub
     if (stalled) return fail(MGWR_ERR_HIP, "pipelined coarse cycles stalled (a progress wait exceeded its bound)");
   }
   s.avg_factor = (s.cycles > 0 && s.res0 > 0) ? std::pow(s.res / s.res0, 1.0 / s.cycles) : 0.0;
+  if (status == MGWR_OK && s.cycles > 0 && !(flags0 & (MGWR_GUESS_IN_U | MGWR_WARM_START)))
+    pl->rate_zero = s.avg_factor;
+  s.solve_ms = ms_since(t_start);
   if (st) *st = s;
   if (status == MGWR_ERR_NOT_CONVERGED) return fail(status, "max_cycles reached before the tolerance");
   if (status == MGWR_ERR_NONFINITE) return fail(status, "residual norm is not finite");
@@ -1464,6 +1499,24 @@ int mgwr_hmatvec(mgwr_plan* pl, const double* x, double* y, int ncols) {
   MarchArgs<double> a = base_args<double>(pl, pl->d64, 0);
   a.F = nullptr; a.U = const_cast<double*>(x); a.Out = y;
   a.ld = ncols; a.ncols = ncols; a.cstride = 1; a.coff = 0; a.dim = 0; a.n = 0; a.inv_h2 = 0.0;
+  HIP_TRY(launch_march<double>(MODE_MATVEC, a, pl->stream));
+  return MGWR_OK;
+}
+
+int mgwr_apply_A(mgwr_plan* pl, const double* u, double* out) {
+  int rc = check_bound(pl);
+  if (rc) return rc;
+  if (!u || !out) return fail(MGWR_ERR_INVALID_ARG, "null array");
+  if ((rc = use_device(pl))) return rc;
+  const HostPlan& hp = pl->hp;
+  const Level& lv = hp.levels[0];
+  const long long MN = (long long)hp.p.M * lv.N;
+  if (u < out + MN && out < u + MN) return fail(MGWR_ERR_INVALID_ARG, "u and out must not overlap");
+  // the product march with the stencil: out = R~ u + A_h u
+  MarchArgs<double> a = base_args<double>(pl, pl->d64, 0);
+  a.F = nullptr; a.U = const_cast<double*>(u); a.Out = out;
+  a.ld = lv.N; a.ncols = lv.N; a.cstride = 1; a.coff = 0;
+  a.dim = hp.p.dim; a.n = lv.n; a.inv_h2 = 1.0 / (lv.h * lv.h);
   HIP_TRY(launch_march<double>(MODE_MATVEC, a, pl->stream));
   return MGWR_OK;
 }
@@ -1525,6 +1578,108 @@ int mgwr_plan_set_warm_start(mgwr_plan* pl, mgwr_net* net, int nslices, const in
   HIP_TRY(hipStreamSynchronize(pl->stream));
   pl->net = net;
   pl->nslices = nslices;
+  return MGWR_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// 64-bit FNV-1a of a byte range (the weight blob's checksum).
+unsigned long long fnv1a64(const unsigned char* p, size_t n) {
+  unsigned long long h = 0xcbf29ce484222325ull;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 0x100000001b3ull;
+  }
+  return h;
+}
+
+// Parses and checks a weight blob (layout in mgwr.h); on success *params
+// points at its nparam float32 weights inside the blob.
+int parse_model(const void* blob, size_t bytes, mgwr_model_info* info, const float** params) {
+  if (!blob || bytes == 0) return fail(MGWR_ERR_MODEL, "no learned weights (empty blob)");
+  const unsigned char* p = static_cast<const unsigned char*>(blob);
+  size_t off = 0;
+  auto take = [&](void* dst, size_t n) -> bool {
+    if (off + n > bytes) return false;
+    std::memcpy(dst, p + off, n);
+    off += n;
+    return true;
+  };
+  char magic[8];
+  int version = 0;
+  mgwr_model_info mi{};
+  if (!take(magic, 8) || std::memcmp(magic, "MGWRNET1", 8) != 0)
+    return fail(MGWR_ERR_MODEL, "weight blob: bad magic");
+  if (!take(&version, 4) || version != 1) return fail(MGWR_ERR_MODEL, "weight blob: unsupported version");
+  if (!take(&mi.layers, 4) || mi.layers < 1 || mi.layers > 16)
+    return fail(MGWR_ERR_MODEL, "weight blob: layer count outside [1, 16]");
+  for (int l = 0; l <= mi.layers; ++l)
+    if (!take(&mi.channels[l], 4) || mi.channels[l] < 1 || mi.channels[l] > 1024)
+      return fail(MGWR_ERR_MODEL, "weight blob: channel count outside [1, 1024]");
+  if (!take(&mi.nsignal, 4) || mi.nsignal < 1 || mi.nsignal > mi.channels[0] - 1)
+    return fail(MGWR_ERR_MODEL, "weight blob: bad signal channel count");
+  if (!take(&mi.nslices, 4) || mi.nslices < 1 || mi.nslices > 64)
+    return fail(MGWR_ERR_MODEL, "weight blob: slice count outside [1, 64]");
+  for (int i = 0; i < mi.nslices; ++i)
+    if (!take(&mi.rows[i], 4) || mi.rows[i] < 0 || (i > 0 && mi.rows[i] <= mi.rows[i - 1]))
+      return fail(MGWR_ERR_MODEL, "weight blob: slice rows must increase from 0");
+  if (!take(&mi.h_min, 8) || !(mi.h_min >= 0.0) || !std::isfinite(mi.h_min))
+    return fail(MGWR_ERR_MODEL, "weight blob: bad h_min");
+  long long expect = 0;
+  for (int l = 0; l < mi.layers; ++l) expect += (long long)mi.channels[l + 1] * mi.channels[l] * 9 + mi.channels[l + 1];
+  if (!take(&mi.nparam, 8) || mi.nparam != expect)
+    return fail(MGWR_ERR_MODEL, "weight blob: parameter count does not match the layer shapes");
+  const size_t pbytes = (size_t)mi.nparam * sizeof(float);
+  const size_t poff = off;
+  if (off + pbytes + 8 != bytes) return fail(MGWR_ERR_MODEL, "weight blob: wrong size");
+  off += pbytes;
+  unsigned long long sum = 0;
+  std::memcpy(&sum, p + off, 8);
+  if (sum != fnv1a64(p, off)) return fail(MGWR_ERR_MODEL, "weight blob: checksum mismatch");
+  for (long long i = 0; i < mi.nparam; ++i) {
+    float v;
+    std::memcpy(&v, p + poff + (size_t)i * 4, 4);
+    if (!std::isfinite(v)) return fail(MGWR_ERR_MODEL, "weight blob: non-finite weight");
+  }
+  if (info) *info = mi;
+  if (params) *params = reinterpret_cast<const float*>(p + poff);
+  return MGWR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mgwr_model_describe(const void* blob, size_t bytes, mgwr_model_info* info) {
+  return parse_model(blob, bytes, info, nullptr);
+}
+
+int mgwr_model_load(mgwr_plan* pl, mgwr_net* net, const void* blob, size_t bytes) {
+  int rc = check_bound(pl);
+  if (rc) return rc;
+  if (!net) return fail(MGWR_ERR_INVALID_ARG, "null network");
+  if (!net_is_bound(net)) return fail(MGWR_ERR_STATE, "network is not bound");
+  mgwr_model_info mi{};
+  const float* w = nullptr;
+  if ((rc = parse_model(blob, bytes, &mi, &w))) return rc;
+  if (!net_same_shape(net, mi.layers, mi.channels, mi.nsignal) || (size_t)mi.nparam != net_param_count(net))
+    return fail(MGWR_ERR_MODEL, "weight blob: network shape differs from the bound network's");
+  for (int i = 0; i < mi.nslices; ++i)
+    if (mi.rows[i] >= pl->hp.p.M) return fail(MGWR_ERR_MODEL, "weight blob: slice row beyond the plan's mesh");
+  if (mi.nsignal != mi.nslices || mi.channels[0] - 1 != mi.nslices + 2 || mi.channels[mi.layers] != mi.nslices)
+    return fail(MGWR_ERR_MODEL, "weight blob: the network must map nslices slices plus 2 extra channels to nslices");
+  // attach first (it checks the plan's grid and the net's capacity), then copy
+  if ((rc = mgwr_plan_set_warm_start(pl, net, mi.nslices, mi.rows))) return rc;
+  std::vector<float> host((size_t)mi.nparam);   // the blob's weights may be unaligned
+  std::memcpy(host.data(), w, host.size() * sizeof(float));
+  HIP_TRY(hipMemcpyAsync(net_params(net), host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice,
+                         net_stream(net)));
+  HIP_TRY(hipStreamSynchronize(net_stream(net)));
+  if ((rc = mgwr_net_sync_weights(net))) return rc;
+  if ((rc = mgwr_net_set_finest(net, mi.h_min))) return rc;
+  HIP_TRY(hipStreamSynchronize(net_stream(net)));
   return MGWR_OK;
 }
 
@@ -1671,8 +1826,20 @@ int solve_staged_side_by_side(mgwr_batch* bt, const std::vector<int>& staged, co
   // work already queued on the plans' own streams (their inputs, earlier
   // solves) completes before another stream touches their arrays
   for (int i : staged) HIP_TRY(hipStreamSynchronize(bt->plans[i]->stream));
+  // Per-launch event timing stays on the calling thread: a plan's events and
+  // its pending list are not touched by the workers (timing is suspended for
+  // the phase and restored after it; the batch times the phase as a whole).
+  std::vector<char> timed(staged.size(), 0);
+  for (size_t j = 0; j < staged.size(); ++j) {
+    mgwr_plan* pl = bt->plans[staged[j]];
+    if (!pl->pending.empty()) drain_timing(pl);
+    timed[j] = pl->timing ? 1 : 0;
+    pl->timing = false;
+  }
+  const auto t_start = std::chrono::steady_clock::now();
   rcs.assign(staged.size(), MGWR_OK);
   msgs.assign(staged.size(), std::string());
+  std::vector<mgwr_stats> sts(staged.size());
   std::atomic<int> next(0);
   auto work = [&](int w) {
     const hipError_t e = hipSetDevice(bt->device);
@@ -1696,7 +1863,7 @@ int solve_staged_side_by_side(mgwr_batch* bt, const std::vector<int>& staged, co
         msgs[j] = std::string("hipStreamSynchronize: ") + hipGetErrorString(se);
       }
       rcs[j] = rc;
-      if (stats) stats[i] = si;
+      sts[j] = si;
     }
   };
   std::vector<std::thread> threads;
@@ -1707,6 +1874,28 @@ int solve_staged_side_by_side(mgwr_batch* bt, const std::vector<int>& staged, co
   }
   work(0);
   for (std::thread& t : threads) t.join();
+  const double wall_ms = ms_since(t_start);
+  double flops = 0.0, bytes = 0.0;
+  for (size_t j = 0; j < staged.size(); ++j) {
+    mgwr_plan* pl = bt->plans[staged[j]];
+    pl->timing = timed[j] != 0;
+    if (stats) stats[staged[j]] = sts[j];
+    if (bt->timing) {
+      // one cycle's stages plus one float64 defect of the full system
+      std::vector<Stage> one;
+      append_cycle_stages(pl, 0, -1, one, pl->mixed);
+      double cf = 2.0 * pl->hp.stored * pl->hp.levels[0].N, cb = 3.0 * pl->hp.p.M * pl->hp.levels[0].N * 8.0;
+      for (const Stage& x : one) stage_work(pl, x, cf, cb);
+      flops += cf * sts[j].cycles;
+      bytes += cb * sts[j].cycles;
+    }
+  }
+  if (bt->timing) {
+    bt->tacc.launches[MGWR_K_SIDE] += 1;
+    bt->tacc.ms[MGWR_K_SIDE] += wall_ms;
+    bt->tacc.flops[MGWR_K_SIDE] += flops;
+    bt->tacc.bytes[MGWR_K_SIDE] += bytes;
+  }
   return MGWR_OK;
 }
 

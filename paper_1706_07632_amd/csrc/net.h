@@ -16,6 +16,11 @@ int net_input_channels(const mgwr_net* net);
 int net_out_channels(const mgwr_net* net);
 long long net_capacity(const mgwr_net* net);
 hipStream_t net_stream(const mgwr_net* net);
+// shape checks and the master weights (for loading a weight blob)
+bool net_same_shape(const mgwr_net* net, int layers, const int* channels, int nsignal);
+bool net_is_bound(const mgwr_net* net);
+float* net_params(mgwr_net* net);
+size_t net_param_count(const mgwr_net* net);
 hipError_t launch_gather_slices(const double* b, const int* rows, int nslices, long long N, double scale,
                                 float alpha, float rdiv, float* x, hipStream_t s);
 hipError_t launch_time_interp(const float* y, const int* rows, int nslices, const double* t, const double* g,

@@ -964,4 +964,13 @@ int net_input_channels(const mgwr_net* net) { return net->in_channels(); }
 int net_out_channels(const mgwr_net* net) { return net->ch.back(); }
 long long net_capacity(const mgwr_net* net) { return net->bound ? net->cap : 0; }
 hipStream_t net_stream(const mgwr_net* net) { return net->stream; }
+bool net_same_shape(const mgwr_net* net, int layers, const int* channels, int nsignal) {
+  if (net->L() != layers || net->nsig != nsignal) return false;
+  for (int l = 0; l <= layers; ++l)
+    if (net->ch[l] != channels[l]) return false;
+  return true;
+}
+bool net_is_bound(const mgwr_net* net) { return net->bound; }
+float* net_params(mgwr_net* net) { return net->params; }
+size_t net_param_count(const mgwr_net* net) { return net->nparam; }
 }  // namespace mgwr

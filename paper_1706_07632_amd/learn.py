@@ -24,7 +24,7 @@ import time
 
 import numpy as np
 
-from . import Net, Plan
+from . import Net, Plan, model_blob
 
 NSLICES = 32
 HIDDEN = 64
@@ -167,9 +167,17 @@ def load(path: str, max_bhw: int):
     return net, meta
 
 
+def blob_for(net, M: int, nslices: int = NSLICES) -> bytes:
+    """The weight blob of `net` (its current master weights and finest-band
+    cut-off) with the slice rows of an M-step mesh."""
+    params = net.params.detach().float().cpu().numpy()
+    return model_blob(net.channels, net.nsignal, slice_rows(M, nslices), getattr(net, "h_min", 0.0), params)
+
+
 def attach(plan, net, nslices: int = NSLICES):
-    """Attach `net` to `plan` for warm-started solves at the plan's slice rows."""
-    plan.set_warm_start(net, slice_rows(plan.M, nslices))
+    """Attach `net` to `plan` for warm-started solves at the plan's slice rows,
+    through the library's weight-blob loader (mgwr_model_load)."""
+    plan.load_model(net, blob_for(net, plan.M, nslices))
 
 
 def main(argv=None):

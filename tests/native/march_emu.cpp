@@ -32,7 +32,7 @@ static void mfma(const double* a, const double* b, double acc[64][4]) {
 
 int main(int argc, char** argv) {
   if (argc < 7) {
-    std::fprintf(stderr, "usage: M alpha r k leaf ncols [level_shift]\n");
+    std::fprintf(stderr, "usage: M alpha r k leaf ncols [eta [cluster]]\n");
     return 2;
   }
   mgwr_params p{};
@@ -46,6 +46,8 @@ int main(int argc, char** argv) {
   p.k = std::atoi(argv[4]);
   p.leaf = std::atoi(argv[5]);
   int ncols = std::atoi(argv[6]);
+  p.eta = argc > 7 ? std::atof(argv[7]) : 1.0;
+  p.cluster = argc > 8 ? std::atoi(argv[8]) : MGWR_CLUSTER_INDEX;
   HostPlan hp;
   std::string e = build_host_plan(p, nullptr, hp);
   if (!e.empty()) {

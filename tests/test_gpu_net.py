@@ -219,13 +219,14 @@ def test_inference_graph_replays_match_eager_inference(dev):
 def test_warm_start_falls_back_on_nan_weights(dev, schedule):
     p = _problem(1, 63, 128, 51)
     ch = learn.channels()
-    params = np.full(N.param_count(ch), np.nan, dtype=np.float32)
-    net = make(ch, 32, params, p.N)
+    net = mg.Net(ch, 32, p.N)
     plan = _plan(p, schedule=schedule)
     f = torch.as_tensor(p.f, dtype=torch.float64, device=dev)
     plan.solve(f, tol=1e-10)
     _, st0 = plan.solve(f, tol=1e-10)   # with the learned cycle count
     learn.attach(plan, net)
+    # non-finite weights written after attaching (a blob with them is refused)
+    net.set_params(np.full(N.param_count(ch), np.nan, dtype=np.float32))
     u, st = plan.solve(f, tol=1e-10, warm_start=True, warm_res0=True)
     assert st["used_warm_start"] == 0 and not np.isfinite(st["warm_res0"])
     assert st["cycles"] == st0["cycles"]
@@ -254,14 +255,17 @@ def test_warm_start_falls_back_on_a_bad_prediction(dev, schedule):
 
 
 @pytest.mark.parametrize("schedule", ["auto", "staged"])
-def test_unchecked_nan_prediction_is_caught_by_the_first_cycles(dev, schedule):
+def test_nan_prediction_is_dropped_without_the_residual_flag(dev, schedule):
+    """The prediction's defect is evaluated whether or not MGWR_WARM_RES0 is
+    given, so a non-finite prediction never reaches the cycles."""
     p = _problem(1, 63, 128, 52)
     ch = learn.channels()
-    net = make(ch, 32, np.full(N.param_count(ch), np.nan, dtype=np.float32), p.N)
+    net = mg.Net(ch, 32, p.N)
     plan = _plan(p, schedule=schedule)
     learn.attach(plan, net)
+    net.set_params(np.full(N.param_count(ch), np.nan, dtype=np.float32))
     f = torch.as_tensor(p.f, dtype=torch.float64, device=dev)
-    u, st = plan.solve(f, tol=1e-10, warm_start=True)    # the prediction's defect is not evaluated
+    u, st = plan.solve(f, tol=1e-10, warm_start=True)
     assert st["used_warm_start"] == 0 and np.isnan(st["warm_res0"])
     assert st["res"] <= 1e-10 * st["bnorm"] and np.isfinite(u.cpu().numpy()).all()
 
@@ -339,3 +343,70 @@ def test_learned_gain_small(dev):
               f"{np.median([r[3] for r in rows]):.3e}", flush=True)
     # training on solver output makes the prediction of unseen solutions better
     assert loss_after < 0.5 * loss_before
+    # and it saves cycles on them against the zero iterate, every prediction
+    # accepted by the float64 residual judge
+    assert sum(r[2] for r in after) == len(after)
+    assert sum(r[1] for r in after) < sum(r[0] for r in after), after
+
+
+def test_model_blob_loads_through_the_library(dev):
+    """mgwr_model_load: a blob with the network's weights gives the same
+    warm-started solve as weights set directly; a corrupt or mismatched blob
+    is refused with MGWR_ERR_MODEL and the plan keeps its network."""
+    p = _problem(1, 63, 128, 45)
+    ch = learn.channels()
+    params = bf16_params(ch, 46, scale=0.5)
+    rows = learn.slice_rows(p.M)
+    f = torch.as_tensor(p.f, dtype=torch.float64, device=dev)
+    net_a = make(ch, 32, params, p.N)
+    plan_a = _plan(p)
+    plan_a.set_warm_start(net_a, rows)
+    ua, sa = plan_a.solve(f, tol=1e-10, warm_start=True)
+    net_b = mg.Net(ch, 32, p.N)                   # different initial weights
+    plan_b = _plan(p)
+    blob = mg.model_blob(ch, 32, rows, 0.0, params)
+    plan_b.load_model(net_b, blob)
+    ub, sb = plan_b.solve(f, tol=1e-10, warm_start=True)
+    assert sa["warm_res0"] == sb["warm_res0"] and sa["cycles"] == sb["cycles"]
+    assert torch.equal(ua, ub)
+    bad = bytearray(blob)
+    bad[200] ^= 0xFF
+    for broken, other_net in ((bytes(bad), net_b), (b"", net_b), (mg.model_blob([35, 16, 32], 32, rows, 0.0,
+                               np.zeros(N.param_count([35, 16, 32]), np.float32)), net_b)):
+        with pytest.raises(mg.MgwrError) as ei:
+            plan_b.load_model(other_net, broken)
+        assert ei.value.code == mg.MGWR_ERR_MODEL
+    # still the loaded network: the same prediction bit for bit (the solve from
+    # it now runs with the cycle count the first one learned)
+    uc, sc = plan_b.solve(f, tol=1e-10, warm_start=True)
+    assert sc["warm_res0"] == sb["warm_res0"] and sc["used_warm_start"] == 1
+    assert float((uc - ub).abs().max()) <= 1e-9 * float(ub.abs().max())
+
+
+@pytest.mark.parametrize("schedule", ["pipelined", "staged"])
+def test_plausible_but_poor_network_is_rejected(dev, schedule):
+    """Moderate constant last-layer biases: a finite, smooth-looking
+    prediction several times larger than the solution.  After its first
+    cycles the residual is well above what the zero iterate reaches in as
+    many cycles, so the judge drops it (used_warm_start 0) and the solve still
+    meets the tolerance, the oracle confirming the result."""
+    p = _problem(1, 63, 128, 62)
+    ch = learn.channels()
+    params = np.zeros(N.param_count(ch), dtype=np.float32)
+    params[-ch[-1]:] = 4.0
+    net = mg.Net(ch, 32, p.N)
+    plan = _plan(p, schedule=schedule)
+    f = torch.as_tensor(p.f, dtype=torch.float64, device=dev)
+    plan.solve(f, tol=1e-10)                          # the zero iterate's rate for the judge
+    _, st0 = plan.solve(f, tol=1e-10)
+    learn.attach(plan, net)
+    net.set_params(params)
+    u, st = plan.solve(f, tol=1e-10, warm_start=True)
+    first = st["history"][0] / st["bnorm"] if st["history"] else float("nan")
+    print(f"{schedule}: warm res0/||b|| {st['warm_res0'] / st['bnorm']:.3e}, first recorded step "
+          f"{first:.3e}, zero-start rate {st0['avg_factor']:.3f}, cycles {st['cycles']} vs {st0['cycles']}", flush=True)
+    assert np.isfinite(st["warm_res0"]) and st["used_warm_start"] == 0
+    assert st["res"] <= 1e-10 * st["bnorm"]
+    b = oracle.rhs(p.f, p.t, p.alpha, None)
+    r = oracle.residual(plan.export_dense(), u.cpu().numpy(), b, p.dim, p.n, p.length)
+    assert np.abs(r).max() <= 1.5e-10 * np.abs(b).max()

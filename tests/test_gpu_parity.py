@@ -429,3 +429,53 @@ def test_degenerate_sizes(dev, schedule, dim, n, M, precision):
     err, res, st = _solve_and_compare(p, dev, g=rng.standard_normal(N), schedule=schedule, precision=precision,
                                       tol=1e-11)
     assert err < 1e-9 and res < 1e-10, (err, res, st)
+
+
+@pytest.mark.parametrize("dim,n,M,alpha,r,k", [(1, 63, 300, 0.4, 4.0, 8), (2, 31, 128, 0.6, 3.0, 10),
+                                               (1, 1, 17, 0.5, 1.0, 4), (2, 15, 2048, 0.3, 17 / 3, 10)])
+def test_apply_A_matches_oracle(dev, dim, n, M, alpha, r, k):
+    """mgwr_apply_A: the float64 space-time operator (R~ in time plus the
+    stencil) on a random iterate against the oracle's (Rt (x) I + I (x) A_h) U."""
+    print(f"apply_A dim={dim} n={n} M={M}", flush=True)
+    t = W.graded_mesh(M, 1.0, r)
+    plan = mg.Plan(dim, n, M, alpha, k=k, t=t).bind()
+    rng = np.random.default_rng([3, dim, n, M])
+    U = rng.standard_normal((M, n ** dim))
+    out = plan.apply_A(_cuda(U, dev)).cpu().numpy()
+    Rt = oracle.hmatrix_dense(t, alpha, k)
+    ref = -oracle.residual(Rt, U, np.zeros_like(U), dim, n, 1.0)
+    assert np.max(np.abs(out - ref)) <= 1e-13 * np.max(np.abs(ref))
+    x = _cuda(U, dev)
+    rc = mg.lib().mgwr_apply_A(plan._h, mg.ctypes.c_void_p(x.data_ptr()), mg.ctypes.c_void_p(x.data_ptr()))
+    assert rc == mg.MGWR_ERR_INVALID_ARG       # in place is refused
+
+
+@pytest.mark.parametrize("schedule", ["staged", "pipelined"])
+@pytest.mark.parametrize("dim,n,M,alpha,r,eta,cluster", [
+    (1, 63, 512, 0.5, 3.0, 2.0, "index"), (1, 63, 300, 0.3, 17 / 3, 1.0, "geometric"),
+    (2, 31, 256, 0.6, 3.0, 2.0, "geometric"), (2, 15, 128, 0.4, 4.0, 0.5, "index")])
+def test_eta_and_geometric_clusters_solve_against_oracle(dev, schedule, dim, n, M, alpha, r, eta, cluster):
+    """The general admissibility parameter and the geometric cluster tree
+    change R~ (and with it the packed program: leaf sizes, far-field stacks,
+    accumulator slots); the solve still matches the oracle built with the same
+    choices to 1e-10."""
+    print(f"eta={eta} cluster={cluster} dim={dim} n={n} M={M} {schedule}", flush=True)
+    p = W.manufactured(dim, n, M, alpha, r=r, k=10)
+    plan = mg.Plan(dim, n, M, alpha, k=10, t=p.t, eta=eta, cluster=cluster, schedule=schedule).bind()
+    rng = np.random.default_rng([17, dim, n, M])
+    F = rng.standard_normal((M, p.N))
+    u, st = plan.solve(_cuda(F, dev), tol=1e-12)
+    Rt = oracle.hmatrix_dense(p.t, alpha, 10, 16, eta=eta, cluster=cluster)
+    ref = oracle.timestep_solve(Rt, F, dim, n, 1.0)
+    U = u.cpu().numpy()
+    assert np.max(np.abs(U - ref)) <= 1e-10 * np.max(np.abs(ref)), st
+    res = np.max(np.abs(oracle.residual(Rt, U, F, dim, n, 1.0))) / np.max(np.abs(F))
+    assert res <= 1.2e-12 + 1e-13
+
+
+def test_stats_report_setup_and_solve_times(dev):
+    p = W.config("small1d")
+    plan = _plan(p, dev)
+    u, st = plan.solve(_cuda(p.f, dev), tol=1e-10)
+    assert st["setup_ms"] > 0.0 and st["solve_ms"] > 0.0
+    assert st["solve_ms"] < 60e3 and np.isnan(st["warm_res0"])

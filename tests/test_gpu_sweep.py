@@ -52,15 +52,20 @@ def test_sweep_against_oracle(dev, case):
     f = rng.standard_normal((M, N))
     g = rng.standard_normal(N) if with_g else None
     plan = mg.Plan(dim, n, M, alpha, k=k, t=t, leaf=leaf, nu1=nu1, nu2=nu2, gamma=gamma, schedule=schedule,
-                   precision=precision, max_cycles=120).bind()
+                   precision=precision, max_cycles=160).bind()
     fd = torch.as_tensor(f, dtype=torch.float64, device=dev)
     gd = None if g is None else torch.as_tensor(g, dtype=torch.float64, device=dev)
-    u, st = plan.solve(fd, gd, tol=1e-10)
+    # float64 plans solve to 1e-12 (every grid here has h >= 1/64, whose float64
+    # residual floor lies below 1e-12) and must match the oracle to 1e-10;
+    # mixed plans stop at 1e-10 and match to 1e-8
+    tol = 1e-12 if precision == "fp64" else 1e-10
+    u, st = plan.solve(fd, gd, tol=tol)
     U = u.cpu().numpy()
     Rt = oracle.hmatrix_dense(t, alpha, k, leaf)
     B = oracle.rhs(f, t, alpha, g)
     ref = oracle.timestep_solve(Rt, B, dim, n, 1.0)
     err = np.max(np.abs(U - ref)) / np.max(np.abs(ref))
     res = np.max(np.abs(oracle.residual(Rt, U, B, dim, n, 1.0))) / np.max(np.abs(B))
-    assert res <= 1e-10 * 1.01 and err < 1e-8, (case, err, res, st["cycles"])
+    bound = 1e-10 if precision == "fp64" else 1e-8
+    assert res <= 1.2 * tol + 1e-13 and err < bound, (case, err, res, st["cycles"])
     plan.close()

@@ -20,7 +20,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared_functions():
     text = open(os.path.join(ROOT, "include", "mgwr.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(mgwr_[a-z_0-9]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(mgwr_[A-Za-z_0-9]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -47,6 +47,9 @@ def test_library_exports_every_declared_symbol():
     (dict(precision="mixed", inner_cycles=0), "inner_cycles"),
     (dict(precision="mixed", inner_cycles=17), "inner_cycles"),
     (dict(precision="mixed_bf16", inner_cycles=0), "inner_cycles"),
+    (dict(eta=0.0), "eta"),
+    (dict(eta=-1.0), "eta"),
+    (dict(eta=float("inf")), "eta"),
 ])
 def test_invalid_parameters_are_rejected(kw, msg):
     args = dict(dim=1, n=31, M=64, alpha=0.5, k=8, r=2.0)
@@ -127,7 +130,99 @@ def test_workspace_grows_with_grid():
     assert b > 3 * a
 
 
-@pytest.mark.parametrize("args", ["128 0.5 3 8 16 40", "4096 0.5 3 10 16 20", "2048 0.2 9 10 16 16",
+@pytest.mark.parametrize("M,alpha,r,k,eta,cluster", [
+    (512, 0.5, 3.0, 8, 2.0, "index"), (512, 0.5, 3.0, 8, 0.5, "index"), (1024, 0.3, 17 / 3, 10, 1.0, "geometric"),
+    (300, 0.7, 1 / 0.7, 6, 2.0, "geometric"), (256, 0.5, 1.0, 8, 1.0, "geometric"),
+])
+def test_packed_hmatrix_matches_oracle_for_eta_and_geometric_clusters(M, alpha, r, k, eta, cluster):
+    """The general admissibility parameter and the geometric cluster tree in
+    the library's host setup against the oracle's independent construction."""
+    t = W.graded_mesh(M, 1.0, r)
+    plan = mg.Plan(1, 15, M, alpha, k=k, t=t, eta=eta, cluster=cluster)
+    Rt_or = oracle.hmatrix_dense(t, alpha, k, 16, eta=eta, cluster=cluster)
+    assert np.max(np.abs(plan.export_dense() - Rt_or)) <= 1e-13 * np.max(np.abs(np.diag(Rt_or)))
+    parts = oracle.block_partition(t, 16, eta, cluster)
+    info = plan.info()
+    assert info["ndense"] == sum(1 for kind, _, _ in parts if kind == "full")
+    assert info["nrk"] == sum(1 for kind, _, _ in parts if kind == "rk")
+
+
+def test_unknown_cluster_rule_rejected():
+    p = mg.Params()
+    mg.lib().mgwr_params_default(mg.ctypes.byref(p))
+    p.cluster = 7
+    h = mg.ctypes.c_void_p()
+    assert mg.lib().mgwr_plan_create(mg.ctypes.byref(p), None, mg.ctypes.byref(h)) == mg.MGWR_ERR_INVALID_ARG
+    assert "cluster" in mg.lib().mgwr_last_error().decode()
+
+
+def _blob(seed=0, layers=(35, 8, 32), rows=None):
+    rng = np.random.default_rng(seed)
+    n = sum(co * ci * 9 + co for ci, co in zip(layers[:-1], layers[1:]))
+    rows = list(range(3, 99, 3)) if rows is None else rows
+    return mg.model_blob(layers, 32, rows[:32], 1.0 / 128, rng.standard_normal(n).astype(np.float32)), n
+
+
+def test_model_blob_is_read_back():
+    blob, n = _blob()
+    info = mg.describe_model(blob)
+    assert info["layers"] == 2 and info["channels"] == [35, 8, 32] and info["nsignal"] == 32
+    assert info["nslices"] == 32 and info["rows"][:3] == [3, 6, 9] and info["nparam"] == n
+    assert info["h_min"] == 1.0 / 128
+
+
+def _corrupt(blob, where, value):
+    b = bytearray(blob)
+    b[where] = value
+    return bytes(b)
+
+
+@pytest.mark.parametrize("case", ["empty", "none", "magic", "version", "truncated", "extra", "checksum",
+                                  "nan_weight", "bad_rows", "bad_count"])
+def test_missing_or_corrupt_model_is_rejected(case):
+    """mgwr_model_describe (host only) returns MGWR_ERR_MODEL for every
+    missing or corrupt blob; the same parser guards mgwr_model_load."""
+    import struct
+    blob, n = _blob()
+    header = 8 + 4 + 4 + 3 * 4 + 4 + 4 + 32 * 4 + 8 + 8
+    if case == "empty":
+        bad = b""
+    elif case == "none":
+        bad = None
+    elif case == "magic":
+        bad = _corrupt(blob, 0, ord("X"))
+    elif case == "version":
+        bad = _corrupt(blob, 8, 2)
+    elif case == "truncated":
+        bad = blob[:-5]
+    elif case == "extra":
+        bad = blob + b"\0"
+    elif case == "checksum":
+        bad = _corrupt(blob, header + 17, blob[header + 17] ^ 1)
+    elif case == "nan_weight":
+        w = np.frombuffer(blob[header:header + 4 * n], dtype="<f4").copy()
+        w[5] = np.nan
+        body = blob[:header] + w.tobytes()
+        bad = body + struct.pack("<Q", mg._fnv1a64(body))
+    elif case == "bad_rows":
+        bad, _ = _blob(rows=[5] * 40)
+    else:   # parameter count that does not match the shapes
+        body = bytearray(blob[:-8])
+        struct.pack_into("<q", body, header - 8, n + 1)
+        bad = bytes(body) + struct.pack("<Q", mg._fnv1a64(bytes(body)))
+    with pytest.raises(mg.MgwrError) as ei:
+        mg.describe_model(bad)
+    assert ei.value.code == mg.MGWR_ERR_MODEL, case
+
+
+def test_fnv_checksum_matches_published_vectors():
+    """64-bit FNV-1a test vectors (offset basis for the empty string, and "a")."""
+    assert mg._fnv1a64(b"") == 0xcbf29ce484222325
+    assert mg._fnv1a64(b"a") == 0xaf63dc4c8601ec8c
+
+
+@pytest.mark.parametrize("args", ["512 0.5 3 8 16 33 2.0 0", "1024 0.3 5.667 10 16 20 1.0 1",
+                                  "300 0.7 1.857 6 12 17 2.0 1", "128 0.5 3 8 16 40", "4096 0.5 3 10 16 20", "2048 0.2 9 10 16 16",
                                   "300 0.7 1.857 6 12 17", "100 0.5 1 10 7 16"])
 def test_kernel_algorithm_emulated_on_cpu(args):
     """The kernel's per-leaf program (ring of recent leaves, stacked far field,

@@ -84,3 +84,29 @@ def test_mittag_leffler_special_values():
     x = np.linspace(0, 1, 5)
     ref = np.array([math.exp(v * v) * math.erfc(v) for v in x])
     assert np.max(np.abs(oracle.mittag_leffler(0.5, -x) - ref)) < 1e-13
+
+
+def test_sampled_residual_equals_full_residual_on_those_points():
+    """The residual from gathered time lines equals the full residual at the
+    same points (1D and 2D, boundary points included)."""
+    rng = np.random.default_rng(5)
+    for dim, n in ((1, 15), (2, 7)):
+        M = 40
+        t = W.graded_mesh(M, 1.0, 3.0)
+        Rt = oracle.hmatrix_dense(t, 0.4, 6)
+        N = n ** dim
+        U = rng.standard_normal((M, N))
+        B = rng.standard_normal((M, N))
+        h = 1.0 / (n + 1)
+        full = oracle.residual(Rt, U, B, dim, n, 1.0)
+        cols = np.array([0, 1, N // 2, N - 1])
+        nb = []
+        if dim == 1:
+            pairs = [(cols - 1, cols >= 1), (cols + 1, cols + 1 < n)]
+        else:
+            ix, iy = cols % n, cols // n
+            pairs = [(cols - 1, ix > 0), (cols + 1, ix < n - 1), (cols - n, iy > 0), (cols + n, iy < n - 1)]
+        for q, ok in pairs:
+            nb.append(np.where(ok[None, :], U[:, np.where(ok, q, 0)], 0.0))
+        r = oracle.residual_sampled(Rt, B[:, cols], U[:, cols], nb, h)
+        assert np.max(np.abs(r - full[:, cols])) <= 1e-12 * np.max(np.abs(full))

@@ -210,3 +210,29 @@ def test_finest_cutoff_drops_the_fine_bands():
     np.testing.assert_allclose(y, N.prolong(yc, False), atol=1e-14)
     _, g = N.gradient(p, channels, x, rng.standard_normal((1, 2, 1, W)), 2, h, h_min=2 * h)
     assert np.all(np.isfinite(g))
+
+
+def test_warm_start_input_hand_built_case():
+    """A worked example written out by hand: the slice rows of b divided by
+    ||b||_inf, then the constant channels alpha and r/10 (1D: an image of
+    height 1; 2D: row-major [iy][ix] with q = iy n + ix)."""
+    b = np.array([[1.0, 2.0, 3.0],
+                  [-4.0, 5.0, 6.0],
+                  [7.0, 8.0, -9.0],
+                  [2.0, 0.0, 1.0]])
+    x, scale = N.warm_start_input(b, [1, 3], 0.25, 7.0, 1, 3)
+    assert scale == 9.0
+    assert x.shape == (1, 4, 1, 3)
+    assert np.array_equal(x[0, 0, 0], np.array([-4.0, 5.0, 6.0]) / 9.0)
+    assert np.array_equal(x[0, 1, 0], np.array([2.0, 0.0, 1.0]) / 9.0)
+    assert np.all(x[0, 2] == 0.25) and np.all(x[0, 3] == 0.7)
+    # 2D, n = 3: the value at flat index q = 5 lands at (iy, ix) = (1, 2)
+    b2 = np.zeros((2, 9))
+    b2[1, 5] = -2.0
+    b2[0, 0] = 1.0
+    x2, s2 = N.warm_start_input(b2, [1], 0.5, 3.0, 2, 3)
+    assert s2 == 2.0 and x2.shape == (1, 3, 3, 3)
+    want = np.zeros((3, 3))
+    want[1, 2] = -1.0
+    assert np.array_equal(x2[0, 0], want)
+    assert np.all(x2[0, 1] == 0.5) and np.all(x2[0, 2] == 0.3)

@@ -67,7 +67,7 @@ def _timestep_transposed(Rt, B, dim, n, length, m_stop=None):
     return U
 
 
-def _admissible_column_diameter(t, rows, cols):
+def _admissible_column_diameter(t, rows, cols, eta=1.0):
     """Definition 3.1 with the diameter of the column interval I_s instead of I_t."""
     M = len(t) - 1
     m1 = rows.lo + 1
@@ -139,3 +139,48 @@ def test_planted_wrong_mesh_width_fails_single_mode(monkeypatch):
         return true(shift, b, dim, n, h * 1.01, length)
     monkeypatch.setattr(od, "solve_shifted_spatial", wrong)
     assert pins.single_mode_mismatch(1, 31) > 1e-6
+
+
+def _admissible_eta_ignored(t, rows, cols, eta=1.0):
+    """The general condition with eta dropped (Definition 3.1 always)."""
+    M = len(t) - 1
+    m1, m2, j2 = rows.lo + 1, rows.hi, cols.hi
+    if j2 + 1 > M:
+        return False
+    a, d = t[m1], t[j2 + 1]
+    return d < a and (t[m2] - t[m1]) <= (a - d)
+
+
+def _admissible_eta_wrong_side(t, rows, cols, eta=1.0):
+    """eta multiplying the diameter instead of the distance."""
+    M = len(t) - 1
+    m1, m2, j2 = rows.lo + 1, rows.hi, cols.hi
+    if j2 + 1 > M:
+        return False
+    a, d = t[m1], t[j2 + 1]
+    return d < a and eta * (t[m2] - t[m1]) <= (a - d)
+
+
+def _eta_pins():
+    """eta -> 0 keeps R exactly; eta = 2 reaches beyond eta = 1's ratio 1/3
+    while staying within eta / (eta + 2)."""
+    t = pins.W.graded_mesh(200, 1.0, 2.5)
+    R = oracle.l1_matrix(t, 0.6)
+    exact = np.array_equal(oracle.hmatrix_dense(t, 0.6, 6, 16, R=R, eta=1e-12), R)
+    qs = []
+    for kind, rows, cols in oracle.block_partition(t, 16, 2.0):
+        if kind == "rk":
+            a, b, d = t[rows.lo + 1], t[rows.hi], t[cols.hi + 1]
+            qs.append(0.5 * (b - a) / (0.5 * (b - a) + (a - d)))
+    return exact and bool(qs) and 1.0 / 3.0 < max(qs) <= 0.5 * (1 + 1e-12)
+
+
+def test_unmutated_oracle_passes_eta_pins():
+    assert _eta_pins()
+
+
+@pytest.mark.parametrize("fn", [_admissible_eta_ignored, _admissible_eta_wrong_side])
+def test_planted_eta_mistake_fails_a_pin(monkeypatch, fn):
+    monkeypatch.setattr(oh, "admissible", fn)
+    monkeypatch.setattr(oracle, "admissible", fn)
+    assert not _eta_pins()
