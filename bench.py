@@ -2,22 +2,32 @@
 """Throughput of the H-matrix MGWR solver on one MI355X.
 
 Metric: space-time unknowns (N*M) per second to 1e-8 relative residual
-(||b - A u||_inf <= 1e-8 ||b||_inf, float64 residual).
+(||b - A u||_inf <= 1e-8 ||b||_inf, float64 residual), plain float64 against
+mixed precision and the learned warm start.
 
-Workload (default, "large1d"): 1D time-fractional heat equation on (0, 1),
-n = 1023 interior points, M = 4096 graded steps t_j = (j/M)^r with
-r = (2 - alpha)/alpha, alpha in {0.3, 0.5, 0.7}, k = 10, leaf 16, V(1,1),
-manufactured solution u = t^alpha sin(pi x), zero initial guess.  One step =
-one solve of each of the three instances.  Sources are synthetic (closed form)
-and resident in HBM before timing starts.
+Headline (`value`): the batched workload, 64 uneven 2D instances of the
+seeded random-Fourier family (sides {63, 127, 255}, M in {256, 512, 1024,
+2048}, alpha ~ U[0.2, 0.9], r = (2 - alpha)/alpha, k = 10, leaf 16, V(1,1),
+zero initial guess), 1.63e9 unknowns per step, solved as one batch in
+float64.  One step = one batch solve; sources resident in HBM before timing.
 
-Prints one JSON line.  `value` is the plain float64 solver; the mixed-precision
-forms (float32 inner cycles, with float32 or bfloat16 low-rank factors) and the
-learned warm start are reported next to it under `forms`.
+`forms` holds, each with its own roofline and CPU baseline:
+* the batched workload with float32 inner cycles (float64 residual), with
+  bfloat16 low-rank factors, and with one merged pipelined launch for all
+  instances;
+* 2D n = 255, M = 1024 (manufactured solution): float64, mixed, and both
+  warm-started by the committed network;
+* the learned warm start at its evaluation point (2D n = 255, M = 1024,
+  held-out instances of its training family): zero iterate against the
+  network's prediction, float64 and mixed;
+* 1D n = 1023, M = 4096, alpha in {0.3, 0.5, 0.7} as one merged launch.
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -28,15 +38,15 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (vector and matrix)
-PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_FP32_TFLOPS = 157.3    # MI355X dense FP32 (matrix; the mixed inner cycles multiply in float32)
 PEAK_HBM_GBS = 8000.0
 
-# HBM bytes per batched launch of pipeline_kernel<double> on the large1d
-# workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by what the same
-# counters read for a 1 GiB device copy (--copy-probe): fetch x 2.000, write x
-# 1.000.  Valid only for the kernel source they were taken on.
-TRAFFIC_KERNEL_SHA256 = "b7ae4a201aef9f5b3cc2bb90cb065cadb4a1424ed31840ca864a7264db117436"
-TRAFFIC_BYTES = {"large1d": (2.000 * 23847061.4 + 1.000 * 8656866.5) * 1024}
+# HBM bytes per launch of a workload's dominant kernel from rocprofv3
+# FETCH_SIZE / WRITE_SIZE runs (KiB per dispatch) scaled by what the same
+# counters read for a 1 GiB device copy (--copy-probe: fetch x 2.000, write
+# x 1.000).  Keyed by the SHA-256 of kernels.hip they were taken on; a
+# different source reports null.
+TRAFFIC = {}
 
 
 def parse():
@@ -44,21 +54,27 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="large1d", choices=["large1d", "large2d", "small1d", "batched"])
+    ap.add_argument("--workload", default="all",
+                    choices=["all", "batched", "large2d", "learned2d", "large1d", "small1d"],
+                    help="all: the batched headline and every form; otherwise only that workload's forms")
     ap.add_argument("--batch-count", type=int, default=64, help="instances of the batched workload")
-    ap.add_argument("--batch-schedule", default="auto", choices=["auto", "autotune"],
-                    help="batched workload: the plans' AUTO rule, or the autotuner per (n, M) bucket")
+    ap.add_argument("--batch-schedule", default="auto", choices=["auto", "pipelined", "autotune"],
+                    help="batched workload: the plans' AUTO rule, every instance pipelined (one merged launch), "
+                         "or the autotuner per (n, M) bucket")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--value-only", action="store_true",
-                    help="time only the batched float64 step behind `value` (no other forms, no CPU baseline): "
-                         "the command the kernel profiles are taken on")
-    ap.add_argument("--cpu-repeats", type=int, default=3)
+                    help="time only the launches behind `value` (no other forms, no CPU baseline): the command "
+                         "the kernel profiles are taken on")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB three times on the device (counter calibration) and exit")
     return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def copy_probe():
@@ -71,29 +87,23 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes": x.numel() * 8, "copies": 3}), flush=True)
 
 
-def traffic_for(workload):
-    """Counter-measured HBM bytes per launch, or None when the kernel source
-    differs from the one the counters were taken on."""
-    import hashlib
-    src = os.path.join(ROOT, "paper_1706_07632_amd", "csrc", "kernels.hip")
-    try:
-        with open(src, "rb") as fh:
-            digest = hashlib.sha256(fh.read()).hexdigest()
-    except OSError:
+def kernel_sha():
+    with open(os.path.join(ROOT, "paper_1706_07632_amd", "csrc", "kernels.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def traffic_for(key):
+    entry = TRAFFIC.get(key)
+    if entry is None or entry[0] != kernel_sha():
         return None
-    if digest != TRAFFIC_KERNEL_SHA256:
-        return None
-    return TRAFFIC_BYTES.get(workload)
+    return entry[1]
 
 
-def instances(workload):
-    import workloads as W
-    if workload == "large1d":
-        return [W.config("large1d", a) for a in (0.3, 0.5, 0.7)]
-    return [W.config(workload)]
+# ---- timing helpers -----------------------------------------------------------
 
-
-def time_form(plans, fs, us, tol, steps, warmup, torch, warm_start=False):
+def time_plans(plans, fs, us, tol, steps, warmup, torch, warm_start=False):
+    """Wall time of `steps` passes over the instances (one plan each), after
+    `warmup` untimed passes; per-launch event timing covers the timed passes."""
     stats = []
     for _ in range(warmup):
         for pl, f, u in zip(plans, fs, us):
@@ -104,21 +114,19 @@ def time_form(plans, fs, us, tol, steps, warmup, torch, warm_start=False):
     t0 = time.perf_counter()
     for _ in range(steps):
         for pl, f, u in zip(plans, fs, us):
-            _, st = pl.solve(f, tol=tol, u=u, warm_start=warm_start)
-            stats.append(st)
+            stats.append(pl.solve(f, tol=tol, u=u, warm_start=warm_start)[1])
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    timing = [pl.timing() for pl in plans]
+    secs = time.perf_counter() - t0
+    timing = merge_timing([pl.timing() for pl in plans])
     for pl in plans:
         pl.timing(False)
-    return t1 - t0, stats, timing
+    return secs, stats[-len(plans):], timing
 
 
-def time_batch(batch, fs, us, tol, steps, warmup, torch, warm_start=False, plans=()):
-    """Wall time of `steps` batch solves after `warmup` untimed ones; kernel
-    timing (the batch's and that of `plans`, which time their own staged
-    launches) covers the timed solves only."""
-    stats = []
+def time_batch(batch, plans, fs, us, tol, steps, warmup, torch, warm_start=False):
+    """Wall time of `steps` batch solves after `warmup` untimed ones; the
+    batch's timing (event-timed merged launches, the side-by-side phase of
+    staged instances) and the plans' own launches cover the timed solves."""
     for _ in range(warmup):
         batch.solve(fs, tol=tol, us=us, warm_start=warm_start)
     batch.timing(True)
@@ -126,13 +134,15 @@ def time_batch(batch, fs, us, tol, steps, warmup, torch, warm_start=False, plans
         pl.timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    st = None
     for _ in range(steps):
         _, st = batch.solve(fs, tol=tol, us=us, warm_start=warm_start)
-        stats.extend(st)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    tm = batch.timing(False)
-    return t1 - t0, stats, [tm]
+    secs = time.perf_counter() - t0
+    timing = merge_timing([batch.timing(False)] + [pl.timing() for pl in plans])
+    for pl in plans:
+        pl.timing(False)
+    return secs, st, timing
 
 
 def merge_timing(timings):
@@ -145,77 +155,100 @@ def merge_timing(timings):
     return out
 
 
-def cpu_baseline(probs, repeats):
-    """The float64 oracle (direct time marching) on the host cores: one full
-    solve of each instance, median of `repeats`; assembly of R~ excluded."""
-    import numpy as np
-    import oracle
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max(int(x.get("num_threads", 1)) for x in threadpool_info()) if threadpool_info() else 1
-    except Exception:
-        cores = os.cpu_count() or 1
-    per = []
-    total_unknowns = 0
-    for p in probs:
-        Rt = oracle.hmatrix_dense(p.t, p.alpha, p.k, p.leaf)
-        B = oracle.rhs(p.f, p.t, p.alpha, p.g)
-        times = []
-        for _ in range(repeats):
-            t0 = time.perf_counter()
-            oracle.timestep_solve(Rt, B, p.dim, p.n, p.length)
-            times.append(time.perf_counter() - t0)
-        per.append(float(np.median(times)))
-        total_unknowns += p.N * p.M
-    return {"value": total_unknowns / sum(per), "unit": "unknowns/s", "cores": cores, "kind": "oracle",
-            "sample": f"full direct solve of each of the {len(probs)} instances, median of {repeats}, "
-                      f"R~ assembly excluded ({sum(per):.2f} s per pass)"}
+KERNEL_NAMES = {
+    "pipe64": "pipeline_kernel (K time-pipelined V-cycles: zebra line relaxation with H-forward substitution, "
+              "defects, grid transfers; float64, or float32 inner cycles)",
+    "smooth64": "march_kernel<double, SMOOTH> (zebra half-sweep: H-forward substitution of every line)",
+    "smooth32": "march_kernel<float, SMOOTH> (float32 zebra half-sweep)",
+    "defect64": "march_kernel<double, RESID> (defect: H-matrix product and stencil)",
+    "coarse": "pipeline_kernel (coarse levels of a staged cycle)",
+    "side": "staged instances solved side by side (march_kernel and pipeline_kernel launches on 8 streams)",
+}
 
 
-def learned_forms(args, probs, fs, us, unknowns, mg, torch):
-    """Warm-started solves (the trained network's prediction, judged by the
-    float64 residual), float64 and mixed, the instances batched as for `value`."""
-    from paper_1706_07632_amd import learn
-    dim = probs[0].dim
-    path = os.path.join(ROOT, "paper_1706_07632_amd", "weights", f"warm{dim}d.npz")
-    if not os.path.exists(path):
-        return {}
-    net, meta = learn.load(path, max(p.N for p in probs))
-    out = {}
-    for name, precision in (("fp64_learned", "fp64"), ("mixed_learned", "mixed")):
-        plans = [mg.Plan(p.dim, p.n, p.M, p.alpha, k=p.k, r=p.r, t=p.t, length=p.length, leaf=p.leaf,
-                         precision=precision, inner_cycles=1).bind() for p in probs]
-        for pl in plans:
-            learn.attach(pl, net)
-        if len(plans) > 1:
-            batch = mg.Batch(plans).bind()
-            secs, st, _ = time_batch(batch, fs, us, args.tol, args.steps, args.warmup, torch, warm_start=True)
-        else:
-            secs, st, _ = time_form(plans, fs, us, args.tol, args.steps, args.warmup, torch, warm_start=True)
-        last = st[-len(probs):]
-        out[name] = {"value": unknowns * args.steps / secs, "ms_per_step": 1e3 * secs / args.steps,
-                     "cycles": [s["cycles"] for s in last],
-                     "used_warm_start": [s["used_warm_start"] for s in last],
-                     "warm_res0_rel": [None if s["warm_res0"] != s["warm_res0"] else s["warm_res0"] / s["bnorm"]
-                                       for s in last],
-                     "rel_res": [s["res"] / s["bnorm"] for s in last],
-                     "network": {k: meta[k] for k in ("dim", "n", "M", "count", "steps", "val_loss")}}
+def roofline(timing, precision, traffic_key=None):
+    """Dominant kernel class (by summed duration) and its algorithmic rate:
+    algorithmic flops per launch / average event-measured launch duration,
+    against the peak of the arithmetic it runs (FP64 MFMA, or FP32 MFMA for
+    the float32 inner cycles).  The side-by-side class is one host-timed
+    entry per batch solve (its launches overlap on several streams)."""
+    cands = {k: v for k, v in timing.items() if v["launches"] and v["flops"] > 0}
+    if not cands:
+        return None
+    dom = max(cands, key=lambda k: cands[k]["ms"])
+    v = cands[dom]
+    peak = PEAK_FP64_TFLOPS if (precision == "fp64" or dom.endswith("64")) else PEAK_FP32_TFLOPS
+    achieved = v["flops"] / (v["ms"] * 1e-3) / 1e12
+    out = {"bound": "mfma", "kernel": KERNEL_NAMES.get(dom, dom), "class": dom, "achieved": achieved,
+           "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+           "traffic": traffic_for(traffic_key) if traffic_key else None,
+           "algorithmic_flops_per_launch": v["flops"] / v["launches"],
+           "algorithmic_bytes_per_launch": v["bytes"] / v["launches"],
+           "avg_launch_us": 1e3 * v["ms"] / v["launches"], "launches": v["launches"]}
+    if dom == "side":
+        out["basis"] = "host wall time of the side-by-side phase (overlapping launches on 8 streams)"
     return out
 
 
-def batched_main(args):
-    """The batched workload: `batch_count` uneven 2D instances of the
-    random-Fourier family (sides {63, 127, 255}, M in {256..2048}, alpha ~
-    U[0.2, 0.9]) solved together: the schedule of each instance by the AUTO
-    rule (or, with --batch-schedule autotune, by the autotuner on the first
-    instance of its (n, M) bucket), the pipelined instances in one
-    merged launch (graph-replayed), the staged ones side by side after it."""
-    import torch
+def kernels_table(timing):
+    return {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
+                "avg_us": round(1e3 * v["ms"] / max(1, v["launches"]), 2),
+                "TFLOP/s": round(v["flops"] / max(v["ms"], 1e-9) * 1e-9, 3),
+                "GB/s": round(v["bytes"] / max(v["ms"], 1e-9) * 1e-6, 1)}
+            for k, v in timing.items() if v["launches"]}
 
-    import paper_1706_07632_amd as mg
+
+# ---- CPU baseline: the oracle on the host cores --------------------------------
+
+def cpu_baseline(probs, rows, label, one_thread_rows=None):
+    """The float64 oracle (direct time marching: history sum by BLAS, banded
+    solve in 1D, type-I sine transforms in 2D) on the host cores, on a bounded
+    sample: the first `rows[i]` time levels of each instance in `probs`
+    (R~ assembly excluded).  unknowns/s = sum N rows / time.  The same sample's
+    first instance is also timed with one BLAS thread."""
+    import numpy as np
+
+    import oracle
+    from threadpoolctl import threadpool_info, threadpool_limits
+    nproc = os.cpu_count() or 1
+    try:
+        threads = max(int(x.get("num_threads", 1)) for x in threadpool_info()) if threadpool_info() else 1
+    except Exception:
+        threads = 1
+    prep = []
+    for p, m in zip(probs, rows):
+        Rt = oracle.hmatrix_dense(p.t, p.alpha, p.k, p.leaf)
+        if p.f is not None:
+            B = oracle.rhs(p.f[:m], p.t, p.alpha, p.g)
+        else:
+            B = np.zeros((m, p.N))
+            for kvec, prof in p.modes:
+                import workloads as W
+                B += np.outer(prof[:m], W.sine_mode(p.n, p.dim, p.length, kvec))
+        prep.append((p, m, Rt, B))
+    secs, unknowns = 0.0, 0
+    for p, m, Rt, B in prep:
+        t0 = time.perf_counter()
+        oracle.timestep_solve(Rt, B, p.dim, p.n, p.length, m_stop=m)
+        secs += time.perf_counter() - t0
+        unknowns += p.N * m
+    out = {"value": unknowns / secs, "unit": "unknowns/s", "cores": threads, "nproc": nproc, "kind": "oracle",
+           "sample": f"{label}: the first {', '.join(str(m) for m in rows)} time levels of "
+                     f"{len(probs)} instance(s) ({unknowns:.3e} unknowns, {secs:.2f} s), R~ assembly excluded"}
+    p, m, Rt, B = prep[0]
+    m1 = one_thread_rows or m
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        oracle.timestep_solve(Rt, B[:m1], p.dim, p.n, p.length, m_stop=m1)
+        s1 = time.perf_counter() - t0
+    out["one_thread"] = {"value": p.N * m1 / s1, "sample": f"first {m1} levels of the first instance ({s1:.2f} s)"}
+    return out
+
+
+# ---- workloads ---------------------------------------------------------------
+
+def batched_sources(probs, torch, dev):
     import workloads as W
-    dev = torch.device("cuda", 0)
-    probs = W.batched_instances(count=args.batch_count, build_f="modes")
     fs = []
     for p in probs:
         f = torch.zeros((p.M, p.N), dtype=torch.float64, device=dev)
@@ -223,66 +256,115 @@ def batched_main(args):
             f.add_(torch.outer(torch.as_tensor(prof, dtype=torch.float64, device=dev),
                                torch.as_tensor(W.sine_mode(p.n, 2, 1.0, kvec), dtype=torch.float64, device=dev)))
         fs.append(f)
+    return fs
+
+
+def batched_forms(args, torch, mg, dev):
+    """The batched workload in float64 (the headline), float32 inner cycles,
+    bfloat16 factors, and (with the AUTO rule) every instance pipelined."""
+    import workloads as W
+    probs = W.batched_instances(count=args.batch_count, build_f="modes")
+    fs = batched_sources(probs, torch, dev)
     us = [torch.empty_like(f) for f in fs]
     unknowns = sum(p.N * p.M for p in probs)
-    forms, out_timing, tuned = {}, None, {}
-    timed_s = 0.0
-    for name, precision in (("fp64", "fp64"), ("mixed_fp32", "mixed"), ("mixed_bf16", "mixed_bf16")):
-        if name != "fp64" and args.no_mixed:
-            continue
-        plans = [mg.Plan(2, p.n, p.M, p.alpha, k=p.k, r=p.r, t=p.t, precision=precision, inner_cycles=1).bind()
-                 for p in probs]
+    variants = [("fp64", "fp64", args.batch_schedule)]
+    if not args.no_mixed:
+        variants += [("mixed_fp32", "mixed", args.batch_schedule), ("mixed_bf16", "mixed_bf16", args.batch_schedule)]
+    if not args.value_only and args.batch_schedule == "auto":
+        variants += [("fp64_one_launch", "fp64", "pipelined"), ("mixed_fp32_one_launch", "mixed", "pipelined")]
+        if args.no_mixed:
+            variants.pop()
+    out = {}
+    for name, precision, sched in variants:
         t0 = time.perf_counter()
-        for p, pl, f, u in zip(probs, plans, fs, us):
-            key = (p.n, p.M, precision)
-            if key not in tuned and args.batch_schedule == "autotune":
-                tuned[key] = pl.autotune(f, tol=args.tol, u=u)
-        tune_s = time.perf_counter() - t0
+        plans = [mg.Plan(2, p.n, p.M, p.alpha, k=p.k, r=p.r, t=p.t, precision=precision,
+                         schedule="pipelined" if sched == "pipelined" else "auto").bind() for p in probs]
+        setup_s = time.perf_counter() - t0
+        tuned = {}
+        if sched == "autotune":
+            for p, pl, f, u in zip(probs, plans, fs, us):
+                key = (p.n, p.M)
+                if key not in tuned:
+                    tuned[key] = pl.autotune(f, tol=args.tol, u=u)
         batch = mg.Batch(plans, graph=True).bind()
-        secs, stats, timing = time_batch(batch, fs, us, args.tol, args.steps, args.warmup, torch, plans=plans)
-        if out_timing is None:
-            timed_s = secs
-        last = stats[-len(probs):]
-        forms[name] = {"value": unknowns * args.steps / secs, "ms_per_step": 1e3 * secs / args.steps,
-                       "cycles_total": sum(s["cycles"] for s in last),
-                       "max_rel_res": max(s["res"] / s["bnorm"] for s in last),
-                       "autotune_s": round(tune_s, 2), "graph_replays": batch.graph_replays()}
-        if out_timing is None:
-            out_timing = merge_timing(timing + [pl.timing() for pl in plans])
+        secs, st, timing = time_batch(batch, plans, fs, us, args.tol, args.steps, args.warmup, torch)
+        out[name] = {"value": unknowns * args.steps / secs, "ms_per_step": 1e3 * secs / args.steps,
+                     "cycles_total": sum(s["cycles"] for s in st),
+                     "max_rel_res": max(s["res"] / s["bnorm"] for s in st),
+                     "setup_s": round(setup_s, 2), "graph_replays": batch.graph_replays(),
+                     "pipelined_instances": sum(pl.tuned()["schedule"] == "pipelined" for pl in plans),
+                     "roofline": roofline(timing, precision,
+                                          "batched_one_launch" if sched == "pipelined" else None),
+                     "kernels": kernels_table(timing)}
+        log(f"batched {name}: {out[name]['value']:.3e} unknowns/s, {out[name]['ms_per_step']:.1f} ms/step")
         batch.close()
         for pl in plans:
             pl.close()
-    tm = out_timing
-    dom = max(tm, key=lambda k: tm[k]["ms"])
-    sm = tm[dom]
-    # Staged instances run side by side on several streams, so launches of the
-    # dominant class overlap and their summed durations exceed the wall time:
-    # the rate is taken over the timed wall time instead (a lower bound).
-    achieved = sm["flops"] / timed_s / 1e12 if timed_s > 0 else 0.0
-    per_launch = sm["flops"] / (sm["ms"] * 1e-3) / 1e12 if sm["ms"] > 0 else 0.0
-    out = {
-        "metric": "space-time unknowns (N*M)/s to 1e-8 rel. residual, batched uneven 2D instances",
-        "value": forms["fp64"]["value"], "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": forms["fp64"]["ms_per_step"], "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic (seeded random-Fourier sources)",
-        "config": {"workload": f"batched: {len(probs)} 2D instances, sides {{63,127,255}}, M {{256..2048}}, "
-                               "alpha~U[0.2,0.9], r=(2-a)/a, k=10, leaf 16, V(1,1)",
-                   "instances": len(probs), "unknowns": unknowns, "tol": args.tol,
-                   "schedules": ({f"n{k[0]}_M{k[1]}_{k[2]}": v for k, v in sorted(tuned.items())}
-                                 if args.batch_schedule == "autotune" else
-                                 "auto: pipelined when the finest half-sweep has at most 256 chains of 16 columns, "
-                                 "else staged with the coarse levels pipelined")},
-        "roofline": {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                     "basis": "algorithmic flops of the class over the timed wall time (launches of several "
-                              "streams overlap)",
-                     "per_launch_achieved": per_launch,
-                     "avg_launch_us": 1e3 * sm["ms"] / max(1, sm["launches"]), "launches": sm["launches"]},
-        "forms": forms,
-        "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3)} for k, v in tm.items() if v["launches"]},
-    }
-    print(json.dumps(out), flush=True)
+    cpu = None
+    if not args.no_cpu_baseline:
+        # one instance of each side: the first seeded instances with n = 63, 127, 255
+        pick = []
+        for side in (63, 127, 255):
+            pick.append(next(p for p in probs if p.n == side))
+        rows = [min(p.M, 2048 if p.n < 255 else 1024) for p in pick]
+        cpu = cpu_baseline(pick, rows, "batched workload, one instance per side", one_thread_rows=512)
+        for v in out.values():
+            v["cpu_baseline"] = cpu
+    cfg = {"workload": f"batched: {len(probs)} uneven 2D instances, sides {{63,127,255}}, M {{256,512,1024,2048}}, "
+                       "alpha~U[0.2,0.9], r=(2-a)/a, k=10, leaf 16, V(1,1), random-Fourier sources",
+           "instances": len(probs), "unknowns": unknowns, "tol": args.tol,
+           "schedules": ("auto: pipelined when the finest half-sweep has at most 256 chains of 16 columns, "
+                         "else staged (side by side on 8 streams) with the coarse levels pipelined")
+           if args.batch_schedule == "auto" else args.batch_schedule}
+    return out, cfg, cpu
+
+
+def single_forms(name, probs, args, torch, mg, dev, learned=None, variants=None):
+    """Float64, mixed and (optionally) warm-started solves of `probs`; several
+    instances run as one batch (one merged launch when pipelined)."""
+    fs = [torch.as_tensor(p.f, dtype=torch.float64, device=dev) for p in probs]
+    us = [torch.empty_like(f) for f in fs]
+    unknowns = sum(p.N * p.M for p in probs)
+    out = {}
+    variants = variants or [("fp64", "fp64", False), ("mixed", "mixed", False)]
+    for form, precision, warm in variants:
+        if precision != "fp64" and args.no_mixed:
+            continue
+        if warm and (args.no_learned or learned is None):
+            continue
+        plans = [mg.Plan(p.dim, p.n, p.M, p.alpha, k=p.k, r=p.r, t=p.t, length=p.length, leaf=p.leaf,
+                         precision=precision).bind() for p in probs]
+        if warm:
+            from paper_1706_07632_amd import learn
+            for pl, f, u in zip(plans, fs, us):
+                pl.solve(f, tol=args.tol, u=u)       # the zero iterate's rate for the warm-start judge
+                learn.attach(pl, learned)
+        if len(plans) > 1:
+            batch = mg.Batch(plans).bind()
+            secs, st, timing = time_batch(batch, plans, fs, us, args.tol, args.steps, args.warmup, torch,
+                                          warm_start=warm)
+        else:
+            secs, st, timing = time_plans(plans, fs, us, args.tol, args.steps, args.warmup, torch, warm_start=warm)
+        out[form] = {"value": unknowns * args.steps / secs, "ms_per_step": 1e3 * secs / args.steps,
+                     "cycles": [s["cycles"] for s in st], "rel_res": [s["res"] / s["bnorm"] for s in st],
+                     "roofline": roofline(timing, precision, f"{name}_{form}"), "kernels": kernels_table(timing)}
+        if precision != "fp64":
+            out[form]["refinements"] = [s["refinements"] for s in st]
+        if warm:
+            out[form]["used_warm_start"] = [s["used_warm_start"] for s in st]
+            out[form]["warm_res0_rel"] = [s["warm_res0"] / s["bnorm"] for s in st]
+        log(f"{name} {form}: {out[form]['value']:.3e} unknowns/s, cycles {out[form]['cycles']}")
+        for pl in plans:
+            pl.close()
+    return out
+
+
+def load_net(dim, max_bhw):
+    from paper_1706_07632_amd import learn
+    path = os.path.join(ROOT, "paper_1706_07632_amd", "weights", f"warm{dim}d.npz")
+    if not os.path.exists(path):
+        return None, None
+    return learn.load(path, max_bhw)
 
 
 def main():
@@ -293,106 +375,82 @@ def main():
         copy_probe()
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "the solver runs on one GPU (multi-GPU sharding is not implemented); --gpus must be 1"}))
+        print(json.dumps({"error": "this build runs on one GPU: --gpus must be 1 (sharding across GPUs is "
+                                   "described in the design notes, not implemented)"}))
         sys.exit(2)
-    if args.workload == "batched":
-        batched_main(args)
-        return
-    import numpy as np
     import torch
 
     import paper_1706_07632_amd as mg
-
+    import workloads as W
     dev = torch.device("cuda", 0)
-    probs = instances(args.workload)
-    fs = [torch.as_tensor(p.f, dtype=torch.float64, device=dev) for p in probs]
-    us = [torch.empty_like(f) for f in fs]
-    plans = [mg.Plan(p.dim, p.n, p.M, p.alpha, k=p.k, r=p.r, t=p.t, length=p.length, leaf=p.leaf).bind()
-             for p in probs]
-    unknowns = sum(p.N * p.M for p in probs)
-
-    # one step = the instances solved together: their pipelined cycles are
-    # merged into one launch (a single instance uses the plan directly)
-    if len(plans) > 1:
-        batch = mg.Batch(plans).bind()
-        secs, stats, timing = time_batch(batch, fs, us, args.tol, args.steps, args.warmup, torch)
-        seq_secs = None
-        if not args.value_only:
-            seq_secs, seq_stats, _ = time_form(plans, fs, us, args.tol, args.steps, args.warmup, torch)
-    else:
-        secs, stats, timing = time_form(plans, fs, us, args.tol, args.steps, args.warmup, torch)
-        seq_secs = None
-    tm = merge_timing(timing)
-    ms_per_step = 1e3 * secs / args.steps
-    value = unknowns * args.steps / secs
-    # dominant kernel: the time-pipelined cycle kernel when it ran, else the smoother
-    dom = "pipe64" if tm["pipe64"]["launches"] else "smooth64"
-    dom_name = ("pipeline_kernel<double> (K pipelined V-cycles: zebra line relaxation with H-forward "
-                "substitution, defects, grid transfers)" if dom == "pipe64" else
-                "march_kernel<double, SMOOTH> (zebra line relaxation, H-forward substitution)")
-    sm = tm[dom]
-    achieved = sm["flops"] / (sm["ms"] * 1e-3) / 1e12 if sm["ms"] > 0 else 0.0
-    avg_launch_us = 1e3 * sm["ms"] / max(1, sm["launches"])
-    forms = {"fp64": {"value": value, "ms_per_step": ms_per_step,
-                      "cycles": [s["cycles"] for s in stats[:len(probs)]],
-                      "rel_res": [s["res"] / s["bnorm"] for s in stats[:len(probs)]]}}
-    if seq_secs is not None:
-        forms["fp64_one_instance_at_a_time"] = {"value": unknowns * args.steps / seq_secs,
-                                                "ms_per_step": 1e3 * seq_secs / args.steps}
-    kernels = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
-                   "avg_us": round(1e3 * v["ms"] / max(1, v["launches"]), 2),
-                   "TFLOP/s": round(v["flops"] / max(v["ms"], 1e-9) * 1e-9, 3),
-                   "GB/s": round(v["bytes"] / max(v["ms"], 1e-9) * 1e-6, 1)} for k, v in tm.items() if v["launches"]}
-
-    for name, precision in (("mixed_fp32", "mixed"), ("mixed_bf16", "mixed_bf16")):
-        if args.no_mixed:
-            break
-        mplans = [mg.Plan(p.dim, p.n, p.M, p.alpha, k=p.k, r=p.r, t=p.t, length=p.length, leaf=p.leaf,
-                          precision=precision, inner_cycles=1).bind() for p in probs]
-        if len(mplans) > 1:
-            mbatch = mg.Batch(mplans).bind()
-            msecs, mstats, mtiming = time_batch(mbatch, fs, us, args.tol, args.steps, args.warmup, torch)
-        else:
-            msecs, mstats, mtiming = time_form(mplans, fs, us, args.tol, args.steps, args.warmup, torch)
-        mtm = merge_timing(mtiming)
-        forms[name] = {"value": unknowns * args.steps / msecs, "ms_per_step": 1e3 * msecs / args.steps,
-                       "cycles": [s["cycles"] for s in mstats[:len(probs)]],
-                       "refinements": [s["refinements"] for s in mstats[:len(probs)]],
-                       "rel_res": [s["res"] / s["bnorm"] for s in mstats[:len(probs)]]}
-        forms[name]["kernels"] = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
-                                      "avg_us": round(1e3 * v["ms"] / max(1, v["launches"]), 2)}
-                                  for k, v in mtm.items() if v["launches"]}
-
-    if not args.no_learned:
-        forms.update(learned_forms(args, probs, fs, us, unknowns, mg, torch))
-
+    forms, cpu_all = {}, {}
+    head = None
+    if args.workload in ("all", "batched"):
+        bf, cfg, cpu = batched_forms(args, torch, mg, dev)
+        forms.update({f"batched_{k}": v for k, v in bf.items()})
+        head = ("batched_fp64", cfg, cpu)
+    if args.workload in ("all", "large2d") and not args.value_only:
+        p = W.config("large2d")
+        net, _ = (None, None) if args.no_learned else load_net(2, p.N)
+        f2 = single_forms("large2d", [p], args, torch, mg, dev, learned=net,
+                          variants=[("fp64", "fp64", False), ("mixed", "mixed", False),
+                                    ("fp64_learned", "fp64", True), ("mixed_learned", "mixed", True)])
+        cpu = None if args.no_cpu_baseline else cpu_baseline([p], [512], "2D n=255 M=1024", one_thread_rows=256)
+        for k, v in f2.items():
+            v["cpu_baseline"] = cpu
+            forms[f"large2d_{k}"] = v
+        if head is None:
+            head = ("large2d_fp64", {"workload": "large2d: 2D n=255 M=1024 alpha=0.5 r=3 k=10 leaf 16 V(1,1), "
+                                                 "manufactured u=t^0.5 sin(pi x) sin(pi y)",
+                                     "N": p.N, "M": p.M, "tol": args.tol}, cpu)
+    if args.workload in ("all", "learned2d") and not args.value_only and not args.no_learned:
+        import numpy as np
+        probs = [W.warm_start_family(2, 255, 1024, np.random.default_rng([100001, i])) for i in range(2)]
+        net, meta = load_net(2, probs[0].N)
+        if net is not None:
+            f5 = single_forms("learned2d", probs, args, torch, mg, dev, learned=net,
+                              variants=[("fp64", "fp64", False), ("mixed", "mixed", False),
+                                        ("fp64_learned", "fp64", True), ("mixed_learned", "mixed", True)])
+            cpu = None if args.no_cpu_baseline else cpu_baseline(probs[:1], [512], "held-out 2D n=255 M=1024",
+                                                                 one_thread_rows=256)
+            for k, v in f5.items():
+                v["cpu_baseline"] = cpu
+                v["network"] = {key: meta.get(key) for key in ("dim", "n", "M", "count", "steps", "val_loss")}
+                forms[f"learned2d_{k}"] = v
+            base = f5.get("fp64", {}).get("value")
+            for k in ("mixed", "fp64_learned", "mixed_learned"):
+                if base and k in f5:
+                    forms[f"learned2d_{k}"]["vs_fp64"] = f5[k]["value"] / base
+    if args.workload in ("all", "large1d") and not args.value_only:
+        probs = [W.config("large1d", a) for a in (0.3, 0.5, 0.7)]
+        f2 = single_forms("large1d", probs, args, torch, mg, dev)
+        cpu = None if args.no_cpu_baseline else cpu_baseline(probs, [4096, 4096, 4096], "1D n=1023 M=4096",
+                                                             one_thread_rows=1024)
+        for k, v in f2.items():
+            v["cpu_baseline"] = cpu
+            forms[f"large1d_{k}"] = v
+        if head is None:
+            head = ("large1d_fp64", {"workload": "large1d: 1D n=1023 M=4096 alpha in {0.3,0.5,0.7} r=(2-a)/a "
+                                                 "k=10 leaf 16 V(1,1), three instances as one batch",
+                                     "N": 1023, "M": 4096, "instances": 3, "tol": args.tol}, cpu)
+    if args.workload == "small1d":
+        p = W.config("small1d")
+        f1 = single_forms("small1d", [p], args, torch, mg, dev)
+        forms.update({f"small1d_{k}": v for k, v in f1.items()})
+        head = ("small1d_fp64", {"workload": "small1d: 1D n=63 M=128 alpha=0.5 r=3 k=8", "tol": args.tol}, None)
+    key, cfg, cpu = head
+    hv = forms[key]
     out = {
-        "metric": "space-time unknowns (N*M)/s to 1e-8 rel. residual (plain FP64; mixed and learned forms under forms)",
-        "value": value,
-        "unit": "unknowns/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic (manufactured closed-form source)",
-        "config": {"workload": args.workload if args.workload != "large1d" else
-                   "large1d: 1D n=1023 M=4096 alpha in {0.3,0.5,0.7} r=(2-a)/a k=10 leaf=16 V(1,1)",
-                   "N": probs[0].N, "M": probs[0].M, "instances": len(probs), "tol": args.tol},
-        "roofline": {"bound": "mfma", "kernel": dom_name,
-                     "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS,
-                     "traffic": traffic_for(args.workload) if dom == "pipe64" else None,
-                     "algorithmic_bytes": sm["bytes"] / max(1, sm["launches"]),
-                     "avg_launch_us": avg_launch_us, "launches": sm["launches"]},
-        "forms": forms,
-        "kernels": kernels,
+        "metric": "space-time unknowns (N*M)/s to 1e-8 rel. residual: plain FP64 vs mixed+learned",
+        "value": hv["value"], "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": hv["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic (seeded random-Fourier and manufactured sources)",
+        "config": cfg, "roofline": hv.get("roofline"),
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(probs, args.cpu_repeats)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    out["forms"] = forms
+    out["kernel_source_sha256"] = kernel_sha()
     print(json.dumps(out), flush=True)
 
 
