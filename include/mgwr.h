@@ -425,6 +425,28 @@ int mgwr_plan_export_dense(const mgwr_plan* plan, double* Rt_host);
  * to exercise this path).  A batch uses the smallest bound of its plans. */
 int mgwr_plan_set_progress_limit(mgwr_plan* plan, unsigned polls);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): mgwr_solve
+ * with the library's own static device array as the plan's workspace, so
+ * that neither the library nor the caller allocates.  The caller passes the
+ * inputs and outputs as for mgwr_solve (f_dev, g_dev, u_dev on the current
+ * device) and the stream (hipStream_t or NULL).  The plan needs no binding of
+ * its own; each call copies the plan's packed H-matrix into the array (one
+ * host-to-device copy), solves, synchronises `stream`, and then points the
+ * plan back at its own workspace if it had one (which keeps working as
+ * before).  Limits: mgwr_plan_workspace_bytes(plan) must not exceed
+ * MGWR_STATIC_WORKSPACE_BYTES (64 MiB: 1D n = 255, M = 512 needs 7 MiB and
+ * 2D n = 63, M = 512 48 MiB; 1D n = 1023, M = 4096 needs 173 MiB), else
+ * MGWR_ERR_INVALID_ARG; MGWR_WARM_START is refused (MGWR_ERR_INVALID_ARG).
+ * Every call on a device shares that device's one array, which keeps the
+ * last call's contents: calls that overlap on one device (other threads or
+ * streams) race and must be serialised by the caller.  Each device the
+ * library runs on holds its array until the process ends.  Returns what
+ * mgwr_solve returns. */
+#define MGWR_STATIC_WORKSPACE_BYTES (64ull << 20)
+int mgwr_solve_static(mgwr_plan* plan, void* stream, const double* f_dev, const double* g_dev, double tol,
+                      double* u_dev, unsigned flags, mgwr_stats* stats);
+
 /* Release host state.  Never frees caller memory.  Safe on NULL. */
 int mgwr_plan_destroy(mgwr_plan* plan);
 

@@ -39,6 +39,7 @@ EXPORTED = [
     "mgwr_net_adam_step", "mgwr_net_destroy",
     "mgwr_plan_set_warm_start", "mgwr_batch_set_graph", "mgwr_batch_graph_replays", "mgwr_plan_autotune",
     "mgwr_plan_set_staging", "mgwr_plan_tuned", "mgwr_apply_A", "mgwr_model_describe", "mgwr_model_load",
+    "mgwr_solve_static",
 ]
 
 KERNEL_CLASSES = ["smooth64", "defect64", "smooth32", "defect32", "restrict", "prolong", "pipe64", "coarse", "side"]
@@ -158,6 +159,7 @@ def lib():
     L.mgwr_net_destroy.argtypes = [vp]
     L.mgwr_plan_set_warm_start.argtypes = [vp, vp, ip, ctypes.POINTER(ctypes.c_int)]
     L.mgwr_apply_A.argtypes = [vp, vp, vp]
+    L.mgwr_solve_static.argtypes = [vp, vp, vp, vp, ctypes.c_double, vp, ctypes.c_uint, ctypes.POINTER(Stats)]
     L.mgwr_model_describe.argtypes = [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ModelInfo)]
     L.mgwr_model_load.argtypes = [vp, vp, ctypes.c_char_p, ctypes.c_size_t]
     L.mgwr_last_error.argtypes = []
@@ -308,6 +310,25 @@ class Plan:
         fl = ((MGWR_GUESS_IN_U if guess else 0) | (MGWR_WARM_START if warm_start else 0) |
               (MGWR_WARM_RES0 if warm_res0 else 0))
         rc = lib().mgwr_solve(self._h, _dptr(f), _dptr(g), float(tol), _dptr(u), fl, ctypes.byref(st))
+        _check(rc, ok=(MGWR_OK, MGWR_ERR_NOT_CONVERGED) if allow_unconverged else (MGWR_OK,))
+        return u, st.as_dict()
+
+    def solve_static(self, f, g=None, tol=1e-10, u=None, guess=False, allow_unconverged=False, stream=None):
+        """mgwr_solve with the library's static device array as the workspace
+        (no allocation by the library; the plan need not be bound)."""
+        import torch
+        _require(f, "f", (self.M, self.N))
+        if g is not None:
+            _require(g, "g", (self.N,))
+        if u is None:
+            u = torch.empty((self.M, self.N), dtype=torch.float64, device=f.device)
+        _require(u, "u", (self.M, self.N))
+        if stream is None:
+            stream = torch.cuda.current_stream(f.device)
+        st = Stats()
+        fl = MGWR_GUESS_IN_U if guess else 0
+        rc = lib().mgwr_solve_static(self._h, ctypes.c_void_p(stream.cuda_stream), _dptr(f), _dptr(g), float(tol),
+                                     _dptr(u), fl, ctypes.byref(st))
         _check(rc, ok=(MGWR_OK, MGWR_ERR_NOT_CONVERGED) if allow_unconverged else (MGWR_OK,))
         return u, st.as_dict()
 

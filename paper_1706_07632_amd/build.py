@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libmgwr.so")
 
-SOURCES = ["hplan.cpp", "kernels.hip", "net.hip", "mgwr.cpp"]
+SOURCES = ["hplan.cpp", "kernels.hip", "net.hip", "mgwr.cpp", "noalloc.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

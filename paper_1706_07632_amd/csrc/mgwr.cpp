@@ -21,6 +21,7 @@
 #include "kernels.h"
 #include "mgwr.h"
 #include "net.h"
+#include "plan_internal.h"
 
 using namespace mgwr;
 
@@ -1227,19 +1228,18 @@ int mgwr_plan_workspace_bytes(const mgwr_plan* plan, size_t* bytes) {
   return MGWR_OK;
 }
 
-int mgwr_plan_bind(mgwr_plan* pl, void* ws, size_t bytes, void* stream) {
-  if (!pl || !ws) return fail(MGWR_ERR_INVALID_ARG, "null argument");
-  if (bytes < pl->off.total) return fail(MGWR_ERR_STATE, "workspace too small");
-  if (((uintptr_t)ws & 255) != 0) return fail(MGWR_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
-  const auto t_start = std::chrono::steady_clock::now();
-  HIP_TRY(hipGetDevice(&pl->device));
-  pl->stream = (hipStream_t)stream;
-  pl->ws = (unsigned char*)ws;
+}  // extern "C"
+
+namespace mgwr {
+
+// Points every device array of the plan into the workspace w (no device
+// work); the per-binding caches (uploaded stage images) are reset.
+void assign_pointers(mgwr_plan* pl, unsigned char* w, size_t bytes, hipStream_t stream) {
+  pl->stream = stream;
+  pl->ws = w;
   pl->ws_bytes = bytes;
   const HostPlan& hp = pl->hp;
-  const PackedPlan& pk = hp.pk;
   const auto& o = pl->off;
-  unsigned char* w = pl->ws;
   pl->leaves = (LeafDesc*)(w + o.leaves);
   pl->dn_list = (int*)(w + o.dn_list);
   pl->ff_row = (int*)(w + o.ff_row);
@@ -1280,6 +1280,55 @@ int mgwr_plan_bind(mgwr_plan* pl, void* ws, size_t bytes, void* stream) {
     if (l > 0) { pl->d64.U[l] = (double*)(w + o.U64[l]); pl->d64.F[l] = (double*)(w + o.F64[l]); }
     if (l + 1 < L || l == 0) pl->d64.R[l] = (double*)(w + o.R64[l]);
   }
+  if (pl->mixed) {
+    pl->d32.dense = (float*)(w + o.dense32);
+    pl->d32.dinv = (float*)(w + o.dinv32);
+    pl->d32.ffA = (float*)(w + o.ffA32);
+    pl->d32.zuB = (float*)(w + o.zuB32);
+    pl->d32.lr_bf16 = pl->bf16 ? 1 : 0;
+    pl->d32.U.assign(L, nullptr); pl->d32.F.assign(L, nullptr); pl->d32.R.assign(L, nullptr);
+    for (int l = 0; l < L; ++l) {
+      pl->d32.U[l] = (float*)(w + o.U32[l]);
+      pl->d32.F[l] = (float*)(w + o.F32[l]);
+      if (l + 1 < L) pl->d32.R[l] = (float*)(w + o.R32[l]);
+    }
+  }
+}
+
+PlanBinding plan_binding(const mgwr_plan* pl) {
+  return PlanBinding{pl->bound, pl->device, pl->ws, pl->ws_bytes, pl->stream, pl->net};
+}
+
+void restore_binding(mgwr_plan* pl, const PlanBinding& b) {
+  if (b.bound) assign_pointers(pl, b.ws, b.bytes, b.stream);
+  pl->bound = b.bound;
+  pl->device = b.device;
+  pl->net = b.net;
+  if (!b.net) pl->nslices = 0;
+}
+
+void detach_network(mgwr_plan* pl) {
+  pl->net = nullptr;
+  pl->nslices = 0;
+}
+
+size_t plan_workspace_bytes(const mgwr_plan* pl) { return pl->off.total; }
+
+}  // namespace mgwr
+
+extern "C" {
+
+int mgwr_plan_bind(mgwr_plan* pl, void* ws, size_t bytes, void* stream) {
+  if (!pl || !ws) return fail(MGWR_ERR_INVALID_ARG, "null argument");
+  if (bytes < pl->off.total) return fail(MGWR_ERR_STATE, "workspace too small");
+  if (((uintptr_t)ws & 255) != 0) return fail(MGWR_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  const auto t_start = std::chrono::steady_clock::now();
+  HIP_TRY(hipGetDevice(&pl->device));
+  assign_pointers(pl, (unsigned char*)ws, bytes, (hipStream_t)stream);
+  const HostPlan& hp = pl->hp;
+  const PackedPlan& pk = hp.pk;
+  const auto& o = pl->off;
+  unsigned char* w = pl->ws;
   // one packed host image, one copy
   std::vector<unsigned char> img(o.total > 0 ? std::min(o.total, o.B0) : 0);
   auto put = [&](size_t off, const void* src, size_t n) {
@@ -1301,17 +1350,6 @@ int mgwr_plan_bind(mgwr_plan* pl, void* ws, size_t bytes, void* stream) {
   put(o.zuB64, pk.zuB.data(), pk.zuB.size() * sizeof(double));
   HIP_TRY(hipMemcpyAsync(w, img.data(), img.size(), hipMemcpyHostToDevice, pl->stream));
   if (pl->mixed) {
-    pl->d32.dense = (float*)(w + o.dense32);
-    pl->d32.dinv = (float*)(w + o.dinv32);
-    pl->d32.ffA = (float*)(w + o.ffA32);
-    pl->d32.zuB = (float*)(w + o.zuB32);
-    pl->d32.lr_bf16 = pl->bf16 ? 1 : 0;
-    pl->d32.U.assign(L, nullptr); pl->d32.F.assign(L, nullptr); pl->d32.R.assign(L, nullptr);
-    for (int l = 0; l < L; ++l) {
-      pl->d32.U[l] = (float*)(w + o.U32[l]);
-      pl->d32.F[l] = (float*)(w + o.F32[l]);
-      if (l + 1 < L) pl->d32.R[l] = (float*)(w + o.R32[l]);
-    }
     // float copies are rounded on the device from the float64 image
     HIP_TRY(launch_cast<double, float>(pl->d64.dense, pl->d32.dense, (long long)pk.dense.size(), pl->stream));
     HIP_TRY(launch_cast<double, float>(pl->d64.dinv, pl->d32.dinv, (long long)pk.dinv.size(), pl->stream));
