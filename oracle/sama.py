@@ -94,3 +94,93 @@ def two_grid_factor(n: int, M: int, alpha: float, r: float, length: float = math
         for k in range(1, (n - 1) // 2 + 1):
             rho = max(rho, spectral_radius(two_grid_block(Rm, h, k * math.pi / (n + 1), nu1, nu2)))
     return rho
+
+
+# ---- two space dimensions ------------------------------------------------------
+#
+# Section 5.2's method on n x n points: checkerboard zebra relaxation ((i + j)
+# even, 1-based, first: the coarse points (both indices even) are among
+# them), 9-point full weighting, bilinear interpolation, R + A_{2h} on the
+# coarse grid.  For a frequency pair k1, k2 <= (n-1)/2 with
+# s(i, j) = sin(k1 pi i/(n+1)) sin(k2 pi j/(n+1)), the four harmonics
+# (k1 or n+1-k1, k2 or n+1-k2) span the same space as the red and black
+# parts of e = s and of f = (-1)^(i+1) s.  With c_d = cos(k_d pi/(n+1)),
+# D = R + (4/h^2) I, gamma_e = 2 (c1 + c2)/h^2, gamma_f = 2 (c2 - c1)/h^2
+# (the 5-point stencil sums the neighbours of s to 2 (c1 + c2) s and those of
+# f to 2 (c2 - c1) f, each neighbour lying in the other colour):
+#   A = diag([[D, -g_e I], [-g_e I, D]], [[D, -g_f I], [-g_f I, D]]) on
+#       (a, b, p, q) = coefficients of (e_R, e_B, f_R, f_B);
+#   smoothing step: a' = g_e D^-1 b, p' = g_f D^-1 q, then b' = g_e D^-1 a',
+#       q' = g_f D^-1 p';
+#   interpolation: e_c -> e_c ((1 + c1 c2)/2, (c1 + c2)/2, (c1 c2 - 1)/2, (c1 - c2)/2)
+#       (coarse points carry e_c s, the other points the bilinear averages
+#       c1 e_c s, c2 e_c s, c1 c2 e_c s);
+#   restriction: half the transpose of the interpolation (9-point weights
+#       (1/16)[1 2 1; 2 4 2; 1 2 1] applied to the four parts);
+#   coarse operator: R + ((sin^2(k1 pi/(n+1)) + sin^2(k2 pi/(n+1)))/h^2) I.
+# Frequencies with k1 or k2 = (n+1)/2 have no coarse representation (the
+# restriction of their residual vanishes): one of them with the other index
+# k <= (n-1)/2 spans the red and black parts of s, coupled through
+# gamma = 2 cos(k pi/(n+1))/h^2 alone, and only the smoother acts on it; both
+# indices (n+1)/2 leave a red-only mode that one half-sweep removes.
+
+def two_grid_block_2d(R: np.ndarray, h: float, theta1: float, theta2: float, nu1: int = 1,
+                      nu2: int = 0) -> np.ndarray:
+    """4M x 4M two-grid error propagation on the harmonics of (theta1,
+    theta2), theta_d = k_d pi/(n+1), k_d = 1..(n-1)/2."""
+    M = R.shape[0]
+    I = np.eye(M)
+    Z = np.zeros((M, M))
+    c1, c2 = math.cos(theta1), math.cos(theta2)
+    D = R + (4.0 / (h * h)) * I
+    Dinv = np.linalg.inv(D)
+    ge, gf = 2.0 * (c1 + c2) / (h * h), 2.0 * (c2 - c1) / (h * h)
+    A = np.block([[D, -ge * I, Z, Z], [-ge * I, D, Z, Z], [Z, Z, D, -gf * I], [Z, Z, -gf * I, D]])
+    S = np.block([[Z, ge * Dinv, Z, Z], [Z, ge * ge * Dinv @ Dinv, Z, Z],
+                  [Z, Z, Z, gf * Dinv], [Z, Z, Z, gf * gf * Dinv @ Dinv]])
+    w = np.array([(1 + c1 * c2) / 2, (c1 + c2) / 2, (c1 * c2 - 1) / 2, (c1 - c2) / 2])
+    P = np.vstack([wi * I for wi in w])
+    Rfw = 0.5 * P.T
+    Ac = R + ((math.sin(theta1) ** 2 + math.sin(theta2) ** 2) / (h * h)) * I
+    K = np.eye(4 * M) - P @ np.linalg.solve(Ac, Rfw @ A)
+    T = K
+    for _ in range(nu1):
+        T = T @ S
+    for _ in range(nu2):
+        T = S @ T
+    return T
+
+
+def smoother_block_2d(R: np.ndarray, h: float, theta: float, nu: int) -> np.ndarray:
+    """2M x 2M error propagation of nu smoothing steps on a frequency with
+    one index (n+1)/2 (no coarse-grid correction reaches it)."""
+    M = R.shape[0]
+    I = np.eye(M)
+    Z = np.zeros((M, M))
+    D = R + (4.0 / (h * h)) * I
+    Dinv = np.linalg.inv(D)
+    g = 2.0 * math.cos(theta) / (h * h)
+    S = np.block([[Z, g * Dinv], [Z, g * g * Dinv @ Dinv]])
+    return np.linalg.matrix_power(S, nu)
+
+
+def two_grid_factor_2d(n: int, M: int, alpha: float, r: float, length: float = math.pi, T: float = 1.0,
+                       nu1: int = 1, nu2: int = 0, R: np.ndarray | None = None) -> float:
+    """SAMA two-grid factor in two space dimensions (exact in time through
+    the 2 x 2 / 4 x 4 diagonal blocks, as in one dimension)."""
+    if R is None:
+        t = T * (np.arange(M + 1) / M) ** r
+        t[-1] = T
+        R = l1_matrix(t, alpha)
+    h = length / (n + 1)
+    nc = (n - 1) // 2
+    th = [k * math.pi / (n + 1) for k in range(1, nc + 1)]
+    rho = 0.0
+    for sigma in np.unique(np.diag(R)):
+        Rm = np.array([[sigma]])
+        for t1 in th:
+            for t2 in th:
+                rho = max(rho, spectral_radius(two_grid_block_2d(Rm, h, t1, t2, nu1, nu2)))
+            if nu1 + nu2 >= 1:
+                rho = max(rho, spectral_radius(smoother_block_2d(Rm, h, t1, nu1 + nu2)))
+    return rho

@@ -172,3 +172,26 @@ def test_table1_discretisation_error_on_the_gpu(dev):
         err = np.abs(u.cpu().numpy() - exact).max()
         print(f"Table 1 alpha=0.4 M={M}: GPU error {err:.3e}, paper {e_ref:.1e}", flush=True)
         assert abs(err - e_ref) <= 0.08 * e_ref
+
+
+def test_fig8_2d_w_cycle_factors_against_the_two_grid_analysis(dev):
+    """Section 5.2, Figure 8: the asymptotic factor of a W(1,0)-cycle in 2D
+    (delta = 0.4, M = 128, n x n from 7^2 to 127^2) against the two-grid
+    factor of the semi-algebraic mode analysis (oracle/sama.py); the paper
+    reports close agreement (its figure has no printed values)."""
+    alpha, M = 0.4, 128
+    for l in (3, 4, 5, 6, 7):
+        n = 2 ** l - 1
+        p = W.paper_2d_polynomial(n, M, alpha, k=20)
+        plan = mg.Plan(2, n, M, alpha, k=20, t=p.t, length=p.length, nu1=1, nu2=0, gamma=2, max_cycles=60,
+                       schedule="staged").bind()
+        rng = np.random.default_rng([37, l])
+        f = torch.zeros((M, n * n), dtype=torch.float64, device=dev)
+        f[:, (n * n) // 2] = 1.0
+        u = torch.as_tensor(rng.standard_normal((M, n * n)), dtype=torch.float64, device=dev)
+        u, st = plan.solve(f, tol=1e-13, u=u, guess=True)
+        h = st["history"]
+        rho = (h[9] / h[3]) ** (1.0 / 6.0)
+        pred = sama.two_grid_factor_2d(n, M, alpha, (2 - alpha) / alpha)
+        print(f"Figure 8 n={n}: measured W(1,0) factor {rho:.3f}, two-grid analysis {pred:.3f}", flush=True)
+        assert abs(rho - pred) <= 0.03 and rho < 0.3, (n, rho, pred)

@@ -161,3 +161,124 @@ def test_planted_mistake_fails_the_brute_force_identity(monkeypatch, mutant):
     with pytest.raises(AssertionError):
         test_blocks_equal_brute_force_two_grid_matrix(7, 8, 0.5, 3.0, 1, 0)
     monkeypatch.setattr(S, "two_grid_block", true)
+
+
+def _two_grid_matrix_2d(R, n, h, nu1, nu2):
+    """The 2D two-grid error propagation assembled from its definitions on an
+    [n][n][M] error array (checkerboard zebra half-sweeps, (i + j) even
+    first, 1-based; 9-point full weighting; bilinear interpolation; exact
+    solve with R + A_{2h} on the coarse grid)."""
+    M = R.shape[0]
+    nc = (n - 1) // 2
+    D = R + (4.0 / h ** 2) * np.eye(M)
+
+    def nbsum(E, i, j):
+        s = 0.0
+        for di, dj in ((-1, 0), (1, 0), (0, -1), (0, 1)):
+            if 0 <= i + di < n and 0 <= j + dj < n:
+                s = s + E[i + di, j + dj]
+        return s
+
+    def A(E):
+        out = np.einsum("ijm,km->ijk", E, R) + (4.0 / h ** 2) * E
+        for i in range(n):
+            for j in range(n):
+                out[i, j] = out[i, j] - nbsum(E, i, j) / h ** 2
+        return out
+
+    def smooth(E):
+        E = E.copy()
+        for parity in (0, 1):      # (i + j) even (1-based) = (i0 + j0) even (0-based) first
+            for i in range(n):
+                for j in range(n):
+                    if (i + j) % 2 == parity:
+                        E[i, j] = np.linalg.solve(D, nbsum(E, i, j) / h ** 2)
+        return E
+
+    H = 2.0 * h
+    T1 = (2 * np.eye(nc) - np.eye(nc, k=1) - np.eye(nc, k=-1)) / H ** 2
+    Ac = np.kron(np.eye(nc * nc), R) + np.kron(np.kron(np.eye(nc), T1) + np.kron(T1, np.eye(nc)), np.eye(M))
+
+    def cgc(E):
+        r = -A(E)
+        rc = np.zeros((nc, nc, M))
+        for I in range(nc):
+            for J in range(nc):
+                fi, fj = 2 * I + 1, 2 * J + 1
+                for di in (-1, 0, 1):
+                    for dj in (-1, 0, 1):
+                        rc[I, J] += (2 - abs(di)) * (2 - abs(dj)) / 16.0 * r[fi + di, fj + dj]
+        ec = np.linalg.solve(Ac, rc.reshape(-1)).reshape(nc, nc, M)
+        corr = np.zeros_like(E)
+        for I in range(nc):
+            for J in range(nc):
+                fi, fj = 2 * I + 1, 2 * J + 1
+                for di in (-1, 0, 1):
+                    for dj in (-1, 0, 1):
+                        corr[fi + di, fj + dj] += (1 - 0.5 * abs(di)) * (1 - 0.5 * abs(dj)) * ec[I, J]
+        return E + corr
+
+    cols = []
+    for col in range(n * n * M):
+        E = np.zeros(n * n * M)
+        E[col] = 1.0
+        E = E.reshape(n, n, M)
+        for _ in range(nu1):
+            E = smooth(E)
+        E = cgc(E)
+        for _ in range(nu2):
+            E = smooth(E)
+        cols.append(E.reshape(-1))
+    return np.array(cols).T
+
+
+@pytest.mark.parametrize("nu1,nu2", [(1, 0), (0, 1)])
+def test_2d_blocks_equal_brute_force_two_grid_matrix(nu1, nu2):
+    """2D: the assembled two-grid matrix maps the four harmonics of every
+    low-frequency pair as the 4M x 4M block says, the frequencies with an
+    index (n+1)/2 as the smoother alone says."""
+    n, M = 7, 3
+    t = W.graded_mesh(M, 1.0, 3.0)
+    R = oracle.l1_matrix(t, 0.4)
+    h = math.pi / (n + 1)
+    Tbf = _two_grid_matrix_2d(R, n, h, nu1, nu2)
+    scale = max(1.0, np.abs(Tbf).max())
+    i = np.arange(1, n + 1)[:, None]
+    j = np.arange(1, n + 1)[None, :]
+    red = (i + j) % 2 == 0
+    rng = np.random.default_rng(3)
+
+    def apply(field_coeffs):
+        v = sum(np.einsum("ij,m->ijm", fld, cf) for fld, cf in field_coeffs)
+        return (Tbf @ v.reshape(-1)).reshape(n, n, M)
+
+    nc = (n - 1) // 2
+    for k1 in range(1, nc + 1):
+        for k2 in range(1, nc + 1):
+            s = np.sin(k1 * math.pi * i / (n + 1)) * np.sin(k2 * math.pi * j / (n + 1))
+            f = (-1.0) ** (i + 1) * s
+            parts = [np.where(red, s, 0.0), np.where(~red, s, 0.0), np.where(red, f, 0.0), np.where(~red, f, 0.0)]
+            coef = [rng.standard_normal(M) for _ in range(4)]
+            out = apply(zip(parts, coef))
+            new = S.two_grid_block_2d(R, h, k1 * math.pi / (n + 1), k2 * math.pi / (n + 1), nu1, nu2) @ \
+                np.concatenate(coef)
+            want = sum(np.einsum("ij,m->ijm", fld, new[q * M:(q + 1) * M]) for q, fld in enumerate(parts))
+            assert np.max(np.abs(out - want)) <= 1e-10 * scale, (k1, k2)
+        # one index (n + 1)/2: the smoother alone
+        kh = (n + 1) // 2
+        for s in (np.sin(kh * math.pi * i / (n + 1)) * np.sin(k1 * math.pi * j / (n + 1)),
+                  np.sin(k1 * math.pi * i / (n + 1)) * np.sin(kh * math.pi * j / (n + 1))):
+            parts = [np.where(red, s, 0.0), np.where(~red, s, 0.0)]
+            coef = [rng.standard_normal(M) for _ in range(2)]
+            out = apply(zip(parts, coef))
+            new = S.smoother_block_2d(R, h, k1 * math.pi / (n + 1), nu1 + nu2) @ np.concatenate(coef)
+            want = sum(np.einsum("ij,m->ijm", fld, new[q * M:(q + 1) * M]) for q, fld in enumerate(parts))
+            assert np.max(np.abs(out - want)) <= 1e-10 * scale, k1
+
+
+def test_2d_no_time_term_is_the_red_black_poisson_factor():
+    """R = 0 leaves the 2D Poisson problem, whose two-grid factor with one
+    red-black smoothing step, full weighting and bilinear interpolation tends
+    to 1/4 as h -> 0 (and stays below it)."""
+    vals = [S.two_grid_factor_2d(2 ** l - 1, 3, 0.5, 1.0, R=np.zeros((3, 3))) for l in (4, 6, 8)]
+    assert all(v < 0.25 for v in vals) and vals[-1] > 0.249 and vals[0] < vals[1] < vals[2], vals
