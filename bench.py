@@ -62,12 +62,15 @@ def parse():
                     help="batched workload: the plans' AUTO rule, every instance pipelined (one merged launch), "
                          "or the autotuner per (n, M) bucket")
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--inner-cycles", type=int, default=0,
+                    help="float32 V-cycles per float64 refinement step of the mixed forms; 0: each workload's "
+                         "measured best (batched 3, 2D n=255 2, 1D 1)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--value-only", action="store_true",
-                    help="time only the launches behind `value` (no other forms, no CPU baseline): the command "
-                         "the kernel profiles are taken on")
+                    help="time only the float64 form of the selected workload (the headline with --workload all; "
+                         "no other forms, no CPU baseline): the command the kernel profiles are taken on")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB three times on the device (counter calibration) and exit")
     return ap.parse_args()
@@ -259,6 +262,18 @@ def batched_sources(probs, torch, dev):
     return fs
 
 
+# Float32 cycles per float64 refinement step of the mixed forms, measured per
+# workload (unknowns/s to 1e-8 for 1..6): more cycles per step amortise the
+# float64 defect and the host-side stopping test, until a step's float32
+# cycles reduce the residual less than the count suggests and cycles are
+# wasted (2D n=255, M=1024: 10, 10, 12, 12, 15, 18 cycles for 1..6).
+BEST_INNER = {"batched": 3, "large2d": 2, "learned2d": 2, "large1d": 1, "small1d": 1}
+
+
+def inner_for(args, workload):
+    return args.inner_cycles if args.inner_cycles > 0 else BEST_INNER[workload]
+
+
 def batched_forms(args, torch, mg, dev):
     """The batched workload in float64 (the headline), float32 inner cycles,
     bfloat16 factors, and (with the AUTO rule) every instance pipelined."""
@@ -278,6 +293,7 @@ def batched_forms(args, torch, mg, dev):
     for name, precision, sched in variants:
         t0 = time.perf_counter()
         plans = [mg.Plan(2, p.n, p.M, p.alpha, k=p.k, r=p.r, t=p.t, precision=precision,
+                         inner_cycles=inner_for(args, "batched") if precision != "fp64" else 1,
                          schedule="pipelined" if sched == "pipelined" else "auto").bind() for p in probs]
         setup_s = time.perf_counter() - t0
         tuned = {}
@@ -289,6 +305,7 @@ def batched_forms(args, torch, mg, dev):
         batch = mg.Batch(plans, graph=True).bind()
         secs, st, timing = time_batch(batch, plans, fs, us, args.tol, args.steps, args.warmup, torch)
         out[name] = {"value": unknowns * args.steps / secs, "ms_per_step": 1e3 * secs / args.steps,
+                     "inner_cycles": inner_for(args, "batched") if precision != "fp64" else None,
                      "cycles_total": sum(s["cycles"] for s in st),
                      "max_rel_res": max(s["res"] / s["bnorm"] for s in st),
                      "setup_s": round(setup_s, 2), "graph_replays": batch.graph_replays(),
@@ -333,7 +350,8 @@ def single_forms(name, probs, args, torch, mg, dev, learned=None, variants=None)
         if warm and (args.no_learned or learned is None):
             continue
         plans = [mg.Plan(p.dim, p.n, p.M, p.alpha, k=p.k, r=p.r, t=p.t, length=p.length, leaf=p.leaf,
-                         precision=precision).bind() for p in probs]
+                         precision=precision, inner_cycles=inner_for(args, name) if precision != "fp64" else 1).bind()
+                 for p in probs]
         if warm:
             from paper_1706_07632_amd import learn
             for pl, f, u in zip(plans, fs, us):
@@ -350,6 +368,7 @@ def single_forms(name, probs, args, torch, mg, dev, learned=None, variants=None)
                      "roofline": roofline(timing, precision, f"{name}_{form}"), "kernels": kernels_table(timing)}
         if precision != "fp64":
             out[form]["refinements"] = [s["refinements"] for s in st]
+            out[form]["inner_cycles"] = inner_for(args, name)
         if warm:
             out[form]["used_warm_start"] = [s["used_warm_start"] for s in st]
             out[form]["warm_res0_rel"] = [s["warm_res0"] / s["bnorm"] for s in st]
@@ -389,7 +408,7 @@ def main():
         bf, cfg, cpu = batched_forms(args, torch, mg, dev)
         forms.update({f"batched_{k}": v for k, v in bf.items()})
         head = ("batched_fp64", cfg, cpu)
-    if args.workload in ("all", "large2d") and not args.value_only:
+    if args.workload == "large2d" or (args.workload == "all" and not args.value_only):
         p = W.config("large2d")
         net, _ = (None, None) if args.no_learned else load_net(2, p.N)
         f2 = single_forms("large2d", [p], args, torch, mg, dev, learned=net,
@@ -403,7 +422,7 @@ def main():
             head = ("large2d_fp64", {"workload": "large2d: 2D n=255 M=1024 alpha=0.5 r=3 k=10 leaf 16 V(1,1), "
                                                  "manufactured u=t^0.5 sin(pi x) sin(pi y)",
                                      "N": p.N, "M": p.M, "tol": args.tol}, cpu)
-    if args.workload in ("all", "learned2d") and not args.value_only and not args.no_learned:
+    if (args.workload == "learned2d" or (args.workload == "all" and not args.value_only)) and not args.no_learned:
         import numpy as np
         probs = [W.warm_start_family(2, 255, 1024, np.random.default_rng([100001, i])) for i in range(2)]
         net, meta = load_net(2, probs[0].N)
@@ -421,7 +440,7 @@ def main():
             for k in ("mixed", "fp64_learned", "mixed_learned"):
                 if base and k in f5:
                     forms[f"learned2d_{k}"]["vs_fp64"] = f5[k]["value"] / base
-    if args.workload in ("all", "large1d") and not args.value_only:
+    if args.workload == "large1d" or (args.workload == "all" and not args.value_only):
         probs = [W.config("large1d", a) for a in (0.3, 0.5, 0.7)]
         f2 = single_forms("large1d", probs, args, torch, mg, dev)
         cpu = None if args.no_cpu_baseline else cpu_baseline(probs, [4096, 4096, 4096], "1D n=1023 M=4096",
