@@ -52,13 +52,32 @@ def grid_shape(dim: int, n: int):
     return (1, n) if dim == 1 else (n, n)
 
 
+def _device_source(p, torch, dev):
+    """f [M][N] on the device from the instance's sine modes."""
+    import workloads as W
+    f = torch.zeros((p.M, p.N), dtype=torch.float64, device=dev)
+    for kvec, prof in p.modes:
+        f.add_(torch.outer(torch.as_tensor(prof, dtype=torch.float64, device=dev),
+                           torch.as_tensor(W.sine_mode(p.n, p.dim, p.length, kvec), dtype=torch.float64, device=dev)))
+    return f
+
+
 def generate(dim: int, n: int, M: int, count: int, seed: int, tol: float = 1e-10, k: int = 10,
-             nslices: int = NSLICES, log=None):
+             nslices: int = NSLICES, log=None, group: int = 1, seconds: float = 0.0):
     """Solver-generated samples: X [count][nslices+2][H][W] (f at the slice
     rows over ||f||_inf, alpha, r/10) and Y [count][nslices][H][W] (the
-    float64 MGWR solution at those rows over ||f||_inf), float32 on the GPU."""
+    float64 MGWR solution at those rows over ||f||_inf), float32 on the GPU.
+    Instances [seed, i] of workloads.warm_start_family; sources are built on
+    the device from their sine modes; with group > 1 that many instances are
+    solved as one batch (their staged solves side by side), and the host
+    set-up of the next group's plans runs on worker threads meanwhile.  With
+    seconds > 0 generation stops after the first group that ends past that
+    wall time; the arrays are then cut to the samples made."""
+    import concurrent.futures as cf
+
     import torch
     import workloads as W
+    from . import Batch
     H, Wd = grid_shape(dim, n)
     rows = slice_rows(M, nslices)
     dev = torch.device("cuda", torch.cuda.current_device())
@@ -67,32 +86,69 @@ def generate(dim: int, n: int, M: int, count: int, seed: int, tol: float = 1e-10
     ridx = torch.tensor(rows, device=dev)
     cycles = []
     t0 = time.time()
-    for i in range(count):
-        p = W.warm_start_family(dim, n, M, np.random.default_rng([seed, i]), k=k)
-        plan = Plan(dim, n, M, p.alpha, k=p.k, r=p.r, t=p.t).bind()
-        f = torch.as_tensor(p.f, dtype=torch.float64, device=dev)
-        u, st = plan.solve(f, tol=tol)
-        scale = f.abs().max()
-        X[i, :nslices] = (f.index_select(0, ridx) / scale).reshape(nslices, H, Wd).float()
-        X[i, nslices] = p.alpha
-        X[i, nslices + 1] = p.r / 10.0
-        Y[i] = (u.index_select(0, ridx) / scale).reshape(nslices, H, Wd).float()
-        cycles.append(st["cycles"])
-        plan.close()
-        if log and (i + 1) % max(1, count // 8) == 0:
-            log(f"generated {i + 1}/{count} samples ({time.time() - t0:.1f} s)")
+
+    def make(i):
+        p = W.warm_start_family(dim, n, M, np.random.default_rng([seed, i]), k=k, build_f=False)
+        return p, Plan(dim, n, M, p.alpha, k=p.k, r=p.r, t=p.t)
+
+    starts = list(range(0, count, group))
+    last_log = t0
+    with cf.ThreadPoolExecutor(max_workers=8) as pool:
+        pending = [pool.submit(make, i) for i in range(starts[0], min(count, starts[0] + group))]
+        for gi, s0 in enumerate(starts):
+            items = [fut.result() for fut in pending]
+            nxt = starts[gi + 1] if gi + 1 < len(starts) else None
+            pending = [pool.submit(make, i) for i in range(nxt, min(count, nxt + group))] if nxt is not None else []
+            probs = [it[0] for it in items]
+            plans = [it[1].bind() for it in items]
+            fs = [_device_source(p, torch, dev) for p in probs]
+            if len(plans) > 1:
+                us, sts = Batch(plans).bind().solve(fs, tol=tol)
+            else:
+                u, st = plans[0].solve(fs[0], tol=tol)
+                us, sts = [u], [st]
+            for j, (p, f, u, st) in enumerate(zip(probs, fs, us, sts)):
+                i = s0 + j
+                scale = f.abs().max()
+                X[i, :nslices] = (f.index_select(0, ridx) / scale).reshape(nslices, H, Wd).float()
+                X[i, nslices] = p.alpha
+                X[i, nslices + 1] = p.r / 10.0
+                Y[i] = (u.index_select(0, ridx) / scale).reshape(nslices, H, Wd).float()
+                cycles.append(st["cycles"])
+            for pl in plans:
+                pl.close()
+            now = time.time()
+            done = min(count, s0 + group)
+            if log and (now - last_log > 30 or done >= count):
+                last_log = now
+                log(f"generated {done}/{count} samples ({now - t0:.1f} s)")
+            if seconds > 0 and now - t0 > seconds and done < count:
+                for fut in pending:
+                    fut.result()[1].close()
+                if log:
+                    log(f"generation stopped at its time budget: {done} samples ({now - t0:.1f} s)")
+                return X[:done].clone(), Y[:done].clone(), cycles
     return X, Y, cycles
 
 
 def train(net, X, Y, h: float, steps: int, batch: int = 16, lr: float = 1e-3, lr_end: float = 1e-5,
-          seed: int = 0, log=None, log_every: int = 250):
-    """Adam with a cosine learning-rate decay on random minibatches."""
+          seed: int = 0, log=None, log_every: int = 250, seconds: float = 0.0):
+    """Adam with a cosine learning-rate decay on random minibatches.  With
+    seconds > 0 the step count is cut, after timing the first 50 steps, to
+    what fits that wall time (the schedule then spans the steps that run)."""
     import torch
     g = torch.Generator(device=X.device)
     g.manual_seed(seed)
     losses = []
     t0 = time.time()
-    for it in range(steps):
+    it = 0
+    while it < steps:
+        if seconds > 0 and it == 50:
+            torch.cuda.synchronize()
+            per = (time.time() - t0) / 50
+            steps = max(51, min(steps, int(seconds / per)))
+            if log:
+                log(f"{per * 1e3:.1f} ms per step: {steps} steps fit the time budget")
         idx = torch.randint(0, X.shape[0], (batch,), device=X.device, generator=g)
         xb = X.index_select(0, idx).contiguous()
         yb = Y.index_select(0, idx).contiguous()
@@ -103,7 +159,8 @@ def train(net, X, Y, h: float, steps: int, batch: int = 16, lr: float = 1e-3, lr
             losses.append((it, loss))
             if log:
                 log(f"step {it} loss {loss:.4e} lr {cur:.2e} ({time.time() - t0:.1f} s)")
-    return losses
+        it += 1
+    return losses, steps
 
 
 def evaluate_loss(net, X, Y, h: float, batch: int = 16) -> float:
@@ -116,7 +173,8 @@ def evaluate_loss(net, X, Y, h: float, batch: int = 16) -> float:
     return tot / max(1, cnt)
 
 
-def gain(net, problems, tol: float = 1e-8, precision: str = "fp64", repeats: int = 2, log=None):
+def gain(net, problems, tol: float = 1e-8, precision: str = "fp64", repeats: int = 2, log=None,
+         inner_cycles: int = 1):
     """Cycles and solve times with the zero iterate and with the warm start on
     `problems` (workloads.Problem); each form is solved `repeats` times on the
     same plan and the last solve counts (it runs with the cycle count the
@@ -125,7 +183,8 @@ def gain(net, problems, tol: float = 1e-8, precision: str = "fp64", repeats: int
     dev = torch.device("cuda", torch.cuda.current_device())
     rows = []
     for p in problems:
-        plan = Plan(p.dim, p.n, p.M, p.alpha, k=p.k, r=p.r, t=p.t, precision=precision).bind()
+        plan = Plan(p.dim, p.n, p.M, p.alpha, k=p.k, r=p.r, t=p.t, precision=precision,
+                    inner_cycles=inner_cycles if precision != "fp64" else 1).bind()
         attach(plan, net)
         f = torch.as_tensor(p.f, dtype=torch.float64, device=dev)
         out = {}
@@ -198,6 +257,9 @@ def main(argv=None):
     ap.add_argument("--eval-n", type=int, default=0, help="held-out evaluation grid (0: skip)")
     ap.add_argument("--eval-M", type=int, default=0)
     ap.add_argument("--eval-count", type=int, default=4)
+    ap.add_argument("--group", type=int, default=16, help="training instances solved together as one batch")
+    ap.add_argument("--gen-seconds", type=float, default=0.0, help="wall-time budget of the sample generation")
+    ap.add_argument("--train-seconds", type=float, default=0.0, help="wall-time budget of the training")
     a = ap.parse_args(argv)
     import torch
 
@@ -207,11 +269,13 @@ def main(argv=None):
     H, Wd = grid_shape(a.dim, a.n)
     h = 1.0 / (a.n + 1)
     log(f"generating {a.count} + {a.val} samples: dim={a.dim} n={a.n} M={a.M}")
-    X, Y, cyc = generate(a.dim, a.n, a.M, a.count, a.seed, tol=a.gen_tol, log=log)
-    Xv, Yv, _ = generate(a.dim, a.n, a.M, a.val, a.seed + 1000, tol=a.gen_tol)
+    X, Y, cyc = generate(a.dim, a.n, a.M, a.count, a.seed, tol=a.gen_tol, log=log, group=a.group,
+                         seconds=a.gen_seconds)
+    a.count = X.shape[0]
+    Xv, Yv, _ = generate(a.dim, a.n, a.M, a.val, a.seed + 1000, tol=a.gen_tol, group=a.group)
     log(f"solver cycles per sample: mean {np.mean(cyc):.2f}")
     net = make_net(max(a.batch, 16) * H * Wd, seed=a.seed)
-    losses = train(net, X, Y, h, a.steps, a.batch, a.lr, log=log)
+    losses, a.steps = train(net, X, Y, h, a.steps, a.batch, a.lr, log=log, seconds=a.train_seconds)
     vloss = evaluate_loss(net, Xv, Yv, h)
     log(f"validation loss {vloss:.4e}")
     meta = {"dim": a.dim, "n": a.n, "M": a.M, "count": a.count, "seed": a.seed, "steps": a.steps,
@@ -229,7 +293,7 @@ def main(argv=None):
         big.set_finest(h)
         for precision in ("fp64", "mixed"):
             log(f"held-out gain at n={a.eval_n} M={a.eval_M} ({precision})")
-            rows = gain(big, probs, precision=precision, log=log)
+            rows = gain(big, probs, precision=precision, log=log, inner_cycles=2 if a.dim == 2 else 1)
             z = sum(r["zero"]["seconds"] for r in rows)
             w = sum(r["warm"]["seconds"] for r in rows)
             log(f"total: zero {sum(r['zero']['cycles'] for r in rows)} cycles {z:.3f} s, warm "

@@ -202,14 +202,15 @@ def batched_instances(count: int = 64, seed: int = 20261203, sides=(63, 127, 255
 
 
 def warm_start_family(dim: int, n: int, M: int, rng: np.random.Generator, alpha_range=(0.2, 0.9),
-                      nmodes: int = 6, kmax: int = 16, k: int = 10) -> Problem:
+                      nmodes: int = 6, kmax: int = 16, k: int = 10, build_f: bool = True) -> Problem:
     """Training and evaluation family of the learned initial guess: alpha ~
     U(alpha_range), r = (2 - alpha)/alpha, zero initial data on (0, 1)^dim,
     T = 1, and a source made of `nmodes` distinct sine modes (wave numbers in
     {1..kmax}^dim, mode 1 always present) with time profiles
     a * Gamma(1 + alpha) + c * t^alpha, a ~ U(0, 1), c ~ N(0, 1), both divided by
     1 + |kvec|^2.  The manufactured sources of the benchmark workloads (one mode,
-    a = 1, c = pi^2 dim) lie in its span."""
+    a = 1, c = pi^2 dim) lie in its span.  With build_f False only the modes are
+    kept (f None; the same random draws)."""
     alpha = float(rng.uniform(*alpha_range))
     r = default_grading(alpha)
     t = graded_mesh(M, 1.0, r)
@@ -218,13 +219,14 @@ def warm_start_family(dim: int, n: int, M: int, rng: np.random.Generator, alpha_
     a = rng.uniform(0.0, 1.0, nmodes)
     c = rng.standard_normal(nmodes)
     tt = t[1:] ** alpha
-    f = np.zeros((M, n ** dim))
+    f = np.zeros((M, n ** dim)) if build_f else None
     modes = []
     for idx, ai, ci in zip(flat, a, c):
         kvec = tuple(int(idx // kmax ** d % kmax) + 1 for d in range(dim))
         w = 1.0 + sum(kk * kk for kk in kvec)
         prof = (ai * math.gamma(1 + alpha) + ci * tt) / w
-        f += np.outer(prof, sine_mode(n, dim, 1.0, kvec))
+        if build_f:
+            f += np.outer(prof, sine_mode(n, dim, 1.0, kvec))
         modes.append((kvec, prof))
     return Problem(dim=dim, n=n, M=M, alpha=alpha, r=r, k=k, t=t, f=f, modes=modes,
                    name=f"warm{dim}d_n{n}_M{M}_a{alpha:.3f}")
