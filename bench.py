@@ -436,6 +436,10 @@ def main():
                 v["cpu_baseline"] = cpu
                 v["network"] = {key: meta.get(key) for key in ("dim", "n", "M", "count", "steps", "val_loss")}
                 forms[f"learned2d_{k}"] = v
+            if head is None and "fp64" in f5:
+                head = ("learned2d_fp64", {"workload": "learned2d: 2D n=255 M=1024, two held-out instances of the "
+                                                       "warm-start family (seeds [100001, i])",
+                                           "N": probs[0].N, "M": probs[0].M, "instances": 2, "tol": args.tol}, cpu)
             base = f5.get("fp64", {}).get("value")
             for k in ("mixed", "fp64_learned", "mixed_learned"):
                 if base and k in f5:

@@ -250,8 +250,9 @@ int mgwr_batch_bind(mgwr_batch* batch, void* workspace_dev, size_t bytes, void* 
  * side by side by up to 8 host threads, each on a HIP stream the batch owns
  * (default priority).  Each plan's own stream is synchronised before its
  * arrays are touched, and all work is complete when the call returns.  They
- * run one by one instead when two entries share a plan or with
- * MGWR_WARM_START (the plans share one network workspace).  Returns MGWR_OK
+ * run one by one instead when two entries share a plan.  With
+ * MGWR_WARM_START the predictions of plans sharing a network take turns on
+ * it (its buffers and stream) while the cycles run side by side.  Returns MGWR_OK
  * when every instance converged, else the first non-OK status in entry
  * order. */
 int mgwr_batch_solve(mgwr_batch* batch, const double* const* f_dev, const double* const* g_dev, double tol,

@@ -152,10 +152,9 @@ struct mgwr_plan {
   mgwr_net* net = nullptr;
   int nslices = 0;
   int* rows_dev = nullptr;
-  float* netx = nullptr;   // network input [nslices + 2][N]
   // offsets computed by layout()
   struct Off {
-    size_t stages, counters, flags, norms, wrows, wx, cstages, ccounters, cflags;
+    size_t stages, counters, flags, norms, wrows, cstages, ccounters, cflags;
     size_t leaves, dn_list, ff_row, zu_row, a1, tm, B0, part, scal;
     size_t dense64, dinv64, ffA64, zuB64, dense32, dinv32, ffA32, zuB32;
     std::vector<size_t> U64, F64, R64, U32, F32, R32;
@@ -239,7 +238,6 @@ void layout(mgwr_plan* pl) {
     o.cflags = cv.take(2 * sizeof(int));
   }
   o.wrows = cv.take(mgwr_plan::kMaxSlices * sizeof(int));
-  o.wx = cv.take((size_t)(mgwr_plan::kMaxSlices + 2) * hp.levels[0].N * sizeof(float));
   o.total = cv.off;
 }
 
@@ -893,13 +891,20 @@ int prepare_solve(mgwr_plan* pl, const double* f, const double* g, double tol, d
     if (s.bnorm > 0.0) {
       const int ns = pl->nslices;
       const int H = hp.p.dim == 1 ? 1 : hp.levels[0].n, W = hp.levels[0].n;
-      HIP_TRY(launch_gather_slices(b, pl->rows_dev, ns, N, s.bnorm, (float)hp.p.alpha, (float)(hp.p.r / 10.0),
-                                   pl->netx, pl->stream));
-      HIP_TRY(hipStreamSynchronize(pl->stream));
-      const float* y = nullptr;
-      if ((rc = net_infer(pl->net, pl->netx, H, W, hp.levels[0].h, &y))) return rc;
-      HIP_TRY(hipStreamSynchronize(net_stream(pl->net)));
-      HIP_TRY(launch_time_interp(y, pl->rows_dev, ns, pl->tpow, g, hp.p.M, N, s.bnorm, u, pl->stream));
+      {
+        // gather, inference and interpolation hold the network (its buffers
+        // and stream are shared by every plan it is attached to)
+        std::lock_guard<std::mutex> lk(net_mutex(pl->net));
+        float* xin = net_input_stage(pl->net);
+        HIP_TRY(launch_gather_slices(b, pl->rows_dev, ns, N, s.bnorm, (float)hp.p.alpha, (float)(hp.p.r / 10.0),
+                                     xin, pl->stream));
+        HIP_TRY(hipStreamSynchronize(pl->stream));
+        const float* y = nullptr;
+        if ((rc = net_infer(pl->net, xin, H, W, hp.levels[0].h, &y))) return rc;
+        HIP_TRY(hipStreamSynchronize(net_stream(pl->net)));
+        HIP_TRY(launch_time_interp(y, pl->rows_dev, ns, pl->tpow, g, hp.p.M, N, s.bnorm, u, pl->stream));
+        HIP_TRY(hipStreamSynchronize(pl->stream));
+      }
       // the prediction's true residual (reported, and the right-hand side of
       // a first refinement step)
       if ((rc = defect<double>(pl, pl->d64, 0, b, u, pl->d64.R[0]))) return rc;
@@ -1250,7 +1255,6 @@ void assign_pointers(mgwr_plan* pl, unsigned char* w, size_t bytes, hipStream_t 
   pl->scal = (double*)(w + o.scal);
   pl->B0 = (double*)(w + o.B0);
   pl->rows_dev = (int*)(w + o.wrows);
-  pl->netx = (float*)(w + o.wx);
   pl->stages_dev = (Stage*)(w + o.stages);
   pl->counters = (int*)(w + o.counters);
   pl->flags_dev = (int*)(w + o.flags);
@@ -1836,14 +1840,16 @@ namespace {
 // threads, each with a stream of its own: a staged solve waits on the host
 // for its stopping tests, and its coarse levels run as latency-bound launches
 // that leave most of the GPU idle, so solving several side by side fills it.
-// Not done when two entries share a plan (one workspace) or with the warm
-// start (the plans share one network and its workspace).  Measured on 64
+// Not done when two entries share a plan (one workspace).  Warm-started
+// instances run side by side too: their predictions take turns on the
+// network they share (net_mutex), their cycles overlap.  Measured on 64
 // uneven 2D instances: one by one 9.6e8 unknowns/s; 2-4 workers 1.15e9, 8
 // workers 1.22e9, 12 or 16 no faster.
 constexpr int kStagedWorkers = 8;
 
 bool staged_side_by_side(const mgwr_batch* bt, const std::vector<int>& staged, unsigned flags) {
-  if (staged.size() < 2 || (flags & MGWR_WARM_START)) return false;
+  (void)flags;   // warm starts too: each prediction holds its network's lock
+  if (staged.size() < 2) return false;
   std::set<const mgwr_plan*> seen;
   for (int i : staged)
     if (!seen.insert(bt->plans[i]).second) return false;

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <string>
 
 #include "mgwr.h"
@@ -16,6 +17,12 @@ int net_input_channels(const mgwr_net* net);
 int net_out_channels(const mgwr_net* net);
 long long net_capacity(const mgwr_net* net);
 hipStream_t net_stream(const mgwr_net* net);
+// Solver predictions from several threads (batches solved side by side) take
+// this lock around gather, inference and interpolation: they share the
+// network's buffers and stream.  The input is staged in a network-owned
+// buffer so that the captured inference graph always reads one address.
+std::mutex& net_mutex(mgwr_net* net);
+float* net_input_stage(mgwr_net* net);
 // shape checks and the master weights (for loading a weight blob)
 bool net_same_shape(const mgwr_net* net, int layers, const int* channels, int nsignal);
 bool net_is_bound(const mgwr_net* net);

@@ -23,6 +23,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -614,6 +615,8 @@ struct mgwr_net {
   uint16_t* wbf = nullptr;
   float *grad = nullptr, *m = nullptr, *v = nullptr;
   float *sig = nullptr, *xin = nullptr, *ybuf = nullptr, *gy = nullptr;  // per-level arenas
+  float* xstage = nullptr;          // the solver's input staging [S+E][cap] (a fixed address for graph replay)
+  std::mutex mu;                    // one solver prediction at a time (shared buffers and stream)
   std::vector<float*> act;          // act[j]: output of layer j at every level
   float *g0 = nullptr, *g1 = nullptr;  // backprop scratch of one level [cap * maxc]
   double* norms = nullptr;          // per-sample loss norms
@@ -664,7 +667,8 @@ struct mgwr_net {
     o.push_back(take((size_t)cap_ * maxc * 4));         // 8 g0
     o.push_back(take((size_t)cap_ * maxc * 4));         // 9 g1
     o.push_back(take(kMaxBatch * 2 * sizeof(double)));  // 10 norms
-    for (int j = 0; j < L(); ++j) o.push_back(take(P * ch[j + 1] * 4));  // 11 + j act
+    o.push_back(take((size_t)cap_ * in_channels() * 4)); // 11 xstage
+    for (int j = 0; j < L(); ++j) o.push_back(take(P * ch[j + 1] * 4));  // 12 + j act
     if (offs) *offs = o;
     return (long long)off;
   }
@@ -801,8 +805,9 @@ int mgwr_net_bind(mgwr_net* net, float* params_dev, long long max_bhw, void* ws,
   net->g0 = (float*)(w + o[8]);
   net->g1 = (float*)(w + o[9]);
   net->norms = (double*)(w + o[10]);
+  net->xstage = (float*)(w + o[11]);
   net->act.assign(net->L(), nullptr);
-  for (int j = 0; j < net->L(); ++j) net->act[j] = (float*)(w + o[11 + j]);
+  for (int j = 0; j < net->L(); ++j) net->act[j] = (float*)(w + o[12 + j]);
   net->cap = max_bhw;
   NET_TRY(hipMemsetAsync(net->m, 0, net->nparam * 4, net->stream));
   NET_TRY(hipMemsetAsync(net->v, 0, net->nparam * 4, net->stream));
@@ -964,6 +969,8 @@ int net_input_channels(const mgwr_net* net) { return net->in_channels(); }
 int net_out_channels(const mgwr_net* net) { return net->ch.back(); }
 long long net_capacity(const mgwr_net* net) { return net->bound ? net->cap : 0; }
 hipStream_t net_stream(const mgwr_net* net) { return net->stream; }
+std::mutex& net_mutex(mgwr_net* net) { return net->mu; }
+float* net_input_stage(mgwr_net* net) { return net->xstage; }
 bool net_same_shape(const mgwr_net* net, int layers, const int* channels, int nsignal) {
   if (net->L() != layers || net->nsig != nsignal) return false;
   for (int l = 0; l <= layers; ++l)

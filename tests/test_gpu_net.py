@@ -410,3 +410,33 @@ def test_plausible_but_poor_network_is_rejected(dev, schedule):
     b = oracle.rhs(p.f, p.t, p.alpha, None)
     r = oracle.residual(plan.export_dense(), u.cpu().numpy(), b, p.dim, p.n, p.length)
     assert np.abs(r).max() <= 1.5e-10 * np.abs(b).max()
+
+
+def test_warm_started_batch_runs_side_by_side_like_one_by_one(dev):
+    """Staged instances sharing one network, solved as a batch with warm
+    starts (their predictions take turns on the network while the cycles run
+    on worker streams): the same predictions and solutions as solving them
+    one by one, each against the oracle."""
+    ch = learn.channels()
+    params = bf16_params(ch, 47, scale=0.5)
+    probs = [_problem(2, 31, 64, 300 + i) for i in range(5)]
+    net = make(ch, 32, params, probs[0].N)
+    fs = [torch.as_tensor(p.f, dtype=torch.float64, device=dev) for p in probs]
+    single = []
+    for p, f in zip(probs, fs):
+        pl = _plan(p, schedule="staged")
+        learn.attach(pl, net)
+        single.append(pl.solve(f, tol=1e-11, warm_start=True))
+    plans = [_plan(p, schedule="staged") for p in probs]
+    for pl in plans:
+        learn.attach(pl, net)
+    batch = mg.Batch(plans).bind()
+    for rep in range(2):
+        us, sts = batch.solve(fs, tol=1e-11, warm_start=True)
+        for p, pl, u, st, (u1, st1) in zip(probs, plans, us, sts, single):
+            assert st["warm_res0"] == st1["warm_res0"] and st["used_warm_start"] == st1["used_warm_start"]
+            assert float((u - u1).abs().max()) <= 1e-10 * float(u1.abs().max())
+            Rt = pl.export_dense()
+            B = oracle.rhs(p.f, p.t, p.alpha, None)
+            ref = oracle.timestep_solve(Rt, B, p.dim, p.n, p.length)
+            assert np.abs(u.cpu().numpy() - ref).max() <= 1e-10 * np.abs(ref).max()
