@@ -322,10 +322,14 @@ int mgwr_plan_tuned(const mgwr_plan* plan, int* schedule, int* prefetch, int* co
  * sampled at the level's points, log2(1/h_l)/10] (channels[0] channels) to
  * out_l (channels[L] channels), and the output is
  * y = sum_l P^l (4 h_l^2 out_l), h_l = 2^l h with h the fine-grid spacing.
- * The forward pass and the data gradient use bfloat16 copies of the
- * convolution weights (biases stay float32) with float32 accumulation; master
- * weights, gradients and Adam moments are float32.  Parameter layout: for each layer, weights [c_out][c_in][3][3]
- * then biases [c_out].  All arrays are device pointers on the stream given to
+ * Inference (mgwr_net_forward and the solver's prediction) runs the
+ * convolutions on the bfloat16 matrix cores: bfloat16 weights and each
+ * convolution's input rounded to bfloat16 (nearest even), float32
+ * accumulation, float32 bias and tanh.  Training (mgwr_net_gradient) runs
+ * float32 kernels on bfloat16 weights with float32 activations, and the
+ * gradient is that of this float32 forward pass; master weights, gradients
+ * and Adam moments are float32.  Parameter layout: for each layer, weights
+ * [c_out][c_in][3][3] then biases [c_out].  All arrays are device pointers on the stream given to
  * mgwr_net_bind; calls are asynchronous unless stated. */
 typedef struct mgwr_net mgwr_net;
 /* layers in [1, 16]; channels[0..layers] in [1, 1024]; nsignal in [1, channels[0] - 1]. */

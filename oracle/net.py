@@ -176,9 +176,11 @@ def level_inputs(x: np.ndarray, nsig: int, h: float):
 
 
 def forward(params: np.ndarray, channels: list[int], x: np.ndarray, nsig: int, h: float, cache: bool = False,
-            h_min: float = 0.0):
+            h_min: float = 0.0, act_bf16: bool = False):
     """Network output y [B][c_L][H][W] (and the activations when cache).
-    Levels with h_l < h_min are left out (out_l = 0)."""
+    Levels with h_l < h_min are left out (out_l = 0).  act_bf16: the input of
+    every convolution is rounded to float32 and then to the nearest bfloat16
+    first (the precision of the library's matrix-core inference)."""
     layers = unpack(params, channels)
     inputs, sizes, two_d = level_inputs(np.asarray(x, dtype=np.float64), nsig, h)
     acts, outs = [], []
@@ -189,7 +191,8 @@ def forward(params: np.ndarray, channels: list[int], x: np.ndarray, nsig: int, h
             continue
         a = [xin]
         for j, (w, b) in enumerate(layers):
-            z = conv3x3(a[-1], w, b)
+            inp = bf16_round(a[-1].astype(np.float32)).astype(np.float64) if act_bf16 else a[-1]
+            z = conv3x3(inp, w, b)
             a.append(np.tanh(z) if j + 1 < len(layers) else z)
         acts.append(a)
         outs.append(a[-1])

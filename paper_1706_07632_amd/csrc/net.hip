@@ -496,6 +496,97 @@ __global__ void round_bf16_kernel(const float* __restrict__ p, uint16_t* __restr
     wbf[i] = f32_to_bf16(p[i]);
 }
 
+// ---------------------------------------------------------------------------
+// Inference convolution on the bfloat16 matrix cores (v_mfma_f32_16x16x32_bf16):
+// the 3x3 convolution as nine shifted 1x1 products,
+//   y[b][co][p] = bias[co] + sum_k sum_ci wk[k][co][ci] x[b][ci][p + off(k)],
+// a GEMM per tap with the output channels as M, the pixels as N and the input
+// channels as K.  The weights are re-laid out per tap as wk[k][co][cpad]
+// (bfloat16, cpad = cin rounded up to 32, zero padded) so that a lane's 8
+// consecutive K entries are one 16-byte load; the activations are read in
+// float32 and rounded to bfloat16 (nearest even) as they enter the product;
+// accumulation is float32.  Operand layout of the 16x16x32 instruction (lane
+// l, c = l % 16, g = l / 16): A lane holds row c, K entries 8g .. 8g+7; B
+// lane holds column c, the same K entries; the result element r of lane l is
+// row 4g + r, column c.  A block of 4 waves covers 64 pixels (16 per wave)
+// and 64 output channels (4 tiles of 16, grid.y over the rest).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kMfmaK = 32;
+
+__global__ __launch_bounds__(256) void conv_fwd_mfma_kernel(const float* __restrict__ x,
+                                                            const uint16_t* __restrict__ wk,
+                                                            const float* __restrict__ bias, float* __restrict__ y,
+                                                            int B, int cin, int cpad, int cout, int H, int W, int act) {
+  const int HW = H * W;
+  const long long total = (long long)B * HW;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  const long long t = ((long long)blockIdx.x * 4 + wave) * 16 + c;   // this lane's pixel (B column)
+  const bool tok = t < total;
+  const long long tt = tok ? t : 0;
+  const int b = (int)(tt / HW), p = (int)(tt % HW);
+  const int py = p / W, px = p % W;
+  const float* xb = x + (long long)b * cin * HW;
+  const int co0 = blockIdx.y * 64;
+  f32x4 acc[4];
+#pragma unroll
+  for (int tl = 0; tl < 4; ++tl) acc[tl] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k = 0; k < 9; ++k) {
+    const int yy = py + k / 3 - 1, xx = px + k % 3 - 1;
+    const bool ok = tok && yy >= 0 && yy < H && xx >= 0 && xx < W;
+    const long long off = ok ? (long long)yy * W + xx : 0;
+    for (int k0 = 0; k0 < cpad; k0 += kMfmaK) {
+      bf16x8 bv;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int ci = k0 + 8 * g + j;
+        const float v = (ok && ci < cin) ? xb[(long long)ci * HW + off] : 0.0f;
+        bv[j] = __builtin_bit_cast(__bf16, f32_to_bf16(v));
+      }
+#pragma unroll
+      for (int tl = 0; tl < 4; ++tl) {
+        if (co0 + 16 * tl >= cout) break;   // uniform across the wave
+        const int co = co0 + 16 * tl + c;
+        bf16x8 av;
+        if (co < cout) {
+          av = *reinterpret_cast<const bf16x8*>(wk + ((long long)k * cout + co) * cpad + k0 + 8 * g);
+        } else {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) av[j] = __builtin_bit_cast(__bf16, (uint16_t)0);
+        }
+        acc[tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[tl], 0, 0, 0);
+      }
+    }
+  }
+  if (!tok) return;
+  float* yb = y + (long long)b * cout * HW + p;
+#pragma unroll
+  for (int tl = 0; tl < 4; ++tl) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int co = co0 + 16 * tl + 4 * g + r;
+      if (co < cout) {
+        const float v = acc[tl][r] + bias[co];
+        yb[(long long)co * HW] = act ? tanhf(v) : v;
+      }
+    }
+  }
+}
+
+// wk[k][co][ci] (ci < cpad, zero beyond cin) = bfloat16 of w[co][ci][k]
+__global__ void relayout_mfma_kernel(const float* __restrict__ w, uint16_t* __restrict__ wk, int cin, int cpad,
+                                     int cout) {
+  const long long n = 9LL * cout * cpad;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < n;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(idx / ((long long)cout * cpad));
+    const long long rem = idx % ((long long)cout * cpad);
+    const int co = (int)(rem / cpad), ci = (int)(rem % cpad);
+    wk[idx] = ci < cin ? f32_to_bf16(w[((long long)co * cin + ci) * 9 + k]) : (uint16_t)0;
+  }
+}
+
 // Input channels of the warm start for one instance: b at the slice rows
 // divided by `scale`, then constant channels alpha and r / 10.
 __global__ void gather_slices_kernel(const double* __restrict__ b, const int* __restrict__ rows, int nslices,
@@ -616,6 +707,9 @@ struct mgwr_net {
   float *grad = nullptr, *m = nullptr, *v = nullptr;
   float *sig = nullptr, *xin = nullptr, *ybuf = nullptr, *gy = nullptr;  // per-level arenas
   float* xstage = nullptr;          // the solver's input staging [S+E][cap] (a fixed address for graph replay)
+  uint16_t* wmf = nullptr;          // per-tap bfloat16 weights of the matrix-core convolution
+  std::vector<size_t> mfoff;        // per layer: offset into wmf (entries)
+  std::vector<int> cpad;            // per layer: input channels rounded up to 32
   std::mutex mu;                    // one solver prediction at a time (shared buffers and stream)
   std::vector<float*> act;          // act[j]: output of layer j at every level
   float *g0 = nullptr, *g1 = nullptr;  // backprop scratch of one level [cap * maxc]
@@ -668,7 +762,10 @@ struct mgwr_net {
     o.push_back(take((size_t)cap_ * maxc * 4));         // 9 g1
     o.push_back(take(kMaxBatch * 2 * sizeof(double)));  // 10 norms
     o.push_back(take((size_t)cap_ * in_channels() * 4)); // 11 xstage
-    for (int j = 0; j < L(); ++j) o.push_back(take(P * ch[j + 1] * 4));  // 12 + j act
+    size_t nmf = 0;
+    for (int j = 0; j < L(); ++j) nmf += (size_t)9 * ch[j + 1] * ((ch[j] + 31) / 32 * 32);
+    o.push_back(take(nmf * 2));                         // 12 wmf
+    for (int j = 0; j < L(); ++j) o.push_back(take(P * ch[j + 1] * 4));  // 13 + j act
     if (offs) *offs = o;
     return (long long)off;
   }
@@ -685,9 +782,16 @@ int check_net(mgwr_net* net, int B, int H, int W, Geo* g) {
   return MGWR_OK;
 }
 
-int launch_conv_fwd(mgwr_net* net, int j, const float* in, float* out, int B, int H, int W) {
+int launch_conv_fwd(mgwr_net* net, int j, const float* in, float* out, int B, int H, int W, bool mfma) {
   const int cin = net->ch[j], cout = net->ch[j + 1];
   const long long px = (long long)B * H * W;
+  if (mfma) {
+    dim3 grid((unsigned)((px + 63) / 64), (unsigned)((cout + 63) / 64));
+    hipLaunchKernelGGL(conv_fwd_mfma_kernel, grid, dim3(256), 0, net->stream, in, net->wmf + net->mfoff[j],
+                       net->params + net->boff[j], out, B, cin, net->cpad[j], cout, H, W, j + 1 < net->L() ? 1 : 0);
+    NET_TRY(hipGetLastError());
+    return MGWR_OK;
+  }
   dim3 grid((unsigned)((px + 256 * kPx - 1) / (256 * kPx)), (unsigned)((cout + kCoTile - 1) / kCoTile));
   hipLaunchKernelGGL(conv_fwd_kernel, grid, dim3(256), 0, net->stream, in, net->wbf + net->woff[j],
                      net->params + net->boff[j], out, B, cin, cout, H, W, j + 1 < net->L() ? 1 : 0);
@@ -695,9 +799,24 @@ int launch_conv_fwd(mgwr_net* net, int j, const float* in, float* out, int B, in
   return MGWR_OK;
 }
 
+// Per-tap bfloat16 weights of the matrix-core convolution from the master
+// weights (after every change of them).
+int refresh_mfma_weights(mgwr_net* net) {
+  for (int j = 0; j < net->L(); ++j) {
+    const long long n = 9LL * net->ch[j + 1] * net->cpad[j];
+    hipLaunchKernelGGL(relayout_mfma_kernel, dim3(grid_of(n)), dim3(256), 0, net->stream, net->params + net->woff[j],
+                       net->wmf + net->mfoff[j], net->ch[j], net->cpad[j], net->ch[j + 1]);
+    NET_TRY(hipGetLastError());
+  }
+  return MGWR_OK;
+}
+
 // Forward pass of the whole pyramid; leaves the activations of every level in
-// the arenas and the output in level 0 of ybuf.
-int net_forward(mgwr_net* net, const float* x, const Geo& g, double h0) {
+// the arenas and the output in level 0 of ybuf.  mfma: the convolutions run
+// on the bfloat16 matrix cores (activations rounded to bfloat16 at their
+// input; inference), else the float32 kernels (training: the gradient is that
+// of this forward pass).
+int net_forward(mgwr_net* net, const float* x, const Geo& g, double h0, bool mfma) {
   const int B = g.B, S = net->nsig, E = net->nextra, C0 = net->ch[0], CL = net->ch.back();
   const long long HW0 = g.hw[0];
   int rc;
@@ -723,7 +842,7 @@ int net_forward(mgwr_net* net, const float* x, const Geo& g, double h0) {
     const float* in = xin;
     for (int j = 0; j < net->L(); ++j) {
       float* out = net->act[j] + (size_t)B * net->ch[j + 1] * g.cum[l];
-      if ((rc = launch_conv_fwd(net, j, in, out, B, Hl, Wl))) return rc;
+      if ((rc = launch_conv_fwd(net, j, in, out, B, Hl, Wl, mfma))) return rc;
       in = out;
     }
   }
@@ -806,14 +925,27 @@ int mgwr_net_bind(mgwr_net* net, float* params_dev, long long max_bhw, void* ws,
   net->g1 = (float*)(w + o[9]);
   net->norms = (double*)(w + o[10]);
   net->xstage = (float*)(w + o[11]);
+  net->wmf = (uint16_t*)(w + o[12]);
+  net->mfoff.clear();
+  net->cpad.clear();
+  {
+    size_t off = 0;
+    for (int j = 0; j < net->L(); ++j) {
+      net->cpad.push_back((net->ch[j] + 31) / 32 * 32);
+      net->mfoff.push_back(off);
+      off += (size_t)9 * net->ch[j + 1] * net->cpad.back();
+    }
+  }
   net->act.assign(net->L(), nullptr);
-  for (int j = 0; j < net->L(); ++j) net->act[j] = (float*)(w + o[12 + j]);
+  for (int j = 0; j < net->L(); ++j) net->act[j] = (float*)(w + o[13 + j]);
   net->cap = max_bhw;
   NET_TRY(hipMemsetAsync(net->m, 0, net->nparam * 4, net->stream));
   NET_TRY(hipMemsetAsync(net->v, 0, net->nparam * 4, net->stream));
   hipLaunchKernelGGL(round_bf16_kernel, dim3(grid_of((long long)net->nparam)), dim3(256), 0, net->stream,
                      net->params, net->wbf, (long long)net->nparam);
   NET_TRY(hipGetLastError());
+  int rc = refresh_mfma_weights(net);
+  if (rc) return rc;
   NET_TRY(hipStreamSynchronize(net->stream));
   net->drop_graph();
   net->bound = true;
@@ -825,7 +957,7 @@ int mgwr_net_sync_weights(mgwr_net* net) {
   hipLaunchKernelGGL(round_bf16_kernel, dim3(grid_of((long long)net->nparam)), dim3(256), 0, net->stream,
                      net->params, net->wbf, (long long)net->nparam);
   NET_TRY(hipGetLastError());
-  return MGWR_OK;
+  return refresh_mfma_weights(net);
 }
 
 int mgwr_net_forward(mgwr_net* net, const float* x, int B, int H, int W, double h, float* y) {
@@ -834,7 +966,7 @@ int mgwr_net_forward(mgwr_net* net, const float* x, int B, int H, int W, double 
   if (rc) return rc;
   if (!x || !y) return nfail(MGWR_ERR_INVALID_ARG, "null array");
   if (!valid_h(h)) return nfail(MGWR_ERR_INVALID_ARG, "h must be positive");
-  if ((rc = net_forward(net, x, g, h))) return rc;
+  if ((rc = net_forward(net, x, g, h, true))) return rc;
   NET_TRY(hipMemcpyAsync(y, net->ybuf, (size_t)B * net->ch.back() * g.hw[0] * 4, hipMemcpyDeviceToDevice,
                          net->stream));
   return MGWR_OK;
@@ -847,7 +979,7 @@ int mgwr_net_gradient(mgwr_net* net, const float* x, const float* target, int B,
   if (rc) return rc;
   if (!x || !target) return nfail(MGWR_ERR_INVALID_ARG, "null array");
   if (!valid_h(h)) return nfail(MGWR_ERR_INVALID_ARG, "h must be positive");
-  if ((rc = net_forward(net, x, g, h))) return rc;
+  if ((rc = net_forward(net, x, g, h, false))) return rc;
   const int L = net->L(), CL = net->ch.back(), C0 = net->ch[0];
   const long long per = (long long)CL * g.hw[0];
   hipLaunchKernelGGL(loss_norms_kernel, dim3(B), dim3(256), 0, net->stream, net->ybuf, target, per, net->norms);
@@ -918,7 +1050,7 @@ int mgwr_net_adam_step(mgwr_net* net, float lr, float beta1, float beta2, float 
   hipLaunchKernelGGL(adam_kernel, dim3(grid_of((long long)net->nparam)), dim3(256), 0, net->stream, net->params,
                      net->grad, net->m, net->v, net->wbf, (long long)net->nparam, lr, beta1, beta2, eps, c1, c2);
   NET_TRY(hipGetLastError());
-  return MGWR_OK;
+  return refresh_mfma_weights(net);
 }
 
 int mgwr_net_destroy(mgwr_net* net) {
@@ -947,7 +1079,7 @@ int net_infer(mgwr_net* net, const float* x, int H, int W, double h, const float
   hipStream_t keep = net->stream;
   net->stream = net->capture_stream;
   NET_TRY(hipStreamBeginCapture(net->capture_stream, hipStreamCaptureModeRelaxed));
-  rc = net_forward(net, x, g, h);
+  rc = net_forward(net, x, g, h, true);
   hipGraph_t gr = nullptr;
   const hipError_t e = hipStreamEndCapture(net->capture_stream, &gr);
   net->stream = keep;

@@ -2,8 +2,15 @@
 float64 network oracle, and the warm-started solve judged by the oracle.
 
 Weights are rounded to bfloat16 on the host first, so that the library's
-bfloat16 copies are exact and the only differences left are float32
-rounding in the kernels."""
+bfloat16 copies are exact.  Inference runs on the bfloat16 matrix cores, which
+round every convolution input to bfloat16: it is compared with the oracle
+that rounds at the same place (act_bf16).  Both sides take that rounding from
+float32 sums accumulated in different orders, so an activation next to a
+rounding boundary can land one bfloat16 step apart; the bound FWD_TOL covers a
+few such flips, and every check also asserts that the output is much closer to
+the rounding oracle than to the unrounded one (a wrong operand layout or a
+missing rounding fails that).  Training runs the float32 kernels; its
+gradient is compared with the unrounded oracle."""
 import numpy as np
 import pytest
 
@@ -37,6 +44,21 @@ def bf16_params(channels, seed, scale=1.0):
     return N.bf16_round(out)
 
 
+FWD_TOL = 4e-4
+
+
+def assert_inference_matches(y, params, channels, x, nsig, h, h_min=0.0):
+    ref = N.forward(params.astype(np.float64), channels, x.astype(np.float64), nsig, h, h_min=h_min, act_bf16=True)
+    plain = N.forward(params.astype(np.float64), channels, x.astype(np.float64), nsig, h, h_min=h_min)
+    scale = np.abs(ref).max()
+    err = np.abs(y - ref).max() / scale
+    err_plain = np.abs(y - plain).max() / scale
+    print(f"  inference vs rounding oracle {err:.2e}, vs unrounded oracle {err_plain:.2e}", flush=True)
+    assert err <= FWD_TOL, err
+    assert np.median(np.abs(y - ref)) <= 1e-5 * scale
+    assert err < 0.25 * err_plain, (err, err_plain)
+
+
 def make(channels, nsig, params, max_bhw):
     net = mg.Net(channels, nsig, max_bhw)
     net.set_params(params)
@@ -61,9 +83,7 @@ def test_forward_matches_oracle(dev, channels, nsig, B, H, W):
     x = rng.standard_normal((B, channels[0] - 1, H, W)).astype(np.float32)
     h = 1.0 / (W + 1)
     y = net.forward(torch.as_tensor(x, device=dev), h).cpu().numpy()
-    ref = N.forward(p.astype(np.float64), channels, x.astype(np.float64), nsig, h)
-    err = np.abs(y - ref).max() / np.abs(ref).max()
-    assert err < 2e-5, err
+    assert_inference_matches(y, p, channels, x, nsig, h)
 
 
 @pytest.mark.parametrize("H,W", [(1, 63), (15, 15)])
@@ -78,8 +98,7 @@ def test_finest_level_cutoff_matches_oracle(dev, H, W):
     t = rng.standard_normal((B, channels[-1], H, W)).astype(np.float32) * 1e-3
     xd, td = torch.as_tensor(x, device=dev), torch.as_tensor(t, device=dev)
     y = net.forward(xd, h).cpu().numpy()
-    ref = N.forward(p.astype(np.float64), channels, x.astype(np.float64), nsig, h, h_min=2 * h)
-    assert np.abs(y - ref).max() <= 2e-5 * np.abs(ref).max()
+    assert_inference_matches(y, p, channels, x, nsig, h, h_min=2 * h)
     _, g = net.gradient(xd, td, h)
     _, rg = N.gradient(p.astype(np.float64), channels, x.astype(np.float64), t.astype(np.float64), nsig, h,
                        h_min=2 * h)
@@ -135,8 +154,7 @@ def test_adam_step_matches_oracle(dev):
     for cin, cout in zip(channels[:-1], channels[1:]):
         pw[off:off + cout * cin * 9] = N.bf16_round(pw[off:off + cout * cin * 9])
         off += cout * cin * 9 + cout
-    ref = N.forward(pw.astype(np.float64), channels, x.cpu().numpy().astype(np.float64), nsig, h)
-    assert np.abs(y - ref).max() <= 2e-5 * np.abs(ref).max()
+    assert_inference_matches(y, pw, channels, x.cpu().numpy(), nsig, h)
 
 
 def test_net_rejects_bad_shapes(dev):
@@ -163,7 +181,7 @@ def _oracle_guess(p, params, channels, plan):
     b = oracle.rhs(p.f, p.t, p.alpha, None)
     x, scale = N.warm_start_input(b, rows, p.alpha, p.r, p.dim, p.n)
     y = N.forward(params.astype(np.float64), channels, x.astype(np.float32).astype(np.float64), len(rows),
-                  1.0 / (p.n + 1))
+                  1.0 / (p.n + 1), act_bf16=True)
     U0 = N.time_interp(scale * y[0].reshape(len(rows), -1), rows, p.t, alpha=p.alpha)
     Rt = plan.export_dense()
     r = oracle.residual(Rt, U0, b, p.dim, p.n, p.length)

@@ -236,3 +236,28 @@ def test_warm_start_input_hand_built_case():
     want[1, 2] = -1.0
     assert np.array_equal(x2[0, 0], want)
     assert np.all(x2[0, 1] == 0.5) and np.all(x2[0, 2] == 0.3)
+
+
+def test_bf16_activations_leave_bf16_inputs_unchanged():
+    """With one layer on a single-level grid (W = 3, h = 1: the band is the
+    signal, the level value log2(1/h)/10 is 0) and inputs that are bfloat16
+    numbers, rounding the convolution input changes nothing."""
+    rng = np.random.default_rng(4)
+    ch = [4, 3]
+    params = N.bf16_round(rng.standard_normal(N.param_count(ch)).astype(np.float32)).astype(np.float64)
+    x = N.bf16_round(rng.standard_normal((2, 3, 1, 3)).astype(np.float32)).astype(np.float64)
+    assert np.array_equal(N.forward(params, ch, x, 2, 1.0, act_bf16=True), N.forward(params, ch, x, 2, 1.0))
+
+
+def test_bf16_activations_stay_within_one_rounding_of_each_input():
+    """One layer, general inputs: the output moves by at most the bfloat16
+    half-step (2^-9 relative) of every input, weighted by |w| (h = 1, W = 3)."""
+    rng = np.random.default_rng(5)
+    ch = [4, 3]
+    params = rng.standard_normal(N.param_count(ch))
+    x = rng.standard_normal((2, 3, 1, 3))
+    d = N.forward(params, ch, x, 2, 1.0, act_bf16=True) - N.forward(params, ch, x, 2, 1.0)
+    (w, b), = N.unpack(params, ch)
+    xin = N.level_inputs(x, 2, 1.0)[0][0]
+    bound = 4.0 * N.conv3x3(np.abs(xin), np.abs(w), np.zeros_like(b)) * 2.0 ** -8
+    assert np.all(np.abs(d) <= bound + 1e-15) and np.abs(d).max() > 0
