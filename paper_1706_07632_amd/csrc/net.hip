@@ -509,20 +509,38 @@ __global__ void round_bf16_kernel(const float* __restrict__ p, uint16_t* __restr
 // l, c = l % 16, g = l / 16): A lane holds row c, K entries 8g .. 8g+7; B
 // lane holds column c, the same K entries; the result element r of lane l is
 // row 4g + r, column c.  A block of 4 waves covers 64 pixels (16 per wave)
-// and 64 output channels (4 tiles of 16, grid.y over the rest).
+// and 64 output channels (4 tiles of 16, grid.y over the rest); one launch
+// covers every level of the pyramid (the small levels alone would leave the
+// chip idle and pay a launch each).
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kMfmaK = 32;
 
-__global__ __launch_bounds__(256) void conv_fwd_mfma_kernel(const float* __restrict__ x,
+// Every pyramid level of one layer in one launch: level l owns the blocks
+// [blk0[l], blk0[l+1]) and reads/writes its own arena regions.
+constexpr int kMaxConvLevels = 32;
+struct ConvLevels {
+  int n;                                   // levels in the table
+  int blk0[kMaxConvLevels + 1];            // first block of each level (blk0[n] = total)
+  int H[kMaxConvLevels], W[kMaxConvLevels];
+  long long in_off[kMaxConvLevels], out_off[kMaxConvLevels];  // floats from the arena bases
+};
+
+__global__ __launch_bounds__(256) void conv_fwd_mfma_kernel(const float* __restrict__ xbase,
                                                             const uint16_t* __restrict__ wk,
-                                                            const float* __restrict__ bias, float* __restrict__ y,
-                                                            int B, int cin, int cpad, int cout, int H, int W, int act) {
+                                                            const float* __restrict__ bias, float* __restrict__ ybase,
+                                                            int B, int cin, int cpad, int cout, ConvLevels lv,
+                                                            int act) {
+  int l = 0;
+  while (l + 1 < lv.n && (int)blockIdx.x >= lv.blk0[l + 1]) ++l;   // uniform across the block
+  const int H = lv.H[l], W = lv.W[l];
+  const float* __restrict__ x = xbase + lv.in_off[l];
+  float* __restrict__ y = ybase + lv.out_off[l];
   const int HW = H * W;
   const long long total = (long long)B * HW;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int c = lane & 15, g = lane >> 4;
-  const long long t = ((long long)blockIdx.x * 4 + wave) * 16 + c;   // this lane's pixel (B column)
+  const long long t = ((long long)(blockIdx.x - lv.blk0[l]) * 4 + wave) * 16 + c;   // this lane's pixel
   const bool tok = t < total;
   const long long tt = tok ? t : 0;
   const int b = (int)(tt / HW), p = (int)(tt % HW);
@@ -532,22 +550,32 @@ __global__ __launch_bounds__(256) void conv_fwd_mfma_kernel(const float* __restr
   f32x4 acc[4];
 #pragma unroll
   for (int tl = 0; tl < 4; ++tl) acc[tl] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  // the nine taps' neighbour offsets (-1: outside the grid or past the end)
+  long long off[9];
+#pragma unroll
   for (int k = 0; k < 9; ++k) {
     const int yy = py + k / 3 - 1, xx = px + k % 3 - 1;
-    const bool ok = tok && yy >= 0 && yy < H && xx >= 0 && xx < W;
-    const long long off = ok ? (long long)yy * W + xx : 0;
-    for (int k0 = 0; k0 < cpad; k0 += kMfmaK) {
-      bf16x8 bv;
+    off[k] = (tok && yy >= 0 && yy < H && xx >= 0 && xx < W) ? (long long)yy * W + xx : -1;
+  }
+  for (int k0 = 0; k0 < cpad; k0 += kMfmaK) {
+    // all nine taps' activations of this K chunk are loaded before the
+    // products, so the loads overlap instead of waiting one tap at a time
+    bf16x8 bv[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int ci = k0 + 8 * g + j;
-        const float v = (ok && ci < cin) ? xb[(long long)ci * HW + off] : 0.0f;
-        bv[j] = __builtin_bit_cast(__bf16, f32_to_bf16(v));
+        const float v = (off[k] >= 0 && ci < cin) ? xb[(long long)ci * HW + off[k]] : 0.0f;
+        bv[k][j] = __builtin_bit_cast(__bf16, f32_to_bf16(v));
       }
+    }
 #pragma unroll
-      for (int tl = 0; tl < 4; ++tl) {
-        if (co0 + 16 * tl >= cout) break;   // uniform across the wave
-        const int co = co0 + 16 * tl + c;
+    for (int tl = 0; tl < 4; ++tl) {
+      if (co0 + 16 * tl >= cout) break;   // uniform across the wave
+      const int co = co0 + 16 * tl + c;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
         bf16x8 av;
         if (co < cout) {
           av = *reinterpret_cast<const bf16x8*>(wk + ((long long)k * cout + co) * cpad + k0 + 8 * g);
@@ -555,7 +583,7 @@ __global__ __launch_bounds__(256) void conv_fwd_mfma_kernel(const float* __restr
 #pragma unroll
           for (int j = 0; j < 8; ++j) av[j] = __builtin_bit_cast(__bf16, (uint16_t)0);
         }
-        acc[tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[tl], 0, 0, 0);
+        acc[tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[k], acc[tl], 0, 0, 0);
       }
     }
   }
@@ -607,25 +635,45 @@ __global__ void gather_slices_kernel(const double* __restrict__ b, const int* __
 // linear in the variable s = t^alpha (tp[m] = t_m^alpha): slice k sits at
 // tp[rows[k] + 1].  Before the first slice it runs from the initial value g
 // (zero if null) at tp[0]; after the last slice it stays constant.
+// Slices a solver prediction may take (the plan's limit).
+constexpr int kMaxSlices = 64;
+
 __global__ void time_interp_kernel(const float* __restrict__ y, const int* __restrict__ rows, int nslices,
                                    const double* __restrict__ t, const double* __restrict__ g, long long M,
                                    long long N, double scale, double* __restrict__ u) {
-  const long long total = M * N;
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
-       idx += (long long)gridDim.x * blockDim.x) {
-    const long long m = idx / N, q = idx % N;
+  // blockIdx.y walks the time rows: the bracketing slices and the weights
+  // are the same for the whole row, the columns are plain coalesced streams
+  __shared__ int srows[kMaxSlices];
+  for (int i = threadIdx.x; i < nslices; i += blockDim.x) srows[i] = rows[i];
+  __syncthreads();
+  for (long long m = blockIdx.y; m < M; m += gridDim.y) {
     int s = 0;
-    while (s < nslices && rows[s] < m) ++s;
-    double v;
-    if (s == nslices) v = scale * y[(long long)(nslices - 1) * N + q];
-    else if (rows[s] == m) v = scale * y[(long long)s * N + q];
-    else {
-      const double ta = s == 0 ? t[0] : t[rows[s - 1] + 1];
-      const double ya = s == 0 ? (g ? g[q] : 0.0) : scale * y[(long long)(s - 1) * N + q];
-      const double tb = t[rows[s] + 1], yb = scale * y[(long long)s * N + q];
-      v = ya + (yb - ya) * (t[m + 1] - ta) / (tb - ta);
+    while (s < nslices && srows[s] < m) ++s;
+    // u[m][q] = wa * ya[q] + wb * yb[q], ya from slice sa (-1: g, or zero)
+    int sa, sb;
+    double wa, wb;
+    if (s == nslices) {
+      sa = -2; sb = nslices - 1; wa = 0.0; wb = scale;
+    } else if (srows[s] == m) {
+      sa = -2; sb = s; wa = 0.0; wb = scale;
+    } else {
+      const double ta = s == 0 ? t[0] : t[srows[s - 1] + 1];
+      const double tb = t[srows[s] + 1];
+      const double th = (t[m + 1] - ta) / (tb - ta);
+      sa = s - 1; sb = s;
+      wa = 1.0 - th; wb = scale * th;
     }
-    u[idx] = v;
+    const float* yb = y + (long long)sb * N;
+    const float* ya = sa >= 0 ? y + (long long)sa * N : nullptr;
+    const double* ga = sa == -1 ? g : nullptr;
+    double* um = u + m * N;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < N;
+         q += (long long)gridDim.x * blockDim.x) {
+      double v = wb * (double)yb[q];
+      if (ya) v += wa * (scale * (double)ya[q]);
+      else if (ga) v += wa * ga[q];
+      um[q] = v;
+    }
   }
 }
 
@@ -643,8 +691,12 @@ hipError_t launch_gather_slices(const double* b, const int* rows, int nslices, l
 
 hipError_t launch_time_interp(const float* y, const int* rows, int nslices, const double* t, const double* g,
                               long long M, long long N, double scale, double* u, hipStream_t s) {
-  hipLaunchKernelGGL(time_interp_kernel, dim3(grid_of(M * N)), dim3(256), 0, s, y, rows, nslices, t, g, M, N, scale,
-                     u);
+  if (nslices < 1 || nslices > kMaxSlices) return hipErrorInvalidValue;
+  // a few blocks per row (each thread streams several columns), rows over y
+  const long long gx = std::min<long long>((N + 255) / 256, 16);
+  const long long gy = std::min<long long>(M, 65535);
+  hipLaunchKernelGGL(time_interp_kernel, dim3((unsigned)std::max<long long>(gx, 1), (unsigned)std::max<long long>(gy, 1)),
+                     dim3(256), 0, s, y, rows, nslices, t, g, M, N, scale, u);
   return hipGetLastError();
 }
 
@@ -782,19 +834,39 @@ int check_net(mgwr_net* net, int B, int H, int W, Geo* g) {
   return MGWR_OK;
 }
 
-int launch_conv_fwd(mgwr_net* net, int j, const float* in, float* out, int B, int H, int W, bool mfma) {
+int launch_conv_fwd(mgwr_net* net, int j, const float* in, float* out, int B, int H, int W) {
   const int cin = net->ch[j], cout = net->ch[j + 1];
   const long long px = (long long)B * H * W;
-  if (mfma) {
-    dim3 grid((unsigned)((px + 63) / 64), (unsigned)((cout + 63) / 64));
-    hipLaunchKernelGGL(conv_fwd_mfma_kernel, grid, dim3(256), 0, net->stream, in, net->wmf + net->mfoff[j],
-                       net->params + net->boff[j], out, B, cin, net->cpad[j], cout, H, W, j + 1 < net->L() ? 1 : 0);
-    NET_TRY(hipGetLastError());
-    return MGWR_OK;
-  }
   dim3 grid((unsigned)((px + 256 * kPx - 1) / (256 * kPx)), (unsigned)((cout + kCoTile - 1) / kCoTile));
   hipLaunchKernelGGL(conv_fwd_kernel, grid, dim3(256), 0, net->stream, in, net->wbf + net->woff[j],
                      net->params + net->boff[j], out, B, cin, cout, H, W, j + 1 < net->L() ? 1 : 0);
+  NET_TRY(hipGetLastError());
+  return MGWR_OK;
+}
+
+// Layer j of every active level on the matrix cores, one launch; in_base /
+// out_base are the arenas (level l at B * channels * cum[l]).
+int launch_conv_fwd_mfma(mgwr_net* net, int j, const float* in_base, float* out_base, const Geo& g, double h0) {
+  const int B = g.B, cin = net->ch[j], cout = net->ch[j + 1];
+  ConvLevels lv{};
+  long long blocks = 0;
+  for (int l = 0; l < g.nlev; ++l) {
+    if (!net->active(std::ldexp(h0, l))) continue;
+    if (lv.n == kMaxConvLevels) return nfail(MGWR_ERR_INVALID_ARG, "too many pyramid levels");
+    lv.blk0[lv.n] = (int)blocks;
+    lv.H[lv.n] = g.two_d ? g.n[l] : 1;
+    lv.W[lv.n] = g.n[l];
+    lv.in_off[lv.n] = (long long)B * cin * g.cum[l];
+    lv.out_off[lv.n] = (long long)B * cout * g.cum[l];
+    blocks += ((long long)B * g.hw[l] + 63) / 64;
+    if (blocks > 0x7fffffffLL) return nfail(MGWR_ERR_INVALID_ARG, "grid too large");
+    ++lv.n;
+  }
+  if (lv.n == 0) return MGWR_OK;
+  lv.blk0[lv.n] = (int)blocks;
+  dim3 grid((unsigned)blocks, (unsigned)((cout + 63) / 64));
+  hipLaunchKernelGGL(conv_fwd_mfma_kernel, grid, dim3(256), 0, net->stream, in_base, net->wmf + net->mfoff[j],
+                     net->params + net->boff[j], out_base, B, cin, net->cpad[j], cout, lv, j + 1 < net->L() ? 1 : 0);
   NET_TRY(hipGetLastError());
   return MGWR_OK;
 }
@@ -839,12 +911,17 @@ int net_forward(mgwr_net* net, const float* x, const Geo& g, double h0, bool mfm
                        sig_at(l), sig_bs(l), sn, x, xin, B, S, E, g.n[l], g.W, 1 << l, g.two_d,
                        (float)(std::log2(1.0 / hl) / 10.0));
     NET_TRY(hipGetLastError());
+    if (mfma) continue;   // the matrix-core layers run all levels at once below
     const float* in = xin;
     for (int j = 0; j < net->L(); ++j) {
       float* out = net->act[j] + (size_t)B * net->ch[j + 1] * g.cum[l];
-      if ((rc = launch_conv_fwd(net, j, in, out, B, Hl, Wl, mfma))) return rc;
+      if ((rc = launch_conv_fwd(net, j, in, out, B, Hl, Wl))) return rc;
       in = out;
     }
+  }
+  if (mfma) {
+    for (int j = 0; j < net->L(); ++j)
+      if ((rc = launch_conv_fwd_mfma(net, j, j == 0 ? net->xin : net->act[j - 1], net->act[j], g, h0))) return rc;
   }
   for (int l = g.nlev - 1; l >= 0; --l) {
     const double hl = std::ldexp(h0, l);
