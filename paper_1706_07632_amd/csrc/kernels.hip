@@ -719,6 +719,9 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
   }
 }
 
+// XCDs of the chip (MI355X: 8, 32 compute units each).
+constexpr int kXcds = 8;
+
 template <typename T, int MODE, bool DEEP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void march_kernel(MarchArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -726,7 +729,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void m
   if (threadIdx.x == 0) sh_abort = 0;
   __syncthreads();
   PipeCtx pc{};
-  march_body<T, MODE, false, DEEP>(a, blockIdx.x, pc, smem_raw, &sh_abort);
+  // Workgroups go to the XCDs round-robin (b mod kXcds), each XCD with its
+  // own L2.  Chains are handed out in contiguous bands per XCD, so the
+  // chains holding a 2D line's neighbours in the rows above and below
+  // (about one grid row of chains away) run on the same XCD and find those
+  // rows in its L2.  The grid is rounded up to whole bands; the surplus
+  // workgroups have no chain.
+  const int nchunks = (a.ncols + 15) / 16;
+  const int band = (nchunks + kXcds - 1) / kXcds;
+  const int chunk = (int)(blockIdx.x % kXcds) * band + (int)(blockIdx.x / kXcds);
+  if (chunk >= nchunks) return;
+  march_body<T, MODE, false, DEEP>(a, chunk, pc, smem_raw, &sh_abort);
 }
 
 // Time leaves from which a march launched on its own takes the deep prefetch.
@@ -1247,7 +1260,8 @@ size_t march_lds_bytes(const MarchArgs<T>& a) {
 template <typename T>
 hipError_t launch_march(int mode, const MarchArgs<T>& a, hipStream_t s) {
   if (a.ncols <= 0) return hipSuccess;
-  dim3 grid((a.ncols + 15) / 16), block(64 * NW);
+  const int nchunks = (a.ncols + 15) / 16;
+  dim3 grid((unsigned)(((nchunks + kXcds - 1) / kXcds) * kXcds)), block(64 * NW);
   size_t lds = march_lds_bytes(a);
   const bool deep = a.prefetch == 2 || (a.prefetch == 0 && a.nleaf >= kDeepPrefetchLeaves);
   switch (mode * 2 + (deep ? 1 : 0)) {
