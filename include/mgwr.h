@@ -281,8 +281,10 @@ int mgwr_batch_graph_replays(const mgwr_batch* batch, long long* replays);
  * cycles time-pipelined in one launch; staged launches per operator with the
  * shallow or the deep operand prefetch in the marches (see
  * mgwr_plan_set_staging) and the coarse pipelined launch starting at the
- * level the rule picks or one level either side.  The choice holds for this
- * plan and for every MGWR_SCHED_AUTO plan of the same (dim, n, M, precision,
+ * level the rule picks or one level either side; in 2D the best of these is
+ * then timed once more in the other storage (mgwr_plan_set_layout).  The
+ * choice holds for this plan and for every MGWR_SCHED_AUTO plan of the same
+ * (dim, n, M, precision,
  * inner cycles, k) in this process; the schedule is returned in *chosen
  * (MGWR_SCHED_STAGED or MGWR_SCHED_PIPELINED, nullable).  u receives the
  * solution.  A batch runs its pipelined instances in one merged launch and
@@ -305,6 +307,22 @@ int mgwr_plan_set_staging(mgwr_plan* plan, int prefetch, int coarse_level);
  * deep) and coarse level (0 none) of the staged schedule.  Host only;
  * every pointer nullable. */
 int mgwr_plan_tuned(const mgwr_plan* plan, int* schedule, int* prefetch, int* coarse_level);
+
+/* Storage of the space-time arrays of a 2D plan inside its solves (host
+ * only; the iterates and the cycle are the same, bit for bit).  The caller's
+ * f, g, u are always in the natural order of the array layout above.
+ * MGWR_LAYOUT_SPLIT: every time row holds the first colour's points (the
+ * even flat indices q, in order) and then the second colour's (the odd
+ * ones), at every level, so a half-sweep of the red-black relaxation reads
+ * and writes whole contiguous lines and the grid transfers touch one colour
+ * block at a time; b = f + a_1 g is formed in it, a given initial iterate is
+ * moved in at the start and the result moved back at the end (two passes
+ * over u each).  MGWR_LAYOUT_NATURAL: natural order throughout.
+ * MGWR_LAYOUT_AUTO (the default): the autotuner's choice for the shape, else
+ * SPLIT.  1D plans always use the natural order.  MGWR_ERR_INVALID_ARG for
+ * other values. */
+enum { MGWR_LAYOUT_AUTO = -1, MGWR_LAYOUT_NATURAL = 0, MGWR_LAYOUT_SPLIT = 1 };
+int mgwr_plan_set_layout(mgwr_plan* plan, int layout);
 
 /* Learned initial guess.  Not part of the paper's method, which starts its
  * iteration from a given iterate: this network only proposes that iterate,
@@ -406,6 +424,7 @@ typedef struct {
   int M, nleaf, nclusters, ndense, nrk, nzclusters, nslots, window, levels, k;
   long long stored_entries;  /* dense entries + k (|rows| + |cols|) over low-rank blocks */
   double shift0;             /* c_0 = 2 dim / h^2 */
+  int layout;                /* storage the next solve uses: MGWR_LAYOUT_NATURAL or MGWR_LAYOUT_SPLIT */
   int nf64leaves;            /* leaves solved in float64 inside float32 cycles (steps within the leaf
                                 differ by more than 8x: the near-origin leaves of graded meshes) */
 } mgwr_plan_info;

@@ -38,7 +38,8 @@ EXPORTED = [
     "mgwr_net_sync_weights", "mgwr_net_forward", "mgwr_net_gradient", "mgwr_net_set_finest",
     "mgwr_net_adam_step", "mgwr_net_destroy",
     "mgwr_plan_set_warm_start", "mgwr_batch_set_graph", "mgwr_batch_graph_replays", "mgwr_plan_autotune",
-    "mgwr_plan_set_staging", "mgwr_plan_tuned", "mgwr_apply_A", "mgwr_model_describe", "mgwr_model_load",
+    "mgwr_plan_set_staging", "mgwr_plan_tuned", "mgwr_plan_set_layout", "mgwr_apply_A", "mgwr_model_describe",
+    "mgwr_model_load",
     "mgwr_solve_static",
 ]
 
@@ -99,7 +100,7 @@ class PlanInfo(ctypes.Structure):
                 ("ndense", ctypes.c_int), ("nrk", ctypes.c_int), ("nzclusters", ctypes.c_int),
                 ("nslots", ctypes.c_int), ("window", ctypes.c_int), ("levels", ctypes.c_int),
                 ("k", ctypes.c_int), ("stored_entries", ctypes.c_longlong), ("shift0", ctypes.c_double),
-                ("nf64leaves", ctypes.c_int)]
+                ("layout", ctypes.c_int), ("nf64leaves", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -145,6 +146,7 @@ def lib():
     L.mgwr_batch_graph_replays.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong)]
     L.mgwr_plan_autotune.argtypes = [vp, vp, vp, ctypes.c_double, vp, ctypes.POINTER(ctypes.c_int)]
     L.mgwr_plan_set_staging.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    L.mgwr_plan_set_layout.argtypes = [vp, ctypes.c_int]
     ipp = ctypes.POINTER(ctypes.c_int)
     L.mgwr_plan_tuned.argtypes = [vp, ipp, ipp, ipp]
     L.mgwr_net_create.argtypes = [ip, ctypes.POINTER(ctypes.c_int), ip, ctypes.POINTER(vp)]
@@ -397,6 +399,18 @@ class Plan:
         2 deep) and the level the coarse pipelined launch starts at (-1 by
         rule, 0 none)."""
         _check(lib().mgwr_plan_set_staging(self._h, int(prefetch), int(coarse_level)))
+        return self
+
+    LAYOUTS = {"auto": -1, "natural": 0, "split": 1}
+
+    def set_layout(self, layout: str = "auto"):
+        """Storage of a 2D plan's arrays inside its solves: "split" (each
+        time row holds the first colour's points, then the second's),
+        "natural", or "auto" (the autotuner's choice, else split).  The
+        caller's arrays are always in natural order."""
+        if layout not in self.LAYOUTS:
+            raise ValueError(f"layout must be one of {sorted(self.LAYOUTS)}")
+        _check(lib().mgwr_plan_set_layout(self._h, self.LAYOUTS[layout]))
         return self
 
     def tuned(self):

@@ -36,7 +36,12 @@ struct MarchArgs {
   T* U;               // iterate: written (SMOOTH, TRSM) or read (RESID, MATVEC)
   T* Out;             // defect (RESID) or product (MATVEC)
   long long ld;
+  // columns: storage index cstride * p + coff (natural layout), or coff + p
+  // in the colour-split layout of 2D grids (split = 1: the n0 = (N + 1) / 2
+  // even flat indices first, then the odd ones; neighbours are mapped)
   int ncols, cstride, coff;
+  int split;
+  long long n0;
   // stencil: dim 0 (none), 1 or 2; n points per side; 1/h^2
   int dim, n;
   T inv_h2;
@@ -82,6 +87,7 @@ struct Stage {
   int dim, nf, nc;
   int red_only;          // STG_RESTRICT*: the defect is held on the first colour only (see launch_restrict)
   int black_only;        // STG_PROLONG*: correct the second-colour points only (see launch_prolong)
+  int split;             // STG_RESTRICT* / STG_PROLONG*: 2D grids in colour-split storage (see MarchArgs)
   long long npoints;     // STG_CAST / STG_CORRECT: points per time row
 };
 
@@ -111,13 +117,18 @@ template <typename T> hipError_t set_march_lds_limit(size_t bytes);
 // points and, in 2D, the diagonal neighbours); the other colour's defect is
 // zero after its line solves and its entries are not read.
 template <typename T> hipError_t launch_restrict(const T* rf, T* fc, int dim, int nf, int M, bool red_only,
-                                                 hipStream_t s);
+                                                 bool split, hipStream_t s);
 // black_only: only the second-colour fine points are corrected.  A
 // first-colour half-sweep that follows reads the iterate only there (its own
 // lines are solved afresh), so the other corrections would be overwritten
 // unread.
 template <typename T> hipError_t launch_prolong(const T* ec, T* uf, int dim, int nf, int M, bool black_only,
-                                                hipStream_t s);
+                                                bool split, hipStream_t s);
+// Colour-split storage of 2D grids (see MarchArgs): b = f + a_1 g written in
+// it (gq may be null), and whole [M][N] arrays moved into or out of it.
+hipError_t launch_rhs0_split(const double* f, const double* gq, const double* a1, double* b, long long M,
+                             long long N, hipStream_t s);
+hipError_t launch_relayout(const double* src, double* dst, long long M, long long N, bool to_split, hipStream_t s);
 hipError_t launch_rhs0(const double* f, const double* gq, const double* a1, double* b, long long M, long long N,
                        hipStream_t s);
 template <typename T> hipError_t launch_fill(T* x, long long count, T v, hipStream_t s);

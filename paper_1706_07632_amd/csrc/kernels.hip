@@ -120,6 +120,11 @@ __device__ __forceinline__ void gst(T* p, T v) {
   }
 }
 
+// Colour-split storage of a 2D grid (see MarchArgs): storage index of flat
+// index q, and back; n0 = (N + 1) / 2 even flat indices come first.
+__device__ __forceinline__ long long split_index(long long q, long long n0) { return (q & 1) ? n0 + (q >> 1) : (q >> 1); }
+__device__ __forceinline__ long long natural_index(long long s, long long n0) { return s < n0 ? 2 * s : 2 * (s - n0) + 1; }
+
 // Progress hand-off between pipeline stages.  done[i] counts the work items of
 // a stage that have finished (and made visible) their rows of leaf i.
 struct PipeCtx {
@@ -251,7 +256,18 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
   const int c = lane & 15;
   const int p = chunk * 16 + c;
   const bool colok = p < a.ncols;
-  const long long q = colok ? (long long)a.cstride * p + a.coff : 0;
+  // The column's natural flat index q (grid position) and its storage index
+  // qs.  Colour-split storage (2D): the even flat indices (first colour)
+  // come first, qs = q / 2, then the odd ones, qs = n0 + (q - 1) / 2; column
+  // p is storage index coff + p, so a half-sweep's lines are contiguous.
+  long long q, qs;
+  if (a.split) {
+    qs = colok ? (long long)a.coff + p : 0;
+    q = qs < a.n0 ? 2 * qs : 2 * (qs - a.n0) + 1;
+  } else {
+    q = colok ? (long long)a.cstride * p + a.coff : 0;
+    qs = q;
+  }
 
   long long nb[4] = {0, 0, 0, 0};
   bool nbok[4] = {false, false, false, false};
@@ -271,6 +287,10 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
     nb[1] = q + 1;   nbok[1] = colok && ix + 1 < a.n;
     nb[2] = q - a.n; nbok[2] = colok && iy >= 1;
     nb[3] = q + a.n; nbok[3] = colok && iy + 1 < a.n;
+    if (a.split) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) nb[e] = (nb[e] & 1) ? a.n0 + (nb[e] >> 1) : (nb[e] >> 1);
+    }
   }
   const T diagc = (T)(2 * a.dim);
   // Low-rank factor operands as ld_lr() loaded them, made values of T.  Every
@@ -347,7 +367,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
       const int row = drow<T>(g, r);
       const bool ok = colok && row < d.sz;
       const long long off = (long long)(d.lo + (ok ? row : 0)) * a.ld;
-      pf_f[r] = (MODE != MODE_MATVEC && ok) ? gld<PIPE>(a.F + off + q) : (T)0;
+      pf_f[r] = (MODE != MODE_MATVEC && ok) ? gld<PIPE>(a.F + off + qs) : (T)0;
       const T* ecrow = fuse_ec ? a.Ec + (long long)(d.lo + (ok ? row : 0)) * a.nc : nullptr;
 #pragma unroll
       for (int e = 0; e < NB; ++e) {
@@ -356,7 +376,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
                          ? gld<PIPE>(src) : (T)0;
       }
       pf_c[r] = (fuse_ec && ok && p < a.nc) ? gld<PIPE>(ecrow + p) : (T)0;
-      pf_u[r] = (kKnownX && ok) ? gld<PIPE>(a.U + off + q) : (T)0;
+      pf_u[r] = (kKnownX && ok) ? gld<PIPE>(a.U + off + qs) : (T)0;
     }
     return true;
   };
@@ -661,7 +681,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
           }
           const bool ok = colok && row < d.sz;
           cur[row * 16 + c] = ok ? x[r] : (T)0;
-          if (ok) gst<PIPE>(a.U + (long long)(d.lo + row) * a.ld + q, x[r]);
+          if (ok) gst<PIPE>(a.U + (long long)(d.lo + row) * a.ld + qs, x[r]);
         }
       } else {
 #pragma unroll
@@ -675,7 +695,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
                 gst<PIPE>(a.Inj0 + (long long)(d.lo + row) * a.nc + p, (T)0);
               }
             } else {
-              gst<PIPE>(a.Out + (long long)(d.lo + row) * a.ld + q, v);
+              gst<PIPE>(a.Out + (long long)(d.lo + row) * a.ld + qs, v);
             }
             if constexpr (PIPE) {
               if (!(v == v) || __builtin_isinf(v)) nbad = true;
@@ -772,9 +792,12 @@ __device__ __forceinline__ void restrict_stage(const Stage& st, int chunk, const
   const int nf = st.nf, nc = st.nc;
   const long long Nc = st.dim == 1 ? nc : (long long)nc * nc;
   const long long Nf = st.dim == 1 ? nf : (long long)nf * nf;
-  const long long Q = (long long)chunk * kStencilCols + (threadIdx.x % kStencilCols);
+  const long long Q = (long long)chunk * kStencilCols + (threadIdx.x % kStencilCols);   // storage index
   const int r0 = threadIdx.x / kStencilCols;
   const bool ok = Q < Nc;
+  const bool split = st.split;
+  const long long n0f = (Nf + 1) / 2;
+  const long long Qn = split ? natural_index(Q, (Nc + 1) / 2) : Q;   // natural flat index
   const int lane = threadIdx.x & 63;
   // fine-grid offsets of the 9-point (2D) / 3-point (1D) weighted stencil;
   // tap t sits at a fixed index (registers, not private memory).  With a
@@ -785,7 +808,7 @@ __device__ __forceinline__ void restrict_stage(const Stage& st, int chunk, const
   T wgt[9];
   bool tap[9];
   {
-    const long long I = st.dim == 1 ? Q : Q % nc, J = st.dim == 1 ? 0 : Q / nc;
+    const long long I = st.dim == 1 ? Q : Qn % nc, J = st.dim == 1 ? 0 : Qn / nc;
     const long long fx = 2 * I + 1, fy = 2 * J + 1;
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
@@ -796,6 +819,7 @@ __device__ __forceinline__ void restrict_stage(const Stage& st, int chunk, const
       } else {
         const int dy = t / 3 - 1, dx = t % 3 - 1;
         off[t] = (fy + dy) * nf + fx + dx;
+        if (split) off[t] = split_index(off[t], n0f);
         wgt[t] = (T)((dx == 0 ? 2 : 1) * (dy == 0 ? 2 : 1)) * (T)(1.0 / 16.0);
         tap[t] = !red_only || (dx == 0) == (dy == 0);   // first colour: centre and corners
       }
@@ -864,7 +888,11 @@ __device__ __forceinline__ void prolong_stage(const Stage& st, int chunk, const 
   const int par1 = st.dim == 1 ? 0 : 1;
   const long long Nq = st.black_only ? (Nf - par1 + 1) / 2 : Nf;
   const long long qi = (long long)chunk * kStencilCols + (threadIdx.x % kStencilCols);
-  const long long q = st.black_only ? 2 * qi + par1 : qi;
+  const bool split = st.split;
+  const long long n0f = (Nf + 1) / 2, n0c = (Nc + 1) / 2;
+  // storage index s of the point, natural flat index q
+  const long long s = split ? (st.black_only ? n0f + qi : qi) : (st.black_only ? 2 * qi + par1 : qi);
+  const long long q = split ? natural_index(s, n0f) : s;
   const int r0 = threadIdx.x / kStencilCols;
   const bool ok = qi < Nq;
   const int lane = threadIdx.x & 63;
@@ -896,6 +924,7 @@ __device__ __forceinline__ void prolong_stage(const Stage& st, int chunk, const 
       const int b = t >> 1, a2 = t & 1;
       cvalid[t] = ok && vx[a2] && vy[b];
       cidx[t] = cvalid[t] ? (st.dim == 1 ? cx[a2] : cy[b] * nc + cx[a2]) : 0;
+      if (split && cvalid[t]) cidx[t] = split_index(cidx[t], n0c);
       cw[t] = wx[a2] * wy[b];
     }
   }
@@ -918,7 +947,7 @@ __device__ __forceinline__ void prolong_stage(const Stage& st, int chunk, const 
         const T* e = src + m * Nc;
 #pragma unroll
         for (int t = 0; t < 4; ++t) raw[j][t] = (rok && cvalid[t]) ? gld<true>(e + cidx[t]) : (T)0;
-        u0[j] = rok ? gld<true>(dst + m * Nf + q) : (T)0;
+        u0[j] = rok ? gld<true>(dst + m * Nf + s) : (T)0;
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -931,7 +960,7 @@ __device__ __forceinline__ void prolong_stage(const Stage& st, int chunk, const 
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int row = r0 + j * kStencilRowsPerPass;
-        if (row < d.sz) gst<true>(dst + (long long)(d.lo + row) * Nf + q, u0[j] + v[j]);
+        if (row < d.sz) gst<true>(dst + (long long)(d.lo + row) * Nf + s, u0[j] + v[j]);
       }
     }
     __builtin_amdgcn_s_waitcnt(0);
@@ -1074,88 +1103,136 @@ __global__ void fill_int_kernel(int* __restrict__ x, long long count, int v) {
 // Stencil kernels (space only, every time row independently)
 
 // Full-weighting restriction of the defect in space only (Algorithm 2).
+// Grid transfers: blockIdx.y walks the time rows, x the points of a row.
 template <typename T>
 __global__ void restrict_kernel(const T* __restrict__ rf, T* __restrict__ fc, int dim, int nf, int nc, long long M,
-                                int red_only) {
+                                int red_only, int split) {
   const long long Nc = dim == 1 ? nc : (long long)nc * nc;
   const long long Nf = dim == 1 ? nf : (long long)nf * nf;
-  const long long total = M * Nc;
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
-       idx += (long long)gridDim.x * blockDim.x) {
-    const long long m = idx / Nc, Q = idx % Nc;
+  const long long n0f = (Nf + 1) / 2, n0c = (Nc + 1) / 2;
+  for (long long m = blockIdx.y; m < M; m += gridDim.y) {
     const T* r = rf + m * Nf;
-    T v;
-    if (dim == 1) {
-      const long long f = 2 * Q + 1;
-      v = red_only ? (T)0.5 * r[f] : (T)0.25 * (r[f - 1] + (T)2 * r[f] + r[f + 1]);
-    } else {
-      const long long I = Q % nc, J = Q / nc;
-      const long long fx = 2 * I + 1, fy = 2 * J + 1;
-      const T* r0 = r + (fy - 1) * nf;
-      const T* r1 = r + fy * nf;
-      const T* r2 = r + (fy + 1) * nf;
-      const T edges = red_only ? (T)0 : (T)2 * (r0[fx] + r2[fx] + r1[fx - 1] + r1[fx + 1]);
-      v = (T)(1.0 / 16.0) * ((r0[fx - 1] + r0[fx + 1] + r2[fx - 1] + r2[fx + 1]) + edges + (T)4 * r1[fx]);
+    for (long long Q = blockIdx.x * (long long)blockDim.x + threadIdx.x; Q < Nc;
+         Q += (long long)gridDim.x * blockDim.x) {
+      T v;
+      if (dim == 1) {
+        const long long f = 2 * Q + 1;
+        v = red_only ? (T)0.5 * r[f] : (T)0.25 * (r[f - 1] + (T)2 * r[f] + r[f + 1]);
+      } else {
+        // coarse point (I, J) is the fine point (2I+1, 2J+1); its corners share
+        // its colour (the first), the edge midpoints have the other one
+        const long long Qn = split ? natural_index(Q, n0c) : Q;
+        const long long I = Qn % nc, J = Qn / nc;
+        const long long fx = 2 * I + 1, fy = 2 * J + 1;
+        auto at = [&](long long y, long long x) -> T {
+          const long long qf = y * nf + x;
+          return r[split ? split_index(qf, n0f) : qf];
+        };
+        const T edges = red_only ? (T)0 : (T)2 * (at(fy - 1, fx) + at(fy + 1, fx) + at(fy, fx - 1) + at(fy, fx + 1));
+        v = (T)(1.0 / 16.0) *
+            ((at(fy - 1, fx - 1) + at(fy - 1, fx + 1) + at(fy + 1, fx - 1) + at(fy + 1, fx + 1)) + edges +
+             (T)4 * at(fy, fx));
+      }
+      fc[m * Nc + Q] = v;
     }
-    fc[idx] = v;
   }
 }
 
-// Linear / bilinear interpolation of the coarse correction in space, added to
-// the fine iterate (the correction step of Algorithm 2).
+// Linear interpolation of the coarse correction, added to the fine iterate.
+// black_only: the second-colour points only (a first-colour half-sweep
+// follows, which never reads its own lines' old values).
 template <typename T>
 __global__ void prolong_kernel(const T* __restrict__ ec, T* __restrict__ uf, int dim, int nf, int nc, long long M,
-                               int black_only) {
+                               int black_only, int split) {
   const long long Nc = dim == 1 ? nc : (long long)nc * nc;
   const long long Nf = dim == 1 ? nf : (long long)nf * nf;
+  const long long n0f = (Nf + 1) / 2, n0c = (Nc + 1) / 2;
   // second colour: flat indices of parity par1 (even in 1D, odd in 2D)
   const int par1 = dim == 1 ? 0 : 1;
   const long long Nq = black_only ? (Nf - par1 + 1) / 2 : Nf;
-  const long long total = M * Nq;
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
-       idx += (long long)gridDim.x * blockDim.x) {
-    const long long m = idx / Nq, qi = idx % Nq;
-    const long long q = black_only ? 2 * qi + par1 : qi;
+  for (long long m = blockIdx.y; m < M; m += gridDim.y) {
     const T* e = ec + m * Nc;
-    T v;
-    if (dim == 1) {
-      if (q & 1) {
-        v = e[(q - 1) / 2];
+    T* u = uf + m * Nf;
+    for (long long qi = blockIdx.x * (long long)blockDim.x + threadIdx.x; qi < Nq;
+         qi += (long long)gridDim.x * blockDim.x) {
+      // storage index s of the point, natural flat index q
+      long long s, q;
+      if (split) {
+        s = black_only ? n0f + qi : qi;
+        q = natural_index(s, n0f);
       } else {
-        const long long I = q / 2;  // between coarse I-1 and I
-        const T lo = I >= 1 ? e[I - 1] : (T)0;
-        const T hi = I < nc ? e[I] : (T)0;
-        v = (T)0.5 * (lo + hi);
+        q = black_only ? 2 * qi + par1 : qi;
+        s = q;
       }
-    } else {
-      const long long ix = q % nf, iy = q / nf;
-      long long cx[2], cy[2];
-      T wx[2], wy[2];
-      int nx, ny;
-      if (ix & 1) { cx[0] = (ix - 1) / 2; wx[0] = (T)1; nx = 1; }
-      else { cx[0] = ix / 2 - 1; cx[1] = ix / 2; wx[0] = wx[1] = (T)0.5; nx = 2; }
-      if (iy & 1) { cy[0] = (iy - 1) / 2; wy[0] = (T)1; ny = 1; }
-      else { cy[0] = iy / 2 - 1; cy[1] = iy / 2; wy[0] = wy[1] = (T)0.5; ny = 2; }
-      v = (T)0;
-      for (int b = 0; b < ny; ++b) {
-        if (cy[b] < 0 || cy[b] >= nc) continue;
-        for (int a2 = 0; a2 < nx; ++a2) {
-          if (cx[a2] < 0 || cx[a2] >= nc) continue;
-          v += wx[a2] * wy[b] * e[cy[b] * nc + cx[a2]];
+      T v;
+      if (dim == 1) {
+        if (q & 1) {
+          v = e[(q - 1) / 2];
+        } else {
+          const long long I = q / 2;  // between coarse I-1 and I
+          const T lo = I >= 1 ? e[I - 1] : (T)0;
+          const T hi = I < nc ? e[I] : (T)0;
+          v = (T)0.5 * (lo + hi);
+        }
+      } else {
+        const long long ix = q % nf, iy = q / nf;
+        long long cx[2], cy[2];
+        T wx[2], wy[2];
+        int nx, ny;
+        if (ix & 1) { cx[0] = (ix - 1) / 2; wx[0] = (T)1; nx = 1; }
+        else { cx[0] = ix / 2 - 1; cx[1] = ix / 2; wx[0] = wx[1] = (T)0.5; nx = 2; }
+        if (iy & 1) { cy[0] = (iy - 1) / 2; wy[0] = (T)1; ny = 1; }
+        else { cy[0] = iy / 2 - 1; cy[1] = iy / 2; wy[0] = wy[1] = (T)0.5; ny = 2; }
+        v = (T)0;
+        for (int b = 0; b < ny; ++b) {
+          if (cy[b] < 0 || cy[b] >= nc) continue;
+          for (int a2 = 0; a2 < nx; ++a2) {
+            if (cx[a2] < 0 || cx[a2] >= nc) continue;
+            const long long qc = cy[b] * nc + cx[a2];
+            v += wx[a2] * wy[b] * e[split ? split_index(qc, n0c) : qc];
+          }
         }
       }
+      u[s] += v;
     }
-    uf[m * Nf + q] += v;
   }
 }
 
-// b = f + a_{m,1} g (initial value moved to the right-hand side).
+// b = f + a_{.,1} g in colour-split storage (2D): b[m][s] from the natural
+// f[m][q(s)], g[q(s)] (g may be null).
+__global__ void rhs0_split_kernel(const double* __restrict__ f, const double* __restrict__ gq,
+                                  const double* __restrict__ a1, double* __restrict__ b, long long M, long long N) {
+  const long long n0 = (N + 1) / 2;
+  for (long long m = blockIdx.y; m < M; m += gridDim.y) {
+    const double am = gq ? a1[m] : 0.0;
+    for (long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x; s < N;
+         s += (long long)gridDim.x * blockDim.x) {
+      const long long q = natural_index(s, n0);
+      b[m * N + s] = gq ? __fma_rn(am, gq[q], f[m * N + q]) : f[m * N + q];   // rounded as rhs0_kernel
+    }
+  }
+}
+
+// [M][N] rows between natural and colour-split storage (2D); src and dst
+// must not overlap.
+__global__ void relayout_kernel(const double* __restrict__ src, double* __restrict__ dst, long long M, long long N,
+                                int to_split) {
+  const long long n0 = (N + 1) / 2;
+  for (long long m = blockIdx.y; m < M; m += gridDim.y) {
+    const double* a = src + m * N;
+    double* b = dst + m * N;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
+         i += (long long)gridDim.x * blockDim.x)
+      b[i] = to_split ? a[natural_index(i, n0)] : a[split_index(i, n0)];
+  }
+}
+
 __global__ void rhs0_kernel(const double* __restrict__ f, const double* __restrict__ gq, const double* __restrict__ a1,
                             double* __restrict__ b, long long M, long long N) {
   const long long total = M * N;
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
        idx += (long long)gridDim.x * blockDim.x)
-    b[idx] = f[idx] + a1[idx / N] * gq[idx % N];
+    b[idx] = __fma_rn(a1[idx / N], gq[idx % N], f[idx]);   // one rounding, as rhs0_split_kernel
 }
 
 template <typename T>
@@ -1303,22 +1380,45 @@ hipError_t set_march_lds_limit(size_t bytes) {
   return e != hipSuccess ? e : set_march_lds_limit_depth<T, true>(bytes);
 }
 
+// Launch shape of the transfer kernels: rows over y (at most 65535), a
+// row's points over x (each thread covers several when the row is long).
+static dim3 row_grid(long long per_row, long long M) {
+  const long long gx = std::min<long long>(std::max<long long>((per_row + 255) / 256, 1), 64);
+  const long long gy = std::min<long long>(std::max<long long>(M, 1), 65535);
+  return dim3((unsigned)gx, (unsigned)gy);
+}
+
 template <typename T>
-hipError_t launch_restrict(const T* rf, T* fc, int dim, int nf, int M, bool red_only, hipStream_t s) {
+hipError_t launch_restrict(const T* rf, T* fc, int dim, int nf, int M, bool red_only, bool split, hipStream_t s) {
   int nc = (nf - 1) / 2;
-  long long total = (long long)M * (dim == 1 ? nc : (long long)nc * nc);
-  hipLaunchKernelGGL(restrict_kernel<T>, dim3(grid_for(total, 256)), dim3(256), 0, s, rf, fc, dim, nf, nc, (long long)M,
-                     red_only ? 1 : 0);
+  const long long Nc = dim == 1 ? nc : (long long)nc * nc;
+  if (Nc <= 0 || M <= 0) return hipSuccess;
+  hipLaunchKernelGGL(restrict_kernel<T>, row_grid(Nc, M), dim3(256), 0, s, rf, fc, dim, nf, nc, (long long)M,
+                     red_only ? 1 : 0, split && dim == 2 ? 1 : 0);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_prolong(const T* ec, T* uf, int dim, int nf, int M, bool black_only, hipStream_t s) {
+hipError_t launch_prolong(const T* ec, T* uf, int dim, int nf, int M, bool black_only, bool split, hipStream_t s) {
   int nc = (nf - 1) / 2;
   const long long Nf = dim == 1 ? nf : (long long)nf * nf;
-  const long long total = (long long)M * (black_only ? (Nf - (dim == 1 ? 0 : 1) + 1) / 2 : Nf);
-  hipLaunchKernelGGL(prolong_kernel<T>, dim3(grid_for(total, 256)), dim3(256), 0, s, ec, uf, dim, nf, nc, (long long)M,
-                     black_only ? 1 : 0);
+  const long long Nq = black_only ? (Nf - (dim == 1 ? 0 : 1) + 1) / 2 : Nf;
+  if (Nq <= 0 || M <= 0) return hipSuccess;
+  hipLaunchKernelGGL(prolong_kernel<T>, row_grid(Nq, M), dim3(256), 0, s, ec, uf, dim, nf, nc, (long long)M,
+                     black_only ? 1 : 0, split && dim == 2 ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs0_split(const double* f, const double* gq, const double* a1, double* b, long long M,
+                             long long N, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(rhs0_split_kernel, row_grid(N, M), dim3(256), 0, s, f, gq, a1, b, M, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_relayout(const double* src, double* dst, long long M, long long N, bool to_split, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(relayout_kernel, row_grid(N, M), dim3(256), 0, s, src, dst, M, N, to_split ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -1377,10 +1477,10 @@ template hipError_t launch_march<double>(int, const MarchArgs<double>&, hipStrea
 template hipError_t launch_march<float>(int, const MarchArgs<float>&, hipStream_t);
 template hipError_t set_march_lds_limit<double>(size_t);
 template hipError_t set_march_lds_limit<float>(size_t);
-template hipError_t launch_restrict<double>(const double*, double*, int, int, int, bool, hipStream_t);
-template hipError_t launch_restrict<float>(const float*, float*, int, int, int, bool, hipStream_t);
-template hipError_t launch_prolong<double>(const double*, double*, int, int, int, bool, hipStream_t);
-template hipError_t launch_prolong<float>(const float*, float*, int, int, int, bool, hipStream_t);
+template hipError_t launch_restrict<double>(const double*, double*, int, int, int, bool, bool, hipStream_t);
+template hipError_t launch_restrict<float>(const float*, float*, int, int, int, bool, bool, hipStream_t);
+template hipError_t launch_prolong<double>(const double*, double*, int, int, int, bool, bool, hipStream_t);
+template hipError_t launch_prolong<float>(const float*, float*, int, int, int, bool, bool, hipStream_t);
 template hipError_t launch_fill<double>(double*, long long, double, hipStream_t);
 template hipError_t launch_fill<float>(float*, long long, float, hipStream_t);
 template hipError_t launch_cast<double, float>(const double*, float*, long long, hipStream_t);

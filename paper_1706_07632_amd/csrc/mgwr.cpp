@@ -98,6 +98,11 @@ struct mgwr_plan {
   DevOps<double> d64;
   DevOps<float> d32;
   bool mixed = false;   // float32 inner cycles (MGWR_MIXED_FP32 or MGWR_MIXED_BF16)
+  // 2D grids in colour-split storage inside a solve (MarchArgs::split): the
+  // caller's arrays are natural; b is formed split, a given iterate is moved
+  // in and the result moved back out (mgwr_plan_set_layout)
+  bool split = false;
+  int set_layout = MGWR_LAYOUT_AUTO;   // mgwr_plan_set_layout (AUTO: tuned for the shape, else split)
   bool bf16 = false;    // their low-rank factors in bfloat16
   // live timing (mgwr_timing_enable)
   struct Pending { hipEvent_t b, e; int cls; double flops, bytes; };
@@ -304,6 +309,8 @@ MarchArgs<T> base_args(mgwr_plan* pl, const DevOps<T>& ops, int level) {
   a.prefetch = pl->prefetch;
   a.k = hp.p.k;
   a.nslots = hp.nslots;
+  a.split = pl->split && hp.p.dim == 2 ? 1 : 0;
+  a.n0 = (hp.levels[level].N + 1) / 2;
   a.ring = std::max(hp.window + 2, 3);  // leaves written while older ones are still read
   return a;
 }
@@ -344,6 +351,7 @@ int smooth(mgwr_plan* pl, DevOps<T>& ops, int l, int colour, T* F, T* U, const T
   MarchArgs<T> a = base_args<T>(pl, ops, l);
   a.F = F; a.U = U; a.Out = nullptr;
   a.ld = lv.N; a.ncols = ncols; a.cstride = 2; a.coff = par;
+  if (a.split) { a.cstride = 1; a.coff = par ? (int)a.n0 : 0; }   // the colour's contiguous block
   a.dim = hp.p.dim; a.n = lv.n; a.inv_h2 = (T)(1.0 / (lv.h * lv.h));
   if (Ec) { a.Ec = Ec; a.nc = hp.levels[l + 1].n; }
   Timed tm(pl, sizeof(T) == 8 ? MGWR_K_SMOOTH64 : MGWR_K_SMOOTH32, 2.0 * hp.stored * ncols,
@@ -358,16 +366,20 @@ int smooth(mgwr_plan* pl, DevOps<T>& ops, int l, int colour, T* F, T* U, const T
 // that only feeds the restriction needs the first colour alone.
 template <typename T>
 // Inj / Inj0 (1D, red_only): the restriction is fused, see MarchArgs.
+// natural: the arrays are in natural order whatever the plan's storage (the
+// defect entry point).
 int defect(mgwr_plan* pl, DevOps<T>& ops, int l, const T* F, T* U, T* Out, bool red_only = false,
-           T* Inj = nullptr, T* Inj0 = nullptr) {
+           T* Inj = nullptr, T* Inj0 = nullptr, bool natural = false) {
   const HostPlan& hp = pl->hp;
   const Level& lv = hp.levels[l];
   MarchArgs<T> a = base_args<T>(pl, ops, l);
+  if (natural) a.split = 0;
   a.F = F; a.U = U; a.Out = Out;
   a.ld = lv.N; a.ncols = lv.N; a.cstride = 1; a.coff = 0;
   if (red_only) {
     const int par0 = hp.p.dim == 1 ? 1 : 0;
     a.ncols = (lv.N - par0 + 1) / 2; a.cstride = 2; a.coff = par0;
+    if (a.split) { a.cstride = 1; a.coff = 0; }   // the first colour is the first block
   }
   a.dim = hp.p.dim; a.n = lv.n; a.inv_h2 = (T)(1.0 / (lv.h * lv.h));
   if (Inj) { a.Inj = Inj; a.Inj0 = Inj0; a.nc = hp.levels[l + 1].n; }
@@ -411,7 +423,8 @@ int cycle(mgwr_plan* pl, DevOps<T>& ops, int l) {
     {
       Timed tm(pl, MGWR_K_RESTRICT, 0.0,
                (double)M * ((red_only ? 0.5 : 1.0) * hp.levels[l].N + 2.0 * hp.levels[l + 1].N) * sizeof(T));
-      HIP_TRY(launch_restrict<T>(ops.R[l], ops.F[l + 1], hp.p.dim, hp.levels[l].n, M, red_only, pl->stream));
+      HIP_TRY(launch_restrict<T>(ops.R[l], ops.F[l + 1], hp.p.dim, hp.levels[l].n, M, red_only, pl->split,
+                                 pl->stream));
     }
     HIP_TRY(launch_fill<T>(ops.U[l + 1], (long long)M * hp.levels[l + 1].N, (T)0, pl->stream));
   }
@@ -420,7 +433,7 @@ int cycle(mgwr_plan* pl, DevOps<T>& ops, int l) {
   if (!fz.prolong_in_smooth) {
     Timed tm(pl, MGWR_K_PROLONG, 0.0,
              (double)M * ((hp.p.nu2 >= 1 ? 1.0 : 2.0) * hp.levels[l].N + hp.levels[l + 1].N) * sizeof(T));
-    HIP_TRY(launch_prolong<T>(ops.U[l + 1], U, hp.p.dim, hp.levels[l].n, M, hp.p.nu2 >= 1, pl->stream));
+    HIP_TRY(launch_prolong<T>(ops.U[l + 1], U, hp.p.dim, hp.levels[l].n, M, hp.p.nu2 >= 1, pl->split, pl->stream));
   }
   for (int s = 0; s < hp.p.nu2; ++s) {
     const T* Ec = (fz.prolong_in_smooth && s == 0) ? ops.U[l + 1] : nullptr;
@@ -464,12 +477,14 @@ int append_cycle_stages(mgwr_plan* pl, int l, int prev, std::vector<Stage>& out,
       st.m = base_args<double>(pl, ops, l);
       st.m.F = ops.F[l]; st.m.U = ops.U[l]; st.m.Out = nullptr;
       st.m.ld = lv.N; st.m.ncols = ncols; st.m.cstride = 2; st.m.coff = par;
+      if (st.m.split) { st.m.cstride = 1; st.m.coff = par ? (int)st.m.n0 : 0; }
       st.m.dim = hp.p.dim; st.m.n = lv.n; st.m.inv_h2 = 1.0 / (lv.h * lv.h);
       if (with_ec) { st.m.Ec = ops.U[l + 1]; st.m.nc = hp.levels[l + 1].n; }
     } else {
       st.mf = base_args<float>(pl, o32, l);
       st.mf.F = o32.F[l]; st.mf.U = o32.U[l]; st.mf.Out = nullptr;
       st.mf.ld = lv.N; st.mf.ncols = ncols; st.mf.cstride = 2; st.mf.coff = par;
+      if (st.mf.split) { st.mf.cstride = 1; st.mf.coff = par ? (int)st.mf.n0 : 0; }
       st.mf.dim = hp.p.dim; st.mf.n = lv.n; st.mf.inv_h2 = (float)(1.0 / (lv.h * lv.h));
       if (with_ec) { st.mf.Ec = o32.U[l + 1]; st.mf.nc = hp.levels[l + 1].n; }
     }
@@ -489,7 +504,9 @@ int append_cycle_stages(mgwr_plan* pl, int l, int prev, std::vector<Stage>& out,
   {
     const int par0 = hp.p.dim == 1 ? 1 : 0;
     const int ncols = red_only ? (lv.N - par0 + 1) / 2 : lv.N;
-    const int cstride = red_only ? 2 : 1, coff = red_only ? par0 : 0;
+    // colour-split storage: the first colour is the first block (coff 0)
+    const bool split = pl->split && hp.p.dim == 2;
+    const int cstride = red_only && !split ? 2 : 1, coff = red_only && !split ? par0 : 0;
     Stage st = base(STG_RESID + kofs);
     if (!f32) {
       st.m = base_args<double>(pl, ops, l);
@@ -518,6 +535,7 @@ int append_cycle_stages(mgwr_plan* pl, int l, int prev, std::vector<Stage>& out,
     else { st.src = o32.R[l]; st.dst = o32.F[l + 1]; st.zero = o32.U[l + 1]; }
     st.dim = hp.p.dim; st.nf = lv.n; st.nc = lc.n;
     st.red_only = red_only ? 1 : 0;
+    st.split = pl->split && hp.p.dim == 2 ? 1 : 0;
     st.nchunks = (lc.N + kStencilCols - 1) / kStencilCols;
     push(st);
   }
@@ -529,6 +547,7 @@ int append_cycle_stages(mgwr_plan* pl, int l, int prev, std::vector<Stage>& out,
     else { st.src = o32.U[l + 1]; st.dst = o32.U[l]; }
     st.dim = hp.p.dim; st.nf = lv.n; st.nc = lc.n;
     st.black_only = hp.p.nu2 >= 1 ? 1 : 0;   // a first-colour half-sweep follows
+    st.split = pl->split && hp.p.dim == 2 ? 1 : 0;
     const long long nq = st.black_only ? (lv.N - (hp.p.dim == 1 ? 0 : 1) + 1) / 2 : lv.N;
     st.nchunks = (int)((nq + kStencilCols - 1) / kStencilCols);
     push(st);
@@ -730,6 +749,7 @@ int coarse_cycle(mgwr_plan* pl, int l) {
 using TuneKey = std::tuple<int, int, int, int, int, int>;
 struct TuneChoice {
   int sched = 0, prefetch = 0, coarse = -1;
+  int layout = MGWR_LAYOUT_AUTO;
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneChoice> g_tuned;
@@ -769,6 +789,33 @@ void staging_choice(const mgwr_plan* pl, int* prefetch, int* coarse) {
     }
   }
   if (*coarse < 0) *coarse = coarse_switch_level(pl->hp);
+}
+
+// Storage of a 2D solve: set on the plan, else measured for its shape (AUTO
+// schedule), else colour-split.  1D is natural.
+bool split_choice(const mgwr_plan* pl) {
+  if (pl->hp.p.dim != 2) return false;
+  if (pl->set_layout != MGWR_LAYOUT_AUTO) return pl->set_layout == MGWR_LAYOUT_SPLIT;
+  if (pl->hp.p.schedule == MGWR_SCHED_AUTO) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(tune_key(pl));
+    if (it != g_tuned.end() && it->second.layout != MGWR_LAYOUT_AUTO) return it->second.layout == MGWR_LAYOUT_SPLIT;
+  }
+  return true;
+}
+
+// Puts the storage choice in force; stage images built for the other one
+// are dropped (they hold the storage flag and column offsets).
+void apply_layout(mgwr_plan* pl) {
+  const bool sp = split_choice(pl);
+  if (sp == pl->split) return;
+  pl->split = sp;
+  pl->stages_f = nullptr;
+  pl->stages_u = nullptr;
+  for (int w = 0; w < 2; ++w) {
+    pl->coarse_stages[w].clear();
+    pl->coarse_up[w] = false;
+  }
 }
 
 // Puts the staged knobs in force; a new coarse level rebuilds the coarse
@@ -876,8 +923,18 @@ int prepare_solve(mgwr_plan* pl, const double* f, const double* g, double tol, d
   s = mgwr_stats{};
   s.warm_res0 = std::nan("");
   s.setup_ms = pl->create_ms + pl->bind_ms;
+  apply_layout(pl);
   b = f;
-  if (g) {
+  if (pl->split) {
+    // colour-split storage: b is formed in it, a given iterate is moved in
+    // (through the level-0 defect array, free until the first defect)
+    HIP_TRY(launch_rhs0_split(f, g, pl->a1, pl->B0, hp.p.M, N, pl->stream));
+    b = pl->B0;
+    if ((flags & MGWR_GUESS_IN_U) && !(flags & MGWR_WARM_START)) {
+      HIP_TRY(launch_relayout(u, pl->d64.R[0], hp.p.M, N, true, pl->stream));
+      HIP_TRY(hipMemcpyAsync(u, pl->d64.R[0], MN * sizeof(double), hipMemcpyDeviceToDevice, pl->stream));
+    }
+  } else if (g) {
     HIP_TRY(launch_rhs0(f, g, pl->a1, pl->B0, hp.p.M, N, pl->stream));
     b = pl->B0;
   }
@@ -897,12 +954,12 @@ int prepare_solve(mgwr_plan* pl, const double* f, const double* g, double tol, d
         std::lock_guard<std::mutex> lk(net_mutex(pl->net));
         float* xin = net_input_stage(pl->net);
         HIP_TRY(launch_gather_slices(b, pl->rows_dev, ns, N, s.bnorm, (float)hp.p.alpha, (float)(hp.p.r / 10.0),
-                                     xin, pl->stream));
+                                     xin, pl->split, pl->stream));
         HIP_TRY(hipStreamSynchronize(pl->stream));
         const float* y = nullptr;
         if ((rc = net_infer(pl->net, xin, H, W, hp.levels[0].h, &y))) return rc;
         HIP_TRY(hipStreamSynchronize(net_stream(pl->net)));
-        HIP_TRY(launch_time_interp(y, pl->rows_dev, ns, pl->tpow, g, hp.p.M, N, s.bnorm, u, pl->stream));
+        HIP_TRY(launch_time_interp(y, pl->rows_dev, ns, pl->tpow, g, hp.p.M, N, s.bnorm, u, pl->split, pl->stream));
         HIP_TRY(hipStreamSynchronize(pl->stream));
       }
       // the prediction's true residual (reported, and the right-hand side of
@@ -932,6 +989,16 @@ int prepare_solve(mgwr_plan* pl, const double* f, const double* g, double tol, d
   } else if (s.res0 <= tol * s.bnorm) {
     status = MGWR_OK;
   }
+  return MGWR_OK;
+}
+
+// The end of a solve: a colour-split iterate goes back to the caller's
+// natural order (through the level-0 defect array), on stream s.
+int finish_solve(mgwr_plan* pl, double* u, hipStream_t s) {
+  if (!pl->split) return MGWR_OK;
+  const long long N = pl->hp.levels[0].N, M = pl->hp.p.M;
+  HIP_TRY(launch_relayout(u, pl->d64.R[0], M, N, false, s));
+  HIP_TRY(hipMemcpyAsync(u, pl->d64.R[0], M * N * sizeof(double), hipMemcpyDeviceToDevice, s));
   return MGWR_OK;
 }
 
@@ -1166,6 +1233,9 @@ int solve_pipelined(mgwr_batch* bt, const double* const* f, const double* const*
     }
   }
   int ret = MGWR_OK;
+  for (int i : sel)
+    if ((rc = finish_solve(bt->plans[i], u[i], bt->stream))) return rc;
+  HIP_TRY(hipStreamSynchronize(bt->stream));
   const double solve_ms = ms_since(t_start);
   for (int i : sel) {
     mgwr_stats& s = st[i];
@@ -1398,7 +1468,7 @@ int mgwr_residual(mgwr_plan* pl, const double* f, const double* g, const double*
     b = pl->B0;
   }
   double* dst = out ? out : pl->d64.R[0];
-  if ((rc = defect<double>(pl, pl->d64, 0, b, const_cast<double*>(u), dst))) return rc;
+  if ((rc = defect<double>(pl, pl->d64, 0, b, const_cast<double*>(u), dst, false, nullptr, nullptr, true))) return rc;
   if (norm) return norm_inf<double>(pl, dst, MN, norm);
   return MGWR_OK;
 }
@@ -1454,6 +1524,7 @@ int mgwr_solve(mgwr_plan* pl, const double* f, const double* g, double tol, doub
   int status = MGWR_ERR_NOT_CONVERGED;
   if ((rc = prepare_solve(pl, f, g, tol, u, flags, s, b, status))) return rc;
   if (!std::isfinite(s.bnorm)) {
+    if ((rc = finish_solve(pl, u, pl->stream))) return rc;
     if (st) *st = s;
     return fail(MGWR_ERR_NONFINITE, "right-hand side is not finite");
   }
@@ -1526,6 +1597,7 @@ int mgwr_solve(mgwr_plan* pl, const double* f, const double* g, double tol, doub
   s.avg_factor = (s.cycles > 0 && s.res0 > 0) ? std::pow(s.res / s.res0, 1.0 / s.cycles) : 0.0;
   if (status == MGWR_OK && s.cycles > 0 && !(flags0 & (MGWR_GUESS_IN_U | MGWR_WARM_START)))
     pl->rate_zero = s.avg_factor;
+  if ((rc = finish_solve(pl, u, pl->stream))) return rc;
   s.solve_ms = ms_since(t_start);
   if (st) *st = s;
   if (status == MGWR_ERR_NOT_CONVERGED) return fail(status, "max_cycles reached before the tolerance");
@@ -1540,7 +1612,7 @@ int mgwr_hmatvec(mgwr_plan* pl, const double* x, double* y, int ncols) {
   if ((rc = use_device(pl))) return rc;
   MarchArgs<double> a = base_args<double>(pl, pl->d64, 0);
   a.F = nullptr; a.U = const_cast<double*>(x); a.Out = y;
-  a.ld = ncols; a.ncols = ncols; a.cstride = 1; a.coff = 0; a.dim = 0; a.n = 0; a.inv_h2 = 0.0;
+  a.ld = ncols; a.ncols = ncols; a.cstride = 1; a.coff = 0; a.dim = 0; a.n = 0; a.inv_h2 = 0.0; a.split = 0;
   HIP_TRY(launch_march<double>(MODE_MATVEC, a, pl->stream));
   return MGWR_OK;
 }
@@ -1557,7 +1629,7 @@ int mgwr_apply_A(mgwr_plan* pl, const double* u, double* out) {
   // the product march with the stencil: out = R~ u + A_h u
   MarchArgs<double> a = base_args<double>(pl, pl->d64, 0);
   a.F = nullptr; a.U = const_cast<double*>(u); a.Out = out;
-  a.ld = lv.N; a.ncols = lv.N; a.cstride = 1; a.coff = 0;
+  a.ld = lv.N; a.ncols = lv.N; a.cstride = 1; a.coff = 0; a.split = 0;   // the caller's natural order
   a.dim = hp.p.dim; a.n = lv.n; a.inv_h2 = 1.0 / (lv.h * lv.h);
   HIP_TRY(launch_march<double>(MODE_MATVEC, a, pl->stream));
   return MGWR_OK;
@@ -1571,7 +1643,7 @@ int mgwr_htrsm(mgwr_plan* pl, int level, const double* b, double* x, int ncols) 
   if ((rc = use_device(pl))) return rc;
   MarchArgs<double> a = base_args<double>(pl, pl->d64, level);
   a.F = b; a.U = x; a.Out = nullptr;
-  a.ld = ncols; a.ncols = ncols; a.cstride = 1; a.coff = 0; a.dim = 0; a.n = 0; a.inv_h2 = 0.0;
+  a.ld = ncols; a.ncols = ncols; a.cstride = 1; a.coff = 0; a.dim = 0; a.n = 0; a.inv_h2 = 0.0; a.split = 0;
   HIP_TRY(launch_march<double>(MODE_TRSM, a, pl->stream));
   return MGWR_OK;
 }
@@ -1740,6 +1812,7 @@ int mgwr_plan_get_info(const mgwr_plan* pl, mgwr_plan_info* info) {
   info->k = hp.p.k;
   info->stored_entries = hp.stored;
   info->shift0 = hp.levels[0].shift;
+  info->layout = split_choice(pl) ? MGWR_LAYOUT_SPLIT : MGWR_LAYOUT_NATURAL;
   info->nf64leaves = 0;
   for (const LeafDesc& d : hp.pk.leaves) info->nf64leaves += d.f64solve;
   return MGWR_OK;
@@ -2011,8 +2084,9 @@ int mgwr_plan_autotune(mgwr_plan* pl, const double* f, const double* g, double t
   // candidates: the pipelined schedule, and the staged one with either march
   // prefetch and the coarse launch from the rule's level or one level either
   // side of it
-  struct Cand { int sched, prefetch, coarse; };
-  std::vector<Cand> cands = {{MGWR_SCHED_PIPELINED, 0, -1}};
+  struct Cand { int sched, prefetch, coarse, layout; };
+  const int lay0 = pl->hp.p.dim == 2 ? MGWR_LAYOUT_SPLIT : MGWR_LAYOUT_NATURAL;
+  std::vector<Cand> cands = {{MGWR_SCHED_PIPELINED, 0, -1, lay0}};
   const int L = (int)pl->hp.levels.size();
   const int c0 = coarse_switch_level(pl->hp);
   std::vector<int> levels;
@@ -2020,18 +2094,27 @@ int mgwr_plan_autotune(mgwr_plan* pl, const double* f, const double* g, double t
   for (int c = c0 - 1; c0 > 0 && c <= c0 + 1; ++c)
     if (c >= 1 && c < L) levels.push_back(c);
   for (int pf : {1, 2})
-    for (int c : levels) cands.push_back({MGWR_SCHED_STAGED, pf, c});
+    for (int c : levels) cands.push_back({MGWR_SCHED_STAGED, pf, c, lay0});
   const int saved = pl->tuned;
   const bool saved_set = pl->staging_set;
-  const int saved_pf = pl->set_prefetch, saved_c = pl->set_coarse;
+  const int saved_pf = pl->set_prefetch, saved_c = pl->set_coarse, saved_lay = pl->set_layout;
   const int keep = pl->hp.p.schedule;
   double best = 1e300;
   Cand pick = cands[0];
-  for (const Cand& cd : cands) {
+  // the last round times the best candidate in the other storage (2D)
+  const size_t nbase = cands.size();
+  for (size_t ci = 0; ci <= nbase; ++ci) {
+    if (ci == nbase) {
+      if (pl->hp.p.dim != 2) break;
+      cands.push_back(pick);
+      cands.back().layout = pick.layout == MGWR_LAYOUT_SPLIT ? MGWR_LAYOUT_NATURAL : MGWR_LAYOUT_SPLIT;
+    }
+    const Cand cd = cands[ci];
     pl->tuned = cd.sched;
     pl->staging_set = true;
     pl->set_prefetch = cd.prefetch;
     pl->set_coarse = cd.coarse;
+    pl->set_layout = cd.layout;
     pl->hp.p.schedule = MGWR_SCHED_AUTO;
     double secs = 0.0;
     // the second solve runs with what the first one learned (cycle count)
@@ -2049,6 +2132,7 @@ int mgwr_plan_autotune(mgwr_plan* pl, const double* f, const double* g, double t
       pl->staging_set = saved_set;
       pl->set_prefetch = saved_pf;
       pl->set_coarse = saved_c;
+      pl->set_layout = saved_lay;
       return rc;
     }
     if (secs < best) {
@@ -2061,12 +2145,14 @@ int mgwr_plan_autotune(mgwr_plan* pl, const double* f, const double* g, double t
   pl->staging_set = pick.sched == MGWR_SCHED_STAGED;
   pl->set_prefetch = pick.sched == MGWR_SCHED_STAGED ? pick.prefetch : 0;
   pl->set_coarse = pick.sched == MGWR_SCHED_STAGED ? pick.coarse : -1;
+  pl->set_layout = pl->hp.p.dim == 2 ? pick.layout : MGWR_LAYOUT_AUTO;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     TuneChoice& tc = g_tuned[tune_key(pl)];
     tc.sched = pick.sched;
     tc.prefetch = pick.prefetch;
     tc.coarse = pick.coarse;
+    tc.layout = pl->hp.p.dim == 2 ? pick.layout : MGWR_LAYOUT_AUTO;
   }
   if (chosen) *chosen = pick.sched;
   return MGWR_OK;
@@ -2081,6 +2167,14 @@ int mgwr_plan_set_staging(mgwr_plan* pl, int prefetch, int coarse_level) {
   pl->staging_set = !(prefetch == 0 && coarse_level == -1);
   pl->set_prefetch = prefetch;
   pl->set_coarse = coarse_level;
+  return MGWR_OK;
+}
+
+int mgwr_plan_set_layout(mgwr_plan* pl, int layout) {
+  if (!pl) return fail(MGWR_ERR_INVALID_ARG, "null plan");
+  if (layout != MGWR_LAYOUT_AUTO && layout != MGWR_LAYOUT_NATURAL && layout != MGWR_LAYOUT_SPLIT)
+    return fail(MGWR_ERR_INVALID_ARG, "layout must be MGWR_LAYOUT_AUTO, MGWR_LAYOUT_NATURAL or MGWR_LAYOUT_SPLIT");
+  pl->set_layout = layout;
   return MGWR_OK;
 }
 

@@ -28,9 +28,11 @@ bool net_same_shape(const mgwr_net* net, int layers, const int* channels, int ns
 bool net_is_bound(const mgwr_net* net);
 float* net_params(mgwr_net* net);
 size_t net_param_count(const mgwr_net* net);
+// split: b (gather) / u (interpolation) in the solver's colour-split storage
+// of 2D grids; the network's arrays are in natural order.
 hipError_t launch_gather_slices(const double* b, const int* rows, int nslices, long long N, double scale,
-                                float alpha, float rdiv, float* x, hipStream_t s);
+                                float alpha, float rdiv, float* x, bool split, hipStream_t s);
 hipError_t launch_time_interp(const float* y, const int* rows, int nslices, const double* t, const double* g,
-                              long long M, long long N, double scale, double* u, hipStream_t s);
+                              long long M, long long N, double scale, double* u, bool split, hipStream_t s);
 void set_last_error(const std::string& msg);
 }  // namespace mgwr

@@ -617,30 +617,36 @@ __global__ void relayout_mfma_kernel(const float* __restrict__ w, uint16_t* __re
 
 // Input channels of the warm start for one instance: b at the slice rows
 // divided by `scale`, then constant channels alpha and r / 10.
+// split: b is in the solver's colour-split storage of 2D grids (the even
+// flat indices first, then the odd ones); x is in natural order.
 __global__ void gather_slices_kernel(const double* __restrict__ b, const int* __restrict__ rows, int nslices,
-                                     long long N, double scale, float alpha, float rdiv, float* __restrict__ x) {
+                                     long long N, double scale, float alpha, float rdiv, float* __restrict__ x,
+                                     int split) {
   const long long total = (long long)(nslices + 2) * N;
+  const long long n0 = (N + 1) / 2;
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
        idx += (long long)gridDim.x * blockDim.x) {
     const int c = (int)(idx / N);
     const long long q = idx % N;
+    const long long qs = split ? ((q & 1) ? n0 + (q >> 1) : (q >> 1)) : q;
     float v;
-    if (c < nslices) v = (float)(b[(long long)rows[c] * N + q] / scale);
+    if (c < nslices) v = (float)(b[(long long)rows[c] * N + qs] / scale);
     else v = c == nslices ? alpha : rdiv;
     x[idx] = v;
   }
 }
 
-// u[m][q] = interpolation of the predicted slices (times scale), piecewise
-// linear in the variable s = t^alpha (tp[m] = t_m^alpha): slice k sits at
-// tp[rows[k] + 1].  Before the first slice it runs from the initial value g
-// (zero if null) at tp[0]; after the last slice it stays constant.
 // Slices a solver prediction may take (the plan's limit).
 constexpr int kMaxSlices = 64;
 
+// u[m][q] = interpolation of the predicted slices (times scale), piecewise
+// linear in the variable s = t^alpha (tp[m] = t_m^alpha): slice k sits at
+// tp[rows[k] + 1].  Before the first slice it runs from the initial value g
+// (zero if null) at tp[0]; after the last slice it stays constant.  split: u
+// is written in the solver's colour-split storage (y and g are natural).
 __global__ void time_interp_kernel(const float* __restrict__ y, const int* __restrict__ rows, int nslices,
                                    const double* __restrict__ t, const double* __restrict__ g, long long M,
-                                   long long N, double scale, double* __restrict__ u) {
+                                   long long N, double scale, double* __restrict__ u, int split) {
   // blockIdx.y walks the time rows: the bracketing slices and the weights
   // are the same for the whole row, the columns are plain coalesced streams
   __shared__ int srows[kMaxSlices];
@@ -667,12 +673,14 @@ __global__ void time_interp_kernel(const float* __restrict__ y, const int* __res
     const float* ya = sa >= 0 ? y + (long long)sa * N : nullptr;
     const double* ga = sa == -1 ? g : nullptr;
     double* um = u + m * N;
-    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < N;
-         q += (long long)gridDim.x * blockDim.x) {
+    const long long n0 = (N + 1) / 2;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
+         i += (long long)gridDim.x * blockDim.x) {
+      const long long q = split ? (i < n0 ? 2 * i : 2 * (i - n0) + 1) : i;   // storage i holds point q
       double v = wb * (double)yb[q];
       if (ya) v += wa * (scale * (double)ya[q]);
       else if (ga) v += wa * ga[q];
-      um[q] = v;
+      um[i] = v;
     }
   }
 }
@@ -683,20 +691,20 @@ static inline int grid_of(long long total) {
 }
 
 hipError_t launch_gather_slices(const double* b, const int* rows, int nslices, long long N, double scale,
-                                float alpha, float rdiv, float* x, hipStream_t s) {
+                                float alpha, float rdiv, float* x, bool split, hipStream_t s) {
   hipLaunchKernelGGL(gather_slices_kernel, dim3(grid_of((long long)(nslices + 2) * N)), dim3(256), 0, s, b, rows,
-                     nslices, N, scale, alpha, rdiv, x);
+                     nslices, N, scale, alpha, rdiv, x, split ? 1 : 0);
   return hipGetLastError();
 }
 
 hipError_t launch_time_interp(const float* y, const int* rows, int nslices, const double* t, const double* g,
-                              long long M, long long N, double scale, double* u, hipStream_t s) {
+                              long long M, long long N, double scale, double* u, bool split, hipStream_t s) {
   if (nslices < 1 || nslices > kMaxSlices) return hipErrorInvalidValue;
   // a few blocks per row (each thread streams several columns), rows over y
   const long long gx = std::min<long long>((N + 255) / 256, 16);
   const long long gy = std::min<long long>(M, 65535);
   hipLaunchKernelGGL(time_interp_kernel, dim3((unsigned)std::max<long long>(gx, 1), (unsigned)std::max<long long>(gy, 1)),
-                     dim3(256), 0, s, y, rows, nslices, t, g, M, N, scale, u);
+                     dim3(256), 0, s, y, rows, nslices, t, g, M, N, scale, u, split ? 1 : 0);
   return hipGetLastError();
 }
 

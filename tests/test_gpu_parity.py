@@ -479,3 +479,53 @@ def test_stats_report_setup_and_solve_times(dev):
     u, st = plan.solve(_cuda(p.f, dev), tol=1e-10)
     assert st["setup_ms"] > 0.0 and st["solve_ms"] > 0.0
     assert st["solve_ms"] < 60e3 and np.isnan(st["warm_res0"])
+
+
+@pytest.mark.parametrize("schedule,n", [("staged", 31), ("staged", 63), ("pipelined", 31)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_bf16"])
+def test_colour_split_storage_is_bit_identical_to_natural(dev, schedule, n, precision):
+    """Colour-split storage moves points, not operations: every point's
+    arithmetic is the same in either storage, so the solutions (from zero
+    and from a given iterate, with an initial value g) agree bit for bit, and
+    the float64 one matches the oracle."""
+    rng = np.random.default_rng(77 + n)
+    M, N = 80, n * n
+    t = W.graded_mesh(M, 1.0, 3.0)
+    p = W.Problem(dim=2, n=n, M=M, alpha=0.5, r=3.0, k=8, t=t, f=rng.standard_normal((M, N)))
+    g = rng.standard_normal(N)
+    u0 = rng.standard_normal((M, N))
+    f, gd = _cuda(p.f, dev), _cuda(g, dev)
+    tol = 1e-12 if precision == "fp64" else 1e-10
+    out = {}
+    for layout, code in (("natural", 0), ("split", 1)):
+        print("case", schedule, n, precision, layout, flush=True)
+        plan = _plan(p, dev, schedule=schedule, precision=precision).set_layout(layout)
+        assert plan.info()["layout"] == code
+        u, st = plan.solve(f, gd, tol=tol)
+        ug = _cuda(u0, dev)
+        _, st2 = plan.solve(f, gd, tol=tol, u=ug, guess=True)
+        out[layout] = (u.cpu().numpy(), ug.cpu().numpy(), st["cycles"], st2["cycles"])
+    a, b = out["natural"], out["split"]
+    assert a[2:] == b[2:]
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    Rt = oracle.hmatrix_dense(p.t, p.alpha, p.k, p.leaf)
+    B = oracle.rhs(p.f, p.t, p.alpha, g)
+    ref = oracle.timestep_solve(Rt, B, p.dim, p.n, p.length)
+    err = np.max(np.abs(b[0] - ref)) / np.max(np.abs(ref))
+    res = np.max(np.abs(oracle.residual(Rt, b[1], B, p.dim, p.n, p.length))) / np.max(np.abs(B))
+    assert err < (1e-10 if precision == "fp64" else 1e-8) and res <= 1.5 * tol, (err, res)
+
+
+def test_autotuner_times_both_storages(dev):
+    """The autotuner's last candidate is its best schedule in the other
+    storage; whatever it keeps, the plan reports it and still solves to the
+    oracle's solution."""
+    p = W.manufactured(2, 63, 128, 0.5, r=3.0, k=8)
+    plan = _plan(p, dev)
+    f = _cuda(p.f, dev)
+    plan.autotune(f, tol=1e-10)
+    assert plan.info()["layout"] in (0, 1)
+    u, st = plan.solve(f, tol=1e-10)
+    Rt, w, s = _single_mode_reference(p)
+    ref = np.outer(w, s)
+    assert np.max(np.abs(u.cpu().numpy() - ref)) / np.max(np.abs(ref)) < 1e-9, st

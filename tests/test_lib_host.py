@@ -116,6 +116,23 @@ def test_staging_knobs_and_their_validation():
     assert mg.Plan(1, 1023, 512, 0.5, k=8, r=3.0).tuned()["schedule"] == "pipelined"
 
 
+def test_storage_choice_and_its_validation():
+    """2D plans default to colour-split storage, 1D plans are always natural;
+    the C entry point rejects unknown values."""
+    plan = mg.Plan(2, 31, 64, 0.5, k=6, r=3.0)
+    assert plan.info()["layout"] == 1
+    plan.set_layout("natural")
+    assert plan.info()["layout"] == 0
+    plan.set_layout("auto")
+    assert plan.info()["layout"] == 1
+    with pytest.raises(ValueError):
+        plan.set_layout("quincunx")
+    for bad in (2, -2, 7):
+        assert mg.lib().mgwr_plan_set_layout(plan._h, bad) == mg.MGWR_ERR_INVALID_ARG
+    one = mg.Plan(1, 31, 64, 0.5, k=6, r=3.0).set_layout("split")
+    assert one.info()["layout"] == 0
+
+
 def test_bfloat16_factors_take_less_workspace():
     args = (1, 255, 1024, 0.5)
     b64 = mg.Plan(*args, k=10, r=3.0).workspace_bytes()
