@@ -45,8 +45,16 @@ PEAK_HBM_GBS = 8000.0
 # FETCH_SIZE / WRITE_SIZE runs (KiB per dispatch) scaled by what the same
 # counters read for a 1 GiB device copy (--copy-probe: fetch x 2.000, write
 # x 1.000).  Keyed by the SHA-256 of kernels.hip they were taken on; a
-# different source reports null.
-TRAFFIC = {}
+# different source reports null.  batched: the side-by-side phase of one
+# batch solve (every kernel of the staged instances, the second solve of the
+# run); large2d: the average float64 SMOOTH march; large1d: the timed
+# pipelined launch (profiles/ holds the runs).
+_SHA = "38d512b9d5383f3f30bffbb781674f0ba28f6801c30da916e92de8ba0dda251a"
+TRAFFIC = {
+    "batched_fp64": (_SHA, 1.4168e12 + 5.957e11),
+    "large2d_fp64": (_SHA, 2.969e8 + 1.252e8),
+    "large1d_fp64": (_SHA, 4.865e10 + 8.865e9),
+}
 
 
 def parse():
@@ -310,8 +318,7 @@ def batched_forms(args, torch, mg, dev):
                      "max_rel_res": max(s["res"] / s["bnorm"] for s in st),
                      "setup_s": round(setup_s, 2), "graph_replays": batch.graph_replays(),
                      "pipelined_instances": sum(pl.tuned()["schedule"] == "pipelined" for pl in plans),
-                     "roofline": roofline(timing, precision,
-                                          "batched_one_launch" if sched == "pipelined" else None),
+                     "roofline": roofline(timing, precision, f"batched_{name}"),
                      "kernels": kernels_table(timing)}
         log(f"batched {name}: {out[name]['value']:.3e} unknowns/s, {out[name]['ms_per_step']:.1f} ms/step")
         batch.close()
