@@ -63,7 +63,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="all",
-                    choices=["all", "batched", "large2d", "learned2d", "large1d", "small1d"],
+                    choices=["all", "batched", "large2d", "learned2d", "large1d", "small1d", "paper1d"],
                     help="all: the batched headline and every form; otherwise only that workload's forms")
     ap.add_argument("--batch-count", type=int, default=64, help="instances of the batched workload")
     ap.add_argument("--batch-schedule", default="auto", choices=["auto", "pipelined", "autotune"],
@@ -385,6 +385,47 @@ def single_forms(name, probs, args, torch, mg, dev, learned=None, variants=None)
     return out
 
 
+# The paper's first experiment at its largest grid (x in (0, pi), f = 0,
+# g = sin x, N x M = 2048 x 2048, i.e. 2047 interior points and 2048 graded
+# steps, r = (2 - alpha)/alpha, k = 20, V(0,1), residual reduced by 1e-10):
+# cycles and seconds of the draft rows of its iteration table (commented out
+# in the paper's source; MATLAB on a 2.7 GHz Core i5 laptop).  Context only.
+PAPER_1D_DRAFT = {0.2: (11, 685.09), 0.4: (9, 598.86), 0.6: (7, 502.67), 0.8: (7, 553.54)}
+PAPER_HARDWARE = "MATLAB, MacBook Pro, Intel Core i5 2.7 GHz, 8 GB (draft timings, float64 inferred)"
+
+
+def paper_forms(args, torch, mg, dev):
+    """The paper's 1D experiment at 2048 x 2048, one solve at a time, next to
+    its draft timings."""
+    import workloads as W
+    per, secs_all, unknowns_all = {}, 0.0, 0
+    for a, (pc, ps) in PAPER_1D_DRAFT.items():
+        p = W.paper_1d_mittag_leffler(2047, 2048, a, k=20)
+        plan = mg.Plan(1, p.n, p.M, a, k=20, t=p.t, length=p.length, nu1=0, nu2=1, max_cycles=60).bind()
+        f = torch.zeros((p.M, p.n), dtype=torch.float64, device=dev)
+        g = torch.as_tensor(p.g, dtype=torch.float64, device=dev)
+        u = torch.empty_like(f)
+        for _ in range(max(args.warmup, 1)):
+            plan.solve(f, g, tol=1e-10, u=u)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, st = plan.solve(f, g, tol=1e-10, u=u)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        nm = p.n * p.M
+        per[str(a)] = {"seconds": dt, "cycles": st["cycles"], "unknowns_per_s": nm / dt,
+                       "paper_draft": {"seconds": ps, "cycles": pc, "unknowns_per_s": nm / ps}}
+        secs_all += dt
+        unknowns_all += nm
+        plan.close()
+        log(f"paper1d alpha={a}: {dt * 1e3:.2f} ms, cycles {st['cycles']} (paper draft {ps} s, {pc} cycles)")
+    return {"value": unknowns_all / secs_all, "ms_per_step": 1e3 * secs_all, "per_alpha": per,
+            "context": "the paper's own problem, grid and stopping rule (1e-10); its draft times are quoted as "
+                       "context, not as a baseline (another machine, MATLAB)",
+            "paper_hardware": PAPER_HARDWARE}
+
+
 def load_net(dim, max_bhw):
     from paper_1706_07632_amd import learn
     path = os.path.join(ROOT, "paper_1706_07632_amd", "weights", f"warm{dim}d.npz")
@@ -463,6 +504,12 @@ def main():
             head = ("large1d_fp64", {"workload": "large1d: 1D n=1023 M=4096 alpha in {0.3,0.5,0.7} r=(2-a)/a "
                                                  "k=10 leaf 16 V(1,1), three instances as one batch",
                                      "N": 1023, "M": 4096, "instances": 3, "tol": args.tol}, cpu)
+    if args.workload == "paper1d" or (args.workload == "all" and not args.value_only):
+        forms["paper1d_fp64"] = paper_forms(args, torch, mg, dev)
+        if head is None:
+            head = ("paper1d_fp64", {"workload": "paper1d: the paper's 1D experiment, N x M = 2048 x 2048, "
+                                                 "alpha in {0.2,0.4,0.6,0.8}, k=20, V(0,1), to 1e-10",
+                                     "N": 2047, "M": 2048, "instances": 4, "tol": 1e-10}, None)
     if args.workload == "small1d":
         p = W.config("small1d")
         f1 = single_forms("small1d", [p], args, torch, mg, dev)
