@@ -56,6 +56,12 @@ struct MarchArgs {
   T* Inj0;
   const T* Ec;
   int nc;
+  // RESID (float64) of a mixed-precision refinement step: the defect goes to
+  // Out32 rounded to float32 (the next inner right-hand side) instead of
+  // Out, and the marches launched on their own write each chain's max |r|
+  // to norm_out[chunk] (null: neither).
+  float* Out32;
+  double* norm_out;
 };
 
 // One stage of the time-pipelined kernel.  Stage kinds:
@@ -138,5 +144,7 @@ hipError_t launch_cast_bf16(const double* x, unsigned short* y, long long count,
 hipError_t launch_add_correction(double* u, const float* e, long long count, hipStream_t s);
 template <typename T>
 hipError_t launch_maxabs(const T* x, long long count, double* part, int nparts, double* out, hipStream_t s);
+// max over nparts partial maxima (NaN if any is NaN) into out[0]
+hipError_t launch_maxabs_parts(const double* part, int nparts, double* out, hipStream_t s);
 
 }  // namespace mgwr

@@ -707,10 +707,14 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
                 gst<PIPE>(a.Inj + (long long)(d.lo + row) * a.nc + p, (T)0.5 * v);
                 gst<PIPE>(a.Inj0 + (long long)(d.lo + row) * a.nc + p, (T)0);
               }
+            } else if (sizeof(T) == 8 && MODE == MODE_RESID && a.Out32) {
+              // the float64 defect of a refinement step, rounded once: the
+              // next float32 right-hand side
+              gst<PIPE>(a.Out32 + (long long)(d.lo + row) * a.ld + qs, (float)v);
             } else {
               gst<PIPE>(a.Out + (long long)(d.lo + row) * a.ld + qs, v);
             }
-            if constexpr (PIPE) {
+            if (PIPE || a.norm_out) {
               if (!(v == v) || __builtin_isinf(v)) nbad = true;
               else nmax = v > nmax ? v : (-v > nmax ? -v : nmax);
             }
@@ -739,15 +743,16 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
   if constexpr (PIPE) {
     if (wave == 0) signal_leaf(pc, nleaf - 1, lane);
   }
-  if constexpr (PIPE && MODE == MODE_RESID) {
-    if (pc.norm_out && wave == 0) {
+  if constexpr (MODE == MODE_RESID) {
+    double* const nout = PIPE ? pc.norm_out : a.norm_out;
+    if (nout && wave == 0) {
       double m = nbad ? __builtin_nan("") : (double)nmax;
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) {
         const double o = __shfl_xor(m, off, 64);
         m = (o != o || m != m) ? __builtin_nan("") : (o > m ? o : m);
       }
-      if (lane == 0) pc.norm_out[chunk] = m;
+      if (lane == 0) nout[chunk] = m;
     }
   }
 }
@@ -1464,6 +1469,11 @@ hipError_t launch_cast_bf16(const double* x, unsigned short* y, long long count,
 hipError_t launch_add_correction(double* u, const float* e, long long count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(add_correction_kernel, dim3(grid_for(count, 256)), dim3(256), 0, s, u, e, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_maxabs_parts(const double* part, int nparts, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(maxabs_final_kernel, dim3(1), dim3(256), 0, s, part, nparts, out);
   return hipGetLastError();
 }
 

@@ -389,6 +389,22 @@ int defect(mgwr_plan* pl, DevOps<T>& ops, int l, const T* F, T* U, T* Out, bool 
   return MGWR_OK;
 }
 
+// The float64 defect b - A u of a mixed-precision refinement step on level
+// 0, written rounded to float32 as the next inner right-hand side, with each
+// chain's max |r| in norms[chunk] (one pass instead of the defect, a cast and
+// a norm over the float64 array).
+int defect_rhs32(mgwr_plan* pl, const double* F, double* U, float* rhs32, double* norms) {
+  const HostPlan& hp = pl->hp;
+  const Level& lv = hp.levels[0];
+  MarchArgs<double> a = base_args<double>(pl, pl->d64, 0);
+  a.F = F; a.U = U; a.Out = nullptr; a.Out32 = rhs32; a.norm_out = norms;
+  a.ld = lv.N; a.ncols = lv.N; a.cstride = 1; a.coff = 0;
+  a.dim = hp.p.dim; a.n = lv.n; a.inv_h2 = 1.0 / (lv.h * lv.h);
+  Timed tm(pl, MGWR_K_DEFECT64, 2.0 * hp.stored * a.ncols, 2.5 * hp.p.M * a.ncols * sizeof(double));
+  HIP_TRY(launch_march<double>(MODE_RESID, a, pl->stream));
+  return MGWR_OK;
+}
+
 template <typename T>
 int coarse_cycle(mgwr_plan* pl, int l);
 
@@ -1575,8 +1591,11 @@ int mgwr_solve(mgwr_plan* pl, const double* f, const double* g, double tol, doub
       }
       HIP_TRY(launch_add_correction(u, pl->d32.U[0], MN, pl->stream));
       s.refinements++;
-      if ((rc = defect<double>(pl, pl->d64, 0, b, u, pl->d64.R[0]))) return rc;
-      if ((rc = norm_inf<double>(pl, pl->d64.R[0], MN, &s.res))) return rc;
+      // the defect is the next float32 right-hand side; its norm from the
+      // chains' partial maxima
+      if ((rc = defect_rhs32(pl, b, u, pl->d32.F[0], pl->norms))) return rc;
+      HIP_TRY(launch_maxabs_parts(pl->norms, (int)((hp.levels[0].N + 15) / 16), pl->scal, pl->stream));
+      if ((rc = read_scalar(pl, &s.res))) return rc;
       if (s.refinements <= 64) s.history[s.refinements - 1] = s.res;
       if (s.refinements == 1 && fall_back_to_zero(pl, b, u, s, s.cycles, tol, &rc)) {
         if (rc) return rc;
@@ -1585,7 +1604,6 @@ int mgwr_solve(mgwr_plan* pl, const double* f, const double* g, double tol, doub
       }
       if (!std::isfinite(s.res)) { status = MGWR_ERR_NONFINITE; break; }
       if (s.res <= target) { status = MGWR_OK; break; }
-      HIP_TRY(launch_cast<double, float>(pl->d64.R[0], pl->d32.F[0], MN, pl->stream));
     }
   }
   if (pl->coarse_l > 0 && s.cycles > 0) {
