@@ -59,7 +59,8 @@ struct MarchArgs {
   // RESID (float64) of a mixed-precision refinement step: the defect goes to
   // Out32 rounded to float32 (the next inner right-hand side) instead of
   // Out, and the marches launched on their own write each chain's max |r|
-  // to norm_out[chunk] (null: neither).
+  // to norm_out[chunk] (null: neither).  A march launched on its own with
+  // neither Out nor Out32 stores no defect, only its norms (stopping tests).
   float* Out32;
   double* norm_out;
 };

@@ -711,7 +711,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
               // the float64 defect of a refinement step, rounded once: the
               // next float32 right-hand side
               gst<PIPE>(a.Out32 + (long long)(d.lo + row) * a.ld + qs, (float)v);
-            } else {
+            } else if (PIPE || a.Out) {   // (a stopping-test defect keeps only its norm)
               gst<PIPE>(a.Out + (long long)(d.lo + row) * a.ld + qs, v);
             }
             if (PIPE || a.norm_out) {

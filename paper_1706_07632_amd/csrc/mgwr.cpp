@@ -405,6 +405,25 @@ int defect_rhs32(mgwr_plan* pl, const double* F, double* U, float* rhs32, double
   return MGWR_OK;
 }
 
+int read_scalar(mgwr_plan* pl, double* host);
+
+// The norm ||b - A u||_inf on level 0 (float64) without storing the defect:
+// each chain's max |r| goes to norms[chunk], reduced into pl->scal and read.
+int defect_norm(mgwr_plan* pl, const double* F, double* U, double* norms, double* host) {
+  const HostPlan& hp = pl->hp;
+  const Level& lv = hp.levels[0];
+  MarchArgs<double> a = base_args<double>(pl, pl->d64, 0);
+  a.F = F; a.U = U; a.Out = nullptr; a.norm_out = norms;
+  a.ld = lv.N; a.ncols = lv.N; a.cstride = 1; a.coff = 0;
+  a.dim = hp.p.dim; a.n = lv.n; a.inv_h2 = 1.0 / (lv.h * lv.h);
+  {
+    Timed tm(pl, MGWR_K_DEFECT64, 2.0 * hp.stored * a.ncols, 2.0 * hp.p.M * a.ncols * sizeof(double));
+    HIP_TRY(launch_march<double>(MODE_RESID, a, pl->stream));
+  }
+  HIP_TRY(launch_maxabs_parts(norms, (int)((lv.N + 15) / 16), pl->scal, pl->stream));
+  return read_scalar(pl, host);
+}
+
 template <typename T>
 int coarse_cycle(mgwr_plan* pl, int l);
 
@@ -1562,8 +1581,7 @@ int mgwr_solve(mgwr_plan* pl, const double* f, const double* g, double tol, doub
       s.cycles++;
       const bool judge = s.used_warm_start && s.cycles == 1;
       if (!judge && s.cycles < skip_to) continue;
-      if ((rc = defect<double>(pl, pl->d64, 0, b, u, pl->d64.R[0]))) return rc;
-      if ((rc = norm_inf<double>(pl, pl->d64.R[0], MN, &s.res))) return rc;
+      if ((rc = defect_norm(pl, b, u, pl->norms, &s.res))) return rc;
       if (s.cycles <= 64) s.history[s.cycles - 1] = s.res;
       if (s.cycles == 1 && fall_back_to_zero(pl, b, u, s, 1, tol, &rc)) {
         if (rc) return rc;
