@@ -74,6 +74,8 @@ def parse():
                     help="float32 V-cycles per float64 refinement step of the mixed forms; 0: each workload's "
                          "measured best (batched 3, 2D n=255 2, 1D 1)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--xcd-queues", action="store_true",
+                    help="deal the pipelined launches' work items to per-XCD queues (off by default)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--value-only", action="store_true",
@@ -450,6 +452,7 @@ def main():
     import paper_1706_07632_amd as mg
     import workloads as W
     dev = torch.device("cuda", 0)
+    mg.set_xcd_queues(args.xcd_queues)
     forms, cpu_all = {}, {}
     head = None
     if args.workload in ("all", "batched"):

@@ -275,6 +275,25 @@ int mgwr_batch_set_graph(mgwr_batch* batch, int enable);
 /* Number of graph replays so far (host). */
 int mgwr_batch_graph_replays(const mgwr_batch* batch, long long* replays);
 
+/* Per-XCD work queues of the time-pipelined launches (process-wide, off by
+ * default: the static split loses the global ticket's load balance, and the
+ * launches measured slower although they fetch less).  Workgroups are dispatched to the chip's 8 XCDs round-robin
+ * (workgroup b on XCD b mod 8, each XCD with its own L2); with the queues a
+ * launch's work items are dealt to the XCDs so that each round of the merged
+ * instances' stages is cut into 8 contiguous blocks, one per XCD: an
+ * instance's chains stay on the same XCDs in every stage, and its H-matrix
+ * rows are read from their L2 instead of once per XCD per stage.  Each
+ * queue lists its work items in stage order and holds exactly as many as its
+ * XCD runs workgroups, which keeps the launch free of deadlock as with one
+ * global ticket; the dispatch order is checked on each device (a probe
+ * launch at the first binding) and the queues are used only where it holds.
+ * Results are the same either way.  *previous (nullable) receives the old
+ * setting. */
+int mgwr_set_xcd_queues(int enable, int* previous);
+/* Whether this plan's pipelined launches use the queues (enabled and the
+ * device's dispatch confirmed); the plan must be bound. */
+int mgwr_xcd_queues_in_use(const mgwr_plan* plan, int* in_use);
+
 /* Autotuner of the schedule and of the staged schedule's knobs: solves f
  * twice with each candidate (the second solve of each runs with the cycle
  * count the first one learned) and keeps the fastest.  Candidates: whole

@@ -39,7 +39,7 @@ EXPORTED = [
     "mgwr_net_adam_step", "mgwr_net_destroy",
     "mgwr_plan_set_warm_start", "mgwr_batch_set_graph", "mgwr_batch_graph_replays", "mgwr_plan_autotune",
     "mgwr_plan_set_staging", "mgwr_plan_tuned", "mgwr_plan_set_layout", "mgwr_apply_A", "mgwr_model_describe",
-    "mgwr_model_load",
+    "mgwr_model_load", "mgwr_set_xcd_queues", "mgwr_xcd_queues_in_use",
     "mgwr_solve_static",
 ]
 
@@ -148,6 +148,8 @@ def lib():
     L.mgwr_plan_set_staging.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     L.mgwr_plan_set_layout.argtypes = [vp, ctypes.c_int]
     ipp = ctypes.POINTER(ctypes.c_int)
+    L.mgwr_set_xcd_queues.argtypes = [ip, ipp]
+    L.mgwr_xcd_queues_in_use.argtypes = [vp, ipp]
     L.mgwr_plan_tuned.argtypes = [vp, ipp, ipp, ipp]
     L.mgwr_net_create.argtypes = [ip, ctypes.POINTER(ctypes.c_int), ip, ctypes.POINTER(vp)]
     L.mgwr_net_param_count.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
@@ -420,6 +422,13 @@ class Plan:
         return {"schedule": {1: "staged", 2: "pipelined"}[s.value],
                 "prefetch": {0: "by_length", 1: "shallow", 2: "deep"}[p.value], "coarse_level": c.value}
 
+    def xcd_queues_in_use(self):
+        """Whether this (bound) plan's pipelined launches deal their work
+        items to per-XCD queues."""
+        v = ctypes.c_int()
+        _check(lib().mgwr_xcd_queues_in_use(self._h, ctypes.byref(v)))
+        return bool(v.value)
+
     def set_progress_limit(self, polls: int):
         """Bound on the polls of one progress wait of a pipelined launch
         (default 4194304); beyond it the solve fails with MGWR_ERR_HIP."""
@@ -646,6 +655,14 @@ def model_blob(channels, nsignal, rows, h_min, params) -> bytes:
     body += struct.pack("<ii", int(nsignal), len(rows)) + struct.pack(f"<{len(rows)}i", *rows)
     body += struct.pack("<dq", float(h_min), int(w.size)) + w.tobytes()
     return body + struct.pack("<Q", _fnv1a64(body))
+
+
+def set_xcd_queues(enable: bool) -> bool:
+    """Per-XCD work queues of the pipelined launches (process-wide, on by
+    default); returns the previous setting."""
+    prev = ctypes.c_int()
+    _check(lib().mgwr_set_xcd_queues(1 if enable else 0, ctypes.byref(prev)))
+    return bool(prev.value)
 
 
 def describe_model(blob):

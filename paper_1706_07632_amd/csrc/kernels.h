@@ -77,6 +77,7 @@ struct Stage {
   int kind;
   int prev;          // producer stage (index into the stage array) or -1
   int nchunks;       // work items of this stage
+  int round;         // stages of one round (the same position in several instances' lists) are independent
   int task0;         // first work item (tickets are taken in stage order)
   int cnt_off;       // this stage's per-leaf counters start at counters + cnt_off
   int nleaf;
@@ -98,15 +99,33 @@ struct Stage {
   long long npoints;     // STG_CAST / STG_CORRECT: points per time row
 };
 
+// Workgroup b of a launch runs on XCD b mod kXcdQueues (round-robin
+// dispatch, checked on the device before per-XCD queues are used).
+constexpr int kXcdQueues = 8;
+
 struct PipeArgs {
-  const Stage* stages;
-  int nstages;
-  int ntasks;
-  int* counters;
-  int* ticket;
-  int* abortf;
-  unsigned spin_limit;   // polls of a progress wait before the launch gives up
+  const Stage* stages = nullptr;
+  int nstages = 0;
+  int ntasks = 0;
+  int* counters = nullptr;
+  int* ticket = nullptr;
+  int* abortf = nullptr;
+  unsigned spin_limit = 0;   // polls of a progress wait before the launch gives up
+  // Per-XCD work queues (xq null: one global ticket).  Workgroup b takes the
+  // next task of queue b mod kXcdQueues: xq[xq_off[x] + t], t < xq_len[x].
+  // Every queue lists its tasks in increasing order (stage order) and holds
+  // exactly as many tasks as workgroups run on its XCD, so a workgroup waits
+  // only for tasks of earlier stages, each already taken by a workgroup that
+  // is running (the argument of the global ticket, per XCD).
+  const int* xq = nullptr;
+  int xq_off[kXcdQueues] = {};
+  int xq_len[kXcdQueues] = {};
+  int* xq_ticket = nullptr;
 };
+
+// One workgroup per block writes the hardware XCD id (XCC_ID) of the XCD it
+// runs on to out[blockIdx.x].
+hipError_t launch_xcc_probe(int* out, int blocks, hipStream_t s);
 
 // Default bound on the polls of one progress wait (each poll sleeps about
 // 128 cycles when it fails): seconds, far beyond any producer's lag.

@@ -1053,7 +1053,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void p
   __shared__ int sh_task;
   __shared__ int sh_abort;
   if (threadIdx.x == 0) {
-    sh_task = atomicAdd(pa.ticket, 1);
+    if (pa.xq) {
+      const int x = (int)(blockIdx.x % kXcdQueues);
+      const int t = atomicAdd(pa.xq_ticket + x, 1);
+      sh_task = t < pa.xq_len[x] ? pa.xq[pa.xq_off[x] + t] : pa.ntasks;
+    } else {
+      sh_task = atomicAdd(pa.ticket, 1);
+    }
     sh_abort = 0;
   }
   __syncthreads();
@@ -1110,6 +1116,16 @@ hipError_t launch_pipeline(const PipeArgs& pa, size_t lds, hipStream_t s) {
 }
 
 hipError_t set_pipeline_lds_limit(size_t bytes) { return set_dyn_lds((const void*)pipeline_kernel, bytes); }
+
+// XCC_ID is hardware register 20 (bits 3:0) on gfx940 and later.
+__global__ void xcc_probe_kernel(int* __restrict__ out) {
+  if (threadIdx.x == 0) out[blockIdx.x] = __builtin_amdgcn_s_getreg(20 | (0 << 6) | ((4 - 1) << 11)) & 15;
+}
+
+hipError_t launch_xcc_probe(int* out, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(xcc_probe_kernel, dim3(blocks), dim3(64), 0, s, out);
+  return hipGetLastError();
+}
 
 __global__ void fill_int_kernel(int* __restrict__ x, long long count, int v) {
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < count;

@@ -119,7 +119,10 @@ struct mgwr_plan {
   const double* stages_u = nullptr;
   Stage* stages_dev = nullptr;
   int* counters = nullptr;
-  int* flags_dev = nullptr;            // [0] ticket, [1] abort
+  int* flags_dev = nullptr;            // [0] ticket, [1] abort, [2 .. 2 + kXcdQueues) per-XCD tickets
+  int* xq = nullptr;                   // per-XCD task queues of its pipelined launches
+  long long xq_cap = 0;                // their capacity (tasks)
+  int* xprobe = nullptr;               // 64 ints: the XCD check at binding
   double* norms = nullptr;             // [kMaxPipeCycles][norm_chunks]
   int khint = 0;                       // cycles the last pipelined solve from a zero or given iterate needed
   int khint_warm = 0;                  // the same from a predicted iterate
@@ -159,7 +162,7 @@ struct mgwr_plan {
   int* rows_dev = nullptr;
   // offsets computed by layout()
   struct Off {
-    size_t stages, counters, flags, norms, wrows, cstages, ccounters, cflags;
+    size_t stages, counters, flags, norms, wrows, cstages, ccounters, cflags, xq, xprobe;
     size_t leaves, dn_list, ff_row, zu_row, a1, tm, B0, part, scal;
     size_t dense64, dinv64, ffA64, zuB64, dense32, dinv32, ffA32, zuB32;
     std::vector<size_t> U64, F64, R64, U32, F32, R32;
@@ -181,6 +184,21 @@ long long stages_per_cycle_bound(const HostPlan& hp) {
     visits *= hp.p.gamma;
   }
   return spc;
+}
+
+// Work items a pipelined launch of one plan can hold: the stages counted as
+// in stages_per_cycle_bound, each with at most one item per 16 points of its
+// level, over kMaxPipeCycles cycles.
+long long xq_capacity(const HostPlan& hp) {
+  const int L = (int)hp.levels.size();
+  long long per = 3 * ((hp.levels[0].N + 15) / 16), visits = 1;
+  for (int l = 0; l < L; ++l) {
+    const long long items = (hp.levels[l].N + 15) / 16;
+    if (l == L - 1) per += 2 * visits * items;
+    else per += visits * (2LL * (hp.p.nu1 + hp.p.nu2) + 3) * items;
+    visits *= hp.p.gamma;
+  }
+  return per * mgwr_plan::kMaxPipeCycles;
 }
 
 void layout(mgwr_plan* pl) {
@@ -234,8 +252,11 @@ void layout(mgwr_plan* pl) {
     const long long S = stages_per_cycle_bound(hp) * mgwr_plan::kMaxPipeCycles;
     o.stages = cv.take((size_t)S * sizeof(Stage));
     o.counters = cv.take((size_t)S * nleaf * sizeof(int));
-    o.flags = cv.take(2 * sizeof(int));
+    o.flags = cv.take((2 + kXcdQueues) * sizeof(int));
     o.norms = cv.take((size_t)mgwr_plan::kMaxPipeCycles * ((hp.levels[0].N + 15) / 16) * sizeof(double));
+    // a launch's tasks: at most every stage with the largest work-item count
+    o.xq = cv.take((size_t)xq_capacity(hp) * sizeof(int));
+    o.xprobe = cv.take(64 * sizeof(int));
     // the coarse part of a staged cycle (one cycle from level >= 1)
     const long long C = stages_per_cycle_bound(hp);
     o.cstages = cv.take((size_t)2 * C * sizeof(Stage));
@@ -762,7 +783,7 @@ int coarse_cycle(mgwr_plan* pl, int l) {
                            pl->stream));
     pl->coarse_up[w] = true;
   }
-  PipeArgs pa;
+  PipeArgs pa{};   // every field zero (no per-XCD queues unless set)
   pa.stages = pl->cstages_dev[w];
   pa.nstages = (int)st.size();
   pa.ntasks = pl->coarse_tasks[w];
@@ -905,7 +926,10 @@ struct mgwr_batch {
   bool bound = false;
   int device = -1;
   hipStream_t stream = nullptr;
-  size_t off_stages = 0, off_counters = 0, off_flags = 0, off_norms = 0, total = 0;
+  size_t off_stages = 0, off_counters = 0, off_flags = 0, off_norms = 0, off_xq = 0, total = 0;
+  int* xq = nullptr;          // per-XCD task queues of the merged launch
+  long long xq_cap = 0;
+  bool graph_xq = false;      // the captured graph uses them
   std::vector<size_t> norm_off;  // per plan, in doubles
   Stage* stages_dev = nullptr;
   int* counters = nullptr;
@@ -1071,10 +1095,82 @@ int fall_back_to_zero(mgwr_plan* pl, const double* b, double* u, mgwr_stats& s, 
 // Launch of the merged stage table: counters and flags cleared, then the
 // pipeline kernel; replayed from a captured graph when the table, counter
 // count and grid equal those of the graph (batches with graphs enabled).
+namespace {
+// Per-XCD work queues of pipelined launches (PipeArgs::xq): off by default
+// (mgwr_set_xcd_queues; measured slower, see the header), used on a device
+// once a probe launch has shown that workgroup b runs on XCD b mod
+// kXcdQueues.
+std::atomic<int> g_xcd_queues{0};
+std::mutex g_xcd_mu;
+std::map<int, bool> g_xcd_ok;   // device -> round-robin dispatch confirmed
+
+// Runs the probe once per device, on `scratch` (64 ints of the caller's
+// workspace); the result is kept for the process.
+int check_xcd_dispatch(int device, int* scratch, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_xcd_mu);
+  if (g_xcd_ok.count(device)) return MGWR_OK;
+  int h[64];
+  HIP_TRY(launch_xcc_probe(scratch, 64, s));
+  HIP_TRY(hipMemcpyAsync(h, scratch, sizeof(h), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  bool ok = true;
+  for (int b = 0; b < 64; ++b) ok = ok && h[b] == b % kXcdQueues;
+  g_xcd_ok[device] = ok;
+  return MGWR_OK;
+}
+
+bool xcd_dispatch_ok(int device) {
+  std::lock_guard<std::mutex> lk(g_xcd_mu);
+  auto it = g_xcd_ok.find(device);
+  return it != g_xcd_ok.end() && it->second;
+}
+
+// Per-XCD queues of a stage table with ntasks work items.  Each round (the
+// stages at one position of the merged instances' lists) is cut into
+// kXcdQueues contiguous blocks of nearly equal size, block x to queue x: an
+// instance's work items of every round land on the same XCDs, whose L2 then
+// holds its H-matrix rows for all its stages.  The queues are then brought
+// to the lengths the dispatch gives each XCD (workgroup b on XCD b mod
+// kXcdQueues) by moving the latest tasks of longer queues, and sorted, so
+// each lists its tasks in stage order.
+void build_xcd_queues(const std::vector<Stage>& st, int ntasks, std::vector<int>& q, int* off, int* len) {
+  std::vector<std::vector<int>> lists(kXcdQueues);
+  for (size_t i = 0; i < st.size();) {
+    size_t j = i;
+    long long n = 0;
+    while (j < st.size() && st[j].round == st[i].round) n += st[j++].nchunks;
+    long long pos = 0;
+    for (size_t k = i; k < j; ++k)
+      for (int c = 0; c < st[k].nchunks; ++c, ++pos) lists[(int)(pos * kXcdQueues / n)].push_back(st[k].task0 + c);
+    i = j;
+  }
+  std::vector<int> want(kXcdQueues);
+  for (int x = 0; x < kXcdQueues; ++x) want[x] = ntasks > x ? (ntasks - x + kXcdQueues - 1) / kXcdQueues : 0;
+  std::vector<int> spare;
+  for (int x = 0; x < kXcdQueues; ++x)
+    while ((int)lists[x].size() > want[x]) {
+      spare.push_back(lists[x].back());
+      lists[x].pop_back();
+    }
+  for (int x = 0; x < kXcdQueues; ++x)
+    while ((int)lists[x].size() < want[x] && !spare.empty()) {
+      lists[x].push_back(spare.back());
+      spare.pop_back();
+    }
+  q.clear();
+  for (int x = 0; x < kXcdQueues; ++x) {
+    std::sort(lists[x].begin(), lists[x].end());
+    off[x] = (int)q.size();
+    len[x] = (int)lists[x].size();
+    q.insert(q.end(), lists[x].begin(), lists[x].end());
+  }
+}
+}  // namespace
+
 int launch_batch_table(mgwr_batch* bt, long long ncnt, int ntasks) {
   bt->spin_limit = kDefaultSpinLimit;
   for (const mgwr_plan* p : bt->plans) bt->spin_limit = std::min(bt->spin_limit, p->spin_limit);
-  PipeArgs pa;
+  PipeArgs pa{};   // every field zero (no per-XCD queues unless set)
   pa.stages = bt->stages_dev;
   pa.nstages = (int)bt->stages.size();
   pa.ntasks = ntasks;
@@ -1082,8 +1178,17 @@ int launch_batch_table(mgwr_batch* bt, long long ncnt, int ntasks) {
   pa.ticket = bt->flags_dev;
   pa.abortf = bt->flags_dev + 1;
   pa.spin_limit = bt->spin_limit;
+  pa.xq = nullptr;
+  pa.xq_ticket = bt->flags_dev + 2;
+  const bool use_xq = g_xcd_queues.load() != 0 && bt->xq && ntasks <= bt->xq_cap && xcd_dispatch_ok(bt->device);
+  std::vector<int> q;
+  if (use_xq) {
+    build_xcd_queues(bt->stages, ntasks, q, pa.xq_off, pa.xq_len);
+    if ((int)q.size() != ntasks) return fail(MGWR_ERR_STATE, "internal error: XCD queues do not hold every task");
+    pa.xq = bt->xq;
+  }
   const bool same = bt->graph_exec && bt->graph_ncnt == ncnt && bt->graph_ntasks == ntasks &&
-                    bt->graph_spin == bt->spin_limit &&
+                    bt->graph_spin == bt->spin_limit && bt->graph_xq == use_xq &&
                     bt->graph_stages.size() == bt->stages.size() &&
                     std::memcmp(bt->graph_stages.data(), bt->stages.data(), bt->stages.size() * sizeof(Stage)) == 0;
   if (same) {
@@ -1093,9 +1198,10 @@ int launch_batch_table(mgwr_batch* bt, long long ncnt, int ntasks) {
   }
   HIP_TRY(hipMemcpyAsync(bt->stages_dev, bt->stages.data(), bt->stages.size() * sizeof(Stage),
                          hipMemcpyHostToDevice, bt->stream));
+  if (use_xq) HIP_TRY(hipMemcpyAsync(bt->xq, q.data(), q.size() * sizeof(int), hipMemcpyHostToDevice, bt->stream));
   if (!bt->use_graph) {
     HIP_TRY(launch_fill_int(bt->counters, ncnt, 0, bt->stream));
-    HIP_TRY(launch_fill_int(bt->flags_dev, 2, 0, bt->stream));
+    HIP_TRY(launch_fill_int(bt->flags_dev, 2 + kXcdQueues, 0, bt->stream));
     HIP_TRY(launch_pipeline(pa, bt->lds, bt->stream));
     return MGWR_OK;
   }
@@ -1106,7 +1212,7 @@ int launch_batch_table(mgwr_batch* bt, long long ncnt, int ntasks) {
   if (!bt->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&bt->capture_stream, hipStreamNonBlocking));
   HIP_TRY(hipStreamBeginCapture(bt->capture_stream, hipStreamCaptureModeRelaxed));
   hipError_t e1 = launch_fill_int(bt->counters, ncnt, 0, bt->capture_stream);
-  hipError_t e2 = launch_fill_int(bt->flags_dev, 2, 0, bt->capture_stream);
+  hipError_t e2 = launch_fill_int(bt->flags_dev, 2 + kXcdQueues, 0, bt->capture_stream);
   hipError_t e3 = launch_pipeline(pa, bt->lds, bt->capture_stream);
   hipGraph_t gr = nullptr;
   hipError_t e4 = hipStreamEndCapture(bt->capture_stream, &gr);
@@ -1120,6 +1226,7 @@ int launch_batch_table(mgwr_batch* bt, long long ncnt, int ntasks) {
   bt->graph_ncnt = ncnt;
   bt->graph_ntasks = ntasks;
   bt->graph_spin = bt->spin_limit;
+  bt->graph_xq = use_xq;
   HIP_TRY(hipGraphLaunch(bt->graph_exec, bt->stream));
   return MGWR_OK;
 }
@@ -1182,6 +1289,7 @@ int solve_pipelined(mgwr_batch* bt, const double* const* f, const double* const*
         if (pos >= lists[a].size()) continue;
         Stage x = lists[a][pos];
         x.prev = x.prev >= 0 ? gidx[a][x.prev] : -1;
+        x.round = (int)pos;
         gidx[a][pos] = (int)bt->stages.size();
         bt->stages.push_back(x);
       }
@@ -1364,6 +1472,9 @@ void assign_pointers(mgwr_plan* pl, unsigned char* w, size_t bytes, hipStream_t 
   pl->counters = (int*)(w + o.counters);
   pl->flags_dev = (int*)(w + o.flags);
   pl->norms = (double*)(w + o.norms);
+  pl->xq = (int*)(w + o.xq);
+  pl->xq_cap = xq_capacity(hp);
+  pl->xprobe = (int*)(w + o.xprobe);
   {
     const long long C = stages_per_cycle_bound(hp);
     pl->cstages_dev[0] = (Stage*)(w + o.cstages);
@@ -1484,6 +1595,10 @@ int mgwr_plan_bind(mgwr_plan* pl, void* ws, size_t bytes, void* stream) {
   HIP_TRY(set_march_lds_limit<double>(cap));
   HIP_TRY(set_march_lds_limit<float>(cap));
   HIP_TRY(set_pipeline_lds_limit(cap));
+  {
+    const int xrc = check_xcd_dispatch(pl->device, pl->xprobe, pl->stream);
+    if (xrc) return xrc;
+  }
   HIP_TRY(hipStreamSynchronize(pl->stream));
   pl->bound = true;
   pl->bind_ms = ms_since(t_start);
@@ -1529,6 +1644,8 @@ int mgwr_solve(mgwr_plan* pl, const double* f, const double* g, double tol, doub
     one.stages_dev = pl->stages_dev;
     one.counters = pl->counters;
     one.flags_dev = pl->flags_dev;
+    one.xq = pl->xq;
+    one.xq_cap = pl->xq_cap;
     one.norms = pl->norms;
     one.lds = march_lds_bytes<double>(base_args<double>(pl, pl->d64, 0));
     if (pl->mixed) one.lds = std::max(one.lds, march_lds_bytes<float>(base_args<float>(pl, pl->d32, 0)));
@@ -1910,10 +2027,14 @@ int mgwr_batch_create(int count, mgwr_plan* const* plans, mgwr_batch** out) {
     bt->lds = std::max(bt->lds, march_lds_bytes<double>(base_args<double>(pl, pl->d64, 0)));
     if (pl->mixed) bt->lds = std::max(bt->lds, march_lds_bytes<float>(base_args<float>(pl, pl->d32, 0)));
   }
+  long long nxq = 0;
+  for (int i = 0; i < count; ++i) nxq += xq_capacity(plans[i]->hp);
   bt->off_stages = cv.take((size_t)nst * sizeof(Stage));
   bt->off_counters = cv.take((size_t)ncnt * sizeof(int));
-  bt->off_flags = cv.take(2 * sizeof(int));
+  bt->off_flags = cv.take((2 + kXcdQueues) * sizeof(int));
   bt->off_norms = cv.take((size_t)nnorm * sizeof(double));
+  bt->off_xq = cv.take((size_t)nxq * sizeof(int));
+  bt->xq_cap = nxq;
   bt->total = cv.off;
   *out = bt;
   return MGWR_OK;
@@ -1937,6 +2058,7 @@ int mgwr_batch_bind(mgwr_batch* bt, void* ws, size_t bytes, void* stream) {
   bt->counters = (int*)(w + bt->off_counters);
   bt->flags_dev = (int*)(w + bt->off_flags);
   bt->norms = (double*)(w + bt->off_norms);
+  bt->xq = (int*)(w + bt->off_xq);
   bt->bound = true;
   return MGWR_OK;
 }
@@ -2097,6 +2219,19 @@ int mgwr_batch_solve(mgwr_batch* bt, const double* const* f, const double* const
     }
   }
   if (ret != MGWR_OK) return batch_fail(ret, msg);
+  return MGWR_OK;
+}
+
+int mgwr_set_xcd_queues(int enable, int* previous) {
+  const int old = g_xcd_queues.exchange(enable ? 1 : 0);
+  if (previous) *previous = old;
+  return MGWR_OK;
+}
+
+int mgwr_xcd_queues_in_use(const mgwr_plan* pl, int* in_use) {
+  if (!pl || !in_use) return fail(MGWR_ERR_INVALID_ARG, "null argument");
+  if (!pl->bound) return fail(MGWR_ERR_STATE, "plan is not bound to a workspace");
+  *in_use = g_xcd_queues.load() != 0 && xcd_dispatch_ok(pl->device) ? 1 : 0;
   return MGWR_OK;
 }
 

@@ -217,3 +217,33 @@ def test_stall_in_one_side_by_side_instance_is_reported(dev):
     us, sts = batch.solve(fs, tol=1e-12)
     for p, u in zip(probs, us):
         _check(p, u, _modewise_reference(p), 1e-12)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_xcd_queues_give_the_same_results(dev, precision):
+    """Pipelined launches deal their work items to per-XCD queues by default
+    (the dispatch order checked on the device) or take them from one global
+    ticket: the same stages run the same arithmetic either way, so batched
+    and single solves agree bit for bit, and match the oracle."""
+    probs = [W.manufactured(1, 127, 512, a, r=(2 - a) / a, k=8) for a in (0.3, 0.5, 0.7)]
+    probs.append(W.manufactured(2, 31, 128, 0.4, r=3.0, k=8))
+    plans = [_plan(p, schedule="pipelined", precision=precision) for p in probs]
+    fs = [_cuda(p.f, dev) for p in probs]
+    batch = mg.Batch(plans).bind()
+    out = {}
+    for on in (True, False):
+        prev = mg.set_xcd_queues(on)
+        try:
+            assert plans[0].xcd_queues_in_use() == on
+            us, sts = batch.solve(fs, tol=1e-11)
+            u1, st1 = plans[0].solve(fs[0], tol=1e-11)
+            out[on] = ([u.cpu().numpy() for u in us], [s["cycles"] for s in sts], u1.cpu().numpy(), st1["cycles"])
+        finally:
+            mg.set_xcd_queues(prev)
+    a, b = out[True], out[False]
+    assert a[1] == b[1] and a[3] == b[3]
+    assert all(np.array_equal(x, y) for x, y in zip(a[0], b[0])) and np.array_equal(a[2], b[2])
+    for p, u in zip(probs, a[0]):
+        ref = _modewise_reference(p)
+        err = np.abs(u - ref).max() / np.abs(ref).max()
+        assert err < (1e-10 if precision == "fp64" else 1e-8), (p.name, err)
