@@ -242,8 +242,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
   T* ring = reinterpret_cast<T*>(smem_raw);   // [R][16][16] x of recent leaves, row-major
   T* part = ring + a.ring * 256;               // [NW + 1][16][16] partial right-hand sides (slot NW:
                                                // the IO wave's, odd leaves)
-  T* tbuf = part + (NW + 1) * 256;             // [16][16] float32 transposition (none in float64)
-  T* Z = tbuf + (sizeof(T) == 4 ? 256 : 0);    // [nslots*k + 1][16]; the last row takes the writes of unused slots
+  T* Z = part + (NW + 1) * 256;                // [nslots*k + 1][16]; the last row takes the writes of unused slots
 
   const int wave = __builtin_amdgcn_readfirstlane(((threadIdx.x >> 6) + kRoleShift) & (NW - 1));   // role
   // In the pipelined kernel the IO wave (producer wait, loads of the leaf
@@ -648,30 +647,26 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
       if constexpr (PIPE) {
         if (s >= 1) signal_leaf(pc, s - 1, lane);   // its rows went out in the last phase 1
       }
+      // The sum of the partial right-hand sides.  A solve takes it as the B
+      // operand of its products: element kc of lane (g, c) sums row
+      // 4 kc + g (the float64 result layout, drow<double>), so no float32
+      // solve moves it between lanes; a defect keeps the result layout.
       v4 acc;
       const T* io = ioslot(s);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        T v = io[drow<T>(g, r) * 16 + c];
+        const int row = kSolve ? drow<double>(g, r) : drow<T>(g, r);
+        T v = io[row * 16 + c];
 #pragma unroll
-        for (int w = 0; w < NPW; ++w) v += part[w * 256 + drow<T>(g, r) * 16 + c];
+        for (int w = 0; w < NPW; ++w) v += part[w * 256 + row * 16 + c];
         acc[r] = v;
       }
       T* cur = ring + (s % a.ring) * 256;
       if constexpr (kSolve) {
         v4 x = {0, 0, 0, 0};
-        if constexpr (sizeof(T) == 8) {
-          // f64 layout: element kc of lane (g, c) holds row g + 4 kc, the B row of chunk kc
+        if (sizeof(T) == 8 || !(d.f64solve && a.dinv_hi)) {
 #pragma unroll
           for (int kc = 0; kc < 4; ++kc) x = mfma(di[kc], acc[kc], x);
-        } else {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) tbuf[drow<T>(g, r) * 16 + c] = acc[r];
-          __builtin_amdgcn_wave_barrier();
-          if (!(d.f64solve && a.dinv_hi)) {
-#pragma unroll
-            for (int kc = 0; kc < 4; ++kc) x = mfma(di[kc], tbuf[(4 * kc + g) * 16 + c], x);
-          }
         }
         if constexpr (sizeof(T) == 4) {
           if (d.f64solve && a.dinv_hi) {
@@ -680,7 +675,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
             d4 xh = {0, 0, 0, 0};
             const double* Dh = a.dinv_hi + (long long)s * 256;
 #pragma unroll
-            for (int kc = 0; kc < 4; ++kc) xh = mfma(ld(Dh + kc * 64 + lane), (double)tbuf[(4 * kc + g) * 16 + c], xh);
+            for (int kc = 0; kc < 4; ++kc) xh = mfma(ld(Dh + kc * 64 + lane), (double)acc[kc], xh);
 #pragma unroll
             for (int r = 0; r < 4; ++r) x[r] = (T)xh[r];
           }
@@ -1365,7 +1360,7 @@ static inline int grid_for(long long total, int block) {
 template <typename T>
 size_t march_lds_bytes(const MarchArgs<T>& a) {
   const size_t zrows = (size_t)a.nslots * a.k + 1;   // accumulators and the sink row
-  return ((size_t)a.ring * 256 + (size_t)(NW + 1) * 256 + (sizeof(T) == 4 ? 256 : 0) + zrows * 16) * sizeof(T);
+  return ((size_t)a.ring * 256 + (size_t)(NW + 1) * 256 + zrows * 16) * sizeof(T);
 }
 
 template <typename T>
