@@ -1227,6 +1227,67 @@ __global__ void prolong_kernel(const T* __restrict__ ec, T* __restrict__ uf, int
   }
 }
 
+// The 2D transfers in colour-split storage with 32-bit indices inside a time
+// row (the generic kernels above divide 64-bit flat indices per point).
+// Second-colour prolongation: the second colour's storage block of a time row
+// lists the fine points with x + y odd row by row; fine rows 2P and 2P + 1
+// hold nc and nc + 1 of them, nf together, so entry i = P nf + r is
+// (x, y) = (2r + 1, 2P) for r < nc and (2(r - nc), 2P + 1) otherwise.  The
+// first kind lies between coarse rows P - 1 and P in coarse column r, the
+// second between coarse columns r - nc - 1 and r - nc in coarse row P; each
+// takes the mean of the (existing) two, as the generic kernel does.
+template <typename T>
+__global__ __launch_bounds__(256) void prolong2_black_split_kernel(const T* __restrict__ ec, T* __restrict__ uf,
+                                                                   int nf, int nc, long long M) {
+  const long long Nf = (long long)nf * nf, Nc = (long long)nc * nc;
+  const int n0f = (int)((Nf + 1) / 2), n0c = (int)((Nc + 1) / 2);
+  const int Nq = (int)(Nf / 2);
+  auto sc = [&](int qc) { return (qc & 1) ? n0c + (qc >> 1) : (qc >> 1); };
+  for (long long m = blockIdx.y; m < M; m += gridDim.y) {
+    const T* e = ec + m * Nc;
+    T* u = uf + m * Nf + n0f;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < Nq; i += gridDim.x * 256) {
+      const int P = i / nf, r = i - P * nf;
+      T lo = (T)0, hi = (T)0;
+      if (r < nc) {
+        if (P >= 1) lo = e[sc((P - 1) * nc + r)];
+        if (P < nc) hi = e[sc(P * nc + r)];
+      } else {
+        const int x = r - nc;
+        if (x >= 1) lo = e[sc(P * nc + x - 1)];
+        if (x < nc) hi = e[sc(P * nc + x)];
+      }
+      u[i] += (T)0.5 * (lo + hi);
+    }
+  }
+}
+
+// Restriction to coarse storage index Q (colour-split on both grids): the
+// coarse point (I, J) is the fine point (2I + 1, 2J + 1), of the first colour
+// as its corners; the edge midpoints have the second.
+template <typename T>
+__global__ __launch_bounds__(256) void restrict2_split_kernel(const T* __restrict__ rf, T* __restrict__ fc, int nf,
+                                                              int nc, long long M, int red_only) {
+  const long long Nf = (long long)nf * nf, Nc = (long long)nc * nc;
+  const int n0f = (int)((Nf + 1) / 2), n0c = (int)((Nc + 1) / 2);
+  for (long long m = blockIdx.y; m < M; m += gridDim.y) {
+    const T* r = rf + m * Nf;
+    for (int Q = blockIdx.x * 256 + threadIdx.x; Q < (int)Nc; Q += gridDim.x * 256) {
+      const int Qn = Q < n0c ? 2 * Q : 2 * (Q - n0c) + 1;
+      const int J = Qn / nc, I = Qn - J * nc;
+      const int c0 = (2 * J + 1) * nf + 2 * I + 1;   // natural fine index of the centre (odd + odd: even)
+      // first-colour fine points (even natural index q) sit at q / 2, the
+      // second colour's (odd q) at n0f + q / 2
+      auto f1 = [&](int q) { return r[q >> 1]; };
+      auto f2 = [&](int q) { return r[n0f + (q >> 1)]; };
+      const T edges = red_only ? (T)0 : (T)2 * (f2(c0 - nf) + f2(c0 + nf) + f2(c0 - 1) + f2(c0 + 1));
+      fc[m * Nc + Q] = (T)(1.0 / 16.0) *
+                       ((f1(c0 - nf - 1) + f1(c0 - nf + 1) + f1(c0 + nf - 1) + f1(c0 + nf + 1)) + edges +
+                        (T)4 * f1(c0));
+    }
+  }
+}
+
 // b = f + a_{.,1} g in colour-split storage (2D): b[m][s] from the natural
 // f[m][q(s)], g[q(s)] (g may be null).
 __global__ void rhs0_split_kernel(const double* __restrict__ f, const double* __restrict__ gq,
@@ -1422,6 +1483,11 @@ hipError_t launch_restrict(const T* rf, T* fc, int dim, int nf, int M, bool red_
   int nc = (nf - 1) / 2;
   const long long Nc = dim == 1 ? nc : (long long)nc * nc;
   if (Nc <= 0 || M <= 0) return hipSuccess;
+  if (dim == 2 && split && (long long)nf * nf < (1ll << 31)) {
+    hipLaunchKernelGGL(restrict2_split_kernel<T>, row_grid(Nc, M), dim3(256), 0, s, rf, fc, nf, nc, (long long)M,
+                       red_only ? 1 : 0);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(restrict_kernel<T>, row_grid(Nc, M), dim3(256), 0, s, rf, fc, dim, nf, nc, (long long)M,
                      red_only ? 1 : 0, split && dim == 2 ? 1 : 0);
   return hipGetLastError();
@@ -1433,6 +1499,11 @@ hipError_t launch_prolong(const T* ec, T* uf, int dim, int nf, int M, bool black
   const long long Nf = dim == 1 ? nf : (long long)nf * nf;
   const long long Nq = black_only ? (Nf - (dim == 1 ? 0 : 1) + 1) / 2 : Nf;
   if (Nq <= 0 || M <= 0) return hipSuccess;
+  if (dim == 2 && split && black_only && Nf < (1ll << 31)) {
+    hipLaunchKernelGGL(prolong2_black_split_kernel<T>, row_grid(Nq, M), dim3(256), 0, s, ec, uf, nf, nc,
+                       (long long)M);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(prolong_kernel<T>, row_grid(Nq, M), dim3(256), 0, s, ec, uf, dim, nf, nc, (long long)M,
                      black_only ? 1 : 0, split && dim == 2 ? 1 : 0);
   return hipGetLastError();
