@@ -49,11 +49,11 @@ PEAK_HBM_GBS = 8000.0
 # batch solve (every kernel of the staged instances, the second solve of the
 # run); large2d: the average float64 SMOOTH march; large1d: the timed
 # pipelined launch (profiles/ holds the runs).
-_SHA = "38d512b9d5383f3f30bffbb781674f0ba28f6801c30da916e92de8ba0dda251a"
+_SHA = "ebc465df268844301f68252a23f4337d565451397165917bd2f97b1947d4f8d9"
 TRAFFIC = {
-    "batched_fp64": (_SHA, 1.4168e12 + 5.957e11),
-    "large2d_fp64": (_SHA, 2.969e8 + 1.252e8),
-    "large1d_fp64": (_SHA, 4.865e10 + 8.865e9),
+    "batched_fp64": (_SHA, 1.4452e12 + 5.882e11),
+    "large2d_fp64": (_SHA, 3.140e8 + 1.273e8),
+    "large1d_fp64": (_SHA, 4.972e10 + 8.865e9),
 }
 
 
