@@ -491,10 +491,6 @@ def main():
                 head = ("learned2d_fp64", {"workload": "learned2d: 2D n=255 M=1024, two held-out instances of the "
                                                        "warm-start family (seeds [100001, i])",
                                            "N": probs[0].N, "M": probs[0].M, "instances": 2, "tol": args.tol}, cpu)
-            base = f5.get("fp64", {}).get("value")
-            for k in ("mixed", "fp64_learned", "mixed_learned"):
-                if base and k in f5:
-                    forms[f"learned2d_{k}"]["vs_fp64"] = f5[k]["value"] / base
     if args.workload == "large1d" or (args.workload == "all" and not args.value_only):
         probs = [W.config("large1d", a) for a in (0.3, 0.5, 0.7)]
         f2 = single_forms("large1d", probs, args, torch, mg, dev)
@@ -518,6 +514,12 @@ def main():
         f1 = single_forms("small1d", [p], args, torch, mg, dev)
         forms.update({f"small1d_{k}": v for k, v in f1.items()})
         head = ("small1d_fp64", {"workload": "small1d: 1D n=63 M=128 alpha=0.5 r=3 k=8", "tol": args.tol}, None)
+    # each form's rate against the float64 form of its workload
+    for name, v in forms.items():
+        wl, _, form = name.partition("_")
+        base = forms.get(f"{wl}_fp64", {}).get("value")
+        if form != "fp64" and base and v.get("value"):
+            v["vs_fp64"] = v["value"] / base
     key, cfg, cpu = head
     hv = forms[key]
     out = {
