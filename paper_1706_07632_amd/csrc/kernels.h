@@ -63,6 +63,13 @@ struct MarchArgs {
   // neither Out nor Out32 stores no defect, only its norms (stopping tests).
   float* Out32;
   double* norm_out;
+  // SMOOTH launched on its own: when set, the change of every solved entry
+  // (new value minus the iterate it replaces) goes to Dout at the same
+  // index.  After a second-colour half-sweep the defect is zero on that
+  // colour and, at a first-colour point, 1/h^2 times the sum of those
+  // changes at its neighbours (each first-colour line was solved exactly
+  // against the old values), which the zebra transfers below use.
+  T* Dout;
 };
 
 // One stage of the time-pipelined kernel.  Stage kinds:
@@ -144,6 +151,17 @@ template <typename T> hipError_t set_march_lds_limit(size_t bytes);
 // zero after its line solves and its entries are not read.
 template <typename T> hipError_t launch_restrict(const T* rf, T* fc, int dim, int nf, int M, bool red_only,
                                                  bool split, hipStream_t s);
+// 2D colour-split grids, right after a second-colour half-sweep that wrote
+// the changes d of its entries (MarchArgs::Dout): the first-colour defect is
+// r(p) = inv_h2 * (sum of d over the neighbours of p) and the second
+// colour's is zero.  launch_restrict_zebra forms the full-weighting
+// restriction of that defect from d (same result as launch_restrict with
+// red_only on the defect, up to rounding); launch_zebra_norm writes the
+// partial maxima of |r| over the first colour to part[0 .. nparts) (NaN if
+// any is NaN), to be reduced by launch_maxabs_parts.
+template <typename T> hipError_t launch_restrict_zebra(const T* d, T* fc, int nf, int M, T inv_h2, hipStream_t s);
+hipError_t launch_zebra_norm(const double* d, int nf, int M, double inv_h2, double* part, int nparts,
+                             hipStream_t s);
 // black_only: only the second-colour fine points are corrected.  A
 // first-colour half-sweep that follows reads the iterate only there (its own
 // lines are solved afresh), so the other corrections would be overwritten

@@ -430,6 +430,25 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
       for (int kc = 0; kc < 4; ++kc) di[kc] = ld(Di + kc * 64 + lane);
     }
   };
+  // wave 0, SMOOTH with Dout: the iterate entries the solve of leaf li
+  // replaces, in the row order of its result
+  T uold[4] = {0, 0, 0, 0};
+  auto prefetch_uold = [&](int li) {
+    if constexpr (!PIPE && MODE == MODE_SMOOTH) {
+      if (a.Dout) {
+        const LeafDesc d = ld_struct<LeafDesc, true>(a.leaves + li);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int row = drow<T>(g, r);
+          if constexpr (sizeof(T) == 4) {
+            if (d.f64solve && a.dinv_hi) row = drow<double>(g, r);
+          }
+          const bool ok = colok && row < d.sz;
+          uold[r] = ok ? ld(a.U + (long long)(d.lo + row) * a.ld + qs) : (T)0;
+        }
+      }
+    }
+  };
 
   // Partial right-hand side of leaf li from this wave's share, to pw.  The
   // IO wave writes its stencil part in phase 1 (stencil) and adds its
@@ -632,7 +651,10 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
 
   // ---- wave 0 and the workers ---------------------------------------------------
   prefetch_tiles(0);
-  if (wave == 0) prefetch_dinv(0);
+  if (wave == 0) {
+    prefetch_dinv(0);
+    prefetch_uold(0);
+  }
   __syncthreads();
   if (*sh_abort) return;
   partial(0, part + wave * 256, true, false);
@@ -690,6 +712,9 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
           const bool ok = colok && row < d.sz;
           cur[row * 16 + c] = ok ? x[r] : (T)0;
           if (ok) gst<PIPE>(a.U + (long long)(d.lo + row) * a.ld + qs, x[r]);
+          if constexpr (!PIPE && MODE == MODE_SMOOTH) {
+            if (ok && a.Dout) a.Dout[(long long)(d.lo + row) * a.ld + qs] = x[r] - uold[r];
+          }
         }
       } else {
 #pragma unroll
@@ -726,7 +751,10 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
     // ---- phase 2 --------------------------------------------------------------
     vm_drain();
     if (s + 1 < nleaf) {
-      if (wave == 0) prefetch_dinv(s + 1);
+      if (wave == 0) {
+        prefetch_dinv(s + 1);
+        prefetch_uold(s + 1);
+      }
       prefetch_zu(s);
       partial(s + 1, part + wave * 256, true, false);
     }
@@ -1288,6 +1316,75 @@ __global__ __launch_bounds__(256) void restrict2_split_kernel(const T* __restric
   }
 }
 
+// Zebra transfers (2D, colour-split storage, right after a second-colour
+// half-sweep that wrote the changes d of its entries): the first-colour
+// defect at natural index q is inv_h2 times the sum of d over its in-grid
+// neighbours, which all have the second colour (stored at n0f + q' / 2).
+template <typename T>
+__device__ __forceinline__ T zebra_defect(const T* __restrict__ d, int q, int nf, int n0f, T inv_h2) {
+  const int y = q / nf, x = q - y * nf;
+  T s = (T)0;
+  if (y >= 1) s += d[n0f + ((q - nf) >> 1)];
+  if (y + 1 < nf) s += d[n0f + ((q + nf) >> 1)];
+  if (x >= 1) s += d[n0f + ((q - 1) >> 1)];
+  if (x + 1 < nf) s += d[n0f + ((q + 1) >> 1)];
+  return inv_h2 * s;
+}
+
+// Full weighting of that defect to coarse storage index Q (the second
+// colour's defect is zero, so only the centre and the corners count, as in
+// the red_only restriction).
+template <typename T>
+__global__ __launch_bounds__(256) void restrict2_zebra_kernel(const T* __restrict__ df, T* __restrict__ fc, int nf,
+                                                              int nc, long long M, T inv_h2) {
+  const long long Nf = (long long)nf * nf, Nc = (long long)nc * nc;
+  const int n0f = (int)((Nf + 1) / 2), n0c = (int)((Nc + 1) / 2);
+  for (long long m = blockIdx.y; m < M; m += gridDim.y) {
+    const T* d = df + m * Nf;
+    for (int Q = blockIdx.x * 256 + threadIdx.x; Q < (int)Nc; Q += gridDim.x * 256) {
+      const int Qn = Q < n0c ? 2 * Q : 2 * (Q - n0c) + 1;
+      const int J = Qn / nc, I = Qn - J * nc;
+      const int c0 = (2 * J + 1) * nf + 2 * I + 1;
+      auto r = [&](int q) { return zebra_defect(d, q, nf, n0f, inv_h2); };
+      fc[m * Nc + Q] = (T)(1.0 / 16.0) *
+                       ((r(c0 - nf - 1) + r(c0 - nf + 1) + r(c0 + nf - 1) + r(c0 + nf + 1)) + (T)4 * r(c0));
+    }
+  }
+}
+
+// max |defect| over the first colour: block b takes the time rows b, b +
+// gridDim.x, ... and writes its maximum to part[b] (0 without rows; NaN
+// propagates)
+__global__ __launch_bounds__(256) void zebra_norm_kernel(const double* __restrict__ df, int nf, long long M,
+                                                         double inv_h2, double* __restrict__ part) {
+  const long long Nf = (long long)nf * nf;
+  const int n0f = (int)((Nf + 1) / 2);
+  double mx = 0.0;
+  bool bad = false;
+  for (long long m = blockIdx.x; m < M; m += gridDim.x) {
+    const double* d = df + m * Nf;
+    for (int s = threadIdx.x; s < n0f; s += 256) {
+      const double v = zebra_defect(d, 2 * s, nf, n0f, inv_h2);
+      if (!(v == v)) bad = true;
+      else mx = fmax(mx, fabs(v));
+    }
+  }
+  double w = bad ? __builtin_nan("") : mx;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_xor(w, off, 64);
+    w = (o != o || w != w) ? __builtin_nan("") : fmax(o, w);
+  }
+  __shared__ double sh[4];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = w;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = sh[0];
+    for (int i = 1; i < 4; ++i) t = (sh[i] != sh[i] || t != t) ? __builtin_nan("") : fmax(t, sh[i]);
+    part[blockIdx.x] = t;
+  }
+}
+
 // b = f + a_{.,1} g in colour-split storage (2D): b[m][s] from the natural
 // f[m][q(s)], g[q(s)] (g may be null).
 __global__ void rhs0_split_kernel(const double* __restrict__ f, const double* __restrict__ gq,
@@ -1494,6 +1591,25 @@ hipError_t launch_restrict(const T* rf, T* fc, int dim, int nf, int M, bool red_
 }
 
 template <typename T>
+hipError_t launch_restrict_zebra(const T* d, T* fc, int nf, int M, T inv_h2, hipStream_t s) {
+  const int nc = (nf - 1) / 2;
+  const long long Nc = (long long)nc * nc;
+  if (Nc <= 0 || M <= 0) return hipSuccess;
+  if ((long long)nf * nf >= (1ll << 31)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(restrict2_zebra_kernel<T>, row_grid(Nc, M), dim3(256), 0, s, d, fc, nf, nc, (long long)M,
+                     inv_h2);
+  return hipGetLastError();
+}
+
+hipError_t launch_zebra_norm(const double* d, int nf, int M, double inv_h2, double* part, int nparts, hipStream_t s) {
+  if (M <= 0 || nparts < 1) return hipErrorInvalidValue;
+  if ((long long)nf * nf >= (1ll << 31)) return hipErrorInvalidValue;
+  // one block per partial maximum (blocks without a row write 0)
+  hipLaunchKernelGGL(zebra_norm_kernel, dim3(nparts), dim3(256), 0, s, d, nf, (long long)M, inv_h2, part);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_prolong(const T* ec, T* uf, int dim, int nf, int M, bool black_only, bool split, hipStream_t s) {
   int nc = (nf - 1) / 2;
   const long long Nf = dim == 1 ? nf : (long long)nf * nf;
@@ -1584,6 +1700,8 @@ template hipError_t set_march_lds_limit<double>(size_t);
 template hipError_t set_march_lds_limit<float>(size_t);
 template hipError_t launch_restrict<double>(const double*, double*, int, int, int, bool, bool, hipStream_t);
 template hipError_t launch_restrict<float>(const float*, float*, int, int, int, bool, bool, hipStream_t);
+template hipError_t launch_restrict_zebra<double>(const double*, double*, int, int, double, hipStream_t);
+template hipError_t launch_restrict_zebra<float>(const float*, float*, int, int, float, hipStream_t);
 template hipError_t launch_prolong<double>(const double*, double*, int, int, int, bool, bool, hipStream_t);
 template hipError_t launch_prolong<float>(const float*, float*, int, int, int, bool, bool, hipStream_t);
 template hipError_t launch_fill<double>(double*, long long, double, hipStream_t);

@@ -362,8 +362,10 @@ TransferFusion transfer_fusion(const HostPlan& hp) {
 // i + j even in 2D), which are the flat indices q with q % 2 == par0.
 // Ec (1D, colour 0 only): coarse correction whose interpolation the
 // half-sweep applies to the neighbours it reads (see MarchArgs).
+// Dout: see MarchArgs (the changes of the solved entries).
 template <typename T>
-int smooth(mgwr_plan* pl, DevOps<T>& ops, int l, int colour, T* F, T* U, const T* Ec = nullptr) {
+int smooth(mgwr_plan* pl, DevOps<T>& ops, int l, int colour, T* F, T* U, const T* Ec = nullptr,
+           T* Dout = nullptr) {
   const HostPlan& hp = pl->hp;
   const Level& lv = hp.levels[l];
   int par0 = hp.p.dim == 1 ? 1 : 0;
@@ -375,8 +377,9 @@ int smooth(mgwr_plan* pl, DevOps<T>& ops, int l, int colour, T* F, T* U, const T
   if (a.split) { a.cstride = 1; a.coff = par ? (int)a.n0 : 0; }   // the colour's contiguous block
   a.dim = hp.p.dim; a.n = lv.n; a.inv_h2 = (T)(1.0 / (lv.h * lv.h));
   if (Ec) { a.Ec = Ec; a.nc = hp.levels[l + 1].n; }
+  a.Dout = Dout;
   Timed tm(pl, sizeof(T) == 8 ? MGWR_K_SMOOTH64 : MGWR_K_SMOOTH32, 2.0 * hp.stored * ncols,
-           3.0 * hp.p.M * ncols * sizeof(T));
+           (Dout ? 5.0 : 3.0) * hp.p.M * ncols * sizeof(T));
   HIP_TRY(launch_march<T>(MODE_SMOOTH, a, pl->stream));
   return MGWR_OK;
 }
@@ -445,15 +448,49 @@ int defect_norm(mgwr_plan* pl, const double* F, double* U, double* norms, double
   return read_scalar(pl, host);
 }
 
+// The same norm right after a cycle whose last half-sweep wrote its changes
+// to d (zebra_stopping_test): the defect is zero on the second colour and a
+// stencil of d on the first.
+int zebra_norm(mgwr_plan* pl, const double* d, double* norms, double* host) {
+  const HostPlan& hp = pl->hp;
+  const Level& lv = hp.levels[0];
+  const int nparts = (int)std::min<long long>(256, (long long)mgwr_plan::kMaxPipeCycles * ((lv.N + 15) / 16));
+  {
+    Timed tm(pl, MGWR_K_DEFECT64, 0.0, 2.5 * hp.p.M * lv.N * sizeof(double));
+    HIP_TRY(launch_zebra_norm(d, lv.n, hp.p.M, 1.0 / (lv.h * lv.h), norms, nparts, pl->stream));
+  }
+  HIP_TRY(launch_maxabs_parts(norms, nparts, pl->scal, pl->stream));
+  return read_scalar(pl, host);
+}
+
 template <typename T>
 int coarse_cycle(mgwr_plan* pl, int l);
+
+// Zebra defects (2D, colour-split storage, at least one pre-smoothing sweep):
+// the defect that feeds the restriction is formed from the changes the last
+// second-colour half-sweep made (see MarchArgs::Dout) instead of by a defect
+// march, which saves the H-matrix product of the first colour.  The result
+// equals the defect b - A u up to the rounding of the line solves.
+bool zebra_defects(const mgwr_plan* pl) {
+  const HostPlan& hp = pl->hp;
+  return hp.p.dim == 2 && pl->split && hp.p.nu1 >= 1 && (long long)hp.levels[0].n * hp.levels[0].n < (1ll << 31);
+}
+// ... and the stopping test's norm from the last post-smoothing sweep's
+// changes on level 0 (the second colour's defect is zero after it).
+bool zebra_stopping_test(const mgwr_plan* pl) {
+  const HostPlan& hp = pl->hp;
+  return hp.p.dim == 2 && pl->split && hp.p.nu2 >= 1 && hp.levels.size() >= 2 &&
+         (long long)hp.levels[0].n * hp.levels[0].n < (1ll << 31);
+}
 
 // One cycle of Algorithm 2 on level l: ops.F[l] is the right-hand side,
 // ops.U[l] the iterate (level 0 arrays are supplied through F0/U0).  From
 // level coarse_l on, where a half-sweep has too few chains to fill the GPU,
 // the whole remaining cycle is one pipelined launch.
+// dlast: when set, the last post-smoothing half-sweep writes its changes
+// there (for a zebra stopping test on level 0).
 template <typename T>
-int cycle(mgwr_plan* pl, DevOps<T>& ops, int l) {
+int cycle(mgwr_plan* pl, DevOps<T>& ops, int l, T* dlast = nullptr) {
   const HostPlan& hp = pl->hp;
   const int L = (int)hp.levels.size();
   const int M = hp.p.M;
@@ -466,13 +503,22 @@ int cycle(mgwr_plan* pl, DevOps<T>& ops, int l) {
     if ((rc = smooth<T>(pl, ops, l, 1, F, U))) return rc;
     return MGWR_OK;
   }
+  const TransferFusion fz = transfer_fusion(hp);
+  const bool zebra = !fz.restrict_in_defect && zebra_defects(pl);
   for (int s = 0; s < hp.p.nu1; ++s) {
     if ((rc = smooth<T>(pl, ops, l, 0, F, U))) return rc;
-    if ((rc = smooth<T>(pl, ops, l, 1, F, U))) return rc;
+    if ((rc = smooth<T>(pl, ops, l, 1, F, U, nullptr, (zebra && s == hp.p.nu1 - 1) ? ops.R[l] : nullptr)))
+      return rc;
   }
   const bool red_only = hp.p.nu1 >= 1;   // the pre-smoothing ended with a second-colour half-sweep
-  const TransferFusion fz = transfer_fusion(hp);
-  if (fz.restrict_in_defect) {
+  if (zebra) {
+    {
+      Timed tm(pl, MGWR_K_RESTRICT, 0.0, (double)M * (0.5 * hp.levels[l].N + 2.0 * hp.levels[l + 1].N) * sizeof(T));
+      const T inv_h2 = (T)(1.0 / (hp.levels[l].h * hp.levels[l].h));
+      HIP_TRY(launch_restrict_zebra<T>(ops.R[l], ops.F[l + 1], hp.levels[l].n, M, inv_h2, pl->stream));
+    }
+    HIP_TRY(launch_fill<T>(ops.U[l + 1], (long long)M * hp.levels[l + 1].N, (T)0, pl->stream));
+  } else if (fz.restrict_in_defect) {
     if ((rc = defect<T>(pl, ops, l, F, U, nullptr, true, ops.F[l + 1], ops.U[l + 1]))) return rc;
   } else {
     if ((rc = defect<T>(pl, ops, l, F, U, ops.R[l], red_only))) return rc;
@@ -494,7 +540,7 @@ int cycle(mgwr_plan* pl, DevOps<T>& ops, int l) {
   for (int s = 0; s < hp.p.nu2; ++s) {
     const T* Ec = (fz.prolong_in_smooth && s == 0) ? ops.U[l + 1] : nullptr;
     if ((rc = smooth<T>(pl, ops, l, 0, F, U, Ec))) return rc;
-    if ((rc = smooth<T>(pl, ops, l, 1, F, U))) return rc;
+    if ((rc = smooth<T>(pl, ops, l, 1, F, U, nullptr, s == hp.p.nu2 - 1 ? dlast : nullptr))) return rc;
   }
   return MGWR_OK;
 }
@@ -1693,12 +1739,19 @@ int mgwr_solve(mgwr_plan* pl, const double* f, const double* g, double tol, doub
     int skip_to = 0;
     if (!(flags & MGWR_GUESS_IN_U)) skip_to = pl->khint_staged;
     else if (s.used_warm_start) skip_to = pl->khint_staged_warm;
+    const bool zt = zebra_stopping_test(pl);
     while (s.cycles < hp.p.max_cycles) {
-      if ((rc = cycle<double>(pl, pl->d64, 0))) return rc;
+      // whether this cycle is followed by a stopping test
+      const bool tested = (s.used_warm_start && s.cycles == 0) || s.cycles + 1 >= skip_to;
+      if ((rc = cycle<double>(pl, pl->d64, 0, zt && tested ? pl->d64.R[0] : nullptr))) return rc;
       s.cycles++;
       const bool judge = s.used_warm_start && s.cycles == 1;
       if (!judge && s.cycles < skip_to) continue;
-      if ((rc = defect_norm(pl, b, u, pl->norms, &s.res))) return rc;
+      if (zt) {
+        if ((rc = zebra_norm(pl, pl->d64.R[0], pl->norms, &s.res))) return rc;
+      } else if ((rc = defect_norm(pl, b, u, pl->norms, &s.res))) {
+        return rc;
+      }
       if (s.cycles <= 64) s.history[s.cycles - 1] = s.res;
       if (s.cycles == 1 && fall_back_to_zero(pl, b, u, s, 1, tol, &rc)) {
         if (rc) return rc;
@@ -2156,11 +2209,21 @@ int solve_staged_side_by_side(mgwr_batch* bt, const std::vector<int>& staged, co
     pl->timing = timed[j] != 0;
     if (stats) stats[staged[j]] = sts[j];
     if (bt->timing) {
-      // one cycle's stages plus one float64 defect of the full system
+      // one cycle's stages plus one float64 defect of the full system; with
+      // zebra defects the defect marches above the pipelined coarse levels
+      // and the stopping-test march are not run
       std::vector<Stage> one;
       append_cycle_stages(pl, 0, -1, one, pl->mixed);
-      double cf = 2.0 * pl->hp.stored * pl->hp.levels[0].N, cb = 3.0 * pl->hp.p.M * pl->hp.levels[0].N * 8.0;
-      for (const Stage& x : one) stage_work(pl, x, cf, cb);
+      const bool zd = zebra_defects(pl), zt = !pl->mixed && zebra_stopping_test(pl);
+      const int ncoarse = pl->coarse_l > 0 ? pl->hp.levels[pl->coarse_l].n : 0;
+      double cf = zt ? 0.0 : 2.0 * pl->hp.stored * pl->hp.levels[0].N;
+      double cb = (zt ? 2.5 : 3.0) * pl->hp.p.M * pl->hp.levels[0].N * 8.0;
+      for (const Stage& x : one) {
+        const bool resid = x.kind == STG_RESID || x.kind == STG_RESID32;
+        const int nlev = x.kind == STG_RESID32 ? x.mf.n : x.m.n;
+        if (zd && resid && nlev > ncoarse) continue;
+        stage_work(pl, x, cf, cb);
+      }
       flops += cf * sts[j].cycles;
       bytes += cb * sts[j].cycles;
     }

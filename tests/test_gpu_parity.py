@@ -484,10 +484,13 @@ def test_stats_report_setup_and_solve_times(dev):
 @pytest.mark.parametrize("schedule,n", [("staged", 31), ("staged", 63), ("pipelined", 31)])
 @pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_bf16"])
 def test_colour_split_storage_is_bit_identical_to_natural(dev, schedule, n, precision):
-    """Colour-split storage moves points, not operations: every point's
-    arithmetic is the same in either storage, so the solutions (from zero
-    and from a given iterate, with an initial value g) agree bit for bit, and
-    the float64 one matches the oracle."""
+    """Colour-split storage moves points, not operations: in the pipelined
+    schedule every point's arithmetic is the same in either storage, so the
+    solutions (from zero and from a given iterate, with an initial value g)
+    agree bit for bit.  The staged schedule in split storage forms its
+    defects from the last half-sweep's changes (zebra defects), which equal
+    the defect march's up to rounding: there the two solutions agree to the
+    solve tolerance.  The float64 one matches the oracle either way."""
     rng = np.random.default_rng(77 + n)
     M, N = 80, n * n
     t = W.graded_mesh(M, 1.0, 3.0)
@@ -504,16 +507,26 @@ def test_colour_split_storage_is_bit_identical_to_natural(dev, schedule, n, prec
         u, st = plan.solve(f, gd, tol=tol)
         ug = _cuda(u0, dev)
         _, st2 = plan.solve(f, gd, tol=tol, u=ug, guess=True)
-        out[layout] = (u.cpu().numpy(), ug.cpu().numpy(), st["cycles"], st2["cycles"])
+        out[layout] = (u.cpu().numpy(), ug.cpu().numpy(), st["cycles"], st2["cycles"], st["res"])
     a, b = out["natural"], out["split"]
-    assert a[2:] == b[2:]
-    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    if schedule == "pipelined":
+        assert a[2:4] == b[2:4]
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    else:
+        for x, y in ((a[0], b[0]), (a[1], b[1])):
+            assert np.max(np.abs(x - y)) / np.max(np.abs(y)) < 100 * tol
+        assert abs(a[2] - b[2]) <= 1 and abs(a[3] - b[3]) <= 1
     Rt = oracle.hmatrix_dense(p.t, p.alpha, p.k, p.leaf)
     B = oracle.rhs(p.f, p.t, p.alpha, g)
     ref = oracle.timestep_solve(Rt, B, p.dim, p.n, p.length)
     err = np.max(np.abs(b[0] - ref)) / np.max(np.abs(ref))
     res = np.max(np.abs(oracle.residual(Rt, b[1], B, p.dim, p.n, p.length))) / np.max(np.abs(B))
     assert err < (1e-10 if precision == "fp64" else 1e-8) and res <= 1.5 * tol, (err, res)
+    if precision == "fp64":
+        # the reported residual (a zebra stopping test in staged split
+        # storage) is the oracle's residual of the returned iterate
+        true_res = np.max(np.abs(oracle.residual(Rt, b[0], B, p.dim, p.n, p.length)))
+        assert abs(b[4] - true_res) <= 0.1 * true_res + 1e-12 * np.max(np.abs(B)), (b[4], true_res)
 
 
 def test_autotuner_times_both_storages(dev):
