@@ -128,7 +128,8 @@ typedef struct {
   int refinements;   /* outer float64 residual evaluations in mixed precision */
   double res0;       /* ||b - A u_initial||_inf */
   double bnorm;      /* ||b||_inf, b = f + a_{.,1} g */
-  double res;        /* final ||b - A u||_inf (float64) */
+  double res;        /* final ||b - A u||_inf (float64; a staged 2D solve in split storage takes it
+                        from the last half-sweep's changes, see mgwr_plan_set_layout) */
   double avg_factor; /* (res/res0)^(1/cycles) */
   double history[64]; /* ||b - A u||_inf after each of the first 64 outer steps (cycles or
                          refinements); 0 where a pipelined launch with a learned cycle count
@@ -328,8 +329,15 @@ int mgwr_plan_set_staging(mgwr_plan* plan, int prefetch, int coarse_level);
 int mgwr_plan_tuned(const mgwr_plan* plan, int* schedule, int* prefetch, int* coarse_level);
 
 /* Storage of the space-time arrays of a 2D plan inside its solves (host
- * only; the iterates and the cycle are the same, bit for bit).  The caller's
- * f, g, u are always in the natural order of the array layout above.
+ * only).  The caller's f, g, u are always in the natural order of the array
+ * layout above.  The pipelined schedule computes the same iterates in either
+ * storage, bit for bit.  The staged schedule in SPLIT storage forms the
+ * defects of its cycles (and the norm of its float64 stopping test) from the
+ * changes of the last second-colour half-sweep: after it the defect is zero
+ * on that colour and, at a first-colour point, 1/h^2 times the sum of those
+ * changes over its neighbours, which saves the H-matrix product of a defect
+ * (Algorithm 3) per level and cycle; its iterates equal NATURAL's up to
+ * rounding.
  * MGWR_LAYOUT_SPLIT: every time row holds the first colour's points (the
  * even flat indices q, in order) and then the second colour's (the odd
  * ones), at every level, so a half-sweep of the red-black relaxation reads
