@@ -434,7 +434,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
   // replaces, in the row order of its result
   T uold[4] = {0, 0, 0, 0};
   auto prefetch_uold = [&](int li) {
-    if constexpr (!PIPE && MODE == MODE_SMOOTH) {
+    if constexpr (MODE == MODE_SMOOTH) {
       if (a.Dout) {
         const LeafDesc d = ld_struct<LeafDesc, true>(a.leaves + li);
 #pragma unroll
@@ -444,7 +444,7 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
             if (d.f64solve && a.dinv_hi) row = drow<double>(g, r);
           }
           const bool ok = colok && row < d.sz;
-          uold[r] = ok ? ld(a.U + (long long)(d.lo + row) * a.ld + qs) : (T)0;
+          uold[r] = ok ? gld<PIPE>(a.U + (long long)(d.lo + row) * a.ld + qs) : (T)0;
         }
       }
     }
@@ -651,12 +651,13 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
 
   // ---- wave 0 and the workers ---------------------------------------------------
   prefetch_tiles(0);
-  if (wave == 0) {
-    prefetch_dinv(0);
-    prefetch_uold(0);
-  }
+  if (wave == 0) prefetch_dinv(0);
   __syncthreads();
   if (*sh_abort) return;
+  // (after the barrier: in the pipelined kernel the IO wave has then waited
+  // for the producer's first leaf, before which these entries may still be
+  // written by an earlier stage)
+  if (wave == 0) prefetch_uold(0);
   partial(0, part + wave * 256, true, false);
   __syncthreads();
   if (*sh_abort) return;
@@ -712,8 +713,8 @@ __device__ __forceinline__ void march_body(const MarchArgs<T>& a, int chunk, con
           const bool ok = colok && row < d.sz;
           cur[row * 16 + c] = ok ? x[r] : (T)0;
           if (ok) gst<PIPE>(a.U + (long long)(d.lo + row) * a.ld + qs, x[r]);
-          if constexpr (!PIPE && MODE == MODE_SMOOTH) {
-            if (ok && a.Dout) a.Dout[(long long)(d.lo + row) * a.ld + qs] = x[r] - uold[r];
+          if constexpr (MODE == MODE_SMOOTH) {
+            if (ok && a.Dout) gst<PIPE>(a.Dout + (long long)(d.lo + row) * a.ld + qs, x[r] - uold[r]);
           }
         }
       } else {
@@ -857,6 +858,10 @@ __device__ __forceinline__ void restrict_stage(const Stage& st, int chunk, const
         off[t] = fx - 1 + (t < 3 ? t : 0);
         wgt[t] = t == 1 ? (T)0.5 : (T)0.25;
         tap[t] = t < 3 && (!red_only || t == 1);
+        if (st.zebra) {   // half the first-colour defect at fx, from the changes at fx -/+ 1
+          wgt[t] = (T)(0.5 * st.zscale);
+          tap[t] = t == 0 || t == 2;
+        }
       } else {
         const int dy = t / 3 - 1, dx = t % 3 - 1;
         off[t] = (fy + dy) * nf + fx + dx;

@@ -53,6 +53,8 @@ namespace {
   } while (0)
 
 constexpr int kNormParts = 1024;
+// Smallest relative tolerance for which solves use zebra defects.
+constexpr double kZebraMinTol = 1e-10;
 
 // Carves the workspace: every array starts on a 256-byte boundary.
 struct Carver {
@@ -148,6 +150,11 @@ struct mgwr_plan {
   int coarse_l = 0;
   unsigned spin_limit = kDefaultSpinLimit;   // polls of a progress wait (mgwr_plan_set_progress_limit)
   std::vector<Stage> coarse_stages[2];
+  bool coarse_zebra[2] = {false, false};   // the zebra setting those stage images were built with
+  // Zebra defects (see zebra_defects) in the current solve: only for
+  // tolerances of at least kZebraMinTol, since they carry the rounding of
+  // the line solves (measured floor about 1e-12 ||b||; 1D n = 127, alpha = 0.7)
+  bool zebra = true;
   int coarse_tasks[2] = {0, 0};
   long long coarse_cnt[2] = {0, 0};
   double coarse_flops[2] = {0.0, 0.0}, coarse_bytes[2] = {0.0, 0.0};
@@ -473,13 +480,14 @@ int coarse_cycle(mgwr_plan* pl, int l);
 // equals the defect b - A u up to the rounding of the line solves.
 bool zebra_defects(const mgwr_plan* pl) {
   const HostPlan& hp = pl->hp;
-  return hp.p.dim == 2 && pl->split && hp.p.nu1 >= 1 && (long long)hp.levels[0].n * hp.levels[0].n < (1ll << 31);
+  return pl->zebra && hp.p.dim == 2 && pl->split && hp.p.nu1 >= 1 &&
+         (long long)hp.levels[0].n * hp.levels[0].n < (1ll << 31);
 }
 // ... and the stopping test's norm from the last post-smoothing sweep's
 // changes on level 0 (the second colour's defect is zero after it).
 bool zebra_stopping_test(const mgwr_plan* pl) {
   const HostPlan& hp = pl->hp;
-  return hp.p.dim == 2 && pl->split && hp.p.nu2 >= 1 && hp.levels.size() >= 2 &&
+  return pl->zebra && hp.p.dim == 2 && pl->split && hp.p.nu2 >= 1 && hp.levels.size() >= 2 &&
          (long long)hp.levels[0].n * hp.levels[0].n < (1ll << 31);
 }
 
@@ -569,7 +577,7 @@ int append_cycle_stages(mgwr_plan* pl, int l, int prev, std::vector<Stage>& out,
     out.push_back(st);
     prev = (int)out.size() - 1;
   };
-  auto smooth_stage = [&](int colour, bool with_ec = false) {
+  auto smooth_stage = [&](int colour, bool with_ec = false, bool dout = false) {
     int par0 = hp.p.dim == 1 ? 1 : 0;
     int par = colour == 0 ? par0 : 1 - par0;
     int ncols = (lv.N - par + 1) / 2;
@@ -582,6 +590,7 @@ int append_cycle_stages(mgwr_plan* pl, int l, int prev, std::vector<Stage>& out,
       if (st.m.split) { st.m.cstride = 1; st.m.coff = par ? (int)st.m.n0 : 0; }
       st.m.dim = hp.p.dim; st.m.n = lv.n; st.m.inv_h2 = 1.0 / (lv.h * lv.h);
       if (with_ec) { st.m.Ec = ops.U[l + 1]; st.m.nc = hp.levels[l + 1].n; }
+      if (dout) st.m.Dout = ops.R[l];
     } else {
       st.mf = base_args<float>(pl, o32, l);
       st.mf.F = o32.F[l]; st.mf.U = o32.U[l]; st.mf.Out = nullptr;
@@ -589,6 +598,7 @@ int append_cycle_stages(mgwr_plan* pl, int l, int prev, std::vector<Stage>& out,
       if (st.mf.split) { st.mf.cstride = 1; st.mf.coff = par ? (int)st.mf.n0 : 0; }
       st.mf.dim = hp.p.dim; st.mf.n = lv.n; st.mf.inv_h2 = (float)(1.0 / (lv.h * lv.h));
       if (with_ec) { st.mf.Ec = o32.U[l + 1]; st.mf.nc = hp.levels[l + 1].n; }
+      if (dout) st.mf.Dout = o32.R[l];
     }
     st.nchunks = (ncols + 15) / 16;
     push(st);
@@ -599,11 +609,27 @@ int append_cycle_stages(mgwr_plan* pl, int l, int prev, std::vector<Stage>& out,
     smooth_stage(1);
     return prev;
   }
-  for (int s2 = 0; s2 < hp.p.nu1; ++s2) { smooth_stage(0); smooth_stage(1); }
+  // 1D zebra restriction: the last pre-smoothing half-sweep (second colour)
+  // writes its changes d, and the restriction of the first-colour defect
+  // (1/h^2 times the sum of d at a point's two neighbours) is formed from
+  // them: no defect stage (see zebra_defects for the 2D staged form)
+  const bool zebra1 = pl->zebra && hp.p.dim == 1 && hp.p.nu1 >= 1;
+  for (int s2 = 0; s2 < hp.p.nu1; ++s2) { smooth_stage(0); smooth_stage(1, false, zebra1 && s2 == hp.p.nu1 - 1); }
   // after a second-colour half-sweep the defect vanishes on that colour: the
   // defect stage covers the first colour and the restriction reads only it
   const bool red_only = hp.p.nu1 >= 1;
-  {
+  if (zebra1) {
+    const Level& lc1 = hp.levels[l + 1];
+    Stage st = base(STG_RESTRICT + kofs);
+    if (!f32) { st.src = ops.R[l]; st.dst = ops.F[l + 1]; st.zero = ops.U[l + 1]; }
+    else { st.src = o32.R[l]; st.dst = o32.F[l + 1]; st.zero = o32.U[l + 1]; }
+    st.dim = 1; st.nf = lv.n; st.nc = lc1.n;
+    st.red_only = 1;
+    st.zebra = 1;
+    st.zscale = 1.0 / (lv.h * lv.h);
+    st.nchunks = (lc1.N + kStencilCols - 1) / kStencilCols;
+    push(st);
+  } else {
     const int par0 = hp.p.dim == 1 ? 1 : 0;
     const int ncols = red_only ? (lv.N - par0 + 1) / 2 : lv.N;
     // colour-split storage: the first colour is the first block (coff 0)
@@ -631,7 +657,7 @@ int append_cycle_stages(mgwr_plan* pl, int l, int prev, std::vector<Stage>& out,
     push(st);
   }
   const Level& lc = hp.levels[l + 1];
-  if (!fz.restrict_in_defect) {
+  if (!fz.restrict_in_defect && !zebra1) {
     Stage st = base(STG_RESTRICT + kofs);
     if (!f32) { st.src = ops.R[l]; st.dst = ops.F[l + 1]; st.zero = ops.U[l + 1]; }
     else { st.src = o32.R[l]; st.dst = o32.F[l + 1]; st.zero = o32.U[l + 1]; }
@@ -799,7 +825,9 @@ template <typename T>
 int coarse_cycle(mgwr_plan* pl, int l) {
   const int w = sizeof(T) == 4 ? 1 : 0;
   std::vector<Stage>& st = pl->coarse_stages[w];
+  if (!st.empty() && pl->coarse_zebra[w] != pl->zebra) st.clear();
   if (st.empty()) {
+    pl->coarse_zebra[w] = pl->zebra;
     append_cycle_stages(pl, l, -1, st, w == 1);
     assign_offsets(st);
     if ((long long)st.size() > stages_per_cycle_bound(pl->hp)) {
@@ -1022,6 +1050,7 @@ namespace {
 int prepare_solve(mgwr_plan* pl, const double* f, const double* g, double tol, double* u, unsigned& flags,
                   mgwr_stats& s, const double*& b, int& status) {
   int rc;
+  pl->zebra = tol >= kZebraMinTol;
   const HostPlan& hp = pl->hp;
   const long long N = hp.levels[0].N;
   const long long MN = (long long)hp.p.M * N;

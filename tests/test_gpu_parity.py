@@ -542,3 +542,45 @@ def test_autotuner_times_both_storages(dev):
     Rt, w, s = _single_mode_reference(p)
     ref = np.outer(w, s)
     assert np.max(np.abs(u.cpu().numpy() - ref)) / np.max(np.abs(ref)) < 1e-9, st
+
+
+@pytest.mark.parametrize("dim,n,M,alpha", [(2, 31, 96, 0.5), (2, 63, 64, 0.3), (1, 127, 256, 0.7), (1, 63, 128, 0.5)])
+def test_zebra_defects_match_defect_marches(dev, dim, n, M, alpha):
+    """Zebra defects (the restriction's defect from the changes of the last
+    second-colour half-sweep; 2D staged in colour-split storage, and the 1D
+    pipelined cycle) against the defect marches of Algorithm 3: the same
+    cycle counts within one, both solutions at the oracle's, and the
+    reported residual (a zebra stopping test in 2D) equal to the oracle's
+    residual of the returned iterate.  Below a tolerance of 1e-10 the
+    library uses the defect marches, which the bit-identity of the two 2D
+    storages at 1e-12 shows."""
+    rng = np.random.default_rng(300 + n)
+    N = n ** dim
+    t = W.graded_mesh(M, 1.0, (2 - alpha) / alpha)
+    p = W.Problem(dim=dim, n=n, M=M, alpha=alpha, r=(2 - alpha) / alpha, k=8, t=t, f=rng.standard_normal((M, N)))
+    f = _cuda(p.f, dev)
+    Rt = oracle.hmatrix_dense(p.t, p.alpha, p.k, p.leaf)
+    B = oracle.rhs(p.f, p.t, p.alpha, None)
+    ref = oracle.timestep_solve(Rt, B, p.dim, p.n, p.length)
+    bn = np.max(np.abs(B))
+    # zebra form, and the same cycle with defect marches
+    if dim == 2:
+        forms = {"zebra": dict(schedule="staged", layout="split"), "march": dict(schedule="staged", layout="natural")}
+    else:
+        forms = {"zebra": dict(schedule="pipelined"), "march": dict(schedule="staged")}
+    out = {}
+    for name, kw in forms.items():
+        print("case", dim, n, M, alpha, name, flush=True)
+        plan = _plan(p, dev, schedule=kw["schedule"])
+        if "layout" in kw:
+            plan.set_layout(kw["layout"])
+        u, st = plan.solve(f, tol=1e-10)
+        un = u.cpu().numpy()
+        true_res = np.max(np.abs(oracle.residual(Rt, un, B, p.dim, p.n, p.length)))
+        err = np.max(np.abs(un - ref)) / np.max(np.abs(ref))
+        assert true_res <= 1.5e-10 * bn and err < 1e-8, (name, true_res / bn, err)
+        assert abs(st["res"] - true_res) <= 0.1 * true_res + 1e-13 * bn, (name, st["res"], true_res)
+        out[name] = (un, st["cycles"])
+    assert abs(out["zebra"][1] - out["march"][1]) <= 1
+    diff = np.max(np.abs(out["zebra"][0] - out["march"][0])) / np.max(np.abs(ref))
+    assert diff < 1e-8, diff
