@@ -162,10 +162,11 @@ template <typename T> hipError_t launch_restrict(const T* rf, T* fc, int dim, in
 // colour's is zero.  launch_restrict_zebra forms the full-weighting
 // restriction of that defect from d (same result as launch_restrict with
 // red_only on the defect, up to rounding); launch_zebra_norm writes the
-// partial maxima of |r| over the first colour to part[0 .. nparts) (NaN if
-// any is NaN), to be reduced by launch_maxabs_parts.
+// partial maxima of |r| over the first colour to part[0 .. *nparts) (NaN if
+// any is NaN; *nparts in: capacity, out: the number written), to be reduced
+// by launch_maxabs_parts.
 template <typename T> hipError_t launch_restrict_zebra(const T* d, T* fc, int nf, int M, T inv_h2, hipStream_t s);
-hipError_t launch_zebra_norm(const double* d, int nf, int M, double inv_h2, double* part, int nparts,
+hipError_t launch_zebra_norm(const double* d, int nf, int M, double inv_h2, double* part, int* nparts,
                              hipStream_t s);
 // black_only: only the second-colour fine points are corrected.  A
 // first-colour half-sweep that follows reads the iterate only there (its own

@@ -1323,22 +1323,18 @@ __global__ __launch_bounds__(256) void restrict2_split_kernel(const T* __restric
 
 // Zebra transfers (2D, colour-split storage, right after a second-colour
 // half-sweep that wrote the changes d of its entries): the first-colour
-// defect at natural index q is inv_h2 times the sum of d over its in-grid
-// neighbours, which all have the second colour (stored at n0f + q' / 2).
+// defect at grid point (y, x) is inv_h2 times the sum of d over its in-grid
+// neighbours, which all have the second colour (point (y, x) is stored at
+// n0f + (y nf + x) / 2 in that colour's block).
 template <typename T>
-__device__ __forceinline__ T zebra_defect(const T* __restrict__ d, int q, int nf, int n0f, T inv_h2) {
-  const int y = q / nf, x = q - y * nf;
-  T s = (T)0;
-  if (y >= 1) s += d[n0f + ((q - nf) >> 1)];
-  if (y + 1 < nf) s += d[n0f + ((q + nf) >> 1)];
-  if (x >= 1) s += d[n0f + ((q - 1) >> 1)];
-  if (x + 1 < nf) s += d[n0f + ((q + 1) >> 1)];
-  return inv_h2 * s;
+__device__ __forceinline__ T zebra_d(const T* __restrict__ d, int y, int x, int nf, int n0f) {
+  return (y >= 0 && y < nf && x >= 0 && x < nf) ? d[n0f + ((y * nf + x) >> 1)] : (T)0;
 }
 
 // Full weighting of that defect to coarse storage index Q (the second
 // colour's defect is zero, so only the centre and the corners count, as in
-// the red_only restriction).
+// the red_only restriction): the centre's four neighbours (edges of the 3x3
+// block) and the eight outer neighbours of the corners.
 template <typename T>
 __global__ __launch_bounds__(256) void restrict2_zebra_kernel(const T* __restrict__ df, T* __restrict__ fc, int nf,
                                                               int nc, long long M, T inv_h2) {
@@ -1349,27 +1345,40 @@ __global__ __launch_bounds__(256) void restrict2_zebra_kernel(const T* __restric
     for (int Q = blockIdx.x * 256 + threadIdx.x; Q < (int)Nc; Q += gridDim.x * 256) {
       const int Qn = Q < n0c ? 2 * Q : 2 * (Q - n0c) + 1;
       const int J = Qn / nc, I = Qn - J * nc;
-      const int c0 = (2 * J + 1) * nf + 2 * I + 1;
-      auto r = [&](int q) { return zebra_defect(d, q, nf, n0f, inv_h2); };
-      fc[m * Nc + Q] = (T)(1.0 / 16.0) *
-                       ((r(c0 - nf - 1) + r(c0 - nf + 1) + r(c0 + nf - 1) + r(c0 + nf + 1)) + (T)4 * r(c0));
+      const int y = 2 * J + 1, x = 2 * I + 1;   // the centre; corners at y -/+ 1, x -/+ 1
+      // edges of the centre (always in the grid)
+      const T eN = d[n0f + (((y - 1) * nf + x) >> 1)], eS = d[n0f + (((y + 1) * nf + x) >> 1)];
+      const T eW = d[n0f + ((y * nf + x - 1) >> 1)], eE = d[n0f + ((y * nf + x + 1) >> 1)];
+      const T rC = inv_h2 * (((eN + eS) + eW) + eE);
+      const T rNW = inv_h2 * (((zebra_d(d, y - 2, x - 1, nf, n0f) + eW) + zebra_d(d, y - 1, x - 2, nf, n0f)) + eN);
+      const T rNE = inv_h2 * (((zebra_d(d, y - 2, x + 1, nf, n0f) + eE) + eN) + zebra_d(d, y - 1, x + 2, nf, n0f));
+      const T rSW = inv_h2 * (((eS + zebra_d(d, y + 2, x - 1, nf, n0f)) + zebra_d(d, y + 1, x - 2, nf, n0f)) + eW);
+      const T rSE = inv_h2 * (((eS + zebra_d(d, y + 2, x + 1, nf, n0f)) + eE) + zebra_d(d, y + 1, x + 2, nf, n0f));
+      fc[m * Nc + Q] = (T)(1.0 / 16.0) * (((rNW + rNE) + rSW + rSE) + (T)4 * rC);
     }
   }
 }
 
-// max |defect| over the first colour: block b takes the time rows b, b +
-// gridDim.x, ... and writes its maximum to part[b] (0 without rows; NaN
-// propagates)
+// max |defect| over the first colour: block (bx, by) takes the time rows
+// by, by + gridDim.y, ... and in each the first-colour points bx * 256 +
+// threadIdx.x + k gridDim.x 256, and writes its maximum to
+// part[by * gridDim.x + bx] (NaN propagates).  First-colour point s of a row
+// is s = P nf + r: (y, x) = (2P, 2r) for r <= nc, (2P + 1, 2(r - nc) - 1)
+// otherwise (nf = 2 nc + 1).
 __global__ __launch_bounds__(256) void zebra_norm_kernel(const double* __restrict__ df, int nf, long long M,
                                                          double inv_h2, double* __restrict__ part) {
   const long long Nf = (long long)nf * nf;
-  const int n0f = (int)((Nf + 1) / 2);
+  const int n0f = (int)((Nf + 1) / 2), nc = (nf - 1) / 2;
   double mx = 0.0;
   bool bad = false;
-  for (long long m = blockIdx.x; m < M; m += gridDim.x) {
+  for (long long m = blockIdx.y; m < M; m += gridDim.y) {
     const double* d = df + m * Nf;
-    for (int s = threadIdx.x; s < n0f; s += 256) {
-      const double v = zebra_defect(d, 2 * s, nf, n0f, inv_h2);
+    for (int s = blockIdx.x * 256 + threadIdx.x; s < n0f; s += gridDim.x * 256) {
+      const int P = s / nf, r = s - P * nf;
+      const int y = r <= nc ? 2 * P : 2 * P + 1;
+      const int x = r <= nc ? 2 * r : 2 * (r - nc) - 1;
+      const double v = inv_h2 * (((zebra_d(d, y - 1, x, nf, n0f) + zebra_d(d, y + 1, x, nf, n0f)) +
+                                  zebra_d(d, y, x - 1, nf, n0f)) + zebra_d(d, y, x + 1, nf, n0f));
       if (!(v == v)) bad = true;
       else mx = fmax(mx, fabs(v));
     }
@@ -1386,7 +1395,7 @@ __global__ __launch_bounds__(256) void zebra_norm_kernel(const double* __restric
   if (threadIdx.x == 0) {
     double t = sh[0];
     for (int i = 1; i < 4; ++i) t = (sh[i] != sh[i] || t != t) ? __builtin_nan("") : fmax(t, sh[i]);
-    part[blockIdx.x] = t;
+    part[blockIdx.y * gridDim.x + blockIdx.x] = t;
   }
 }
 
@@ -1606,11 +1615,17 @@ hipError_t launch_restrict_zebra(const T* d, T* fc, int nf, int M, T inv_h2, hip
   return hipGetLastError();
 }
 
-hipError_t launch_zebra_norm(const double* d, int nf, int M, double inv_h2, double* part, int nparts, hipStream_t s) {
-  if (M <= 0 || nparts < 1) return hipErrorInvalidValue;
+hipError_t launch_zebra_norm(const double* d, int nf, int M, double inv_h2, double* part, int* nparts,
+                             hipStream_t s) {
+  if (M <= 0 || !nparts || *nparts < 1) return hipErrorInvalidValue;
   if ((long long)nf * nf >= (1ll << 31)) return hipErrorInvalidValue;
-  // one block per partial maximum (blocks without a row write 0)
-  hipLaunchKernelGGL(zebra_norm_kernel, dim3(nparts), dim3(256), 0, s, d, nf, (long long)M, inv_h2, part);
+  // gx blocks along a row (at most what its first colour needs), gy over the
+  // rows, gx gy <= *nparts; every block has rows and writes its part
+  const long long n0f = ((long long)nf * nf + 1) / 2;
+  const int gx = (int)std::max<long long>(1, std::min<long long>(std::min<long long>((n0f + 255) / 256, 16), *nparts));
+  const int gy = std::max(1, std::min(M, *nparts / gx));
+  hipLaunchKernelGGL(zebra_norm_kernel, dim3(gx, gy), dim3(256), 0, s, d, nf, (long long)M, inv_h2, part);
+  *nparts = gx * gy;
   return hipGetLastError();
 }
 

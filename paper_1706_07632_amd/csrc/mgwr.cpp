@@ -461,10 +461,10 @@ int defect_norm(mgwr_plan* pl, const double* F, double* U, double* norms, double
 int zebra_norm(mgwr_plan* pl, const double* d, double* norms, double* host) {
   const HostPlan& hp = pl->hp;
   const Level& lv = hp.levels[0];
-  const int nparts = (int)std::min<long long>(256, (long long)mgwr_plan::kMaxPipeCycles * ((lv.N + 15) / 16));
+  int nparts = (int)std::min<long long>(4096, (long long)mgwr_plan::kMaxPipeCycles * ((lv.N + 15) / 16));
   {
     Timed tm(pl, MGWR_K_DEFECT64, 0.0, 2.5 * hp.p.M * lv.N * sizeof(double));
-    HIP_TRY(launch_zebra_norm(d, lv.n, hp.p.M, 1.0 / (lv.h * lv.h), norms, nparts, pl->stream));
+    HIP_TRY(launch_zebra_norm(d, lv.n, hp.p.M, 1.0 / (lv.h * lv.h), norms, &nparts, pl->stream));
   }
   HIP_TRY(launch_maxabs_parts(norms, nparts, pl->scal, pl->stream));
   return read_scalar(pl, host);
