@@ -49,11 +49,11 @@ PEAK_HBM_GBS = 8000.0
 # batch solve (every kernel of the staged instances, the second solve of the
 # run); large2d: the average float64 SMOOTH march; large1d: the timed
 # pipelined launch (profiles/ holds the runs).
-_SHA = "ebc465df268844301f68252a23f4337d565451397165917bd2f97b1947d4f8d9"
+_SHA = "0ce7b258650b2594f66fc7d13cb9f5ef2c078b84566671dbbbbde47ac3c7b8db"
 TRAFFIC = {
-    "batched_fp64": (_SHA, 1.4452e12 + 5.882e11),
-    "large2d_fp64": (_SHA, 3.140e8 + 1.273e8),
-    "large1d_fp64": (_SHA, 4.972e10 + 8.865e9),
+    "batched_fp64": (_SHA, 1.2459e12 + 5.958e11),
+    "large2d_fp64": (_SHA, 3.553e8 + 1.696e8),
+    "large1d_fp64": (_SHA, 4.118e10 + 1.036e10),
 }
 
 
