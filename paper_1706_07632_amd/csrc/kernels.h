@@ -103,9 +103,11 @@ struct Stage {
   int red_only;          // STG_RESTRICT*: the defect is held on the first colour only (see launch_restrict)
   int black_only;        // STG_PROLONG*: correct the second-colour points only (see launch_prolong)
   int split;             // STG_RESTRICT* / STG_PROLONG*: 2D grids in colour-split storage (see MarchArgs)
-  // STG_RESTRICT* in 1D: src holds the changes d of the second-colour
-  // half-sweep before it (MarchArgs::Dout), and the restriction of the
-  // first-colour defect is zscale / 2 * (d[2p] + d[2p + 2]), zscale = 1/h^2
+  // STG_RESTRICT* with zebra set: src holds the changes d of the
+  // second-colour half-sweep before it (MarchArgs::Dout), and the stage
+  // restricts the first-colour defect formed from them (zscale = 1/h^2 times
+  // the sum of d over a point's neighbours): 1D zscale / 2 * (d[2p] +
+  // d[2p + 2]); 2D the full weighting of that defect (centre and corners)
   int zebra;
   double zscale;
   long long npoints;     // STG_CAST / STG_CORRECT: points per time row

@@ -826,7 +826,9 @@ constexpr int kStencilRowsPerPass = 256 / kStencilCols;
 
 // Full-weighting restriction of the rows of one leaf, and the zero start of
 // the coarse iterate on those rows.
-template <typename T>
+// Z2: 2D zebra restriction (12 taps on the changes d); otherwise the 9-point
+// (2D) / 3-point (1D) stencil on the defect, or the 1D zebra form
+template <typename T, bool Z2>
 __device__ __forceinline__ void restrict_stage(const Stage& st, int chunk, const PipeCtx& pc, int* sh_abort) {
   const T* src = static_cast<const T*>(st.src);
   T* dst = static_cast<T*>(st.dst);
@@ -843,17 +845,32 @@ __device__ __forceinline__ void restrict_stage(const Stage& st, int chunk, const
   const int lane = threadIdx.x & 63;
   // fine-grid offsets of the 9-point (2D) / 3-point (1D) weighted stencil;
   // tap t sits at a fixed index (registers, not private memory).  With a
-  // first-colour defect only the first-colour taps are read.
-  const int nw = st.dim == 1 ? 3 : 9;
+  // first-colour defect only the first-colour taps are read.  Zebra
+  // restrictions (src = the changes d of the second colour) read d at the
+  // first-colour points' neighbours instead: in 2D the centre's four
+  // neighbours (each counted by the centre and two corners, weight 6/16)
+  // and the corners' eight outer neighbours (1/16), times 1/h^2.
+  constexpr int NT = Z2 ? 12 : 9;
+  const int nw = Z2 ? 12 : (st.dim == 1 ? 3 : 9);
   const bool red_only = st.red_only;
-  long long off[9];
-  T wgt[9];
-  bool tap[9];
+  long long off[NT];
+  T wgt[NT];
+  bool tap[NT];
   {
     const long long I = st.dim == 1 ? Q : Qn % nc, J = st.dim == 1 ? 0 : Qn / nc;
     const long long fx = 2 * I + 1, fy = 2 * J + 1;
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
+    for (int t = 0; t < NT; ++t) {
+      if constexpr (Z2) {
+        constexpr int zdy[12] = {-1, 1, 0, 0, -2, -2, 2, 2, -1, 1, -1, 1};
+        constexpr int zdx[12] = {0, 0, -1, 1, -1, 1, -1, 1, -2, -2, 2, 2};
+        const long long y = fy + zdy[t], x = fx + zdx[t];
+        tap[t] = y >= 0 && y < nf && x >= 0 && x < nf;
+        off[t] = tap[t] ? y * nf + x : 0;
+        if (split) off[t] = split_index(off[t], n0f);
+        wgt[t] = (T)((t < 4 ? 6.0 : 1.0) / 16.0 * st.zscale);
+        continue;
+      }
       if (st.dim == 1) {
         off[t] = fx - 1 + (t < 3 ? t : 0);
         wgt[t] = t == 1 ? (T)0.5 : (T)0.25;
@@ -885,21 +902,21 @@ __device__ __forceinline__ void restrict_stage(const Stage& st, int chunk, const
       T v[4];
       const int rows_per_group = st.dim == 1 ? 4 : 2;
       for (int j0 = 0; j0 < 4; j0 += rows_per_group) {
-        T raw[4][9];
+        T raw[4][NT];
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
           const int row = r0 + (j0 + jj) * kStencilRowsPerPass;
           const bool rok = jj < rows_per_group && row < d.sz;
           const T* r = src + (long long)(d.lo + (rok ? row : 0)) * Nf;
 #pragma unroll
-          for (int t = 0; t < 9; ++t) raw[jj][t] = (rok && t < nw && tap[t]) ? gld<true>(r + off[t]) : (T)0;
+          for (int t = 0; t < NT; ++t) raw[jj][t] = (rok && t < nw && tap[t]) ? gld<true>(r + off[t]) : (T)0;
         }
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
           if (jj < rows_per_group) {
             T acc = (T)0;
 #pragma unroll
-            for (int t = 0; t < 9; ++t)
+            for (int t = 0; t < NT; ++t)
               if (t < nw && tap[t]) acc += wgt[t] * raw[jj][t];
             v[j0 + jj] = acc;
           }
@@ -1127,9 +1144,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void p
   __syncthreads();
   const Stage& st = *stp;
   switch (kind) {
-    case STG_RESTRICT: restrict_stage<double>(st, chunk, pc, &sh_abort); break;
+    case STG_RESTRICT:
+      if (st.zebra && st.dim == 2) restrict_stage<double, true>(st, chunk, pc, &sh_abort);
+      else restrict_stage<double, false>(st, chunk, pc, &sh_abort);
+      break;
     case STG_PROLONG: prolong_stage<double>(st, chunk, pc, &sh_abort); break;
-    case STG_RESTRICT32: restrict_stage<float>(st, chunk, pc, &sh_abort); break;
+    case STG_RESTRICT32:
+      if (st.zebra && st.dim == 2) restrict_stage<float, true>(st, chunk, pc, &sh_abort);
+      else restrict_stage<float, false>(st, chunk, pc, &sh_abort);
+      break;
     case STG_PROLONG32: prolong_stage<float>(st, chunk, pc, &sh_abort); break;
     case STG_CAST:
     case STG_CORRECT: pointwise_stage(st, chunk, pc, &sh_abort); break;

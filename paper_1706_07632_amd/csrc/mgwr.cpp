@@ -150,7 +150,6 @@ struct mgwr_plan {
   int coarse_l = 0;
   unsigned spin_limit = kDefaultSpinLimit;   // polls of a progress wait (mgwr_plan_set_progress_limit)
   std::vector<Stage> coarse_stages[2];
-  bool coarse_zebra[2] = {false, false};   // the zebra setting those stage images were built with
   // Zebra defects (see zebra_defects) in the current solve: only for
   // tolerances of at least kZebraMinTol, since they carry the rounding of
   // the line solves (measured floor about 1e-12 ||b||; 1D n = 127, alpha = 0.7)
@@ -609,11 +608,12 @@ int append_cycle_stages(mgwr_plan* pl, int l, int prev, std::vector<Stage>& out,
     smooth_stage(1);
     return prev;
   }
-  // 1D zebra restriction: the last pre-smoothing half-sweep (second colour)
+  // Zebra restriction: the last pre-smoothing half-sweep (second colour)
   // writes its changes d, and the restriction of the first-colour defect
-  // (1/h^2 times the sum of d at a point's two neighbours) is formed from
-  // them: no defect stage (see zebra_defects for the 2D staged form)
-  const bool zebra1 = pl->zebra && hp.p.dim == 1 && hp.p.nu1 >= 1;
+  // (1/h^2 times the sum of d over a point's neighbours) is formed from them:
+  // no defect stage (see zebra_defects for the staged form)
+  const bool zebra1 = pl->zebra && hp.p.nu1 >= 1 &&
+                      (hp.p.dim == 1 || (long long)lv.n * lv.n < (1ll << 31));
   for (int s2 = 0; s2 < hp.p.nu1; ++s2) { smooth_stage(0); smooth_stage(1, false, zebra1 && s2 == hp.p.nu1 - 1); }
   // after a second-colour half-sweep the defect vanishes on that colour: the
   // defect stage covers the first colour and the restriction reads only it
@@ -623,8 +623,9 @@ int append_cycle_stages(mgwr_plan* pl, int l, int prev, std::vector<Stage>& out,
     Stage st = base(STG_RESTRICT + kofs);
     if (!f32) { st.src = ops.R[l]; st.dst = ops.F[l + 1]; st.zero = ops.U[l + 1]; }
     else { st.src = o32.R[l]; st.dst = o32.F[l + 1]; st.zero = o32.U[l + 1]; }
-    st.dim = 1; st.nf = lv.n; st.nc = lc1.n;
+    st.dim = hp.p.dim; st.nf = lv.n; st.nc = lc1.n;
     st.red_only = 1;
+    st.split = pl->split && hp.p.dim == 2 ? 1 : 0;
     st.zebra = 1;
     st.zscale = 1.0 / (lv.h * lv.h);
     st.nchunks = (lc1.N + kStencilCols - 1) / kStencilCols;
@@ -825,10 +826,13 @@ template <typename T>
 int coarse_cycle(mgwr_plan* pl, int l) {
   const int w = sizeof(T) == 4 ? 1 : 0;
   std::vector<Stage>& st = pl->coarse_stages[w];
-  if (!st.empty() && pl->coarse_zebra[w] != pl->zebra) st.clear();
   if (st.empty()) {
-    pl->coarse_zebra[w] = pl->zebra;
+    // with defect stages: these latency-bound levels ran 12 % slower with
+    // zebra restrictions (2D n = 255, levels 3-7: 475 -> 532 us per cycle)
+    const bool zebra = pl->zebra;
+    pl->zebra = false;
     append_cycle_stages(pl, l, -1, st, w == 1);
+    pl->zebra = zebra;
     assign_offsets(st);
     if ((long long)st.size() > stages_per_cycle_bound(pl->hp)) {
       st.clear();
@@ -2241,9 +2245,14 @@ int solve_staged_side_by_side(mgwr_batch* bt, const std::vector<int>& staged, co
       // one cycle's stages plus one float64 defect of the full system; with
       // zebra defects the defect marches above the pipelined coarse levels
       // and the stopping-test march are not run
-      std::vector<Stage> one;
-      append_cycle_stages(pl, 0, -1, one, pl->mixed);
+      // (the stage list of a cycle with defect stages, as the coarse launch
+      // runs them; the staged levels' are dropped below with zebra defects)
       const bool zd = zebra_defects(pl), zt = !pl->mixed && zebra_stopping_test(pl);
+      std::vector<Stage> one;
+      const bool zebra = pl->zebra;
+      pl->zebra = false;
+      append_cycle_stages(pl, 0, -1, one, pl->mixed);
+      pl->zebra = zebra;
       const int ncoarse = pl->coarse_l > 0 ? pl->hp.levels[pl->coarse_l].n : 0;
       double cf = zt ? 0.0 : 2.0 * pl->hp.stored * pl->hp.levels[0].N;
       double cb = (zt ? 2.5 : 3.0) * pl->hp.p.M * pl->hp.levels[0].N * 8.0;

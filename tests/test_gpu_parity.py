@@ -547,8 +547,10 @@ def test_autotuner_times_both_storages(dev):
 @pytest.mark.parametrize("dim,n,M,alpha", [(2, 31, 96, 0.5), (2, 63, 64, 0.3), (1, 127, 256, 0.7), (1, 63, 128, 0.5)])
 def test_zebra_defects_match_defect_marches(dev, dim, n, M, alpha):
     """Zebra defects (the restriction's defect from the changes of the last
-    second-colour half-sweep; 2D staged in colour-split storage, and the 1D
-    pipelined cycle) against the defect marches of Algorithm 3: the same
+    second-colour half-sweep; 2D staged in colour-split storage, the
+    pipelined cycles in either storage) against the defect marches of
+    Algorithm 3 (the staged levels in natural storage, the 1D staged
+    cycle): the same
     cycle counts within one, both solutions at the oracle's, and the
     reported residual (a zebra stopping test in 2D) equal to the oracle's
     residual of the returned iterate.  Below a tolerance of 1e-10 the
@@ -565,7 +567,10 @@ def test_zebra_defects_match_defect_marches(dev, dim, n, M, alpha):
     bn = np.max(np.abs(B))
     # zebra form, and the same cycle with defect marches
     if dim == 2:
-        forms = {"zebra": dict(schedule="staged", layout="split"), "march": dict(schedule="staged", layout="natural")}
+        forms = {"zebra": dict(schedule="staged", layout="split"),
+                 "zebra_pipelined": dict(schedule="pipelined", layout="split"),
+                 "zebra_pipelined_natural": dict(schedule="pipelined", layout="natural"),
+                 "march": dict(schedule="staged", layout="natural")}
     else:
         forms = {"zebra": dict(schedule="pipelined"), "march": dict(schedule="staged")}
     out = {}
@@ -581,6 +586,7 @@ def test_zebra_defects_match_defect_marches(dev, dim, n, M, alpha):
         assert true_res <= 1.5e-10 * bn and err < 1e-8, (name, true_res / bn, err)
         assert abs(st["res"] - true_res) <= 0.1 * true_res + 1e-13 * bn, (name, st["res"], true_res)
         out[name] = (un, st["cycles"])
-    assert abs(out["zebra"][1] - out["march"][1]) <= 1
-    diff = np.max(np.abs(out["zebra"][0] - out["march"][0])) / np.max(np.abs(ref))
-    assert diff < 1e-8, diff
+    for name in out:
+        assert abs(out[name][1] - out["march"][1]) <= 1, name
+        diff = np.max(np.abs(out[name][0] - out["march"][0])) / np.max(np.abs(ref))
+        assert diff < 1e-8, (name, diff)
