@@ -337,7 +337,9 @@ int mgwr_plan_tuned(const mgwr_plan* plan, int* schedule, int* prefetch, int* co
  * on that colour and, at a first-colour point, 1/h^2 times the sum of those
  * changes over its neighbours, which saves the H-matrix product of a defect
  * (Algorithm 3) per level and cycle; its iterates equal NATURAL's up to
- * rounding.  (1D pipelined cycles restrict the same way.)  These zebra
+ * rounding.  (Pipelined cycles, 1D and 2D in either storage, restrict the
+ * same way; the coarse launch of the staged schedule keeps its defect
+ * stages.)  These zebra
  * defects carry the rounding of the line solves, so solves with a tolerance
  * below 1e-10 use the defect of Algorithm 3 throughout.
  * MGWR_LAYOUT_SPLIT: every time row holds the first colour's points (the
