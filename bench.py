@@ -49,11 +49,11 @@ PEAK_HBM_GBS = 8000.0
 # batch solve (every kernel of the staged instances, the second solve of the
 # run); large2d: the average float64 SMOOTH march; large1d: the timed
 # pipelined launch (profiles/ holds the runs).
-_SHA = "0ce7b258650b2594f66fc7d13cb9f5ef2c078b84566671dbbbbde47ac3c7b8db"
+_SHA = "49d8b39a4ff58e7e56d84f97005c125dfcbb75cfbe8220df102681c8f69bd63d"
 TRAFFIC = {
-    "batched_fp64": (_SHA, 1.2459e12 + 5.958e11),
-    "large2d_fp64": (_SHA, 3.553e8 + 1.696e8),
-    "large1d_fp64": (_SHA, 4.118e10 + 1.036e10),
+    "batched_fp64": (_SHA, 1.2448e12 + 5.959e11),
+    "large2d_fp64": (_SHA, 3.554e8 + 1.696e8),
+    "large1d_fp64": (_SHA, 4.023e10 + 1.036e10),
 }
 
 
