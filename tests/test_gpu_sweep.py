@@ -69,3 +69,32 @@ def test_sweep_against_oracle(dev, case):
     bound = 1e-10 if precision == "fp64" else 1e-8
     assert res <= 1.2 * tol + 1e-13 and err < bound, (case, err, res, st["cycles"])
     plan.close()
+
+
+@pytest.mark.parametrize("case", [c for c in _cases() if c[12] == "fp64"], ids=lambda c: f"z{c[0]}")
+def test_sweep_zebra_tolerance(dev, case):
+    """The float64 cases of the sweep at a tolerance of 1e-10, where the
+    cycles form their restriction's defect (and, staged in 2D, the stopping
+    test's norm) from the changes of the last half-sweep wherever the
+    smoothing counts allow it: the oracle's residual of the returned iterate
+    meets the tolerance and the error matches the mixed cases' bound."""
+    i, dim, n, M, alpha, r, k, leaf, nu1, nu2, gamma, schedule, precision, with_g = case
+    print("case", case, flush=True)
+    rng = np.random.default_rng([7, i])
+    N = n ** dim
+    t = W.graded_mesh(M, 1.0, r)
+    f = rng.standard_normal((M, N))
+    g = rng.standard_normal(N) if with_g else None
+    plan = mg.Plan(dim, n, M, alpha, k=k, t=t, leaf=leaf, nu1=nu1, nu2=nu2, gamma=gamma, schedule=schedule,
+                   max_cycles=160).bind()
+    fd = torch.as_tensor(f, dtype=torch.float64, device=dev)
+    gd = None if g is None else torch.as_tensor(g, dtype=torch.float64, device=dev)
+    u, st = plan.solve(fd, gd, tol=1e-10)
+    U = u.cpu().numpy()
+    Rt = oracle.hmatrix_dense(t, alpha, k, leaf)
+    B = oracle.rhs(f, t, alpha, g)
+    ref = oracle.timestep_solve(Rt, B, dim, n, 1.0)
+    err = np.max(np.abs(U - ref)) / np.max(np.abs(ref))
+    res = np.max(np.abs(oracle.residual(Rt, U, B, dim, n, 1.0))) / np.max(np.abs(B))
+    assert res <= 1.2e-10 + 1e-13 and err < 1e-8, (case, err, res, st["cycles"])
+    plan.close()
