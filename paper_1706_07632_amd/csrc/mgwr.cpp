@@ -827,8 +827,8 @@ int coarse_cycle(mgwr_plan* pl, int l) {
   const int w = sizeof(T) == 4 ? 1 : 0;
   std::vector<Stage>& st = pl->coarse_stages[w];
   if (st.empty()) {
-    // with defect stages: these latency-bound levels ran 12 % slower with
-    // zebra restrictions (2D n = 255, levels 3-7: 475 -> 532 us per cycle)
+    // with defect stages: these latency-bound levels ran 2 % slower with
+    // zebra restriction stages (2D n = 255, levels 3-7)
     const bool zebra = pl->zebra;
     pl->zebra = false;
     append_cycle_stages(pl, l, -1, st, w == 1);
