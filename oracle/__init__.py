@@ -12,6 +12,11 @@ relaxation, namely the solution of the fully discrete system
 direct spatial solve (Rt lower triangular), where Rt is either the L1 matrix R
 of Section 2 (k = None) or its H-matrix representation of Section 3.
 
+oracle.mgwr (imported on its own) takes the steps of one cycle of Algorithm
+2 (zebra-in-time line relaxation, defect, full weighting, coarse cycles,
+linear interpolation), so that iterates after a fixed number of cycles can be
+compared as well.
+
 Pins (tests/test_oracle_*.py):
 * R: invariants with closed forms (row sums, exactness on linear functions,
   the uniform-mesh L1 coefficients), the defining integral evaluated with
@@ -20,7 +25,10 @@ Pins (tests/test_oracle_*.py):
 * time marching: dense Kronecker LU on tiny grids, single-sine-mode reduction
   (eigenvectors of the finite-difference Laplacian);
 * the whole chain: the maximum errors printed in Table 1 and the graded-mesh
-  convergence order for the manufactured solution.
+  convergence order for the manufactured solution;
+* the cycle (oracle.mgwr): on two grids it reproduces the semi-algebraic mode
+  analysis blocks of oracle.sama element by element (1D and 2D), the direct
+  solution is its fixed point, cycles converge to it.
 """
 from .l1 import steps, pow_diff, l1_weights, l1_matrix, initial_value_weights  # noqa: F401
 from .hmatrix import (cluster_tree, admissible, block_partition, taylor_coeffs, rk_factors,  # noqa: F401
