@@ -1,0 +1,114 @@
+"""GPU iterates after a fixed number of cycles against the oracle's cycle
+(Algorithm 2 written out, oracle/mgwr.py), float64, element by element.
+
+The other parity tests compare converged solutions with the direct solution;
+these compare the iterate itself after one, two and three cycles, so a cycle
+that still converges but computes a different iteration (a transfer weight, a
+colour order, a coarse operator, the defect formed from the last half-sweep's
+changes) fails here.  Every float64 form of the cycle is covered: staged and
+pipelined schedules, colour-split and natural storage (2D), the defect marches
+(tolerance below 1e-10) and the zebra defects (tolerance 1e-8), V and W
+cycles with several smoothing counts, from zero and from a random iterate.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.mgwr as omg
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1706_07632_amd as mg  # noqa: E402  (fails loudly if the library is missing)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+# dim, n, M, alpha, r, k, nu1, nu2, gamma, with_g
+CASES = {
+    "1d_v11": (1, 63, 128, 0.5, 3.0, 8, 1, 1, 1, False),
+    "1d_w21": (1, 127, 96, 0.3, 17 / 3, 10, 2, 1, 2, True),
+    "1d_v01": (1, 63, 80, 0.7, 2.0, 8, 0, 1, 1, False),
+    "2d_v11": (2, 31, 64, 0.4, 3.0, 10, 1, 1, 1, False),
+    "2d_w11": (2, 15, 48, 0.6, 2.5, 8, 1, 1, 2, True),
+    "2d_v10": (2, 31, 40, 0.5, 3.0, 8, 1, 0, 1, False),
+}
+FORMS = [(s, lay, tol) for s in ("staged", "pipelined") for lay in ("split", "natural") for tol in (1e-8, 1e-14)]
+
+
+def _params():
+    out = []
+    for name, c in CASES.items():
+        for s, lay, tol in FORMS:
+            if c[0] == 1 and lay == "natural":
+                continue            # 1D has one storage
+            out.append(pytest.param(name, s, lay, tol, id=f"{name}-{s}-{lay if c[0] == 2 else '1d'}-{tol:g}"))
+    return out
+
+
+def _problem(name):
+    dim, n, M, alpha, r, k, nu1, nu2, gamma, with_g = CASES[name]
+    rng = np.random.default_rng(sum(map(ord, name)))
+    t = W.graded_mesh(M, 1.0, r)
+    N = n ** dim
+    f = rng.standard_normal((M, N))
+    g = rng.standard_normal(N) if with_g else None
+    U0 = rng.standard_normal((M, N))
+    Rt = oracle.hmatrix_dense(t, alpha, k, 16)
+    B = oracle.rhs(f, t, alpha, g)
+    return dict(dim=dim, n=n, M=M, alpha=alpha, k=k, t=t, nu1=nu1, nu2=nu2, gamma=gamma, f=f, g=g, U0=U0,
+                Rt=Rt, B=B)
+
+
+def _cuda(a, dev):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.mark.parametrize("name,schedule,layout,tol", _params())
+def test_iterates_match_the_oracle_cycle(dev, name, schedule, layout, tol):
+    P = _problem(name)
+    dim, n = P["dim"], P["n"]
+    print("case", name, schedule, layout, tol, flush=True)
+    kw = dict(k=P["k"], t=P["t"], nu1=P["nu1"], nu2=P["nu2"], gamma=P["gamma"], schedule=schedule)
+    okw = dict(nu1=P["nu1"], nu2=P["nu2"], gamma=P["gamma"])
+    f = _cuda(P["f"], dev)
+    g = None if P["g"] is None else _cuda(P["g"], dev)
+    # three cycles from zero, in one solve
+    plan = mg.Plan(dim, n, P["M"], P["alpha"], max_cycles=3, **kw)
+    if dim == 2:
+        plan.set_layout(layout)
+    plan.bind()
+    u, st = plan.solve(f, g, tol=tol, allow_unconverged=True)
+    assert st["cycles"] == 3, st
+    ref3 = omg.cycles(P["Rt"], P["B"], dim, n, 1.0, 3, **okw)[-1]
+    e3 = _rel(u.cpu().numpy(), ref3)
+    plan.close()
+    # one cycle at a time from a random iterate, each against the oracle's
+    # cycle from the library's previous iterate
+    plan = mg.Plan(dim, n, P["M"], P["alpha"], max_cycles=1, **kw)
+    if dim == 2:
+        plan.set_layout(layout)
+    plan.bind()
+    U = P["U0"]
+    worst = 0.0
+    for c in range(2):
+        u = _cuda(U, dev)
+        _, st = plan.solve(f, g, tol=tol, u=u, guess=True, allow_unconverged=True)
+        assert st["cycles"] == 1, st
+        want = omg.cycle(P["Rt"], U, P["B"], dim, n, 1.0, **okw)
+        U = u.cpu().numpy()
+        worst = max(worst, _rel(U, want))
+    plan.close()
+    print(f"{name} {schedule} {layout} tol={tol:g}: three cycles from zero {e3:.2e}, "
+          f"single cycles from a random iterate {worst:.2e}", flush=True)
+    assert e3 < 1e-10 and worst < 1e-10, (e3, worst)
