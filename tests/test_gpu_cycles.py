@@ -112,3 +112,39 @@ def test_iterates_match_the_oracle_cycle(dev, name, schedule, layout, tol):
     print(f"{name} {schedule} {layout} tol={tol:g}: three cycles from zero {e3:.2e}, "
           f"single cycles from a random iterate {worst:.2e}", flush=True)
     assert e3 < 1e-10 and worst < 1e-10, (e3, worst)
+
+
+MIXED = [pytest.param(name, s, lay, inner, id=f"{name}-{s}-{lay if CASES[name][0] == 2 else '1d'}-inner{inner}")
+         for name in ("1d_v11", "1d_w21", "2d_v11", "2d_w11") for s in ("staged", "pipelined")
+         for lay in (("split", "natural") if CASES[name][0] == 2 else ("split",)) for inner in (1, 2)]
+
+
+@pytest.mark.parametrize("name,schedule,layout,inner", MIXED)
+def test_float32_inner_cycles_follow_the_oracle_cycle(dev, name, schedule, layout, inner):
+    """Float32 inner cycles on A e = r with the float64 residual between them:
+    a cycle is affine, u + cycle(0, b - A u) = cycle(u, b), so after c inner
+    cycles in all (however they are grouped into refinement steps) the iterate
+    is the oracle's after c cycles up to float32 rounding.  Bound: a float32
+    cycle's line solves of M <= 128 unknowns lose about M eps_32 = 8e-6
+    relative, and the contracting iteration does not amplify earlier losses
+    beyond a factor 1 / (1 - rho) < 2 here: 1e-4 leaves a margin of 6."""
+    P = _problem(name)
+    dim, n = P["dim"], P["n"]
+    print("case", name, schedule, layout, "inner", inner, flush=True)
+    okw = dict(nu1=P["nu1"], nu2=P["nu2"], gamma=P["gamma"])
+    plan = mg.Plan(dim, n, P["M"], P["alpha"], k=P["k"], t=P["t"], nu1=P["nu1"], nu2=P["nu2"], gamma=P["gamma"],
+                   schedule=schedule, precision="mixed", inner_cycles=inner, max_cycles=3)
+    if dim == 2:
+        plan.set_layout(layout)
+    plan.bind()
+    f = _cuda(P["f"], dev)
+    g = None if P["g"] is None else _cuda(P["g"], dev)
+    u, st = plan.solve(f, g, tol=1e-8, allow_unconverged=True)
+    plan.close()
+    c = st["cycles"]
+    assert 1 <= c <= 3, st
+    ref = omg.cycles(P["Rt"], P["B"], dim, n, 1.0, c, **okw)[-1]
+    e = _rel(u.cpu().numpy(), ref)
+    print(f"{name} {schedule} {layout} inner={inner}: {c} float32 cycles ({st['refinements']} refinements), "
+          f"relative difference to the oracle's float64 iterate {e:.2e}", flush=True)
+    assert e < 1e-4, (c, e)
