@@ -148,3 +148,48 @@ def test_float32_inner_cycles_follow_the_oracle_cycle(dev, name, schedule, layou
     print(f"{name} {schedule} {layout} inner={inner}: {c} float32 cycles ({st['refinements']} refinements), "
           f"relative difference to the oracle's float64 iterate {e:.2e}", flush=True)
     assert e < 1e-4, (c, e)
+
+
+BATCH = [  # dim, n, M, alpha, r, k, schedule, with_g
+    (1, 63, 96, 0.5, 3.0, 8, "pipelined", False),
+    (2, 15, 64, 0.3, 17 / 3, 10, "pipelined", True),
+    (2, 31, 48, 0.7, 2.0, 8, "staged", False),
+    (1, 127, 64, 0.4, 4.0, 10, "staged", True),
+    (2, 31, 80, 0.6, 2.5, 10, "pipelined", False),
+    (2, 15, 32, 0.5, 3.0, 8, "staged", False),
+]
+
+
+@pytest.mark.parametrize("tol", [1e-8, 1e-14])
+def test_batch_iterates_match_the_oracle_cycle(dev, tol):
+    """Uneven instances in one batch (the pipelined ones merged into one
+    graph-replayed launch, the staged ones side by side on their own streams),
+    two cycles each, twice in a row (the second solve replays the captured
+    launch): every instance's iterate against the oracle's two cycles."""
+    rng = np.random.default_rng(77)
+    probs, plans = [], []
+    for dim, n, M, alpha, r, k, sched, with_g in BATCH:
+        t = W.graded_mesh(M, 1.0, r)
+        N = n ** dim
+        f = rng.standard_normal((M, N))
+        g = rng.standard_normal(N) if with_g else None
+        Rt = oracle.hmatrix_dense(t, alpha, k, 16)
+        ref = omg.cycles(Rt, oracle.rhs(f, t, alpha, g), dim, n, 1.0, 2)[-1]
+        probs.append((f, g, ref))
+        plans.append(mg.Plan(dim, n, M, alpha, k=k, t=t, schedule=sched, max_cycles=2).bind())
+    batch = mg.Batch(plans, graph=True).bind()
+    fs = [_cuda(f, dev) for f, _, _ in probs]
+    gs = [None if g is None else _cuda(g, dev) for _, g, _ in probs]
+    us = [torch.empty_like(f) for f in fs]
+    for rep in range(2):
+        us, sts = batch.solve(fs, gs, tol=tol, us=us, allow_unconverged=True)
+        errs = [_rel(u.cpu().numpy(), ref) for u, (_, _, ref) in zip(us, probs)]
+        print(f"tol={tol:g} solve {rep}: cycles {[s['cycles'] for s in sts]}, relative differences "
+              + " ".join(f"{e:.1e}" for e in errs), flush=True)
+        assert all(s["cycles"] == 2 for s in sts), sts
+        assert max(errs) < 1e-10, errs
+    print("graph replays", batch.graph_replays(), flush=True)
+    assert batch.graph_replays() >= 1
+    batch.close()
+    for pl in plans:
+        pl.close()
