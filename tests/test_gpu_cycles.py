@@ -38,6 +38,12 @@ CASES = {
     "2d_v11": (2, 31, 64, 0.4, 3.0, 10, 1, 1, 1, False),
     "2d_w11": (2, 15, 48, 0.6, 2.5, 8, 1, 1, 2, True),
     "2d_v10": (2, 31, 40, 0.5, 3.0, 8, 1, 0, 1, False),
+    # time leaves shorter than 16 (M = 37: leaves of 9, 9, 9 and 10 levels;
+    # M = 33: 16, 8 and 9) and a 3 x 3 grid whose next level is the
+    # one-point coarsest grid
+    "1d_ragged": (1, 31, 37, 0.45, 2.5, 6, 1, 1, 1, True),
+    "2d_ragged": (2, 7, 33, 0.55, 2.0, 6, 1, 1, 1, True),
+    "2d_n3_w": (2, 3, 20, 0.5, 2.0, 6, 1, 1, 2, False),
 }
 FORMS = [(s, lay, tol) for s in ("staged", "pipelined") for lay in ("split", "natural") for tol in (1e-8, 1e-14)]
 
