@@ -44,16 +44,18 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of a workload's dominant kernel from rocprofv3
 # FETCH_SIZE / WRITE_SIZE runs (KiB per dispatch) scaled by what the same
 # counters read for a 1 GiB device copy (--copy-probe: fetch x 2.000, write
-# x 1.000).  Keyed by the SHA-256 of kernels.hip they were taken on; a
-# different source reports null.  batched: the side-by-side phase of one
+# x 1.000).  Keyed by the SHA-256 of kernels.hip and of mgwr.cpp (the
+# launch schedule) they were taken on; a different source reports null.
+# batched: the side-by-side phase of one
 # batch solve (every kernel of the staged instances, the second solve of the
 # run); large2d: the average float64 SMOOTH march; large1d: the timed
 # pipelined launch (profiles/ holds the runs).
 _SHA = "49d8b39a4ff58e7e56d84f97005c125dfcbb75cfbe8220df102681c8f69bd63d"
+_SCHED = "pending"
 TRAFFIC = {
-    "batched_fp64": (_SHA, 1.2448e12 + 5.959e11),
-    "large2d_fp64": (_SHA, 3.554e8 + 1.696e8),
-    "large1d_fp64": (_SHA, 4.023e10 + 1.036e10),
+    "batched_fp64": (_SHA, _SCHED, 1.2448e12 + 5.959e11),
+    "large2d_fp64": (_SHA, _SCHED, 3.554e8 + 1.696e8),
+    "large1d_fp64": (_SHA, _SCHED, 4.023e10 + 1.036e10),
 }
 
 
@@ -100,16 +102,24 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes": x.numel() * 8, "copies": 3}), flush=True)
 
 
-def kernel_sha():
-    with open(os.path.join(ROOT, "paper_1706_07632_amd", "csrc", "kernels.hip"), "rb") as fh:
+def source_sha(name):
+    with open(os.path.join(ROOT, "paper_1706_07632_amd", "csrc", name), "rb") as fh:
         return hashlib.sha256(fh.read()).hexdigest()
+
+
+def kernel_sha():
+    return source_sha("kernels.hip")
+
+
+def schedule_sha():
+    return source_sha("mgwr.cpp")
 
 
 def traffic_for(key):
     entry = TRAFFIC.get(key)
-    if entry is None or entry[0] != kernel_sha():
+    if entry is None or entry[0] != kernel_sha() or entry[1] != schedule_sha():
         return None
-    return entry[1]
+    return entry[2]
 
 
 # ---- timing helpers -----------------------------------------------------------
@@ -533,6 +543,7 @@ def main():
         out["cpu_baseline"] = cpu
     out["forms"] = forms
     out["kernel_source_sha256"] = kernel_sha()
+    out["schedule_source_sha256"] = schedule_sha()
     print(json.dumps(out), flush=True)
 
 
