@@ -51,11 +51,11 @@ PEAK_HBM_GBS = 8000.0
 # run); large2d: the average float64 SMOOTH march; large1d: the timed
 # pipelined launch (profiles/ holds the runs).
 _SHA = "49d8b39a4ff58e7e56d84f97005c125dfcbb75cfbe8220df102681c8f69bd63d"
-_SCHED = "pending"
+_SCHED = "c26d9be9073462bde7d56f7a0c3ab3021c60e6bbaf06f7526ea5cbd4eebd6c52"
 TRAFFIC = {
-    "batched_fp64": (_SHA, _SCHED, 1.2448e12 + 5.959e11),
-    "large2d_fp64": (_SHA, _SCHED, 3.554e8 + 1.696e8),
-    "large1d_fp64": (_SHA, _SCHED, 4.023e10 + 1.036e10),
+    "batched_fp64": (_SHA, _SCHED, 1.2547e12 + 5.9417e11),
+    "large2d_fp64": (_SHA, _SCHED, 3.5545e8 + 1.6950e8),
+    "large1d_fp64": (_SHA, _SCHED, 4.0491e10 + 1.0359e10),
 }
 
 
