@@ -136,7 +136,7 @@ struct mgwr_plan {
   int set_prefetch = 0;
   int set_coarse = -1;
   bool staging_set = false;
-  bool side_by_side = false;           // solved beside other staged instances (a batch's workers)
+  bool side_by_side = false;           // solved beside enough staged instances to busy every batch worker
   int prefetch = 0;                    // in use
   int khint_staged = 0;                // cycles the last staged float64 solve from zero needed
   int khint_staged_warm = 0;           // the same from a predicted iterate
@@ -810,13 +810,17 @@ constexpr int kAutoPipelineChains = 256;
 // from level 2.
 constexpr int kCoarsePipelineChains = 64;
 
-// Solved side by side with other staged instances, a plan's coarse launch
-// starts one level below the rule's (when that level exists): the small
-// staged launches it then keeps fill the gaps the other instances leave,
-// and its own latency-bound coarse launch is shorter.  Measured on the
-// 64-instance batch: 2D n = 127 and 255 from n = 15 instead of 31, 937
-// against 953 ms per batch solve; two levels below 960 ms, one above
-// 1,059 ms, no coarse launch 1,001 ms.
+// Solved side by side with enough other staged instances to keep every
+// worker busy, a plan's coarse launch starts one level below the rule's
+// (when that level exists): the small staged launches it then keeps fill
+// the gaps the other instances leave, and its own latency-bound coarse
+// launch is shorter.  Measured on the 64-instance batch (40 staged): 2D
+// n = 127 and 255 from n = 15 instead of 31, 937 against 953 ms per batch
+// solve; two levels below 960 ms, one above 1,059 ms, no coarse launch
+// 1,001 ms.  Two instances side by side do not fill the GPU and keep the
+// rule (pairs of 2D n = 255, M = 1024 instances: mixed 69.9 ms with the
+// shift against 65.8, mixed with warm starts 57.5 against 55.3, float64
+// with warm starts 67.9 against 66.5, float64 76.1 against 77.0).
 constexpr int kSideCoarseShift = 1;
 
 // First level below the finest whose half-sweeps have at most
@@ -2193,6 +2197,7 @@ int solve_staged_side_by_side(mgwr_batch* bt, const std::vector<int>& staged, co
                               const double* const* g, double tol, double* const* u, unsigned flags,
                               mgwr_stats* stats, std::vector<int>& rcs, std::vector<std::string>& msgs) {
   const int nw = std::min<int>(kStagedWorkers, (int)staged.size());
+  const bool full = (int)staged.size() >= kStagedWorkers;   // every worker busy: coarse launches one level lower
   while ((int)bt->worker_streams.size() < nw) {
     hipStream_t s = nullptr;
     HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
@@ -2228,7 +2233,7 @@ int solve_staged_side_by_side(mgwr_batch* bt, const std::vector<int>& staged, co
       mgwr_plan* pl = bt->plans[i];
       hipStream_t own = pl->stream;
       pl->stream = bt->worker_streams[w];
-      pl->side_by_side = true;
+      pl->side_by_side = full;
       mgwr_stats si{};
       int rc = mgwr_solve(pl, f[i], g ? g[i] : nullptr, tol, u[i], flags, &si);
       if (rc != MGWR_OK) msgs[j] = mgwr_last_error();
