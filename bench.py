@@ -51,11 +51,11 @@ PEAK_HBM_GBS = 8000.0
 # run); large2d: the average float64 SMOOTH march; large1d: the timed
 # pipelined launch (profiles/ holds the runs).
 _SHA = "49d8b39a4ff58e7e56d84f97005c125dfcbb75cfbe8220df102681c8f69bd63d"
-_SCHED = "c26d9be9073462bde7d56f7a0c3ab3021c60e6bbaf06f7526ea5cbd4eebd6c52"
+_SCHED = "c1b8cbeacc2aebeaacf8280053e8f6c3a6e5aa6678d851682e6c47291949a5c5"
 TRAFFIC = {
-    "batched_fp64": (_SHA, _SCHED, 1.2547e12 + 5.9417e11),
-    "large2d_fp64": (_SHA, _SCHED, 3.5545e8 + 1.6950e8),
-    "large1d_fp64": (_SHA, _SCHED, 4.0491e10 + 1.0359e10),
+    "batched_fp64": (_SHA, _SCHED, 1.2556e12 + 5.9425e11),
+    "large2d_fp64": (_SHA, _SCHED, 3.5520e8 + 1.6951e8),
+    "large1d_fp64": (_SHA, _SCHED, 4.0423e10 + 1.0359e10),
 }
 
 
