@@ -199,3 +199,35 @@ def test_batch_iterates_match_the_oracle_cycle(dev, tol):
     batch.close()
     for pl in plans:
         pl.close()
+
+
+def test_full_side_by_side_batch_iterates_match_the_oracle_cycle(dev):
+    """Ten staged instances (at least one per worker thread: their coarse
+    pipelined launch then starts one level below the single-solve rule) and
+    two pipelined ones, two cycles each, against the oracle's two cycles."""
+    rng = np.random.default_rng(91)
+    shapes = [(2, 31, 32), (2, 31, 48), (2, 31, 40), (2, 63, 32), (2, 31, 64), (2, 31, 36),
+              (1, 127, 48), (1, 63, 64), (1, 255, 32), (1, 127, 40)]
+    probs, plans = [], []
+    for j, (dim, n, M) in enumerate(shapes + [(2, 15, 48), (1, 31, 64)]):
+        alpha = float(rng.uniform(0.25, 0.85))
+        t = W.graded_mesh(M, 1.0, (2 - alpha) / alpha)
+        N = n ** dim
+        f = rng.standard_normal((M, N))
+        Rt = oracle.hmatrix_dense(t, alpha, 8, 16)
+        ref = omg.cycles(Rt, oracle.rhs(f, t, alpha, None), dim, n, 1.0, 2)[-1]
+        probs.append((f, ref))
+        plans.append(mg.Plan(dim, n, M, alpha, k=8, t=t, max_cycles=2,
+                             schedule="staged" if j < len(shapes) else "pipelined").bind())
+    batch = mg.Batch(plans, graph=True).bind()
+    fs = [_cuda(f, dev) for f, _ in probs]
+    us = [torch.empty_like(f) for f in fs]
+    for rep in range(2):
+        us, sts = batch.solve(fs, tol=1e-8, us=us, allow_unconverged=True)
+        errs = [_rel(u.cpu().numpy(), ref) for u, (_, ref) in zip(us, probs)]
+        print(f"solve {rep}: worst relative difference {max(errs):.2e}", flush=True)
+        assert all(s["cycles"] == 2 for s in sts), sts
+        assert max(errs) < 1e-10, errs
+    batch.close()
+    for pl in plans:
+        pl.close()
