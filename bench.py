@@ -54,9 +54,9 @@ PEAK_HBM_GBS = 8000.0
 _SHA = "49d8b39a4ff58e7e56d84f97005c125dfcbb75cfbe8220df102681c8f69bd63d"
 _SCHED = "c1b8cbeacc2aebeaacf8280053e8f6c3a6e5aa6678d851682e6c47291949a5c5"
 TRAFFIC = {
-    "batched_fp64": (_SHA, _SCHED, 1.2556e12 + 5.9425e11),
-    "large2d_fp64": (_SHA, _SCHED, 3.5520e8 + 1.6951e8),
-    "large1d_fp64": (_SHA, _SCHED, 4.0423e10 + 1.0359e10),
+    "batched_fp64": (_SHA, _SCHED, 1.2598e12 + 5.9479e11),
+    "large2d_fp64": (_SHA, _SCHED, 3.5508e8 + 1.6939e8),
+    "large1d_fp64": (_SHA, _SCHED, 4.0701e10 + 1.0359e10),
 }
 
 
