@@ -253,9 +253,13 @@ int mgwr_batch_bind(mgwr_batch* batch, void* workspace_dev, size_t bytes, void* 
  * arrays are touched, and all work is complete when the call returns.  They
  * run one by one instead when two entries share a plan.  With
  * MGWR_WARM_START the predictions of plans sharing a network take turns on
- * it (its buffers and stream) while the cycles run side by side.  Returns MGWR_OK
- * when every instance converged, else the first non-OK status in entry
- * order. */
+ * it (its buffers and stream) while the cycles run side by side.  With at
+ * least 8 staged instances each starts its coarse pipelined launch one level
+ * below the single-solve rule (mgwr_plan_tuned reports the single-solve
+ * choice).  The worker streams overlap only on hardware queues of their own:
+ * HIP gives a process 4 unless GPU_MAX_HW_QUEUES (read when HIP starts) asks
+ * for more; 16 suits the 8 workers.  Returns MGWR_OK when every instance
+ * converged, else the first non-OK status in entry order. */
 int mgwr_batch_solve(mgwr_batch* batch, const double* const* f_dev, const double* const* g_dev, double tol,
                      double* const* u_dev, unsigned flags, mgwr_stats* stats);
 /* Timing of the batch's work: event-timed merged launches (class
